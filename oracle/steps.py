@@ -1,0 +1,286 @@
+"""Oracle optimiser steps (DE, PSO, GA) -- TEST INFRASTRUCTURE ONLY.
+
+Plain per-individual Python loops that follow the paper's algorithms in the
+paper's order:
+  - Differential Evolution: Alg. 1 (Mutate, Crossover, Repair, selection),
+    Section IV-B (valid-only initial population, "u not in X", reinit);
+  - Particle Swarm Optimization: Section IV-C (inertia, cognitive, social
+    terms; mapping to [0,1]^N; evaluation through Alg. 2's repair, position
+    unchanged);
+  - Genetic Algorithm: Section IV-D (sorted population, beta-distributed rank
+    selection, single-point crossover, Alg. 3 repair, then mutation to a
+    random valid Hamming neighbour).
+
+Randomness: every draw is a Philox4x32-10 output at a counter that names
+its use (individual, generation, purpose, sub-index), so the step is a pure
+function of (space, state, generation, seed).  Fixed-point rules (Q16.16 for
+DE mutation and PSO coordinates) make every result an exact integer.
+
+Where the paper is silent the readings are:
+  DE  - synchronous generation; "u not in X" tested against the population at
+        the start of the generation, later duplicates of an accepted trial are
+        rejected (lowest individual index wins); reinitialise after a
+        generation with no accepted trial; initial sample stratified over the
+        ascending valid list (one stratum per member).
+  PSO - positions in index units (the largest domain spans [0, M)), centre of
+        value k at k + 1/2, snap = floor then clip to the domain; per-dimension
+        r1, r2; zero initial velocity; pbest on strict improvement; gbest
+        recomputed after all particles moved.
+  GA  - rank selection from Beta(1, b) over normalised rank; cut point uniform
+        in 1..D-1; two children per pair (the last one dropped for odd P);
+        repair, then mutation with probability 1/mutation_chance.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional
+
+import numpy as np
+
+from . import core
+
+P_INIT, P_DE_PICK, P_DE_CR, P_PSO_R, P_GA_SEL, P_GA_MUT = 1, 2, 3, 4, 5, 6
+
+
+def uniform_below(u: int, n: int) -> int:
+    """Integer in [0, n) from a 32-bit draw: floor(u * n / 2^32)."""
+    return (int(u) * int(n)) >> 32
+
+
+def pick_excluding(u: int, n: int, excluded: List[int]) -> int:
+    """Uniform member of {0..n-1} minus `excluded` (the k-th member in ascending order)."""
+    k = uniform_below(u, n - len(excluded))
+    for e in sorted(excluded):
+        if k >= e:
+            k += 1
+    return k
+
+
+def draw(seed: int, c0: int, c1: int, purpose: int, sub: int = 0) -> List[int]:
+    return core.philox(seed, [c0 & 0xFFFFFFFF, c1 & 0xFFFFFFFF, (purpose << 24) | sub, 0])
+
+
+def init_positions(space: core.Space, P: int, seed: int, tag: int) -> np.ndarray:
+    """Valid-only initial sample: member i is uniform inside stratum i of the valid list.
+
+    Stratum i is [floor(i*|V|/P), floor((i+1)*|V|/P)); the strata are disjoint
+    and non-empty for P <= |V|, so the members are distinct.
+    """
+    n = space.n_valid
+    out = np.zeros(P, dtype=np.int64)
+    for i in range(P):
+        lo, hi = (i * n) // P, ((i + 1) * n) // P
+        out[i] = lo + uniform_below(draw(seed, i, tag, P_INIT)[0], hi - lo)
+    return out
+
+
+def beta_rank_table(P: int, b: int) -> List[int]:
+    """Cumulative Beta(1, b) selection thresholds over ranks, as exact 32-bit fractions.
+
+    Rank r (0 = best) is chosen with probability CDF((r+1)/P) - CDF(r/P), where
+    CDF(x) = 1 - (1 - x)^b.  Entry r is floor(CDF((r+1)/P) * 2^32); the last
+    entry is 2^32.
+    """
+    Pb = P ** b
+    return [((Pb - (P - r - 1) ** b) << 32) // Pb for r in range(P)]
+
+
+def rank_from_draw(table: List[int], u: int) -> int:
+    for r, t in enumerate(table):
+        if u < t:
+            return r
+    raise AssertionError("unreachable: last threshold is 2^32")
+
+
+def _lexmin(a, b):
+    return a if (a[0], a[1]) <= (b[0], b[1]) else b
+
+
+# ---------------------------------------------------------------------------
+# Differential Evolution (Alg. 1)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class DEState:
+    pos: np.ndarray            # population as positions in the valid list
+    f: np.ndarray              # float32 objective of each member
+    best_f: float
+    best_pos: int
+    gen: int = 0
+    reinits: int = 0
+
+
+def de_init(space, obj, P, seed) -> DEState:
+    pos = init_positions(space, P, seed, 0)
+    f = obj[pos].astype(np.float32)
+    b = min(zip(f.tolist(), pos.tolist()))
+    return DEState(pos, f, np.float32(b[0]), int(b[1]))
+
+
+def de_step(space: core.Space, obj: np.ndarray, st: DEState, seed: int, F_q16: int, CR_q32: int,
+            use_best: bool = True) -> DEState:
+    P, D, g = len(st.pos), space.D, st.gen
+    if P < 4:
+        raise ValueError("DE needs at least 4 members")
+    rad = space.radices
+    X = space.vrows[st.pos]                              # value indices of the population
+    best_row = space.vrows[st.best_pos]
+    trials = np.zeros((P, D), dtype=np.int32)
+    for i in range(P):
+        o = draw(seed, i, g, P_DE_PICK)
+        r1 = pick_excluding(o[0], P, [i])
+        r2 = pick_excluding(o[1], P, [i, r1])
+        r3 = pick_excluding(o[2], P, [i, r1, r2])
+        j_rand = uniform_below(o[3], D)
+        base = best_row if use_best else X[r1]
+        for j in range(D):
+            # m = i_r1 + F*(i_r2 - i_r3), rounded half up in Q16.16, clipped to the domain
+            num = int(base[j]) * 65536 + F_q16 * (int(X[r2, j]) - int(X[r3, j])) + 32768
+            m = min(max(num // 65536, 0), int(rad[j]) - 1)
+            cr = draw(seed, i, g, P_DE_CR, j >> 2)[j & 3]
+            trials[i, j] = m if (cr < CR_q32 or j == j_rand) else X[i, j]
+    # Repair: invalid trials move to the nearest valid configuration by index distance
+    trials = space.repair(trials, core.INDEX_L1)
+    upos = space.pos(space.encode(trials))
+    fu = obj[upos].astype(np.float32)
+    members = set(st.pos.tolist())
+    pre = [bool(fu[i] <= st.f[i]) and int(upos[i]) not in members for i in range(P)]
+    taken = set()
+    new_pos, new_f = st.pos.copy(), st.f.copy()
+    accepted = 0
+    for i in range(P):
+        if pre[i] and int(upos[i]) not in taken:
+            taken.add(int(upos[i]))
+            new_pos[i], new_f[i] = upos[i], fu[i]
+            accepted += 1
+    best = (float(st.best_f), st.best_pos)
+    for i in range(P):
+        best = _lexmin(best, (float(new_f[i]), int(new_pos[i])))
+    reinits = st.reinits
+    if accepted == 0:
+        new_pos = init_positions(space, P, seed, g + 1)
+        new_f = obj[new_pos].astype(np.float32)
+        for i in range(P):
+            best = _lexmin(best, (float(new_f[i]), int(new_pos[i])))
+        reinits += 1
+    return DEState(new_pos, new_f, np.float32(best[0]), int(best[1]), g + 1, reinits)
+
+
+# ---------------------------------------------------------------------------
+# Particle Swarm Optimization (Section IV-C, Alg. 2)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class PSOState:
+    X: np.ndarray              # P x D positions, Q16.16 index units
+    V: np.ndarray              # P x D velocities, Q16.16
+    PB: np.ndarray             # P x D personal-best positions
+    f_pb: np.ndarray           # personal-best objective
+    pb_pos: np.ndarray         # valid-list position evaluated at the personal best
+    g_idx: int                 # particle holding the global best
+    gen: int = 0
+
+    @property
+    def best_f(self):
+        return self.f_pb[self.g_idx]
+
+    @property
+    def best_pos(self):
+        return int(self.pb_pos[self.g_idx])
+
+
+def _gbest(f_pb: np.ndarray) -> int:
+    return int(min(range(len(f_pb)), key=lambda i: (float(f_pb[i]), i)))
+
+
+def centre_q16(k):
+    return (2 * np.asarray(k, dtype=np.int64) + 1) * 32768
+
+
+def pso_init(space, obj, P, seed) -> PSOState:
+    pos = init_positions(space, P, seed, 0)
+    X = centre_q16(space.vrows[pos])
+    f = obj[pos].astype(np.float32)
+    return PSOState(X.copy(), np.zeros_like(X), X.copy(), f.copy(), pos.copy(), _gbest(f))
+
+
+def pso_step(space: core.Space, obj: np.ndarray, st: PSOState, seed: int, w_q16: int, c1_q16: int,
+             c2_q16: int) -> PSOState:
+    P, D, g = st.X.shape[0], space.D, st.gen
+    M = int(space.radices.max())
+    hi = M * 65536 - 1
+    X, V, PB = st.X.copy(), st.V.copy(), st.PB.copy()
+    GB = st.PB[st.g_idx].copy()
+    snapped = np.zeros((P, D), dtype=np.int32)
+    for i in range(P):
+        for j in range(D):
+            o = draw(seed, i, g, P_PSO_R, j)
+            r1, r2 = o[0] >> 16, o[1] >> 16
+            x = int(X[i, j])
+            v = ((w_q16 * int(V[i, j])) >> 16) \
+                + ((((c1_q16 * r1) >> 16) * (int(PB[i, j]) - x)) >> 16) \
+                + ((((c2_q16 * r2) >> 16) * (int(GB[j]) - x)) >> 16)
+            x = min(max(x + v, 0), hi)
+            V[i, j], X[i, j] = v, x
+            snapped[i, j] = min(x >> 16, int(space.radices[j]) - 1)
+    # Evaluation goes through Alg. 2: invalid snapped points are replaced by the nearest
+    # neighbour (Euclidean distance to the particle) of the first non-empty neighbour set.
+    ev = space.repair(snapped, core.TIER_EUCLID, pos_q16=X)
+    epos = space.pos(space.encode(ev))
+    f = obj[epos].astype(np.float32)
+    f_pb, pb_pos = st.f_pb.copy(), st.pb_pos.copy()
+    for i in range(P):
+        if f[i] < f_pb[i]:
+            PB[i], f_pb[i], pb_pos[i] = X[i], f[i], epos[i]
+    return PSOState(X, V, PB, f_pb, pb_pos, _gbest(f_pb), g + 1)
+
+
+# ---------------------------------------------------------------------------
+# Genetic Algorithm (Section IV-D, Alg. 3)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class GAState:
+    pos: np.ndarray
+    f: np.ndarray
+    best_f: float
+    best_pos: int
+    gen: int = 0
+
+
+def ga_init(space, obj, P, seed) -> GAState:
+    pos = init_positions(space, P, seed, 0)
+    f = obj[pos].astype(np.float32)
+    b = min(zip(f.tolist(), pos.tolist()))
+    return GAState(pos, f, np.float32(b[0]), int(b[1]))
+
+
+def ga_step(space: core.Space, obj: np.ndarray, st: GAState, seed: int, mutation_chance: int,
+            beta_b: int, table: Optional[List[int]] = None) -> GAState:
+    P, D, g = len(st.pos), space.D, st.gen
+    order = sorted(range(P), key=lambda i: (float(st.f[i]), int(st.pos[i])))
+    table = table or beta_rank_table(P, beta_b)
+    rows = space.vrows[st.pos]
+    children = np.zeros((P, D), dtype=np.int32)
+    for k in range((P + 1) // 2):
+        o = draw(seed, k, g, P_GA_SEL)
+        A = rows[order[rank_from_draw(table, o[0])]]
+        B = rows[order[rank_from_draw(table, o[1])]]
+        cut = 1 + uniform_below(o[2], D - 1)
+        children[2 * k] = np.concatenate([A[:cut], B[cut:]])
+        if 2 * k + 1 < P:
+            children[2 * k + 1] = np.concatenate([B[:cut], A[cut:]])
+    # Alg. 3: invalid children become a random member of the first non-empty neighbour set
+    children = space.repair(children, core.TIER_RANDOM, key=seed, gen=g)
+    # Mutation (after repair): with chance 1/mutation_chance, a random valid Hamming neighbour
+    thresh = (1 << 32) // mutation_chance
+    mut = [i for i in range(P) if draw(seed, i, g, P_GA_MUT)[0] < thresh]
+    if mut:
+        mutated = space.repair(children[mut], core.HAM1_RANDOM, who=np.array(mut), key=seed, gen=g)
+        children[mut] = mutated
+    pos = space.pos(space.encode(children))
+    f = obj[pos].astype(np.float32)
+    best = (float(st.best_f), st.best_pos)
+    for i in range(P):
+        best = _lexmin(best, (float(f[i]), int(pos[i])))
+    return GAState(pos, f, np.float32(best[0]), int(best[1]), g + 1)
