@@ -1,0 +1,261 @@
+/*
+ * ct.h -- C ABI of the MI355X constraint-aware auto-tuning library (libct.so).
+ *
+ * The library implements, on one gfx950 GPU, the data-parallel hot path of
+ * constraint-aware evolutionary auto-tuning (Willemsen et al.,
+ * "Constraint-aware Optimization in Auto-Tuning"):
+ *   - evaluating the correctness constraints of a discrete tunable-parameter
+ *     space (the CSP (X, D, C) of Section IV-A) over every configuration,
+ *     giving a validity bitmask and the ascending list of valid
+ *     configurations (Section IV-A: the full space is resolved before tuning);
+ *   - validity queries and repair of invalid configurations to a valid one
+ *     under the neighbour rules of Section IV-A (Alg. 1 Repair, Alg. 2, Alg. 3);
+ *   - whole-population generation steps of constraint-aware Differential
+ *     Evolution (Alg. 1, Section IV-B), Particle Swarm Optimization
+ *     (Section IV-C) and the Genetic Algorithm (Section IV-D).
+ *
+ * Conventions
+ *   - Every function returns CT_OK (0) or a negative ct_status; on error
+ *     nothing is written to caller buffers and ct_last_error() returns a
+ *     message for the calling thread.
+ *   - "d_" pointers are device pointers on the current HIP device (for
+ *     example torch tensors' data_ptr()); "h_" pointers are host memory.
+ *     The caller owns every buffer it passes; handles own their internal
+ *     device buffers and release them in the matching *_free.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *     stream-ordered and asynchronous unless stated otherwise.
+ *   - A configuration is a row of value indices ("digits"), one uint8 per
+ *     parameter, padded with zeros to row_bytes = 4, 8, 16 or 32 bytes
+ *     (D <= 4, 8, 16, 32).  Its linear index is row-major with the last
+ *     parameter fastest: L = sum_j d_j * prod_{k>j} r_k.
+ *   - Randomness is Philox4x32-10 (Salmon et al., SC'11) keyed by a 64-bit
+ *     seed at counters that name each draw, so results are bit-exact and
+ *     independent of launch shape, batching and stream interleaving.
+ */
+#ifndef CT_H
+#define CT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ct_space ct_space;   /* a resolved search space (device-resident) */
+typedef struct ct_pop ct_pop;       /* one optimiser run's device state */
+
+enum ct_status {
+    CT_OK = 0,
+    CT_EINVAL = -1,     /* bad argument, malformed bytecode, unsupported size */
+    CT_ENOMEM = -2,     /* device allocation failed */
+    CT_EOVERFLOW = -3,  /* a constraint may overflow 64-bit integers */
+    CT_EEMPTY = -4,     /* repair/step on a space with no valid configuration */
+    CT_EDEVICE = -5,    /* HIP runtime error */
+    CT_ESYNTAX = -6     /* constraint text not in the accepted expression language */
+};
+
+/* Repair keys (Section IV-A neighbour rules).  Ties always go to the lowest linear index. */
+enum ct_metric {
+    CT_HAMMING = 0,      /* number of differing parameters ("Hamming") */
+    CT_INDEX_L1 = 1,     /* sum of |index differences| ("index-distance"; DE repair, Alg. 1) */
+    CT_TIER_EUCLID = 2,  /* first non-empty of strictly-adjacent / adjacent / Hamming-1, nearest to a
+                            continuous position by Euclidean distance (PSO, Alg. 2) */
+    CT_TIER_RANDOM = 3,  /* same sets, uniformly random member (GA, Alg. 3) */
+    CT_HAM1_RANDOM = 4   /* uniformly random valid Hamming-1 neighbour (GA mutation, Section IV-D) */
+};
+
+enum ct_algo { CT_DE = 0, CT_PSO = 1, CT_GA = 2 };
+
+enum ct_step_flags {
+    CT_STEP_PLAIN = 0,    /* each population advanced by its own launch sequence */
+    CT_STEP_BATCHED = 1,  /* all populations advanced together, one launch per phase */
+    CT_STEP_GRAPH = 2     /* BATCHED, captured once into a hipGraph and replayed per generation */
+};
+
+#define CT_MAX_PARAMS 32
+#define CT_MAX_RADIX 255
+#define CT_MAX_POP 65536
+#define CT_MAX_CARTESIAN_LOG2 46
+
+/* Message for the last error on this thread (never NULL). */
+const char* ct_last_error(void);
+
+/* Library ABI version (currently 1). */
+int ct_version(void);
+
+/*
+ * ct_compile -- constraint text -> integer expression bytecode (host only, no GPU).
+ *
+ * Section IV-A defines each constraint as a predicate over a subset of the
+ * parameters; here a constraint is a Python integer expression over the
+ * parameter names: integer literals, True/False, + - * // %, unary - and +,
+ * abs(x), min(a, b, ...), max(a, b, ...), comparisons (chains allowed),
+ * and / or / not, parentheses.  Semantics are Python's: floor division,
+ * modulo with the sign of the divisor, 'and'/'or' return an operand, a
+ * division or modulo by zero makes the whole constraint false (where Python
+ * would raise), and a configuration is valid iff every constraint is truthy.
+ * Interval analysis over the value tables must prove every intermediate fits
+ * in int64 (else CT_EOVERFLOW).
+ *
+ *   names[n_params], values (concatenated value lists), radices[n_params]
+ *   constraints[n_cons]: NUL-terminated strings
+ *   code[code_cap]: output words; cons_offsets[n_cons + 1]: start of each program
+ *   *code_len: words written.
+ * Errors: CT_ESYNTAX (message names the constraint and position),
+ *         CT_EOVERFLOW, CT_EINVAL (sizes, unknown name, capacity too small).
+ */
+int ct_compile(const char* const* names, uint32_t n_params, const int64_t* values, const uint32_t* radices,
+               const char* const* constraints, uint32_t n_cons,
+               uint32_t* code, uint32_t code_cap, uint32_t* cons_offsets, uint32_t* code_len);
+
+/*
+ * ct_space_build -- resolve the whole space on the GPU (Section IV-A).
+ *
+ * Decodes every linear index L in [0, prod r_j), evaluates every constraint
+ * program, writes the validity bitmask (bit L%64 of word L/64) and compacts
+ * the valid configurations into an ascending list of linear indices plus
+ * their digit rows.  Inputs are host arrays copied into the handle.
+ *   1 <= n_params <= 32, 1 <= r_j <= 255, prod r_j < 2^46.
+ * Errors: CT_EINVAL (sizes, malformed bytecode: unknown opcode, stack
+ * under/overflow, parameter id out of range), CT_ENOMEM, CT_EDEVICE.
+ * An empty valid set is not an error (count 0).
+ */
+int ct_space_build(const int64_t* values, const uint32_t* radices, uint32_t n_params,
+                   const uint32_t* code, const uint32_t* cons_offsets, uint32_t n_cons,
+                   void* stream, ct_space** out);
+
+/* Number of valid and of all configurations.  Synchronises with the build. */
+int ct_space_count(const ct_space* s, uint64_t* n_valid, uint64_t* n_cartesian);
+
+/* Number of parameters and the row width in bytes. */
+int ct_space_info(const ct_space* s, uint32_t* n_params, uint32_t* row_bytes);
+
+/* Borrowed device pointers (valid until ct_space_free): ascending linear indices
+   [n_valid] and digit rows [n_valid][row_bytes]. */
+int ct_space_valid_list(const ct_space* s, const uint64_t** d_lin, const uint8_t** d_rows);
+
+/* Borrowed device pointer to the validity bitmask [ceil(n_cartesian/64)] words. */
+int ct_space_bitmask(const ct_space* s, const uint64_t** d_words, uint64_t* n_words);
+
+/* Stream-ordered device-to-device copies of the valid list / bitmask into
+   caller-owned buffers: d_lin[n_valid] (nullable), d_rows[n_valid][row_bytes]
+   (nullable); d_words[ceil(n_cartesian/64)]. */
+int ct_space_copy_list(const ct_space* s, uint64_t* d_lin, uint8_t* d_rows, void* stream);
+int ct_space_copy_bitmask(const ct_space* s, uint64_t* d_words, void* stream);
+
+void ct_space_free(ct_space* s);
+
+/*
+ * ct_valid_mask -- is each row a solution (Section IV-A validity query)?
+ *   d_rows[n][row_bytes] -> d_out[n] (1 valid, 0 invalid; a digit >= its
+ *   radix counts as invalid).
+ */
+int ct_valid_mask(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint8_t* d_out, void* stream);
+
+/*
+ * ct_rank -- position of each row in the ascending valid list, or -1 if the
+ * row is not valid.  d_rows[n][row_bytes] -> d_pos[n] (int64).
+ */
+int ct_rank(const ct_space* s, const uint8_t* d_rows, uint64_t n, int64_t* d_pos, void* stream);
+
+/*
+ * ct_repair -- move invalid rows to a valid configuration.
+ *
+ * For metrics HAMMING, INDEX_L1, TIER_EUCLID and TIER_RANDOM a valid row is
+ * returned unchanged; an invalid row c becomes the valid v minimising the
+ * lexicographic key (k(c, v), L(v)):
+ *   HAMMING      k = #differing parameters
+ *   INDEX_L1     k = sum_j |v_j - c_j|
+ *   TIER_*       k = (tier, sub): tier 0 strictly adjacent (every |v_j - c_j| <= 1),
+ *                1 adjacent (every v_j is c_j or the nearest lower/higher value index of
+ *                parameter j that occurs in some solution), 2 Hamming-1, 3 otherwise;
+ *                sub = squared distance between the particle position X (Q16.16 index
+ *                units, d_pos_q16[n][n_params]) and the value centres (2 v_j + 1) * 2^15
+ *                for TIER_EUCLID, or a Philox draw at counter
+ *                (who, generation, 7<<24 | L>>32, L & 0xffffffff) for TIER_RANDOM;
+ *                in tier 3 sub is the Hamming distance.
+ * HAM1_RANDOM applies to every row: it becomes the valid Hamming-1 neighbour
+ * with the smallest Philox draw at counter (who, generation, 8<<24 | L>>32, L),
+ * or stays unchanged if it has none.
+ *   d_who[n] (nullable: row index) is the counter word naming each row.
+ * Outputs: d_out_rows[n][row_bytes], d_out_pos[n] (position of the result in
+ * the valid list, or 0xFFFFFFFF for an unchanged invalid HAM1_RANDOM row).
+ * d_out_rows may equal d_rows.
+ * Errors: CT_EEMPTY (no valid configuration), CT_EINVAL, CT_ENOMEM.
+ */
+int ct_repair(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t metric,
+              uint64_t seed, uint32_t generation, const uint32_t* d_who, const int32_t* d_pos_q16,
+              uint8_t* d_out_rows, uint32_t* d_out_pos, void* stream);
+
+/*
+ * Optimiser hyperparameters in integer form (Table IV defaults in brackets).
+ *   DE:  F_q16 = round(F * 2^16) [45875], CR_q32 = round(CR * 2^32) [2576980378],
+ *        de_best 1 = best1bin, 0 = rand1bin [1]; requires 4 <= pop_size.
+ *   PSO: w_q16 < 65536, c1_q16, c2_q16 <= 2^20  [32768, 196608, 32768].
+ *   GA:  mutation_chance X = "one in X" [5]; rank selection Beta(1, beta_b), 1 <= beta_b <= 5 [3].
+ * Every algorithm requires pop_size <= n_valid (its initial sample is stratified
+ * over the valid list, one stratum per member).
+ */
+typedef struct {
+    uint32_t algo;
+    uint32_t pop_size;
+    uint64_t seed;
+    uint32_t F_q16;
+    uint32_t de_best;
+    uint64_t CR_q32;
+    uint32_t w_q16, c1_q16, c2_q16;
+    uint32_t mutation_chance;
+    uint32_t beta_b;
+    uint32_t reserved[3];
+} ct_pop_params;
+
+/*
+ * ct_pop_create -- allocate a run and draw its initial population (generation 0).
+ * d_objective[n_valid] (float32, > 0, borrowed: must outlive the run) stands
+ * for the measured runtime of each valid configuration, indexed by position
+ * in the valid list; lower is better.
+ * Errors: CT_EINVAL (parameters), CT_EEMPTY, CT_ENOMEM.
+ */
+int ct_pop_create(const ct_space* s, const ct_pop_params* p, const float* d_objective, void* stream,
+                  ct_pop** out);
+
+/*
+ * ct_step -- advance n_pops runs by n_generations generations each.
+ * DE (Alg. 1): mutate, binomial crossover, INDEX_L1 repair, greedy selection
+ * with "u not in X", reinitialisation after a generation without change.
+ * PSO (Section IV-C): velocity/position update in Q16.16 index units,
+ * snap, TIER_EUCLID evaluation (position unchanged), personal/global best.
+ * GA (Section IV-D): sort, Beta rank selection, single-point crossover,
+ * TIER_RANDOM repair, HAM1_RANDOM mutation with chance 1/mutation_chance.
+ * Results do not depend on `flags`.  Runs may belong to different spaces.
+ */
+int ct_step(ct_pop* const* pops, uint32_t n_pops, uint32_t n_generations, uint32_t flags, void* stream);
+
+/*
+ * ct_pop_read -- copy a run's state to the host (synchronises its stream).
+ * h_pos[pop_size]: population as valid-list positions (PSO: the personal-best
+ * configurations); h_f[pop_size]: their objective values.  Any output may be
+ * NULL.  *best_pos / *best_f: best configuration found so far.
+ */
+int ct_pop_read(const ct_pop* p, uint32_t* h_pos, float* h_f, uint32_t* best_pos, float* best_f,
+                uint32_t* generation, uint32_t* reinits);
+
+/*
+ * ct_pop_snapshot / ct_pop_restore -- full run state as bytes (synchronising).
+ * Layout: uint32 header[8] = {magic 0x43545031, algo, pop_size, n_params,
+ * generation, reinits, best_pos, best_f bits}, then for DE/GA uint32 pos[P],
+ * float f[P]; for PSO int32 X[P][D], int64 V[P][D], int32 PB[P][D],
+ * float f_pb[P], uint32 pb_pos[P], uint32 gbest_index.  Call with
+ * h_buf = NULL to get the size.  A restored run continues bit-identically.
+ */
+int ct_pop_snapshot(const ct_pop* p, void* h_buf, size_t* len);
+int ct_pop_restore(ct_pop* p, const void* h_buf, size_t len);
+
+void ct_pop_free(ct_pop* p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CT_H */

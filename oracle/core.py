@@ -166,10 +166,18 @@ class Space:
         return out
 
     # -- Section IV-A: full enumeration before tuning ----------------------------------
-    def enumerate(self) -> "Space":
+    def enumerate(self, progress=None, chunk_words: int = 1 << 22) -> "Space":
+        """Every configuration, in chunks of chunk_words bitmask words (progress(msg) after each)."""
         n_words = (self.n_cartesian + 63) // 64
-        self.words = self.mask_words(0, n_words)
-        self.vlin = words_to_lin(self.words, 0)
+        self.words = np.zeros(n_words, dtype=np.uint64)
+        parts = []
+        for w0 in range(0, n_words, chunk_words):
+            w1 = min(n_words, w0 + chunk_words)
+            self.words[w0:w1] = self.mask_words(w0, w1)
+            parts.append(words_to_lin(self.words[w0:w1], w0))
+            if progress:
+                progress(f"oracle enumeration: words {w1}/{n_words}")
+        self.vlin = np.concatenate(parts) if parts else np.zeros(0, dtype=np.uint64)
         self._finish_list()
         return self
 

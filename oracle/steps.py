@@ -284,3 +284,29 @@ def ga_step(space: core.Space, obj: np.ndarray, st: GAState, seed: int, mutation
     for i in range(P):
         best = _lexmin(best, (float(f[i]), int(pos[i])))
     return GAState(pos, f, np.float32(best[0]), int(best[1]), g + 1)
+
+
+def ga_children(space: core.Space, obj: np.ndarray, st: GAState, seed: int, mutation_chance: int, beta_b: int,
+                indices, table: Optional[List[int]] = None) -> np.ndarray:
+    """Final rows of selected children of generation st.gen (same definition as ga_step).
+
+    Lets a test check a sample of a large population without computing all of it.
+    """
+    P, D, g = len(st.pos), space.D, st.gen
+    idx = np.asarray(indices, dtype=np.int64)
+    order = sorted(range(P), key=lambda i: (float(st.f[i]), int(st.pos[i])))
+    table = table or beta_rank_table(P, beta_b)
+    rows = space.vrows[st.pos]
+    kids = np.zeros((len(idx), D), dtype=np.int32)
+    for n, i in enumerate(idx):
+        o = draw(seed, int(i) // 2, g, P_GA_SEL)
+        A = rows[order[rank_from_draw(table, o[0])]]
+        B = rows[order[rank_from_draw(table, o[1])]]
+        cut = 1 + uniform_below(o[2], D - 1)
+        kids[n] = np.concatenate([A[:cut], B[cut:]]) if i % 2 == 0 else np.concatenate([B[:cut], A[cut:]])
+    kids = space.repair(kids, core.TIER_RANDOM, who=idx, key=seed, gen=g)
+    thresh = (1 << 32) // mutation_chance
+    mut = [n for n, i in enumerate(idx) if draw(seed, int(i), g, P_GA_MUT)[0] < thresh]
+    if mut:
+        kids[mut] = space.repair(kids[mut], core.HAM1_RANDOM, who=idx[mut], key=seed, gen=g)
+    return kids

@@ -1,0 +1,223 @@
+"""MI355X-native constraint-aware evolutionary auto-tuning (Python binding of libct).
+
+Thin marshalling over the C ABI of include/ct.h: torch tensors provide device
+memory and the current HIP stream; every step of the method runs in the
+library's HIP kernels.  Importing this package loads nothing; the first call
+loads lib/libct.so and raises if it was not built.
+
+    sp = Space(names, values, constraints)          # ct_compile + ct_space_build
+    sp.n_valid, sp.valid_list(), sp.bitmask()
+    sp.valid_mask(rows), sp.rank(rows), sp.repair(rows, CT_HAMMING)
+    run = Pop(sp, algo=CT_DE, pop_size=20, seed=0, objective=obj)   # ct_pop_create
+    run.step(100); run.read()                                        # ct_step, ct_pop_read
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import _lib
+from ._lib import (CT_DE, CT_GA, CT_HAM1_RANDOM, CT_HAMMING, CT_INDEX_L1, CT_PSO, CT_STEP_BATCHED,  # noqa: F401
+                   CT_STEP_GRAPH, CT_STEP_PLAIN, CT_TIER_EUCLID, CT_TIER_RANDOM, CtError, ct_pop_params)
+
+__all__ = ["Space", "Pop", "compile_constraints", "step_many", "CtError", "CT_HAMMING", "CT_INDEX_L1",
+           "CT_TIER_EUCLID", "CT_TIER_RANDOM", "CT_HAM1_RANDOM", "CT_DE", "CT_PSO", "CT_GA",
+           "CT_STEP_PLAIN", "CT_STEP_BATCHED", "CT_STEP_GRAPH"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr() if t is not None else 0)
+
+
+def compile_constraints(names: Sequence[str], values: Sequence[Sequence[int]],
+                        constraints: Sequence[str]) -> Tuple[np.ndarray, np.ndarray]:
+    """ct_compile: constraint strings -> (bytecode words, program offsets)."""
+    L = _lib.load()
+    n = len(names)
+    flat = np.ascontiguousarray([int(x) for v in values for x in v], dtype=np.int64)
+    rad = np.ascontiguousarray([len(v) for v in values], dtype=np.uint32)
+    cnames = (ctypes.c_char_p * n)(*[s.encode() for s in names])
+    ccons = (ctypes.c_char_p * max(1, len(constraints)))(*[c.encode() for c in constraints])
+    cap = 64 + 64 * sum(len(c) for c in constraints)
+    code = np.zeros(cap, dtype=np.uint32)
+    offs = np.zeros(len(constraints) + 1, dtype=np.uint32)
+    used = ctypes.c_uint32(0)
+    _lib.check(L.ct_compile(cnames, n, flat.ctypes.data, rad.ctypes.data, ccons, len(constraints),
+                            code.ctypes.data, cap, offs.ctypes.data, ctypes.byref(used)))
+    return code[: used.value].copy(), offs
+
+
+class Space:
+    """A resolved search space on the current GPU (ct_space)."""
+
+    def __init__(self, names: Sequence[str], values: Sequence[Sequence[int]], constraints: Sequence[str]):
+        L = _lib.load()
+        self.names = list(names)
+        self.values = [list(map(int, v)) for v in values]
+        self.constraints = list(constraints)
+        self.code, self.offsets = compile_constraints(self.names, self.values, self.constraints)
+        flat = np.ascontiguousarray([x for v in self.values for x in v], dtype=np.int64)
+        rad = np.ascontiguousarray([len(v) for v in self.values], dtype=np.uint32)
+        self._h = ctypes.c_void_p()
+        code = self.code if len(self.code) else np.zeros(1, dtype=np.uint32)
+        _lib.check(L.ct_space_build(flat.ctypes.data, rad.ctypes.data, len(self.names), code.ctypes.data,
+                                    self.offsets.ctypes.data, len(self.constraints), _stream(),
+                                    ctypes.byref(self._h)))
+        nv, nc = ctypes.c_uint64(), ctypes.c_uint64()
+        _lib.check(L.ct_space_count(self._h, ctypes.byref(nv), ctypes.byref(nc)))
+        d, r = ctypes.c_uint32(), ctypes.c_uint32()
+        _lib.check(L.ct_space_info(self._h, ctypes.byref(d), ctypes.byref(r)))
+        self.n_valid, self.n_cartesian = int(nv.value), int(nc.value)
+        self.D, self.row_bytes = int(d.value), int(r.value)
+
+    @classmethod
+    def from_spec(cls, spec) -> "Space":
+        return cls(spec.names, list(spec.params.values()), spec.constraints)
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def valid_list(self):
+        """(linear indices int64 [n_valid], digit rows uint8 [n_valid, row_bytes]) as new device tensors."""
+        torch = _torch()
+        lin = torch.empty(self.n_valid, dtype=torch.int64, device="cuda")
+        rows = torch.empty((self.n_valid, self.row_bytes), dtype=torch.uint8, device="cuda")
+        _lib.check(_lib.load().ct_space_copy_list(self._h, _ptr(lin), _ptr(rows), _stream()))
+        return lin, rows
+
+    def bitmask(self):
+        torch = _torch()
+        w = torch.empty((self.n_cartesian + 63) // 64, dtype=torch.int64, device="cuda")
+        _lib.check(_lib.load().ct_space_copy_bitmask(self._h, _ptr(w), _stream()))
+        return w
+
+    def pack_rows(self, digits) -> "object":
+        """Digit matrix [n, D] (any integer tensor/array) -> uint8 rows [n, row_bytes] on the GPU."""
+        torch = _torch()
+        d = torch.as_tensor(np.asarray(digits) if not isinstance(digits, torch.Tensor) else digits)
+        out = torch.zeros((d.shape[0], self.row_bytes), dtype=torch.uint8, device="cuda")
+        out[:, : self.D] = d.to(device="cuda", dtype=torch.uint8)
+        return out
+
+    def valid_mask(self, rows):
+        torch = _torch()
+        out = torch.empty(rows.shape[0], dtype=torch.uint8, device="cuda")
+        _lib.check(_lib.load().ct_valid_mask(self._h, _ptr(rows), rows.shape[0], _ptr(out), _stream()))
+        return out
+
+    def rank(self, rows):
+        torch = _torch()
+        out = torch.empty(rows.shape[0], dtype=torch.int64, device="cuda")
+        _lib.check(_lib.load().ct_rank(self._h, _ptr(rows), rows.shape[0], _ptr(out), _stream()))
+        return out
+
+    def repair(self, rows, metric: int, seed: int = 0, generation: int = 0, who=None, pos_q16=None,
+               out_rows=None, out_pos=None):
+        """ct_repair: returns (rows uint8 [n, row_bytes], positions int32 [n] (0xFFFFFFFF = none))."""
+        torch = _torch()
+        n = rows.shape[0]
+        if out_rows is None:
+            out_rows = torch.empty_like(rows)
+        if out_pos is None:
+            out_pos = torch.empty(n, dtype=torch.int32, device="cuda")
+        _lib.check(_lib.load().ct_repair(self._h, _ptr(rows), n, metric, seed, generation, _ptr(who),
+                                         _ptr(pos_q16), _ptr(out_rows), _ptr(out_pos), _stream()))
+        return out_rows, out_pos
+
+    def close(self):
+        if self._h:
+            _lib.load().ct_space_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_params(algo: int, pop_size: int, seed: int, **kw) -> ct_pop_params:
+    p = ct_pop_params()
+    p.algo, p.pop_size, p.seed = algo, pop_size, seed
+    p.F_q16, p.CR_q32, p.de_best = kw.get("F_q16", 45875), kw.get("CR_q32", 2576980378), kw.get("de_best", 1)
+    p.w_q16, p.c1_q16, p.c2_q16 = kw.get("w_q16", 32768), kw.get("c1_q16", 196608), kw.get("c2_q16", 32768)
+    p.mutation_chance, p.beta_b = kw.get("mutation_chance", 5), kw.get("beta_b", 3)
+    return p
+
+
+class Pop:
+    """One optimiser run (ct_pop) over a Space; the objective tensor must outlive it."""
+
+    def __init__(self, space: Space, algo: int, pop_size: int, seed: int, objective, **kw):
+        self.space = space
+        self.objective = objective
+        self.algo, self.pop_size = algo, pop_size
+        self.params = make_params(algo, pop_size, seed, **kw)
+        self._h = ctypes.c_void_p()
+        _lib.check(_lib.load().ct_pop_create(space.handle, ctypes.byref(self.params), _ptr(objective), _stream(),
+                                             ctypes.byref(self._h)))
+
+    @classmethod
+    def from_opt(cls, space: Space, opt, objective) -> "Pop":
+        """From a workloads.OptParams."""
+        return cls(space, opt.algo, opt.pop_size, opt.seed, objective, F_q16=opt.F_q16, CR_q32=opt.CR_q32,
+                   de_best=opt.de_best, w_q16=opt.w_q16, c1_q16=opt.c1_q16, c2_q16=opt.c2_q16,
+                   mutation_chance=opt.mutation_chance, beta_b=opt.beta_b)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def step(self, n_generations: int = 1, flags: int = CT_STEP_PLAIN):
+        step_many([self], n_generations, flags)
+
+    def read(self) -> Dict[str, object]:
+        pos = np.zeros(self.pop_size, dtype=np.uint32)
+        f = np.zeros(self.pop_size, dtype=np.float32)
+        bp, bf, g, r = ctypes.c_uint32(), ctypes.c_float(), ctypes.c_uint32(), ctypes.c_uint32()
+        _lib.check(_lib.load().ct_pop_read(self._h, pos.ctypes.data, f.ctypes.data, ctypes.byref(bp),
+                                           ctypes.byref(bf), ctypes.byref(g), ctypes.byref(r)))
+        return {"pos": pos, "f": f, "best_pos": int(bp.value), "best_f": np.float32(bf.value),
+                "generation": int(g.value), "reinits": int(r.value)}
+
+    def snapshot(self) -> bytes:
+        L = _lib.load()
+        n = ctypes.c_size_t(0)
+        _lib.check(L.ct_pop_snapshot(self._h, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _lib.check(L.ct_pop_snapshot(self._h, buf, ctypes.byref(n)))
+        return buf.raw[: n.value]
+
+    def restore(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _lib.check(_lib.load().ct_pop_restore(self._h, buf, len(blob)))
+
+    def close(self):
+        if self._h:
+            _lib.load().ct_pop_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def step_many(pops: List[Pop], n_generations: int = 1, flags: int = CT_STEP_PLAIN):
+    """ct_step over several runs (possibly of different spaces)."""
+    arr = (ctypes.c_void_p * max(1, len(pops)))(*[p.handle for p in pops])
+    _lib.check(_lib.load().ct_step(arr, len(pops), n_generations, flags, _stream()))

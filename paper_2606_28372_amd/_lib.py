@@ -1,0 +1,86 @@
+"""ctypes loader for libct.so: the C-ABI entry points of include/ct.h, same names.
+
+The library is built in-tree by `python -m paper_2606_28372_amd.build`.  There
+is no fallback: if the shared library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libct.so")
+
+CT_OK, CT_EINVAL, CT_ENOMEM, CT_EOVERFLOW, CT_EEMPTY, CT_EDEVICE, CT_ESYNTAX = 0, -1, -2, -3, -4, -5, -6
+STATUS = {CT_EINVAL: "CT_EINVAL", CT_ENOMEM: "CT_ENOMEM", CT_EOVERFLOW: "CT_EOVERFLOW", CT_EEMPTY: "CT_EEMPTY",
+          CT_EDEVICE: "CT_EDEVICE", CT_ESYNTAX: "CT_ESYNTAX"}
+CT_HAMMING, CT_INDEX_L1, CT_TIER_EUCLID, CT_TIER_RANDOM, CT_HAM1_RANDOM = 0, 1, 2, 3, 4
+CT_DE, CT_PSO, CT_GA = 0, 1, 2
+CT_STEP_PLAIN, CT_STEP_BATCHED, CT_STEP_GRAPH = 0, 1, 2
+
+
+class CtError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class ct_pop_params(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_uint32), ("pop_size", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+                ("F_q16", ctypes.c_uint32), ("de_best", ctypes.c_uint32), ("CR_q32", ctypes.c_uint64),
+                ("w_q16", ctypes.c_uint32), ("c1_q16", ctypes.c_uint32), ("c2_q16", ctypes.c_uint32),
+                ("mutation_chance", ctypes.c_uint32), ("beta_b", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 3)]
+
+
+_vp, _u32, _u64, _i32, _sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_size_t
+_P = ctypes.POINTER
+
+# name -> (restype, argtypes), exactly the declarations of include/ct.h
+SIGNATURES = {
+    "ct_last_error": (ctypes.c_char_p, []),
+    "ct_version": (_i32, []),
+    "ct_compile": (_i32, [_P(ctypes.c_char_p), _u32, _vp, _vp, _P(ctypes.c_char_p), _u32, _vp, _u32, _vp, _P(_u32)]),
+    "ct_space_build": (_i32, [_vp, _vp, _u32, _vp, _vp, _u32, _vp, _P(_vp)]),
+    "ct_space_count": (_i32, [_vp, _P(_u64), _P(_u64)]),
+    "ct_space_info": (_i32, [_vp, _P(_u32), _P(_u32)]),
+    "ct_space_valid_list": (_i32, [_vp, _P(_vp), _P(_vp)]),
+    "ct_space_bitmask": (_i32, [_vp, _P(_vp), _P(_u64)]),
+    "ct_space_copy_list": (_i32, [_vp, _vp, _vp, _vp]),
+    "ct_space_copy_bitmask": (_i32, [_vp, _vp, _vp]),
+    "ct_space_free": (None, [_vp]),
+    "ct_valid_mask": (_i32, [_vp, _vp, _u64, _vp, _vp]),
+    "ct_rank": (_i32, [_vp, _vp, _u64, _vp, _vp]),
+    "ct_repair": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _vp, _vp, _vp, _vp]),
+    "ct_pop_create": (_i32, [_vp, _P(ct_pop_params), _vp, _vp, _P(_vp)]),
+    "ct_step": (_i32, [_P(_vp), _u32, _u32, _u32, _vp]),
+    "ct_pop_read": (_i32, [_vp, _vp, _vp, _P(_u32), _P(ctypes.c_float), _P(_u32), _P(_u32)]),
+    "ct_pop_snapshot": (_i32, [_vp, _vp, _P(_sz)]),
+    "ct_pop_restore": (_i32, [_vp, _vp, _sz]),
+    "ct_pop_free": (None, [_vp]),
+}
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """The loaded libct.so; raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2606_28372_amd.build`")
+            lib = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in SIGNATURES.items():
+                fn = getattr(lib, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = lib
+    return _lib
+
+
+def check(rc: int) -> None:
+    if rc != CT_OK:
+        raise CtError(rc, load().ct_last_error().decode())

@@ -1,0 +1,483 @@
+// extern "C" entry points of libct: argument validation, handle ownership,
+// device allocation and launch sequencing.  All arithmetic of the method
+// runs in the kernels of space.hip, repair.hip and step.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ct_host.h"
+
+namespace {
+thread_local std::string g_err = "no error";
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int require_device() {
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n < 1) return ct_fail(CT_EDEVICE, "no HIP device available");
+    return CT_OK;
+}
+
+// Check a constraint program's stack discipline and operands; returns the largest parameter read (-1: none).
+int check_program(const uint32_t* code, uint32_t b, uint32_t e, uint32_t n_params, int* max_param,
+                  std::string* why) {
+    int depth = 0;
+    *max_param = -1;
+    for (uint32_t pc = b; pc < e;) {
+        uint32_t w = code[pc++];
+        uint32_t op = w & 0xFFu;
+        int32_t imm = (int32_t)w >> 8;
+        switch (op) {
+        case OP_PARAM:
+            if (imm < 0 || (uint32_t)imm >= n_params) { *why = "parameter id out of range"; return -1; }
+            *max_param = std::max(*max_param, imm);
+            depth++;
+            break;
+        case OP_CONST: depth++; break;
+        case OP_CONST64:
+            if (pc + 2 > e) { *why = "truncated 64-bit constant"; return -1; }
+            pc += 2;
+            depth++;
+            break;
+        case OP_NEG: case OP_ABS: case OP_NOT:
+            if (depth < 1) { *why = "stack underflow"; return -1; }
+            break;
+        default:
+            if (op < OP_ADD || op > OP_LAST) { *why = "unknown opcode " + std::to_string(op); return -1; }
+            if (depth < 2) { *why = "stack underflow"; return -1; }
+            depth--;
+        }
+        if (depth > CT_STACK) { *why = "stack deeper than 16"; return -1; }
+    }
+    if (depth != 1) { *why = "program must leave exactly one value"; return -1; }
+    return 0;
+}
+
+template <typename T>
+int dalloc(ct_pop* p, T** ptr, size_t n) {
+    void* q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return ct_fail(CT_ENOMEM, "hipMalloc failed");
+    p->allocs.push_back(q);
+    *ptr = reinterpret_cast<T*>(q);
+    return CT_OK;
+}
+
+}  // namespace
+
+int ct_fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+extern "C" {
+
+const char* ct_last_error(void) { return g_err.c_str(); }
+
+int ct_version(void) { return 1; }
+
+int ct_space_build(const int64_t* values, const uint32_t* radices, uint32_t n_params, const uint32_t* code,
+                   const uint32_t* cons_offsets, uint32_t n_cons, void* stream, ct_space** out) {
+    if (!values || !radices || !out || (n_cons && (!code || !cons_offsets)))
+        return ct_fail(CT_EINVAL, "ct_space_build: null argument");
+    *out = nullptr;
+    if (n_params < 1 || n_params > CT_MAX_PARAMS) return ct_fail(CT_EINVAL, "ct_space_build: 1..32 parameters supported");
+    if (n_cons > CT_MAX_PROGRAMS) return ct_fail(CT_EINVAL, "ct_space_build: at most 64 constraint programs");
+    unsigned __int128 N = 1;
+    uint32_t n_vals = 0, max_radix = 0;
+    for (uint32_t j = 0; j < n_params; j++) {
+        if (radices[j] < 1 || radices[j] > CT_MAX_RADIX) return ct_fail(CT_EINVAL, "ct_space_build: radix must be 1..255");
+        N *= radices[j];
+        n_vals += radices[j];
+        max_radix = std::max(max_radix, radices[j]);
+    }
+    if (N >= ((unsigned __int128)1 << CT_MAX_CARTESIAN_LOG2))
+        return ct_fail(CT_EINVAL, "ct_space_build: Cartesian size must be below 2^46");
+    // validate programs and sort them into prefix-only / the rest
+    std::vector<int> maxp(n_cons);
+    for (uint32_t c = 0; c < n_cons; c++) {
+        if (cons_offsets[c] > cons_offsets[c + 1]) return ct_fail(CT_EINVAL, "ct_space_build: offsets not ascending");
+        std::string why;
+        if (check_program(code, cons_offsets[c], cons_offsets[c + 1], n_params, &maxp[c], &why))
+            return ct_fail(CT_EINVAL, "ct_space_build: program " + std::to_string(c) + ": " + why);
+    }
+    int rc = require_device();
+    if (rc) return rc;
+
+    ct_space* s = new ct_space();
+    s->D = n_params;
+    s->R = n_params <= 4 ? 4 : n_params <= 8 ? 8 : n_params <= 16 ? 16 : 32;
+    s->n_cons = n_cons;
+    s->values.assign(values, values + n_vals);
+    s->radices.assign(radices, radices + n_params);
+    s->n_cartesian = (uint64_t)N;
+    (void)hipGetDevice(&s->device);
+    DevSpace& S = s->dev;
+    S.D = n_params;
+    S.R = s->R;
+    S.N = (uint64_t)N;
+    S.max_radix = max_radix;
+    // prefix split: the longest leading run of parameters whose product is at most 2^24
+    uint64_t Ps = 1;
+    uint32_t split = 0;
+    while (split < n_params && Ps * radices[split] <= (1ull << 24)) Ps *= radices[split++];
+    S.split = split;
+    S.P_s = Ps;
+    S.I_s = S.N / Ps;
+    ct_magic((uint32_t)S.I_s, &S.Is_m, &S.Is_l);
+    uint64_t stride = 1;
+    uint32_t off = 0;
+    for (uint32_t j = 0; j < n_params; j++) S.val_off[j] = 0;
+    for (uint32_t j = 0; j < n_params; j++) {
+        S.radix[j] = radices[j];
+        ct_magic(radices[j], &S.mag_m[j], &S.mag_l[j]);
+        S.val_off[j] = off;
+        off += radices[j];
+    }
+    for (uint32_t j = n_params; j-- > 0;) {
+        S.stride[j] = stride;
+        stride *= radices[j];
+    }
+    std::vector<uint32_t> order;
+    for (uint32_t c = 0; c < n_cons; c++)
+        if (maxp[c] < (int)split) order.push_back(c);
+    S.n_pre = (uint32_t)order.size();
+    for (uint32_t c = 0; c < n_cons; c++)
+        if (maxp[c] >= (int)split) order.push_back(c);
+    S.n_cons = n_cons;
+    std::vector<uint32_t> code2;
+    for (uint32_t k = 0; k < n_cons; k++) {
+        uint32_t c = order[k];
+        S.cons_off[k] = (uint32_t)code2.size();
+        code2.insert(code2.end(), code + cons_offsets[c], code + cons_offsets[c + 1]);
+    }
+    S.cons_off[n_cons] = (uint32_t)code2.size();
+    s->lds_values_bytes = (size_t)n_vals * sizeof(int64_t);
+
+    hipStream_t st = as_stream(stream);
+    auto fail = [&](int code_) {
+        ct_space_free(s);
+        return code_;
+    };
+    if (hipMalloc(&s->d_values, n_vals * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc(&s->d_code, std::max<size_t>(code2.size(), 1) * sizeof(uint32_t)) != hipSuccess)
+        return fail(ct_fail(CT_ENOMEM, "ct_space_build: hipMalloc failed"));
+    if (hipMemcpyAsync(s->d_values, values, n_vals * sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+        (code2.size() && hipMemcpyAsync(s->d_code, code2.data(), code2.size() * sizeof(uint32_t),
+                                        hipMemcpyHostToDevice, st) != hipSuccess))
+        return fail(ct_fail(CT_EDEVICE, "ct_space_build: upload failed"));
+    S.values = s->d_values;
+    S.code = s->d_code;
+    rc = space_build_device(s, st);
+    if (rc) return fail(rc);
+    *out = s;
+    return CT_OK;
+}
+
+int ct_space_count(const ct_space* s, uint64_t* n_valid, uint64_t* n_cartesian) {
+    if (!s) return ct_fail(CT_EINVAL, "ct_space_count: null space");
+    if (n_valid) *n_valid = s->n_valid;
+    if (n_cartesian) *n_cartesian = s->n_cartesian;
+    return CT_OK;
+}
+
+int ct_space_info(const ct_space* s, uint32_t* n_params, uint32_t* row_bytes) {
+    if (!s) return ct_fail(CT_EINVAL, "ct_space_info: null space");
+    if (n_params) *n_params = s->D;
+    if (row_bytes) *row_bytes = s->R;
+    return CT_OK;
+}
+
+int ct_space_valid_list(const ct_space* s, const uint64_t** d_lin, const uint8_t** d_rows) {
+    if (!s) return ct_fail(CT_EINVAL, "ct_space_valid_list: null space");
+    if (d_lin) *d_lin = s->d_lin;
+    if (d_rows) *d_rows = s->d_rows;
+    return CT_OK;
+}
+
+int ct_space_bitmask(const ct_space* s, const uint64_t** d_words, uint64_t* n_words) {
+    if (!s) return ct_fail(CT_EINVAL, "ct_space_bitmask: null space");
+    if (d_words) *d_words = s->d_words;
+    if (n_words) *n_words = s->n_words;
+    return CT_OK;
+}
+
+int ct_space_copy_list(const ct_space* s, uint64_t* d_lin, uint8_t* d_rows, void* stream) {
+    if (!s) return ct_fail(CT_EINVAL, "ct_space_copy_list: null space");
+    hipStream_t st = as_stream(stream);
+    if (s->n_valid && d_lin)
+        CT_HIP(hipMemcpyAsync(d_lin, s->d_lin, s->n_valid * 8, hipMemcpyDeviceToDevice, st));
+    if (s->n_valid && d_rows)
+        CT_HIP(hipMemcpyAsync(d_rows, s->d_rows, s->n_valid * s->R, hipMemcpyDeviceToDevice, st));
+    return CT_OK;
+}
+
+int ct_space_copy_bitmask(const ct_space* s, uint64_t* d_words, void* stream) {
+    if (!s || !d_words) return ct_fail(CT_EINVAL, "ct_space_copy_bitmask: null argument");
+    CT_HIP(hipMemcpyAsync(d_words, s->d_words, s->n_words * 8, hipMemcpyDeviceToDevice, as_stream(stream)));
+    return CT_OK;
+}
+
+void ct_space_free(ct_space* s) {
+    if (!s) return;
+    (void)hipDeviceSynchronize();
+    void* bufs[] = {s->d_values, s->d_code, s->d_prefix, s->d_words, s->d_lin, s->d_rows, s->d_prevnext};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    delete s;
+}
+
+int ct_valid_mask(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint8_t* d_out, void* stream) {
+    if (!s || (n && (!d_rows || !d_out))) return ct_fail(CT_EINVAL, "ct_valid_mask: null argument");
+    return launch_valid_mask(s, d_rows, n, d_out, as_stream(stream));
+}
+
+int ct_rank(const ct_space* s, const uint8_t* d_rows, uint64_t n, int64_t* d_pos, void* stream) {
+    if (!s || (n && (!d_rows || !d_pos))) return ct_fail(CT_EINVAL, "ct_rank: null argument");
+    return launch_rank(s, d_rows, n, d_pos, as_stream(stream));
+}
+
+int ct_repair(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t metric, uint64_t seed,
+              uint32_t generation, const uint32_t* d_who, const int32_t* d_pos_q16, uint8_t* d_out_rows,
+              uint32_t* d_out_pos, void* stream) {
+    if (!s || (n && (!d_rows || !d_out_rows || !d_out_pos))) return ct_fail(CT_EINVAL, "ct_repair: null argument");
+    if (metric > CT_HAM1_RANDOM) return ct_fail(CT_EINVAL, "ct_repair: unknown metric");
+    if (metric == CT_TIER_EUCLID && n && !d_pos_q16)
+        return ct_fail(CT_EINVAL, "ct_repair: TIER_EUCLID needs particle positions");
+    if (n > 0xFFFFFFFFull) return ct_fail(CT_EINVAL, "ct_repair: at most 2^32-1 rows per call");
+    if (s->n_valid == 0) return ct_fail(CT_EEMPTY, "ct_repair: the space has no valid configuration");
+    if (n == 0) return CT_OK;
+    hipStream_t st = as_stream(stream);
+    RepairScratch rs;
+    int rc = repair_scratch_alloc(rs, n, 0, st);
+    if (rc) return rc;
+    RepairJob J{};
+    J.S_host = &s->dev;
+    J.S = s->dev;
+    J.rows = d_rows;
+    J.n = n;
+    J.metric = metric;
+    J.seed = seed;
+    J.d_gen = nullptr;
+    J.gen_value = generation;
+    J.who = d_who;
+    J.pos_q16 = d_pos_q16;
+    J.out_rows = d_out_rows;
+    J.out_pos = d_out_pos;
+    J.apply = nullptr;
+    rc = launch_repair(s, J, rs, st);
+    repair_scratch_free(rs, st);
+    return rc;
+}
+
+int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_objective, void* stream,
+                  ct_pop** out) {
+    if (!s || !prm || !d_objective || !out) return ct_fail(CT_EINVAL, "ct_pop_create: null argument");
+    *out = nullptr;
+    const ct_pop_params& q = *prm;
+    if (q.algo > CT_GA) return ct_fail(CT_EINVAL, "ct_pop_create: unknown algorithm");
+    if (s->n_valid == 0) return ct_fail(CT_EEMPTY, "ct_pop_create: the space has no valid configuration");
+    if (q.pop_size < 1 || q.pop_size > CT_MAX_POP) return ct_fail(CT_EINVAL, "ct_pop_create: pop_size out of range");
+    if (q.pop_size > s->n_valid)
+        return ct_fail(CT_EINVAL, "ct_pop_create: pop_size exceeds the number of valid configurations");
+    if (q.algo == CT_DE && q.pop_size < 4) return ct_fail(CT_EINVAL, "ct_pop_create: DE needs pop_size >= 4");
+    if (q.algo == CT_DE && q.CR_q32 > (1ull << 32)) return ct_fail(CT_EINVAL, "ct_pop_create: CR_q32 above 2^32");
+    if (q.algo == CT_PSO && (q.w_q16 >= 65536 || q.c1_q16 > (1u << 20) || q.c2_q16 > (1u << 20)))
+        return ct_fail(CT_EINVAL, "ct_pop_create: PSO coefficients out of range");
+    if (q.algo == CT_GA && (q.mutation_chance < 1 || q.beta_b < 1 || q.beta_b > 5 || q.pop_size > 8192))
+        return ct_fail(CT_EINVAL, "ct_pop_create: GA needs mutation_chance >= 1, 1 <= beta_b <= 5, pop_size <= 8192");
+    int rc = require_device();
+    if (rc) return rc;
+    hipStream_t st = as_stream(stream);
+    ct_pop* p = new ct_pop();
+    p->space = s;
+    p->prm = q;
+    PopDev& d = p->dev;
+    d.S = s->dev;
+    d.algo = q.algo;
+    d.P = q.pop_size;
+    d.D = s->D;
+    d.R = s->R;
+    d.seed = q.seed;
+    d.F_q16 = q.F_q16;
+    d.de_best = q.de_best;
+    d.CR_q32 = q.CR_q32;
+    d.w_q16 = q.w_q16;
+    d.c1_q16 = q.c1_q16;
+    d.c2_q16 = q.c2_q16;
+    d.mut_thresh = q.algo == CT_GA ? (uint32_t)((1ull << 32) / q.mutation_chance) : 0;
+    if (q.algo == CT_GA && q.mutation_chance == 1) d.mut_thresh = 0xFFFFFFFFu;
+    d.M = s->dev.max_radix;
+    d.obj = d_objective;
+    const uint32_t P = d.P;
+    auto fail = [&](int code_) {
+        ct_pop_free(p);
+        return code_;
+    };
+    if ((rc = dalloc(p, &d.state, 4)) || (rc = dalloc(p, &d.best, 1)) || (rc = dalloc(p, &d.trial, (size_t)P * d.R)) ||
+        (rc = dalloc(p, &d.out, (size_t)P * d.R)) || (rc = dalloc(p, &d.tpos, P)) || (rc = dalloc(p, &d.apply, P)))
+        return fail(rc);
+    if (q.algo == CT_PSO) {
+        if ((rc = dalloc(p, &d.X, (size_t)P * d.D)) || (rc = dalloc(p, &d.V, (size_t)P * d.D)) ||
+            (rc = dalloc(p, &d.PB, (size_t)P * d.D)) || (rc = dalloc(p, &d.f_pb, P)) || (rc = dalloc(p, &d.pb_pos, P)))
+            return fail(rc);
+    } else {
+        if ((rc = dalloc(p, &d.pos, P)) || (rc = dalloc(p, &d.f, P))) return fail(rc);
+    }
+    if (q.algo == CT_DE) {
+        size_t words = (s->n_valid + 31) / 32;
+        if ((rc = dalloc(p, &d.member, words)) || (rc = dalloc(p, &d.claim, s->n_valid))) return fail(rc);
+        if (hipMemsetAsync(d.member, 0, words * 4, st) != hipSuccess ||
+            hipMemsetAsync(d.claim, 0xFF, s->n_valid * 4, st) != hipSuccess)
+            return fail(ct_fail(CT_EDEVICE, "ct_pop_create: memset failed"));
+    }
+    if (q.algo == CT_GA) {
+        // cumulative Beta(1, b) rank-selection thresholds: floor((P^b - (P-r-1)^b) * 2^32 / P^b)
+        std::vector<uint64_t> t(P);
+        unsigned __int128 Pb = 1;
+        for (uint32_t k = 0; k < q.beta_b; k++) Pb *= P;
+        for (uint32_t r = 0; r < P; r++) {
+            unsigned __int128 x = 1;
+            for (uint32_t k = 0; k < q.beta_b; k++) x *= (P - r - 1);
+            t[r] = (uint64_t)(((Pb - x) << 32) / Pb);
+        }
+        uint64_t* d_beta = nullptr;
+        if ((rc = dalloc(p, &d_beta, P)) || (rc = dalloc(p, &d.sorted, P))) return fail(rc);
+        if (hipMemcpy(d_beta, t.data(), P * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(ct_fail(CT_EDEVICE, "ct_pop_create: upload failed"));
+        d.beta = d_beta;
+    }
+    if ((rc = repair_scratch_alloc(p->rs, P, 0, st))) return fail(rc);
+    if ((rc = pop_init_device(p, st))) return fail(rc);
+    *out = p;
+    return CT_OK;
+}
+
+int ct_step(ct_pop* const* pops, uint32_t n_pops, uint32_t n_generations, uint32_t flags, void* stream) {
+    if (n_pops && !pops) return ct_fail(CT_EINVAL, "ct_step: null population list");
+    if (flags > CT_STEP_GRAPH) return ct_fail(CT_EINVAL, "ct_step: unknown flags");
+    for (uint32_t k = 0; k < n_pops; k++)
+        if (!pops[k]) return ct_fail(CT_EINVAL, "ct_step: null population");
+    hipStream_t st = as_stream(stream);
+    for (uint32_t g = 0; g < n_generations; g++)
+        for (uint32_t k = 0; k < n_pops; k++) {
+            int rc = pop_step_plain(pops[k], st);
+            if (rc) return rc;
+        }
+    return CT_OK;
+}
+
+int ct_pop_read(const ct_pop* p, uint32_t* h_pos, float* h_f, uint32_t* best_pos, float* best_f,
+                uint32_t* generation, uint32_t* reinits) {
+    if (!p) return ct_fail(CT_EINVAL, "ct_pop_read: null population");
+    const PopDev& d = p->dev;
+    CT_HIP(hipDeviceSynchronize());
+    if (h_pos) CT_HIP(hipMemcpy(h_pos, d.algo == CT_PSO ? d.pb_pos : d.pos, d.P * 4, hipMemcpyDeviceToHost));
+    if (h_f) CT_HIP(hipMemcpy(h_f, d.algo == CT_PSO ? d.f_pb : d.f, d.P * 4, hipMemcpyDeviceToHost));
+    uint64_t b = 0;
+    uint32_t stt[4];
+    CT_HIP(hipMemcpy(&b, d.best, 8, hipMemcpyDeviceToHost));
+    CT_HIP(hipMemcpy(stt, d.state, 16, hipMemcpyDeviceToHost));
+    if (best_pos) *best_pos = (uint32_t)b;
+    if (best_f) {
+        uint32_t o = (uint32_t)(b >> 32);
+        uint32_t bits = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
+        memcpy(best_f, &bits, 4);
+    }
+    if (generation) *generation = stt[0];
+    if (reinits) *reinits = stt[1];
+    return CT_OK;
+}
+
+static size_t snapshot_size(const PopDev& d) {
+    size_t n = 32;
+    if (d.algo == CT_PSO) n += (size_t)d.P * d.D * (4 + 8 + 4) + (size_t)d.P * 8 + 4;
+    else n += (size_t)d.P * 8;
+    return n;
+}
+
+int ct_pop_snapshot(const ct_pop* p, void* h_buf, size_t* len) {
+    if (!p || !len) return ct_fail(CT_EINVAL, "ct_pop_snapshot: null argument");
+    const PopDev& d = p->dev;
+    size_t need = snapshot_size(d);
+    if (!h_buf) { *len = need; return CT_OK; }
+    if (*len < need) return ct_fail(CT_EINVAL, "ct_pop_snapshot: buffer too small");
+    CT_HIP(hipDeviceSynchronize());
+    uint8_t* o = static_cast<uint8_t*>(h_buf);
+    uint32_t stt[4];
+    uint64_t b;
+    CT_HIP(hipMemcpy(stt, d.state, 16, hipMemcpyDeviceToHost));
+    CT_HIP(hipMemcpy(&b, d.best, 8, hipMemcpyDeviceToHost));
+    uint32_t h[8] = {0x43545031u, d.algo, d.P, d.D, stt[0], stt[1], (uint32_t)b, (uint32_t)(b >> 32)};
+    memcpy(o, h, 32);
+    o += 32;
+    if (d.algo == CT_PSO) {
+        size_t PD = (size_t)d.P * d.D;
+        CT_HIP(hipMemcpy(o, d.X, PD * 4, hipMemcpyDeviceToHost)); o += PD * 4;
+        CT_HIP(hipMemcpy(o, d.V, PD * 8, hipMemcpyDeviceToHost)); o += PD * 8;
+        CT_HIP(hipMemcpy(o, d.PB, PD * 4, hipMemcpyDeviceToHost)); o += PD * 4;
+        CT_HIP(hipMemcpy(o, d.f_pb, d.P * 4, hipMemcpyDeviceToHost)); o += d.P * 4;
+        CT_HIP(hipMemcpy(o, d.pb_pos, d.P * 4, hipMemcpyDeviceToHost)); o += d.P * 4;
+        memcpy(o, &stt[2], 4);
+    } else {
+        CT_HIP(hipMemcpy(o, d.pos, d.P * 4, hipMemcpyDeviceToHost)); o += d.P * 4;
+        CT_HIP(hipMemcpy(o, d.f, d.P * 4, hipMemcpyDeviceToHost));
+    }
+    *len = need;
+    return CT_OK;
+}
+
+int ct_pop_restore(ct_pop* p, const void* h_buf, size_t len) {
+    if (!p || !h_buf) return ct_fail(CT_EINVAL, "ct_pop_restore: null argument");
+    PopDev& d = p->dev;
+    if (len != snapshot_size(d)) return ct_fail(CT_EINVAL, "ct_pop_restore: size mismatch");
+    const uint8_t* o = static_cast<const uint8_t*>(h_buf);
+    uint32_t h[8];
+    memcpy(h, o, 32);
+    o += 32;
+    if (h[0] != 0x43545031u || h[1] != d.algo || h[2] != d.P || h[3] != d.D)
+        return ct_fail(CT_EINVAL, "ct_pop_restore: snapshot is for a different run shape");
+    CT_HIP(hipDeviceSynchronize());
+    uint32_t stt[4] = {h[4], h[5], 0, 0};
+    uint64_t b = ((uint64_t)h[7] << 32) | h[6];
+    if (d.algo == CT_PSO) {
+        size_t PD = (size_t)d.P * d.D;
+        CT_HIP(hipMemcpy(d.X, o, PD * 4, hipMemcpyHostToDevice)); o += PD * 4;
+        CT_HIP(hipMemcpy(d.V, o, PD * 8, hipMemcpyHostToDevice)); o += PD * 8;
+        CT_HIP(hipMemcpy(d.PB, o, PD * 4, hipMemcpyHostToDevice)); o += PD * 4;
+        CT_HIP(hipMemcpy(d.f_pb, o, d.P * 4, hipMemcpyHostToDevice)); o += d.P * 4;
+        CT_HIP(hipMemcpy(d.pb_pos, o, d.P * 4, hipMemcpyHostToDevice)); o += d.P * 4;
+        memcpy(&stt[2], o, 4);
+    } else {
+        std::vector<uint32_t> pos(d.P);
+        memcpy(pos.data(), o, d.P * 4);
+        CT_HIP(hipMemcpy(d.pos, o, d.P * 4, hipMemcpyHostToDevice)); o += d.P * 4;
+        CT_HIP(hipMemcpy(d.f, o, d.P * 4, hipMemcpyHostToDevice));
+        if (d.algo == CT_DE) {
+            // membership bitmap is derived from the positions
+            std::vector<uint32_t> words((p->space->n_valid + 31) / 32, 0);
+            for (uint32_t v : pos) {
+                if (v >= p->space->n_valid) return ct_fail(CT_EINVAL, "ct_pop_restore: position out of range");
+                words[v >> 5] |= 1u << (v & 31u);
+            }
+            CT_HIP(hipMemcpy(d.member, words.data(), words.size() * 4, hipMemcpyHostToDevice));
+        }
+    }
+    CT_HIP(hipMemcpy(d.state, stt, 16, hipMemcpyHostToDevice));
+    CT_HIP(hipMemcpy(d.best, &b, 8, hipMemcpyHostToDevice));
+    return CT_OK;
+}
+
+void ct_pop_free(ct_pop* p) {
+    if (!p) return;
+    (void)hipDeviceSynchronize();
+    repair_scratch_free(p->rs, nullptr);
+    (void)hipDeviceSynchronize();
+    for (void* q : p->allocs) (void)hipFree(q);
+    delete p;
+}
+
+}  // extern "C"

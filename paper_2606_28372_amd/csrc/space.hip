@@ -1,0 +1,379 @@
+// Search-space resolution on the GPU (Section IV-A: the whole space is
+// enumerated before tuning, giving the list of valid configurations).
+//
+// Layout of the work: a "group" is 64 bitmask words = 4096 consecutive linear
+// indices, owned by one wave.  In each of 64 steps the wave's lanes take 64
+// consecutive configurations, decode them, run the constraint programs and
+// ballot the results into one word, which stays in the register of lane k;
+// the 64 words leave with one coalesced 512-byte store.
+//
+// Constraint scopes are hoisted: programs that only read the first `split`
+// parameters are evaluated once per prefix (a bit table over prod_{j<split}
+// r_j prefixes), and a group whose prefixes are all invalid is written as
+// zeros without decoding anything.  The valid list is then compacted in
+// ascending order: per-group counts, a two-level exclusive scan, and a
+// per-wave emission stage that spreads the group's valid indices over the
+// wave's lanes through LDS before decoding their digit rows.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "ct_host.h"
+
+namespace {
+
+constexpr int kBlock = 256;            // 4 waves
+constexpr int kWavesPerBlock = kBlock / 64;
+constexpr int kTileGroups = 256;       // groups per scan tile
+constexpr int kEmit = 256;             // LDS entries per wave in the emission stage
+
+__device__ __forceinline__ void load_values_lds(const DevSpace& S, int64_t* lds, uint32_t n_vals) {
+    for (uint32_t i = threadIdx.x; i < n_vals; i += blockDim.x) lds[i] = S.values[i];
+    __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t lane) {
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o) x += y;
+    }
+    return x - v;
+}
+
+// Bits for linear indices x in [0, total) (total <= 2^32) under programs [0, c1),
+// decoding only parameters [0, dlim).  One group (64 words) per wave.
+__global__ __launch_bounds__(kBlock) void k_table(DevSpace S, uint64_t total, uint32_t dlim, uint32_t c1,
+                                                  uint32_t n_vals, uint64_t n_words, uint64_t* __restrict__ words,
+                                                  uint32_t* __restrict__ group_counts) {
+    extern __shared__ int64_t lds_vals[];
+    load_values_lds(S, lds_vals, n_vals);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t g = (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const uint64_t base = g * 4096u;
+    if (base >= total) return;
+    uint64_t mine = 0;
+    for (uint32_t k = 0; k < 64; ++k) {
+        uint64_t x = base + k * 64u + lane;
+        bool ok = x < total;
+        if (__any(ok)) {
+            Row r;
+#pragma unroll
+            for (int q = 0; q < CT_DMAX / 4; ++q) r.w[q] = 0;
+            decode_range(S, (uint32_t)(ok ? x : 0), 0, dlim, r);
+            ok = ok && ct_eval(S, 0, c1, r, lds_vals);
+        }
+        uint64_t b = __ballot(ok);
+        if (lane == k) mine = b;
+    }
+    uint64_t w = g * 64u + lane;
+    if (w < n_words) words[w] = mine;
+    if (group_counts) {
+        uint32_t c = wave_sum((uint32_t)__popcll(mine));
+        if (lane == 0) group_counts[g] = c;
+    }
+}
+
+// Full bitmask when a prefix table exists (split < D).
+__global__ __launch_bounds__(kBlock) void k_mask(DevSpace S, uint32_t n_vals, uint64_t n_words,
+                                                 uint64_t* __restrict__ words, uint32_t* __restrict__ group_counts) {
+    extern __shared__ int64_t lds_vals[];
+    load_values_lds(S, lds_vals, n_vals);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t g = (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const uint64_t L0 = g * 4096u;
+    if (L0 >= S.N) return;
+    const uint64_t last = std::min<uint64_t>(L0 + 4095u, S.N - 1);
+    const uint64_t p0 = L0 / S.I_s;
+    const uint32_t r0 = (uint32_t)(L0 - p0 * S.I_s);
+    const uint64_t p_hi = last / S.I_s;
+    // does any prefix spanned by the group hold?
+    bool any = false;
+    for (uint64_t wlo = p0 >> 6; wlo <= (p_hi >> 6) && !any; wlo += 64) {
+        uint64_t wi = wlo + lane;
+        uint64_t bits = 0;
+        if (wi <= (p_hi >> 6)) {
+            bits = S.prefix_words[wi];
+            if (wi == (p0 >> 6)) bits &= ~0ull << (p0 & 63u);
+            if (wi == (p_hi >> 6) && (p_hi & 63u) != 63u) bits &= (2ull << (p_hi & 63u)) - 1ull;
+        }
+        any = __any(bits != 0);
+    }
+    uint64_t mine = 0;
+    if (any) {
+        for (uint32_t k = 0; k < 64; ++k) {
+            const uint32_t off = k * 64u + lane;
+            const uint64_t L = L0 + off;
+            const uint32_t x = r0 + off;
+            const uint32_t q = ct_udiv(x, S.Is_m, S.Is_l);
+            const uint32_t inner = x - q * (uint32_t)S.I_s;
+            const uint64_t p = p0 + q;
+            const bool inr = L < S.N;
+            const uint64_t pp = inr ? p : 0u;     // p < P_s whenever L < N
+            bool ok = inr && ((S.prefix_words[pp >> 6] >> (pp & 63u)) & 1ull);
+            if (__any(ok)) {
+                Row r;
+#pragma unroll
+                for (int t = 0; t < CT_DMAX / 4; ++t) r.w[t] = 0;
+                decode_range(S, ok ? (uint32_t)p : 0u, 0, S.split, r);
+                decode_range(S, ok ? inner : 0u, S.split, S.D, r);
+                ok = ok && ct_eval(S, S.n_pre, S.n_cons, r, lds_vals);
+            }
+            uint64_t b = __ballot(ok);
+            if (lane == k) mine = b;
+        }
+    }
+    uint64_t w = g * 64u + lane;
+    if (w < n_words) words[w] = mine;
+    uint32_t c = wave_sum((uint32_t)__popcll(mine));
+    if (lane == 0) group_counts[g] = c;
+}
+
+// Sum of each tile of kTileGroups group counts.
+__global__ __launch_bounds__(kTileGroups) void k_tile_sums(const uint32_t* __restrict__ counts, uint64_t n_groups,
+                                                           uint64_t* __restrict__ tile_sums) {
+    __shared__ uint64_t part[kTileGroups / 64];
+    uint64_t g = (uint64_t)blockIdx.x * kTileGroups + threadIdx.x;
+    uint32_t v = g < n_groups ? counts[g] : 0u;
+    uint32_t s = wave_sum(v);
+    if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int i = 0; i < kTileGroups / 64; ++i) t += part[i];
+        tile_sums[blockIdx.x] = t;
+    }
+}
+
+// Exclusive scan of the tile sums by one block; total at tile_off[n_tiles].
+__global__ __launch_bounds__(1024) void k_scan_tiles(const uint64_t* __restrict__ tile_sums, uint64_t n_tiles,
+                                                     uint64_t* __restrict__ tile_off) {
+    __shared__ uint64_t buf[1024];
+    __shared__ uint64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint64_t b = 0; b < n_tiles; b += 1024) {
+        uint64_t i = b + threadIdx.x;
+        uint64_t v = i < n_tiles ? tile_sums[i] : 0;
+        buf[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            uint64_t y = threadIdx.x >= (unsigned)o ? buf[threadIdx.x - o] : 0;
+            __syncthreads();
+            buf[threadIdx.x] += y;
+            __syncthreads();
+        }
+        if (i < n_tiles) tile_off[i] = carry + buf[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += buf[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tile_off[n_tiles] = carry;
+}
+
+// Ascending valid list from the bitmask: one group per wave.
+__global__ __launch_bounds__(kBlock) void k_compact(DevSpace S, const uint64_t* __restrict__ words, uint64_t n_words,
+                                                    const uint32_t* __restrict__ counts,
+                                                    const uint64_t* __restrict__ tile_off, uint64_t n_groups,
+                                                    uint64_t* __restrict__ lin, uint8_t* __restrict__ rows) {
+    __shared__ uint64_t emit[kWavesPerBlock][kEmit];
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint64_t g = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
+    if (g >= n_groups) return;
+    const uint64_t tile = g / kTileGroups;
+    // offset of this group = tile offset + counts of earlier groups in the tile
+    uint32_t before = 0;
+    for (uint64_t t = tile * kTileGroups + lane; t < g; t += 64) before += counts[t];
+    const uint64_t base = tile_off[tile] + wave_sum(before);
+    const uint64_t wi = g * 64u + lane;
+    uint64_t rem = wi < n_words ? words[wi] : 0ull;
+    const uint32_t c = (uint32_t)__popcll(rem);
+    const uint32_t excl = wave_excl_scan(c, lane);
+    const uint32_t total = wave_sum(c);
+    uint32_t e = excl;                       // list index (within the group) of the lane's next bit
+    for (uint32_t cs = 0; cs < total; cs += kEmit) {
+        const uint32_t ce = cs + kEmit;
+        while (rem && e < ce) {
+            uint32_t b = (uint32_t)__ffsll((long long)rem) - 1u;
+            rem &= rem - 1ull;
+            emit[wv][e - cs] = wi * 64u + b;
+            ++e;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t nchunk = std::min<uint32_t>(kEmit, total - cs);
+        for (uint32_t i = lane; i < nchunk; i += 64) {
+            const uint64_t L = emit[wv][i];
+            const uint64_t pos = base + cs + i;
+            Row r;
+            decode_lin(S, L, r);
+            lin[pos] = L;
+            row_store(r, rows + pos * S.R, S.R);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// Which value indices of each parameter occur in some solution, then the
+// nearest present index below/above each index ("adjacent" neighbour rule).
+__global__ __launch_bounds__(kBlock) void k_presence(DevSpace S, uint32_t* __restrict__ present /*[D][8]*/) {
+    __shared__ uint32_t loc[CT_DMAX * 8];
+    for (uint32_t i = threadIdx.x; i < CT_DMAX * 8; i += blockDim.x) loc[i] = 0;
+    __syncthreads();
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < S.n_valid;
+         v += (uint64_t)gridDim.x * blockDim.x) {
+        Row r;
+        row_load(r, S.rows + v * S.R, S.R);
+        for (uint32_t j = 0; j < S.D; ++j) {
+            uint32_t d = r.digit(j);
+            atomicOr(&loc[j * 8 + (d >> 5)], 1u << (d & 31u));
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < S.D * 8; i += blockDim.x)
+        if (loc[i]) atomicOr(&present[i], loc[i]);
+}
+
+__global__ void k_prevnext(uint32_t D, const uint32_t* __restrict__ present, uint8_t* __restrict__ pn) {
+    uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= D * 256u) return;
+    uint32_t j = t >> 8, k = t & 255u;
+    auto has = [&](uint32_t v) { return (present[j * 8 + (v >> 5)] >> (v & 31u)) & 1u; };
+    uint32_t prev = 0xFF, next = 0xFF;
+    for (int v = (int)k - 1; v >= 0; --v)
+        if (has((uint32_t)v)) { prev = (uint32_t)v; break; }
+    for (uint32_t v = k + 1; v < 256; ++v)
+        if (has(v)) { next = v; break; }
+    pn[t * 2 + 0] = (uint8_t)prev;
+    pn[t * 2 + 1] = (uint8_t)next;
+}
+
+__global__ __launch_bounds__(kBlock) void k_valid_rows(DevSpace S, uint32_t n_vals, const uint8_t* __restrict__ rows,
+                                                       uint64_t n, uint8_t* __restrict__ out) {
+    extern __shared__ int64_t lds_vals[];
+    load_values_lds(S, lds_vals, n_vals);
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n; base += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t i = base + threadIdx.x;
+        bool in = i < n;
+        Row r;
+        if (in) row_load(r, rows + i * S.R, S.R);
+        else
+            for (int q = 0; q < CT_DMAX / 4; ++q) r.w[q] = 0;
+        bool ok = in && row_in_domain(S, r);
+        if (!ok) {
+#pragma unroll
+            for (int q = 0; q < CT_DMAX / 4; ++q) r.w[q] = 0;
+        }
+        ok = ct_eval(S, 0, S.n_cons, r, lds_vals) && ok;
+        if (in) out[i] = ok ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_rank(DevSpace S, const uint8_t* __restrict__ rows, uint64_t n,
+                                                 int64_t* __restrict__ pos) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Row r;
+    row_load(r, rows + i * S.R, S.R);
+    pos[i] = row_in_domain(S, r) ? rank_of(S, row_encode(S, r)) : -1;
+}
+
+uint32_t grid_for(uint64_t items, uint32_t per_block, uint32_t cap = 0x7FFFFFFFu) {
+    uint64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    return (uint32_t)std::min<uint64_t>(g, cap);
+}
+
+}  // namespace
+
+int space_build_device(ct_space* s, hipStream_t st) {
+    DevSpace& S = s->dev;
+    const uint32_t n_vals = (uint32_t)s->values.size();
+    const size_t lds = s->lds_values_bytes;
+    const uint64_t n_groups = (S.N + 4095u) / 4096u;
+    s->n_words = (S.N + 63u) / 64u;
+    const uint64_t n_words_alloc = n_groups * 64u;
+    uint32_t* d_counts = nullptr;
+    uint64_t* d_tiles = nullptr;
+    uint64_t* d_off = nullptr;
+    const uint64_t n_tiles = (n_groups + kTileGroups - 1) / kTileGroups;
+    CT_HIP(hipMalloc(&s->d_words, n_words_alloc * sizeof(uint64_t)));
+    CT_HIP(hipMallocAsync((void**)&d_counts, n_groups * sizeof(uint32_t), st));
+    CT_HIP(hipMallocAsync((void**)&d_tiles, n_tiles * sizeof(uint64_t), st));
+    CT_HIP(hipMallocAsync((void**)&d_off, (n_tiles + 1) * sizeof(uint64_t), st));
+
+    if (S.split == S.D) {
+        // the whole space is one table
+        hipLaunchKernelGGL(k_table, dim3(grid_for(n_groups, kWavesPerBlock)), dim3(kBlock), lds, st, S, S.N, S.D,
+                           S.n_cons, n_vals, s->n_words, s->d_words, d_counts);
+    } else {
+        const uint64_t p_groups = (S.P_s + 4095u) / 4096u;
+        CT_HIP(hipMalloc(&s->d_prefix, p_groups * 64u * sizeof(uint64_t)));
+        hipLaunchKernelGGL(k_table, dim3(grid_for(p_groups, kWavesPerBlock)), dim3(kBlock), lds, st, S, S.P_s,
+                           S.split, S.n_pre, n_vals, p_groups * 64u, s->d_prefix, (uint32_t*)nullptr);
+        S.prefix_words = s->d_prefix;
+        hipLaunchKernelGGL(k_mask, dim3(grid_for(n_groups, kWavesPerBlock)), dim3(kBlock), lds, st, S, n_vals,
+                           s->n_words, s->d_words, d_counts);
+    }
+    CT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_tile_sums, dim3((uint32_t)n_tiles), dim3(kTileGroups), 0, st, d_counts, n_groups, d_tiles);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, d_tiles, n_tiles, d_off);
+    CT_HIP(hipGetLastError());
+    uint64_t total = 0;
+    CT_HIP(hipMemcpyAsync(&total, d_off + n_tiles, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    CT_HIP(hipStreamSynchronize(st));
+    s->n_valid = total;
+    S.n_valid = total;
+    const uint64_t alloc_n = total ? total : 1;
+    CT_HIP(hipMalloc(&s->d_lin, alloc_n * sizeof(uint64_t)));
+    CT_HIP(hipMalloc(&s->d_rows, alloc_n * S.R));
+    CT_HIP(hipMalloc(&s->d_prevnext, (size_t)S.D * 256 * 2));
+    uint32_t* d_present = nullptr;
+    CT_HIP(hipMallocAsync((void**)&d_present, (size_t)S.D * 8 * sizeof(uint32_t), st));
+    CT_HIP(hipMemsetAsync(d_present, 0, (size_t)S.D * 8 * sizeof(uint32_t), st));
+    if (total) {
+        hipLaunchKernelGGL(k_compact, dim3(grid_for(n_groups, kWavesPerBlock)), dim3(kBlock), 0, st, S, s->d_words,
+                           s->n_words, d_counts, d_off, n_groups, s->d_lin, s->d_rows);
+    }
+    S.lin = s->d_lin;
+    S.rows = s->d_rows;
+    if (total) {
+        hipLaunchKernelGGL(k_presence, dim3(grid_for(total, kBlock, 1024)), dim3(kBlock), 0, st, S, d_present);
+    }
+    hipLaunchKernelGGL(k_prevnext, dim3(grid_for(S.D * 256u, 256)), dim3(256), 0, st, S.D, d_present,
+                       s->d_prevnext);
+    S.prevnext = s->d_prevnext;
+    CT_HIP(hipGetLastError());
+    CT_HIP(hipFreeAsync(d_present, st));
+    CT_HIP(hipFreeAsync(d_counts, st));
+    CT_HIP(hipFreeAsync(d_tiles, st));
+    CT_HIP(hipFreeAsync(d_off, st));
+    CT_HIP(hipStreamSynchronize(st));
+    return CT_OK;
+}
+
+int launch_valid_mask(const ct_space* s, const uint8_t* rows, uint64_t n, uint8_t* out, hipStream_t st) {
+    if (n == 0) return CT_OK;
+    hipLaunchKernelGGL(k_valid_rows, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), s->lds_values_bytes, st, s->dev,
+                       (uint32_t)s->values.size(), rows, n, out);
+    CT_HIP(hipGetLastError());
+    return CT_OK;
+}
+
+int launch_rank(const ct_space* s, const uint8_t* rows, uint64_t n, int64_t* pos, hipStream_t st) {
+    if (n == 0) return CT_OK;
+    hipLaunchKernelGGL(k_rank, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, st, s->dev, rows, n, pos);
+    CT_HIP(hipGetLastError());
+    return CT_OK;
+}

@@ -1,0 +1,70 @@
+"""CPU checks of the C-ABI library: it loads, exports every function that
+include/ct.h declares, and its constraint compiler (host-only, no GPU) emits
+bytecode whose documented semantics match Python's on random expressions."""
+import ctypes
+import os
+import re
+
+import hypothesis.strategies as st
+import numpy as np
+import pytest
+from hypothesis import given, settings, HealthCheck
+
+from paper_2606_28372_amd import _lib, compile_constraints, CtError
+from tests.helpers import bytecode
+from tests.test_oracle_expr import exprs, py_value
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "ct.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?(?:int|void|char\s*\*|const char\s*\*)\s*\*?\s*(ct_\w+)\s*\(",
+                                 src, flags=re.M)))
+
+
+def test_library_exports_every_declared_function():
+    lib = _lib.load()
+    names = header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.SIGNATURES), "binding and header disagree"
+    assert lib.ct_version() == 1
+
+
+def eval_compiled(code, offs, k, pv):
+    return bytecode.run(code, int(offs[k]), int(offs[k + 1]), pv)
+
+
+@settings(max_examples=300, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(e=exprs(3), a=st.integers(-6, 6), b=st.integers(-6, 6), c=st.integers(-6, 6))
+def test_compiled_programs_follow_python(e, a, b, c):
+    env = {"a": a, "b": b, "c": c}
+    code, offs = compile_constraints(["a", "b", "c"], [[a], [b], [c]], [e])
+    v, raised = py_value(e, env)
+    got, graised = eval_compiled(code, offs, 0, [a, b, c])
+    if raised:
+        assert graised
+    else:
+        assert not graised and got == v
+
+
+@pytest.mark.parametrize("bad,code", [
+    ("a / 2 > 1", _lib.CT_ESYNTAX), ("a ** 2 > 1", _lib.CT_ESYNTAX), ("zz > 1", _lib.CT_ESYNTAX),
+    ("a > 1.5", _lib.CT_ESYNTAX), ("'x' == a", _lib.CT_ESYNTAX), ("foo(a) > 1", _lib.CT_ESYNTAX),
+    ("a << 2 > 1", _lib.CT_ESYNTAX), ("(a > 1", _lib.CT_ESYNTAX), ("a > 1)", _lib.CT_ESYNTAX),
+    ("a * a * a * a * a > 1", _lib.CT_EOVERFLOW),
+])
+def test_compile_errors(bad, code):
+    with pytest.raises(CtError) as ei:
+        compile_constraints(["a"], [[1, 2 ** 20]], [bad])
+    assert ei.value.code == code
+
+
+def test_large_constants_and_precedence():
+    code, offs = compile_constraints(["a"], [[3]], ["a * 10_000_000_000 == 30000000000", "-a * 2 == -6",
+                                                    "not a == 4", "0x10 + a == 19", "True + a == 4"])
+    for k in range(5):
+        assert eval_compiled(code, offs, k, [3]) == (1, False)
