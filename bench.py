@@ -1,0 +1,213 @@
+"""Benchmark of the constraint-aware auto-tuning hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload gemm|gemm10|tiny|sparse16]
+
+A step is one pass of the whole path over the workload: compile the
+constraints and resolve the space (enumeration + compaction), then create and
+run every optimiser run of the workload for its generations (propose,
+validity, repair, mutation, selection), reading the results back.  Inputs
+(value lists, constraint text, objective tables) are resident before the
+timed region.  One JSON line is printed:
+
+  value      configurations checked per second (every Cartesian configuration
+             in the space build plus every proposal validated by a generation),
+  repairs_per_s, mutation_scans_per_s, generations_per_s_plain,
+  roofline   for the kernel that takes most of the step (HIP events around its
+             launches on its stream, over the timed steps),
+  cpu_baseline  the oracle on the host cores on a bounded sample of the same job.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads as W  # noqa: E402
+
+METRIC = "configs checked/s + repairs/s; batched vs plain generations/s on 1 GPU"
+
+# MI355X published peaks and the derived integer-ALU peak
+HBM_PEAK_GBS = 8000.0
+N_CU, CLOCK_GHZ, LANES_PER_CU_CLK = 256, 2.4, 64
+ALU_PEAK_TOPS = N_CU * LANES_PER_CU_CLK * CLOCK_GHZ * 1e9 / 1e12          # 32-bit lane ops: 39.3 T/s
+BYTE_PEAK_TOPS = 4 * ALU_PEAK_TOPS                                           # 4 byte lanes per op: 157.3 T/s
+
+WORKLOADS = {
+    "gemm": ("gemm13", "13-parameter GEMM-like space (16,000,000 configurations, 206,786 valid); "
+                       "DE, PSO and GA with population 1024, {G} generations each"),
+    "gemm10": ("gemm10", "10-parameter GEMM-like space (128,000 configurations, 3,629 valid); "
+                         "DE, PSO and GA with population 1024, {G} generations each"),
+    "tiny": ("tiny", "3-parameter thread-block space (168 configurations, 100 valid); DE population 20, "
+                     "{G} generations"),
+    "sparse16": ("sparse16", "16-parameter sparse space (4,353,564,672 configurations, 4,657,116 valid); "
+                             "GA population 4096, {G} generations"),
+}
+CONFIG_KEY = {"gemm": "gemm", "gemm10": "gemm10", "tiny": "tiny", "sparse16": "sparse16"}
+
+
+def kernel_names():
+    return ["k_table", "k_mask", "k_tile_sums", "k_scan_tiles", "k_compact", "k_presence", "k_prevnext",
+            "k_repair_prep", "k_repair_scan", "k_repair_finish", "k_init", "k_init_finish", "k_de_propose",
+            "k_de_select", "k_pso_move", "k_pso_select", "k_ga_sort", "k_ga_cross", "k_ga_select"]
+
+
+def run_job(ct, spec, runs, objective_t, gens):
+    """One pass of the whole path; returns (space stats, per-run counters)."""
+    import torch
+    sp = ct.Space.from_spec(spec)
+    pops = [ct.Pop.from_opt(sp, opt, objective_t) for opt in runs]
+    for p in pops:
+        p.step(gens)
+    out = []
+    for p in pops:
+        r = p.read()
+        c = p.counters()
+        out.append((r, c))
+        p.close()
+    torch.cuda.synchronize()
+    stats = (sp.n_cartesian, sp.n_valid)
+    sp.close()
+    return stats, out
+
+
+def cpu_baseline(spec, runs, obj, gens):
+    """The oracle on the host cores: full space build plus one generation of every run,
+    extrapolated to the job's generation count (same unit as value)."""
+    from oracle import core as ocore
+    from oracle import steps as ost
+    t0 = time.perf_counter()
+    osp = ocore.Space.from_spec(spec).enumerate()
+    t_build = time.perf_counter() - t0
+    t_gens = 0.0
+    for opt in runs:
+        if opt.algo == W.ALGO_DE:
+            st = ost.de_init(osp, obj, opt.pop_size, opt.seed)
+            t1 = time.perf_counter()
+            ost.de_step(osp, obj, st, opt.seed, opt.F_q16, opt.CR_q32, bool(opt.de_best))
+        elif opt.algo == W.ALGO_PSO:
+            st = ost.pso_init(osp, obj, opt.pop_size, opt.seed)
+            t1 = time.perf_counter()
+            ost.pso_step(osp, obj, st, opt.seed, opt.w_q16, opt.c1_q16, opt.c2_q16)
+        else:
+            st = ost.ga_init(osp, obj, opt.pop_size, opt.seed)
+            t1 = time.perf_counter()
+            ost.ga_step(osp, obj, st, opt.seed, opt.mutation_chance, opt.beta_b)
+        t_gens += time.perf_counter() - t1
+    checked = osp.n_cartesian + gens * sum(o.pop_size for o in runs)
+    t_job = t_build + gens * t_gens
+    return {"value": checked / t_job, "unit": "configs/s", "cores": ocore.num_threads(), "kind": "oracle",
+            "sample": (f"oracle: full space build ({osp.n_cartesian} configurations, {t_build:.2f} s) plus one "
+                       f"generation of each of the {len(runs)} runs ({t_gens:.2f} s), extrapolated to "
+                       f"{gens} generations per run")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="gemm", choices=sorted(WORKLOADS))
+    ap.add_argument("--generations", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2606_28372_amd as ct
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    space_name, desc = WORKLOADS[args.workload]
+    cfg = W.CONFIGS[CONFIG_KEY[args.workload]]
+    gens = args.generations if args.generations is not None else cfg["generations"]
+    runs = cfg["runs"]
+    spec = W.space(space_name)
+
+    # resident inputs: objective table sized by the valid set (one untimed resolution to size it)
+    probe = ct.Space.from_spec(spec)
+    n_valid = probe.n_valid
+    probe.close()
+    obj = W.objective(n_valid, cfg["obj_seed"])
+    obj_t = torch.tensor(obj, device="cuda")
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        run_job(ct, spec, runs, obj_t, gens)
+
+    ct.prof_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(args.steps):
+        results.append(run_job(ct, spec, runs, obj_t, gens))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = dt * 1e3 / args.steps
+
+    per_kernel = {k: ct.prof_read(k) for k in kernel_names()}
+    ct.prof_enable(False)
+    n_cart = results[0][0][0]
+    checked = n_cart + gens * sum(o.pop_size for o in runs)
+    repairs = sum(c["repairs"] for _, rc in results for _, c in rc) / args.steps
+    mutations = sum(c["mutations"] for _, rc in results for _, c in rc) / args.steps
+    gens_total = gens * len(runs)
+
+    # dominant kernel and its roofline
+    dom = max(per_kernel, key=lambda k: per_kernel[k][0])
+    dom_ms, dom_n = per_kernel[dom]
+    avg_ms = dom_ms / max(dom_n, 1)
+    D = len(spec.params)
+    if dom == "k_repair_scan":
+        # each scanned (candidate, valid row) pair compares D digit pairs; the chip's densest
+        # byte instruction does 4 digit pairs per lane op
+        pairs = (repairs + mutations) * n_valid
+        ops = pairs * D / max(dom_n / args.steps, 1)              # per launch
+        achieved = ops / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": BYTE_PEAK_TOPS, "unit": "Tdigitop/s",
+                "frac": achieved / BYTE_PEAK_TOPS, "traffic": None, "kernel": dom, "avg_launch_ms": avg_ms}
+    else:
+        # enumeration kernels: one validity bit written per configuration
+        nbytes = n_cart / 8 / max(dom_n / args.steps, 1)
+        achieved = nbytes / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom, "avg_launch_ms": avg_ms}
+
+    line = {
+        "metric": METRIC,
+        "value": checked / (ms_step * 1e-3),
+        "unit": "configs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": desc.format(G=gens), "space": space_name, "configurations": n_cart,
+                   "valid": n_valid, "runs": [W.ALGO_NAMES[o.algo] for o in runs],
+                   "population": [o.pop_size for o in runs], "generations": gens},
+        "repairs_per_s": repairs / (ms_step * 1e-3),
+        "mutation_scans_per_s": mutations / (ms_step * 1e-3),
+        "generations_per_s_plain": gens_total / (ms_step * 1e-3),
+        "generations_per_s_batched": None,
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in per_kernel.items() if v[1]},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(spec, runs, obj, gens)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -241,6 +241,10 @@ int ct_step(ct_pop* const* pops, uint32_t n_pops, uint32_t n_generations, uint32
 int ct_pop_read(const ct_pop* p, uint32_t* h_pos, float* h_f, uint32_t* best_pos, float* best_f,
                 uint32_t* generation, uint32_t* reinits);
 
+/* Cumulative number of configurations the run has sent through a repair scan
+   (invalid proposals) and through a mutation scan (GA).  Synchronises. */
+int ct_pop_counters(const ct_pop* p, uint64_t* repairs, uint64_t* mutations);
+
 /*
  * ct_pop_snapshot / ct_pop_restore -- full run state as bytes (synchronising).
  * Layout: uint32 header[8] = {magic 0x43545031, algo, pop_size, n_params,
@@ -253,6 +257,17 @@ int ct_pop_snapshot(const ct_pop* p, void* h_buf, size_t* len);
 int ct_pop_restore(ct_pop* p, const void* h_buf, size_t len);
 
 void ct_pop_free(ct_pop* p);
+
+/*
+ * Kernel timing (measurement support, not part of the method).  While enabled,
+ * the library records a pair of HIP events on the launch stream around every
+ * kernel launch; ct_prof_read synchronises and returns the summed elapsed time
+ * and the number of launches of the kernel with the given base name (for
+ * example "k_repair_scan", "k_mask", "k_de_select").  Enabling or disabling
+ * clears the records.
+ */
+int ct_prof_enable(int on);
+int ct_prof_read(const char* kernel, double* total_ms, uint64_t* launches);
 
 #ifdef __cplusplus
 }

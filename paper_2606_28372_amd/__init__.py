@@ -193,6 +193,11 @@ class Pop:
         return {"pos": pos, "f": f, "best_pos": int(bp.value), "best_f": np.float32(bf.value),
                 "generation": int(g.value), "reinits": int(r.value)}
 
+    def counters(self) -> Dict[str, int]:
+        r, m = ctypes.c_uint64(), ctypes.c_uint64()
+        _lib.check(_lib.load().ct_pop_counters(self._h, ctypes.byref(r), ctypes.byref(m)))
+        return {"repairs": int(r.value), "mutations": int(m.value)}
+
     def snapshot(self) -> bytes:
         L = _lib.load()
         n = ctypes.c_size_t(0)
@@ -215,6 +220,18 @@ class Pop:
             self.close()
         except Exception:
             pass
+
+
+def prof_enable(on: bool = True):
+    """Kernel timing with HIP events (measurement support)."""
+    _lib.check(_lib.load().ct_prof_enable(1 if on else 0))
+
+
+def prof_read(kernel: str):
+    """(total milliseconds, launches) of a kernel's base name since prof_enable."""
+    t, n = ctypes.c_double(), ctypes.c_uint64()
+    _lib.check(_lib.load().ct_prof_read(kernel.encode(), ctypes.byref(t), ctypes.byref(n)))
+    return float(t.value), int(n.value)
 
 
 def step_many(pops: List[Pop], n_generations: int = 1, flags: int = CT_STEP_PLAIN):

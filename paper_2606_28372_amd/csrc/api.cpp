@@ -224,7 +224,8 @@ int ct_space_copy_bitmask(const ct_space* s, uint64_t* d_words, void* stream) {
 void ct_space_free(ct_space* s) {
     if (!s) return;
     (void)hipDeviceSynchronize();
-    void* bufs[] = {s->d_values, s->d_code, s->d_prefix, s->d_words, s->d_lin, s->d_rows, s->d_prevnext};
+    void* bufs[] = {s->d_values, s->d_code, s->d_prefix, s->d_words, s->d_lin, s->d_rows, s->d_prevnext,
+                    s->d_grp_off, s->d_dir8, s->d_boxes};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete s;
@@ -317,7 +318,7 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_ob
         ct_pop_free(p);
         return code_;
     };
-    if ((rc = dalloc(p, &d.state, 4)) || (rc = dalloc(p, &d.best, 1)) || (rc = dalloc(p, &d.trial, (size_t)P * d.R)) ||
+    if ((rc = dalloc(p, &d.state, 4)) || (rc = dalloc(p, &d.tally, 2)) || (rc = dalloc(p, &d.best, 1)) || (rc = dalloc(p, &d.trial, (size_t)P * d.R)) ||
         (rc = dalloc(p, &d.out, (size_t)P * d.R)) || (rc = dalloc(p, &d.tpos, P)) || (rc = dalloc(p, &d.apply, P)))
         return fail(rc);
     if (q.algo == CT_PSO) {
@@ -350,6 +351,8 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_ob
             return fail(ct_fail(CT_EDEVICE, "ct_pop_create: upload failed"));
         d.beta = d_beta;
     }
+    if (hipMemsetAsync(d.tally, 0, 2 * sizeof(unsigned long long), st) != hipSuccess)
+        return fail(ct_fail(CT_EDEVICE, "ct_pop_create: memset failed"));
     if ((rc = repair_scratch_alloc(p->rs, P, 0, st))) return fail(rc);
     if ((rc = pop_init_device(p, st))) return fail(rc);
     *out = p;
@@ -389,6 +392,16 @@ int ct_pop_read(const ct_pop* p, uint32_t* h_pos, float* h_f, uint32_t* best_pos
     }
     if (generation) *generation = stt[0];
     if (reinits) *reinits = stt[1];
+    return CT_OK;
+}
+
+int ct_pop_counters(const ct_pop* p, uint64_t* repairs, uint64_t* mutations) {
+    if (!p) return ct_fail(CT_EINVAL, "ct_pop_counters: null population");
+    unsigned long long t[2];
+    CT_HIP(hipDeviceSynchronize());
+    CT_HIP(hipMemcpy(t, p->dev.tally, sizeof(t), hipMemcpyDeviceToHost));
+    if (repairs) *repairs = t[0];
+    if (mutations) *mutations = t[1];
     return CT_OK;
 }
 

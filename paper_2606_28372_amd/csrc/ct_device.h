@@ -41,7 +41,28 @@ struct DevSpace {
     const uint64_t* lin;        // valid list: ascending linear indices
     const uint8_t* rows;        // valid list: digit rows [n_valid][R]
     const uint8_t* prevnext;    // [D][256][2] nearest present value index below/above (0xFF: none)
+    const uint64_t* words;      // validity bitmask [n_words]
+    uint64_t n_words;
+    const uint64_t* grp_off;    // valid configurations before each 64-word group
+    const uint16_t* dir8;       // valid configurations from the group start to each 8-word block
+    const uint8_t* boxes;       // per 64-row block of the valid list: min row, max row (2 * R bytes)
+    uint64_t n_sub;             // number of 64-row blocks
 };
+
+// Validity of a linear index from the bitmask.
+__device__ __forceinline__ bool bit_valid(const DevSpace& S, uint64_t L) {
+    return L < S.N && ((S.words[L >> 6] >> (L & 63u)) & 1ull);
+}
+
+// Number of valid configurations with linear index below L (the rank of L when it is valid),
+// from the group offsets, the 8-word directory and at most 8 word popcounts.
+__device__ __forceinline__ uint64_t rank_dir(const DevSpace& S, uint64_t L) {
+    if (L >= S.N) return S.n_valid;
+    const uint64_t w = L >> 6;
+    uint64_t r = S.grp_off[w >> 6] + S.dir8[w >> 3];
+    for (uint64_t q = w & ~7ull; q < w; ++q) r += __popcll(S.words[q]);
+    return r + __popcll(S.words[w] & ((1ull << (L & 63u)) - 1ull));
+}
 
 // ---------------------------------------------------------------------------
 // Exact q = x / d for all 32-bit x, with (m, l) precomputed for d:

@@ -11,6 +11,17 @@
 
 int ct_fail(int code, const std::string& msg);
 
+// Records HIP events around the enclosed launch when kernel timing is enabled.
+class ProfScope {
+  public:
+    ProfScope(const char* name, hipStream_t st);
+    ~ProfScope();
+  private:
+    const char* name_;
+    hipStream_t st_;
+    void* a_;
+};
+
 #define CT_HIP(expr)                                                                          \
     do {                                                                                      \
         hipError_t e_ = (expr);                                                               \
@@ -32,6 +43,9 @@ struct ct_space {
     uint64_t* d_lin = nullptr;
     uint8_t* d_rows = nullptr;
     uint8_t* d_prevnext = nullptr;
+    uint64_t* d_grp_off = nullptr;
+    uint16_t* d_dir8 = nullptr;
+    uint8_t* d_boxes = nullptr;
     size_t lds_values_bytes = 0;      // dynamic LDS for the value tables
 };
 
@@ -55,13 +69,15 @@ struct RepairJob {
     uint8_t* out_rows;
     uint32_t* out_pos;
     const uint8_t* apply;             // nullable: per-candidate flag, 0 = leave alone (still written)
+    unsigned long long* tally;        // nullable: += number of candidates scanned
 };
 
 struct RepairScratch {
-    uint32_t* list = nullptr;         // indices of candidates that need a scan [cap]
-    uint32_t* count = nullptr;        // [1]
-    uint64_t* part_key = nullptr;     // [max_parts][cap]
-    uint32_t* part_pos = nullptr;     // [max_parts][cap]
+    uint32_t* list = nullptr;         // candidates that need a scan, then the fallback list [2][cap]
+    uint64_t* list_L = nullptr;       // their linear indices [2][cap]
+    uint32_t* count = nullptr;        // [2]: list length, fallback length
+    uint64_t* part_key = nullptr;     // per (candidate, part) best key
+    uint32_t* part_pos = nullptr;     // per (candidate, part) best position
     uint64_t cap = 0;
     uint32_t max_parts = 0;
 };
@@ -98,6 +114,7 @@ struct PopDev {
     int32_t* PB;                      // PSO [P][D] personal-best positions
     float* f_pb;                      // PSO [P]
     uint32_t* pb_pos;                 // PSO [P]
+    unsigned long long* tally;        // [0] repair scans, [1] mutation scans (cumulative)
 };
 
 struct ct_pop {

@@ -1,0 +1,77 @@
+// Kernel timing with HIP events recorded on the launch stream around each
+// launch (enabled on request; used by the benchmark to time the kernels that
+// bound a step against their roofline).
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ct_host.h"
+
+namespace {
+struct Rec {
+    const char* name;
+    hipEvent_t a, b;
+};
+std::mutex g_mu;
+bool g_on = false;
+std::vector<Rec> g_recs;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t take() {
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+}  // namespace
+
+ProfScope::ProfScope(const char* name, hipStream_t st) : name_(name), st_(st), a_(nullptr) {
+    std::lock_guard<std::mutex> g(g_mu);
+    if (!g_on) return;
+    a_ = take();
+    (void)hipEventRecord((hipEvent_t)a_, st_);
+}
+
+ProfScope::~ProfScope() {
+    if (!a_) return;
+    std::lock_guard<std::mutex> g(g_mu);
+    hipEvent_t b = take();
+    (void)hipEventRecord(b, st_);
+    g_recs.push_back(Rec{name_, (hipEvent_t)a_, b});
+}
+
+extern "C" int ct_prof_enable(int on) {
+    std::lock_guard<std::mutex> g(g_mu);
+    CT_HIP(hipDeviceSynchronize());
+    for (auto& r : g_recs) {
+        g_pool.push_back(r.a);
+        g_pool.push_back(r.b);
+    }
+    g_recs.clear();
+    g_on = on != 0;
+    return CT_OK;
+}
+
+extern "C" int ct_prof_read(const char* kernel, double* total_ms, uint64_t* launches) {
+    if (!kernel || !total_ms || !launches) return ct_fail(CT_EINVAL, "ct_prof_read: null argument");
+    std::lock_guard<std::mutex> g(g_mu);
+    CT_HIP(hipDeviceSynchronize());
+    double t = 0;
+    uint64_t n = 0;
+    for (auto& r : g_recs) {
+        if (std::string(r.name) != kernel) continue;
+        float ms = 0;
+        CT_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        t += ms;
+        n++;
+    }
+    *total_ms = t;
+    *launches = n;
+    return CT_OK;
+}

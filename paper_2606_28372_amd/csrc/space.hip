@@ -183,7 +183,8 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const uint64_t* __restrict_
 __global__ __launch_bounds__(kBlock) void k_compact(DevSpace S, const uint64_t* __restrict__ words, uint64_t n_words,
                                                     const uint32_t* __restrict__ counts,
                                                     const uint64_t* __restrict__ tile_off, uint64_t n_groups,
-                                                    uint64_t* __restrict__ lin, uint8_t* __restrict__ rows) {
+                                                    uint64_t* __restrict__ lin, uint8_t* __restrict__ rows,
+                                                    uint64_t* __restrict__ grp_off, uint16_t* __restrict__ dir8) {
     __shared__ uint64_t emit[kWavesPerBlock][kEmit];
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const uint64_t g = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
@@ -198,6 +199,9 @@ __global__ __launch_bounds__(kBlock) void k_compact(DevSpace S, const uint64_t* 
     const uint32_t c = (uint32_t)__popcll(rem);
     const uint32_t excl = wave_excl_scan(c, lane);
     const uint32_t total = wave_sum(c);
+    // rank directory: offset of the group, and of each 8-word block inside it
+    if (lane == 0) grp_off[g] = base;
+    if ((lane & 7u) == 0 && wi < n_words) dir8[wi >> 3] = (uint16_t)excl;
     uint32_t e = excl;                       // list index (within the group) of the lane's next bit
     for (uint32_t cs = 0; cs < total; cs += kEmit) {
         const uint32_t ce = cs + kEmit;
@@ -222,6 +226,31 @@ __global__ __launch_bounds__(kBlock) void k_compact(DevSpace S, const uint64_t* 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// Per 64-row block of the valid list, the smallest and the largest value
+// index of every parameter (a bounding box used to prune repair scans).
+__global__ __launch_bounds__(kBlock) void k_boxes(DevSpace S, uint8_t* __restrict__ boxes) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t sb = (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (sb >= S.n_sub) return;
+    const uint64_t v = sb * 64u + lane;
+    const bool in = v < S.n_valid;
+    Row r;
+    row_load(r, S.rows + (in ? v : sb * 64u) * S.R, S.R);
+    for (uint32_t j = 0; j < S.R; ++j) {
+        uint32_t d = j < S.D ? r.digit(j) : 0u;
+        uint32_t lo = d, hi = d;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, 64));
+            hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
+        }
+        if (lane == 0) {
+            boxes[sb * 2u * S.R + j] = (uint8_t)lo;
+            boxes[sb * 2u * S.R + S.R + j] = (uint8_t)hi;
+        }
     }
 }
 
@@ -315,20 +344,20 @@ int space_build_device(ct_space* s, hipStream_t st) {
 
     if (S.split == S.D) {
         // the whole space is one table
-        hipLaunchKernelGGL(k_table, dim3(grid_for(n_groups, kWavesPerBlock)), dim3(kBlock), lds, st, S, S.N, S.D,
-                           S.n_cons, n_vals, s->n_words, s->d_words, d_counts);
+        { ProfScope ps_("k_table", st); hipLaunchKernelGGL(k_table, dim3(grid_for(n_groups, kWavesPerBlock)), dim3(kBlock), lds, st, S, S.N, S.D,
+                           S.n_cons, n_vals, s->n_words, s->d_words, d_counts); }
     } else {
         const uint64_t p_groups = (S.P_s + 4095u) / 4096u;
         CT_HIP(hipMalloc(&s->d_prefix, p_groups * 64u * sizeof(uint64_t)));
-        hipLaunchKernelGGL(k_table, dim3(grid_for(p_groups, kWavesPerBlock)), dim3(kBlock), lds, st, S, S.P_s,
-                           S.split, S.n_pre, n_vals, p_groups * 64u, s->d_prefix, (uint32_t*)nullptr);
+        { ProfScope ps_("k_table", st); hipLaunchKernelGGL(k_table, dim3(grid_for(p_groups, kWavesPerBlock)), dim3(kBlock), lds, st, S, S.P_s,
+                           S.split, S.n_pre, n_vals, p_groups * 64u, s->d_prefix, (uint32_t*)nullptr); }
         S.prefix_words = s->d_prefix;
-        hipLaunchKernelGGL(k_mask, dim3(grid_for(n_groups, kWavesPerBlock)), dim3(kBlock), lds, st, S, n_vals,
-                           s->n_words, s->d_words, d_counts);
+        { ProfScope ps_("k_mask", st); hipLaunchKernelGGL(k_mask, dim3(grid_for(n_groups, kWavesPerBlock)), dim3(kBlock), lds, st, S, n_vals,
+                           s->n_words, s->d_words, d_counts); }
     }
     CT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_tile_sums, dim3((uint32_t)n_tiles), dim3(kTileGroups), 0, st, d_counts, n_groups, d_tiles);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, d_tiles, n_tiles, d_off);
+    { ProfScope ps_("k_tile_sums", st); hipLaunchKernelGGL(k_tile_sums, dim3((uint32_t)n_tiles), dim3(kTileGroups), 0, st, d_counts, n_groups, d_tiles); }
+    { ProfScope ps_("k_scan_tiles", st); hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, d_tiles, n_tiles, d_off); }
     CT_HIP(hipGetLastError());
     uint64_t total = 0;
     CT_HIP(hipMemcpyAsync(&total, d_off + n_tiles, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
@@ -342,17 +371,29 @@ int space_build_device(ct_space* s, hipStream_t st) {
     uint32_t* d_present = nullptr;
     CT_HIP(hipMallocAsync((void**)&d_present, (size_t)S.D * 8 * sizeof(uint32_t), st));
     CT_HIP(hipMemsetAsync(d_present, 0, (size_t)S.D * 8 * sizeof(uint32_t), st));
+    CT_HIP(hipMalloc(&s->d_grp_off, n_groups * sizeof(uint64_t)));
+    CT_HIP(hipMalloc(&s->d_dir8, (n_words_alloc / 8) * sizeof(uint16_t)));
+    S.n_sub = (total + 63u) / 64u;
+    CT_HIP(hipMalloc(&s->d_boxes, std::max<uint64_t>(S.n_sub, 1) * 2u * S.R));
     if (total) {
-        hipLaunchKernelGGL(k_compact, dim3(grid_for(n_groups, kWavesPerBlock)), dim3(kBlock), 0, st, S, s->d_words,
-                           s->n_words, d_counts, d_off, n_groups, s->d_lin, s->d_rows);
+        { ProfScope ps_("k_compact", st); hipLaunchKernelGGL(k_compact, dim3(grid_for(n_groups, kWavesPerBlock)), dim3(kBlock), 0, st, S, s->d_words,
+                           s->n_words, d_counts, d_off, n_groups, s->d_lin, s->d_rows, s->d_grp_off, s->d_dir8); }
     }
     S.lin = s->d_lin;
     S.rows = s->d_rows;
+    S.words = s->d_words;
+    S.n_words = s->n_words;
+    S.grp_off = s->d_grp_off;
+    S.dir8 = s->d_dir8;
+    S.boxes = s->d_boxes;
     if (total) {
-        hipLaunchKernelGGL(k_presence, dim3(grid_for(total, kBlock, 1024)), dim3(kBlock), 0, st, S, d_present);
+        { ProfScope ps_("k_boxes", st); hipLaunchKernelGGL(k_boxes, dim3(grid_for(S.n_sub, kWavesPerBlock)), dim3(kBlock), 0, st, S, s->d_boxes); }
     }
-    hipLaunchKernelGGL(k_prevnext, dim3(grid_for(S.D * 256u, 256)), dim3(256), 0, st, S.D, d_present,
-                       s->d_prevnext);
+    if (total) {
+        { ProfScope ps_("k_presence", st); hipLaunchKernelGGL(k_presence, dim3(grid_for(total, kBlock, 1024)), dim3(kBlock), 0, st, S, d_present); }
+    }
+    { ProfScope ps_("k_prevnext", st); hipLaunchKernelGGL(k_prevnext, dim3(grid_for(S.D * 256u, 256)), dim3(256), 0, st, S.D, d_present,
+                       s->d_prevnext); }
     S.prevnext = s->d_prevnext;
     CT_HIP(hipGetLastError());
     CT_HIP(hipFreeAsync(d_present, st));
@@ -365,15 +406,15 @@ int space_build_device(ct_space* s, hipStream_t st) {
 
 int launch_valid_mask(const ct_space* s, const uint8_t* rows, uint64_t n, uint8_t* out, hipStream_t st) {
     if (n == 0) return CT_OK;
-    hipLaunchKernelGGL(k_valid_rows, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), s->lds_values_bytes, st, s->dev,
-                       (uint32_t)s->values.size(), rows, n, out);
+    { ProfScope ps_("k_valid_rows", st); hipLaunchKernelGGL(k_valid_rows, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), s->lds_values_bytes, st, s->dev,
+                       (uint32_t)s->values.size(), rows, n, out); }
     CT_HIP(hipGetLastError());
     return CT_OK;
 }
 
 int launch_rank(const ct_space* s, const uint8_t* rows, uint64_t n, int64_t* pos, hipStream_t st) {
     if (n == 0) return CT_OK;
-    hipLaunchKernelGGL(k_rank, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, st, s->dev, rows, n, pos);
+    { ProfScope ps_("k_rank", st); hipLaunchKernelGGL(k_rank, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, st, s->dev, rows, n, pos); }
     CT_HIP(hipGetLastError());
     return CT_OK;
 }

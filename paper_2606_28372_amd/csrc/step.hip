@@ -390,6 +390,7 @@ RepairJob make_job(const ct_pop* p, uint32_t metric, const uint8_t* rows, uint8_
     J.out_rows = out;
     J.out_pos = p->dev.tpos;
     J.apply = apply;
+    J.tally = p->dev.tally + (metric == CT_HAM1_RANDOM ? 1 : 0);
     return J;
 }
 
@@ -397,8 +398,8 @@ RepairJob make_job(const ct_pop* p, uint32_t metric, const uint8_t* rows, uint8_
 
 int pop_init_device(ct_pop* p, hipStream_t st) {
     const PopDev& d = p->dev;
-    hipLaunchKernelGGL(k_init, dim3((d.P + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d);
-    hipLaunchKernelGGL(k_init_finish, dim3(1), dim3(kSelBlock), 0, st, d);
+    { ProfScope ps_("k_init", st); hipLaunchKernelGGL(k_init, dim3((d.P + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d); }
+    { ProfScope ps_("k_init_finish", st); hipLaunchKernelGGL(k_init_finish, dim3(1), dim3(kSelBlock), 0, st, d); }
     CT_HIP(hipGetLastError());
     return CT_OK;
 }
@@ -409,25 +410,25 @@ int pop_step_plain(ct_pop* p, hipStream_t st) {
     int rc = CT_OK;
     switch (d.algo) {
     case CT_DE:
-        hipLaunchKernelGGL(k_de_propose, gi, b, 0, st, d);
+        { ProfScope ps_("k_de_propose", st); hipLaunchKernelGGL(k_de_propose, gi, b, 0, st, d); }
         rc = launch_repair(p->space, make_job(p, CT_INDEX_L1, d.trial, d.out, nullptr), p->rs, st);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_de_select, dim3(1), dim3(kSelBlock), 0, st, d);
+        { ProfScope ps_("k_de_select", st); hipLaunchKernelGGL(k_de_select, dim3(1), dim3(kSelBlock), 0, st, d); }
         break;
     case CT_PSO:
-        hipLaunchKernelGGL(k_pso_move, gi, b, 0, st, d);
+        { ProfScope ps_("k_pso_move", st); hipLaunchKernelGGL(k_pso_move, gi, b, 0, st, d); }
         rc = launch_repair(p->space, make_job(p, CT_TIER_EUCLID, d.trial, d.out, nullptr), p->rs, st);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_pso_select, dim3(1), dim3(kSelBlock), 0, st, d);
+        { ProfScope ps_("k_pso_select", st); hipLaunchKernelGGL(k_pso_select, dim3(1), dim3(kSelBlock), 0, st, d); }
         break;
     default:
-        hipLaunchKernelGGL(k_ga_sort, dim3(1), dim3(kSelBlock), 0, st, d);
-        hipLaunchKernelGGL(k_ga_cross, dim3((d.P / 2 + 1 + kBlock - 1) / kBlock), b, 0, st, d);
+        { ProfScope ps_("k_ga_sort", st); hipLaunchKernelGGL(k_ga_sort, dim3(1), dim3(kSelBlock), 0, st, d); }
+        { ProfScope ps_("k_ga_cross", st); hipLaunchKernelGGL(k_ga_cross, dim3((d.P / 2 + 1 + kBlock - 1) / kBlock), b, 0, st, d); }
         rc = launch_repair(p->space, make_job(p, CT_TIER_RANDOM, d.trial, d.out, nullptr), p->rs, st);
         if (rc) return rc;
         rc = launch_repair(p->space, make_job(p, CT_HAM1_RANDOM, d.out, d.out, d.apply), p->rs, st);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_ga_select, dim3(1), dim3(kSelBlock), 0, st, d);
+        { ProfScope ps_("k_ga_select", st); hipLaunchKernelGGL(k_ga_select, dim3(1), dim3(kSelBlock), 0, st, d); }
         break;
     }
     CT_HIP(hipGetLastError());
