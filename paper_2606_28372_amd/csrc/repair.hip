@@ -33,8 +33,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr uint32_t kTargetWaves = 8192;   // scan items launched per pass
-constexpr uint32_t kMinSubPerPart = 4;    // 64-row blocks per part, at least
-constexpr uint32_t kSortCap = 4096;       // candidates sorted by linear index up to this count
+constexpr uint32_t kMinSubPerPart = 32;   // 64-row blocks per part, at least
 constexpr uint64_t kNoKey = ~0ull;
 constexpr uint32_t kNoPos = 0xFFFFFFFFu;
 constexpr uint64_t kTier3 = 3ull << 62;
@@ -46,14 +45,13 @@ __device__ __forceinline__ uint32_t ne_bytes(uint32_t x) {
 
 __device__ __forceinline__ uint32_t job_gen(const RepairJob& j) { return j.d_gen ? *j.d_gen : j.gen_value; }
 
-__device__ __forceinline__ void scan_shape(uint32_t count, uint64_t n_sub, uint32_t* n_cw, uint32_t* parts) {
-    uint32_t nc = (count + 63u) / 64u;
-    if (nc == 0) nc = 1;
-    uint64_t p = kTargetWaves / nc;
-    uint64_t pmax = n_sub / kMinSubPerPart;
+// Parts of the valid list per candidate: enough (candidate, part) waves to fill the chip,
+// each part at least kMinSubPerPart 64-row blocks.  count * parts <= max(count, kTargetWaves).
+__device__ __forceinline__ void scan_parts(uint32_t count, uint64_t n_sub, uint32_t* parts) {
+    uint64_t p = count ? kTargetWaves / count : 1;
+    const uint64_t pmax = n_sub / kMinSubPerPart;
     if (p > pmax) p = pmax;
     if (p < 1) p = 1;
-    *n_cw = nc;
     *parts = (uint32_t)p;
 }
 
@@ -96,44 +94,22 @@ __global__ __launch_bounds__(kBlock) void k_repair_prep(RepairJob J, uint32_t* _
     }
 }
 
-// Sort (L, candidate) pairs of the list by L (one block; lists above kSortCap stay unsorted).
-__global__ __launch_bounds__(1024) void k_repair_sort(uint32_t* __restrict__ list, uint64_t* __restrict__ list_L,
-                                                      const uint32_t* __restrict__ count_p) {
-    __shared__ uint64_t key[kSortCap];
-    __shared__ uint32_t val[kSortCap];
-    const uint32_t count = *count_p;
-    if (count <= 1 || count > kSortCap) return;
-    uint32_t n = 1;
-    while (n < count) n <<= 1;
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-        key[i] = i < count ? list_L[i] : ~0ull;
-        val[i] = i < count ? list[i] : 0xFFFFFFFFu;
+// ---------------------------------------------------------------------------
+// the scan: one candidate per wave, lanes over boxes and then over rows
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)v, o, 64), hi = __shfl_xor((uint32_t)(v >> 32), o, 64);
+        const uint64_t w = ((uint64_t)hi << 32) | lo;
+        v = w < v ? w : v;
     }
-    __syncthreads();
-    for (uint32_t k = 2; k <= n; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-                uint32_t l = i ^ j;
-                if (l > i) {
-                    bool up = (i & k) == 0;
-                    uint64_t a = key[i], b = key[l];
-                    uint32_t va = val[i], vb = val[l];
-                    bool gt = a > b || (a == b && va > vb);
-                    if (gt == up) { key[i] = b; key[l] = a; val[i] = vb; val[l] = va; }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (uint32_t i = threadIdx.x; i < count; i += blockDim.x) {
-        list_L[i] = key[i];
-        list[i] = val[i];
-    }
+    return v;
 }
 
-// ---------------------------------------------------------------------------
-// per-candidate state and the metric keys
-// ---------------------------------------------------------------------------
+// Per-candidate state, wave-uniform (the candidate is the same in every lane).
 template <int M, int RW>
 struct Cand {
     uint32_t c[RW];
@@ -151,7 +127,7 @@ struct Cand {
             // bytes past the last parameter are padding: force them to zero
             const int live = (int)S.D - 4 * k;
             const uint32_t keep = live >= 4 ? 0xFFFFFFFFu : (live <= 0 ? 0u : ((1u << (8 * live)) - 1u));
-            c[k] = cr[k] & keep;
+            c[k] = uni(cr[k] & keep);
         }
         adj_is_sa = true;
         if constexpr (M == CT_TIER_EUCLID || M == CT_TIER_RANDOM) {
@@ -159,11 +135,11 @@ struct Cand {
             for (int k = 0; k < RW; ++k) { pv[k] = 0; nx[k] = 0; }
 #pragma unroll
             for (int j = 0; j < RW * 4; ++j) {
-                uint32_t d = (c[j >> 2] >> ((j & 3) * 8)) & 0xFFu;
+                const uint32_t d = (c[j >> 2] >> ((j & 3) * 8)) & 0xFFu;
                 uint32_t p = d, n = d;
                 if ((uint32_t)j < S.D) {
-                    p = S.prevnext[((uint32_t)j * 256u + d) * 2u + 0u];
-                    n = S.prevnext[((uint32_t)j * 256u + d) * 2u + 1u];
+                    p = uni(S.prevnext[((uint32_t)j * 256u + d) * 2u + 0u]);
+                    n = uni(S.prevnext[((uint32_t)j * 256u + d) * 2u + 1u]);
                     // the two rules agree on parameter j unless a present value lies below (above) d while
                     // d-1 (d+1) itself never occurs in a solution; "none" is 0xFF, which no digit equals
                     adj_is_sa &= (p == d - 1u || p == 0xFFu) && (n == d + 1u || n == 0xFFu);
@@ -174,16 +150,17 @@ struct Cand {
         }
         if constexpr (M == CT_TIER_EUCLID) {
 #pragma unroll
-            for (int j = 0; j < RW * 4; ++j) X[j] = (uint32_t)j < S.D ? J.pos_q16[(uint64_t)ci * S.D + j] : 0;
+            for (int j = 0; j < RW * 4; ++j)
+                X[j] = (uint32_t)j < S.D ? (int32_t)uni((uint32_t)J.pos_q16[(uint64_t)ci * S.D + j]) : 0;
         }
         if constexpr (M == CT_TIER_RANDOM || M == CT_HAM1_RANDOM) {
-            who = J.who ? J.who[ci] : ci;
-            gen = job_gen(J);
+            who = uni(J.who ? J.who[ci] : ci);
+            gen = uni(job_gen(J));
             seed = J.seed;
         }
     }
 
-    // key of row v (at list position pos) if it can beat `bound`, else kNoKey
+    // key of row v (at list position pos) if it can go below `bound`, else kNoKey
     __device__ __forceinline__ uint64_t key(const DevSpace& S, const uint32_t* v, uint64_t pos, uint64_t bound) const {
         if constexpr (M == CT_HAMMING) {
             uint32_t h = 0;
@@ -193,7 +170,7 @@ struct Cand {
         } else if constexpr (M == CT_INDEX_L1) {
             uint32_t s = 0;
 #pragma unroll
-            for (int k = 0; k < RW; ++k) s = __builtin_amdgcn_sad_u8(c[k], v[k], s);
+            for (int k = 0; k < RW; ++k) s = __builtin_amdgcn_sad_u8(v[k], c[k], s);
             return s;
         } else {
             uint32_t h = 0;
@@ -207,7 +184,7 @@ struct Cand {
             } else {
                 uint32_t s = 0;
 #pragma unroll
-                for (int k = 0; k < RW; ++k) s = __builtin_amdgcn_sad_u8(c[k], v[k], s);
+                for (int k = 0; k < RW; ++k) s = __builtin_amdgcn_sad_u8(v[k], c[k], s);
                 uint32_t tier;
                 if (s == h) {
                     tier = 0;                      // every differing digit differs by exactly one
@@ -230,8 +207,8 @@ struct Cand {
                     uint64_t d2 = 0;
 #pragma unroll
                     for (int j = 0; j < RW * 4; ++j) {
-                        int64_t cen = (int64_t)((((v[j >> 2] >> ((j & 3) * 8)) & 0xFFu) * 2u + 1u) << 15);
-                        int64_t d = (int64_t)X[j] - cen;
+                        const int32_t cen = (int32_t)((((v[j >> 2] >> ((j & 3) * 8)) & 0xFFu) << 16) + 32768u);
+                        const int64_t d = (int64_t)(X[j] - cen);
                         d2 += (uint64_t)(d * d);   // padding digits add the same constant to every row
                     }
                     return ((uint64_t)tier << 62) | d2;
@@ -246,47 +223,53 @@ struct Cand {
     }
 
     // lower bound of key() over every row inside the box [lo, hi]
-    __device__ __forceinline__ uint64_t bound_box(const DevSpace& S, const uint8_t* lo, const uint8_t* hi) const {
+    __device__ __forceinline__ uint64_t bound_box(const uint32_t* lo32, const uint32_t* hi32) const {
         uint32_t miss = 0, sum = 0, far = 0;
         bool adj_ok = true;
-        const uint32_t* lo32 = reinterpret_cast<const uint32_t*>(lo);
-        const uint32_t* hi32 = reinterpret_cast<const uint32_t*>(hi);
+        uint64_t e2 = 0;
 #pragma unroll
         for (int k = 0; k < RW; ++k) {
             const uint32_t lw = lo32[k], hw = hi32[k];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 // padding digits are 0 in the candidate and in both box rows, so they add nothing
-                const uint32_t cj = (c[k] >> (q * 8)) & 0xFFu;
-                const uint32_t a = (lw >> (q * 8)) & 0xFFu, b = (hw >> (q * 8)) & 0xFFu;
-                const uint32_t d = a > cj ? a - cj : (cj > b ? cj - b : 0u);
+                const int32_t cj = (int32_t)((c[k] >> (q * 8)) & 0xFFu);
+                const int32_t a = (int32_t)((lw >> (q * 8)) & 0xFFu), b = (int32_t)((hw >> (q * 8)) & 0xFFu);
+                const uint32_t d = (uint32_t)max(max(a - cj, cj - b), 0);
                 miss += d != 0u;
                 sum += d;
                 far += d > 1u;
                 if constexpr (M == CT_TIER_EUCLID || M == CT_TIER_RANDOM) {
                     if (!adj_is_sa && d != 0u) {
-                        const uint32_t p = (pv[k] >> (q * 8)) & 0xFFu;
-                        const uint32_t n = (nx[k] >> (q * 8)) & 0xFFu;
-                        adj_ok &= (p != 0xFFu && p >= a && p <= b) || (n != 0xFFu && n >= a && n <= b);
+                        const int32_t p = (int32_t)((pv[k] >> (q * 8)) & 0xFFu);
+                        const int32_t n = (int32_t)((nx[k] >> (q * 8)) & 0xFFu);
+                        adj_ok &= (p != 0xFF && p >= a && p <= b) || (n != 0xFF && n >= a && n <= b);
                     }
+                }
+                if constexpr (M == CT_TIER_EUCLID) {
+                    // distance from the particle to the nearest value centre inside [a, b]
+                    const int32_t x = X[k * 4 + q];
+                    const int32_t ca = (a << 16) + 32768, cb = (b << 16) + 32768;
+                    const int64_t t = (int64_t)max(max(ca - x, x - cb), 0);
+                    e2 += (uint64_t)(t * t);
                 }
             }
         }
-        (void)S;
         if constexpr (M == CT_HAMMING) return miss;
         else if constexpr (M == CT_INDEX_L1) return sum;
         else if constexpr (M == CT_HAM1_RANDOM) return miss <= 1u ? 0ull : kNoKey;
         else {
-            if (far == 0u) return 0ull;                         // strictly adjacent rows possible
-            if (!adj_is_sa && adj_ok) return 1ull << 62;         // adjacent rows possible
-            if (miss <= 1u) return 2ull << 62;                   // Hamming-1 rows possible
+            const uint64_t sub = M == CT_TIER_EUCLID ? e2 : 0ull;
+            if (far == 0u) return sub;                              // strictly adjacent rows possible
+            if (!adj_is_sa && adj_ok) return (1ull << 62) | sub;     // adjacent rows possible
+            if (miss <= 1u) return (2ull << 62) | sub;               // Hamming-1 rows possible
             return kTier3;
         }
     }
 };
 
-// Scan one part of the valid list for the 64 candidates of one wave.  For the tiered
-// metrics the bound starts at tier 3, so only neighbours of tiers 0-2 are wanted.
+// One wave = one (candidate, part) item.  For the tiered metrics the bound starts at tier 3,
+// so only neighbours of tiers 0-2 are wanted; the Hamming fallback handles the rest.
 template <int M, int RW>
 __global__ __launch_bounds__(kBlock) void k_repair_scan(RepairJob J, const uint32_t* __restrict__ list,
                                                         const uint64_t* __restrict__ list_L,
@@ -296,60 +279,88 @@ __global__ __launch_bounds__(kBlock) void k_repair_scan(RepairJob J, const uint3
     const DevSpace& S = J.S;
     const uint32_t count = *count_p;
     if (count == 0) return;
-    uint32_t n_cw, parts;
-    scan_shape(count, S.n_sub, &n_cw, &parts);
-    const uint32_t item = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    if (item >= n_cw * parts) return;
-    const uint32_t cw = item / parts, part = item % parts;
+    uint32_t parts;
+    scan_parts(count, S.n_sub, &parts);
+    const uint32_t item = uni(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
+    if (item >= count * parts) return;
+    const uint32_t li = item / parts, part = item % parts;
     const uint32_t lane = wave_lane();
-    const uint32_t li = cw * 64u + lane;
-    const bool active = li < count;
-    const uint32_t lj = active ? li : cw * 64u;              // inactive lanes mirror an active one
-    const uint32_t ci = list[lj];
+    const uint32_t ci = uni(list[li]);
     Cand<M, RW> C;
     C.load(J, ci);
+    const uint32_t* rows32 = reinterpret_cast<const uint32_t*>(S.rows);
 
     constexpr bool tiered = (M == CT_TIER_EUCLID || M == CT_TIER_RANDOM);
-    uint64_t bk = tiered ? kTier3 : kNoKey;                  // exclusive bound: keys below it are wanted
-    uint32_t bp = kNoPos;
-    // seed the bound from the valid rows adjacent in linear-index order
-    const uint64_t L = list_L[lj];
-    if (L != ~0ull && S.n_valid) {
+    uint64_t bk = tiered ? kTier3 : kNoKey;        // wave-uniform exclusive bound: keys below it are wanted
+    // seed the bound from the 64 valid rows around the candidate's place in linear-index order
+    const uint64_t L = ((uint64_t)uni((uint32_t)(list_L[li] >> 32)) << 32) | uni((uint32_t)list_L[li]);
+    if (L != ~0ull) {
         const uint64_t ins = rank_dir(S, L);
-        for (int t = -1; t <= 1; ++t) {
-            const int64_t q = (int64_t)ins + t;
-            if (q < 0 || (uint64_t)q >= S.n_valid) continue;
-            const uint32_t* v = reinterpret_cast<const uint32_t*>(S.rows + (uint64_t)q * S.R);
-            uint32_t vv[RW];
-#pragma unroll
-            for (int k = 0; k < RW; ++k) vv[k] = v[k];
-            const uint64_t k = C.key(S, vv, (uint64_t)q, bk);
-            if (k != kNoKey && k + 1 < bk) bk = k + 1;
-        }
-    }
-
-    const uint64_t s0 = (uint64_t)part * S.n_sub / parts, s1 = (uint64_t)(part + 1) * S.n_sub / parts;
-    for (uint64_t sb = s0; sb < s1; ++sb) {
-        const uint8_t* box = S.boxes + sb * 2u * S.R;
-        const uint64_t lb = C.bound_box(S, box, box + S.R);
-        if (!__any(active && lb < bk)) continue;
-        const uint64_t r0 = sb * 64u;
-        const uint32_t nr = (uint32_t)min((uint64_t)64, S.n_valid - r0);
-        const uint32_t* rows32 = reinterpret_cast<const uint32_t*>(S.rows) + r0 * RW;
-        for (uint32_t r = 0; r < nr; ++r) {
+        const int64_t q = (int64_t)ins - 32 + (int64_t)lane;
+        uint64_t k = kNoKey;
+        if (q >= 0 && (uint64_t)q < S.n_valid) {
             uint32_t v[RW];
 #pragma unroll
-            for (int k = 0; k < RW; ++k) v[k] = rows32[r * RW + k];
-            const uint64_t k = C.key(S, v, r0 + r, bk);
-            if (k < bk) {
-                bk = k;
-                bp = (uint32_t)(r0 + r);
+            for (int w = 0; w < RW; ++w) v[w] = rows32[(uint64_t)q * RW + w];
+            k = C.key(S, v, (uint64_t)q, bk);
+        }
+        k = wave_min_u64(k);
+        if (k != kNoKey && k + 1 < bk) bk = k + 1;
+    }
+
+    uint64_t mk = bk;                               // this lane's best key (exclusive until a row is found)
+    uint32_t mp = kNoPos;
+    const uint64_t b0 = (uint64_t)part * S.n_sub / parts, b1 = (uint64_t)(part + 1) * S.n_sub / parts;
+    const uint32_t* box32 = reinterpret_cast<const uint32_t*>(S.boxes);
+    for (uint64_t cb = b0; cb < b1; cb += 64) {
+        // lanes over 64 boxes: which ones can hold a row below the bound?
+        const uint64_t b = cb + lane;
+        bool pass = false;
+        uint64_t lb = kNoKey;
+        if (b < b1) {
+            uint32_t lo[RW], hi[RW];
+#pragma unroll
+            for (int w = 0; w < RW; ++w) {
+                lo[w] = box32[b * 2u * RW + w];
+                hi[w] = box32[b * 2u * RW + RW + w];
+            }
+            lb = C.bound_box(lo, hi);
+            pass = lb < bk;
+        }
+        uint64_t m = __ballot(pass);
+        while (m) {
+            const uint32_t t = (uint32_t)__ffsll((long long)m) - 1u;
+            m &= m - 1ull;
+            // lanes over the 64 rows of box cb + t
+            const uint64_t r = (cb + t) * 64u + lane;
+            if (r < S.n_valid) {
+                uint32_t v[RW];
+#pragma unroll
+                for (int w = 0; w < RW; ++w) v[w] = rows32[r * RW + w];
+                const uint64_t k = C.key(S, v, r, mk < bk ? mk : bk);
+                if (k < mk) { mk = k; mp = (uint32_t)r; }
+            }
+            const uint64_t wm = wave_min_u64(mk);
+            bk = wm < bk ? wm : bk;
+            if (m) {
+                // drop boxes of this chunk that the tighter bound now rules out
+                m &= __ballot(lb < bk);
             }
         }
     }
-    if (active) {
-        part_key[(uint64_t)li * parts + part] = bp == kNoPos ? kNoKey : bk;
-        part_pos[(uint64_t)li * parts + part] = bp;
+    // lexicographic (key, position) minimum over the wave
+    uint64_t k2 = mp == kNoPos ? kNoKey : mk;
+    uint32_t p2 = mp;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t klo = __shfl_xor((uint32_t)k2, o, 64), khi = __shfl_xor((uint32_t)(k2 >> 32), o, 64);
+        const uint32_t pq = __shfl_xor(p2, o, 64);
+        const uint64_t kq = ((uint64_t)khi << 32) | klo;
+        if (kq < k2 || (kq == k2 && pq < p2)) { k2 = kq; p2 = pq; }
+    }
+    if (lane == 0) {
+        part_key[(uint64_t)li * parts + part] = k2;
+        part_pos[(uint64_t)li * parts + part] = p2;
     }
 }
 
@@ -363,8 +374,8 @@ __global__ __launch_bounds__(kBlock) void k_repair_finish(RepairJob J, const uin
                                                           uint32_t* __restrict__ fb_count) {
     const DevSpace& S = J.S;
     const uint32_t count = *count_p;
-    uint32_t n_cw, parts;
-    scan_shape(count, S.n_sub, &n_cw, &parts);
+    uint32_t parts;
+    scan_parts(count, S.n_sub, &parts);
     if (J.tally && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(J.tally, (unsigned long long)count);
     const uint32_t lane = wave_lane();
     const uint32_t waves = gridDim.x * (kBlock / 64);
@@ -392,7 +403,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_finish(RepairJob J, const uin
         } else if (fb_count && lane == 0) {
             const uint32_t k = atomicAdd(fb_count, 1u);
             fb_list[k] = ci;
-            fb_L[k] = ~0ull;             // no seed needed: the fallback scans everything
+            fb_L[k] = ~0ull;             // no seed: the fallback scans the whole list
         }
     }
 }
@@ -400,8 +411,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_finish(RepairJob J, const uin
 template <int M>
 void launch_scan_w(const RepairJob& J, uint32_t RW, const uint32_t* list, const uint64_t* list_L,
                    const uint32_t* count, const RepairScratch& rs, hipStream_t st) {
-    const uint64_t ncw = (J.n + 63) / 64;
-    const uint64_t items = std::max<uint64_t>(kTargetWaves, ncw);
+    const uint64_t items = std::max<uint64_t>(kTargetWaves, J.n);   // >= count * parts
     dim3 g((uint32_t)((items + 3) / 4)), b(kBlock);
     ProfScope ps_("k_repair_scan", st);
     switch (RW) {
@@ -425,8 +435,8 @@ void launch_finish(const RepairJob& J, const uint32_t* list, const uint32_t* cou
 int repair_scratch_alloc(RepairScratch& rs, uint64_t cap, uint32_t max_parts, hipStream_t st) {
     (void)max_parts;
     rs.cap = cap ? cap : 1;
-    // parts * count <= max(count, kTargetWaves * 64)
-    const uint64_t slots = std::max<uint64_t>(rs.cap, (uint64_t)kTargetWaves * 64u);
+    // parts * count <= max(count, kTargetWaves)
+    const uint64_t slots = std::max<uint64_t>(rs.cap, (uint64_t)kTargetWaves);
     rs.max_parts = kTargetWaves;
     CT_HIP(hipMallocAsync((void**)&rs.list, 2 * rs.cap * sizeof(uint32_t), st));
     CT_HIP(hipMallocAsync((void**)&rs.list_L, 2 * rs.cap * sizeof(uint64_t), st));
@@ -457,7 +467,6 @@ int launch_repair(const ct_space* s, const RepairJob& J, RepairScratch& rs, hipS
     CT_HIP(hipMemsetAsync(rs.count, 0, 2 * sizeof(uint32_t), st));
     uint32_t gp = (uint32_t)std::min<uint64_t>((J.n + kBlock - 1) / kBlock, 0x7FFFFFFFull);
     { ProfScope ps_("k_repair_prep", st); hipLaunchKernelGGL(k_repair_prep, dim3(gp), dim3(kBlock), 0, st, J, list, list_L, count); }
-    { ProfScope ps_("k_repair_sort", st); hipLaunchKernelGGL(k_repair_sort, dim3(1), dim3(1024), 0, st, list, list_L, count); }
     const uint32_t RW = s->R / 4;
     switch (J.metric) {
     case CT_HAMMING:

@@ -81,3 +81,9 @@ def test_repair_empty_space_and_empty_batch():
     out, pos = sp2.repair(r0, ocore.HAMMING)
     t.cuda.synchronize()
     assert out.shape[0] == 0
+
+
+def test_repair_large_batch():
+    """More candidates than the scan launches items for: one part per candidate."""
+    run_parity(W.gemm10(), oracle_space("gemm10"), 20000, 5, metrics=[ocore.HAMMING, ocore.INDEX_L1,
+                                                                          ocore.TIER_RANDOM, ocore.HAM1_RANDOM])
