@@ -5,15 +5,21 @@
 A step is one pass of the whole path over the workload: compile the
 constraints and resolve the space (enumeration + compaction), then create and
 run every optimiser run of the workload for its generations (propose,
-validity, repair, mutation, selection), reading the results back.  Inputs
-(value lists, constraint text, objective tables) are resident before the
-timed region.  One JSON line is printed:
+validity, repair, mutation, selection; the runs advance together, one launch
+per phase), reading the results back.  Inputs (value lists, constraint text,
+objective tables) are resident before the timed region.  One JSON line is
+printed:
 
   value      configurations checked per second (every Cartesian configuration
              in the space build plus every proposal validated by a generation),
-  repairs_per_s, mutation_scans_per_s, generations_per_s_plain,
+  repairs_per_s, mutation_scans_per_s,
   roofline   for the kernel that takes most of the step (HIP events around its
              launches on its stream, over the timed steps),
+  batched    generations/s of 256 independent problems (uneven spaces,
+             dimensions, populations and algorithms) stepped one run at a time
+             (plain), with one launch per phase for all runs (batched), and by
+             replaying a captured hipGraph of one generation (graph); all three
+             start from the same state and must end in the same state,
   cpu_baseline  the oracle on the host cores on a bounded sample of the same job.
 """
 from __future__ import annotations
@@ -53,9 +59,9 @@ CONFIG_KEY = {"gemm": "gemm", "gemm10": "gemm10", "tiny": "tiny", "sparse16": "s
 
 
 def kernel_names():
-    return ["k_table", "k_mask", "k_tile_sums", "k_scan_tiles", "k_compact", "k_presence", "k_prevnext",
-            "k_repair_prep", "k_repair_scan", "k_repair_finish", "k_init", "k_init_finish", "k_de_propose",
-            "k_de_select", "k_pso_move", "k_pso_select", "k_ga_sort", "k_ga_cross", "k_ga_select"]
+    return ["k_table", "k_mask", "k_tile_sums", "k_scan_tiles", "k_compact", "k_boxes", "k_presence",
+            "k_prevnext", "k_init", "k_init_finish", "k_ga_sort", "k_propose", "k_repair_zero", "k_repair_prep",
+            "k_repair_plan", "k_repair_scan", "k_repair_finish", "k_select"]
 
 
 def run_job(ct, spec, runs, objective_t, gens):
@@ -63,8 +69,7 @@ def run_job(ct, spec, runs, objective_t, gens):
     import torch
     sp = ct.Space.from_spec(spec)
     pops = [ct.Pop.from_opt(sp, opt, objective_t) for opt in runs]
-    for p in pops:
-        p.step(gens)
+    ct.step_many(pops, gens, ct.CT_STEP_BATCHED)
     out = []
     for p in pops:
         r = p.read()
@@ -108,6 +113,60 @@ def cpu_baseline(spec, runs, obj, gens):
                        f"{gens} generations per run")}
 
 
+def batched_leg(ct, n_problems, gens):
+    """Plain vs batched vs graph generations/s over the many-problem workload (same start state)."""
+    import torch
+    probs = W.batched(n_problems)
+    t0 = time.perf_counter()
+    spaces, objs, pops = [], [], []
+    for pr in probs:
+        sp = ct.Space.from_spec(pr.spec)
+        obj = torch.tensor(W.objective(sp.n_valid, pr.obj_seed), device="cuda")
+        spaces.append(sp)
+        objs.append(obj)
+        pops.append(ct.Pop.from_opt(sp, W.fit_pop(pr.opt, sp.n_valid), obj))
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    start = [p.snapshot() for p in pops]
+    batch = ct.Batch(pops)
+
+    def restore():
+        for p, blob in zip(pops, start):
+            p.restore(blob)
+        torch.cuda.synchronize()
+
+    out = {}
+    ends = {}
+    for mode in ("plain", "batched", "graph"):
+        restore()
+        if mode == "graph":
+            batch.step(1, ct.CT_STEP_GRAPH)        # capture + first replay, untimed
+            restore()
+        t1 = time.perf_counter()
+        if mode == "plain":
+            ct.step_many(pops, gens, ct.CT_STEP_PLAIN)
+        elif mode == "batched":
+            batch.step(gens, ct.CT_STEP_BATCHED)
+        else:
+            batch.step(gens, ct.CT_STEP_GRAPH)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        out[mode] = n_problems * gens / dt
+        ends[mode] = [p.snapshot() for p in pops]
+    same = ends["plain"] == ends["batched"] == ends["graph"]
+    batch.close()
+    for p in pops:
+        p.close()
+    n_valid = [s.n_valid for s in spaces]
+    for s in spaces:
+        s.close()
+    return {"problems": n_problems, "generations": gens, "generations_per_s": out,
+            "speedup_graph_vs_plain": out["graph"] / out["plain"], "identical_end_state": same,
+            "setup_s": t_setup, "valid_total": int(sum(n_valid)),
+            "population_total": int(sum(W.fit_pop(pr.opt, n).pop_size for pr, n in zip(probs, n_valid))),
+            "algorithms": {W.ALGO_NAMES[a]: sum(1 for pr in probs if pr.opt.algo == a) for a in range(3)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +175,9 @@ def main():
     ap.add_argument("--workload", default="gemm", choices=sorted(WORKLOADS))
     ap.add_argument("--generations", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-problems", type=int, default=256)
+    ap.add_argument("--batched-generations", type=int, default=20)
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -199,11 +261,15 @@ def main():
                    "population": [o.pop_size for o in runs], "generations": gens},
         "repairs_per_s": repairs / (ms_step * 1e-3),
         "mutation_scans_per_s": mutations / (ms_step * 1e-3),
-        "generations_per_s_plain": gens_total / (ms_step * 1e-3),
-        "generations_per_s_batched": None,
+        "generations_per_s_job": gens_total / (ms_step * 1e-3),
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in per_kernel.items() if v[1]},
         "roofline": roof,
     }
+    if not args.no_batched:
+        bl = batched_leg(ct, args.batched_problems, args.batched_generations)
+        line["generations_per_s_plain"] = bl["generations_per_s"]["plain"]
+        line["generations_per_s_batched"] = bl["generations_per_s"]["graph"]
+        line["batched"] = bl
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec, runs, obj, gens)
     print(json.dumps(line), flush=True)

@@ -233,6 +233,21 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* p, const float* d_obje
 int ct_step(ct_pop* const* pops, uint32_t n_pops, uint32_t n_generations, uint32_t flags, void* stream);
 
 /*
+ * Batches: a fixed group of runs (of any spaces and algorithms) advanced
+ * together with one launch per phase of the generation for all of them.
+ * ct_batch_step with CT_STEP_GRAPH captures one generation into a hipGraph on
+ * first use and replays it n_generations times (the generation counters live
+ * on the device, so replays need no host work); CT_STEP_BATCHED launches the
+ * same kernels directly.  Results equal those of stepping each run alone.
+ * The runs must outlive the batch; a run may be in several batches but only
+ * one of them may be stepped at a time.  At most 4096 runs per batch.
+ */
+typedef struct ct_batch ct_batch;
+int ct_batch_create(ct_pop* const* pops, uint32_t n_pops, ct_batch** out);
+int ct_batch_step(ct_batch* b, uint32_t n_generations, uint32_t flags, void* stream);
+void ct_batch_free(ct_batch* b);
+
+/*
  * ct_pop_read -- copy a run's state to the host (synchronises its stream).
  * h_pos[pop_size]: population as valid-list positions (PSO: the personal-best
  * configurations); h_f[pop_size]: their objective values.  Any output may be

@@ -22,7 +22,7 @@ from . import _lib
 from ._lib import (CT_DE, CT_GA, CT_HAM1_RANDOM, CT_HAMMING, CT_INDEX_L1, CT_PSO, CT_STEP_BATCHED,  # noqa: F401
                    CT_STEP_GRAPH, CT_STEP_PLAIN, CT_TIER_EUCLID, CT_TIER_RANDOM, CtError, ct_pop_params)
 
-__all__ = ["Space", "Pop", "compile_constraints", "step_many", "CtError", "CT_HAMMING", "CT_INDEX_L1",
+__all__ = ["Space", "Pop", "Batch", "compile_constraints", "step_many", "CtError", "CT_HAMMING", "CT_INDEX_L1",
            "CT_TIER_EUCLID", "CT_TIER_RANDOM", "CT_HAM1_RANDOM", "CT_DE", "CT_PSO", "CT_GA",
            "CT_STEP_PLAIN", "CT_STEP_BATCHED", "CT_STEP_GRAPH"]
 
@@ -213,6 +213,31 @@ class Pop:
     def close(self):
         if self._h:
             _lib.load().ct_pop_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """A fixed group of runs advanced together (ct_batch): one launch per phase for all of them;
+    with CT_STEP_GRAPH one generation is captured into a hipGraph once and replayed."""
+
+    def __init__(self, pops: List[Pop]):
+        self.pops = list(pops)
+        arr = (ctypes.c_void_p * max(1, len(self.pops)))(*[p.handle for p in self.pops])
+        self._h = ctypes.c_void_p()
+        _lib.check(_lib.load().ct_batch_create(arr, len(self.pops), ctypes.byref(self._h)))
+
+    def step(self, n_generations: int = 1, flags: int = CT_STEP_GRAPH):
+        _lib.check(_lib.load().ct_batch_step(self._h, n_generations, flags, _stream()))
+
+    def close(self):
+        if self._h:
+            _lib.load().ct_batch_free(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

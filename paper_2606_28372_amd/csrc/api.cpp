@@ -68,6 +68,114 @@ int dalloc(ct_pop* p, T** ptr, size_t n) {
 
 }  // namespace
 
+int batch_build(const std::vector<ct_pop*>& pops, ct_batch** out, hipStream_t st) {
+    (void)st;
+    *out = nullptr;
+    if (pops.size() > 4096) return ct_fail(CT_EINVAL, "batch: at most 4096 populations");
+    ct_batch* b = new ct_batch();
+    b->pops = pops;
+    b->n = (uint32_t)pops.size();
+    auto fail = [&](int code_) {
+        batch_free(b);
+        return code_;
+    };
+    auto own = [&](void** q, size_t bytes) -> int {
+        if (hipMalloc(q, std::max<size_t>(bytes, 8)) != hipSuccess) return ct_fail(CT_ENOMEM, "batch: hipMalloc failed");
+        b->owned.push_back(*q);
+        return CT_OK;
+    };
+    auto upload = [&](void* dst, const void* src, size_t bytes) -> int {
+        if (hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+            return ct_fail(CT_EDEVICE, "batch: descriptor upload failed");
+        return CT_OK;
+    };
+    std::vector<PopDev> pd;
+    std::vector<uint32_t> ind_off{0}, ga_off{0};
+    std::vector<RepairSet> setsA, setsC;
+    uint32_t maskA = 0;
+    for (ct_pop* p : pops) {
+        const PopDev& d = p->dev;
+        pd.push_back(d);
+        ind_off.push_back(ind_off.back() + d.P);
+        RepairSet r{};
+        r.S = d.S;
+        r.rows = d.trial;
+        r.n = d.P;
+        r.metric = d.algo == CT_DE ? CT_INDEX_L1 : d.algo == CT_PSO ? CT_TIER_EUCLID : CT_TIER_RANDOM;
+        r.seed = d.seed;
+        r.gen = d.state;
+        r.who = nullptr;
+        r.pos_q16 = d.algo == CT_PSO ? d.X : nullptr;
+        r.out_rows = d.out;
+        r.out_pos = d.tpos;
+        r.apply = nullptr;
+        r.list = p->r_list;
+        r.list_L = p->r_list_L;
+        r.fb_list = p->r_fb;
+        r.fb_L = p->r_fb_L;
+        r.count = d.rcount;
+        r.part_key = p->r_part_key;
+        r.part_pos = p->r_part_pos;
+        r.tally = d.tally;
+        setsA.push_back(r);
+        maskA |= 1u << r.metric;
+        if (d.algo == CT_GA) {
+            RepairSet m = r;
+            m.metric = CT_HAM1_RANDOM;
+            m.rows = d.out;
+            m.apply = d.apply;
+            m.count = d.rcount + 2;
+            m.tally = d.tally + 1;
+            setsC.push_back(m);
+            ga_off.push_back(ga_off.back() + d.P);
+        }
+        b->max_pop = std::max(b->max_pop, d.P);
+    }
+    b->total_ind = ind_off.back();
+    b->n_ga = (uint32_t)setsC.size();
+    int rc;
+    void* q = nullptr;
+    if ((rc = own(&q, pd.size() * sizeof(PopDev)))) return fail(rc);
+    b->d_pops = (PopDev*)q;
+    if ((rc = own(&q, ind_off.size() * 4))) return fail(rc);
+    b->d_ind_off = (uint32_t*)q;
+    if ((rc = upload(b->d_pops, pd.data(), pd.size() * sizeof(PopDev)))) return fail(rc);
+    if ((rc = upload(b->d_ind_off, ind_off.data(), ind_off.size() * 4))) return fail(rc);
+    // main repair pass: every run (its prep items are its individuals)
+    if ((rc = own(&q, setsA.size() * sizeof(RepairSet)))) return fail(rc);
+    if ((rc = upload(q, setsA.data(), setsA.size() * sizeof(RepairSet)))) return fail(rc);
+    b->passA.n_sets = b->n;
+    b->passA.d_sets = (RepairSet*)q;
+    b->passA.d_prep_off = b->d_ind_off;
+    b->passA.total_n = b->total_ind;
+    b->passA.metrics_mask = maskA;
+    if ((rc = repair_plan_alloc(b->passA.plan, b->n, b->owned))) return fail(rc);
+    // GA mutation pass
+    if (b->n_ga) {
+        if ((rc = own(&q, setsC.size() * sizeof(RepairSet)))) return fail(rc);
+        if ((rc = upload(q, setsC.data(), setsC.size() * sizeof(RepairSet)))) return fail(rc);
+        b->passC.d_sets = (RepairSet*)q;
+        if ((rc = own(&q, ga_off.size() * 4))) return fail(rc);
+        if ((rc = upload(q, ga_off.data(), ga_off.size() * 4))) return fail(rc);
+        b->passC.d_prep_off = (uint32_t*)q;
+        b->passC.n_sets = b->n_ga;
+        b->passC.total_n = ga_off.back();
+        b->passC.metrics_mask = 1u << CT_HAM1_RANDOM;
+        if ((rc = repair_plan_alloc(b->passC.plan, b->n_ga, b->owned))) return fail(rc);
+    }
+    *out = b;
+    return CT_OK;
+}
+
+void batch_free(ct_batch* b) {
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (void* q : b->owned) (void)hipFree(q);
+    delete b;
+}
+
 int ct_fail(int code, const std::string& msg) {
     g_err = msg;
     return code;
@@ -173,6 +281,10 @@ int ct_space_build(const int64_t* values, const uint32_t* radices, uint32_t n_pa
     S.code = s->d_code;
     rc = space_build_device(s, st);
     if (rc) return fail(rc);
+    if (hipMalloc(&s->d_dev, sizeof(DevSpace)) != hipSuccess)
+        return fail(ct_fail(CT_ENOMEM, "ct_space_build: hipMalloc failed"));
+    if (hipMemcpy(s->d_dev, &s->dev, sizeof(DevSpace), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(ct_fail(CT_EDEVICE, "ct_space_build: upload failed"));
     *out = s;
     return CT_OK;
 }
@@ -225,7 +337,7 @@ void ct_space_free(ct_space* s) {
     if (!s) return;
     (void)hipDeviceSynchronize();
     void* bufs[] = {s->d_values, s->d_code, s->d_prefix, s->d_words, s->d_lin, s->d_rows, s->d_prevnext,
-                    s->d_grp_off, s->d_dir8, s->d_boxes};
+                    s->d_grp_off, s->d_dir8, s->d_boxes, s->d_dev};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete s;
@@ -248,29 +360,57 @@ int ct_repair(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t met
     if (metric > CT_HAM1_RANDOM) return ct_fail(CT_EINVAL, "ct_repair: unknown metric");
     if (metric == CT_TIER_EUCLID && n && !d_pos_q16)
         return ct_fail(CT_EINVAL, "ct_repair: TIER_EUCLID needs particle positions");
-    if (n > 0xFFFFFFFFull) return ct_fail(CT_EINVAL, "ct_repair: at most 2^32-1 rows per call");
+    if (n > 0x7FFFFFFFull) return ct_fail(CT_EINVAL, "ct_repair: at most 2^31-1 rows per call");
     if (s->n_valid == 0) return ct_fail(CT_EEMPTY, "ct_repair: the space has no valid configuration");
     if (n == 0) return CT_OK;
     hipStream_t st = as_stream(stream);
-    RepairScratch rs;
-    int rc = repair_scratch_alloc(rs, n, 0, st);
-    if (rc) return rc;
-    RepairJob J{};
-    J.S_host = &s->dev;
-    J.S = s->dev;
-    J.rows = d_rows;
-    J.n = n;
-    J.metric = metric;
-    J.seed = seed;
-    J.d_gen = nullptr;
-    J.gen_value = generation;
-    J.who = d_who;
-    J.pos_q16 = d_pos_q16;
-    J.out_rows = d_out_rows;
-    J.out_pos = d_out_pos;
-    J.apply = nullptr;
-    rc = launch_repair(s, J, rs, st);
-    repair_scratch_free(rs, st);
+    // one candidate set: scratch lists, per-part winners, the set itself and its plan
+    const uint64_t slots = std::max<uint64_t>(n, kRepairTargetWaves);
+    const size_t bytes = n * (4 + 8 + 4 + 8) + slots * (8 + 4) + 2 * 4 + 2 * 4 + sizeof(RepairSet) + 64;
+    uint8_t* buf = nullptr;
+    CT_HIP(hipMallocAsync((void**)&buf, bytes, st));
+    RepairSet h{};
+    size_t o = 0;
+    auto take = [&](size_t sz) { void* q = buf + o; o += (sz + 7) & ~size_t(7); return q; };
+    h.S = s->d_dev;
+    h.rows = d_rows;
+    h.n = (uint32_t)n;
+    h.metric = metric;
+    h.seed = seed;
+    h.gen = nullptr;
+    h.gen_value = generation;
+    h.who = d_who;
+    h.pos_q16 = d_pos_q16;
+    h.out_rows = d_out_rows;
+    h.out_pos = d_out_pos;
+    h.apply = nullptr;
+    h.list = (uint32_t*)take(n * 4);
+    h.list_L = (uint64_t*)take(n * 8);
+    h.fb_list = (uint32_t*)take(n * 4);
+    h.fb_L = (uint64_t*)take(n * 8);
+    h.part_key = (uint64_t*)take(slots * 8);
+    h.part_pos = (uint32_t*)take(slots * 4);
+    h.count = (uint32_t*)take(2 * 4);
+    h.tally = nullptr;
+    uint32_t* prep_off = (uint32_t*)take(2 * 4);
+    RepairSet* d_set = (RepairSet*)take(sizeof(RepairSet));
+    const uint32_t h_off[2] = {0, (uint32_t)n};
+    std::vector<void*> owned;
+    RepairPasses rp;
+    int rc = repair_plan_alloc(rp.plan, 1, owned);
+    if (!rc) {
+        CT_HIP(hipMemcpyAsync(d_set, &h, sizeof(RepairSet), hipMemcpyHostToDevice, st));
+        CT_HIP(hipMemcpyAsync(prep_off, h_off, sizeof(h_off), hipMemcpyHostToDevice, st));
+        rp.n_sets = 1;
+        rp.d_sets = d_set;
+        rp.d_prep_off = prep_off;
+        rp.total_n = (uint32_t)n;
+        rp.metrics_mask = 1u << metric;
+        rc = launch_repair_passes(rp, true, st);
+    }
+    (void)hipFreeAsync(buf, st);
+    (void)hipStreamSynchronize(st);
+    for (void* q : owned) (void)hipFree(q);
     return rc;
 }
 
@@ -297,7 +437,8 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_ob
     p->space = s;
     p->prm = q;
     PopDev& d = p->dev;
-    d.S = s->dev;
+    d.S = s->d_dev;
+    d.n_valid = s->n_valid;
     d.algo = q.algo;
     d.P = q.pop_size;
     d.D = s->D;
@@ -318,7 +459,8 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_ob
         ct_pop_free(p);
         return code_;
     };
-    if ((rc = dalloc(p, &d.state, 4)) || (rc = dalloc(p, &d.tally, 2)) || (rc = dalloc(p, &d.best, 1)) || (rc = dalloc(p, &d.trial, (size_t)P * d.R)) ||
+    const uint64_t slots = std::max<uint64_t>(P, kRepairTargetWaves);
+    if ((rc = dalloc(p, &d.state, 4)) || (rc = dalloc(p, &d.tally, 2)) || (rc = dalloc(p, &d.rcount, 4)) || (rc = dalloc(p, &d.best, 1)) || (rc = dalloc(p, &d.trial, (size_t)P * d.R)) ||
         (rc = dalloc(p, &d.out, (size_t)P * d.R)) || (rc = dalloc(p, &d.tpos, P)) || (rc = dalloc(p, &d.apply, P)))
         return fail(rc);
     if (q.algo == CT_PSO) {
@@ -353,8 +495,12 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_ob
     }
     if (hipMemsetAsync(d.tally, 0, 2 * sizeof(unsigned long long), st) != hipSuccess)
         return fail(ct_fail(CT_EDEVICE, "ct_pop_create: memset failed"));
-    if ((rc = repair_scratch_alloc(p->rs, P, 0, st))) return fail(rc);
+    if ((rc = dalloc(p, &p->r_list, P)) || (rc = dalloc(p, &p->r_list_L, P)) || (rc = dalloc(p, &p->r_fb, P)) ||
+        (rc = dalloc(p, &p->r_fb_L, P)) || (rc = dalloc(p, &p->r_part_key, slots)) ||
+        (rc = dalloc(p, &p->r_part_pos, slots)))
+        return fail(rc);
     if ((rc = pop_init_device(p, st))) return fail(rc);
+    if ((rc = batch_build(std::vector<ct_pop*>{p}, &p->single, st))) return fail(rc);
     *out = p;
     return CT_OK;
 }
@@ -365,13 +511,70 @@ int ct_step(ct_pop* const* pops, uint32_t n_pops, uint32_t n_generations, uint32
     for (uint32_t k = 0; k < n_pops; k++)
         if (!pops[k]) return ct_fail(CT_EINVAL, "ct_step: null population");
     hipStream_t st = as_stream(stream);
-    for (uint32_t g = 0; g < n_generations; g++)
-        for (uint32_t k = 0; k < n_pops; k++) {
-            int rc = pop_step_plain(pops[k], st);
+    if (flags == CT_STEP_PLAIN) {
+        for (uint32_t g = 0; g < n_generations; g++)
+            for (uint32_t k = 0; k < n_pops; k++) {
+                int rc = batch_generation(pops[k]->single, st);
+                if (rc) return rc;
+            }
+        return CT_OK;
+    }
+    ct_batch* b = nullptr;
+    int rc = ct_batch_create(pops, n_pops, &b);
+    if (rc) return rc;
+    rc = ct_batch_step(b, n_generations, flags, stream);
+    (void)hipStreamSynchronize(st);
+    ct_batch_free(b);
+    return rc;
+}
+
+int ct_batch_create(ct_pop* const* pops, uint32_t n_pops, ct_batch** out) {
+    if (!out || (n_pops && !pops)) return ct_fail(CT_EINVAL, "ct_batch_create: null argument");
+    *out = nullptr;
+    std::vector<ct_pop*> v(pops, pops + n_pops);
+    for (ct_pop* p : v)
+        if (!p) return ct_fail(CT_EINVAL, "ct_batch_create: null population");
+    for (size_t a = 0; a < v.size(); a++)
+        for (size_t b = a + 1; b < v.size(); b++)
+            if (v[a] == v[b]) return ct_fail(CT_EINVAL, "ct_batch_create: a population appears twice");
+    return batch_build(v, out, nullptr);
+}
+
+int ct_batch_step(ct_batch* b, uint32_t n_generations, uint32_t flags, void* stream) {
+    if (!b) return ct_fail(CT_EINVAL, "ct_batch_step: null batch");
+    if (flags != CT_STEP_BATCHED && flags != CT_STEP_GRAPH) return ct_fail(CT_EINVAL, "ct_batch_step: flags");
+    hipStream_t st = as_stream(stream);
+    if (flags == CT_STEP_BATCHED) {
+        for (uint32_t g = 0; g < n_generations; g++) {
+            int rc = batch_generation(b, st);
             if (rc) return rc;
         }
+        return CT_OK;
+    }
+    if (!b->exec) {
+        // capture one generation once; replays need no host work (the generation counter is on the device)
+        hipStream_t cs = nullptr;
+        CT_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        prof_suspend(true);
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        int rc = e == hipSuccess ? batch_generation(b, cs) : ct_fail(CT_EDEVICE, "hipStreamBeginCapture failed");
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        prof_suspend(false);
+        (void)hipStreamDestroy(cs);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e2 != hipSuccess || !g) return ct_fail(CT_EDEVICE, "hipStreamEndCapture failed");
+        b->graph = g;
+        CT_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    for (uint32_t g = 0; g < n_generations; g++) CT_HIP(hipGraphLaunch(b->exec, st));
     return CT_OK;
 }
+
+void ct_batch_free(ct_batch* b) { batch_free(b); }
 
 int ct_pop_read(const ct_pop* p, uint32_t* h_pos, float* h_f, uint32_t* best_pos, float* best_f,
                 uint32_t* generation, uint32_t* reinits) {
@@ -487,8 +690,7 @@ int ct_pop_restore(ct_pop* p, const void* h_buf, size_t len) {
 void ct_pop_free(ct_pop* p) {
     if (!p) return;
     (void)hipDeviceSynchronize();
-    repair_scratch_free(p->rs, nullptr);
-    (void)hipDeviceSynchronize();
+    batch_free(p->single);
     for (void* q : p->allocs) (void)hipFree(q);
     delete p;
 }

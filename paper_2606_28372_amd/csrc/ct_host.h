@@ -1,4 +1,5 @@
-// Host-side internals of libct: handle layouts, error reporting, launch wrappers.
+// Host-side internals of libct: handle layouts, device descriptors shared by
+// host and kernels, error reporting and the launch entry points of each file.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,6 +11,7 @@
 #include "ct_device.h"
 
 int ct_fail(int code, const std::string& msg);
+void prof_suspend(bool on);          // no event records (while a stream is being captured)
 
 // Records HIP events around the enclosed launch when kernel timing is enabled.
 class ProfScope {
@@ -30,7 +32,8 @@ class ProfScope {
     } while (0)
 
 struct ct_space {
-    DevSpace dev{};                   // device view handed to kernels
+    DevSpace dev{};                   // host copy of the device view
+    DevSpace* d_dev = nullptr;        // the same view in device memory
     uint32_t D = 0, R = 0, n_cons = 0;
     std::vector<int64_t> values;
     std::vector<uint32_t> radices;
@@ -54,41 +57,62 @@ int space_build_device(ct_space* s, hipStream_t st);
 int launch_valid_mask(const ct_space* s, const uint8_t* rows, uint64_t n, uint8_t* out, hipStream_t st);
 int launch_rank(const ct_space* s, const uint8_t* rows, uint64_t n, int64_t* pos, hipStream_t st);
 
-// Per-candidate repair job description shared by ct_repair and the optimiser steps.
-struct RepairJob {
-    const DevSpace* S_host;           // host copy of the space view (for launch shapes)
-    DevSpace S;                       // passed to kernels
+// ---------------------------------------------------------------------------
+// Repair: one RepairSet per (candidate batch, pass); sets live in device
+// memory so one launch can serve many runs of different spaces.
+// ---------------------------------------------------------------------------
+struct RepairSet {
+    const DevSpace* S;                // device view of the space
     const uint8_t* rows;              // candidates [n][R]
-    uint64_t n;
+    uint32_t n;
     uint32_t metric;
     uint64_t seed;
-    const uint32_t* d_gen;            // device generation counter (nullable -> gen_value)
+    const uint32_t* gen;              // device generation counter (nullable -> gen_value)
     uint32_t gen_value;
+    uint32_t pad0;
     const uint32_t* who;              // nullable: candidate index
     const int32_t* pos_q16;           // TIER_EUCLID positions [n][D]
-    uint8_t* out_rows;
-    uint32_t* out_pos;
-    const uint8_t* apply;             // nullable: per-candidate flag, 0 = leave alone (still written)
-    unsigned long long* tally;        // nullable: += number of candidates scanned
+    uint8_t* out_rows;                // [n][R]
+    uint32_t* out_pos;                // [n]
+    const uint8_t* apply;             // nullable: per-candidate flag, 0 = leave alone
+    uint32_t* list;                   // candidates that need a scan [n]
+    uint64_t* list_L;                 // their linear indices [n]
+    uint32_t* fb_list;                // candidates without any tier 0-2 neighbour [n]
+    uint64_t* fb_L;
+    uint32_t* count;                  // [0] list length, [1] fallback length
+    uint64_t* part_key;               // per (candidate, part) winners [slots]
+    uint32_t* part_pos;
+    unsigned long long* tally;        // nullable: += candidates scanned
 };
 
-struct RepairScratch {
-    uint32_t* list = nullptr;         // candidates that need a scan, then the fallback list [2][cap]
-    uint64_t* list_L = nullptr;       // their linear indices [2][cap]
-    uint32_t* count = nullptr;        // [2]: list length, fallback length
-    uint64_t* part_key = nullptr;     // per (candidate, part) best key
-    uint32_t* part_pos = nullptr;     // per (candidate, part) best position
-    uint64_t cap = 0;
-    uint32_t max_parts = 0;
+// Device-side plan of one scan pass over a set array (written by k_repair_plan).
+struct RepairPlan {
+    uint32_t* cand_off;               // [n_sets + 1] prefix of candidate counts
+    uint32_t* item_off;               // [5][n_sets + 1] prefix of (candidate, part) items per metric
+    uint32_t* parts;                  // [n_sets]
 };
 
-int repair_scratch_alloc(RepairScratch& rs, uint64_t cap, uint32_t max_parts, hipStream_t st);
-void repair_scratch_free(RepairScratch& rs, hipStream_t st);
-int launch_repair(const ct_space* s, const RepairJob& job, RepairScratch& rs, hipStream_t st);
+constexpr uint32_t kRepairTargetWaves = 8192;   // scan items per pass (also the per-set slot minimum)
 
-// One optimiser run's device view (kernel argument).
+// Host helpers to run a repair pass sequence over a device set array.
+struct RepairPasses {
+    uint32_t n_sets = 0;
+    const RepairSet* d_sets = nullptr;
+    const uint32_t* d_prep_off = nullptr;   // [n_sets + 1] prefix of n
+    uint32_t total_n = 0;
+    uint32_t metrics_mask = 0;              // metrics present among the sets (bit per ct_metric)
+    RepairPlan plan{};
+};
+int repair_plan_alloc(RepairPlan& p, uint32_t n_sets, std::vector<void*>& owned);
+// prep + scan + finish (+ Hamming fallback for tiered metrics); `zero_counts` clears the
+// sets' counters with a kernel first (the step sequence clears them in its propose kernel).
+int launch_repair_passes(const RepairPasses& rp, bool zero_counts, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Optimiser runs
+// ---------------------------------------------------------------------------
 struct PopDev {
-    DevSpace S;
+    const DevSpace* S;                // device view of the run's space
     uint32_t algo, P, D, R;
     uint64_t seed;
     uint32_t F_q16, de_best;
@@ -96,9 +120,10 @@ struct PopDev {
     int64_t w_q16, c1_q16, c2_q16;
     uint32_t mut_thresh;              // floor(2^32 / mutation_chance)
     uint32_t M;                       // largest radix (PSO domain [0, M) per dimension)
+    uint64_t n_valid;
     const float* obj;                 // [n_valid]
     uint32_t* state;                  // [0] generation, [1] reinits, [2] gbest index, [3] accepted
-    uint64_t* best;                   // packed (float bits << 32) | position
+    uint64_t* best;                   // packed (orderable float bits << 32) | position
     uint32_t* pos;                    // [P] population (DE/GA) as valid-list positions
     float* f;                         // [P]
     uint8_t* trial;                   // [P][R] proposals
@@ -115,16 +140,44 @@ struct PopDev {
     float* f_pb;                      // PSO [P]
     uint32_t* pb_pos;                 // PSO [P]
     unsigned long long* tally;        // [0] repair scans, [1] mutation scans (cumulative)
+    uint32_t* rcount;                 // [4] repair counters: main pass, fallback, mutation pass, spare
 };
+
+struct ct_batch;
 
 struct ct_pop {
     const ct_space* space = nullptr;
     ct_pop_params prm{};
     PopDev dev{};
-    RepairScratch rs;
     std::vector<void*> allocs;
+    ct_batch* single = nullptr;       // batch of this run alone (plain stepping)
+    // repair scratch of this run
+    uint32_t* r_list = nullptr;
+    uint64_t* r_list_L = nullptr;
+    uint32_t* r_fb = nullptr;
+    uint64_t* r_fb_L = nullptr;
+    uint64_t* r_part_key = nullptr;
+    uint32_t* r_part_pos = nullptr;
+};
+
+// A fixed group of runs stepped together (descriptor arrays and, once captured, a graph).
+struct ct_batch {
+    std::vector<ct_pop*> pops;
+    uint32_t n = 0;
+    PopDev* d_pops = nullptr;
+    uint32_t* d_ind_off = nullptr;    // [n + 1] prefix of population sizes
+    uint32_t total_ind = 0;
+    uint32_t n_ga = 0, max_pop = 0;
+    RepairPasses passA, passC;        // main repair, GA mutation
+    std::vector<void*> owned;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 // step.hip
 int pop_init_device(ct_pop* p, hipStream_t st);
-int pop_step_plain(ct_pop* p, hipStream_t st);
+int batch_generation(ct_batch* b, hipStream_t st);
+
+// api.cpp
+int batch_build(const std::vector<ct_pop*>& pops, ct_batch** out, hipStream_t st);
+void batch_free(ct_batch* b);

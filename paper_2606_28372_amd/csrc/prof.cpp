@@ -16,6 +16,7 @@ struct Rec {
 };
 std::mutex g_mu;
 bool g_on = false;
+bool g_suspend = false;
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 
@@ -33,7 +34,7 @@ hipEvent_t take() {
 
 ProfScope::ProfScope(const char* name, hipStream_t st) : name_(name), st_(st), a_(nullptr) {
     std::lock_guard<std::mutex> g(g_mu);
-    if (!g_on) return;
+    if (!g_on || g_suspend) return;
     a_ = take();
     (void)hipEventRecord((hipEvent_t)a_, st_);
 }
@@ -44,6 +45,11 @@ ProfScope::~ProfScope() {
     hipEvent_t b = take();
     (void)hipEventRecord(b, st_);
     g_recs.push_back(Rec{name_, (hipEvent_t)a_, b});
+}
+
+void prof_suspend(bool on) {
+    std::lock_guard<std::mutex> g(g_mu);
+    g_suspend = on;
 }
 
 extern "C" int ct_prof_enable(int on) {

@@ -7,22 +7,26 @@
 // with a metric-specific key k.  The work is a branch-and-bound scan:
 //   - the valid list is cut into 64-row blocks, each with a per-parameter
 //     bounding box [min, max] of its value indices (built with the space);
-//   - a wave holds 64 candidates (sorted by linear index so that lanes are
-//     close in the space), one per lane, and walks a contiguous part of the
-//     list; for every block each lane computes a lower bound of its key over
-//     the box, and the whole wave skips the block when no lane could improve;
-//   - every lane starts from an upper bound taken from the valid rows next to
-//     the candidate in linear-index order, so pruning starts at once;
-//   - rows of a block are wave-uniform loads; keys are computed with byte-SIMD
-//     instructions (v_sad_u8 for index distance, a byte-equality mask for
-//     Hamming) and only rows whose tier can still win pay for the expensive
-//     part (Euclidean distance, Philox draw);
-//   - parts are reduced lexicographically (key, position) by one wave per
-//     candidate, and ties resolve to the lowest linear index everywhere
-//     because rows are visited in ascending order within a part.
-// The tiered rules of Alg. 2 / Alg. 3 search the strictly-adjacent,
-// adjacent and Hamming-1 neighbours first; only candidates with none of
-// those fall back to a Hamming scan of the whole list.
+//   - one wave owns one (candidate, part of the list) item and holds the
+//     candidate wave-uniform; its lanes first test 64 boxes at once against
+//     the candidate's current bound (a lower bound of the key over the box),
+//     then evaluate each surviving block with one row per lane;
+//   - the bound starts from the 64 valid rows around the candidate's place in
+//     linear-index order, so pruning is effective from the first block;
+//   - keys use byte-SIMD instructions (v_sad_u8 for index distance, a
+//     byte-equality mask for Hamming); only rows whose tier can still win pay
+//     for the expensive part (Euclidean distance, Philox draw);
+//   - per-part winners are reduced lexicographically (key, position) by one
+//     wave per candidate; ties resolve to the lowest linear index because rows
+//     are visited in ascending order within a part.
+// The tiered rules of Alg. 2 / Alg. 3 search the strictly-adjacent, adjacent
+// and Hamming-1 neighbours first; only candidates with none of those fall
+// back to a Hamming scan of the whole list.
+//
+// Every kernel walks an array of RepairSets (device memory), so one launch per
+// phase serves any number of candidate batches over any number of spaces; a
+// one-block plan kernel turns the per-set candidate counts into the item
+// space of each scan without a round trip to the host.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,71 +36,20 @@
 namespace {
 
 constexpr int kBlock = 256;
-constexpr uint32_t kTargetWaves = 8192;   // scan items launched per pass
+constexpr uint32_t kTargetWaves = kRepairTargetWaves;
 constexpr uint32_t kMinSubPerPart = 32;   // 64-row blocks per part, at least
 constexpr uint64_t kNoKey = ~0ull;
 constexpr uint32_t kNoPos = 0xFFFFFFFFu;
 constexpr uint64_t kTier3 = 3ull << 62;
+constexpr uint32_t kMaxSets = 4096;
+constexpr uint32_t kNumMetrics = 5;
 
 __device__ __forceinline__ uint32_t ne_bytes(uint32_t x) {
     // 0x80 in every byte of x that is non-zero
     return ((((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u);
 }
 
-__device__ __forceinline__ uint32_t job_gen(const RepairJob& j) { return j.d_gen ? *j.d_gen : j.gen_value; }
-
-// Parts of the valid list per candidate: enough (candidate, part) waves to fill the chip,
-// each part at least kMinSubPerPart 64-row blocks.  count * parts <= max(count, kTargetWaves).
-__device__ __forceinline__ void scan_parts(uint32_t count, uint64_t n_sub, uint32_t* parts) {
-    uint64_t p = count ? kTargetWaves / count : 1;
-    const uint64_t pmax = n_sub / kMinSubPerPart;
-    if (p > pmax) p = pmax;
-    if (p < 1) p = 1;
-    *parts = (uint32_t)p;
-}
-
 __device__ __forceinline__ uint32_t wave_lane() { return threadIdx.x & 63u; }
-
-// ---------------------------------------------------------------------------
-// prep: validity from the bitmask, rank from the directory, list of the
-// candidates that need a scan (with their linear index for sorting)
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_repair_prep(RepairJob J, uint32_t* __restrict__ list,
-                                                        uint64_t* __restrict__ list_L, uint32_t* __restrict__ count) {
-    const DevSpace& S = J.S;
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool in = i < J.n;
-    bool need = false;
-    uint64_t L = ~0ull;
-    if (in) {
-        Row c;
-        row_load(c, J.rows + i * S.R, S.R);
-        const bool dom = row_in_domain(S, c);
-        L = dom ? row_encode(S, c) : ~0ull;
-        const bool valid = dom && bit_valid(S, L);
-        row_store(c, J.out_rows + i * S.R, S.R);
-        J.out_pos[i] = valid ? (uint32_t)rank_dir(S, L) : kNoPos;
-        const bool act = J.apply == nullptr || J.apply[i];
-        need = act && (J.metric == CT_HAM1_RANDOM || !valid);
-    }
-    uint64_t m = __ballot(need);
-    if (m) {
-        uint32_t lane = wave_lane();
-        uint32_t leader = (uint32_t)__ffsll((long long)m) - 1u;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(m));
-        base = __shfl(base, (int)leader, 64);
-        if (need) {
-            uint32_t k = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-            list[k] = (uint32_t)i;
-            list_L[k] = L;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// the scan: one candidate per wave, lanes over boxes and then over rows
-// ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
@@ -109,7 +62,21 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
     return v;
 }
 
+// largest s with off[s] <= item, for off[0] = 0 <= item < off[n]
+__device__ __forceinline__ uint32_t find_set(const uint32_t* off, uint32_t n, uint32_t item) {
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= item) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool tiered_metric(uint32_t m) { return m == CT_TIER_EUCLID || m == CT_TIER_RANDOM; }
+
+// ---------------------------------------------------------------------------
 // Per-candidate state, wave-uniform (the candidate is the same in every lane).
+// ---------------------------------------------------------------------------
 template <int M, int RW>
 struct Cand {
     uint32_t c[RW];
@@ -119,8 +86,7 @@ struct Cand {
     uint32_t who, gen;
     uint64_t seed;
 
-    __device__ void load(const RepairJob& J, uint32_t ci) {
-        const DevSpace& S = J.S;
+    __device__ void load(const RepairSet& J, const DevSpace& S, uint32_t ci) {
         const uint32_t* cr = reinterpret_cast<const uint32_t*>(J.rows + (uint64_t)ci * S.R);
 #pragma unroll
         for (int k = 0; k < RW; ++k) {
@@ -155,7 +121,7 @@ struct Cand {
         }
         if constexpr (M == CT_TIER_RANDOM || M == CT_HAM1_RANDOM) {
             who = uni(J.who ? J.who[ci] : ci);
-            gen = uni(job_gen(J));
+            gen = uni(J.gen ? *J.gen : J.gen_value);
             seed = J.seed;
         }
     }
@@ -268,33 +234,22 @@ struct Cand {
     }
 };
 
-// One wave = one (candidate, part) item.  For the tiered metrics the bound starts at tier 3,
-// so only neighbours of tiers 0-2 are wanted; the Hamming fallback handles the rest.
+// One (candidate, part) item.  For the tiered metrics the bound starts at tier 3, so only
+// neighbours of tiers 0-2 are wanted; the Hamming fallback pass handles the rest.
 template <int M, int RW>
-__global__ __launch_bounds__(kBlock) void k_repair_scan(RepairJob J, const uint32_t* __restrict__ list,
-                                                        const uint64_t* __restrict__ list_L,
-                                                        const uint32_t* __restrict__ count_p,
-                                                        uint64_t* __restrict__ part_key,
-                                                        uint32_t* __restrict__ part_pos) {
-    const DevSpace& S = J.S;
-    const uint32_t count = *count_p;
-    if (count == 0) return;
-    uint32_t parts;
-    scan_parts(count, S.n_sub, &parts);
-    const uint32_t item = uni(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
-    if (item >= count * parts) return;
-    const uint32_t li = item / parts, part = item % parts;
+__device__ void scan_item(const RepairSet& J, const DevSpace& S, const uint32_t* list, const uint64_t* list_L,
+                          uint32_t li, uint32_t part, uint32_t parts) {
     const uint32_t lane = wave_lane();
     const uint32_t ci = uni(list[li]);
     Cand<M, RW> C;
-    C.load(J, ci);
+    C.load(J, S, ci);
     const uint32_t* rows32 = reinterpret_cast<const uint32_t*>(S.rows);
 
     constexpr bool tiered = (M == CT_TIER_EUCLID || M == CT_TIER_RANDOM);
     uint64_t bk = tiered ? kTier3 : kNoKey;        // wave-uniform exclusive bound: keys below it are wanted
-    // seed the bound from the 64 valid rows around the candidate's place in linear-index order
     const uint64_t L = ((uint64_t)uni((uint32_t)(list_L[li] >> 32)) << 32) | uni((uint32_t)list_L[li]);
     if (L != ~0ull) {
+        // seed the bound from the 64 valid rows around the candidate's place in linear-index order
         const uint64_t ins = rank_dir(S, L);
         const int64_t q = (int64_t)ins - 32 + (int64_t)lane;
         uint64_t k = kNoKey;
@@ -315,7 +270,6 @@ __global__ __launch_bounds__(kBlock) void k_repair_scan(RepairJob J, const uint3
     for (uint64_t cb = b0; cb < b1; cb += 64) {
         // lanes over 64 boxes: which ones can hold a row below the bound?
         const uint64_t b = cb + lane;
-        bool pass = false;
         uint64_t lb = kNoKey;
         if (b < b1) {
             uint32_t lo[RW], hi[RW];
@@ -325,9 +279,8 @@ __global__ __launch_bounds__(kBlock) void k_repair_scan(RepairJob J, const uint3
                 hi[w] = box32[b * 2u * RW + RW + w];
             }
             lb = C.bound_box(lo, hi);
-            pass = lb < bk;
         }
-        uint64_t m = __ballot(pass);
+        uint64_t m = __ballot(lb < bk);
         while (m) {
             const uint32_t t = (uint32_t)__ffsll((long long)m) - 1u;
             m &= m - 1ull;
@@ -342,10 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_scan(RepairJob J, const uint3
             }
             const uint64_t wm = wave_min_u64(mk);
             bk = wm < bk ? wm : bk;
-            if (m) {
-                // drop boxes of this chunk that the tighter bound now rules out
-                m &= __ballot(lb < bk);
-            }
+            if (m) m &= __ballot(lb < bk);          // drop boxes the tighter bound now rules out
         }
     }
     // lexicographic (key, position) minimum over the wave
@@ -359,32 +309,154 @@ __global__ __launch_bounds__(kBlock) void k_repair_scan(RepairJob J, const uint3
         if (kq < k2 || (kq == k2 && pq < p2)) { k2 = kq; p2 = pq; }
     }
     if (lane == 0) {
-        part_key[(uint64_t)li * parts + part] = k2;
-        part_pos[(uint64_t)li * parts + part] = p2;
+        J.part_key[(uint64_t)li * parts + part] = k2;
+        J.part_pos[(uint64_t)li * parts + part] = p2;
     }
 }
 
-// Reduce the parts of every candidate (one wave per candidate) and write the result.
-// fb_list / fb_count (nullable): candidates whose first pass found nothing.
-__global__ __launch_bounds__(kBlock) void k_repair_finish(RepairJob J, const uint32_t* __restrict__ list,
-                                                          const uint32_t* __restrict__ count_p,
-                                                          const uint64_t* __restrict__ part_key,
-                                                          const uint32_t* __restrict__ part_pos,
-                                                          uint32_t* __restrict__ fb_list, uint64_t* __restrict__ fb_L,
-                                                          uint32_t* __restrict__ fb_count) {
-    const DevSpace& S = J.S;
-    const uint32_t count = *count_p;
-    uint32_t parts;
-    scan_parts(count, S.n_sub, &parts);
-    if (J.tally && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(J.tally, (unsigned long long)count);
+// ---------------------------------------------------------------------------
+// kernels over set arrays
+// ---------------------------------------------------------------------------
+__global__ void k_repair_zero(const RepairSet* __restrict__ sets, uint32_t n_sets) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n_sets) {
+        sets[s].count[0] = 0;
+        sets[s].count[1] = 0;
+    }
+}
+
+// Validity from the bitmask, rank from the directory, list of the candidates that need a scan.
+__global__ __launch_bounds__(kBlock) void k_repair_prep(const RepairSet* __restrict__ sets, uint32_t n_sets,
+                                                        const uint32_t* __restrict__ prep_off) {
+    const uint32_t total = prep_off[n_sets];
+    for (uint32_t item = blockIdx.x * blockDim.x + threadIdx.x; item < total; item += gridDim.x * blockDim.x) {
+        const uint32_t s = find_set(prep_off, n_sets, item);
+        const RepairSet& J = sets[s];
+        const DevSpace& S = *J.S;
+        const uint32_t i = item - prep_off[s];
+        Row c;
+        row_load(c, J.rows + (uint64_t)i * S.R, S.R);
+        const bool dom = row_in_domain(S, c);
+        const uint64_t L = dom ? row_encode(S, c) : ~0ull;
+        const bool valid = dom && bit_valid(S, L);
+        row_store(c, J.out_rows + (uint64_t)i * S.R, S.R);
+        J.out_pos[i] = valid ? (uint32_t)rank_dir(S, L) : kNoPos;
+        const bool act = J.apply == nullptr || J.apply[i];
+        if (act && (J.metric == CT_HAM1_RANDOM || !valid)) {
+            const uint32_t k = atomicAdd(&J.count[0], 1u);
+            J.list[k] = i;
+            J.list_L[k] = L;
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t lane) {
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o) x += y;
+    }
+    return x - v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// One wave: per-set candidate counts -> parts and item offsets of one scan pass.  Lane l owns
+// a contiguous slice of the sets; offsets are the wave prefix of the lanes' totals plus the
+// running sum inside the slice.  which = 0: main lists with each set's metric; which = 1:
+// fallback lists, Hamming.
+__global__ __launch_bounds__(64) void k_repair_plan(const RepairSet* __restrict__ sets, uint32_t n_sets,
+                                                    uint32_t which, RepairPlan plan) {
+    const uint32_t lane = threadIdx.x;
+    const uint32_t chunk = (n_sets + 63u) / 64u;
+    const uint32_t s0 = min(n_sets, lane * chunk), s1 = min(n_sets, s0 + chunk);
+    uint32_t local = 0;
+    for (uint32_t s = s0; s < s1; ++s) local += sets[s].count[which];
+    const uint32_t total = wave_sum_u32(local);
+    uint64_t gp = total ? kTargetWaves / total : 1;
+    if (gp < 1) gp = 1;
+    uint32_t tc = 0, ti[kNumMetrics] = {0, 0, 0, 0, 0};
+    for (uint32_t s = s0; s < s1; ++s) {
+        const uint64_t pmax = sets[s].S->n_sub / kMinSubPerPart;
+        uint64_t p = gp > pmax ? pmax : gp;
+        if (p < 1) p = 1;
+        plan.parts[s] = (uint32_t)p;
+        const uint32_t c = sets[s].count[which];
+        const uint32_t m = which ? (uint32_t)CT_HAMMING : sets[s].metric;
+        tc += c;
+#pragma unroll
+        for (uint32_t q = 0; q < kNumMetrics; ++q) ti[q] += q == m ? c * (uint32_t)p : 0u;
+    }
+    uint32_t oc = wave_excl_scan(tc, lane), oi[kNumMetrics];
+#pragma unroll
+    for (uint32_t q = 0; q < kNumMetrics; ++q) oi[q] = wave_excl_scan(ti[q], lane);
+    for (uint32_t s = s0; s < s1; ++s) {
+        const uint32_t p = plan.parts[s];
+        const uint32_t c = sets[s].count[which];
+        const uint32_t m = which ? (uint32_t)CT_HAMMING : sets[s].metric;
+        plan.cand_off[s] = oc;
+#pragma unroll
+        for (uint32_t q = 0; q < kNumMetrics; ++q) plan.item_off[q * (n_sets + 1) + s] = oi[q];
+        oc += c;
+#pragma unroll
+        for (uint32_t q = 0; q < kNumMetrics; ++q) oi[q] += q == m ? c * p : 0u;
+    }
+    if (lane == 63) {
+        plan.cand_off[n_sets] = oc;
+#pragma unroll
+        for (uint32_t q = 0; q < kNumMetrics; ++q) plan.item_off[q * (n_sets + 1) + n_sets] = oi[q];
+    }
+}
+
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_repair_scan(const RepairSet* __restrict__ sets, uint32_t n_sets,
+                                                        RepairPlan plan, uint32_t which) {
+    const uint32_t* off = plan.item_off + M * (n_sets + 1);
+    const uint32_t total = off[n_sets];
+    const uint32_t waves = gridDim.x * (kBlock / 64);
+    for (uint32_t item = uni(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)); item < total; item += waves) {
+        const uint32_t s = uni(find_set(off, n_sets, item));
+        const RepairSet& J = sets[s];
+        const DevSpace& S = *J.S;
+        const uint32_t parts = uni(plan.parts[s]);
+        const uint32_t local = item - off[s];
+        const uint32_t li = local / parts, part = local % parts;
+        const uint32_t* list = which ? J.fb_list : J.list;
+        const uint64_t* list_L = which ? J.fb_L : J.list_L;
+        switch (uni(S.R)) {
+        case 4: scan_item<M, 1>(J, S, list, list_L, li, part, parts); break;
+        case 8: scan_item<M, 2>(J, S, list, list_L, li, part, parts); break;
+        case 16: scan_item<M, 4>(J, S, list, list_L, li, part, parts); break;
+        default: scan_item<M, 8>(J, S, list, list_L, li, part, parts); break;
+        }
+    }
+}
+
+// Reduce the parts of every candidate (one wave per candidate) and write the result.  In the main
+// pass of a tiered set, candidates without a tier 0-2 neighbour go to the fallback list.
+__global__ __launch_bounds__(kBlock) void k_repair_finish(const RepairSet* __restrict__ sets, uint32_t n_sets,
+                                                          RepairPlan plan, uint32_t which) {
+    const uint32_t total = plan.cand_off[n_sets];
     const uint32_t lane = wave_lane();
     const uint32_t waves = gridDim.x * (kBlock / 64);
-    for (uint32_t li = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); li < count; li += waves) {
+    for (uint32_t item = uni(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)); item < total; item += waves) {
+        const uint32_t s = uni(find_set(plan.cand_off, n_sets, item));
+        const RepairSet& J = sets[s];
+        const DevSpace& S = *J.S;
+        const uint32_t parts = plan.parts[s];
+        const uint32_t li = item - plan.cand_off[s];
+        if (which == 0 && li == 0 && lane == 0 && J.tally)
+            atomicAdd(J.tally, (unsigned long long)(plan.cand_off[s + 1] - plan.cand_off[s]));
         uint64_t bk = kNoKey;
         uint32_t bp = kNoPos;
         for (uint32_t p = lane; p < parts; p += 64) {
-            const uint64_t k = part_key[(uint64_t)li * parts + p];
-            const uint32_t q = part_pos[(uint64_t)li * parts + p];
+            const uint64_t k = J.part_key[(uint64_t)li * parts + p];
+            const uint32_t q = J.part_pos[(uint64_t)li * parts + p];
             if (q != kNoPos && (k < bk || (k == bk && q < bp))) { bk = k; bp = q; }
         }
 #pragma unroll
@@ -394,105 +466,80 @@ __global__ __launch_bounds__(kBlock) void k_repair_finish(RepairJob J, const uin
             const uint64_t k = ((uint64_t)khi << 32) | klo;
             if (k < bk || (k == bk && q < bp)) { bk = k; bp = q; }
         }
-        const uint32_t ci = list[li];
+        const uint32_t ci = (which ? J.fb_list : J.list)[li];
         if (bp != kNoPos) {
             const uint32_t* src = reinterpret_cast<const uint32_t*>(S.rows + (uint64_t)bp * S.R);
             uint32_t* dst = reinterpret_cast<uint32_t*>(J.out_rows + (uint64_t)ci * S.R);
             if (lane < S.R / 4) dst[lane] = src[lane];
             if (lane == 0) J.out_pos[ci] = bp;
-        } else if (fb_count && lane == 0) {
-            const uint32_t k = atomicAdd(fb_count, 1u);
-            fb_list[k] = ci;
-            fb_L[k] = ~0ull;             // no seed: the fallback scans the whole list
+        } else if (which == 0 && tiered_metric(J.metric) && lane == 0) {
+            const uint32_t k = atomicAdd(&J.count[1], 1u);
+            J.fb_list[k] = ci;
+            J.fb_L[k] = ~0ull;           // no seed: the fallback scans the whole list
         }
     }
 }
 
 template <int M>
-void launch_scan_w(const RepairJob& J, uint32_t RW, const uint32_t* list, const uint64_t* list_L,
-                   const uint32_t* count, const RepairScratch& rs, hipStream_t st) {
-    const uint64_t items = std::max<uint64_t>(kTargetWaves, J.n);   // >= count * parts
-    dim3 g((uint32_t)((items + 3) / 4)), b(kBlock);
+void launch_scan(const RepairPasses& rp, uint32_t which, hipStream_t st) {
     ProfScope ps_("k_repair_scan", st);
-    switch (RW) {
-    case 1: hipLaunchKernelGGL((k_repair_scan<M, 1>), g, b, 0, st, J, list, list_L, count, rs.part_key, rs.part_pos); break;
-    case 2: hipLaunchKernelGGL((k_repair_scan<M, 2>), g, b, 0, st, J, list, list_L, count, rs.part_key, rs.part_pos); break;
-    case 4: hipLaunchKernelGGL((k_repair_scan<M, 4>), g, b, 0, st, J, list, list_L, count, rs.part_key, rs.part_pos); break;
-    default: hipLaunchKernelGGL((k_repair_scan<M, 8>), g, b, 0, st, J, list, list_L, count, rs.part_key, rs.part_pos); break;
-    }
+    hipLaunchKernelGGL((k_repair_scan<M>), dim3(kTargetWaves / (kBlock / 64)), dim3(kBlock), 0, st, rp.d_sets,
+                       rp.n_sets, rp.plan, which);
 }
 
-void launch_finish(const RepairJob& J, const uint32_t* list, const uint32_t* count, const RepairScratch& rs,
-                   uint32_t* fb_list, uint64_t* fb_L, uint32_t* fb_count, hipStream_t st) {
-    uint32_t gf = (uint32_t)std::min<uint64_t>((J.n + 3) / 4, 4096);
-    ProfScope ps_("k_repair_finish", st);
-    hipLaunchKernelGGL(k_repair_finish, dim3(gf), dim3(kBlock), 0, st, J, list, count, rs.part_key, rs.part_pos,
-                       fb_list, fb_L, fb_count);
-}
+uint32_t finish_grid(uint32_t n) { return std::max<uint32_t>(1, std::min<uint32_t>((n + 3) / 4, 2048)); }
 
 }  // namespace
 
-int repair_scratch_alloc(RepairScratch& rs, uint64_t cap, uint32_t max_parts, hipStream_t st) {
-    (void)max_parts;
-    rs.cap = cap ? cap : 1;
-    // parts * count <= max(count, kTargetWaves)
-    const uint64_t slots = std::max<uint64_t>(rs.cap, (uint64_t)kTargetWaves);
-    rs.max_parts = kTargetWaves;
-    CT_HIP(hipMallocAsync((void**)&rs.list, 2 * rs.cap * sizeof(uint32_t), st));
-    CT_HIP(hipMallocAsync((void**)&rs.list_L, 2 * rs.cap * sizeof(uint64_t), st));
-    CT_HIP(hipMallocAsync((void**)&rs.count, 2 * sizeof(uint32_t), st));
-    CT_HIP(hipMallocAsync((void**)&rs.part_key, slots * sizeof(uint64_t), st));
-    CT_HIP(hipMallocAsync((void**)&rs.part_pos, slots * sizeof(uint32_t), st));
+int repair_plan_alloc(RepairPlan& p, uint32_t n_sets, std::vector<void*>& owned) {
+    if (n_sets > kMaxSets) return ct_fail(CT_EINVAL, "repair: at most 4096 candidate sets per launch");
+    void* a = nullptr;
+    const size_t words = (size_t)(n_sets + 1) * (1 + kNumMetrics) + n_sets;
+    CT_HIP(hipMalloc(&a, words * sizeof(uint32_t)));
+    owned.push_back(a);
+    uint32_t* w = static_cast<uint32_t*>(a);
+    p.cand_off = w;
+    p.item_off = w + (n_sets + 1);
+    p.parts = w + (n_sets + 1) * (1 + kNumMetrics);
     return CT_OK;
 }
 
-void repair_scratch_free(RepairScratch& rs, hipStream_t st) {
-    if (rs.list) (void)hipFreeAsync(rs.list, st);
-    if (rs.list_L) (void)hipFreeAsync(rs.list_L, st);
-    if (rs.count) (void)hipFreeAsync(rs.count, st);
-    if (rs.part_key) (void)hipFreeAsync(rs.part_key, st);
-    if (rs.part_pos) (void)hipFreeAsync(rs.part_pos, st);
-    rs = RepairScratch{};
-}
-
-int launch_repair(const ct_space* s, const RepairJob& J, RepairScratch& rs, hipStream_t st) {
-    if (J.n == 0) return CT_OK;
-    if (J.n > rs.cap) return ct_fail(CT_EINVAL, "repair: more candidates than the scratch holds");
-    uint32_t* list = rs.list;
-    uint64_t* list_L = rs.list_L;
-    uint32_t* fb_list = rs.list + rs.cap;
-    uint64_t* fb_L = rs.list_L + rs.cap;
-    uint32_t* count = rs.count;
-    uint32_t* fb_count = rs.count + 1;
-    CT_HIP(hipMemsetAsync(rs.count, 0, 2 * sizeof(uint32_t), st));
-    uint32_t gp = (uint32_t)std::min<uint64_t>((J.n + kBlock - 1) / kBlock, 0x7FFFFFFFull);
-    { ProfScope ps_("k_repair_prep", st); hipLaunchKernelGGL(k_repair_prep, dim3(gp), dim3(kBlock), 0, st, J, list, list_L, count); }
-    const uint32_t RW = s->R / 4;
-    switch (J.metric) {
-    case CT_HAMMING:
-        launch_scan_w<CT_HAMMING>(J, RW, list, list_L, count, rs, st);
-        launch_finish(J, list, count, rs, nullptr, nullptr, nullptr, st);
-        break;
-    case CT_INDEX_L1:
-        launch_scan_w<CT_INDEX_L1>(J, RW, list, list_L, count, rs, st);
-        launch_finish(J, list, count, rs, nullptr, nullptr, nullptr, st);
-        break;
-    case CT_HAM1_RANDOM:
-        launch_scan_w<CT_HAM1_RANDOM>(J, RW, list, list_L, count, rs, st);
-        launch_finish(J, list, count, rs, nullptr, nullptr, nullptr, st);
-        break;
-    default: {
-        // tiered rules: neighbours first, Hamming over the whole list for candidates without any
-        if (J.metric == CT_TIER_EUCLID) launch_scan_w<CT_TIER_EUCLID>(J, RW, list, list_L, count, rs, st);
-        else launch_scan_w<CT_TIER_RANDOM>(J, RW, list, list_L, count, rs, st);
-        launch_finish(J, list, count, rs, fb_list, fb_L, fb_count, st);
-        RepairJob J2 = J;
-        J2.metric = CT_HAMMING;
-        J2.tally = nullptr;
-        launch_scan_w<CT_HAMMING>(J2, RW, fb_list, fb_L, fb_count, rs, st);
-        launch_finish(J2, fb_list, fb_count, rs, nullptr, nullptr, nullptr, st);
-        break;
+int launch_repair_passes(const RepairPasses& rp, bool zero_counts, hipStream_t st) {
+    if (rp.n_sets == 0 || rp.total_n == 0) return CT_OK;
+    if (zero_counts) {
+        ProfScope ps_("k_repair_zero", st);
+        hipLaunchKernelGGL(k_repair_zero, dim3((rp.n_sets + 255) / 256), dim3(256), 0, st, rp.d_sets, rp.n_sets);
     }
+    {
+        ProfScope ps_("k_repair_prep", st);
+        const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>((rp.total_n + kBlock - 1) / kBlock, 4096));
+        hipLaunchKernelGGL(k_repair_prep, dim3(g), dim3(kBlock), 0, st, rp.d_sets, rp.n_sets, rp.d_prep_off);
+    }
+    {
+        ProfScope ps_("k_repair_plan", st);
+        hipLaunchKernelGGL(k_repair_plan, dim3(1), dim3(64), 0, st, rp.d_sets, rp.n_sets, 0u, rp.plan);
+    }
+    if (rp.metrics_mask & (1u << CT_HAMMING)) launch_scan<CT_HAMMING>(rp, 0, st);
+    if (rp.metrics_mask & (1u << CT_INDEX_L1)) launch_scan<CT_INDEX_L1>(rp, 0, st);
+    if (rp.metrics_mask & (1u << CT_TIER_EUCLID)) launch_scan<CT_TIER_EUCLID>(rp, 0, st);
+    if (rp.metrics_mask & (1u << CT_TIER_RANDOM)) launch_scan<CT_TIER_RANDOM>(rp, 0, st);
+    if (rp.metrics_mask & (1u << CT_HAM1_RANDOM)) launch_scan<CT_HAM1_RANDOM>(rp, 0, st);
+    {
+        ProfScope ps_("k_repair_finish", st);
+        hipLaunchKernelGGL(k_repair_finish, dim3(finish_grid(rp.total_n)), dim3(kBlock), 0, st, rp.d_sets, rp.n_sets,
+                           rp.plan, 0u);
+    }
+    if (rp.metrics_mask & ((1u << CT_TIER_EUCLID) | (1u << CT_TIER_RANDOM))) {
+        {
+            ProfScope ps_("k_repair_plan", st);
+            hipLaunchKernelGGL(k_repair_plan, dim3(1), dim3(64), 0, st, rp.d_sets, rp.n_sets, 1u, rp.plan);
+        }
+        launch_scan<CT_HAMMING>(rp, 1, st);
+        {
+            ProfScope ps_("k_repair_finish", st);
+            hipLaunchKernelGGL(k_repair_finish, dim3(finish_grid(rp.total_n)), dim3(kBlock), 0, st, rp.d_sets,
+                               rp.n_sets, rp.plan, 1u);
+        }
     }
     CT_HIP(hipGetLastError());
     return CT_OK;

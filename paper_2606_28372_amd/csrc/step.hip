@@ -1,4 +1,4 @@
-// Constraint-aware population steps on the GPU.
+// Constraint-aware population steps on the GPU, for any number of runs per launch.
 //
 //   DE  (Alg. 1, Section IV-B): best1bin/rand1bin mutation on value indices in
 //       Q16.16 (round half up, clip), binomial crossover with j_rand, repair by
@@ -13,9 +13,13 @@
 //       selection, single-point crossover, Alg. 3 repair, then mutation to a
 //       random valid Hamming neighbour with chance 1/mutation_chance.
 //
-// The generation number lives on the device and every random draw is a
-// Philox block at a counter (individual, generation, purpose | sub-index), so
-// a step is a pure function of the state and replays bit-identically.
+// One generation of a batch of runs is: sort (GA runs, one block each) ->
+// propose (one thread per individual of every run) -> repair passes (shared
+// kernels over the runs' repair sets) -> select (one block per run).  The
+// generation number lives on the device and every random draw is a Philox
+// block at a counter (individual, generation, purpose | sub-index), so a step
+// is a pure function of the state; the same sequence is captured once into a
+// hipGraph and replayed for every generation.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,8 +45,8 @@ __device__ __forceinline__ uint64_t below64(uint32_t u, uint64_t n) {
 
 // member i of the stratified initial sample (stratum [i n / P, (i+1) n / P) of the valid list)
 __device__ __forceinline__ uint32_t init_pos(const PopDev& p, uint32_t i, uint32_t tag) {
-    uint64_t n = p.S.n_valid;
-    uint64_t lo = (uint64_t)i * n / p.P, hi = (uint64_t)(i + 1) * n / p.P;
+    const uint64_t n = p.n_valid;
+    const uint64_t lo = (uint64_t)i * n / p.P, hi = (uint64_t)(i + 1) * n / p.P;
     U4 o = ct_philox(p.seed, i, tag, (uint32_t)PUR_INIT << 24, 0);
     return (uint32_t)(lo + below64(o.x, hi - lo));
 }
@@ -83,15 +87,25 @@ __device__ uint32_t block_sum_u32(uint32_t v) {
 }
 
 __device__ __forceinline__ void valid_row(const PopDev& p, uint32_t pos, Row& r) {
-    row_load(r, p.S.rows + (uint64_t)pos * p.R, p.R);
+    row_load(r, p.S->rows + (uint64_t)pos * p.R, p.R);
 }
 
 __device__ __forceinline__ uint32_t member_load(const uint32_t* m, uint32_t pos) {
     return (__hip_atomic_load(m + (pos >> 5), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> (pos & 31u)) & 1u;
 }
 
+// largest s with off[s] <= item
+__device__ __forceinline__ uint32_t find_run(const uint32_t* off, uint32_t n, uint32_t item) {
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= item) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 // ---------------------------------------------------------------------------
-// initial population (generation 0)
+// initial population (generation 0), one run
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_init(PopDev p) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -137,36 +151,33 @@ __global__ __launch_bounds__(kSelBlock) void k_init_finish(PopDev p) {
 }
 
 // ---------------------------------------------------------------------------
-// DE
+// propose: one thread per individual of every run
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t pick_excl(uint32_t u, uint32_t n, uint32_t* ex, uint32_t n_ex) {
+__device__ __forceinline__ uint32_t pick_excl(uint32_t u, uint32_t n, const uint32_t* ex, uint32_t n_ex) {
     uint32_t k = ct_below(u, n - n_ex);
     for (uint32_t a = 0; a < n_ex; ++a)          // ex is sorted ascending
         if (k >= ex[a]) ++k;
     return k;
 }
 
-__device__ __forceinline__ void sort_small(uint32_t* e, uint32_t n) {
+__device__ __forceinline__ void sort3(uint32_t* e, uint32_t n) {
     for (uint32_t a = 1; a < n; ++a)
         for (uint32_t b = a; b > 0 && e[b - 1] > e[b]; --b) {
             uint32_t t = e[b]; e[b] = e[b - 1]; e[b - 1] = t;
         }
 }
 
-__global__ __launch_bounds__(kBlock) void k_de_propose(PopDev p) {
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= p.P) return;
-    const uint32_t g = p.state[0];
+__device__ void de_propose(const PopDev& p, uint32_t i, uint32_t g) {
     U4 o = ct_philox(p.seed, i, g, (uint32_t)PUR_DE_PICK << 24, 0);
     uint32_t ex[3] = {i, 0, 0};
-    uint32_t r1 = pick_excl(o.x, p.P, ex, 1);
+    const uint32_t r1 = pick_excl(o.x, p.P, ex, 1);
     ex[1] = r1;
-    sort_small(ex, 2);
-    uint32_t r2 = pick_excl(o.y, p.P, ex, 2);
+    sort3(ex, 2);
+    const uint32_t r2 = pick_excl(o.y, p.P, ex, 2);
     ex[2] = r2;
-    sort_small(ex, 3);
-    uint32_t r3 = pick_excl(o.z, p.P, ex, 3);
-    uint32_t jr = ct_below(o.w, p.D);
+    sort3(ex, 3);
+    const uint32_t r3 = pick_excl(o.z, p.P, ex, 3);
+    const uint32_t jr = ct_below(o.w, p.D);
     Row base, x, a, b, u;
     valid_row(p, p.de_best ? (uint32_t)(*p.best & 0xFFFFFFFFu) : p.pos[r1], base);
     valid_row(p, p.pos[i], x);
@@ -175,24 +186,125 @@ __global__ __launch_bounds__(kBlock) void k_de_propose(PopDev p) {
     u = x;
     U4 cr{0, 0, 0, 0};
     for (uint32_t j = 0; j < p.D; ++j) {
-        int64_t num = (int64_t)base.digit(j) * 65536 + (int64_t)p.F_q16 * ((int64_t)a.digit(j) - (int64_t)b.digit(j)) +
-                      32768;
+        const int64_t num = (int64_t)base.digit(j) * 65536 +
+                            (int64_t)p.F_q16 * ((int64_t)a.digit(j) - (int64_t)b.digit(j)) + 32768;
         int64_t m = num >> 16;                    // floor
-        int64_t hi = (int64_t)p.S.radix[j] - 1;
+        const int64_t hi = (int64_t)p.S->radix[j] - 1;
         m = m < 0 ? 0 : (m > hi ? hi : m);
         if ((j & 3u) == 0) cr = ct_philox(p.seed, i, g, ((uint32_t)PUR_DE_CR << 24) | (j >> 2), 0);
-        uint32_t cu = (j & 3u) == 0 ? cr.x : (j & 3u) == 1 ? cr.y : (j & 3u) == 2 ? cr.z : cr.w;
+        const uint32_t cu = (j & 3u) == 0 ? cr.x : (j & 3u) == 1 ? cr.y : (j & 3u) == 2 ? cr.z : cr.w;
         if ((uint64_t)cu < p.CR_q32 || j == jr) u.set(j, (uint32_t)m);
     }
     row_store(u, p.trial + (uint64_t)i * p.R, p.R);
 }
 
-__global__ __launch_bounds__(kSelBlock) void k_de_select(PopDev p) {
+__device__ void pso_propose(const PopDev& p, uint32_t i, uint32_t g) {
+    const uint32_t gi = p.state[2];
+    const int64_t xmax = (int64_t)p.M * 65536 - 1;
+    Row c;
+#pragma unroll
+    for (int q = 0; q < CT_DMAX / 4; ++q) c.w[q] = 0;
+    for (uint32_t j = 0; j < p.D; ++j) {
+        U4 o = ct_philox(p.seed, i, g, ((uint32_t)PUR_PSO_R << 24) | j, 0);
+        const int64_t r1 = o.x >> 16, r2 = o.y >> 16;
+        const uint64_t k = (uint64_t)i * p.D + j;
+        int64_t x = p.X[k], v = p.V[k];
+        const int64_t pb = p.PB[k], gb = p.PB[(uint64_t)gi * p.D + j];
+        v = ((p.w_q16 * v) >> 16) + ((((p.c1_q16 * r1) >> 16) * (pb - x)) >> 16) +
+            ((((p.c2_q16 * r2) >> 16) * (gb - x)) >> 16);
+        x += v;
+        x = x < 0 ? 0 : (x > xmax ? xmax : x);
+        p.V[k] = v;
+        p.X[k] = (int32_t)x;
+        const uint32_t d = (uint32_t)(x >> 16);
+        c.set(j, d < p.S->radix[j] ? d : p.S->radix[j] - 1u);
+    }
+    row_store(c, p.trial + (uint64_t)i * p.R, p.R);
+}
+
+__device__ __forceinline__ uint32_t beta_rank(const PopDev& p, uint32_t u) {
+    uint32_t lo = 0, hi = p.P - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if ((uint64_t)u < p.beta[mid]) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+// child i of pair i/2: A[:cut] + B[cut:] for even i, B[:cut] + A[cut:] for odd i
+__device__ void ga_propose(const PopDev& p, uint32_t i, uint32_t g) {
+    const uint32_t k = i >> 1;
+    U4 o = ct_philox(p.seed, k, g, (uint32_t)PUR_GA_SEL << 24, 0);
+    const uint32_t a = beta_rank(p, o.x), b = beta_rank(p, o.y);
+    const uint32_t cut = 1u + ct_below(o.z, p.D - 1u);
+    Row A, B;
+    valid_row(p, p.sorted[a], A);
+    valid_row(p, p.sorted[b], B);
+    Row c = (i & 1u) ? B : A;
+    const Row& tail = (i & 1u) ? A : B;
+    for (uint32_t j = cut; j < p.D; ++j) c.set(j, tail.digit(j));
+    row_store(c, p.trial + (uint64_t)i * p.R, p.R);
+    U4 m = ct_philox(p.seed, i, g, (uint32_t)PUR_GA_MUT << 24, 0);
+    p.apply[i] = m.x < p.mut_thresh;
+}
+
+__global__ __launch_bounds__(kBlock) void k_propose(const PopDev* __restrict__ pops, uint32_t n,
+                                                    const uint32_t* __restrict__ ind_off) {
+    const uint32_t total = ind_off[n];
+    for (uint32_t item = blockIdx.x * blockDim.x + threadIdx.x; item < total; item += gridDim.x * blockDim.x) {
+        const uint32_t r = find_run(ind_off, n, item);
+        const PopDev& p = pops[r];
+        const uint32_t i = item - ind_off[r];
+        const uint32_t g = p.state[0];
+        if (i == 0) {
+            // repair counters of this generation (no memset nodes inside captured graphs)
+            p.rcount[0] = 0;
+            p.rcount[1] = 0;
+            p.rcount[2] = 0;
+            p.rcount[3] = 0;
+        }
+        if (p.algo == CT_DE) de_propose(p, i, g);
+        else if (p.algo == CT_PSO) pso_propose(p, i, g);
+        else ga_propose(p, i, g);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// GA: sort the population by (objective, position), one block per GA run
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kSelBlock) void k_ga_sort(const PopDev* __restrict__ pops, uint32_t n) {
+    __shared__ uint64_t key[kGaMaxSort];
+    const PopDev& p = pops[blockIdx.x];
+    if (p.algo != CT_GA) return;
+    uint32_t m = 1;
+    while (m < p.P) m <<= 1;
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) key[i] = i < p.P ? best_key(p.f[i], p.pos[i]) : ~0ull;
+    __syncthreads();
+    for (uint32_t k = 2; k <= m; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const bool up = (i & k) == 0;
+                    const uint64_t a = key[i], b = key[l];
+                    if ((a > b) == up) { key[i] = b; key[l] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < p.P; i += blockDim.x) p.sorted[i] = (uint32_t)key[i];
+}
+
+// ---------------------------------------------------------------------------
+// select: one block per run
+// ---------------------------------------------------------------------------
+__device__ void de_select(const PopDev& p) {
     const uint32_t g = p.state[0];
     // pre-accept: no worse than the member it would replace and not already in X
     for (uint32_t i = threadIdx.x; i < p.P; i += blockDim.x) {
-        uint32_t t = p.tpos[i];
-        bool pa = t < p.S.n_valid && p.obj[t] <= p.f[i] && !member_load(p.member, t);
+        const uint32_t t = p.tpos[i];
+        const bool pa = t < p.n_valid && p.obj[t] <= p.f[i] && !member_load(p.member, t);
         p.apply[i] = pa ? 1 : 0;
         if (pa) atomicMin(&p.claim[t], i);
     }
@@ -201,8 +313,7 @@ __global__ __launch_bounds__(kSelBlock) void k_de_select(PopDev p) {
     uint32_t acc = 0;
     for (uint32_t i = threadIdx.x; i < p.P; i += blockDim.x) {
         if (p.apply[i]) {
-            uint32_t t = p.tpos[i];
-            uint32_t owner = __hip_atomic_load(&p.claim[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t owner = __hip_atomic_load(&p.claim[p.tpos[i]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (owner == i) { p.apply[i] = 2; ++acc; }
         }
     }
@@ -215,7 +326,7 @@ __global__ __launch_bounds__(kSelBlock) void k_de_select(PopDev p) {
     uint64_t m = ~0ull;
     for (uint32_t i = threadIdx.x; i < p.P; i += blockDim.x) {
         if (p.apply[i] == 2) {
-            uint32_t t = p.tpos[i];
+            const uint32_t t = p.tpos[i];
             atomicOr(&p.member[t >> 5], 1u << (t & 31u));
             p.pos[i] = t;
             p.f[i] = p.obj[t];
@@ -230,7 +341,7 @@ __global__ __launch_bounds__(kSelBlock) void k_de_select(PopDev p) {
         __syncthreads();
         uint64_t m2 = ~0ull;
         for (uint32_t i = threadIdx.x; i < p.P; i += blockDim.x) {
-            uint32_t t = init_pos(p, i, g + 1);
+            const uint32_t t = init_pos(p, i, g + 1);
             atomicOr(&p.member[t >> 5], 1u << (t & 31u));
             p.pos[i] = t;
             p.f[i] = p.obj[t];
@@ -240,7 +351,7 @@ __global__ __launch_bounds__(kSelBlock) void k_de_select(PopDev p) {
         m = min(m, m2);
     }
     if (threadIdx.x == 0) {
-        uint64_t b = *p.best;
+        const uint64_t b = *p.best;
         *p.best = m < b ? m : b;
         p.state[3] = acc;
         if (acc == 0) p.state[1] += 1;
@@ -248,40 +359,12 @@ __global__ __launch_bounds__(kSelBlock) void k_de_select(PopDev p) {
     }
 }
 
-// ---------------------------------------------------------------------------
-// PSO
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_pso_move(PopDev p) {
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= p.P) return;
-    const uint32_t g = p.state[0], gi = p.state[2];
-    const int64_t xmax = (int64_t)p.M * 65536 - 1;
-    Row c;
-#pragma unroll
-    for (int q = 0; q < CT_DMAX / 4; ++q) c.w[q] = 0;
-    for (uint32_t j = 0; j < p.D; ++j) {
-        U4 o = ct_philox(p.seed, i, g, ((uint32_t)PUR_PSO_R << 24) | j, 0);
-        int64_t r1 = o.x >> 16, r2 = o.y >> 16;
-        uint64_t k = (uint64_t)i * p.D + j;
-        int64_t x = p.X[k], v = p.V[k], pb = p.PB[k], gb = p.PB[(uint64_t)gi * p.D + j];
-        v = ((p.w_q16 * v) >> 16) + ((((p.c1_q16 * r1) >> 16) * (pb - x)) >> 16) +
-            ((((p.c2_q16 * r2) >> 16) * (gb - x)) >> 16);
-        x += v;
-        x = x < 0 ? 0 : (x > xmax ? xmax : x);
-        p.V[k] = v;
-        p.X[k] = (int32_t)x;
-        uint32_t d = (uint32_t)(x >> 16);
-        c.set(j, d < p.S.radix[j] ? d : p.S.radix[j] - 1u);
-    }
-    row_store(c, p.trial + (uint64_t)i * p.R, p.R);
-}
-
-__global__ __launch_bounds__(kSelBlock) void k_pso_select(PopDev p) {
+__device__ void pso_select(const PopDev& p) {
     const uint32_t g = p.state[0];
     uint64_t m = ~0ull;
     for (uint32_t i = threadIdx.x; i < p.P; i += blockDim.x) {
-        uint32_t t = p.tpos[i];
-        float fv = t < p.S.n_valid ? p.obj[t] : __int_as_float(0x7F800000);   // +inf: never improves
+        const uint32_t t = p.tpos[i];
+        const float fv = t < p.n_valid ? p.obj[t] : __int_as_float(0x7F800000);   // +inf: never improves
         if (fv < p.f_pb[i]) {
             for (uint32_t j = 0; j < p.D; ++j) p.PB[(uint64_t)i * p.D + j] = p.X[(uint64_t)i * p.D + j];
             p.f_pb[i] = fv;
@@ -291,107 +374,36 @@ __global__ __launch_bounds__(kSelBlock) void k_pso_select(PopDev p) {
     }
     m = block_min_u64(m);
     if (threadIdx.x == 0) {
-        uint32_t gi = (uint32_t)m;
+        const uint32_t gi = (uint32_t)m;
         p.state[2] = gi;
         *p.best = best_key(p.f_pb[gi], p.pb_pos[gi]);
         p.state[0] = g + 1;
     }
 }
 
-// ---------------------------------------------------------------------------
-// GA
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kSelBlock) void k_ga_sort(PopDev p) {
-    __shared__ uint64_t key[kGaMaxSort];
-    uint32_t n = 1;
-    while (n < p.P) n <<= 1;
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) key[i] = i < p.P ? best_key(p.f[i], p.pos[i]) : ~0ull;
-    __syncthreads();
-    for (uint32_t k = 2; k <= n; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-                uint32_t l = i ^ j;
-                if (l > i) {
-                    bool up = (i & k) == 0;
-                    uint64_t a = key[i], b = key[l];
-                    if ((a > b) == up) { key[i] = b; key[l] = a; }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (uint32_t i = threadIdx.x; i < p.P; i += blockDim.x) p.sorted[i] = (uint32_t)key[i];
-}
-
-__device__ __forceinline__ uint32_t beta_rank(const PopDev& p, uint32_t u) {
-    uint32_t lo = 0, hi = p.P - 1;
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        if ((uint64_t)u < p.beta[mid]) hi = mid; else lo = mid + 1;
-    }
-    return lo;
-}
-
-__global__ __launch_bounds__(kBlock) void k_ga_cross(PopDev p) {
-    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (2 * k >= p.P) return;
-    const uint32_t g = p.state[0];
-    U4 o = ct_philox(p.seed, k, g, (uint32_t)PUR_GA_SEL << 24, 0);
-    uint32_t a = beta_rank(p, o.x), b = beta_rank(p, o.y);
-    uint32_t cut = 1u + ct_below(o.z, p.D - 1u);
-    Row A, B, c0, c1;
-    valid_row(p, p.sorted[a], A);
-    valid_row(p, p.sorted[b], B);
-    c0 = A;
-    c1 = B;
-    for (uint32_t j = cut; j < p.D; ++j) {
-        c0.set(j, B.digit(j));
-        c1.set(j, A.digit(j));
-    }
-    row_store(c0, p.trial + (uint64_t)(2 * k) * p.R, p.R);
-    U4 m0 = ct_philox(p.seed, 2 * k, g, (uint32_t)PUR_GA_MUT << 24, 0);
-    p.apply[2 * k] = m0.x < p.mut_thresh;
-    if (2 * k + 1 < p.P) {
-        row_store(c1, p.trial + (uint64_t)(2 * k + 1) * p.R, p.R);
-        U4 m1 = ct_philox(p.seed, 2 * k + 1, g, (uint32_t)PUR_GA_MUT << 24, 0);
-        p.apply[2 * k + 1] = m1.x < p.mut_thresh;
-    }
-}
-
-__global__ __launch_bounds__(kSelBlock) void k_ga_select(PopDev p) {
+__device__ void ga_select(const PopDev& p) {
     const uint32_t g = p.state[0];
     uint64_t m = ~0ull;
     for (uint32_t i = threadIdx.x; i < p.P; i += blockDim.x) {
         uint32_t t = p.tpos[i];
-        if (t >= p.S.n_valid) t = p.pos[i];      // unreachable: every repaired child is valid
+        if (t >= p.n_valid) t = p.pos[i];      // unreachable: every repaired child is valid
         p.pos[i] = t;
         p.f[i] = p.obj[t];
         m = min(m, best_key(p.f[i], t));
     }
     m = block_min_u64(m);
     if (threadIdx.x == 0) {
-        uint64_t b = *p.best;
+        const uint64_t b = *p.best;
         *p.best = m < b ? m : b;
         p.state[0] = g + 1;
     }
 }
 
-RepairJob make_job(const ct_pop* p, uint32_t metric, const uint8_t* rows, uint8_t* out, const uint8_t* apply) {
-    RepairJob J{};
-    J.S_host = &p->space->dev;
-    J.S = p->dev.S;
-    J.rows = rows;
-    J.n = p->dev.P;
-    J.metric = metric;
-    J.seed = p->dev.seed;
-    J.d_gen = p->dev.state;
-    J.who = nullptr;
-    J.pos_q16 = metric == CT_TIER_EUCLID ? p->dev.X : nullptr;
-    J.out_rows = out;
-    J.out_pos = p->dev.tpos;
-    J.apply = apply;
-    J.tally = p->dev.tally + (metric == CT_HAM1_RANDOM ? 1 : 0);
-    return J;
+__global__ __launch_bounds__(kSelBlock) void k_select(const PopDev* __restrict__ pops, uint32_t n) {
+    const PopDev& p = pops[blockIdx.x];
+    if (p.algo == CT_DE) de_select(p);
+    else if (p.algo == CT_PSO) pso_select(p);
+    else ga_select(p);
 }
 
 }  // namespace
@@ -404,32 +416,26 @@ int pop_init_device(ct_pop* p, hipStream_t st) {
     return CT_OK;
 }
 
-int pop_step_plain(ct_pop* p, hipStream_t st) {
-    const PopDev& d = p->dev;
-    const dim3 gi((d.P + kBlock - 1) / kBlock), b(kBlock);
-    int rc = CT_OK;
-    switch (d.algo) {
-    case CT_DE:
-        { ProfScope ps_("k_de_propose", st); hipLaunchKernelGGL(k_de_propose, gi, b, 0, st, d); }
-        rc = launch_repair(p->space, make_job(p, CT_INDEX_L1, d.trial, d.out, nullptr), p->rs, st);
+int batch_generation(ct_batch* b, hipStream_t st) {
+    if (b->n == 0) return CT_OK;
+    if (b->n_ga) {
+        ProfScope ps_("k_ga_sort", st);
+        hipLaunchKernelGGL(k_ga_sort, dim3(b->n), dim3(kSelBlock), 0, st, b->d_pops, b->n);
+    }
+    {
+        ProfScope ps_("k_propose", st);
+        const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>((b->total_ind + kBlock - 1) / kBlock, 4096));
+        hipLaunchKernelGGL(k_propose, dim3(g), dim3(kBlock), 0, st, b->d_pops, b->n, b->d_ind_off);
+    }
+    int rc = launch_repair_passes(b->passA, false, st);
+    if (rc) return rc;
+    if (b->n_ga) {
+        rc = launch_repair_passes(b->passC, false, st);
         if (rc) return rc;
-        { ProfScope ps_("k_de_select", st); hipLaunchKernelGGL(k_de_select, dim3(1), dim3(kSelBlock), 0, st, d); }
-        break;
-    case CT_PSO:
-        { ProfScope ps_("k_pso_move", st); hipLaunchKernelGGL(k_pso_move, gi, b, 0, st, d); }
-        rc = launch_repair(p->space, make_job(p, CT_TIER_EUCLID, d.trial, d.out, nullptr), p->rs, st);
-        if (rc) return rc;
-        { ProfScope ps_("k_pso_select", st); hipLaunchKernelGGL(k_pso_select, dim3(1), dim3(kSelBlock), 0, st, d); }
-        break;
-    default:
-        { ProfScope ps_("k_ga_sort", st); hipLaunchKernelGGL(k_ga_sort, dim3(1), dim3(kSelBlock), 0, st, d); }
-        { ProfScope ps_("k_ga_cross", st); hipLaunchKernelGGL(k_ga_cross, dim3((d.P / 2 + 1 + kBlock - 1) / kBlock), b, 0, st, d); }
-        rc = launch_repair(p->space, make_job(p, CT_TIER_RANDOM, d.trial, d.out, nullptr), p->rs, st);
-        if (rc) return rc;
-        rc = launch_repair(p->space, make_job(p, CT_HAM1_RANDOM, d.out, d.out, d.apply), p->rs, st);
-        if (rc) return rc;
-        { ProfScope ps_("k_ga_select", st); hipLaunchKernelGGL(k_ga_select, dim3(1), dim3(kSelBlock), 0, st, d); }
-        break;
+    }
+    {
+        ProfScope ps_("k_select", st);
+        hipLaunchKernelGGL(k_select, dim3(b->n), dim3(kSelBlock), 0, st, b->d_pops, b->n);
     }
     CT_HIP(hipGetLastError());
     return CT_OK;

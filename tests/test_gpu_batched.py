@@ -1,0 +1,133 @@
+"""Batched stepping is bit-identical to stepping each run alone.
+
+A mixed group of runs (DE, PSO and GA over spaces with different parameter
+counts, row widths and valid-set sizes) is advanced (a) one run at a time,
+(b) with one launch per phase for the whole group, and (c) by replaying a
+captured hipGraph of one generation; every run's full state must be equal
+after every stage, and one run is also checked against the oracle.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import steps as ost
+from tests.gpu_common import gpu_space, oracle_space, say, torch
+from tests.test_gpu_steps import compare, oracle_init, oracle_step
+
+pytestmark = pytest.mark.gpu
+
+
+SPECS = [("tiny", W.OptParams(W.ALGO_DE, 20, 1)), ("gemm10", W.OptParams(W.ALGO_PSO, 200, 2)),
+         ("gemm10", W.OptParams(W.ALGO_GA, 129, 3)), ("gemm13", W.OptParams(W.ALGO_DE, 512, 4)),
+         ("tiny", W.OptParams(W.ALGO_GA, 33, 5)), ("gemm13", W.OptParams(W.ALGO_PSO, 300, 6)),
+         ("gemm13", W.OptParams(W.ALGO_GA, 1024, 7)), ("gemm10", W.OptParams(W.ALGO_DE, 64, 8))]
+OBJ_SEED = {"tiny": 10, "gemm10": 11, "gemm13": 12}
+
+
+def make_runs(t, spaces):
+    from paper_2606_28372_amd import Pop
+    runs = []
+    for name, opt in SPECS:
+        sp, obj = spaces[name]
+        runs.append(Pop.from_opt(sp, opt, obj))
+    return runs
+
+
+@pytest.fixture(scope="module")
+def spaces():
+    t = torch()
+    out = {}
+    for k, name in enumerate(["tiny", "gemm10", "gemm13"]):
+        sp = gpu_space(W.space(name))
+        out[name] = (sp, t.tensor(W.objective(sp.n_valid, OBJ_SEED[name]), device="cuda"))
+    return out
+
+
+def test_batched_and_graph_equal_plain(spaces):
+    from paper_2606_28372_amd import Batch, CT_STEP_BATCHED, CT_STEP_GRAPH, step_many
+    t = torch()
+    plain, batched, graph = make_runs(t, spaces), make_runs(t, spaces), make_runs(t, spaces)
+    b1, b2 = Batch(batched), Batch(graph)
+    for stage in range(3):
+        say(f"[gpu_batched] stage {stage}")
+        step_many(plain, 4)
+        b1.step(4, CT_STEP_BATCHED)
+        b2.step(4, CT_STEP_GRAPH)
+        t.cuda.synchronize()
+        for k, (a, b, c) in enumerate(zip(plain, batched, graph)):
+            sa = a.snapshot()
+            assert sa == b.snapshot(), f"run {k}: batched differs at stage {stage}"
+            assert sa == c.snapshot(), f"run {k}: graph replay differs at stage {stage}"
+    b1.close()
+    b2.close()
+
+
+def test_batched_run_matches_oracle(spaces):
+    from paper_2606_28372_amd import Batch, CT_STEP_GRAPH
+    t = torch()
+    runs = make_runs(t, spaces)
+    b = Batch(runs)
+    b.step(3, CT_STEP_GRAPH)
+    t.cuda.synchronize()
+    osp = oracle_space("gemm13")
+    obj = W.objective(osp.n_valid, 12)
+    for k in (3, 5, 6):
+        name, opt = SPECS[k]
+        osp = oracle_space(name)
+        obj = W.objective(osp.n_valid, OBJ_SEED[name])
+        st = oracle_init(osp, obj, opt)
+        for _ in range(3):
+            st = oracle_step(osp, obj, st, opt)
+        compare(runs[k], st, opt, len(W.space(name).params), f"run {k} ({name}) after 3 graph generations")
+    b.close()
+
+
+def test_step_flags_equal(spaces):
+    from paper_2606_28372_amd import CT_STEP_BATCHED, CT_STEP_GRAPH, step_many
+    t = torch()
+    a, b, c = make_runs(t, spaces), make_runs(t, spaces), make_runs(t, spaces)
+    step_many(a, 3)
+    step_many(b, 3, CT_STEP_BATCHED)
+    step_many(c, 3, CT_STEP_GRAPH)
+    for x, y, z in zip(a, b, c):
+        assert x.snapshot() == y.snapshot() == z.snapshot()
+
+
+def test_many_problem_batch():
+    """24 problems of the many-problem distribution (uneven spaces, dimensions, populations,
+    algorithms): graph replay equals plain stepping; the smallest space of each algorithm also
+    matches the oracle."""
+    from oracle import core as ocore
+    from paper_2606_28372_amd import Batch, CT_STEP_GRAPH, Pop, step_many
+    t = torch()
+    probs = W.batched(24, seed=5)
+    spaces, objs, a, b, opts = [], [], [], [], []
+    for pr in probs:
+        sp = gpu_space(pr.spec)
+        obj = t.tensor(W.objective(sp.n_valid, pr.obj_seed), device="cuda")
+        opt = W.fit_pop(pr.opt, sp.n_valid)
+        spaces.append(sp)
+        objs.append(obj)
+        opts.append(opt)
+        a.append(Pop.from_opt(sp, opt, obj))
+        b.append(Pop.from_opt(sp, opt, obj))
+    say(f"[gpu_batched] many-problem batch: valid sizes {[s.n_valid for s in spaces]}")
+    bt = Batch(b)
+    for stage in range(2):
+        step_many(a, 3)
+        bt.step(3, CT_STEP_GRAPH)
+        t.cuda.synchronize()
+        for k in range(len(probs)):
+            assert a[k].snapshot() == b[k].snapshot(), f"problem {k} differs at stage {stage}"
+    bt.close()
+    for algo in (W.ALGO_DE, W.ALGO_PSO, W.ALGO_GA):
+        mine = [k for k in range(len(probs)) if opts[k].algo == algo]
+        k = min(mine, key=lambda q: spaces[q].n_cartesian)
+        pr, opt = probs[k], opts[k]
+        say(f"[gpu_batched] oracle check of problem {k} ({W.ALGO_NAMES[algo]}, {spaces[k].n_cartesian} configurations)")
+        osp = ocore.Space.from_spec(pr.spec).enumerate()
+        obj = W.objective(osp.n_valid, pr.obj_seed)
+        st = oracle_init(osp, obj, opt)
+        for _ in range(6):
+            st = oracle_step(osp, obj, st, opt)
+        compare(b[k], st, opt, len(pr.spec.params), f"problem {k} after 6 generations")

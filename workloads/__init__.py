@@ -253,6 +253,11 @@ def batched(n_problems: int = 256, seed: int = 3, max_pop: int = 1024) -> List[P
     return [batched_problem(rng, k, max_pop) for k in range(n_problems)]
 
 
+def fit_pop(opt: OptParams, n_valid: int) -> OptParams:
+    """The run's parameters with the population capped at the space's valid-set size."""
+    return dataclasses.replace(opt, pop_size=min(opt.pop_size, n_valid)) if opt.pop_size > n_valid else opt
+
+
 def serving_arrivals(n: int = 2000, mean_interval_s: float = 0.005, seed: int = 4) -> np.ndarray:
     """Poisson arrival times (seconds) of optimiser runs: exponential inter-arrival gaps."""
     rng = np.random.default_rng(seed)
