@@ -20,6 +20,11 @@ printed:
              (plain), with one launch per phase for all runs (batched), and by
              replaying a captured hipGraph of one generation (graph); all three
              start from the same state and must end in the same state,
+  serving    Poisson arrivals of runs from the same many-problem distribution
+             (200 runs/s, 200 generations each) through the serving loop:
+             admission by device footprint into one continuously re-formed
+             batch; p50/p99 per-run step latency (completion to completion),
+             queueing delay and end-to-end time, and run-generations/s,
   cpu_baseline  the oracle on the host cores on a bounded sample of the same job.
 """
 from __future__ import annotations
@@ -167,6 +172,57 @@ def batched_leg(ct, n_problems, gens):
             "algorithms": {W.ALGO_NAMES[a]: sum(1 for pr in probs if pr.opt.algo == a) for a in range(3)}}
 
 
+def serving_leg(ct, n_runs, gens, mean_interval_ms, reserve_gib=8.0):
+    """Serving loop under Poisson arrivals; objective tables are prepared before the clock starts
+    (they stand for measurements the tuning client already holds)."""
+    import torch
+    probs = W.batched(n_runs, seed=4)
+    arrivals = W.serving_arrivals(n_runs, mean_interval_ms / 1e3, seed=4)
+    t_prep = time.perf_counter()
+    tables = []
+    for pr in probs:
+        sp = ct.Space.from_spec(pr.spec)
+        tables.append(W.objective(sp.n_valid, pr.obj_seed))
+        sp.close()
+    t_prep = time.perf_counter() - t_prep
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(free - reserve_gib * (1 << 30))
+    by_id = {}
+    srv = ct.Server(lambda rid, nv: by_id[rid], hbm_budget=budget, max_active=1024)
+    t0 = srv.now()
+    i, busy = 0, 0
+    while i < n_runs or busy:
+        t = srv.now() - t0
+        while i < n_runs and arrivals[i] <= t:
+            rid = srv.submit(probs[i].spec, probs[i].opt, gens, arrival_s=t0 + float(arrivals[i]))
+            by_id[rid] = tables[i]
+            i += 1
+            busy += 1
+        if busy:
+            busy = srv.step()
+        else:
+            time.sleep(max(0.0, min(float(arrivals[i]) - t, 0.002)))
+    wall = srv.now() - t0
+    res = srv.poll()
+    st = srv.stats()
+    ms, act = srv.step_times()
+    srv.close()
+    ok = [r for r in res if r["status"] == 0]
+    per_run = np.repeat(ms, act)
+    q = np.array([r["t_admit"] - r["t_submit"] for r in ok]) * 1e3
+    e2e = np.array([r["t_done"] - r["t_submit"] for r in ok]) * 1e3
+    pct = lambda a, p: float(np.percentile(a, p)) if len(a) else None  # noqa: E731
+    return {"runs": n_runs, "generations_per_run": gens, "mean_interarrival_ms": mean_interval_ms,
+            "completed": st["completed"], "rejected": st["rejected"], "wall_s": wall,
+            "run_generations_per_s": st["run_generations"] / wall,
+            "step_latency_ms": {"p50": pct(per_run, 50), "p99": pct(per_run, 99), "mean": float(per_run.mean())},
+            "queueing_ms": {"p50": pct(q, 50), "p99": pct(q, 99)},
+            "end_to_end_ms": {"p50": pct(e2e, 50), "p99": pct(e2e, 99)},
+            "mean_active": float(act.mean()) if len(act) else 0.0, "max_active": int(act.max()) if len(act) else 0,
+            "steps": st["steps"], "hbm_budget_bytes": budget, "peak_resident_bytes": st["peak_bytes"],
+            "objective_prep_s": t_prep}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +234,10 @@ def main():
     ap.add_argument("--batched-problems", type=int, default=256)
     ap.add_argument("--batched-generations", type=int, default=20)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--serving-runs", type=int, default=2000)
+    ap.add_argument("--serving-generations", type=int, default=200)
+    ap.add_argument("--serving-interarrival-ms", type=float, default=5.0)
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -270,6 +330,8 @@ def main():
         line["generations_per_s_plain"] = bl["generations_per_s"]["plain"]
         line["generations_per_s_batched"] = bl["generations_per_s"]["graph"]
         line["batched"] = bl
+    if not args.no_serving:
+        line["serving"] = serving_leg(ct, args.serving_runs, args.serving_generations, args.serving_interarrival_ms)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec, runs, obj, gens)
     print(json.dumps(line), flush=True)

@@ -274,6 +274,95 @@ int ct_pop_restore(ct_pop* p, const void* h_buf, size_t len);
 void ct_pop_free(ct_pop* p);
 
 /*
+ * Device bytes held by a built space (bitmask, valid list, rank directory,
+ * bounding boxes, value tables) and by a run (population state and repair
+ * scratch; DE adds 4 bytes + 1 bit per valid configuration).  Sizes are the
+ * bytes requested from the allocator.  The objective table is the caller's.
+ */
+int ct_space_footprint(const ct_space* s, uint64_t* bytes);
+int ct_pop_footprint(const ct_pop* p, uint64_t* bytes);
+
+/*
+ * Serving (many optimiser runs arriving over time on one GPU).
+ *
+ * A server keeps every admitted run's space, population and objective table
+ * resident and advances all admitted runs together, one generation per
+ * ct_server_step, as one batch (same kernels and results as ct_batch_step).
+ * Runs are admitted in submission order when (a) fewer than max_active runs
+ * are active and (b) the run's footprint -- its resolved space, its
+ * population state and its objective table, in bytes as ct_space_footprint /
+ * ct_pop_footprint count them -- fits in hbm_budget beside the active runs.
+ * A run's space is resolved at admission on a second stream while the current
+ * generation runs; the resolution stops before allocating the valid list if
+ * it would not fit, and the run then waits.  Runs join and leave at generation
+ * boundaries; each run's results equal those of stepping it alone.
+ *
+ * objective(ctx, run_id, n_valid, h_out) is called on the thread that calls
+ * ct_server_step, once per admitted run, to fill h_out[n_valid] (float32 > 0,
+ * indexed by valid-list position); a non-zero return ends the run with
+ * CT_EINVAL.
+ *
+ * A population larger than the run's valid set is cut to n_valid (reported in
+ * ct_run_result.pop_size).  A run that can never fit (footprint above
+ * hbm_budget), has no valid configuration, or is DE with fewer than 4 valid
+ * configurations ends with status CT_ENOMEM / CT_EEMPTY / CT_EINVAL instead
+ * of running.  The server is not thread-safe:
+ * one thread submits, steps and polls.
+ */
+typedef struct ct_server ct_server;
+typedef int (*ct_objective_fn)(void* ctx, uint64_t run_id, uint64_t n_valid, float* h_out);
+
+typedef struct {
+    uint64_t hbm_budget;            /* bytes for resident runs */
+    uint32_t max_active;            /* slot cap, 1..4096 */
+    uint32_t max_admit_per_step;    /* 0 = no limit */
+    uint32_t keep_snapshots;        /* keep each finished run's ct_pop_snapshot bytes */
+    uint32_t reserved;
+    ct_objective_fn objective;
+    void* objective_ctx;
+} ct_server_config;
+
+typedef struct {
+    uint64_t id;
+    int32_t status;                 /* CT_OK, or why the run did not run */
+    uint32_t generations;           /* generations completed */
+    uint64_t n_valid;
+    uint64_t footprint;             /* device bytes charged while resident */
+    uint32_t best_pos;              /* best configuration (valid-list position) */
+    float best_f;
+    uint32_t reinits;
+    uint32_t pop_size;
+    double t_submit, t_admit, t_done;   /* seconds on the server clock; t_admit < 0: never admitted */
+} ct_run_result;
+
+typedef struct {
+    uint64_t steps, run_generations, submitted, admitted, rejected, completed;
+    uint64_t queued, active, used_bytes, peak_bytes;
+} ct_server_counters;
+
+int ct_server_create(const ct_server_config* cfg, ct_server** out);
+/* Queue a run: the space (as for ct_space_build), its parameters and its
+   generation count.  arrival_s < 0 stamps the submission with ct_server_now(). */
+int ct_server_submit(ct_server* s, const int64_t* values, const uint32_t* radices, uint32_t n_params,
+                     const uint32_t* code, const uint32_t* cons_offsets, uint32_t n_cons, const ct_pop_params* p,
+                     uint32_t n_generations, double arrival_s, uint64_t* run_id);
+/* One generation of the active runs (with admissions overlapped and
+   retirements after it); *n_busy = active + queued runs afterwards. */
+int ct_server_step(ct_server* s, uint32_t* n_busy);
+double ct_server_now(const ct_server* s);
+/* Finished runs not yet polled, oldest first (at most cap). */
+int ct_server_poll(ct_server* s, ct_run_result* out, uint32_t cap, uint32_t* n_out);
+/* The kept snapshot of a finished run (h_buf = NULL: size only). */
+int ct_server_snapshot(const ct_server* s, uint64_t run_id, void* h_buf, size_t* len);
+/* Drop a polled run's host record. */
+int ct_server_release(ct_server* s, uint64_t run_id);
+int ct_server_stats(const ct_server* s, ct_server_counters* out);
+/* Step intervals: completion-to-completion milliseconds of consecutive
+   generations and the number of runs each advanced (cap = 0: count only). */
+int ct_server_step_times(const ct_server* s, float* h_ms, uint32_t* h_active, uint64_t cap, uint64_t* n_out);
+void ct_server_free(ct_server* s);
+
+/*
  * Kernel timing (measurement support, not part of the method).  While enabled,
  * the library records a pair of HIP events on the launch stream around every
  * kernel launch; ct_prof_read synchronises and returns the summed elapsed time

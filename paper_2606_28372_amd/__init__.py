@@ -22,7 +22,7 @@ from . import _lib
 from ._lib import (CT_DE, CT_GA, CT_HAM1_RANDOM, CT_HAMMING, CT_INDEX_L1, CT_PSO, CT_STEP_BATCHED,  # noqa: F401
                    CT_STEP_GRAPH, CT_STEP_PLAIN, CT_TIER_EUCLID, CT_TIER_RANDOM, CtError, ct_pop_params)
 
-__all__ = ["Space", "Pop", "Batch", "compile_constraints", "step_many", "CtError", "CT_HAMMING", "CT_INDEX_L1",
+__all__ = ["Space", "Pop", "Batch", "Server", "compile_constraints", "step_many", "CtError", "CT_HAMMING", "CT_INDEX_L1",
            "CT_TIER_EUCLID", "CT_TIER_RANDOM", "CT_HAM1_RANDOM", "CT_DE", "CT_PSO", "CT_GA",
            "CT_STEP_PLAIN", "CT_STEP_BATCHED", "CT_STEP_GRAPH"]
 
@@ -89,6 +89,12 @@ class Space:
     @property
     def handle(self) -> ctypes.c_void_p:
         return self._h
+
+    def footprint(self) -> int:
+        """Device bytes the built space holds (ct_space_footprint)."""
+        b = ctypes.c_uint64()
+        _lib.check(_lib.load().ct_space_footprint(self._h, ctypes.byref(b)))
+        return int(b.value)
 
     def valid_list(self):
         """(linear indices int64 [n_valid], digit rows uint8 [n_valid, row_bytes]) as new device tensors."""
@@ -198,6 +204,12 @@ class Pop:
         _lib.check(_lib.load().ct_pop_counters(self._h, ctypes.byref(r), ctypes.byref(m)))
         return {"repairs": int(r.value), "mutations": int(m.value)}
 
+    def footprint(self) -> int:
+        """Device bytes the run holds (ct_pop_footprint)."""
+        b = ctypes.c_uint64()
+        _lib.check(_lib.load().ct_pop_footprint(self._h, ctypes.byref(b)))
+        return int(b.value)
+
     def snapshot(self) -> bytes:
         L = _lib.load()
         n = ctypes.c_size_t(0)
@@ -238,6 +250,111 @@ class Batch:
     def close(self):
         if self._h:
             _lib.load().ct_batch_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """ct_server: runs arriving over time, admitted by device footprint into one continuously
+    re-formed batch.  `objective(run_id, n_valid)` returns the float32 objective table of an
+    admitted run (called from inside step())."""
+
+    def __init__(self, objective, hbm_budget: int, max_active: int = 1024, max_admit_per_step: int = 0,
+                 keep_snapshots: bool = False):
+        self._objective = objective
+        self._errors: List[BaseException] = []
+
+        def fill(ctx, run_id, n_valid, h_out):
+            try:
+                v = np.ascontiguousarray(self._objective(int(run_id), int(n_valid)), dtype=np.float32)
+                if v.shape != (int(n_valid),):
+                    raise ValueError(f"objective table of run {run_id} has shape {v.shape}, expected ({n_valid},)")
+                ctypes.memmove(h_out, v.ctypes.data, v.nbytes)
+                return 0
+            except BaseException as e:  # reported by step()
+                self._errors.append(e)
+                return 1
+
+        self._cb = _lib.ct_objective_fn(fill)
+        cfg = _lib.ct_server_config(hbm_budget=int(hbm_budget), max_active=int(max_active),
+                                    max_admit_per_step=int(max_admit_per_step),
+                                    keep_snapshots=1 if keep_snapshots else 0, objective=self._cb)
+        self._h = ctypes.c_void_p()
+        _lib.check(_lib.load().ct_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+
+    def submit(self, spec, opt, n_generations: int, arrival_s: float = -1.0) -> int:
+        values = list(spec.params.values())
+        code, offs = compile_constraints(spec.names, values, spec.constraints)
+        flat = np.ascontiguousarray([int(x) for v in values for x in v], dtype=np.int64)
+        rad = np.ascontiguousarray([len(v) for v in values], dtype=np.uint32)
+        code = code if len(code) else np.zeros(1, dtype=np.uint32)
+        prm = make_params(opt.algo, opt.pop_size, opt.seed, F_q16=opt.F_q16, CR_q32=opt.CR_q32,
+                          de_best=opt.de_best, w_q16=opt.w_q16, c1_q16=opt.c1_q16, c2_q16=opt.c2_q16,
+                          mutation_chance=opt.mutation_chance, beta_b=opt.beta_b)
+        rid = ctypes.c_uint64()
+        _lib.check(_lib.load().ct_server_submit(self._h, flat.ctypes.data, rad.ctypes.data, len(values),
+                                                code.ctypes.data, offs.ctypes.data, len(spec.constraints),
+                                                ctypes.byref(prm), int(n_generations), float(arrival_s),
+                                                ctypes.byref(rid)))
+        return int(rid.value)
+
+    def step(self) -> int:
+        """One server step; returns the number of active + queued runs."""
+        busy = ctypes.c_uint32()
+        _lib.check(_lib.load().ct_server_step(self._h, ctypes.byref(busy)))
+        if self._errors:
+            raise self._errors.pop(0)
+        return int(busy.value)
+
+    def now(self) -> float:
+        return float(_lib.load().ct_server_now(self._h))
+
+    def poll(self) -> List[Dict[str, object]]:
+        out = []
+        buf = (_lib.ct_run_result * 256)()
+        while True:
+            n = ctypes.c_uint32()
+            _lib.check(_lib.load().ct_server_poll(self._h, buf, 256, ctypes.byref(n)))
+            for k in range(n.value):
+                r = buf[k]
+                out.append({f: getattr(r, f) for f, _ in _lib.ct_run_result._fields_})
+            if n.value < 256:
+                return out
+
+    def snapshot(self, run_id: int) -> bytes:
+        L = _lib.load()
+        n = ctypes.c_size_t(0)
+        _lib.check(L.ct_server_snapshot(self._h, run_id, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _lib.check(L.ct_server_snapshot(self._h, run_id, buf, ctypes.byref(n)))
+        return buf.raw[: n.value]
+
+    def release(self, run_id: int):
+        _lib.check(_lib.load().ct_server_release(self._h, run_id))
+
+    def stats(self) -> Dict[str, int]:
+        c = _lib.ct_server_counters()
+        _lib.check(_lib.load().ct_server_stats(self._h, ctypes.byref(c)))
+        return {f: int(getattr(c, f)) for f, _ in _lib.ct_server_counters._fields_}
+
+    def step_times(self):
+        """(interval ms float32 [n], runs advanced uint32 [n]) of every step that followed another."""
+        L = _lib.load()
+        n = ctypes.c_uint64()
+        _lib.check(L.ct_server_step_times(self._h, None, None, 0, ctypes.byref(n)))
+        ms = np.zeros(n.value, dtype=np.float32)
+        act = np.zeros(n.value, dtype=np.uint32)
+        _lib.check(L.ct_server_step_times(self._h, ms.ctypes.data, act.ctypes.data, n.value, ctypes.byref(n)))
+        return ms[: n.value], act[: n.value]
+
+    def close(self):
+        if self._h:
+            _lib.load().ct_server_free(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

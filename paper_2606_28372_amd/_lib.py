@@ -37,6 +37,27 @@ class ct_pop_params(ctypes.Structure):
 _vp, _u32, _u64, _i32, _sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_size_t
 _P = ctypes.POINTER
 
+ct_objective_fn = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
+                                   ctypes.POINTER(ctypes.c_float))
+
+
+class ct_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_active", ctypes.c_uint32),
+                ("max_admit_per_step", ctypes.c_uint32), ("keep_snapshots", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("objective", ct_objective_fn), ("objective_ctx", ctypes.c_void_p)]
+
+
+class ct_run_result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int32), ("generations", ctypes.c_uint32),
+                ("n_valid", ctypes.c_uint64), ("footprint", ctypes.c_uint64), ("best_pos", ctypes.c_uint32),
+                ("best_f", ctypes.c_float), ("reinits", ctypes.c_uint32), ("pop_size", ctypes.c_uint32),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class ct_server_counters(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("steps", "run_generations", "submitted", "admitted", "rejected",
+                                               "completed", "queued", "active", "used_bytes", "peak_bytes")]
+
 # name -> (restype, argtypes), exactly the declarations of include/ct.h
 SIGNATURES = {
     "ct_last_error": (ctypes.c_char_p, []),
@@ -63,6 +84,19 @@ SIGNATURES = {
     "ct_pop_snapshot": (_i32, [_vp, _vp, _P(_sz)]),
     "ct_pop_restore": (_i32, [_vp, _vp, _sz]),
     "ct_pop_free": (None, [_vp]),
+    "ct_space_footprint": (_i32, [_vp, _P(_u64)]),
+    "ct_pop_footprint": (_i32, [_vp, _P(_u64)]),
+    "ct_server_create": (_i32, [_P(ct_server_config), _P(_vp)]),
+    "ct_server_submit": (_i32, [_vp, _vp, _vp, _u32, _vp, _vp, _u32, _P(ct_pop_params), _u32, ctypes.c_double,
+                                _P(_u64)]),
+    "ct_server_step": (_i32, [_vp, _P(_u32)]),
+    "ct_server_now": (ctypes.c_double, [_vp]),
+    "ct_server_poll": (_i32, [_vp, _P(ct_run_result), _u32, _P(_u32)]),
+    "ct_server_snapshot": (_i32, [_vp, _u64, _vp, _P(_sz)]),
+    "ct_server_release": (_i32, [_vp, _u64]),
+    "ct_server_stats": (_i32, [_vp, _P(ct_server_counters)]),
+    "ct_server_step_times": (_i32, [_vp, _vp, _vp, _u64, _P(_u64)]),
+    "ct_server_free": (None, [_vp]),
     "ct_prof_enable": (_i32, [_i32]),
     "ct_prof_read": (_i32, [ctypes.c_char_p, _P(ctypes.c_double), _P(_u64)]),
 }
@@ -78,6 +112,10 @@ def load() -> ctypes.CDLL:
         if _lib is None:
             if not os.path.exists(LIB_PATH):
                 raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2606_28372_amd.build`")
+            # torch carries its own HIP runtime under the same soname as the system one; loading torch
+            # first makes libct bind to that runtime, so there is one runtime per process and torch's
+            # streams and allocations are the library's too
+            import torch  # noqa: F401
             lib = ctypes.CDLL(LIB_PATH)
             for name, (res, args) in SIGNATURES.items():
                 fn = getattr(lib, name)

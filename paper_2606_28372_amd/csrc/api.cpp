@@ -62,37 +62,20 @@ int dalloc(ct_pop* p, T** ptr, size_t n) {
     void* q = nullptr;
     if (hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return ct_fail(CT_ENOMEM, "hipMalloc failed");
     p->allocs.push_back(q);
+    p->dev_bytes += std::max<size_t>(n, 1) * sizeof(T);
     *ptr = reinterpret_cast<T*>(q);
     return CT_OK;
 }
 
 }  // namespace
 
-int batch_build(const std::vector<ct_pop*>& pops, ct_batch** out, hipStream_t st) {
-    (void)st;
-    *out = nullptr;
+int batch_fill(ct_batch* b, const std::vector<ct_pop*>& pops) {
     if (pops.size() > 4096) return ct_fail(CT_EINVAL, "batch: at most 4096 populations");
-    ct_batch* b = new ct_batch();
-    b->pops = pops;
-    b->n = (uint32_t)pops.size();
-    auto fail = [&](int code_) {
-        batch_free(b);
-        return code_;
-    };
-    auto own = [&](void** q, size_t bytes) -> int {
-        if (hipMalloc(q, std::max<size_t>(bytes, 8)) != hipSuccess) return ct_fail(CT_ENOMEM, "batch: hipMalloc failed");
-        b->owned.push_back(*q);
-        return CT_OK;
-    };
-    auto upload = [&](void* dst, const void* src, size_t bytes) -> int {
-        if (hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
-            return ct_fail(CT_EDEVICE, "batch: descriptor upload failed");
-        return CT_OK;
-    };
+    const uint32_t n = (uint32_t)pops.size();
     std::vector<PopDev> pd;
     std::vector<uint32_t> ind_off{0}, ga_off{0};
     std::vector<RepairSet> setsA, setsC;
-    uint32_t maskA = 0;
+    uint32_t maskA = 0, max_pop = 0;
     for (ct_pop* p : pops) {
         const PopDev& d = p->dev;
         pd.push_back(d);
@@ -129,42 +112,102 @@ int batch_build(const std::vector<ct_pop*>& pops, ct_batch** out, hipStream_t st
             setsC.push_back(m);
             ga_off.push_back(ga_off.back() + d.P);
         }
-        b->max_pop = std::max(b->max_pop, d.P);
+        max_pop = std::max(max_pop, d.P);
     }
+    // a changed group invalidates any captured graph
+    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    if (n > b->cap || !b->d_pops) {
+        for (void* q : b->owned) (void)hipFree(q);
+        b->owned.clear();
+        const uint32_t cap = std::max<uint32_t>(n, 1);
+        void* q = nullptr;
+        auto own = [&](size_t bytes) -> void* {
+            q = nullptr;
+            if (hipMalloc(&q, std::max<size_t>(bytes, 8)) != hipSuccess) return nullptr;
+            b->owned.push_back(q);
+            return q;
+        };
+        b->d_pops = (PopDev*)own(cap * sizeof(PopDev));
+        b->d_ind_off = (uint32_t*)own((cap + 1) * 4);
+        b->d_ga_off = (uint32_t*)own((cap + 1) * 4);
+        b->d_setsA = (RepairSet*)own(cap * sizeof(RepairSet));
+        b->d_setsC = (RepairSet*)own(cap * sizeof(RepairSet));
+        if (!b->d_pops || !b->d_ind_off || !b->d_ga_off || !b->d_setsA || !b->d_setsC) {
+            b->cap = 0;
+            b->d_pops = nullptr;
+            return ct_fail(CT_ENOMEM, "batch: hipMalloc failed");
+        }
+        int rc = repair_plan_alloc(b->passA.plan, cap, b->owned);
+        if (!rc) rc = repair_plan_alloc(b->passC.plan, cap, b->owned);
+        if (rc) {
+            b->cap = 0;
+            b->d_pops = nullptr;
+            return rc;
+        }
+        b->cap = cap;
+    }
+    auto upload = [&](void* dst, const void* src, size_t bytes) -> int {
+        if (bytes && hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+            return ct_fail(CT_EDEVICE, "batch: descriptor upload failed");
+        return CT_OK;
+    };
+    int rc;
+    if ((rc = upload(b->d_pops, pd.data(), pd.size() * sizeof(PopDev))) ||
+        (rc = upload(b->d_ind_off, ind_off.data(), ind_off.size() * 4)) ||
+        (rc = upload(b->d_setsA, setsA.data(), setsA.size() * sizeof(RepairSet))) ||
+        (rc = upload(b->d_setsC, setsC.data(), setsC.size() * sizeof(RepairSet))) ||
+        (rc = upload(b->d_ga_off, ga_off.data(), ga_off.size() * 4)))
+        return rc;
+    b->pops = pops;
+    b->n = n;
     b->total_ind = ind_off.back();
     b->n_ga = (uint32_t)setsC.size();
-    int rc;
-    void* q = nullptr;
-    if ((rc = own(&q, pd.size() * sizeof(PopDev)))) return fail(rc);
-    b->d_pops = (PopDev*)q;
-    if ((rc = own(&q, ind_off.size() * 4))) return fail(rc);
-    b->d_ind_off = (uint32_t*)q;
-    if ((rc = upload(b->d_pops, pd.data(), pd.size() * sizeof(PopDev)))) return fail(rc);
-    if ((rc = upload(b->d_ind_off, ind_off.data(), ind_off.size() * 4))) return fail(rc);
+    b->max_pop = max_pop;
     // main repair pass: every run (its prep items are its individuals)
-    if ((rc = own(&q, setsA.size() * sizeof(RepairSet)))) return fail(rc);
-    if ((rc = upload(q, setsA.data(), setsA.size() * sizeof(RepairSet)))) return fail(rc);
-    b->passA.n_sets = b->n;
-    b->passA.d_sets = (RepairSet*)q;
+    b->passA.n_sets = n;
+    b->passA.d_sets = b->d_setsA;
     b->passA.d_prep_off = b->d_ind_off;
     b->passA.total_n = b->total_ind;
     b->passA.metrics_mask = maskA;
-    if ((rc = repair_plan_alloc(b->passA.plan, b->n, b->owned))) return fail(rc);
     // GA mutation pass
-    if (b->n_ga) {
-        if ((rc = own(&q, setsC.size() * sizeof(RepairSet)))) return fail(rc);
-        if ((rc = upload(q, setsC.data(), setsC.size() * sizeof(RepairSet)))) return fail(rc);
-        b->passC.d_sets = (RepairSet*)q;
-        if ((rc = own(&q, ga_off.size() * 4))) return fail(rc);
-        if ((rc = upload(q, ga_off.data(), ga_off.size() * 4))) return fail(rc);
-        b->passC.d_prep_off = (uint32_t*)q;
-        b->passC.n_sets = b->n_ga;
-        b->passC.total_n = ga_off.back();
-        b->passC.metrics_mask = 1u << CT_HAM1_RANDOM;
-        if ((rc = repair_plan_alloc(b->passC.plan, b->n_ga, b->owned))) return fail(rc);
+    b->passC.n_sets = b->n_ga;
+    b->passC.d_sets = b->d_setsC;
+    b->passC.d_prep_off = b->d_ga_off;
+    b->passC.total_n = ga_off.back();
+    b->passC.metrics_mask = b->n_ga ? 1u << CT_HAM1_RANDOM : 0u;
+    return CT_OK;
+}
+
+int batch_build(const std::vector<ct_pop*>& pops, ct_batch** out, hipStream_t st) {
+    (void)st;
+    *out = nullptr;
+    ct_batch* b = new ct_batch();
+    int rc = batch_fill(b, pops);
+    if (rc) {
+        batch_free(b);
+        return rc;
     }
     *out = b;
     return CT_OK;
+}
+
+uint64_t pop_footprint_bytes(uint32_t algo, uint32_t P, uint32_t D, uint32_t R, uint64_t n_valid) {
+    const uint64_t p = P, pd = (uint64_t)P * D;
+    const uint64_t slots = std::max<uint64_t>(P, kRepairTargetWaves);
+    uint64_t b = 16 + 16 + 16 + 8 + 2 * p * R + 4 * p + p;      // state, tally, rcount, best, trial, out, tpos, apply
+    if (algo == CT_PSO) b += pd * (4 + 8 + 4) + 8 * p;           // X, V, PB, f_pb, pb_pos
+    else b += 8 * p;                                              // pos, f
+    if (algo == CT_DE) b += (n_valid + 31) / 32 * 4 + std::max<uint64_t>(n_valid, 1) * 4;   // member, claim
+    if (algo == CT_GA) b += 8 * p + 4 * p;                        // beta table, sorted
+    b += 4 * p + 8 * p + 4 * p + 8 * p + slots * (8 + 4);         // repair scratch
+    return b;
+}
+
+uint64_t batch_bytes(uint32_t cap) {
+    const uint64_t c = std::max<uint32_t>(cap, 1);
+    const uint64_t plan = ((c + 1) * 6 + c) * 4;
+    return c * sizeof(PopDev) + 2 * (c + 1) * 4 + 2 * c * sizeof(RepairSet) + 2 * plan;
 }
 
 void batch_free(ct_batch* b) {
@@ -176,19 +219,8 @@ void batch_free(ct_batch* b) {
     delete b;
 }
 
-int ct_fail(int code, const std::string& msg) {
-    g_err = msg;
-    return code;
-}
-
-extern "C" {
-
-const char* ct_last_error(void) { return g_err.c_str(); }
-
-int ct_version(void) { return 1; }
-
-int ct_space_build(const int64_t* values, const uint32_t* radices, uint32_t n_params, const uint32_t* code,
-                   const uint32_t* cons_offsets, uint32_t n_cons, void* stream, ct_space** out) {
+int space_prepare(const int64_t* values, const uint32_t* radices, uint32_t n_params, const uint32_t* code,
+                  const uint32_t* cons_offsets, uint32_t n_cons, ct_space** out) {
     if (!values || !radices || !out || (n_cons && (!code || !cons_offsets)))
         return ct_fail(CT_EINVAL, "ct_space_build: null argument");
     *out = nullptr;
@@ -264,27 +296,57 @@ int ct_space_build(const int64_t* values, const uint32_t* radices, uint32_t n_pa
     }
     S.cons_off[n_cons] = (uint32_t)code2.size();
     s->lds_values_bytes = (size_t)n_vals * sizeof(int64_t);
+    s->code = std::move(code2);
+    *out = s;
+    return CT_OK;
+}
 
-    hipStream_t st = as_stream(stream);
-    auto fail = [&](int code_) {
-        ct_space_free(s);
-        return code_;
-    };
+int space_realize(ct_space* s, hipStream_t st, uint64_t byte_limit) {
+    const size_t n_vals = s->values.size();
     if (hipMalloc(&s->d_values, n_vals * sizeof(int64_t)) != hipSuccess ||
-        hipMalloc(&s->d_code, std::max<size_t>(code2.size(), 1) * sizeof(uint32_t)) != hipSuccess)
-        return fail(ct_fail(CT_ENOMEM, "ct_space_build: hipMalloc failed"));
-    if (hipMemcpyAsync(s->d_values, values, n_vals * sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess ||
-        (code2.size() && hipMemcpyAsync(s->d_code, code2.data(), code2.size() * sizeof(uint32_t),
-                                        hipMemcpyHostToDevice, st) != hipSuccess))
-        return fail(ct_fail(CT_EDEVICE, "ct_space_build: upload failed"));
-    S.values = s->d_values;
-    S.code = s->d_code;
-    rc = space_build_device(s, st);
-    if (rc) return fail(rc);
-    if (hipMalloc(&s->d_dev, sizeof(DevSpace)) != hipSuccess)
-        return fail(ct_fail(CT_ENOMEM, "ct_space_build: hipMalloc failed"));
+        hipMalloc(&s->d_code, std::max<size_t>(s->code.size(), 1) * sizeof(uint32_t)) != hipSuccess)
+        return ct_fail(CT_ENOMEM, "ct_space_build: hipMalloc failed");
+    if (hipMemcpyAsync(s->d_values, s->values.data(), n_vals * sizeof(int64_t), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        (s->code.size() && hipMemcpyAsync(s->d_code, s->code.data(), s->code.size() * sizeof(uint32_t),
+                                          hipMemcpyHostToDevice, st) != hipSuccess))
+        return ct_fail(CT_EDEVICE, "ct_space_build: upload failed");
+    s->dev.values = s->d_values;
+    s->dev.code = s->d_code;
+    s->byte_limit = byte_limit;
+    int rc = space_build_device(s, st);
+    if (rc) return rc;
+    if (hipMalloc(&s->d_dev, sizeof(DevSpace)) != hipSuccess) return ct_fail(CT_ENOMEM, "ct_space_build: hipMalloc failed");
     if (hipMemcpy(s->d_dev, &s->dev, sizeof(DevSpace), hipMemcpyHostToDevice) != hipSuccess)
-        return fail(ct_fail(CT_EDEVICE, "ct_space_build: upload failed"));
+        return ct_fail(CT_EDEVICE, "ct_space_build: upload failed");
+    s->dev_bytes = space_resident_bytes(s, s->n_valid);
+    return CT_OK;
+}
+
+
+int ct_fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+extern "C" {
+
+const char* ct_last_error(void) { return g_err.c_str(); }
+
+int ct_version(void) { return 1; }
+
+int ct_space_build(const int64_t* values, const uint32_t* radices, uint32_t n_params, const uint32_t* code,
+                   const uint32_t* cons_offsets, uint32_t n_cons, void* stream, ct_space** out) {
+    if (!out) return ct_fail(CT_EINVAL, "ct_space_build: null argument");
+    *out = nullptr;
+    ct_space* s = nullptr;
+    int rc = space_prepare(values, radices, n_params, code, cons_offsets, n_cons, &s);
+    if (rc) return rc;
+    rc = space_realize(s, as_stream(stream), 0);
+    if (rc) {
+        ct_space_free(s);
+        return rc;
+    }
     *out = s;
     return CT_OK;
 }
@@ -500,7 +562,6 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_ob
         (rc = dalloc(p, &p->r_part_pos, slots)))
         return fail(rc);
     if ((rc = pop_init_device(p, st))) return fail(rc);
-    if ((rc = batch_build(std::vector<ct_pop*>{p}, &p->single, st))) return fail(rc);
     *out = p;
     return CT_OK;
 }
@@ -512,6 +573,11 @@ int ct_step(ct_pop* const* pops, uint32_t n_pops, uint32_t n_generations, uint32
         if (!pops[k]) return ct_fail(CT_EINVAL, "ct_step: null population");
     hipStream_t st = as_stream(stream);
     if (flags == CT_STEP_PLAIN) {
+        for (uint32_t k = 0; k < n_pops; k++)
+            if (!pops[k]->single) {
+                int rc = batch_build(std::vector<ct_pop*>{pops[k]}, &pops[k]->single, st);
+                if (rc) return rc;
+            }
         for (uint32_t g = 0; g < n_generations; g++)
             for (uint32_t k = 0; k < n_pops; k++) {
                 int rc = batch_generation(pops[k]->single, st);
@@ -684,6 +750,18 @@ int ct_pop_restore(ct_pop* p, const void* h_buf, size_t len) {
     }
     CT_HIP(hipMemcpy(d.state, stt, 16, hipMemcpyHostToDevice));
     CT_HIP(hipMemcpy(d.best, &b, 8, hipMemcpyHostToDevice));
+    return CT_OK;
+}
+
+int ct_space_footprint(const ct_space* s, uint64_t* bytes) {
+    if (!s || !bytes) return ct_fail(CT_EINVAL, "ct_space_footprint: null argument");
+    *bytes = s->dev_bytes;
+    return CT_OK;
+}
+
+int ct_pop_footprint(const ct_pop* p, uint64_t* bytes) {
+    if (!p || !bytes) return ct_fail(CT_EINVAL, "ct_pop_footprint: null argument");
+    *bytes = p->dev_bytes + (p->single ? batch_bytes(p->single->cap) : 0);
     return CT_OK;
 }
 

@@ -50,10 +50,21 @@ struct ct_space {
     uint16_t* d_dir8 = nullptr;
     uint8_t* d_boxes = nullptr;
     size_t lds_values_bytes = 0;      // dynamic LDS for the value tables
+    std::vector<uint32_t> code;       // constraint programs, prefix-only ones first
+    uint64_t byte_limit = 0;          // build: fail with CT_ENOMEM (n_valid set) if the space would exceed it
+    bool over_limit = false;          // the last build stopped at byte_limit
+    uint64_t dev_bytes = 0;           // device bytes held once built
 };
+
+// api.cpp: host-side validation and layout, then device build (optionally under a byte limit)
+int space_prepare(const int64_t* values, const uint32_t* radices, uint32_t n_params, const uint32_t* code,
+                  const uint32_t* cons_offsets, uint32_t n_cons, ct_space** out);
+int space_realize(ct_space* s, hipStream_t st, uint64_t byte_limit);
 
 // space.hip
 int space_build_device(ct_space* s, hipStream_t st);
+uint64_t space_resident_bytes(const ct_space* s, uint64_t n_valid);   // device bytes of the built space
+uint64_t space_build_scratch_bytes(const ct_space* s);                // temporaries during the build
 int launch_valid_mask(const ct_space* s, const uint8_t* rows, uint64_t n, uint8_t* out, hipStream_t st);
 int launch_rank(const ct_space* s, const uint8_t* rows, uint64_t n, int64_t* pos, hipStream_t st);
 
@@ -150,6 +161,7 @@ struct ct_pop {
     ct_pop_params prm{};
     PopDev dev{};
     std::vector<void*> allocs;
+    uint64_t dev_bytes = 0;           // device bytes of the run's own buffers
     ct_batch* single = nullptr;       // batch of this run alone (plain stepping)
     // repair scratch of this run
     uint32_t* r_list = nullptr;
@@ -160,12 +172,16 @@ struct ct_pop {
     uint32_t* r_part_pos = nullptr;
 };
 
-// A fixed group of runs stepped together (descriptor arrays and, once captured, a graph).
+// A group of runs stepped together: descriptor arrays in device memory (sized for `cap`
+// runs, refilled in place when the group changes) and, once captured, a graph.
 struct ct_batch {
     std::vector<ct_pop*> pops;
-    uint32_t n = 0;
+    uint32_t n = 0, cap = 0;
     PopDev* d_pops = nullptr;
     uint32_t* d_ind_off = nullptr;    // [n + 1] prefix of population sizes
+    uint32_t* d_ga_off = nullptr;     // [n_ga + 1] prefix of GA population sizes
+    RepairSet* d_setsA = nullptr;
+    RepairSet* d_setsC = nullptr;
     uint32_t total_ind = 0;
     uint32_t n_ga = 0, max_pop = 0;
     RepairPasses passA, passC;        // main repair, GA mutation
@@ -174,10 +190,16 @@ struct ct_batch {
     hipGraphExec_t exec = nullptr;
 };
 
+// Device bytes a run of this shape allocates (its buffers and its one-run batch).
+uint64_t pop_footprint_bytes(uint32_t algo, uint32_t P, uint32_t D, uint32_t R, uint64_t n_valid);
+
 // step.hip
 int pop_init_device(ct_pop* p, hipStream_t st);
 int batch_generation(ct_batch* b, hipStream_t st);
 
 // api.cpp
 int batch_build(const std::vector<ct_pop*>& pops, ct_batch** out, hipStream_t st);
+// refill a batch with another group of runs (reallocating only if it outgrows the capacity);
+// the caller makes sure no launch that reads the old descriptors is still pending
+int batch_fill(ct_batch* b, const std::vector<ct_pop*>& pops);
 void batch_free(ct_batch* b);

@@ -326,6 +326,26 @@ uint32_t grid_for(uint64_t items, uint32_t per_block, uint32_t cap = 0x7FFFFFFFu
 
 }  // namespace
 
+uint64_t space_resident_bytes(const ct_space* s, uint64_t n_valid) {
+    const DevSpace& S = s->dev;
+    const uint64_t n_groups = (S.N + 4095u) / 4096u, n_words_alloc = n_groups * 64u;
+    uint64_t b = n_words_alloc * 8u;                                      // validity bitmask
+    if (S.split != S.D) b += (S.P_s + 4095u) / 4096u * 64u * 8u;          // prefix table
+    const uint64_t nv = n_valid ? n_valid : 1;
+    b += nv * (8u + S.R);                                                  // linear indices + rows
+    b += (uint64_t)S.D * 256u * 2u;                                        // prev/next present values
+    b += n_groups * 8u + (n_words_alloc / 8u) * 2u;                        // rank directory
+    b += std::max<uint64_t>((n_valid + 63u) / 64u, 1) * 2u * S.R;          // 64-row bounding boxes
+    b += s->values.size() * 8u + std::max<size_t>(s->code.size(), 1) * 4u + sizeof(DevSpace);
+    return b;
+}
+
+uint64_t space_build_scratch_bytes(const ct_space* s) {
+    const uint64_t n_groups = (s->dev.N + 4095u) / 4096u;
+    const uint64_t n_tiles = (n_groups + kTileGroups - 1) / kTileGroups;
+    return n_groups * 4u + (2u * n_tiles + 1u) * 8u + (uint64_t)s->dev.D * 32u;
+}
+
 int space_build_device(ct_space* s, hipStream_t st) {
     DevSpace& S = s->dev;
     const uint32_t n_vals = (uint32_t)s->values.size();
@@ -364,6 +384,14 @@ int space_build_device(ct_space* s, hipStream_t st) {
     CT_HIP(hipStreamSynchronize(st));
     s->n_valid = total;
     S.n_valid = total;
+    s->over_limit = s->byte_limit && space_resident_bytes(s, total) > s->byte_limit;
+    if (s->over_limit) {
+        (void)hipFreeAsync(d_counts, st);
+        (void)hipFreeAsync(d_tiles, st);
+        (void)hipFreeAsync(d_off, st);
+        (void)hipStreamSynchronize(st);
+        return ct_fail(CT_ENOMEM, "space build: the resolved space exceeds the byte limit");
+    }
     const uint64_t alloc_n = total ? total : 1;
     CT_HIP(hipMalloc(&s->d_lin, alloc_n * sizeof(uint64_t)));
     CT_HIP(hipMalloc(&s->d_rows, alloc_n * S.R));

@@ -20,7 +20,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_functions():
     src = open(os.path.join(ROOT, "include", "ct.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?(?:int|void|char\s*\*|const char\s*\*)\s*\*?\s*(ct_\w+)\s*\(",
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?(?:int|void|double|char\s*\*|const char\s*\*)\s*\*?\s*(ct_\w+)\s*\(",
                                  src, flags=re.M)))
 
 
@@ -68,3 +68,18 @@ def test_large_constants_and_precedence():
                                                     "not a == 4", "0x10 + a == 19", "True + a == 4"])
     for k in range(5):
         assert eval_compiled(code, offs, k, [3]) == (1, False)
+
+
+def test_server_needs_device_and_objective():
+    """Server creation fails cleanly without an objective callback, and without a HIP device."""
+    import torch
+    from paper_2606_28372_amd import CtError, Server, _lib
+    cfg = _lib.ct_server_config(hbm_budget=1 << 20, max_active=4)
+    h = ctypes.c_void_p()
+    assert _lib.load().ct_server_create(ctypes.byref(cfg), ctypes.byref(h)) == _lib.CT_EINVAL
+    cfg.max_active = 0
+    assert _lib.load().ct_server_create(ctypes.byref(cfg), ctypes.byref(h)) == _lib.CT_EINVAL
+    if not torch.cuda.is_available():
+        with pytest.raises(CtError) as e:
+            Server(lambda rid, nv: None, hbm_budget=1 << 20)
+        assert e.value.code == _lib.CT_EDEVICE
