@@ -248,6 +248,21 @@ int ct_batch_step(ct_batch* b, uint32_t n_generations, uint32_t flags, void* str
 void ct_batch_free(ct_batch* b);
 
 /*
+ * ct_batch_autotune -- advance the batch by exactly one generation, choosing the
+ * work partitioning of its repair scans (candidates x list parts per launch,
+ * least 64-row boxes per part, waves in the grid) by timing the generation's
+ * repair pass under each candidate partitioning; every candidate computes the
+ * same result, so the run's state advances exactly as with ct_batch_step.
+ * The choice is kept for the batch and, process-wide, for later batches of the
+ * same shape (per run: algorithm, row bytes, parameters, log2 |V|, log2 P);
+ * when the shape was tuned before and force is 0 this is a plain generation.
+ * Synchronises the stream.
+ */
+int ct_batch_autotune(ct_batch* b, uint32_t force, void* stream);
+/* The batch's scan partitioning and whether it came from tuning. */
+int ct_batch_tuning(const ct_batch* b, uint32_t* items, uint32_t* min_boxes, uint32_t* grid_waves, uint32_t* tuned);
+
+/*
  * ct_pop_read -- copy a run's state to the host (synchronises its stream).
  * h_pos[pop_size]: population as valid-list positions (PSO: the personal-best
  * configurations); h_f[pop_size]: their objective values.  Any output may be
@@ -372,6 +387,8 @@ void ct_server_free(ct_server* s);
  */
 int ct_prof_enable(int on);
 int ct_prof_read(const char* kernel, double* total_ms, uint64_t* launches);
+/* Record events only around launches of the named kernel (NULL: every kernel). */
+int ct_prof_select(const char* kernel);
 
 #ifdef __cplusplus
 }

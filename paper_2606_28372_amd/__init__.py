@@ -247,6 +247,15 @@ class Batch:
     def step(self, n_generations: int = 1, flags: int = CT_STEP_GRAPH):
         _lib.check(_lib.load().ct_batch_step(self._h, n_generations, flags, _stream()))
 
+    def autotune(self, force: bool = False):
+        """One generation that also picks the repair scans' work partitioning (ct_batch_autotune)."""
+        _lib.check(_lib.load().ct_batch_autotune(self._h, 1 if force else 0, _stream()))
+
+    def tuning(self) -> Dict[str, int]:
+        v = [ctypes.c_uint32() for _ in range(4)]
+        _lib.check(_lib.load().ct_batch_tuning(self._h, *[ctypes.byref(x) for x in v]))
+        return {"items": v[0].value, "min_boxes": v[1].value, "grid_waves": v[2].value, "tuned": bool(v[3].value)}
+
     def close(self):
         if self._h:
             _lib.load().ct_batch_free(self._h)
@@ -367,6 +376,11 @@ class Server:
 def prof_enable(on: bool = True):
     """Kernel timing with HIP events (measurement support)."""
     _lib.check(_lib.load().ct_prof_enable(1 if on else 0))
+
+
+def prof_select(kernel: Optional[str]):
+    """Record events only around the named kernel's launches (None: all kernels)."""
+    _lib.check(_lib.load().ct_prof_select(kernel.encode() if kernel else None))
 
 
 def prof_read(kernel: str):

@@ -81,6 +81,8 @@ SIGNATURES = {
     "ct_batch_create": (_i32, [_P(_vp), _u32, _P(_vp)]),
     "ct_batch_step": (_i32, [_vp, _u32, _u32, _vp]),
     "ct_batch_free": (None, [_vp]),
+    "ct_batch_autotune": (_i32, [_vp, _u32, _vp]),
+    "ct_batch_tuning": (_i32, [_vp, _P(_u32), _P(_u32), _P(_u32), _P(_u32)]),
     "ct_pop_snapshot": (_i32, [_vp, _vp, _P(_sz)]),
     "ct_pop_restore": (_i32, [_vp, _vp, _sz]),
     "ct_pop_free": (None, [_vp]),
@@ -99,6 +101,7 @@ SIGNATURES = {
     "ct_server_free": (None, [_vp]),
     "ct_prof_enable": (_i32, [_i32]),
     "ct_prof_read": (_i32, [ctypes.c_char_p, _P(ctypes.c_double), _P(_u64)]),
+    "ct_prof_select": (_i32, [ctypes.c_char_p]),
 }
 
 _lock = threading.Lock()

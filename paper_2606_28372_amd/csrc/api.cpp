@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -57,6 +59,25 @@ int check_program(const uint32_t* code, uint32_t b, uint32_t e, uint32_t n_param
     return 0;
 }
 
+// Scan partitionings chosen by the autotuner, by group shape (process-wide).
+std::mutex g_tune_mu;
+std::map<std::string, RepairTune> g_tune;
+
+// Shape of a group of runs: per run (algorithm, row bytes, parameters, log2 |V|, log2 P), sorted.
+std::string group_shape(const std::vector<ct_pop*>& pops) {
+    std::vector<std::string> parts;
+    auto lg = [](uint64_t x) { uint32_t k = 0; while (x >>= 1) ++k; return k; };
+    for (const ct_pop* p : pops) {
+        const PopDev& d = p->dev;
+        parts.push_back(std::to_string(d.algo) + "," + std::to_string(d.R) + "," + std::to_string(d.D) + "," +
+                        std::to_string(lg(d.n_valid)) + "," + std::to_string(lg(d.P)));
+    }
+    std::sort(parts.begin(), parts.end());
+    std::string s;
+    for (const std::string& x : parts) s += x + ";";
+    return s;
+}
+
 template <typename T>
 int dalloc(ct_pop* p, T** ptr, size_t n) {
     void* q = nullptr;
@@ -75,7 +96,7 @@ int batch_fill(ct_batch* b, const std::vector<ct_pop*>& pops) {
     std::vector<PopDev> pd;
     std::vector<uint32_t> ind_off{0}, ga_off{0};
     std::vector<RepairSet> setsA, setsC;
-    uint32_t maskA = 0, max_pop = 0;
+    uint32_t maskA = 0, fbA = 0, max_pop = 0, tabA = 0;
     for (ct_pop* p : pops) {
         const PopDev& d = p->dev;
         pd.push_back(d);
@@ -99,9 +120,12 @@ int batch_fill(ct_batch* b, const std::vector<ct_pop*>& pops) {
         r.count = d.rcount;
         r.part_key = p->r_part_key;
         r.part_pos = p->r_part_pos;
+        r.inc = p->r_inc;
         r.tally = d.tally;
         setsA.push_back(r);
-        maskA |= 1u << r.metric;
+        maskA |= 1u << repair_class(r.metric, d.R);
+        if (r.metric == CT_TIER_EUCLID || r.metric == CT_TIER_RANDOM) fbA |= 1u << repair_class(CT_HAMMING, d.R);
+        if (r.metric == CT_TIER_EUCLID) tabA = std::max(tabA, p->space->dev.max_radix * d.D);
         if (d.algo == CT_GA) {
             RepairSet m = r;
             m.metric = CT_HAM1_RANDOM;
@@ -169,13 +193,26 @@ int batch_fill(ct_batch* b, const std::vector<ct_pop*>& pops) {
     b->passA.d_sets = b->d_setsA;
     b->passA.d_prep_off = b->d_ind_off;
     b->passA.total_n = b->total_ind;
-    b->passA.metrics_mask = maskA;
+    b->passA.class_mask = maskA;
+    b->passA.fb_class_mask = fbA;
+    b->passA.euclid_tab = tabA;
     // GA mutation pass
     b->passC.n_sets = b->n_ga;
     b->passC.d_sets = b->d_setsC;
     b->passC.d_prep_off = b->d_ga_off;
     b->passC.total_n = ga_off.back();
-    b->passC.metrics_mask = b->n_ga ? 1u << CT_HAM1_RANDOM : 0u;
+    b->passC.class_mask = 0;
+    for (ct_pop* p : pops)
+        if (p->dev.algo == CT_GA) b->passC.class_mask |= 1u << repair_class(CT_HAM1_RANDOM, p->dev.R);
+    b->passC.fb_class_mask = 0;
+    // a group of a shape tuned before reuses that partitioning
+    b->shape = group_shape(pops);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune.find(b->shape);
+        b->tuned = it != g_tune.end();
+        b->passA.tune = b->tuned ? it->second : RepairTune{};
+    }
     return CT_OK;
 }
 
@@ -200,7 +237,7 @@ uint64_t pop_footprint_bytes(uint32_t algo, uint32_t P, uint32_t D, uint32_t R, 
     else b += 8 * p;                                              // pos, f
     if (algo == CT_DE) b += (n_valid + 31) / 32 * 4 + std::max<uint64_t>(n_valid, 1) * 4;   // member, claim
     if (algo == CT_GA) b += 8 * p + 4 * p;                        // beta table, sorted
-    b += 4 * p + 8 * p + 4 * p + 8 * p + slots * (8 + 4);         // repair scratch
+    b += 4 * p + 8 * p + 4 * p + 8 * p + 8 * p + slots * (8 + 4); // repair scratch
     return b;
 }
 
@@ -428,7 +465,7 @@ int ct_repair(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t met
     hipStream_t st = as_stream(stream);
     // one candidate set: scratch lists, per-part winners, the set itself and its plan
     const uint64_t slots = std::max<uint64_t>(n, kRepairTargetWaves);
-    const size_t bytes = n * (4 + 8 + 4 + 8) + slots * (8 + 4) + 2 * 4 + 2 * 4 + sizeof(RepairSet) + 64;
+    const size_t bytes = n * (4 + 8 + 4 + 8 + 8) + slots * (8 + 4) + 2 * 4 + 2 * 4 + sizeof(RepairSet) + 64;
     uint8_t* buf = nullptr;
     CT_HIP(hipMallocAsync((void**)&buf, bytes, st));
     RepairSet h{};
@@ -452,6 +489,7 @@ int ct_repair(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t met
     h.fb_L = (uint64_t*)take(n * 8);
     h.part_key = (uint64_t*)take(slots * 8);
     h.part_pos = (uint32_t*)take(slots * 4);
+    h.inc = (uint64_t*)take(n * 8);
     h.count = (uint32_t*)take(2 * 4);
     h.tally = nullptr;
     uint32_t* prep_off = (uint32_t*)take(2 * 4);
@@ -467,7 +505,9 @@ int ct_repair(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t met
         rp.d_sets = d_set;
         rp.d_prep_off = prep_off;
         rp.total_n = (uint32_t)n;
-        rp.metrics_mask = 1u << metric;
+        rp.class_mask = 1u << repair_class(metric, s->R);
+        rp.fb_class_mask = (metric == CT_TIER_EUCLID || metric == CT_TIER_RANDOM) ? 1u << repair_class(CT_HAMMING, s->R) : 0u;
+        rp.euclid_tab = s->dev.max_radix * s->D;
         rc = launch_repair_passes(rp, true, st);
     }
     (void)hipFreeAsync(buf, st);
@@ -559,7 +599,7 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_ob
         return fail(ct_fail(CT_EDEVICE, "ct_pop_create: memset failed"));
     if ((rc = dalloc(p, &p->r_list, P)) || (rc = dalloc(p, &p->r_list_L, P)) || (rc = dalloc(p, &p->r_fb, P)) ||
         (rc = dalloc(p, &p->r_fb_L, P)) || (rc = dalloc(p, &p->r_part_key, slots)) ||
-        (rc = dalloc(p, &p->r_part_pos, slots)))
+        (rc = dalloc(p, &p->r_part_pos, slots)) || (rc = dalloc(p, &p->r_inc, P)))
         return fail(rc);
     if ((rc = pop_init_device(p, st))) return fail(rc);
     *out = p;
@@ -637,6 +677,32 @@ int ct_batch_step(ct_batch* b, uint32_t n_generations, uint32_t flags, void* str
         CT_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
     }
     for (uint32_t g = 0; g < n_generations; g++) CT_HIP(hipGraphLaunch(b->exec, st));
+    return CT_OK;
+}
+
+int ct_batch_autotune(ct_batch* b, uint32_t force, void* stream) {
+    if (!b) return ct_fail(CT_EINVAL, "ct_batch_autotune: null batch");
+    hipStream_t st = as_stream(stream);
+    if (b->tuned && !force) return batch_generation(b, st);
+    int rc = batch_autotune_generation(b, st);
+    if (rc) return rc;
+    b->tuned = true;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune[b->shape] = b->passA.tune;
+    }
+    // a captured generation holds the old partitioning
+    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    return CT_OK;
+}
+
+int ct_batch_tuning(const ct_batch* b, uint32_t* items, uint32_t* min_boxes, uint32_t* grid_waves, uint32_t* tuned) {
+    if (!b) return ct_fail(CT_EINVAL, "ct_batch_tuning: null batch");
+    if (items) *items = b->passA.tune.items;
+    if (min_boxes) *min_boxes = b->passA.tune.min_sub;
+    if (grid_waves) *grid_waves = b->passA.tune.grid_waves;
+    if (tuned) *tuned = b->tuned ? 1u : 0u;
     return CT_OK;
 }
 

@@ -93,31 +93,49 @@ struct RepairSet {
     uint32_t* count;                  // [0] list length, [1] fallback length
     uint64_t* part_key;               // per (candidate, part) winners [slots]
     uint32_t* part_pos;
+    uint64_t* inc;                    // per listed candidate: smallest key any of its parts has found [n]
     unsigned long long* tally;        // nullable: += candidates scanned
 };
+
+// Scan kernels are specialised by (metric, row width): class = metric * 4 + log2(R / 4).
+constexpr uint32_t kRepairClasses = 20;
+__host__ __device__ inline uint32_t repair_class(uint32_t metric, uint32_t R) {
+    return metric * 4u + (R <= 4 ? 0u : R <= 8 ? 1u : R <= 16 ? 2u : 3u);
+}
 
 // Device-side plan of one scan pass over a set array (written by k_repair_plan).
 struct RepairPlan {
     uint32_t* cand_off;               // [n_sets + 1] prefix of candidate counts
-    uint32_t* item_off;               // [5][n_sets + 1] prefix of (candidate, part) items per metric
+    uint32_t* item_off;               // [kRepairClasses][n_sets + 1] prefix of (candidate, part) items per class
     uint32_t* parts;                  // [n_sets]
 };
 
 constexpr uint32_t kRepairTargetWaves = 8192;   // scan items per pass (also the per-set slot minimum)
 
+// Work partitioning of the scan launches (chosen by the autotuner; results do not depend on it):
+// items per launch (candidates x parts), least 64-row boxes per part, waves in the grid.
+struct RepairTune {
+    uint32_t items = kRepairTargetWaves;
+    uint32_t min_sub = 32;
+    uint32_t grid_waves = 8192;
+};
+
 // Host helpers to run a repair pass sequence over a device set array.
 struct RepairPasses {
+    RepairTune tune;
     uint32_t n_sets = 0;
     const RepairSet* d_sets = nullptr;
     const uint32_t* d_prep_off = nullptr;   // [n_sets + 1] prefix of n
     uint32_t total_n = 0;
-    uint32_t metrics_mask = 0;              // metrics present among the sets (bit per ct_metric)
+    uint32_t class_mask = 0;                // scan classes of the main pass (bit per repair_class)
+    uint32_t fb_class_mask = 0;             // Hamming classes of the fallback pass of tiered sets (0: none)
+    uint32_t euclid_tab = 0;                // largest max_radix * D over TIER_EUCLID sets (LDS table entries)
     RepairPlan plan{};
 };
 int repair_plan_alloc(RepairPlan& p, uint32_t n_sets, std::vector<void*>& owned);
 // prep + scan + finish (+ Hamming fallback for tiered metrics); `zero_counts` clears the
 // sets' counters with a kernel first (the step sequence clears them in its propose kernel).
-int launch_repair_passes(const RepairPasses& rp, bool zero_counts, hipStream_t st);
+int launch_repair_passes(const RepairPasses& rp, bool zero_counts, hipStream_t st, bool count_tally = true);
 
 // ---------------------------------------------------------------------------
 // Optimiser runs
@@ -170,6 +188,7 @@ struct ct_pop {
     uint64_t* r_fb_L = nullptr;
     uint64_t* r_part_key = nullptr;
     uint32_t* r_part_pos = nullptr;
+    uint64_t* r_inc = nullptr;
 };
 
 // A group of runs stepped together: descriptor arrays in device memory (sized for `cap`
@@ -188,6 +207,8 @@ struct ct_batch {
     std::vector<void*> owned;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::string shape;                // signature of the group for the tuning cache
+    bool tuned = false;
 };
 
 // Device bytes a run of this shape allocates (its buffers and its one-run batch).
@@ -196,6 +217,8 @@ uint64_t pop_footprint_bytes(uint32_t algo, uint32_t P, uint32_t D, uint32_t R, 
 // step.hip
 int pop_init_device(ct_pop* p, hipStream_t st);
 int batch_generation(ct_batch* b, hipStream_t st);
+// one generation in which the main repair pass is timed under each candidate partitioning
+int batch_autotune_generation(ct_batch* b, hipStream_t st);
 
 // api.cpp
 int batch_build(const std::vector<ct_pop*>& pops, ct_batch** out, hipStream_t st);

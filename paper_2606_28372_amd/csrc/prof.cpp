@@ -17,6 +17,7 @@ struct Rec {
 std::mutex g_mu;
 bool g_on = false;
 bool g_suspend = false;
+std::string g_only;                 // empty: every kernel
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 
@@ -34,7 +35,7 @@ hipEvent_t take() {
 
 ProfScope::ProfScope(const char* name, hipStream_t st) : name_(name), st_(st), a_(nullptr) {
     std::lock_guard<std::mutex> g(g_mu);
-    if (!g_on || g_suspend) return;
+    if (!g_on || g_suspend || (!g_only.empty() && g_only != name_)) return;
     a_ = take();
     (void)hipEventRecord((hipEvent_t)a_, st_);
 }
@@ -61,6 +62,12 @@ extern "C" int ct_prof_enable(int on) {
     }
     g_recs.clear();
     g_on = on != 0;
+    return CT_OK;
+}
+
+extern "C" int ct_prof_select(const char* kernel) {
+    std::lock_guard<std::mutex> g(g_mu);
+    g_only = kernel ? kernel : "";
     return CT_OK;
 }
 

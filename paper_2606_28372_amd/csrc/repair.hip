@@ -36,13 +36,11 @@
 namespace {
 
 constexpr int kBlock = 256;
-constexpr uint32_t kTargetWaves = kRepairTargetWaves;
-constexpr uint32_t kMinSubPerPart = 32;   // 64-row blocks per part, at least
 constexpr uint64_t kNoKey = ~0ull;
 constexpr uint32_t kNoPos = 0xFFFFFFFFu;
 constexpr uint64_t kTier3 = 3ull << 62;
 constexpr uint32_t kMaxSets = 4096;
-constexpr uint32_t kNumMetrics = 5;
+constexpr uint32_t kNumClasses = kRepairClasses;
 
 __device__ __forceinline__ uint32_t ne_bytes(uint32_t x) {
     // 0x80 in every byte of x that is non-zero
@@ -82,11 +80,16 @@ struct Cand {
     uint32_t c[RW];
     uint32_t pv[RW], nx[RW];     // nearest present value index below / above each digit
     bool adj_is_sa;
-    int32_t X[RW * 4];           // particle position (TIER_EUCLID)
+    // TIER_EUCLID: squared distance of the particle to each value centre, T[v * D + j] =
+    // (X_j - (v * 2^16 + 2^15))^2 in this wave's LDS slice, and the value index s_j whose centre
+    // is nearest to X_j (the squared distance is convex in v, so over a box's range [a, b] its
+    // minimum is at clamp(s_j, a, b))
+    const uint64_t* tab;
+    uint32_t s[RW];
     uint32_t who, gen;
     uint64_t seed;
 
-    __device__ void load(const RepairSet& J, const DevSpace& S, uint32_t ci) {
+    __device__ void load(const RepairSet& J, const DevSpace& S, uint32_t ci, uint64_t* lds_tab) {
         const uint32_t* cr = reinterpret_cast<const uint32_t*>(J.rows + (uint64_t)ci * S.R);
 #pragma unroll
         for (int k = 0; k < RW; ++k) {
@@ -115,9 +118,27 @@ struct Cand {
             }
         }
         if constexpr (M == CT_TIER_EUCLID) {
+            const int32_t* xp = J.pos_q16 + (uint64_t)ci * S.D;
+            const uint32_t n_tab = S.max_radix * S.D;
+            for (uint32_t e = wave_lane(); e < n_tab; e += 64) {
+                const uint32_t v = e / S.D, j = e - v * S.D;
+                const int64_t d = (int64_t)xp[j] - (int64_t)((v << 16) + 32768u);
+                lds_tab[e] = (uint64_t)(d * d);
+            }
 #pragma unroll
-            for (int j = 0; j < RW * 4; ++j)
-                X[j] = (uint32_t)j < S.D ? (int32_t)uni((uint32_t)J.pos_q16[(uint64_t)ci * S.D + j]) : 0;
+            for (int k = 0; k < RW; ++k) s[k] = 0;
+#pragma unroll
+            for (int j = 0; j < RW * 4; ++j) {
+                if ((uint32_t)j < S.D) {
+                    const int32_t x = (int32_t)uni((uint32_t)xp[j]);
+                    const int32_t hi = (int32_t)S.radix[j] - 1;
+                    const int32_t sj = min(max(x >> 16, 0), hi);
+                    s[j >> 2] |= (uint32_t)sj << ((j & 3) * 8);
+                }
+            }
+            tab = lds_tab;
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         }
         if constexpr (M == CT_TIER_RANDOM || M == CT_HAM1_RANDOM) {
             who = uni(J.who ? J.who[ci] : ci);
@@ -172,11 +193,8 @@ struct Cand {
                 if constexpr (M == CT_TIER_EUCLID) {
                     uint64_t d2 = 0;
 #pragma unroll
-                    for (int j = 0; j < RW * 4; ++j) {
-                        const int32_t cen = (int32_t)((((v[j >> 2] >> ((j & 3) * 8)) & 0xFFu) << 16) + 32768u);
-                        const int64_t d = (int64_t)(X[j] - cen);
-                        d2 += (uint64_t)(d * d);   // padding digits add the same constant to every row
-                    }
+                    for (int j = 0; j < RW * 4; ++j)
+                        if ((uint32_t)j < S.D) d2 += tab[((v[j >> 2] >> ((j & 3) * 8)) & 0xFFu) * S.D + (uint32_t)j];
                     return ((uint64_t)tier << 62) | d2;
                 } else {
                     const uint64_t L = S.lin[pos];
@@ -189,7 +207,7 @@ struct Cand {
     }
 
     // lower bound of key() over every row inside the box [lo, hi]
-    __device__ __forceinline__ uint64_t bound_box(const uint32_t* lo32, const uint32_t* hi32) const {
+    __device__ __forceinline__ uint64_t bound_box(const uint32_t* lo32, const uint32_t* hi32, uint32_t D) const {
         uint32_t miss = 0, sum = 0, far = 0;
         bool adj_ok = true;
         uint64_t e2 = 0;
@@ -213,11 +231,12 @@ struct Cand {
                     }
                 }
                 if constexpr (M == CT_TIER_EUCLID) {
-                    // distance from the particle to the nearest value centre inside [a, b]
-                    const int32_t x = X[k * 4 + q];
-                    const int32_t ca = (a << 16) + 32768, cb = (b << 16) + 32768;
-                    const int64_t t = (int64_t)max(max(ca - x, x - cb), 0);
-                    e2 += (uint64_t)(t * t);
+                    // squared distance from the particle to the nearest value centre inside [a, b]
+                    const uint32_t j = (uint32_t)(k * 4 + q);
+                    if (j < D) {
+                        const int32_t sj = (int32_t)((s[k] >> (q * 8)) & 0xFFu);
+                        e2 += tab[(uint32_t)min(max(sj, a), b) * D + j];
+                    }
                 }
             }
         }
@@ -234,83 +253,213 @@ struct Cand {
     }
 };
 
-// One (candidate, part) item.  For the tiered metrics the bound starts at tier 3, so only
-// neighbours of tiers 0-2 are wanted; the Hamming fallback pass handles the rest.
+// lexicographic (key, position) minimum over the wave; every lane gets the result
+__device__ __forceinline__ void wave_lexmin(uint64_t& k, uint32_t& p) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t klo = __shfl_xor((uint32_t)k, o, 64), khi = __shfl_xor((uint32_t)(k >> 32), o, 64);
+        const uint32_t pq = __shfl_xor(p, o, 64);
+        const uint64_t kq = ((uint64_t)khi << 32) | klo;
+        if (kq < k || (kq == k && pq < p)) { k = kq; p = pq; }
+    }
+    k = ((uint64_t)uni((uint32_t)(k >> 32)) << 32) | uni((uint32_t)k);
+    p = uni(p);
+}
+
+// the builtin returns a signed int: both halves go through uint32_t so the low half does not sign-extend
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t l) {
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)l);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, (int)l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Bitonic sort of (key, index) pairs across the 64 lanes, ascending; lane t ends with the t-th.
+__device__ __forceinline__ void wave_sort(uint64_t& key, uint32_t& idx) {
+    const uint32_t lane = wave_lane();
+#pragma unroll
+    for (uint32_t k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t klo = __shfl_xor((uint32_t)key, (int)j, 64), khi = __shfl_xor((uint32_t)(key >> 32), (int)j, 64);
+            const uint32_t oi = __shfl_xor(idx, (int)j, 64);
+            const uint64_t ok = ((uint64_t)khi << 32) | klo;
+            const bool other_less = ok < key || (ok == key && oi < idx);
+            const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+            if (keep_min == other_less) { key = ok; idx = oi; }
+        }
+    }
+}
+
+// One (candidate, part) item: the lexicographic (key, position) minimum over the seed rows and
+// the rows of the part's boxes that cannot be ruled out.
+//   - (bk, bp) is the best row this item has seen; the candidate's shared incumbent holds the
+//     smallest key any of its parts has found so far (atomic minimum, read again before every
+//     box), so parts prune with each other's finds;
+//   - a box can still win if its lower bound lb is below the best known key, or equal to this
+//     item's own best key while the box starts before that row (the shared key carries no
+//     position, so a box whose bound merely equals it stays open);
+//   - each run of 64 boxes is sorted by (lb, box) across the wave and opened in that order, so
+//     the bound tightens as early as possible and the first box that cannot win ends the run;
+//     the rows of the next box in that order load while the current box is evaluated.
+// Tiered metrics only accept tiers 0-2 here; the Hamming fallback pass handles the rest.
 template <int M, int RW>
 __device__ void scan_item(const RepairSet& J, const DevSpace& S, const uint32_t* list, const uint64_t* list_L,
-                          uint32_t li, uint32_t part, uint32_t parts) {
+                          uint32_t li, uint32_t part, uint32_t parts, uint64_t* lds_tab) {
     const uint32_t lane = wave_lane();
     const uint32_t ci = uni(list[li]);
     Cand<M, RW> C;
-    C.load(J, S, ci);
+    C.load(J, S, ci, lds_tab);
     const uint32_t* rows32 = reinterpret_cast<const uint32_t*>(S.rows);
+    uint64_t* inc = J.inc + li;
 
     constexpr bool tiered = (M == CT_TIER_EUCLID || M == CT_TIER_RANDOM);
-    uint64_t bk = tiered ? kTier3 : kNoKey;        // wave-uniform exclusive bound: keys below it are wanted
+    constexpr uint64_t cap = tiered ? kTier3 : kNoKey;     // keys at or above cap are not wanted
+    uint64_t bk = kNoKey;
+    uint32_t bp = kNoPos;
     const uint64_t L = ((uint64_t)uni((uint32_t)(list_L[li] >> 32)) << 32) | uni((uint32_t)list_L[li]);
     if (L != ~0ull) {
-        // seed the bound from the 64 valid rows around the candidate's place in linear-index order
+        // seed with the 64 valid rows around the candidate's place in linear-index order
         const uint64_t ins = rank_dir(S, L);
         const int64_t q = (int64_t)ins - 32 + (int64_t)lane;
         uint64_t k = kNoKey;
+        uint32_t p = kNoPos;
         if (q >= 0 && (uint64_t)q < S.n_valid) {
             uint32_t v[RW];
 #pragma unroll
             for (int w = 0; w < RW; ++w) v[w] = rows32[(uint64_t)q * RW + w];
-            k = C.key(S, v, (uint64_t)q, bk);
+            k = C.key(S, v, (uint64_t)q, cap);
+            if (k >= cap) k = kNoKey;
+            else p = (uint32_t)q;
         }
-        k = wave_min_u64(k);
-        if (k != kNoKey && k + 1 < bk) bk = k + 1;
+        wave_lexmin(k, p);
+        bk = k;
+        bp = p;
+        if (bk != kNoKey && lane == 0) atomicMin((unsigned long long*)inc, (unsigned long long)bk);
     }
+    auto read_inc = [&]() -> uint64_t {
+        const uint64_t g = __hip_atomic_load(inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return ((uint64_t)uni((uint32_t)(g >> 32)) << 32) | uni((uint32_t)g);
+    };
+    uint64_t g = read_inc();
+    auto can_win = [&](uint64_t lb, uint64_t box) {
+        const uint64_t ub = min(min(bk, g), cap - 1);
+        return lb < ub || (lb == ub && !(ub == bk && box * 64u > bp));
+    };
 
-    uint64_t mk = bk;                               // this lane's best key (exclusive until a row is found)
-    uint32_t mp = kNoPos;
     const uint64_t b0 = (uint64_t)part * S.n_sub / parts, b1 = (uint64_t)(part + 1) * S.n_sub / parts;
     const uint32_t* box32 = reinterpret_cast<const uint32_t*>(S.boxes);
-    for (uint64_t cb = b0; cb < b1; cb += 64) {
-        // lanes over 64 boxes: which ones can hold a row below the bound?
+    uint32_t nlo[RW], nhi[RW], nv[RW];
+    auto fetch_boxes = [&](uint64_t cb) {
         const uint64_t b = cb + lane;
-        uint64_t lb = kNoKey;
-        if (b < b1) {
-            uint32_t lo[RW], hi[RW];
 #pragma unroll
-            for (int w = 0; w < RW; ++w) {
-                lo[w] = box32[b * 2u * RW + w];
-                hi[w] = box32[b * 2u * RW + RW + w];
-            }
-            lb = C.bound_box(lo, hi);
+        for (int w = 0; w < RW; ++w) {
+            nlo[w] = b < b1 ? box32[b * 2u * RW + w] : 0u;
+            nhi[w] = b < b1 ? box32[b * 2u * RW + RW + w] : 0u;
         }
-        uint64_t m = __ballot(lb < bk);
-        while (m) {
-            const uint32_t t = (uint32_t)__ffsll((long long)m) - 1u;
-            m &= m - 1ull;
-            // lanes over the 64 rows of box cb + t
-            const uint64_t r = (cb + t) * 64u + lane;
+    };
+    auto fetch_rows = [&](uint64_t box) {
+        const uint64_t r = box * 64u + lane;
+#pragma unroll
+        for (int w = 0; w < RW; ++w) nv[w] = r < S.n_valid ? rows32[r * RW + w] : 0u;
+    };
+    if (b0 < b1) fetch_boxes(b0);
+    for (uint64_t cb = b0; cb < b1; cb += 64) {
+        uint32_t lo[RW], hi[RW];
+#pragma unroll
+        for (int w = 0; w < RW; ++w) { lo[w] = nlo[w]; hi[w] = nhi[w]; }
+        if (cb + 64 < b1) fetch_boxes(cb + 64);    // the next 64 boxes load while these are examined
+        uint64_t slb = cb + lane < b1 ? C.bound_box(lo, hi, S.D) : kNoKey;
+        uint32_t sidx = lane;
+        wave_sort(slb, sidx);
+        g = min(g, read_inc());
+        uint64_t lbt = readlane64(slb, 0);
+        uint64_t bt = cb + (uint32_t)__builtin_amdgcn_readlane((int)sidx, 0);
+        if (!can_win(lbt, bt)) continue;
+        fetch_rows(bt);
+        for (uint32_t t = 0;;) {
+            uint32_t v[RW];
+#pragma unroll
+            for (int w = 0; w < RW; ++w) v[w] = nv[w];
+            const uint64_t cur = bt;
+            // the next box in bound order, fetched now if it can still win
+            bool more = false;
+            if (t + 1 < 64) {
+                lbt = readlane64(slb, t + 1);
+                bt = cb + (uint32_t)__builtin_amdgcn_readlane((int)sidx, (int)(t + 1));
+                more = can_win(lbt, bt);
+                if (more) fetch_rows(bt);
+            }
+            const uint64_t gn = __hip_atomic_load(inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // lanes over the 64 rows of the current box
+            const uint64_t r = cur * 64u + lane;
+            const uint64_t ub = min(min(bk, g), cap - 1);
+            uint64_t k = kNoKey;
+            uint32_t p = kNoPos;
             if (r < S.n_valid) {
-                uint32_t v[RW];
-#pragma unroll
-                for (int w = 0; w < RW; ++w) v[w] = rows32[r * RW + w];
-                const uint64_t k = C.key(S, v, r, mk < bk ? mk : bk);
-                if (k < mk) { mk = k; mp = (uint32_t)r; }
+                k = C.key(S, v, r, ub + 1);
+                if (k > ub) k = kNoKey;
+                else p = (uint32_t)r;
             }
-            const uint64_t wm = wave_min_u64(mk);
-            bk = wm < bk ? wm : bk;
-            if (m) m &= __ballot(lb < bk);          // drop boxes the tighter bound now rules out
+            if (__ballot(k < bk || (k == bk && p < bp))) {
+                wave_lexmin(k, p);
+                if (k < bk && lane == 0) atomicMin((unsigned long long*)inc, (unsigned long long)k);
+                bk = k;
+                bp = p;
+            }
+            g = min(g, ((uint64_t)uni((uint32_t)(gn >> 32)) << 32) | uni((uint32_t)gn));
+            if (!more || !can_win(lbt, bt)) break;
+            ++t;
         }
-    }
-    // lexicographic (key, position) minimum over the wave
-    uint64_t k2 = mp == kNoPos ? kNoKey : mk;
-    uint32_t p2 = mp;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const uint32_t klo = __shfl_xor((uint32_t)k2, o, 64), khi = __shfl_xor((uint32_t)(k2 >> 32), o, 64);
-        const uint32_t pq = __shfl_xor(p2, o, 64);
-        const uint64_t kq = ((uint64_t)khi << 32) | klo;
-        if (kq < k2 || (kq == k2 && pq < p2)) { k2 = kq; p2 = pq; }
     }
     if (lane == 0) {
-        J.part_key[(uint64_t)li * parts + part] = k2;
-        J.part_pos[(uint64_t)li * parts + part] = p2;
+        J.part_key[(uint64_t)li * parts + part] = bk;
+        J.part_pos[(uint64_t)li * parts + part] = bp;
+    }
+}
+
+// HAM1_RANDOM by enumeration: the Hamming-1 neighbours of c are the configurations that change
+// one parameter to another of its values; each is looked up in the validity bitmask and the
+// valid ones compete with their Philox key, ties to the lowest linear index (the same minimum
+// as a scan of the valid list).  One wave per candidate; lanes over (parameter, value) pairs.
+__device__ void ham1_item(const RepairSet& J, const DevSpace& S, uint32_t li) {
+    const uint32_t lane = wave_lane();
+    const uint32_t ci = uni(J.list[li]);
+    const uint8_t* cr = J.rows + (uint64_t)ci * S.R;
+    // linear index over the in-domain digits, and the digits outside their domain
+    uint64_t Lp = 0;
+    uint32_t bad = 0, bad_j = 0;
+    for (uint32_t j = 0; j < S.D; ++j) {
+        const uint32_t d = cr[j];
+        if (d < S.radix[j]) Lp += (uint64_t)d * S.stride[j];
+        else { ++bad; bad_j = j; }
+    }
+    const uint32_t who = J.who ? J.who[ci] : ci;
+    const uint32_t gen = J.gen ? *J.gen : J.gen_value;
+    uint64_t bkey = kNoKey, bL = ~0ull;
+    const uint32_t n_pairs = S.val_off[S.D - 1] + S.radix[S.D - 1];
+    if (bad <= 1) {
+        for (uint32_t e = lane; e < n_pairs; e += 64) {
+            uint32_t j = 0;
+            while (j + 1 < S.D && S.val_off[j + 1] <= e) ++j;
+            const uint32_t v = e - S.val_off[j];
+            const uint32_t d = cr[j];
+            if (v == d || (bad == 1 && j != bad_j)) continue;
+            const uint64_t Lq = (d < S.radix[j] ? Lp - (uint64_t)d * S.stride[j] : Lp) + (uint64_t)v * S.stride[j];
+            if (!bit_valid(S, Lq)) continue;
+            const U4 o = ct_philox(J.seed, who, gen, (PUR_MUT_KEY << 24) | (uint32_t)((Lq >> 32) & 0xFFFFFFu), (uint32_t)Lq);
+            if (o.x < bkey || (o.x == bkey && Lq < bL)) { bkey = o.x; bL = Lq; }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t klo = __shfl_xor((uint32_t)bkey, o, 64), khi = __shfl_xor((uint32_t)(bkey >> 32), o, 64);
+        const uint32_t llo = __shfl_xor((uint32_t)bL, o, 64), lhi = __shfl_xor((uint32_t)(bL >> 32), o, 64);
+        const uint64_t kq = ((uint64_t)khi << 32) | klo, lq = ((uint64_t)lhi << 32) | llo;
+        if (kq < bkey || (kq == bkey && lq < bL)) { bkey = kq; bL = lq; }
+    }
+    if (lane == 0) {
+        J.part_key[li] = bkey;
+        J.part_pos[li] = bkey == kNoKey ? kNoPos : (uint32_t)rank_dir(S, bL);
     }
 }
 
@@ -346,6 +495,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_prep(const RepairSet* __restr
             const uint32_t k = atomicAdd(&J.count[0], 1u);
             J.list[k] = i;
             J.list_L[k] = L;
+            J.inc[k] = kNoKey;
         }
     }
 }
@@ -369,70 +519,96 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 // One wave: per-set candidate counts -> parts and item offsets of one scan pass.  Lane l owns
 // a contiguous slice of the sets; offsets are the wave prefix of the lanes' totals plus the
 // running sum inside the slice.  which = 0: main lists with each set's metric; which = 1:
-// fallback lists, Hamming.
+// fallback lists, Hamming.  Each scan class is its own launch, so its candidates are split
+// into parts to give that launch about target_items items, each part min_sub boxes or more.
 __global__ __launch_bounds__(64) void k_repair_plan(const RepairSet* __restrict__ sets, uint32_t n_sets,
-                                                    uint32_t which, RepairPlan plan) {
+                                                    uint32_t which, RepairPlan plan, uint32_t class_mask,
+                                                    uint32_t target_items, uint32_t min_sub) {
     const uint32_t lane = threadIdx.x;
     const uint32_t chunk = (n_sets + 63u) / 64u;
     const uint32_t s0 = min(n_sets, lane * chunk), s1 = min(n_sets, s0 + chunk);
-    uint32_t local = 0;
-    for (uint32_t s = s0; s < s1; ++s) local += sets[s].count[which];
-    const uint32_t total = wave_sum_u32(local);
-    uint64_t gp = total ? kTargetWaves / total : 1;
-    if (gp < 1) gp = 1;
-    uint32_t tc = 0, ti[kNumMetrics] = {0, 0, 0, 0, 0};
+    uint32_t acc[kNumClasses];
+#pragma unroll
+    for (uint32_t q = 0; q < kNumClasses; ++q) acc[q] = 0;
     for (uint32_t s = s0; s < s1; ++s) {
-        const uint64_t pmax = sets[s].S->n_sub / kMinSubPerPart;
+        const uint32_t cls = repair_class(which ? (uint32_t)CT_HAMMING : sets[s].metric, sets[s].S->R);
+        const uint32_t c = sets[s].count[which];
+#pragma unroll
+        for (uint32_t q = 0; q < kNumClasses; ++q) acc[q] += q == cls ? c : 0u;
+    }
+    uint32_t gpc[kNumClasses];
+#pragma unroll
+    for (uint32_t q = 0; q < kNumClasses; ++q) {
+        gpc[q] = 1u;
+        if (class_mask & (1u << q)) {
+            const uint32_t total = wave_sum_u32(acc[q]);
+            gpc[q] = total ? max(target_items / total, 1u) : 1u;
+        }
+    }
+    uint32_t tc = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < kNumClasses; ++q) acc[q] = 0;
+    for (uint32_t s = s0; s < s1; ++s) {
+        const uint64_t pmax = sets[s].S->n_sub / min_sub;
+        const uint32_t cls = repair_class(which ? (uint32_t)CT_HAMMING : sets[s].metric, sets[s].S->R);
+        uint32_t gp = gpc[0];
+#pragma unroll
+        for (uint32_t q = 1; q < kNumClasses; ++q) gp = q == cls ? gpc[q] : gp;
         uint64_t p = gp > pmax ? pmax : gp;
-        if (p < 1) p = 1;
+        if (p < 1 || cls / 4u == (uint32_t)CT_HAM1_RANDOM) p = 1;   // enumerated, not scanned
         plan.parts[s] = (uint32_t)p;
         const uint32_t c = sets[s].count[which];
-        const uint32_t m = which ? (uint32_t)CT_HAMMING : sets[s].metric;
         tc += c;
 #pragma unroll
-        for (uint32_t q = 0; q < kNumMetrics; ++q) ti[q] += q == m ? c * (uint32_t)p : 0u;
+        for (uint32_t q = 0; q < kNumClasses; ++q) acc[q] += q == cls ? c * (uint32_t)p : 0u;
     }
-    uint32_t oc = wave_excl_scan(tc, lane), oi[kNumMetrics];
+    uint32_t oc = wave_excl_scan(tc, lane);
 #pragma unroll
-    for (uint32_t q = 0; q < kNumMetrics; ++q) oi[q] = wave_excl_scan(ti[q], lane);
+    for (uint32_t q = 0; q < kNumClasses; ++q)
+        if (class_mask & (1u << q)) acc[q] = wave_excl_scan(acc[q], lane);
     for (uint32_t s = s0; s < s1; ++s) {
         const uint32_t p = plan.parts[s];
         const uint32_t c = sets[s].count[which];
-        const uint32_t m = which ? (uint32_t)CT_HAMMING : sets[s].metric;
+        const uint32_t cls = repair_class(which ? (uint32_t)CT_HAMMING : sets[s].metric, sets[s].S->R);
         plan.cand_off[s] = oc;
 #pragma unroll
-        for (uint32_t q = 0; q < kNumMetrics; ++q) plan.item_off[q * (n_sets + 1) + s] = oi[q];
+        for (uint32_t q = 0; q < kNumClasses; ++q)
+            if (class_mask & (1u << q)) plan.item_off[q * (n_sets + 1) + s] = acc[q];
         oc += c;
 #pragma unroll
-        for (uint32_t q = 0; q < kNumMetrics; ++q) oi[q] += q == m ? c * p : 0u;
+        for (uint32_t q = 0; q < kNumClasses; ++q) acc[q] += q == cls ? c * p : 0u;
     }
     if (lane == 63) {
         plan.cand_off[n_sets] = oc;
 #pragma unroll
-        for (uint32_t q = 0; q < kNumMetrics; ++q) plan.item_off[q * (n_sets + 1) + n_sets] = oi[q];
+        for (uint32_t q = 0; q < kNumClasses; ++q)
+            if (class_mask & (1u << q)) plan.item_off[q * (n_sets + 1) + n_sets] = acc[q];
     }
 }
 
-template <int M>
+template <int M, int RW>
 __global__ __launch_bounds__(kBlock) void k_repair_scan(const RepairSet* __restrict__ sets, uint32_t n_sets,
-                                                        RepairPlan plan, uint32_t which) {
-    const uint32_t* off = plan.item_off + M * (n_sets + 1);
+                                                        RepairPlan plan, uint32_t which, uint32_t tab_stride) {
+    constexpr uint32_t cls = (uint32_t)M * 4u + (RW == 1 ? 0u : RW == 2 ? 1u : RW == 4 ? 2u : 3u);
+    extern __shared__ uint64_t lds_tabs[];
+    const uint32_t wpb = blockDim.x / 64;
+    uint64_t* lds_tab = lds_tabs + (threadIdx.x >> 6) * tab_stride;
+    const uint32_t* off = plan.item_off + cls * (n_sets + 1);
     const uint32_t total = off[n_sets];
-    const uint32_t waves = gridDim.x * (kBlock / 64);
-    for (uint32_t item = uni(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)); item < total; item += waves) {
+    const uint32_t waves = gridDim.x * wpb;
+    for (uint32_t item = uni(blockIdx.x * wpb + (threadIdx.x >> 6)); item < total; item += waves) {
         const uint32_t s = uni(find_set(off, n_sets, item));
         const RepairSet& J = sets[s];
         const DevSpace& S = *J.S;
         const uint32_t parts = uni(plan.parts[s]);
         const uint32_t local = item - off[s];
         const uint32_t li = local / parts, part = local % parts;
-        const uint32_t* list = which ? J.fb_list : J.list;
-        const uint64_t* list_L = which ? J.fb_L : J.list_L;
-        switch (uni(S.R)) {
-        case 4: scan_item<M, 1>(J, S, list, list_L, li, part, parts); break;
-        case 8: scan_item<M, 2>(J, S, list, list_L, li, part, parts); break;
-        case 16: scan_item<M, 4>(J, S, list, list_L, li, part, parts); break;
-        default: scan_item<M, 8>(J, S, list, list_L, li, part, parts); break;
+        if constexpr (M == CT_HAM1_RANDOM) {
+            ham1_item(J, S, li);
+        } else {
+            const uint32_t* list = which ? J.fb_list : J.list;
+            const uint64_t* list_L = which ? J.fb_L : J.list_L;
+            scan_item<M, RW>(J, S, list, list_L, li, part, parts, lds_tab);
         }
     }
 }
@@ -440,7 +616,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_scan(const RepairSet* __restr
 // Reduce the parts of every candidate (one wave per candidate) and write the result.  In the main
 // pass of a tiered set, candidates without a tier 0-2 neighbour go to the fallback list.
 __global__ __launch_bounds__(kBlock) void k_repair_finish(const RepairSet* __restrict__ sets, uint32_t n_sets,
-                                                          RepairPlan plan, uint32_t which) {
+                                                          RepairPlan plan, uint32_t which, uint32_t count_tally) {
     const uint32_t total = plan.cand_off[n_sets];
     const uint32_t lane = wave_lane();
     const uint32_t waves = gridDim.x * (kBlock / 64);
@@ -450,7 +626,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_finish(const RepairSet* __res
         const DevSpace& S = *J.S;
         const uint32_t parts = plan.parts[s];
         const uint32_t li = item - plan.cand_off[s];
-        if (which == 0 && li == 0 && lane == 0 && J.tally)
+        if (which == 0 && count_tally && li == 0 && lane == 0 && J.tally)
             atomicAdd(J.tally, (unsigned long long)(plan.cand_off[s + 1] - plan.cand_off[s]));
         uint64_t bk = kNoKey;
         uint32_t bp = kNoPos;
@@ -476,15 +652,29 @@ __global__ __launch_bounds__(kBlock) void k_repair_finish(const RepairSet* __res
             const uint32_t k = atomicAdd(&J.count[1], 1u);
             J.fb_list[k] = ci;
             J.fb_L[k] = ~0ull;           // no seed: the fallback scans the whole list
+            J.inc[k] = kNoKey;           // the main pass is over: the incumbents are free again
         }
     }
 }
 
-template <int M>
-void launch_scan(const RepairPasses& rp, uint32_t which, hipStream_t st) {
+template <int M, int RW>
+void launch_scan_rw(const RepairPasses& rp, uint32_t which, hipStream_t st) {
     ProfScope ps_("k_repair_scan", st);
-    hipLaunchKernelGGL((k_repair_scan<M>), dim3(kTargetWaves / (kBlock / 64)), dim3(kBlock), 0, st, rp.d_sets,
-                       rp.n_sets, rp.plan, which);
+    // TIER_EUCLID keeps one distance table per wave in LDS (at most 64 KiB per block)
+    const uint32_t stride = M == CT_TIER_EUCLID ? std::max<uint32_t>(rp.euclid_tab, 1) : 0;
+    uint32_t wpb = kBlock / 64;
+    while (wpb > 1 && (size_t)wpb * stride * 8 > 65536) wpb >>= 1;
+    hipLaunchKernelGGL((k_repair_scan<M, RW>), dim3(std::max<uint32_t>(rp.tune.grid_waves / wpb, 1)), dim3(wpb * 64),
+                       (size_t)wpb * stride * 8, st,
+                       rp.d_sets, rp.n_sets, rp.plan, which, stride);
+}
+
+template <int M>
+void launch_scan(const RepairPasses& rp, uint32_t mask, uint32_t which, hipStream_t st) {
+    if (mask & (1u << (M * 4 + 0))) launch_scan_rw<M, 1>(rp, which, st);
+    if (mask & (1u << (M * 4 + 1))) launch_scan_rw<M, 2>(rp, which, st);
+    if (mask & (1u << (M * 4 + 2))) launch_scan_rw<M, 4>(rp, which, st);
+    if (mask & (1u << (M * 4 + 3))) launch_scan_rw<M, 8>(rp, which, st);
 }
 
 uint32_t finish_grid(uint32_t n) { return std::max<uint32_t>(1, std::min<uint32_t>((n + 3) / 4, 2048)); }
@@ -494,17 +684,17 @@ uint32_t finish_grid(uint32_t n) { return std::max<uint32_t>(1, std::min<uint32_
 int repair_plan_alloc(RepairPlan& p, uint32_t n_sets, std::vector<void*>& owned) {
     if (n_sets > kMaxSets) return ct_fail(CT_EINVAL, "repair: at most 4096 candidate sets per launch");
     void* a = nullptr;
-    const size_t words = (size_t)(n_sets + 1) * (1 + kNumMetrics) + n_sets;
+    const size_t words = (size_t)(n_sets + 1) * (1 + kNumClasses) + n_sets;
     CT_HIP(hipMalloc(&a, words * sizeof(uint32_t)));
     owned.push_back(a);
     uint32_t* w = static_cast<uint32_t*>(a);
     p.cand_off = w;
     p.item_off = w + (n_sets + 1);
-    p.parts = w + (n_sets + 1) * (1 + kNumMetrics);
+    p.parts = w + (n_sets + 1) * (1 + kNumClasses);
     return CT_OK;
 }
 
-int launch_repair_passes(const RepairPasses& rp, bool zero_counts, hipStream_t st) {
+int launch_repair_passes(const RepairPasses& rp, bool zero_counts, hipStream_t st, bool count_tally) {
     if (rp.n_sets == 0 || rp.total_n == 0) return CT_OK;
     if (zero_counts) {
         ProfScope ps_("k_repair_zero", st);
@@ -517,28 +707,30 @@ int launch_repair_passes(const RepairPasses& rp, bool zero_counts, hipStream_t s
     }
     {
         ProfScope ps_("k_repair_plan", st);
-        hipLaunchKernelGGL(k_repair_plan, dim3(1), dim3(64), 0, st, rp.d_sets, rp.n_sets, 0u, rp.plan);
+        hipLaunchKernelGGL(k_repair_plan, dim3(1), dim3(64), 0, st, rp.d_sets, rp.n_sets, 0u, rp.plan, rp.class_mask,
+                           rp.tune.items, rp.tune.min_sub);
     }
-    if (rp.metrics_mask & (1u << CT_HAMMING)) launch_scan<CT_HAMMING>(rp, 0, st);
-    if (rp.metrics_mask & (1u << CT_INDEX_L1)) launch_scan<CT_INDEX_L1>(rp, 0, st);
-    if (rp.metrics_mask & (1u << CT_TIER_EUCLID)) launch_scan<CT_TIER_EUCLID>(rp, 0, st);
-    if (rp.metrics_mask & (1u << CT_TIER_RANDOM)) launch_scan<CT_TIER_RANDOM>(rp, 0, st);
-    if (rp.metrics_mask & (1u << CT_HAM1_RANDOM)) launch_scan<CT_HAM1_RANDOM>(rp, 0, st);
+    launch_scan<CT_HAMMING>(rp, rp.class_mask, 0, st);
+    launch_scan<CT_INDEX_L1>(rp, rp.class_mask, 0, st);
+    launch_scan<CT_TIER_EUCLID>(rp, rp.class_mask, 0, st);
+    launch_scan<CT_TIER_RANDOM>(rp, rp.class_mask, 0, st);
+    launch_scan<CT_HAM1_RANDOM>(rp, rp.class_mask, 0, st);
     {
         ProfScope ps_("k_repair_finish", st);
         hipLaunchKernelGGL(k_repair_finish, dim3(finish_grid(rp.total_n)), dim3(kBlock), 0, st, rp.d_sets, rp.n_sets,
-                           rp.plan, 0u);
+                           rp.plan, 0u, count_tally ? 1u : 0u);
     }
-    if (rp.metrics_mask & ((1u << CT_TIER_EUCLID) | (1u << CT_TIER_RANDOM))) {
+    if (rp.fb_class_mask) {
         {
             ProfScope ps_("k_repair_plan", st);
-            hipLaunchKernelGGL(k_repair_plan, dim3(1), dim3(64), 0, st, rp.d_sets, rp.n_sets, 1u, rp.plan);
+            hipLaunchKernelGGL(k_repair_plan, dim3(1), dim3(64), 0, st, rp.d_sets, rp.n_sets, 1u, rp.plan,
+                               rp.fb_class_mask, rp.tune.items, rp.tune.min_sub);
         }
-        launch_scan<CT_HAMMING>(rp, 1, st);
+        launch_scan<CT_HAMMING>(rp, rp.fb_class_mask, 1, st);
         {
             ProfScope ps_("k_repair_finish", st);
             hipLaunchKernelGGL(k_repair_finish, dim3(finish_grid(rp.total_n)), dim3(kBlock), 0, st, rp.d_sets,
-                               rp.n_sets, rp.plan, 1u);
+                               rp.n_sets, rp.plan, 1u, 0u);
         }
     }
     CT_HIP(hipGetLastError());

@@ -440,3 +440,54 @@ int batch_generation(ct_batch* b, hipStream_t st) {
     CT_HIP(hipGetLastError());
     return CT_OK;
 }
+
+int batch_autotune_generation(ct_batch* b, hipStream_t st) {
+    if (b->n == 0) return CT_OK;
+    if (b->n_ga) hipLaunchKernelGGL(k_ga_sort, dim3(b->n), dim3(kSelBlock), 0, st, b->d_pops, b->n);
+    {
+        const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>((b->total_ind + kBlock - 1) / kBlock, 4096));
+        hipLaunchKernelGGL(k_propose, dim3(g), dim3(kBlock), 0, st, b->d_pops, b->n, b->d_ind_off);
+    }
+    CT_HIP(hipGetLastError());
+    // The main repair pass reads the proposals and writes only its outputs, lists and counters (the
+    // counters are cleared first and the scan tally is left alone), so it can run once per candidate
+    // partitioning with identical results; the fastest one is kept.
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    CT_HIP(hipEventCreate(&e0));
+    CT_HIP(hipEventCreate(&e1));
+    prof_suspend(true);
+    RepairPasses rp = b->passA;
+    int rc = launch_repair_passes(rp, true, st, false);     // warm the caches
+    float best = 3.0e38f;
+    RepairTune choice = b->passA.tune;
+    const uint32_t items[] = {2048, 4096, 8192};
+    const uint32_t min_sub[] = {8, 16, 32, 64};
+    const uint32_t grid[] = {4096, 8192};
+    for (uint32_t it : items)
+        for (uint32_t ms : min_sub)
+            for (uint32_t gw : grid) {
+                if (rc) break;
+                rp.tune = RepairTune{it, ms, gw};
+                (void)hipEventRecord(e0, st);
+                rc = launch_repair_passes(rp, true, st, false);
+                (void)hipEventRecord(e1, st);
+                if (hipEventSynchronize(e1) != hipSuccess) rc = ct_fail(CT_EDEVICE, "autotune: event wait failed");
+                float t = 0;
+                if (!rc && hipEventElapsedTime(&t, e0, e1) == hipSuccess && t < best) {
+                    best = t;
+                    choice = rp.tune;
+                }
+            }
+    prof_suspend(false);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    b->passA.tune = choice;
+    // the generation's own pass, with the chosen partitioning, counting its scans
+    if ((rc = launch_repair_passes(b->passA, true, st, true))) return rc;
+    if (b->n_ga && (rc = launch_repair_passes(b->passC, false, st))) return rc;
+    hipLaunchKernelGGL(k_select, dim3(b->n), dim3(kSelBlock), 0, st, b->d_pops, b->n);
+    CT_HIP(hipGetLastError());
+    return CT_OK;
+}
+

@@ -131,3 +131,30 @@ def test_many_problem_batch():
         for _ in range(6):
             st = oracle_step(osp, obj, st, opt)
         compare(b[k], st, opt, len(pr.spec.params), f"problem {k} after 6 generations")
+
+
+def test_autotuned_batch_equals_plain(spaces):
+    """The autotuner's generation advances the runs exactly like a plain generation, whatever
+    partitioning it picks; a later batch of the same shape reuses the choice."""
+    from paper_2606_28372_amd import Batch, CT_STEP_GRAPH, step_many
+    t = torch()
+    plain, tuned = make_runs(t, spaces), make_runs(t, spaces)
+    b = Batch(tuned)
+    b.autotune(force=True)
+    tn = b.tuning()
+    say(f"[gpu_batched] tuning {tn}")
+    assert tn["tuned"] and tn["items"] in (2048, 4096, 8192) and tn["min_boxes"] in (8, 16, 32, 64)
+    assert tn["grid_waves"] in (4096, 8192)
+    step_many(plain, 1)
+    t.cuda.synchronize()
+    for x, y in zip(plain, tuned):
+        assert x.snapshot() == y.snapshot()
+    b.step(3, CT_STEP_GRAPH)
+    step_many(plain, 3)
+    t.cuda.synchronize()
+    for x, y in zip(plain, tuned):
+        assert x.snapshot() == y.snapshot()
+    again = Batch(make_runs(t, spaces))
+    assert again.tuning() == tn
+    again.close()
+    b.close()
