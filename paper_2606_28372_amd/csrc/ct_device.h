@@ -50,8 +50,19 @@ struct DevSpace {
 };
 
 // Validity of a linear index from the bitmask.
+// Pointers read out of descriptor structs are generic: the compiler cannot tell device memory
+// from LDS and issues flat accesses, which count against both the vector-memory and the LDS
+// counters, so every cross-lane shuffle would wait for all loads in flight.  Hot loads go
+// through these address-space-typed pointers instead.
+#define CT_GLOBAL __attribute__((address_space(1)))
+#define CT_LDS __attribute__((address_space(3)))
+template <typename T>
+__device__ __forceinline__ const CT_GLOBAL T* gptr(const T* p) { return (const CT_GLOBAL T*)p; }
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) { return *(const CT_GLOBAL T*)p; }
+
 __device__ __forceinline__ bool bit_valid(const DevSpace& S, uint64_t L) {
-    return L < S.N && ((S.words[L >> 6] >> (L & 63u)) & 1ull);
+    return L < S.N && ((gld(S.words + (L >> 6)) >> (L & 63u)) & 1ull);
 }
 
 // Number of valid configurations with linear index below L (the rank of L when it is valid),
@@ -59,9 +70,10 @@ __device__ __forceinline__ bool bit_valid(const DevSpace& S, uint64_t L) {
 __device__ __forceinline__ uint64_t rank_dir(const DevSpace& S, uint64_t L) {
     if (L >= S.N) return S.n_valid;
     const uint64_t w = L >> 6;
-    uint64_t r = S.grp_off[w >> 6] + S.dir8[w >> 3];
-    for (uint64_t q = w & ~7ull; q < w; ++q) r += __popcll(S.words[q]);
-    return r + __popcll(S.words[w] & ((1ull << (L & 63u)) - 1ull));
+    const CT_GLOBAL uint64_t* words = gptr(S.words);
+    uint64_t r = gld(S.grp_off + (w >> 6)) + gld(S.dir8 + (w >> 3));
+    for (uint64_t q = w & ~7ull; q < w; ++q) r += __popcll(words[q]);
+    return r + __popcll(words[w] & ((1ull << (L & 63u)) - 1ull));
 }
 
 // ---------------------------------------------------------------------------

@@ -84,13 +84,18 @@ struct Cand {
     // (X_j - (v * 2^16 + 2^15))^2 in this wave's LDS slice, and the value index s_j whose centre
     // is nearest to X_j (the squared distance is convex in v, so over a box's range [a, b] its
     // minimum is at clamp(s_j, a, b))
-    const uint64_t* tab;
+    const CT_LDS uint64_t* tab;
+    const CT_GLOBAL uint64_t* lin;   // linear indices of the valid list
+    uint32_t D;
     uint32_t s[RW];
     uint32_t who, gen;
     uint64_t seed;
 
-    __device__ void load(const RepairSet& J, const DevSpace& S, uint32_t ci, uint64_t* lds_tab) {
-        const uint32_t* cr = reinterpret_cast<const uint32_t*>(J.rows + (uint64_t)ci * S.R);
+    __device__ void load(const RepairSet& J, const CT_GLOBAL DevSpace* Sg, uint32_t ci, CT_LDS uint64_t* lds_tab) {
+        const CT_GLOBAL DevSpace& S = *Sg;
+        const CT_GLOBAL uint32_t* cr = gptr(reinterpret_cast<const uint32_t*>(J.rows + (uint64_t)ci * S.R));
+        lin = gptr(S.lin);
+        D = S.D;
 #pragma unroll
         for (int k = 0; k < RW; ++k) {
             // bytes past the last parameter are padding: force them to zero
@@ -107,8 +112,9 @@ struct Cand {
                 const uint32_t d = (c[j >> 2] >> ((j & 3) * 8)) & 0xFFu;
                 uint32_t p = d, n = d;
                 if ((uint32_t)j < S.D) {
-                    p = uni(S.prevnext[((uint32_t)j * 256u + d) * 2u + 0u]);
-                    n = uni(S.prevnext[((uint32_t)j * 256u + d) * 2u + 1u]);
+                    const CT_GLOBAL uint8_t* pn = gptr(S.prevnext);
+                    p = uni(pn[((uint32_t)j * 256u + d) * 2u + 0u]);
+                    n = uni(pn[((uint32_t)j * 256u + d) * 2u + 1u]);
                     // the two rules agree on parameter j unless a present value lies below (above) d while
                     // d-1 (d+1) itself never occurs in a solution; "none" is 0xFF, which no digit equals
                     adj_is_sa &= (p == d - 1u || p == 0xFFu) && (n == d + 1u || n == 0xFFu);
@@ -118,7 +124,7 @@ struct Cand {
             }
         }
         if constexpr (M == CT_TIER_EUCLID) {
-            const int32_t* xp = J.pos_q16 + (uint64_t)ci * S.D;
+            const CT_GLOBAL int32_t* xp = gptr(J.pos_q16 + (uint64_t)ci * S.D);
             const uint32_t n_tab = S.max_radix * S.D;
             for (uint32_t e = wave_lane(); e < n_tab; e += 64) {
                 const uint32_t v = e / S.D, j = e - v * S.D;
@@ -165,7 +171,7 @@ struct Cand {
             for (int k = 0; k < RW; ++k) h += __popc(ne_bytes(c[k] ^ v[k]));
             if constexpr (M == CT_HAM1_RANDOM) {
                 if (h != 1u) return kNoKey;
-                const uint64_t L = S.lin[pos];
+                const uint64_t L = lin[pos];
                 U4 o = ct_philox(seed, who, gen, (PUR_MUT_KEY << 24) | (uint32_t)((L >> 32) & 0xFFFFFFu), (uint32_t)L);
                 return o.x;
             } else {
@@ -194,10 +200,10 @@ struct Cand {
                     uint64_t d2 = 0;
 #pragma unroll
                     for (int j = 0; j < RW * 4; ++j)
-                        if ((uint32_t)j < S.D) d2 += tab[((v[j >> 2] >> ((j & 3) * 8)) & 0xFFu) * S.D + (uint32_t)j];
+                        if ((uint32_t)j < D) d2 += tab[((v[j >> 2] >> ((j & 3) * 8)) & 0xFFu) * D + (uint32_t)j];
                     return ((uint64_t)tier << 62) | d2;
                 } else {
-                    const uint64_t L = S.lin[pos];
+                    const uint64_t L = lin[pos];
                     U4 o = ct_philox(seed, who, gen, (PUR_REPAIR_KEY << 24) | (uint32_t)((L >> 32) & 0xFFFFFFu),
                                      (uint32_t)L);
                     return ((uint64_t)tier << 62) | o.x;
@@ -266,154 +272,113 @@ __device__ __forceinline__ void wave_lexmin(uint64_t& k, uint32_t& p) {
     p = uni(p);
 }
 
-// the builtin returns a signed int: both halves go through uint32_t so the low half does not sign-extend
-__device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t l) {
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)l);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, (int)l);
-    return ((uint64_t)hi << 32) | lo;
+// rank_dir on a descriptor typed as device memory
+__device__ __forceinline__ uint64_t rank_g(const CT_GLOBAL DevSpace* S, uint64_t L) {
+    if (L >= S->N) return S->n_valid;
+    const uint64_t w = L >> 6;
+    const CT_GLOBAL uint64_t* words = gptr(S->words);
+    uint64_t r = gptr(S->grp_off)[w >> 6] + gptr(S->dir8)[w >> 3];
+    for (uint64_t q = w & ~7ull; q < w; ++q) r += __popcll(words[q]);
+    return r + __popcll(words[w] & ((1ull << (L & 63u)) - 1ull));
 }
 
-// Bitonic sort of (key, index) pairs across the 64 lanes, ascending; lane t ends with the t-th.
-__device__ __forceinline__ void wave_sort(uint64_t& key, uint32_t& idx) {
-    const uint32_t lane = wave_lane();
-#pragma unroll
-    for (uint32_t k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            const uint32_t klo = __shfl_xor((uint32_t)key, (int)j, 64), khi = __shfl_xor((uint32_t)(key >> 32), (int)j, 64);
-            const uint32_t oi = __shfl_xor(idx, (int)j, 64);
-            const uint64_t ok = ((uint64_t)khi << 32) | klo;
-            const bool other_less = ok < key || (ok == key && oi < idx);
-            const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
-            if (keep_min == other_less) { key = ok; idx = oi; }
-        }
-    }
-}
-
-// One (candidate, part) item: the lexicographic (key, position) minimum over the seed rows and
-// the rows of the part's boxes that cannot be ruled out.
-//   - (bk, bp) is the best row this item has seen; the candidate's shared incumbent holds the
-//     smallest key any of its parts has found so far (atomic minimum, read again before every
-//     box), so parts prune with each other's finds;
-//   - a box can still win if its lower bound lb is below the best known key, or equal to this
-//     item's own best key while the box starts before that row (the shared key carries no
-//     position, so a box whose bound merely equals it stays open);
-//   - each run of 64 boxes is sorted by (lb, box) across the wave and opened in that order, so
-//     the bound tightens as early as possible and the first box that cannot win ends the run;
-//     the rows of the next box in that order load while the current box is evaluated.
-// Tiered metrics only accept tiers 0-2 here; the Hamming fallback pass handles the rest.
+// One (candidate, part) item: the lexicographic (key, position) minimum over the rows of the
+// part's boxes that cannot be ruled out.
+//   - bk is an exclusive bound (keys below it are wanted); it starts from the 64 valid rows
+//     around the candidate's place in linear-index order, and from tier 3 for the tiered
+//     metrics (their fallback pass handles candidates without a tier 0-2 neighbour);
+//   - boxes are visited in position order, lanes over 64 boxes at a time: a box is opened only
+//     if its lower bound is below bk, one row per lane, and the rows of the next surviving box
+//     load while the current one is evaluated;
+//   - after each box bk drops to the smallest key found, so later boxes (higher positions) with
+//     an equal bound are skipped: ties go to the lowest position.
 template <int M, int RW>
 __device__ void scan_item(const RepairSet& J, const DevSpace& S, const uint32_t* list, const uint64_t* list_L,
-                          uint32_t li, uint32_t part, uint32_t parts, uint64_t* lds_tab) {
+                          uint32_t li, uint32_t part, uint32_t parts, CT_LDS uint64_t* lds_tab) {
     const uint32_t lane = wave_lane();
-    const uint32_t ci = uni(list[li]);
+    const CT_GLOBAL DevSpace* Sg = gptr(&S);
+    const uint32_t ci = uni(gld(list + li));
     Cand<M, RW> C;
-    C.load(J, S, ci, lds_tab);
-    const uint32_t* rows32 = reinterpret_cast<const uint32_t*>(S.rows);
-    uint64_t* inc = J.inc + li;
+    C.load(J, Sg, ci, lds_tab);
+    const CT_GLOBAL uint32_t* rows32 = gptr(reinterpret_cast<const uint32_t*>(Sg->rows));
+    const CT_GLOBAL uint32_t* box32 = gptr(reinterpret_cast<const uint32_t*>(Sg->boxes));
+    const uint64_t n_valid = Sg->n_valid, n_sub = Sg->n_sub;
+    const uint32_t D = Sg->D;
 
     constexpr bool tiered = (M == CT_TIER_EUCLID || M == CT_TIER_RANDOM);
-    constexpr uint64_t cap = tiered ? kTier3 : kNoKey;     // keys at or above cap are not wanted
-    uint64_t bk = kNoKey;
-    uint32_t bp = kNoPos;
-    const uint64_t L = ((uint64_t)uni((uint32_t)(list_L[li] >> 32)) << 32) | uni((uint32_t)list_L[li]);
+    uint64_t bk = tiered ? kTier3 : kNoKey;
+    const uint64_t Lc = gld(list_L + li);
+    const uint64_t L = ((uint64_t)uni((uint32_t)(Lc >> 32)) << 32) | uni((uint32_t)Lc);
     if (L != ~0ull) {
-        // seed with the 64 valid rows around the candidate's place in linear-index order
-        const uint64_t ins = rank_dir(S, L);
+        const uint64_t ins = rank_g(Sg, L);
         const int64_t q = (int64_t)ins - 32 + (int64_t)lane;
         uint64_t k = kNoKey;
-        uint32_t p = kNoPos;
-        if (q >= 0 && (uint64_t)q < S.n_valid) {
+        if (q >= 0 && (uint64_t)q < n_valid) {
             uint32_t v[RW];
 #pragma unroll
             for (int w = 0; w < RW; ++w) v[w] = rows32[(uint64_t)q * RW + w];
-            k = C.key(S, v, (uint64_t)q, cap);
-            if (k >= cap) k = kNoKey;
-            else p = (uint32_t)q;
+            k = C.key(S, v, (uint64_t)q, bk);
         }
-        wave_lexmin(k, p);
-        bk = k;
-        bp = p;
-        if (bk != kNoKey && lane == 0) atomicMin((unsigned long long*)inc, (unsigned long long)bk);
+        k = wave_min_u64(k);
+        if (k < bk) bk = k + 1;
     }
-    auto read_inc = [&]() -> uint64_t {
-        const uint64_t g = __hip_atomic_load(inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return ((uint64_t)uni((uint32_t)(g >> 32)) << 32) | uni((uint32_t)g);
-    };
-    uint64_t g = read_inc();
-    auto can_win = [&](uint64_t lb, uint64_t box) {
-        const uint64_t ub = min(min(bk, g), cap - 1);
-        return lb < ub || (lb == ub && !(ub == bk && box * 64u > bp));
-    };
 
-    const uint64_t b0 = (uint64_t)part * S.n_sub / parts, b1 = (uint64_t)(part + 1) * S.n_sub / parts;
-    const uint32_t* box32 = reinterpret_cast<const uint32_t*>(S.boxes);
-    uint32_t nlo[RW], nhi[RW], nv[RW];
-    auto fetch_boxes = [&](uint64_t cb) {
-        const uint64_t b = cb + lane;
-#pragma unroll
-        for (int w = 0; w < RW; ++w) {
-            nlo[w] = b < b1 ? box32[b * 2u * RW + w] : 0u;
-            nhi[w] = b < b1 ? box32[b * 2u * RW + RW + w] : 0u;
-        }
-    };
-    auto fetch_rows = [&](uint64_t box) {
-        const uint64_t r = box * 64u + lane;
-#pragma unroll
-        for (int w = 0; w < RW; ++w) nv[w] = r < S.n_valid ? rows32[r * RW + w] : 0u;
-    };
-    if (b0 < b1) fetch_boxes(b0);
+    uint64_t mk = bk;                               // this lane's best key (exclusive until a row is found)
+    uint32_t mp = kNoPos;
+    const uint64_t b0 = (uint64_t)part * n_sub / parts, b1 = (uint64_t)(part + 1) * n_sub / parts;
+    uint32_t nv[RW];
     for (uint64_t cb = b0; cb < b1; cb += 64) {
-        uint32_t lo[RW], hi[RW];
+        // lanes over 64 boxes: which ones can hold a row below the bound?
+        const uint64_t b = cb + lane;
+        uint64_t lb = kNoKey;
+        if (b < b1) {
+            uint32_t lo[RW], hi[RW];
 #pragma unroll
-        for (int w = 0; w < RW; ++w) { lo[w] = nlo[w]; hi[w] = nhi[w]; }
-        if (cb + 64 < b1) fetch_boxes(cb + 64);    // the next 64 boxes load while these are examined
-        uint64_t slb = cb + lane < b1 ? C.bound_box(lo, hi, S.D) : kNoKey;
-        uint32_t sidx = lane;
-        wave_sort(slb, sidx);
-        g = min(g, read_inc());
-        uint64_t lbt = readlane64(slb, 0);
-        uint64_t bt = cb + (uint32_t)__builtin_amdgcn_readlane((int)sidx, 0);
-        if (!can_win(lbt, bt)) continue;
-        fetch_rows(bt);
-        for (uint32_t t = 0;;) {
+            for (int w = 0; w < RW; ++w) {
+                lo[w] = box32[b * 2u * RW + w];
+                hi[w] = box32[b * 2u * RW + RW + w];
+            }
+            lb = C.bound_box(lo, hi, D);
+        }
+        uint64_t m = __ballot(lb < bk);
+        int tn = m ? __ffsll((long long)m) - 1 : -1;
+        auto fetch = [&](int t) {
+            const uint64_t q = (cb + (uint32_t)t) * 64u + lane;
+#pragma unroll
+            for (int w = 0; w < RW; ++w) nv[w] = q < n_valid ? rows32[q * RW + w] : 0u;
+        };
+        if (tn >= 0) fetch(tn);
+        while (tn >= 0) {
+            const uint32_t t = (uint32_t)tn;
+            m &= ~(1ull << t);
             uint32_t v[RW];
 #pragma unroll
             for (int w = 0; w < RW; ++w) v[w] = nv[w];
-            const uint64_t cur = bt;
-            // the next box in bound order, fetched now if it can still win
-            bool more = false;
-            if (t + 1 < 64) {
-                lbt = readlane64(slb, t + 1);
-                bt = cb + (uint32_t)__builtin_amdgcn_readlane((int)sidx, (int)(t + 1));
-                more = can_win(lbt, bt);
-                if (more) fetch_rows(bt);
+            tn = m ? __ffsll((long long)m) - 1 : -1;
+            if (tn >= 0) fetch(tn);
+            const uint64_t r = (cb + t) * 64u + lane;
+            if (r < n_valid) {
+                const uint64_t k = C.key(S, v, r, mk < bk ? mk : bk);
+                if (k < mk) { mk = k; mp = (uint32_t)r; }
             }
-            const uint64_t gn = __hip_atomic_load(inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            // lanes over the 64 rows of the current box
-            const uint64_t r = cur * 64u + lane;
-            const uint64_t ub = min(min(bk, g), cap - 1);
-            uint64_t k = kNoKey;
-            uint32_t p = kNoPos;
-            if (r < S.n_valid) {
-                k = C.key(S, v, r, ub + 1);
-                if (k > ub) k = kNoKey;
-                else p = (uint32_t)r;
+            const uint64_t wm = wave_min_u64(mk);
+            bk = wm < bk ? wm : bk;
+            if (m) {
+                m &= __ballot(lb < bk);             // drop boxes the tighter bound now rules out
+                if (tn >= 0 && !((m >> tn) & 1ull)) {
+                    tn = m ? __ffsll((long long)m) - 1 : -1;
+                    if (tn >= 0) fetch(tn);
+                }
             }
-            if (__ballot(k < bk || (k == bk && p < bp))) {
-                wave_lexmin(k, p);
-                if (k < bk && lane == 0) atomicMin((unsigned long long*)inc, (unsigned long long)k);
-                bk = k;
-                bp = p;
-            }
-            g = min(g, ((uint64_t)uni((uint32_t)(gn >> 32)) << 32) | uni((uint32_t)gn));
-            if (!more || !can_win(lbt, bt)) break;
-            ++t;
         }
     }
+    // lexicographic (key, position) minimum over the wave
+    uint64_t k2 = mp == kNoPos ? kNoKey : mk;
+    uint32_t p2 = mp;
+    wave_lexmin(k2, p2);
     if (lane == 0) {
-        J.part_key[(uint64_t)li * parts + part] = bk;
-        J.part_pos[(uint64_t)li * parts + part] = bp;
+        J.part_key[(uint64_t)li * parts + part] = k2;
+        J.part_pos[(uint64_t)li * parts + part] = p2;
     }
 }
 
@@ -592,7 +557,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_scan(const RepairSet* __restr
     constexpr uint32_t cls = (uint32_t)M * 4u + (RW == 1 ? 0u : RW == 2 ? 1u : RW == 4 ? 2u : 3u);
     extern __shared__ uint64_t lds_tabs[];
     const uint32_t wpb = blockDim.x / 64;
-    uint64_t* lds_tab = lds_tabs + (threadIdx.x >> 6) * tab_stride;
+    CT_LDS uint64_t* lds_tab = (CT_LDS uint64_t*)lds_tabs + (threadIdx.x >> 6) * tab_stride;
     const uint32_t* off = plan.item_off + cls * (n_sets + 1);
     const uint32_t total = off[n_sets];
     const uint32_t waves = gridDim.x * wpb;
