@@ -30,8 +30,10 @@ printed:
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -67,6 +69,24 @@ def kernel_names():
     return ["k_table", "k_mask", "k_tile_sums", "k_scan_tiles", "k_compact", "k_boxes", "k_presence",
             "k_prevnext", "k_init", "k_init_finish", "k_ga_sort", "k_propose", "k_repair_zero", "k_repair_prep",
             "k_repair_plan", "k_repair_scan", "k_repair_finish", "k_select"]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary (rocprofv3 FETCH_SIZE and
+    WRITE_SIZE, scaled by a 1 GiB copy), if it was taken on the gemm13 job with the current sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_counters_gemm13_job.md")
+    if workload != "gemm" or not os.path.exists(path):
+        return None
+    m = re.search(r"<!-- traffic (\{.*\}) -->", open(path).read())
+    if not m:
+        return None
+    meta = json.loads(m.group(1))
+    h = hashlib.sha256()
+    for f in meta["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if meta["kernel"] != kernel or h.hexdigest() != meta["sources_sha256"]:
+        return None                      # the kernel changed since the counters were taken
+    return meta["bytes_per_launch"]
 
 
 def run_job(ct, spec, runs, objective_t, gens):
@@ -321,7 +341,8 @@ def main():
         ops = pairs * D / max(dom_n / args.steps, 1)              # per launch
         achieved = ops / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": BYTE_PEAK_TOPS, "unit": "Tdigitop/s",
-                "frac": achieved / BYTE_PEAK_TOPS, "traffic": None, "kernel": dom, "avg_launch_ms": avg_ms}
+                "frac": achieved / BYTE_PEAK_TOPS, "traffic": measured_traffic(dom, args.workload), "kernel": dom,
+                "avg_launch_ms": avg_ms}
     else:
         # enumeration kernels: one validity bit written per configuration
         nbytes = n_cart / 8 / max(dom_n / args.steps, 1)

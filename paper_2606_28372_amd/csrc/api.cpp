@@ -120,7 +120,6 @@ int batch_fill(ct_batch* b, const std::vector<ct_pop*>& pops) {
         r.count = d.rcount;
         r.part_key = p->r_part_key;
         r.part_pos = p->r_part_pos;
-        r.inc = p->r_inc;
         r.tally = d.tally;
         setsA.push_back(r);
         maskA |= 1u << repair_class(r.metric, d.R);
@@ -237,7 +236,7 @@ uint64_t pop_footprint_bytes(uint32_t algo, uint32_t P, uint32_t D, uint32_t R, 
     else b += 8 * p;                                              // pos, f
     if (algo == CT_DE) b += (n_valid + 31) / 32 * 4 + std::max<uint64_t>(n_valid, 1) * 4;   // member, claim
     if (algo == CT_GA) b += 8 * p + 4 * p;                        // beta table, sorted
-    b += 4 * p + 8 * p + 4 * p + 8 * p + 8 * p + slots * (8 + 4); // repair scratch
+    b += 4 * p + 8 * p + 4 * p + 8 * p + slots * (8 + 4);         // repair scratch
     return b;
 }
 
@@ -465,7 +464,7 @@ int ct_repair(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t met
     hipStream_t st = as_stream(stream);
     // one candidate set: scratch lists, per-part winners, the set itself and its plan
     const uint64_t slots = std::max<uint64_t>(n, kRepairTargetWaves);
-    const size_t bytes = n * (4 + 8 + 4 + 8 + 8) + slots * (8 + 4) + 2 * 4 + 2 * 4 + sizeof(RepairSet) + 64;
+    const size_t bytes = n * (4 + 8 + 4 + 8) + slots * (8 + 4) + 2 * 4 + 2 * 4 + sizeof(RepairSet) + 64;
     uint8_t* buf = nullptr;
     CT_HIP(hipMallocAsync((void**)&buf, bytes, st));
     RepairSet h{};
@@ -489,7 +488,6 @@ int ct_repair(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t met
     h.fb_L = (uint64_t*)take(n * 8);
     h.part_key = (uint64_t*)take(slots * 8);
     h.part_pos = (uint32_t*)take(slots * 4);
-    h.inc = (uint64_t*)take(n * 8);
     h.count = (uint32_t*)take(2 * 4);
     h.tally = nullptr;
     uint32_t* prep_off = (uint32_t*)take(2 * 4);
@@ -599,7 +597,7 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_ob
         return fail(ct_fail(CT_EDEVICE, "ct_pop_create: memset failed"));
     if ((rc = dalloc(p, &p->r_list, P)) || (rc = dalloc(p, &p->r_list_L, P)) || (rc = dalloc(p, &p->r_fb, P)) ||
         (rc = dalloc(p, &p->r_fb_L, P)) || (rc = dalloc(p, &p->r_part_key, slots)) ||
-        (rc = dalloc(p, &p->r_part_pos, slots)) || (rc = dalloc(p, &p->r_inc, P)))
+        (rc = dalloc(p, &p->r_part_pos, slots)))
         return fail(rc);
     if ((rc = pop_init_device(p, st))) return fail(rc);
     *out = p;

@@ -93,7 +93,6 @@ struct RepairSet {
     uint32_t* count;                  // [0] list length, [1] fallback length
     uint64_t* part_key;               // per (candidate, part) winners [slots]
     uint32_t* part_pos;
-    uint64_t* inc;                    // per listed candidate: smallest key any of its parts has found [n]
     unsigned long long* tally;        // nullable: += candidates scanned
 };
 
@@ -188,7 +187,6 @@ struct ct_pop {
     uint64_t* r_fb_L = nullptr;
     uint64_t* r_part_key = nullptr;
     uint32_t* r_part_pos = nullptr;
-    uint64_t* r_inc = nullptr;
 };
 
 // A group of runs stepped together: descriptor arrays in device memory (sized for `cap`

@@ -460,7 +460,6 @@ __global__ __launch_bounds__(kBlock) void k_repair_prep(const RepairSet* __restr
             const uint32_t k = atomicAdd(&J.count[0], 1u);
             J.list[k] = i;
             J.list_L[k] = L;
-            J.inc[k] = kNoKey;
         }
     }
 }
@@ -617,7 +616,6 @@ __global__ __launch_bounds__(kBlock) void k_repair_finish(const RepairSet* __res
             const uint32_t k = atomicAdd(&J.count[1], 1u);
             J.fb_list[k] = ci;
             J.fb_L[k] = ~0ull;           // no seed: the fallback scans the whole list
-            J.inc[k] = kNoKey;           // the main pass is over: the incumbents are free again
         }
     }
 }
