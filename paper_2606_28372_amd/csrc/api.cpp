@@ -296,10 +296,14 @@ int space_prepare(const int64_t* values, const uint32_t* radices, uint32_t n_par
     S.R = s->R;
     S.N = (uint64_t)N;
     S.max_radix = max_radix;
-    // prefix split: the longest leading run of parameters whose product is at most 2^24
+    // prefix split: the longest leading run of parameters whose product is at most
+    // min(2^24, N / 64), so the prefix table stays small and every prefix owns at least one
+    // wave's worth of inner configurations; constraints over the prefix alone are then
+    // evaluated once per prefix and invalid prefixes skip their inner configurations
+    const uint64_t cap = std::max<uint64_t>(1, std::min<uint64_t>(1ull << 24, (uint64_t)N / 64));
     uint64_t Ps = 1;
     uint32_t split = 0;
-    while (split < n_params && Ps * radices[split] <= (1ull << 24)) Ps *= radices[split++];
+    while (split < n_params && Ps * radices[split] <= cap) Ps *= radices[split++];
     S.split = split;
     S.P_s = Ps;
     S.I_s = S.N / Ps;

@@ -49,67 +49,107 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t lane) {
     return x - v;
 }
 
-// Bits for linear indices x in [0, total) (total <= 2^32) under programs [0, c1),
-// decoding only parameters [0, dlim).  One group (64 words) per wave.
+// Bits for linear indices x in [0, total) (total <= 2^32) under programs [0, c1), decoding only
+// parameters [0, dlim).  Work unit: kSubWords bitmask words (64 configurations each) per wave, so
+// that even small tables spread over many waves (the interpreter's instruction fetches are a
+// dependent chain; other waves hide it).  Lane k keeps word k of the unit.  With group_counts,
+// the valid configurations of each 4096-index group are added to its (zeroed) counter.
+constexpr uint32_t kSubWords = 8;
+
 __global__ __launch_bounds__(kBlock) void k_table(DevSpace S, uint64_t total, uint32_t dlim, uint32_t c1,
                                                   uint32_t n_vals, uint64_t n_words, uint64_t* __restrict__ words,
                                                   uint32_t* __restrict__ group_counts) {
     extern __shared__ int64_t lds_vals[];
     load_values_lds(S, lds_vals, n_vals);
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t g = (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    const uint64_t base = g * 4096u;
-    if (base >= total) return;
-    uint64_t mine = 0;
-    for (uint32_t k = 0; k < 64; ++k) {
-        uint64_t x = base + k * 64u + lane;
-        bool ok = x < total;
-        if (__any(ok)) {
-            Row r;
+    const uint64_t n_units = (total + 64u * kSubWords - 1) / (64u * kSubWords);
+    const uint64_t stride = (uint64_t)gridDim.x * kWavesPerBlock;
+    for (uint64_t u = (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); u < n_units; u += stride) {
+        const uint64_t base = u * 64u * kSubWords;
+        uint64_t mine = 0;
+        for (uint32_t k = 0; k < kSubWords; ++k) {
+            const uint64_t x = base + k * 64u + lane;
+            bool ok = x < total;
+            if (__any(ok)) {
+                Row r;
 #pragma unroll
-            for (int q = 0; q < CT_DMAX / 4; ++q) r.w[q] = 0;
-            decode_range(S, (uint32_t)(ok ? x : 0), 0, dlim, r);
-            ok = ok && ct_eval(S, 0, c1, r, lds_vals);
+                for (int q = 0; q < CT_DMAX / 4; ++q) r.w[q] = 0;
+                decode_range(S, (uint32_t)(ok ? x : 0), 0, dlim, r);
+                ok = ok && ct_eval(S, 0, c1, r, lds_vals);
+            }
+            const uint64_t b = __ballot(ok);
+            if (lane == k) mine = b;
         }
-        uint64_t b = __ballot(ok);
-        if (lane == k) mine = b;
-    }
-    uint64_t w = g * 64u + lane;
-    if (w < n_words) words[w] = mine;
-    if (group_counts) {
-        uint32_t c = wave_sum((uint32_t)__popcll(mine));
-        if (lane == 0) group_counts[g] = c;
+        const uint64_t w = u * kSubWords + lane;
+        if (lane < kSubWords && w < n_words) words[w] = mine;
+        if (group_counts) {
+            const uint32_t c = wave_sum(lane < kSubWords ? (uint32_t)__popcll(mine) : 0u);
+            if (lane == 0 && c) atomicAdd(&group_counts[base / 4096u], c);
+        }
     }
 }
 
-// Full bitmask when a prefix table exists (split < D).
-__global__ __launch_bounds__(kBlock) void k_mask(DevSpace S, uint32_t n_vals, uint64_t n_words,
-                                                 uint64_t* __restrict__ words, uint32_t* __restrict__ group_counts) {
+// Full bitmask when a prefix table exists (split < D), in two kernels.
+// k_mask_classify: persistent waves take 64 groups at a time; lane l checks whether group l spans
+// any valid prefix (the prefix bits it covers).  Groups that span none are written as zeros with
+// one coalesced store each; the others are appended to a work list.
+__global__ __launch_bounds__(kBlock) void k_mask_classify(DevSpace S, uint64_t n_groups, uint64_t n_words,
+                                                          uint64_t* __restrict__ words, uint32_t* __restrict__ group_counts,
+                                                          uint32_t* __restrict__ todo, uint32_t* __restrict__ n_todo) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t n_batches = (n_groups + 63u) / 64u;
+    const uint64_t stride = (uint64_t)gridDim.x * kWavesPerBlock;
+    for (uint64_t bt = (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); bt < n_batches; bt += stride) {
+        const uint64_t gl = bt * 64u + lane;
+        bool need = false;
+        if (gl < n_groups) {
+            const uint64_t L0 = gl * 4096u;
+            const uint64_t last = std::min<uint64_t>(L0 + 4095u, S.N - 1);
+            const uint64_t p0 = L0 / S.I_s, p_hi = last / S.I_s;
+            for (uint64_t w = p0 >> 6; w <= (p_hi >> 6) && !need; ++w) {
+                uint64_t bits = S.prefix_words[w];
+                if (w == (p0 >> 6)) bits &= ~0ull << (p0 & 63u);
+                if (w == (p_hi >> 6) && (p_hi & 63u) != 63u) bits &= (2ull << (p_hi & 63u)) - 1ull;
+                need = bits != 0;
+            }
+            group_counts[gl] = 0;
+        }
+        // the wave's groups that need the programs go to the work list with one atomic
+        const uint64_t nm = __ballot(need);
+        uint32_t base = 0;
+        if (lane == 0 && nm) base = atomicAdd(n_todo, (uint32_t)__popcll(nm));
+        base = __shfl(base, 0, 64);
+        if (need) todo[base + (uint32_t)__popcll(nm & ((1ull << lane) - 1ull))] = (uint32_t)gl;
+        uint64_t zero = __ballot(gl < n_groups && !need);
+        while (zero) {
+            const uint64_t g = bt * 64u + (uint64_t)(__ffsll((long long)zero) - 1);
+            zero &= zero - 1ull;
+            const uint64_t w = g * 64u + lane;
+            if (w < n_words) words[w] = 0;
+        }
+    }
+}
+
+// k_mask_eval: work unit = kSubWords words of a listed group per wave; in each step the lanes
+// take 64 consecutive configurations, skip the ones whose prefix is invalid, and run the programs
+// that read inner parameters on the rest.  Counts are added to the group's counter.
+__global__ __launch_bounds__(kBlock) void k_mask_eval(DevSpace S, uint32_t n_vals, uint64_t n_words,
+                                                      uint64_t* __restrict__ words, uint32_t* __restrict__ group_counts,
+                                                      const uint32_t* __restrict__ todo, const uint32_t* __restrict__ n_todo) {
     extern __shared__ int64_t lds_vals[];
     load_values_lds(S, lds_vals, n_vals);
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t g = (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    const uint64_t L0 = g * 4096u;
-    if (L0 >= S.N) return;
-    const uint64_t last = std::min<uint64_t>(L0 + 4095u, S.N - 1);
-    const uint64_t p0 = L0 / S.I_s;
-    const uint32_t r0 = (uint32_t)(L0 - p0 * S.I_s);
-    const uint64_t p_hi = last / S.I_s;
-    // does any prefix spanned by the group hold?
-    bool any = false;
-    for (uint64_t wlo = p0 >> 6; wlo <= (p_hi >> 6) && !any; wlo += 64) {
-        uint64_t wi = wlo + lane;
-        uint64_t bits = 0;
-        if (wi <= (p_hi >> 6)) {
-            bits = S.prefix_words[wi];
-            if (wi == (p0 >> 6)) bits &= ~0ull << (p0 & 63u);
-            if (wi == (p_hi >> 6) && (p_hi & 63u) != 63u) bits &= (2ull << (p_hi & 63u)) - 1ull;
-        }
-        any = __any(bits != 0);
-    }
-    uint64_t mine = 0;
-    if (any) {
-        for (uint32_t k = 0; k < 64; ++k) {
+    constexpr uint32_t kUnits = 64u / kSubWords;
+    const uint64_t total = (uint64_t)(*n_todo) * kUnits;
+    const uint64_t stride = (uint64_t)gridDim.x * kWavesPerBlock;
+    for (uint64_t it = (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); it < total; it += stride) {
+        const uint64_t g = todo[it / kUnits];
+        const uint32_t sub = (uint32_t)(it % kUnits);
+        const uint64_t L0 = g * 4096u + (uint64_t)sub * kSubWords * 64u;
+        const uint64_t p0 = L0 / S.I_s;
+        const uint32_t r0 = (uint32_t)(L0 - p0 * S.I_s);
+        uint64_t mine = 0;
+        for (uint32_t k = 0; k < kSubWords; ++k) {
             const uint32_t off = k * 64u + lane;
             const uint64_t L = L0 + off;
             const uint32_t x = r0 + off;
@@ -127,14 +167,14 @@ __global__ __launch_bounds__(kBlock) void k_mask(DevSpace S, uint32_t n_vals, ui
                 decode_range(S, ok ? inner : 0u, S.split, S.D, r);
                 ok = ok && ct_eval(S, S.n_pre, S.n_cons, r, lds_vals);
             }
-            uint64_t b = __ballot(ok);
+            const uint64_t b = __ballot(ok);
             if (lane == k) mine = b;
         }
+        const uint64_t w = g * 64u + (uint64_t)sub * kSubWords + lane;
+        if (lane < kSubWords && w < n_words) words[w] = mine;
+        const uint32_t c = wave_sum(lane < kSubWords ? (uint32_t)__popcll(mine) : 0u);
+        if (lane == 0 && c) atomicAdd(&group_counts[g], c);
     }
-    uint64_t w = g * 64u + lane;
-    if (w < n_words) words[w] = mine;
-    uint32_t c = wave_sum((uint32_t)__popcll(mine));
-    if (lane == 0) group_counts[g] = c;
 }
 
 // Sum of each tile of kTileGroups group counts.
@@ -363,17 +403,28 @@ int space_build_device(ct_space* s, hipStream_t st) {
     CT_HIP(hipMallocAsync((void**)&d_off, (n_tiles + 1) * sizeof(uint64_t), st));
 
     if (S.split == S.D) {
-        // the whole space is one table
-        { ProfScope ps_("k_table", st); hipLaunchKernelGGL(k_table, dim3(grid_for(n_groups, kWavesPerBlock)), dim3(kBlock), lds, st, S, S.N, S.D,
+        // the whole space is one table (only when N < 64 or every parameter has one value)
+        CT_HIP(hipMemsetAsync(d_counts, 0, n_groups * sizeof(uint32_t), st));
+        CT_HIP(hipMemsetAsync(s->d_words, 0, n_words_alloc * sizeof(uint64_t), st));
+        const uint64_t units = (S.N + 64u * kSubWords - 1) / (64u * kSubWords);
+        { ProfScope ps_("k_table", st); hipLaunchKernelGGL(k_table, dim3(grid_for(units, kWavesPerBlock, 4096)), dim3(kBlock), lds, st, S, S.N, S.D,
                            S.n_cons, n_vals, s->n_words, s->d_words, d_counts); }
     } else {
         const uint64_t p_groups = (S.P_s + 4095u) / 4096u;
         CT_HIP(hipMalloc(&s->d_prefix, p_groups * 64u * sizeof(uint64_t)));
-        { ProfScope ps_("k_table", st); hipLaunchKernelGGL(k_table, dim3(grid_for(p_groups, kWavesPerBlock)), dim3(kBlock), lds, st, S, S.P_s,
+        CT_HIP(hipMemsetAsync(s->d_prefix, 0, p_groups * 64u * sizeof(uint64_t), st));
+        const uint64_t units = (S.P_s + 64u * kSubWords - 1) / (64u * kSubWords);
+        { ProfScope ps_("k_table", st); hipLaunchKernelGGL(k_table, dim3(grid_for(units, kWavesPerBlock, 4096)), dim3(kBlock), lds, st, S, S.P_s,
                            S.split, S.n_pre, n_vals, p_groups * 64u, s->d_prefix, (uint32_t*)nullptr); }
         S.prefix_words = s->d_prefix;
-        { ProfScope ps_("k_mask", st); hipLaunchKernelGGL(k_mask, dim3(grid_for(n_groups, kWavesPerBlock)), dim3(kBlock), lds, st, S, n_vals,
-                           s->n_words, s->d_words, d_counts); }
+        uint32_t* d_todo = nullptr;
+        CT_HIP(hipMallocAsync((void**)&d_todo, (n_groups + 1) * sizeof(uint32_t), st));
+        CT_HIP(hipMemsetAsync(d_todo + n_groups, 0, sizeof(uint32_t), st));
+        { ProfScope ps_("k_mask", st); hipLaunchKernelGGL(k_mask_classify, dim3(grid_for((n_groups + 63u) / 64u, kWavesPerBlock, 2048)), dim3(kBlock), 0, st, S, n_groups,
+                           s->n_words, s->d_words, d_counts, d_todo, d_todo + n_groups); }
+        { ProfScope ps_("k_mask", st); hipLaunchKernelGGL(k_mask_eval, dim3(grid_for(n_groups * (64u / kSubWords), kWavesPerBlock, 4096)), dim3(kBlock), lds, st, S, n_vals,
+                           s->n_words, s->d_words, d_counts, d_todo, d_todo + n_groups); }
+        CT_HIP(hipFreeAsync(d_todo, st));
     }
     CT_HIP(hipGetLastError());
     { ProfScope ps_("k_tile_sums", st); hipLaunchKernelGGL(k_tile_sums, dim3((uint32_t)n_tiles), dim3(kTileGroups), 0, st, d_counts, n_groups, d_tiles); }
