@@ -45,6 +45,7 @@ import numpy as np  # noqa: E402
 import workloads as W  # noqa: E402
 
 METRIC = "configs checked/s + repairs/s; batched vs plain generations/s on 1 GPU"
+AUTOTUNE_SAMPLES = 8              # tuning generations per run: repair passes timed under every partitioning
 
 # MI355X published peaks and the derived integer-ALU peak
 HBM_PEAK_GBS = 8000.0
@@ -96,8 +97,9 @@ def run_job(ct, spec, runs, objective_t, gens):
     pops = [ct.Pop.from_opt(sp, opt, objective_t) for opt in runs]
     batch = ct.Batch(pops)
     if gens:
-        batch.autotune()                  # picks the scan partitioning once per shape; a plain generation after
-        batch.step(gens - 1, ct.CT_STEP_BATCHED)
+        # tuning generations spread over the run pick the scan partitioning (once per shape: plain
+        # generations when the shape is cached)
+        batch.autotune(gens, max(1, gens // AUTOTUNE_SAMPLES))
     batch.close()
     out = []
     for p in pops:
@@ -157,7 +159,8 @@ def batched_leg(ct, n_problems, gens):
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     batch = ct.Batch(pops)
-    batch.autotune()                      # the scan partitioning for this group, before the clock starts
+    # the scan partitioning, before the clock starts: two sweeps, the stream setting timed between
+    batch.autotune(gens, max(1, gens // 2))
     torch.cuda.synchronize()
     start = [p.snapshot() for p in pops]
 

@@ -248,19 +248,34 @@ int ct_batch_step(ct_batch* b, uint32_t n_generations, uint32_t flags, void* str
 void ct_batch_free(ct_batch* b);
 
 /*
- * ct_batch_autotune -- advance the batch by exactly one generation, choosing the
- * work partitioning of its repair scans (candidates x list parts per launch,
- * least 64-row boxes per part, waves in the grid) by timing the generation's
- * repair pass under each candidate partitioning; every candidate computes the
- * same result, so the run's state advances exactly as with ct_batch_step.
- * The choice is kept for the batch and, process-wide, for later batches of the
- * same shape (per run: algorithm, row bytes, parameters, log2 |V|, log2 P);
- * when the shape was tuned before and force is 0 this is a plain generation.
- * Synchronises the stream.
+ * ct_batch_autotune -- advance the batch by exactly n_generations generations,
+ * choosing the work partitioning of its repair scans (candidates x list parts
+ * per launch, least 64-row boxes per part, waves in the grid, independent scan
+ * classes on side streams or not).  Generations 0, sample_every,
+ * 2 * sample_every, ... (sample_every 0 counts as 1) are tuning generations:
+ * their main repair pass also runs under every candidate partitioning, back to
+ * back, each one timed; the candidate with the lowest time summed over the
+ * tuning generations is kept.  The repair load changes as the populations
+ * converge, so samples spread over the run choose better than the first
+ * generations alone.  Every candidate computes the same result, so the runs'
+ * state advances exactly as with ct_batch_step.  The choice is kept for the
+ * batch and, process-wide, for later batches of the same shape (per run:
+ * algorithm, row bytes, parameters, log2 |V|, log2 P); when the shape was
+ * tuned before and force is 0 these are plain generations.  Synchronises the
+ * stream at each tuning generation.
  */
-int ct_batch_autotune(ct_batch* b, uint32_t force, void* stream);
+int ct_batch_autotune(ct_batch* b, uint32_t n_generations, uint32_t sample_every, uint32_t force, void* stream);
+/*
+ * ct_batch_set_tuning -- install a scan partitioning for this batch (one saved
+ * from ct_batch_tuning, say): items in [64, 8192], min_boxes in [1, 2^20],
+ * grid_waves in [64, 2^20], overlap 0 or 1; CT_EINVAL otherwise.  Results do
+ * not depend on it.  The batch counts as tuned; the process-wide cache is left
+ * alone.
+ */
+int ct_batch_set_tuning(ct_batch* b, uint32_t items, uint32_t min_boxes, uint32_t grid_waves, uint32_t overlap);
 /* The batch's scan partitioning and whether it came from tuning. */
-int ct_batch_tuning(const ct_batch* b, uint32_t* items, uint32_t* min_boxes, uint32_t* grid_waves, uint32_t* tuned);
+int ct_batch_tuning(const ct_batch* b, uint32_t* items, uint32_t* min_boxes, uint32_t* grid_waves,
+                    uint32_t* overlap, uint32_t* tuned);
 
 /*
  * ct_pop_read -- copy a run's state to the host (synchronises its stream).

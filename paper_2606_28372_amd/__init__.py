@@ -247,14 +247,21 @@ class Batch:
     def step(self, n_generations: int = 1, flags: int = CT_STEP_GRAPH):
         _lib.check(_lib.load().ct_batch_step(self._h, n_generations, flags, _stream()))
 
-    def autotune(self, force: bool = False):
-        """One generation that also picks the repair scans' work partitioning (ct_batch_autotune)."""
-        _lib.check(_lib.load().ct_batch_autotune(self._h, 1 if force else 0, _stream()))
+    def autotune(self, n_generations: int = 1, sample_every: int = 1, force: bool = False):
+        """n_generations generations, every sample_every-th of which also times the repair scans'
+        candidate work partitionings; the best total is kept (ct_batch_autotune)."""
+        _lib.check(_lib.load().ct_batch_autotune(self._h, n_generations, sample_every, 1 if force else 0,
+                                                 _stream()))
+
+    def set_tuning(self, items: int, min_boxes: int, grid_waves: int, overlap: int = 0):
+        """Install a scan partitioning (ct_batch_set_tuning)."""
+        _lib.check(_lib.load().ct_batch_set_tuning(self._h, items, min_boxes, grid_waves, overlap))
 
     def tuning(self) -> Dict[str, int]:
-        v = [ctypes.c_uint32() for _ in range(4)]
+        v = [ctypes.c_uint32() for _ in range(5)]
         _lib.check(_lib.load().ct_batch_tuning(self._h, *[ctypes.byref(x) for x in v]))
-        return {"items": v[0].value, "min_boxes": v[1].value, "grid_waves": v[2].value, "tuned": bool(v[3].value)}
+        return {"items": v[0].value, "min_boxes": v[1].value, "grid_waves": v[2].value,
+                "overlap": v[3].value, "tuned": bool(v[4].value)}
 
     def close(self):
         if self._h:

@@ -81,8 +81,9 @@ SIGNATURES = {
     "ct_batch_create": (_i32, [_P(_vp), _u32, _P(_vp)]),
     "ct_batch_step": (_i32, [_vp, _u32, _u32, _vp]),
     "ct_batch_free": (None, [_vp]),
-    "ct_batch_autotune": (_i32, [_vp, _u32, _vp]),
-    "ct_batch_tuning": (_i32, [_vp, _P(_u32), _P(_u32), _P(_u32), _P(_u32)]),
+    "ct_batch_autotune": (_i32, [_vp, _u32, _u32, _u32, _vp]),
+    "ct_batch_set_tuning": (_i32, [_vp, _u32, _u32, _u32, _u32]),
+    "ct_batch_tuning": (_i32, [_vp, _P(_u32), _P(_u32), _P(_u32), _P(_u32), _P(_u32)]),
     "ct_pop_snapshot": (_i32, [_vp, _vp, _P(_sz)]),
     "ct_pop_restore": (_i32, [_vp, _vp, _sz]),
     "ct_pop_free": (None, [_vp]),

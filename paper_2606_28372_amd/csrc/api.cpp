@@ -188,6 +188,8 @@ int batch_fill(ct_batch* b, const std::vector<ct_pop*>& pops) {
     b->n_ga = (uint32_t)setsC.size();
     b->max_pop = max_pop;
     // main repair pass: every run (its prep items are its individuals)
+    b->passA.fan = &b->fan;
+    b->passC.fan = &b->fan;
     b->passA.n_sets = n;
     b->passA.d_sets = b->d_setsA;
     b->passA.d_prep_off = b->d_ind_off;
@@ -210,7 +212,10 @@ int batch_fill(ct_batch* b, const std::vector<ct_pop*>& pops) {
         std::lock_guard<std::mutex> g(g_tune_mu);
         auto it = g_tune.find(b->shape);
         b->tuned = it != g_tune.end();
+        b->tune_cand.clear();
+        b->tune_ms.clear();
         b->passA.tune = b->tuned ? it->second : RepairTune{};
+        if (!b->tuned) b->passA.tune.overlap = n > 4 ? 1u : 0u;   // untuned groups: overlap many runs' classes
     }
     return CT_OK;
 }
@@ -219,7 +224,9 @@ int batch_build(const std::vector<ct_pop*>& pops, ct_batch** out, hipStream_t st
     (void)st;
     *out = nullptr;
     ct_batch* b = new ct_batch();
-    int rc = batch_fill(b, pops);
+    // one run has one scan class per pass: only groups get the auxiliary streams
+    int rc = pops.size() > 1 ? fan_create(&b->fan) : CT_OK;
+    if (!rc) rc = batch_fill(b, pops);
     if (rc) {
         batch_free(b);
         return rc;
@@ -252,6 +259,7 @@ void batch_free(ct_batch* b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     for (void* q : b->owned) (void)hipFree(q);
+    fan_destroy(&b->fan);
     delete b;
 }
 
@@ -682,12 +690,18 @@ int ct_batch_step(ct_batch* b, uint32_t n_generations, uint32_t flags, void* str
     return CT_OK;
 }
 
-int ct_batch_autotune(ct_batch* b, uint32_t force, void* stream) {
+int ct_batch_autotune(ct_batch* b, uint32_t n_generations, uint32_t sample_every, uint32_t force, void* stream) {
     if (!b) return ct_fail(CT_EINVAL, "ct_batch_autotune: null batch");
     hipStream_t st = as_stream(stream);
-    if (b->tuned && !force) return batch_generation(b, st);
-    int rc = batch_autotune_generation(b, st);
-    if (rc) return rc;
+    if (b->tuned && !force) {
+        for (uint32_t g = 0; g < n_generations; g++) {
+            int rc = batch_generation(b, st);
+            if (rc) return rc;
+        }
+        return CT_OK;
+    }
+    if (n_generations == 0) return CT_OK;
+    if (int rc = batch_autotune(b, n_generations, sample_every, st)) return rc;
     b->tuned = true;
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
@@ -699,11 +713,29 @@ int ct_batch_autotune(ct_batch* b, uint32_t force, void* stream) {
     return CT_OK;
 }
 
-int ct_batch_tuning(const ct_batch* b, uint32_t* items, uint32_t* min_boxes, uint32_t* grid_waves, uint32_t* tuned) {
+int ct_batch_set_tuning(ct_batch* b, uint32_t items, uint32_t min_boxes, uint32_t grid_waves, uint32_t overlap) {
+    if (!b) return ct_fail(CT_EINVAL, "ct_batch_set_tuning: null batch");
+    // items <= kRepairTargetWaves keeps every set's (candidate, part) winners within its slots
+    if (items < 64 || items > kRepairTargetWaves || min_boxes < 1 || min_boxes > (1u << 20) || grid_waves < 64 ||
+        grid_waves > (1u << 20) || overlap > 1)
+        return ct_fail(CT_EINVAL, "ct_batch_set_tuning: items in [64, 8192], min_boxes in [1, 2^20], "
+                                  "grid_waves in [64, 2^20], overlap 0 or 1");
+    b->passA.tune = RepairTune{items, min_boxes, grid_waves, overlap};
+    b->tuned = true;
+    b->tune_cand.clear();
+    b->tune_ms.clear();
+    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    return CT_OK;
+}
+
+int ct_batch_tuning(const ct_batch* b, uint32_t* items, uint32_t* min_boxes, uint32_t* grid_waves,
+                    uint32_t* overlap, uint32_t* tuned) {
     if (!b) return ct_fail(CT_EINVAL, "ct_batch_tuning: null batch");
     if (items) *items = b->passA.tune.items;
     if (min_boxes) *min_boxes = b->passA.tune.min_sub;
     if (grid_waves) *grid_waves = b->passA.tune.grid_waves;
+    if (overlap) *overlap = b->passA.tune.overlap;
     if (tuned) *tuned = b->tuned ? 1u : 0u;
     return CT_OK;
 }

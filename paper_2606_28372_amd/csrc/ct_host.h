@@ -117,11 +117,25 @@ struct RepairTune {
     uint32_t items = kRepairTargetWaves;
     uint32_t min_sub = 32;
     uint32_t grid_waves = 8192;
+    uint32_t overlap = 0;             // run independent scan classes on the fan's streams side by side
 };
+
+// Auxiliary streams (default priority) on which the independent scan classes of one pass run
+// side by side: fork after the plan, join before the finish.  Three lanes plus the launch stream
+// fit the four hardware queues a process gets by default.
+struct StreamFan {
+    static constexpr int kLanes = 3;
+    hipStream_t s[kLanes] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kLanes] = {};
+};
+int fan_create(StreamFan* f);
+void fan_destroy(StreamFan* f);
 
 // Host helpers to run a repair pass sequence over a device set array.
 struct RepairPasses {
     RepairTune tune;
+    StreamFan* fan = nullptr;               // nullable: run the scan classes one after another
     uint32_t n_sets = 0;
     const RepairSet* d_sets = nullptr;
     const uint32_t* d_prep_off = nullptr;   // [n_sets + 1] prefix of n
@@ -133,8 +147,10 @@ struct RepairPasses {
 };
 int repair_plan_alloc(RepairPlan& p, uint32_t n_sets, std::vector<void*>& owned);
 // prep + scan + finish (+ Hamming fallback for tiered metrics); `zero_counts` clears the
-// sets' counters with a kernel first (the step sequence clears them in its propose kernel).
-int launch_repair_passes(const RepairPasses& rp, bool zero_counts, hipStream_t st, bool count_tally = true);
+// sets' counters with a kernel first (the step sequence clears them in its selection kernel);
+// prep = false when the candidates were already listed (the step's propose kernel does it).
+int launch_repair_passes(const RepairPasses& rp, bool zero_counts, hipStream_t st, bool count_tally = true,
+                         bool prep = true);
 
 // ---------------------------------------------------------------------------
 // Optimiser runs
@@ -207,6 +223,9 @@ struct ct_batch {
     hipGraphExec_t exec = nullptr;
     std::string shape;                // signature of the group for the tuning cache
     bool tuned = false;
+    std::vector<RepairTune> tune_cand;   // autotuner: candidate partitionings
+    std::vector<double> tune_ms;         // their pass times summed over the tuning generations
+    StreamFan fan;
 };
 
 // Device bytes a run of this shape allocates (its buffers and its one-run batch).
@@ -215,8 +234,9 @@ uint64_t pop_footprint_bytes(uint32_t algo, uint32_t P, uint32_t D, uint32_t R, 
 // step.hip
 int pop_init_device(ct_pop* p, hipStream_t st);
 int batch_generation(ct_batch* b, hipStream_t st);
-// one generation in which the main repair pass is timed under each candidate partitioning
-int batch_autotune_generation(ct_batch* b, hipStream_t st);
+// n_generations generations; every sample_every-th sweeps the main repair pass over the candidate
+// partitionings, those in between decide the side-stream setting; installs the choice
+int batch_autotune(ct_batch* b, uint32_t n_generations, uint32_t sample_every, hipStream_t st);
 
 // api.cpp
 int batch_build(const std::vector<ct_pop*>& pops, ct_batch** out, hipStream_t st);

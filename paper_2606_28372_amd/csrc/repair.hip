@@ -633,16 +633,77 @@ void launch_scan_rw(const RepairPasses& rp, uint32_t which, hipStream_t st) {
 }
 
 template <int M>
-void launch_scan(const RepairPasses& rp, uint32_t mask, uint32_t which, hipStream_t st) {
-    if (mask & (1u << (M * 4 + 0))) launch_scan_rw<M, 1>(rp, which, st);
-    if (mask & (1u << (M * 4 + 1))) launch_scan_rw<M, 2>(rp, which, st);
-    if (mask & (1u << (M * 4 + 2))) launch_scan_rw<M, 4>(rp, which, st);
-    if (mask & (1u << (M * 4 + 3))) launch_scan_rw<M, 8>(rp, which, st);
+void launch_class_rw(const RepairPasses& rp, uint32_t rwi, uint32_t which, hipStream_t st) {
+    if (rwi == 0) launch_scan_rw<M, 1>(rp, which, st);
+    else if (rwi == 1) launch_scan_rw<M, 2>(rp, which, st);
+    else if (rwi == 2) launch_scan_rw<M, 4>(rp, which, st);
+    else launch_scan_rw<M, 8>(rp, which, st);
+}
+
+void launch_class(const RepairPasses& rp, uint32_t cls, uint32_t which, hipStream_t st) {
+    switch (cls / 4u) {
+    case CT_HAMMING: launch_class_rw<CT_HAMMING>(rp, cls % 4u, which, st); break;
+    case CT_INDEX_L1: launch_class_rw<CT_INDEX_L1>(rp, cls % 4u, which, st); break;
+    case CT_TIER_EUCLID: launch_class_rw<CT_TIER_EUCLID>(rp, cls % 4u, which, st); break;
+    case CT_TIER_RANDOM: launch_class_rw<CT_TIER_RANDOM>(rp, cls % 4u, which, st); break;
+    default: launch_class_rw<CT_HAM1_RANDOM>(rp, cls % 4u, which, st); break;
+    }
+}
+
+// Every scan class in `mask`: one after another on st, or, with a fan and more than one class,
+// each on an auxiliary stream forked from st and joined back into it (the classes touch disjoint
+// sets, so they may overlap).
+int launch_scans(const RepairPasses& rp, uint32_t mask, uint32_t which, hipStream_t st) {
+    StreamFan* f = rp.fan;
+    if (!f || !f->fork || !rp.tune.overlap || __builtin_popcount(mask) < 2) {
+        for (uint32_t cls = 0; cls < kNumClasses; ++cls)
+            if (mask & (1u << cls)) launch_class(rp, cls, which, st);
+        return CT_OK;
+    }
+    CT_HIP(hipEventRecord(f->fork, st));
+    uint32_t used = 0, k = 0;
+    for (uint32_t cls = 0; cls < kNumClasses; ++cls) {
+        if (!(mask & (1u << cls))) continue;
+        const uint32_t l = k++ % StreamFan::kLanes;
+        if (!(used & (1u << l))) {
+            CT_HIP(hipStreamWaitEvent(f->s[l], f->fork, 0));
+            used |= 1u << l;
+        }
+        launch_class(rp, cls, which, f->s[l]);
+    }
+    for (uint32_t l = 0; l < (uint32_t)StreamFan::kLanes; ++l) {
+        if (!(used & (1u << l))) continue;
+        CT_HIP(hipEventRecord(f->join[l], f->s[l]));
+        CT_HIP(hipStreamWaitEvent(st, f->join[l], 0));
+    }
+    return CT_OK;
 }
 
 uint32_t finish_grid(uint32_t n) { return std::max<uint32_t>(1, std::min<uint32_t>((n + 3) / 4, 2048)); }
 
 }  // namespace
+
+int fan_create(StreamFan* f) {
+    // the fork and join events order work of one device: a device-scope release is enough
+    const unsigned flags = hipEventDisableTiming | hipEventReleaseToDevice;
+    for (int l = 0; l < StreamFan::kLanes; ++l) {
+        CT_HIP(hipStreamCreateWithFlags(&f->s[l], hipStreamNonBlocking));
+        CT_HIP(hipEventCreateWithFlags(&f->join[l], flags));
+    }
+    CT_HIP(hipEventCreateWithFlags(&f->fork, flags));
+    return CT_OK;
+}
+
+void fan_destroy(StreamFan* f) {
+    for (int l = 0; l < StreamFan::kLanes; ++l) {
+        if (f->s[l]) (void)hipStreamDestroy(f->s[l]);
+        if (f->join[l]) (void)hipEventDestroy(f->join[l]);
+        f->s[l] = nullptr;
+        f->join[l] = nullptr;
+    }
+    if (f->fork) (void)hipEventDestroy(f->fork);
+    f->fork = nullptr;
+}
 
 int repair_plan_alloc(RepairPlan& p, uint32_t n_sets, std::vector<void*>& owned) {
     if (n_sets > kMaxSets) return ct_fail(CT_EINVAL, "repair: at most 4096 candidate sets per launch");
@@ -657,13 +718,13 @@ int repair_plan_alloc(RepairPlan& p, uint32_t n_sets, std::vector<void*>& owned)
     return CT_OK;
 }
 
-int launch_repair_passes(const RepairPasses& rp, bool zero_counts, hipStream_t st, bool count_tally) {
+int launch_repair_passes(const RepairPasses& rp, bool zero_counts, hipStream_t st, bool count_tally, bool prep) {
     if (rp.n_sets == 0 || rp.total_n == 0) return CT_OK;
     if (zero_counts) {
         ProfScope ps_("k_repair_zero", st);
         hipLaunchKernelGGL(k_repair_zero, dim3((rp.n_sets + 255) / 256), dim3(256), 0, st, rp.d_sets, rp.n_sets);
     }
-    {
+    if (prep) {
         ProfScope ps_("k_repair_prep", st);
         const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>((rp.total_n + kBlock - 1) / kBlock, 4096));
         hipLaunchKernelGGL(k_repair_prep, dim3(g), dim3(kBlock), 0, st, rp.d_sets, rp.n_sets, rp.d_prep_off);
@@ -673,11 +734,7 @@ int launch_repair_passes(const RepairPasses& rp, bool zero_counts, hipStream_t s
         hipLaunchKernelGGL(k_repair_plan, dim3(1), dim3(64), 0, st, rp.d_sets, rp.n_sets, 0u, rp.plan, rp.class_mask,
                            rp.tune.items, rp.tune.min_sub);
     }
-    launch_scan<CT_HAMMING>(rp, rp.class_mask, 0, st);
-    launch_scan<CT_INDEX_L1>(rp, rp.class_mask, 0, st);
-    launch_scan<CT_TIER_EUCLID>(rp, rp.class_mask, 0, st);
-    launch_scan<CT_TIER_RANDOM>(rp, rp.class_mask, 0, st);
-    launch_scan<CT_HAM1_RANDOM>(rp, rp.class_mask, 0, st);
+    if (int rc = launch_scans(rp, rp.class_mask, 0, st)) return rc;
     {
         ProfScope ps_("k_repair_finish", st);
         hipLaunchKernelGGL(k_repair_finish, dim3(finish_grid(rp.total_n)), dim3(kBlock), 0, st, rp.d_sets, rp.n_sets,
@@ -689,7 +746,7 @@ int launch_repair_passes(const RepairPasses& rp, bool zero_counts, hipStream_t s
             hipLaunchKernelGGL(k_repair_plan, dim3(1), dim3(64), 0, st, rp.d_sets, rp.n_sets, 1u, rp.plan,
                                rp.fb_class_mask, rp.tune.items, rp.tune.min_sub);
         }
-        launch_scan<CT_HAMMING>(rp, rp.fb_class_mask, 1, st);
+        if (int rc = launch_scans(rp, rp.fb_class_mask, 1, st)) return rc;
         {
             ProfScope ps_("k_repair_finish", st);
             hipLaunchKernelGGL(k_repair_finish, dim3(finish_grid(rp.total_n)), dim3(kBlock), 0, st, rp.d_sets,

@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 
 #include "ct_host.h"
 
@@ -135,6 +136,7 @@ __global__ __launch_bounds__(kSelBlock) void k_init_finish(PopDev p) {
     for (uint32_t i = threadIdx.x; i < p.P; i += blockDim.x)
         m = min(m, p.algo == CT_PSO ? (((uint64_t)ford(p.f_pb[i]) << 32) | i) : best_key(p.f[i], p.pos[i]));
     m = block_min_u64(m);
+    if (threadIdx.x < 4) p.rcount[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
         p.state[0] = 0;
         p.state[1] = 0;
@@ -167,7 +169,7 @@ __device__ __forceinline__ void sort3(uint32_t* e, uint32_t n) {
         }
 }
 
-__device__ void de_propose(const PopDev& p, uint32_t i, uint32_t g) {
+__device__ Row de_propose(const PopDev& p, uint32_t i, uint32_t g) {
     U4 o = ct_philox(p.seed, i, g, (uint32_t)PUR_DE_PICK << 24, 0);
     uint32_t ex[3] = {i, 0, 0};
     const uint32_t r1 = pick_excl(o.x, p.P, ex, 1);
@@ -184,27 +186,39 @@ __device__ void de_propose(const PopDev& p, uint32_t i, uint32_t g) {
     valid_row(p, p.pos[r2], a);
     valid_row(p, p.pos[r3], b);
     u = x;
-    U4 cr{0, 0, 0, 0};
-    for (uint32_t j = 0; j < p.D; ++j) {
-        const int64_t num = (int64_t)base.digit(j) * 65536 +
-                            (int64_t)p.F_q16 * ((int64_t)a.digit(j) - (int64_t)b.digit(j)) + 32768;
-        int64_t m = num >> 16;                    // floor
-        const int64_t hi = (int64_t)p.S->radix[j] - 1;
-        m = m < 0 ? 0 : (m > hi ? hi : m);
-        if ((j & 3u) == 0) cr = ct_philox(p.seed, i, g, ((uint32_t)PUR_DE_CR << 24) | (j >> 2), 0);
-        const uint32_t cu = (j & 3u) == 0 ? cr.x : (j & 3u) == 1 ? cr.y : (j & 3u) == 2 ? cr.z : cr.w;
-        if ((uint64_t)cu < p.CR_q32 || j == jr) u.set(j, (uint32_t)m);
+    // words of 4 digits, one Philox block per word (draw t of block j/4 decides digit j); both
+    // loops unrolled so every digit index is a compile-time constant and the rows stay in registers
+#pragma unroll
+    for (uint32_t q = 0; q < CT_DMAX / 4; ++q) {
+        if (q * 4u >= p.D) break;
+        const U4 cr = ct_philox(p.seed, i, g, ((uint32_t)PUR_DE_CR << 24) | q, 0);
+#pragma unroll
+        for (uint32_t t = 0; t < 4; ++t) {
+            const uint32_t j = q * 4u + t;
+            if (j < p.D) {
+                const int64_t num = (int64_t)base.digit(j) * 65536 +
+                                    (int64_t)p.F_q16 * ((int64_t)a.digit(j) - (int64_t)b.digit(j)) + 32768;
+                int64_t m = num >> 16;            // floor
+                const int64_t hi = (int64_t)p.S->radix[j] - 1;
+                m = m < 0 ? 0 : (m > hi ? hi : m);
+                const uint32_t cu = t == 0 ? cr.x : t == 1 ? cr.y : t == 2 ? cr.z : cr.w;
+                if ((uint64_t)cu < p.CR_q32 || j == jr) u.set(j, (uint32_t)m);
+            }
+        }
     }
     row_store(u, p.trial + (uint64_t)i * p.R, p.R);
+    return u;
 }
 
-__device__ void pso_propose(const PopDev& p, uint32_t i, uint32_t g) {
+__device__ Row pso_propose(const PopDev& p, uint32_t i, uint32_t g) {
     const uint32_t gi = p.state[2];
     const int64_t xmax = (int64_t)p.M * 65536 - 1;
     Row c;
 #pragma unroll
     for (int q = 0; q < CT_DMAX / 4; ++q) c.w[q] = 0;
-    for (uint32_t j = 0; j < p.D; ++j) {
+#pragma unroll
+    for (uint32_t j = 0; j < CT_DMAX; ++j) {
+        if (j >= p.D) break;
         U4 o = ct_philox(p.seed, i, g, ((uint32_t)PUR_PSO_R << 24) | j, 0);
         const int64_t r1 = o.x >> 16, r2 = o.y >> 16;
         const uint64_t k = (uint64_t)i * p.D + j;
@@ -220,6 +234,7 @@ __device__ void pso_propose(const PopDev& p, uint32_t i, uint32_t g) {
         c.set(j, d < p.S->radix[j] ? d : p.S->radix[j] - 1u);
     }
     row_store(c, p.trial + (uint64_t)i * p.R, p.R);
+    return c;
 }
 
 __device__ __forceinline__ uint32_t beta_rank(const PopDev& p, uint32_t u) {
@@ -232,7 +247,7 @@ __device__ __forceinline__ uint32_t beta_rank(const PopDev& p, uint32_t u) {
 }
 
 // child i of pair i/2: A[:cut] + B[cut:] for even i, B[:cut] + A[cut:] for odd i
-__device__ void ga_propose(const PopDev& p, uint32_t i, uint32_t g) {
+__device__ Row ga_propose(const PopDev& p, uint32_t i, uint32_t g) {
     const uint32_t k = i >> 1;
     U4 o = ct_philox(p.seed, k, g, (uint32_t)PUR_GA_SEL << 24, 0);
     const uint32_t a = beta_rank(p, o.x), b = beta_rank(p, o.y);
@@ -240,32 +255,61 @@ __device__ void ga_propose(const PopDev& p, uint32_t i, uint32_t g) {
     Row A, B;
     valid_row(p, p.sorted[a], A);
     valid_row(p, p.sorted[b], B);
-    Row c = (i & 1u) ? B : A;
-    const Row& tail = (i & 1u) ? A : B;
-    for (uint32_t j = cut; j < p.D; ++j) c.set(j, tail.digit(j));
+    // word-wise selects keep both rows in registers (a reference picked at run time would not)
+    const bool odd = (i & 1u) != 0;
+    Row c, tail;
+#pragma unroll
+    for (int q = 0; q < CT_DMAX / 4; ++q) {
+        c.w[q] = odd ? B.w[q] : A.w[q];
+        tail.w[q] = odd ? A.w[q] : B.w[q];
+    }
+#pragma unroll
+    for (uint32_t j = 1; j < CT_DMAX; ++j)
+        if (j >= cut && j < p.D) c.set(j, tail.digit(j));
     row_store(c, p.trial + (uint64_t)i * p.R, p.R);
     U4 m = ct_philox(p.seed, i, g, (uint32_t)PUR_GA_MUT << 24, 0);
     p.apply[i] = m.x < p.mut_thresh;
+    return c;
 }
 
+// What the main repair pass's prep step computes for a proposal -- its validity from the
+// bitmask, its position (or insertion point) from the rank directory, and its entry in the
+// list of candidates to repair -- done here while the row is still in registers.
+__device__ __forceinline__ void list_for_repair(const PopDev& p, const RepairSet& J, uint32_t i, const Row& u) {
+    const DevSpace& S = *p.S;
+    uint64_t L = 0;
+    bool dom = true;
+#pragma unroll
+    for (uint32_t j = 0; j < CT_DMAX; ++j) {
+        if (j >= p.D) break;
+        dom &= u.digit(j) < S.radix[j];
+        L += (uint64_t)u.digit(j) * S.stride[j];
+    }
+    if (!dom) L = ~0ull;
+    const bool valid = dom && bit_valid(S, L);
+    row_store(u, J.out_rows + (uint64_t)i * p.R, p.R);
+    J.out_pos[i] = valid ? (uint32_t)rank_dir(S, L) : 0xFFFFFFFFu;
+    if (!valid) {
+        const uint32_t k = atomicAdd(&J.count[0], 1u);
+        J.list[k] = i;
+        J.list_L[k] = L;
+    }
+}
+
+// Proposals of every run, one thread per individual, each listed for the main repair pass
+// (`sets`, one per run in run order).  The repair counters were cleared by the previous
+// generation's selection (or at creation), never by a memset node inside a captured graph.
 __global__ __launch_bounds__(kBlock) void k_propose(const PopDev* __restrict__ pops, uint32_t n,
-                                                    const uint32_t* __restrict__ ind_off) {
+                                                    const uint32_t* __restrict__ ind_off,
+                                                    const RepairSet* __restrict__ sets) {
     const uint32_t total = ind_off[n];
     for (uint32_t item = blockIdx.x * blockDim.x + threadIdx.x; item < total; item += gridDim.x * blockDim.x) {
         const uint32_t r = find_run(ind_off, n, item);
         const PopDev& p = pops[r];
         const uint32_t i = item - ind_off[r];
         const uint32_t g = p.state[0];
-        if (i == 0) {
-            // repair counters of this generation (no memset nodes inside captured graphs)
-            p.rcount[0] = 0;
-            p.rcount[1] = 0;
-            p.rcount[2] = 0;
-            p.rcount[3] = 0;
-        }
-        if (p.algo == CT_DE) de_propose(p, i, g);
-        else if (p.algo == CT_PSO) pso_propose(p, i, g);
-        else ga_propose(p, i, g);
+        const Row u = p.algo == CT_DE ? de_propose(p, i, g) : p.algo == CT_PSO ? pso_propose(p, i, g) : ga_propose(p, i, g);
+        list_for_repair(p, sets[r], i, u);
     }
 }
 
@@ -278,6 +322,29 @@ __global__ __launch_bounds__(kSelBlock) void k_ga_sort(const PopDev* __restrict_
     if (p.algo != CT_GA) return;
     uint32_t m = 1;
     while (m < p.P) m <<= 1;
+    if (m <= blockDim.x) {
+        // one key per thread: bitonic stages whose partner is in the same wave exchange through
+        // cross-lane shuffles; only partners 64 or more apart go through LDS and a barrier
+        const uint32_t i = threadIdx.x;
+        uint64_t v = i < p.P ? best_key(p.f[i], p.pos[i]) : ~0ull;
+        for (uint32_t k = 2; k <= m; k <<= 1) {
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                uint64_t o;
+                if (j >= 64) {
+                    key[i] = v;
+                    __syncthreads();
+                    o = key[i ^ j];
+                    __syncthreads();
+                } else {
+                    o = shfl_xor_u64(v, (int)j);
+                }
+                const bool keep_min = ((i & j) == 0) == ((i & k) == 0);
+                v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
+            }
+        }
+        if (i < p.P) p.sorted[i] = (uint32_t)v;
+        return;
+    }
     for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) key[i] = i < p.P ? best_key(p.f[i], p.pos[i]) : ~0ull;
     __syncthreads();
     for (uint32_t k = 2; k <= m; k <<= 1) {
@@ -404,6 +471,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select(const PopDev* __restrict__
     if (p.algo == CT_DE) de_select(p);
     else if (p.algo == CT_PSO) pso_select(p);
     else ga_select(p);
+    if (threadIdx.x < 4) p.rcount[threadIdx.x] = 0;      // repair counters of the next generation
 }
 
 }  // namespace
@@ -425,9 +493,9 @@ int batch_generation(ct_batch* b, hipStream_t st) {
     {
         ProfScope ps_("k_propose", st);
         const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>((b->total_ind + kBlock - 1) / kBlock, 4096));
-        hipLaunchKernelGGL(k_propose, dim3(g), dim3(kBlock), 0, st, b->d_pops, b->n, b->d_ind_off);
+        hipLaunchKernelGGL(k_propose, dim3(g), dim3(kBlock), 0, st, b->d_pops, b->n, b->d_ind_off, b->passA.d_sets);
     }
-    int rc = launch_repair_passes(b->passA, false, st);
+    int rc = launch_repair_passes(b->passA, false, st, true, false);
     if (rc) return rc;
     if (b->n_ga) {
         rc = launch_repair_passes(b->passC, false, st);
@@ -441,53 +509,127 @@ int batch_generation(ct_batch* b, hipStream_t st) {
     return CT_OK;
 }
 
-int batch_autotune_generation(ct_batch* b, hipStream_t st) {
-    if (b->n == 0) return CT_OK;
+namespace {
+
+// Sweep of one tuning generation: the main repair pass reads the proposals and writes only its
+// outputs, lists and counters (the counters are cleared first and the scan tally is left alone),
+// so it can run once per candidate partitioning with identical results; each candidate's time is
+// added to its total over the batch's tuning generations.
+int autotune_sweep(ct_batch* b, hipStream_t st) {
+    if (b->tune_cand.empty()) {
+        for (uint32_t ov = 0; ov <= (b->fan.fork ? 1u : 0u); ++ov)
+            for (uint32_t it : {2048u, 4096u, 8192u})
+                for (uint32_t ms : {8u, 16u, 32u, 64u})
+                    for (uint32_t gw : {4096u, 8192u}) b->tune_cand.push_back(RepairTune{it, ms, gw, ov});
+        b->tune_ms.assign(b->tune_cand.size(), 0.0);
+    }
+    const std::vector<RepairTune>& cand = b->tune_cand;
+    // The candidates run back to back with one wait at the end, so that each is timed with the
+    // launch queue full, as in the generations that follow.  A pass on side streams delays the
+    // launches after its join, so each candidate's window holds the tail of the pass before it:
+    // candidates are grouped by that setting and every group starts after an untimed pass of
+    // its own kind.
+    std::vector<hipEvent_t> ev(2 * cand.size(), nullptr);
+    int rc = CT_OK;
+    for (hipEvent_t& e : ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess)
+            rc = ct_fail(CT_EDEVICE, "autotune: event create failed");
+    prof_suspend(true);
+    RepairPasses rp = b->passA;
+    for (size_t v = 0; v < cand.size() && !rc; ++v) {
+        rp.tune = cand[v];
+        if (v == 0 || cand[v].overlap != cand[v - 1].overlap) rc = launch_repair_passes(rp, true, st, false);
+        if (!rc && hipEventRecord(ev[2 * v], st) != hipSuccess) rc = ct_fail(CT_EDEVICE, "autotune: event record failed");
+        if (!rc) rc = launch_repair_passes(rp, true, st, false);
+        if (!rc && hipEventRecord(ev[2 * v + 1], st) != hipSuccess)
+            rc = ct_fail(CT_EDEVICE, "autotune: event record failed");
+    }
+    if (!rc && hipEventSynchronize(ev.back()) != hipSuccess) rc = ct_fail(CT_EDEVICE, "autotune: event wait failed");
+    for (size_t v = 0; v < cand.size() && !rc; ++v) {
+        float t = 0;
+        if (hipEventElapsedTime(&t, ev[2 * v], ev[2 * v + 1]) != hipSuccess) rc = ct_fail(CT_EDEVICE, "autotune: no timing");
+        b->tune_ms[v] += t;
+    }
+    prof_suspend(false);
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return rc;
+}
+
+// Candidate with the lowest sweep total among those with the given side-stream setting (-1: any).
+RepairTune sweep_best(const ct_batch* b, int overlap) {
+    size_t pick = b->tune_cand.size();
+    for (size_t v = 0; v < b->tune_cand.size(); ++v)
+        if ((overlap < 0 || b->tune_cand[v].overlap == (uint32_t)overlap) &&
+            (pick == b->tune_cand.size() || b->tune_ms[v] < b->tune_ms[pick]))
+            pick = v;
+    return pick < b->tune_cand.size() ? b->tune_cand[pick] : b->passA.tune;
+}
+
+// One generation whose main repair pass is first swept over every candidate partitioning.
+int autotune_generation(ct_batch* b, hipStream_t st) {
     if (b->n_ga) hipLaunchKernelGGL(k_ga_sort, dim3(b->n), dim3(kSelBlock), 0, st, b->d_pops, b->n);
     {
         const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>((b->total_ind + kBlock - 1) / kBlock, 4096));
-        hipLaunchKernelGGL(k_propose, dim3(g), dim3(kBlock), 0, st, b->d_pops, b->n, b->d_ind_off);
+        hipLaunchKernelGGL(k_propose, dim3(g), dim3(kBlock), 0, st, b->d_pops, b->n, b->d_ind_off, b->passA.d_sets);
     }
     CT_HIP(hipGetLastError());
-    // The main repair pass reads the proposals and writes only its outputs, lists and counters (the
-    // counters are cleared first and the scan tally is left alone), so it can run once per candidate
-    // partitioning with identical results; the fastest one is kept.
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    CT_HIP(hipEventCreate(&e0));
-    CT_HIP(hipEventCreate(&e1));
-    prof_suspend(true);
-    RepairPasses rp = b->passA;
-    int rc = launch_repair_passes(rp, true, st, false);     // warm the caches
-    float best = 3.0e38f;
-    RepairTune choice = b->passA.tune;
-    const uint32_t items[] = {2048, 4096, 8192};
-    const uint32_t min_sub[] = {8, 16, 32, 64};
-    const uint32_t grid[] = {4096, 8192};
-    for (uint32_t it : items)
-        for (uint32_t ms : min_sub)
-            for (uint32_t gw : grid) {
-                if (rc) break;
-                rp.tune = RepairTune{it, ms, gw};
-                (void)hipEventRecord(e0, st);
-                rc = launch_repair_passes(rp, true, st, false);
-                (void)hipEventRecord(e1, st);
-                if (hipEventSynchronize(e1) != hipSuccess) rc = ct_fail(CT_EDEVICE, "autotune: event wait failed");
-                float t = 0;
-                if (!rc && hipEventElapsedTime(&t, e0, e1) == hipSuccess && t < best) {
-                    best = t;
-                    choice = rp.tune;
-                }
-            }
-    prof_suspend(false);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    int rc = autotune_sweep(b, st);
     if (rc) return rc;
-    b->passA.tune = choice;
-    // the generation's own pass, with the chosen partitioning, counting its scans
+    b->passA.tune = sweep_best(b, -1);
+    // the generation's own pass, counting its scans
     if ((rc = launch_repair_passes(b->passA, true, st, true))) return rc;
     if (b->n_ga && (rc = launch_repair_passes(b->passC, false, st))) return rc;
     hipLaunchKernelGGL(k_select, dim3(b->n), dim3(kSelBlock), 0, st, b->d_pops, b->n);
     CT_HIP(hipGetLastError());
+    return CT_OK;
+}
+
+}  // namespace
+
+int batch_autotune(ct_batch* b, uint32_t n_generations, uint32_t sample_every, hipStream_t st) {
+    if (b->n == 0 || n_generations == 0) return CT_OK;
+    const uint32_t every = std::max<uint32_t>(sample_every, 1);
+    b->tune_cand.clear();
+    b->tune_ms.clear();
+    // The sweep times the main pass alone on the device, but side streams cost more than that: the
+    // host spends longer issuing a generation that forks and joins streams, and the device waits
+    // at the joins.  That setting is therefore decided on whole generations by the host clock:
+    // the generations between sweeps run in blocks of kBlockGens with one setting (the best
+    // candidate of that setting so far), alternating, each block between two stream waits; the
+    // setting with the lower mean block time wins.
+    constexpr uint32_t kBlockGens = 4;
+    double block_ms[2] = {0, 0};
+    uint32_t block_n[2] = {0, 0};
+    int rc = CT_OK;
+    uint32_t blocks = 0;
+    for (uint32_t g = 0; g < n_generations && !rc;) {
+        if (g % every == 0) {
+            rc = autotune_generation(b, st);
+            ++g;
+            continue;
+        }
+        const uint32_t k = std::min(every - g % every, n_generations - g);   // generations before the next sweep
+        if (!b->fan.fork || k < kBlockGens) {
+            for (uint32_t i = 0; i < k && !rc; ++i) rc = batch_generation(b, st);
+            g += k;
+            continue;
+        }
+        const uint32_t ov = blocks++ & 1u;
+        b->passA.tune = sweep_best(b, (int)ov);
+        if (hipStreamSynchronize(st) != hipSuccess) { rc = ct_fail(CT_EDEVICE, "autotune: stream wait failed"); break; }
+        const auto t0 = std::chrono::steady_clock::now();
+        for (uint32_t i = 0; i < kBlockGens && !rc; ++i) rc = batch_generation(b, st);
+        if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = ct_fail(CT_EDEVICE, "autotune: stream wait failed");
+        block_ms[ov] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        block_n[ov] += 1;
+        g += kBlockGens;
+    }
+    if (rc) return rc;
+    if (block_n[0] && block_n[1])
+        b->passA.tune = sweep_best(b, block_ms[1] / block_n[1] < block_ms[0] / block_n[0] ? 1 : 0);
+    else
+        b->passA.tune = sweep_best(b, -1);
     return CT_OK;
 }
 

@@ -83,3 +83,12 @@ def test_server_needs_device_and_objective():
         with pytest.raises(CtError) as e:
             Server(lambda rid, nv: None, hbm_budget=1 << 20)
         assert e.value.code == _lib.CT_EDEVICE
+
+
+def test_batch_tuning_null_handles():
+    """The tuning entry points reject a null batch before touching the device."""
+    from paper_2606_28372_amd import _lib
+    lib = _lib.load()
+    assert lib.ct_batch_set_tuning(None, 4096, 16, 8192, 0) == _lib.CT_EINVAL
+    assert lib.ct_batch_tuning(None, None, None, None, None, None) == _lib.CT_EINVAL
+    assert lib.ct_batch_autotune(None, 1, 1, 0, None) == _lib.CT_EINVAL

@@ -140,12 +140,12 @@ def test_autotuned_batch_equals_plain(spaces):
     t = torch()
     plain, tuned = make_runs(t, spaces), make_runs(t, spaces)
     b = Batch(tuned)
-    b.autotune(force=True)
+    b.autotune(11, sample_every=5, force=True)    # sweeps at 0, 5 and 10; a timed block of each stream setting between
     tn = b.tuning()
     say(f"[gpu_batched] tuning {tn}")
     assert tn["tuned"] and tn["items"] in (2048, 4096, 8192) and tn["min_boxes"] in (8, 16, 32, 64)
-    assert tn["grid_waves"] in (4096, 8192)
-    step_many(plain, 1)
+    assert tn["grid_waves"] in (4096, 8192) and tn["overlap"] in (0, 1)
+    step_many(plain, 11)
     t.cuda.synchronize()
     for x, y in zip(plain, tuned):
         assert x.snapshot() == y.snapshot()
@@ -157,4 +157,38 @@ def test_autotuned_batch_equals_plain(spaces):
     again = Batch(make_runs(t, spaces))
     assert again.tuning() == tn
     again.close()
+    b.close()
+
+
+@pytest.mark.parametrize("tune", [(64, 1, 64, 0), (2048, 8, 4096, 1), (8192, 64, 8192, 1), (8192, 1024, 512, 0)])
+def test_set_tuning_equals_plain(spaces, tune):
+    """Any installed scan partitioning (few or many items per launch, small or large boxes per
+    part, small or large grids, scan classes on side streams or not) gives the plain results,
+    both launched directly and replayed from a graph."""
+    from paper_2606_28372_amd import Batch, CT_STEP_BATCHED, CT_STEP_GRAPH, step_many
+    t = torch()
+    plain, tuned = make_runs(t, spaces), make_runs(t, spaces)
+    b = Batch(tuned)
+    b.set_tuning(*tune)
+    got = b.tuning()
+    assert (got["items"], got["min_boxes"], got["grid_waves"], got["overlap"]) == tune and got["tuned"]
+    say(f"[gpu_batched] set_tuning {tune}")
+    b.step(3, CT_STEP_BATCHED)
+    b.step(3, CT_STEP_GRAPH)
+    step_many(plain, 6)
+    t.cuda.synchronize()
+    for k, (x, y) in enumerate(zip(plain, tuned)):
+        assert x.snapshot() == y.snapshot(), f"run {k} differs under {tune}"
+    b.close()
+
+
+def test_set_tuning_rejects_out_of_range(spaces):
+    from paper_2606_28372_amd import Batch, CtError
+    t = torch()
+    b = Batch(make_runs(t, spaces))
+    before = b.tuning()
+    for bad in [(63, 16, 4096, 0), (8193, 16, 4096, 0), (4096, 0, 4096, 0), (4096, 16, 32, 0), (4096, 16, 4096, 2)]:
+        with pytest.raises(CtError):
+            b.set_tuning(*bad)
+    assert b.tuning() == before
     b.close()
