@@ -247,35 +247,44 @@ int ct_batch_create(ct_pop* const* pops, uint32_t n_pops, ct_batch** out);
 int ct_batch_step(ct_batch* b, uint32_t n_generations, uint32_t flags, void* stream);
 void ct_batch_free(ct_batch* b);
 
+/* How the repair scan classes of one pass are launched (results never depend on it). */
+#define CT_SCAN_SERIAL 0u          /* one launch per (metric, row width), one after another */
+#define CT_SCAN_STREAMS 1u         /* those launches side by side on auxiliary streams */
+#define CT_SCAN_FUSED 2u           /* the scanned metrics of one row width in a single launch */
+
 /*
  * ct_batch_autotune -- advance the batch by exactly n_generations generations,
- * choosing the work partitioning of its repair scans (candidates x list parts
- * per launch, least 64-row boxes per part, waves in the grid, independent scan
- * classes on side streams or not).  Generations 0, sample_every,
- * 2 * sample_every, ... (sample_every 0 counts as 1) are tuning generations:
+ * choosing the work partitioning of its repair scans: items per class launch
+ * (candidates x list parts), least 64-row boxes per part, waves in the grid,
+ * and the launch mode (CT_SCAN_*).  Generations 0, sample_every,
+ * 2 * sample_every, ... (sample_every 0 counts as 1) are sweep generations:
  * their main repair pass also runs under every candidate partitioning, back to
- * back, each one timed; the candidate with the lowest time summed over the
- * tuning generations is kept.  The repair load changes as the populations
- * converge, so samples spread over the run choose better than the first
- * generations alone.  Every candidate computes the same result, so the runs'
- * state advances exactly as with ct_batch_step.  The choice is kept for the
- * batch and, process-wide, for later batches of the same shape (per run:
- * algorithm, row bytes, parameters, log2 |V|, log2 P); when the shape was
- * tuned before and force is 0 these are plain generations.  Synchronises the
- * stream at each tuning generation.
+ * back, each one timed on the device; totals add up over the sweeps.  Streams
+ * also cost host time and waits outside the pass, so CT_SCAN_STREAMS is decided
+ * on whole generations: the generations between sweeps run in blocks of four
+ * with the best candidate with and the best without streams, alternating,
+ * timed by the host clock; the lower mean block time wins (with no room for
+ * blocks, the lowest sweep total wins).  The repair load changes as the
+ * populations converge, so sweeps spread over a run choose better than its
+ * first generations alone.  Every candidate computes the same result, so the
+ * runs' state advances exactly as with ct_batch_step.  The choice is kept for
+ * the batch and, process-wide, for later batches of the same shape (per run:
+ * algorithm, row bytes, parameters, log2 |V|, log2 P); when the shape was tuned
+ * before and force is 0 these are plain generations.  Synchronises the stream
+ * at each sweep and block.
  */
 int ct_batch_autotune(ct_batch* b, uint32_t n_generations, uint32_t sample_every, uint32_t force, void* stream);
 /*
  * ct_batch_set_tuning -- install a scan partitioning for this batch (one saved
  * from ct_batch_tuning, say): items in [64, 8192], min_boxes in [1, 2^20],
- * grid_waves in [64, 2^20], overlap 0 or 1; CT_EINVAL otherwise.  Results do
- * not depend on it.  The batch counts as tuned; the process-wide cache is left
- * alone.
+ * grid_waves in [64, 2^20], mode one of CT_SCAN_*; CT_EINVAL otherwise.
+ * Results do not depend on it.  The batch counts as tuned; the process-wide
+ * cache is left alone.  CT_SCAN_STREAMS on a batch of one run launches serially.
  */
-int ct_batch_set_tuning(ct_batch* b, uint32_t items, uint32_t min_boxes, uint32_t grid_waves, uint32_t overlap);
+int ct_batch_set_tuning(ct_batch* b, uint32_t items, uint32_t min_boxes, uint32_t grid_waves, uint32_t mode);
 /* The batch's scan partitioning and whether it came from tuning. */
 int ct_batch_tuning(const ct_batch* b, uint32_t* items, uint32_t* min_boxes, uint32_t* grid_waves,
-                    uint32_t* overlap, uint32_t* tuned);
+                    uint32_t* mode, uint32_t* tuned);
 
 /*
  * ct_pop_read -- copy a run's state to the host (synchronises its stream).

@@ -19,12 +19,13 @@ from typing import Dict, List, Optional, Sequence, Tuple
 import numpy as np
 
 from . import _lib
-from ._lib import (CT_DE, CT_GA, CT_HAM1_RANDOM, CT_HAMMING, CT_INDEX_L1, CT_PSO, CT_STEP_BATCHED,  # noqa: F401
-                   CT_STEP_GRAPH, CT_STEP_PLAIN, CT_TIER_EUCLID, CT_TIER_RANDOM, CtError, ct_pop_params)
+from ._lib import (CT_DE, CT_GA, CT_HAM1_RANDOM, CT_HAMMING, CT_INDEX_L1, CT_PSO, CT_SCAN_FUSED,  # noqa: F401
+                   CT_SCAN_SERIAL, CT_SCAN_STREAMS, CT_STEP_BATCHED, CT_STEP_GRAPH, CT_STEP_PLAIN, CT_TIER_EUCLID,
+                   CT_TIER_RANDOM, CtError, ct_pop_params)
 
 __all__ = ["Space", "Pop", "Batch", "Server", "compile_constraints", "step_many", "CtError", "CT_HAMMING", "CT_INDEX_L1",
            "CT_TIER_EUCLID", "CT_TIER_RANDOM", "CT_HAM1_RANDOM", "CT_DE", "CT_PSO", "CT_GA",
-           "CT_STEP_PLAIN", "CT_STEP_BATCHED", "CT_STEP_GRAPH"]
+           "CT_STEP_PLAIN", "CT_STEP_BATCHED", "CT_STEP_GRAPH", "CT_SCAN_SERIAL", "CT_SCAN_STREAMS", "CT_SCAN_FUSED"]
 
 
 def _torch():
@@ -253,15 +254,15 @@ class Batch:
         _lib.check(_lib.load().ct_batch_autotune(self._h, n_generations, sample_every, 1 if force else 0,
                                                  _stream()))
 
-    def set_tuning(self, items: int, min_boxes: int, grid_waves: int, overlap: int = 0):
-        """Install a scan partitioning (ct_batch_set_tuning)."""
-        _lib.check(_lib.load().ct_batch_set_tuning(self._h, items, min_boxes, grid_waves, overlap))
+    def set_tuning(self, items: int, min_boxes: int, grid_waves: int, mode: int = 0):
+        """Install a scan partitioning; mode is one of CT_SCAN_* (ct_batch_set_tuning)."""
+        _lib.check(_lib.load().ct_batch_set_tuning(self._h, items, min_boxes, grid_waves, mode))
 
     def tuning(self) -> Dict[str, int]:
         v = [ctypes.c_uint32() for _ in range(5)]
         _lib.check(_lib.load().ct_batch_tuning(self._h, *[ctypes.byref(x) for x in v]))
         return {"items": v[0].value, "min_boxes": v[1].value, "grid_waves": v[2].value,
-                "overlap": v[3].value, "tuned": bool(v[4].value)}
+                "mode": v[3].value, "tuned": bool(v[4].value)}
 
     def close(self):
         if self._h:

@@ -18,6 +18,7 @@ STATUS = {CT_EINVAL: "CT_EINVAL", CT_ENOMEM: "CT_ENOMEM", CT_EOVERFLOW: "CT_EOVE
 CT_HAMMING, CT_INDEX_L1, CT_TIER_EUCLID, CT_TIER_RANDOM, CT_HAM1_RANDOM = 0, 1, 2, 3, 4
 CT_DE, CT_PSO, CT_GA = 0, 1, 2
 CT_STEP_PLAIN, CT_STEP_BATCHED, CT_STEP_GRAPH = 0, 1, 2
+CT_SCAN_SERIAL, CT_SCAN_STREAMS, CT_SCAN_FUSED = 0, 1, 2
 
 
 class CtError(RuntimeError):

@@ -215,7 +215,7 @@ int batch_fill(ct_batch* b, const std::vector<ct_pop*>& pops) {
         b->tune_cand.clear();
         b->tune_ms.clear();
         b->passA.tune = b->tuned ? it->second : RepairTune{};
-        if (!b->tuned) b->passA.tune.overlap = n > 4 ? 1u : 0u;   // untuned groups: overlap many runs' classes
+        if (!b->tuned) b->passA.tune.mode = kScanFused;
     }
     return CT_OK;
 }
@@ -713,14 +713,14 @@ int ct_batch_autotune(ct_batch* b, uint32_t n_generations, uint32_t sample_every
     return CT_OK;
 }
 
-int ct_batch_set_tuning(ct_batch* b, uint32_t items, uint32_t min_boxes, uint32_t grid_waves, uint32_t overlap) {
+int ct_batch_set_tuning(ct_batch* b, uint32_t items, uint32_t min_boxes, uint32_t grid_waves, uint32_t mode) {
     if (!b) return ct_fail(CT_EINVAL, "ct_batch_set_tuning: null batch");
     // items <= kRepairTargetWaves keeps every set's (candidate, part) winners within its slots
     if (items < 64 || items > kRepairTargetWaves || min_boxes < 1 || min_boxes > (1u << 20) || grid_waves < 64 ||
-        grid_waves > (1u << 20) || overlap > 1)
+        grid_waves > (1u << 20) || mode > CT_SCAN_FUSED)
         return ct_fail(CT_EINVAL, "ct_batch_set_tuning: items in [64, 8192], min_boxes in [1, 2^20], "
-                                  "grid_waves in [64, 2^20], overlap 0 or 1");
-    b->passA.tune = RepairTune{items, min_boxes, grid_waves, overlap};
+                                  "grid_waves in [64, 2^20], mode CT_SCAN_SERIAL, _STREAMS or _FUSED");
+    b->passA.tune = RepairTune{items, min_boxes, grid_waves, mode};
     b->tuned = true;
     b->tune_cand.clear();
     b->tune_ms.clear();
@@ -730,12 +730,12 @@ int ct_batch_set_tuning(ct_batch* b, uint32_t items, uint32_t min_boxes, uint32_
 }
 
 int ct_batch_tuning(const ct_batch* b, uint32_t* items, uint32_t* min_boxes, uint32_t* grid_waves,
-                    uint32_t* overlap, uint32_t* tuned) {
+                    uint32_t* mode, uint32_t* tuned) {
     if (!b) return ct_fail(CT_EINVAL, "ct_batch_tuning: null batch");
     if (items) *items = b->passA.tune.items;
     if (min_boxes) *min_boxes = b->passA.tune.min_sub;
     if (grid_waves) *grid_waves = b->passA.tune.grid_waves;
-    if (overlap) *overlap = b->passA.tune.overlap;
+    if (mode) *mode = b->passA.tune.mode;
     if (tuned) *tuned = b->tuned ? 1u : 0u;
     return CT_OK;
 }

@@ -111,13 +111,18 @@ struct RepairPlan {
 
 constexpr uint32_t kRepairTargetWaves = 8192;   // scan items per pass (also the per-set slot minimum)
 
+// How the scan classes of one pass are launched: one after another, side by side on the fan's
+// streams, or the scanned metrics of one row width together in one launch.
+constexpr uint32_t kScanSerial = CT_SCAN_SERIAL, kScanStreams = CT_SCAN_STREAMS, kScanFused = CT_SCAN_FUSED;
+
 // Work partitioning of the scan launches (chosen by the autotuner; results do not depend on it):
-// items per launch (candidates x parts), least 64-row boxes per part, waves in the grid.
+// items per class (candidates x parts), least 64-row boxes per part, waves in the grid, and how
+// the classes are launched.
 struct RepairTune {
     uint32_t items = kRepairTargetWaves;
     uint32_t min_sub = 32;
     uint32_t grid_waves = 8192;
-    uint32_t overlap = 0;             // run independent scan classes on the fan's streams side by side
+    uint32_t mode = kScanSerial;
 };
 
 // Auxiliary streams (default priority) on which the independent scan classes of one pass run

@@ -550,8 +550,17 @@ __global__ __launch_bounds__(64) void k_repair_plan(const RepairSet* __restrict_
     }
 }
 
+// The scan is a latency chain per wave (candidate -> tables -> seed rows -> boxes), so waves in
+// flight matter more than registers: left alone the compiler spends up to 180 VGPRs on the tiered
+// metrics of 16-byte rows (two waves per SIMD); held to five waves per SIMD (at most 102 VGPRs, a
+// few spilled bytes) the 13-parameter job's generations run ~15% faster, and eight waves per SIMD
+// spill too much.  32-byte rows hold twice the digits and spill hundreds of bytes per lane under
+// any such limit, so they are left to the compiler.
+template <int RW>
+constexpr int scan_waves_per_eu() { return RW >= 8 ? 1 : 5; }
+
 template <int M, int RW>
-__global__ __launch_bounds__(kBlock) void k_repair_scan(const RepairSet* __restrict__ sets, uint32_t n_sets,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<RW>()))) void k_repair_scan(const RepairSet* __restrict__ sets, uint32_t n_sets,
                                                         RepairPlan plan, uint32_t which, uint32_t tab_stride) {
     constexpr uint32_t cls = (uint32_t)M * 4u + (RW == 1 ? 0u : RW == 2 ? 1u : RW == 4 ? 2u : 3u);
     extern __shared__ uint64_t lds_tabs[];
@@ -573,6 +582,47 @@ __global__ __launch_bounds__(kBlock) void k_repair_scan(const RepairSet* __restr
             const uint32_t* list = which ? J.fb_list : J.list;
             const uint64_t* list_L = which ? J.fb_L : J.list_L;
             scan_item<M, RW>(J, S, list, list_L, li, part, parts, lds_tab);
+        }
+    }
+}
+
+// All scanned metrics of one row width in a single launch: the item ranges of the classes in
+// `mmask` (bit m: metric m, Hamming to Alg. 3) are laid end to end and every wave takes items of
+// any of them, so the latency chains of the classes overlap instead of running one launch after
+// another.  Each item runs the same code as in its own class's kernel.
+template <int RW>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<RW>()))) void k_repair_scan_mix(const RepairSet* __restrict__ sets, uint32_t n_sets,
+                                                            RepairPlan plan, uint32_t which, uint32_t tab_stride,
+                                                            uint32_t mmask) {
+    constexpr uint32_t rwi = RW == 1 ? 0u : RW == 2 ? 1u : RW == 4 ? 2u : 3u;
+    extern __shared__ uint64_t lds_tabs[];
+    const uint32_t wpb = blockDim.x / 64;
+    CT_LDS uint64_t* lds_tab = (CT_LDS uint64_t*)lds_tabs + (threadIdx.x >> 6) * tab_stride;
+    uint32_t end[4];
+    uint32_t acc = 0;
+#pragma unroll
+    for (uint32_t m = 0; m < 4; ++m) {
+        if (mmask & (1u << m)) acc += plan.item_off[(m * 4u + rwi) * (n_sets + 1) + n_sets];
+        end[m] = acc;
+    }
+    const uint32_t waves = gridDim.x * wpb;
+    for (uint32_t item = uni(blockIdx.x * wpb + (threadIdx.x >> 6)); item < acc; item += waves) {
+        const uint32_t m = item < end[0] ? 0u : item < end[1] ? 1u : item < end[2] ? 2u : 3u;
+        const uint32_t* off = plan.item_off + (m * 4u + rwi) * (n_sets + 1);
+        const uint32_t local_item = item - (m ? end[m - 1] : 0u);
+        const uint32_t s = uni(find_set(off, n_sets, local_item));
+        const RepairSet& J = sets[s];
+        const DevSpace& S = *J.S;
+        const uint32_t parts = uni(plan.parts[s]);
+        const uint32_t local = local_item - off[s];
+        const uint32_t li = local / parts, part = local % parts;
+        const uint32_t* list = which ? J.fb_list : J.list;
+        const uint64_t* list_L = which ? J.fb_L : J.list_L;
+        switch (m) {
+        case CT_HAMMING: scan_item<CT_HAMMING, RW>(J, S, list, list_L, li, part, parts, lds_tab); break;
+        case CT_INDEX_L1: scan_item<CT_INDEX_L1, RW>(J, S, list, list_L, li, part, parts, lds_tab); break;
+        case CT_TIER_EUCLID: scan_item<CT_TIER_EUCLID, RW>(J, S, list, list_L, li, part, parts, lds_tab); break;
+        default: scan_item<CT_TIER_RANDOM, RW>(J, S, list, list_L, li, part, parts, lds_tab); break;
         }
     }
 }
@@ -632,6 +682,23 @@ void launch_scan_rw(const RepairPasses& rp, uint32_t which, hipStream_t st) {
                        rp.d_sets, rp.n_sets, rp.plan, which, stride);
 }
 
+template <int RW>
+void launch_mix_rw(const RepairPasses& rp, uint32_t mmask, uint32_t which, hipStream_t st) {
+    ProfScope ps_("k_repair_scan", st);
+    const uint32_t stride = (mmask & (1u << CT_TIER_EUCLID)) ? std::max<uint32_t>(rp.euclid_tab, 1) : 0;
+    uint32_t wpb = kBlock / 64;
+    while (wpb > 1 && (size_t)wpb * stride * 8 > 65536) wpb >>= 1;
+    hipLaunchKernelGGL((k_repair_scan_mix<RW>), dim3(std::max<uint32_t>(rp.tune.grid_waves / wpb, 1)), dim3(wpb * 64),
+                       (size_t)wpb * stride * 8, st, rp.d_sets, rp.n_sets, rp.plan, which, stride, mmask);
+}
+
+void launch_mix(const RepairPasses& rp, uint32_t rwi, uint32_t mmask, uint32_t which, hipStream_t st) {
+    if (rwi == 0) launch_mix_rw<1>(rp, mmask, which, st);
+    else if (rwi == 1) launch_mix_rw<2>(rp, mmask, which, st);
+    else if (rwi == 2) launch_mix_rw<4>(rp, mmask, which, st);
+    else launch_mix_rw<8>(rp, mmask, which, st);
+}
+
 template <int M>
 void launch_class_rw(const RepairPasses& rp, uint32_t rwi, uint32_t which, hipStream_t st) {
     if (rwi == 0) launch_scan_rw<M, 1>(rp, which, st);
@@ -654,8 +721,21 @@ void launch_class(const RepairPasses& rp, uint32_t cls, uint32_t which, hipStrea
 // each on an auxiliary stream forked from st and joined back into it (the classes touch disjoint
 // sets, so they may overlap).
 int launch_scans(const RepairPasses& rp, uint32_t mask, uint32_t which, hipStream_t st) {
+    if (rp.tune.mode == kScanFused) {
+        // per row width, the scanned metrics together; the enumerated mutation metric alone
+        for (uint32_t rwi = 0; rwi < 4; ++rwi) {
+            uint32_t mm = 0;
+            for (uint32_t m = 0; m < (uint32_t)CT_HAM1_RANDOM; ++m)
+                if (mask & (1u << (m * 4u + rwi))) mm |= 1u << m;
+            if (__builtin_popcount(mm) > 1) launch_mix(rp, rwi, mm, which, st);
+            else if (mm) launch_class(rp, (uint32_t)__builtin_ctz(mm) * 4u + rwi, which, st);
+            if (mask & (1u << ((uint32_t)CT_HAM1_RANDOM * 4u + rwi)))
+                launch_class(rp, (uint32_t)CT_HAM1_RANDOM * 4u + rwi, which, st);
+        }
+        return CT_OK;
+    }
     StreamFan* f = rp.fan;
-    if (!f || !f->fork || !rp.tune.overlap || __builtin_popcount(mask) < 2) {
+    if (!f || !f->fork || rp.tune.mode != kScanStreams || __builtin_popcount(mask) < 2) {
         for (uint32_t cls = 0; cls < kNumClasses; ++cls)
             if (mask & (1u << cls)) launch_class(rp, cls, which, st);
         return CT_OK;

@@ -517,10 +517,12 @@ namespace {
 // added to its total over the batch's tuning generations.
 int autotune_sweep(ct_batch* b, hipStream_t st) {
     if (b->tune_cand.empty()) {
-        for (uint32_t ov = 0; ov <= (b->fan.fork ? 1u : 0u); ++ov)
+        std::vector<uint32_t> modes = {kScanSerial, kScanFused};
+        if (b->fan.fork) modes.push_back(kScanStreams);
+        for (uint32_t mode : modes)
             for (uint32_t it : {2048u, 4096u, 8192u})
                 for (uint32_t ms : {8u, 16u, 32u, 64u})
-                    for (uint32_t gw : {4096u, 8192u}) b->tune_cand.push_back(RepairTune{it, ms, gw, ov});
+                    for (uint32_t gw : {4096u, 8192u}) b->tune_cand.push_back(RepairTune{it, ms, gw, mode});
         b->tune_ms.assign(b->tune_cand.size(), 0.0);
     }
     const std::vector<RepairTune>& cand = b->tune_cand;
@@ -538,7 +540,7 @@ int autotune_sweep(ct_batch* b, hipStream_t st) {
     RepairPasses rp = b->passA;
     for (size_t v = 0; v < cand.size() && !rc; ++v) {
         rp.tune = cand[v];
-        if (v == 0 || cand[v].overlap != cand[v - 1].overlap) rc = launch_repair_passes(rp, true, st, false);
+        if (v == 0 || cand[v].mode != cand[v - 1].mode) rc = launch_repair_passes(rp, true, st, false);
         if (!rc && hipEventRecord(ev[2 * v], st) != hipSuccess) rc = ct_fail(CT_EDEVICE, "autotune: event record failed");
         if (!rc) rc = launch_repair_passes(rp, true, st, false);
         if (!rc && hipEventRecord(ev[2 * v + 1], st) != hipSuccess)
@@ -556,11 +558,11 @@ int autotune_sweep(ct_batch* b, hipStream_t st) {
     return rc;
 }
 
-// Candidate with the lowest sweep total among those with the given side-stream setting (-1: any).
-RepairTune sweep_best(const ct_batch* b, int overlap) {
+// Candidate with the lowest sweep total: streams < 0 any, 0 without side streams, 1 with them.
+RepairTune sweep_best(const ct_batch* b, int streams) {
     size_t pick = b->tune_cand.size();
     for (size_t v = 0; v < b->tune_cand.size(); ++v)
-        if ((overlap < 0 || b->tune_cand[v].overlap == (uint32_t)overlap) &&
+        if ((streams < 0 || (b->tune_cand[v].mode == kScanStreams) == (streams == 1)) &&
             (pick == b->tune_cand.size() || b->tune_ms[v] < b->tune_ms[pick]))
             pick = v;
     return pick < b->tune_cand.size() ? b->tune_cand[pick] : b->passA.tune;
@@ -594,10 +596,10 @@ int batch_autotune(ct_batch* b, uint32_t n_generations, uint32_t sample_every, h
     b->tune_ms.clear();
     // The sweep times the main pass alone on the device, but side streams cost more than that: the
     // host spends longer issuing a generation that forks and joins streams, and the device waits
-    // at the joins.  That setting is therefore decided on whole generations by the host clock:
-    // the generations between sweeps run in blocks of kBlockGens with one setting (the best
-    // candidate of that setting so far), alternating, each block between two stream waits; the
-    // setting with the lower mean block time wins.
+    // at the joins.  Streams or not is therefore decided on whole generations by the host clock:
+    // the generations between sweeps run in blocks of kBlockGens with the best candidate with or
+    // without streams so far, alternating, each block between two stream waits; the lower mean
+    // block time wins.
     constexpr uint32_t kBlockGens = 4;
     double block_ms[2] = {0, 0};
     uint32_t block_n[2] = {0, 0};

@@ -144,7 +144,7 @@ def test_autotuned_batch_equals_plain(spaces):
     tn = b.tuning()
     say(f"[gpu_batched] tuning {tn}")
     assert tn["tuned"] and tn["items"] in (2048, 4096, 8192) and tn["min_boxes"] in (8, 16, 32, 64)
-    assert tn["grid_waves"] in (4096, 8192) and tn["overlap"] in (0, 1)
+    assert tn["grid_waves"] in (4096, 8192) and tn["mode"] in (0, 1, 2)
     step_many(plain, 11)
     t.cuda.synchronize()
     for x, y in zip(plain, tuned):
@@ -160,10 +160,12 @@ def test_autotuned_batch_equals_plain(spaces):
     b.close()
 
 
-@pytest.mark.parametrize("tune", [(64, 1, 64, 0), (2048, 8, 4096, 1), (8192, 64, 8192, 1), (8192, 1024, 512, 0)])
+@pytest.mark.parametrize("tune", [(64, 1, 64, 0), (2048, 8, 4096, 1), (8192, 64, 8192, 1), (8192, 1024, 512, 0),
+                                  (64, 1, 64, 2), (4096, 16, 8192, 2), (8192, 64, 512, 2)])
 def test_set_tuning_equals_plain(spaces, tune):
     """Any installed scan partitioning (few or many items per launch, small or large boxes per
-    part, small or large grids, scan classes on side streams or not) gives the plain results,
+    part, small or large grids; scan classes one after another, on side streams or fused per row
+    width) gives the plain results,
     both launched directly and replayed from a graph."""
     from paper_2606_28372_amd import Batch, CT_STEP_BATCHED, CT_STEP_GRAPH, step_many
     t = torch()
@@ -171,7 +173,7 @@ def test_set_tuning_equals_plain(spaces, tune):
     b = Batch(tuned)
     b.set_tuning(*tune)
     got = b.tuning()
-    assert (got["items"], got["min_boxes"], got["grid_waves"], got["overlap"]) == tune and got["tuned"]
+    assert (got["items"], got["min_boxes"], got["grid_waves"], got["mode"]) == tune and got["tuned"]
     say(f"[gpu_batched] set_tuning {tune}")
     b.step(3, CT_STEP_BATCHED)
     b.step(3, CT_STEP_GRAPH)
@@ -187,7 +189,7 @@ def test_set_tuning_rejects_out_of_range(spaces):
     t = torch()
     b = Batch(make_runs(t, spaces))
     before = b.tuning()
-    for bad in [(63, 16, 4096, 0), (8193, 16, 4096, 0), (4096, 0, 4096, 0), (4096, 16, 32, 0), (4096, 16, 4096, 2)]:
+    for bad in [(63, 16, 4096, 0), (8193, 16, 4096, 0), (4096, 0, 4096, 0), (4096, 16, 32, 0), (4096, 16, 4096, 3)]:
         with pytest.raises(CtError):
             b.set_tuning(*bad)
     assert b.tuning() == before
