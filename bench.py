@@ -90,16 +90,20 @@ def measured_traffic(kernel, workload):
     return meta["bytes_per_launch"]
 
 
-def run_job(ct, spec, runs, objective_t, gens):
-    """One pass of the whole path; returns (space stats, per-run counters)."""
+def run_job(ct, spec, runs, objective_t, gens, tuning=None):
+    """One pass of the whole path; returns (space stats, per-run counters, scan tuning)."""
     import torch
     sp = ct.Space.from_spec(spec)
     pops = [ct.Pop.from_opt(sp, opt, objective_t) for opt in runs]
     batch = ct.Batch(pops)
-    if gens:
+    if gens and tuning:
+        batch.set_tuning(*tuning)         # a partitioning given on the command line
+        batch.step(gens, ct.CT_STEP_BATCHED)
+    elif gens:
         # tuning generations spread over the run pick the scan partitioning (once per shape: plain
         # generations when the shape is cached)
         batch.autotune(gens, max(1, gens // AUTOTUNE_SAMPLES))
+    tn = batch.tuning()
     batch.close()
     out = []
     for p in pops:
@@ -110,7 +114,7 @@ def run_job(ct, spec, runs, objective_t, gens):
     torch.cuda.synchronize()
     stats = (sp.n_cartesian, sp.n_valid)
     sp.close()
-    return stats, out
+    return stats, out, tn
 
 
 def cpu_baseline(spec, runs, obj, gens):
@@ -268,12 +272,20 @@ def main():
     ap.add_argument("--serving-generations", type=int, default=200)
     ap.add_argument("--serving-interarrival-ms", type=float, default=5.0)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--tuning", default=None,
+                    help="items,min_boxes,grid_waves,mode: install this scan partitioning in the job instead of "
+                         "autotuning it (profiling runs repeat the timed configuration this way)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="copy a buffer of this size once before the job (reference dispatch for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
               file=sys.stderr)
+        sys.exit(2)
+
+    tuning = tuple(int(x) for x in args.tuning.split(",")) if args.tuning else None
+    if tuning is not None and len(tuning) != 4:
+        print("--tuning takes items,min_boxes,grid_waves,mode", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -307,7 +319,7 @@ def main():
     if args.warmup:
         ct.prof_enable(True)
         for _ in range(args.warmup):
-            run_job(ct, spec, runs, obj_t, gens)
+            run_job(ct, spec, runs, obj_t, gens, tuning)
         per_kernel = {k: ct.prof_read(k) for k in kernel_names()}
         ct.prof_enable(False)
         per_kernel = {k: (v[0] / args.warmup, v[1] / args.warmup) for k, v in per_kernel.items() if v[1]}
@@ -320,7 +332,7 @@ def main():
     t0 = time.perf_counter()
     results = []
     for _ in range(args.steps):
-        results.append(run_job(ct, spec, runs, obj_t, gens))
+        results.append(run_job(ct, spec, runs, obj_t, gens, tuning))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_step = dt * 1e3 / args.steps
@@ -329,8 +341,8 @@ def main():
     ct.prof_select(None)
     n_cart = results[0][0][0]
     checked = n_cart + gens * sum(o.pop_size for o in runs)
-    repairs = sum(c["repairs"] for _, rc in results for _, c in rc) / args.steps
-    mutations = sum(c["mutations"] for _, rc in results for _, c in rc) / args.steps
+    repairs = sum(c["repairs"] for _, rc, _ in results for _, c in rc) / args.steps
+    mutations = sum(c["mutations"] for _, rc, _ in results for _, c in rc) / args.steps
     gens_total = gens * len(runs)
 
     # the dominant kernel's roofline, from its launches inside the timed steps
@@ -373,6 +385,7 @@ def main():
         "mutation_scans_per_s": mutations / (ms_step * 1e-3),
         "generations_per_s_job": gens_total / (ms_step * 1e-3),
         "kernel_ms_per_step_warmup": {k: v[0] for k, v in per_kernel.items()},
+        "scan_tuning": results[-1][2],
         "roofline": roof,
     }
     if not args.no_batched:

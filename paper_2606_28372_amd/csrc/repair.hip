@@ -91,7 +91,7 @@ struct Cand {
     uint32_t who, gen;
     uint64_t seed;
 
-    __device__ void load(const RepairSet& J, const CT_GLOBAL DevSpace* Sg, uint32_t ci, CT_LDS uint64_t* lds_tab) {
+    __device__ __forceinline__ void load(const RepairSet& J, const CT_GLOBAL DevSpace* Sg, uint32_t ci, CT_LDS uint64_t* lds_tab) {
         const CT_GLOBAL DevSpace& S = *Sg;
         const CT_GLOBAL uint32_t* cr = gptr(reinterpret_cast<const uint32_t*>(J.rows + (uint64_t)ci * S.R));
         lin = gptr(S.lin);
@@ -292,8 +292,10 @@ __device__ __forceinline__ uint64_t rank_g(const CT_GLOBAL DevSpace* S, uint64_t
 //     load while the current one is evaluated;
 //   - after each box bk drops to the smallest key found, so later boxes (higher positions) with
 //     an equal bound are skipped: ties go to the lowest position.
+// Always inlined: with two kernels calling it the compiler would otherwise emit a call, whose
+// register convention costs the tiered metrics twice the VGPRs plus stack spills.
 template <int M, int RW>
-__device__ void scan_item(const RepairSet& J, const DevSpace& S, const uint32_t* list, const uint64_t* list_L,
+__device__ __forceinline__ void scan_item(const RepairSet& J, const DevSpace& S, const uint32_t* list, const uint64_t* list_L,
                           uint32_t li, uint32_t part, uint32_t parts, CT_LDS uint64_t* lds_tab) {
     const uint32_t lane = wave_lane();
     const CT_GLOBAL DevSpace* Sg = gptr(&S);
@@ -386,7 +388,7 @@ __device__ void scan_item(const RepairSet& J, const DevSpace& S, const uint32_t*
 // one parameter to another of its values; each is looked up in the validity bitmask and the
 // valid ones compete with their Philox key, ties to the lowest linear index (the same minimum
 // as a scan of the valid list).  One wave per candidate; lanes over (parameter, value) pairs.
-__device__ void ham1_item(const RepairSet& J, const DevSpace& S, uint32_t li) {
+__device__ __forceinline__ void ham1_item(const RepairSet& J, const DevSpace& S, uint32_t li) {
     const uint32_t lane = wave_lane();
     const uint32_t ci = uni(J.list[li]);
     const uint8_t* cr = J.rows + (uint64_t)ci * S.R;
@@ -550,17 +552,8 @@ __global__ __launch_bounds__(64) void k_repair_plan(const RepairSet* __restrict_
     }
 }
 
-// The scan is a latency chain per wave (candidate -> tables -> seed rows -> boxes), so waves in
-// flight matter more than registers: left alone the compiler spends up to 180 VGPRs on the tiered
-// metrics of 16-byte rows (two waves per SIMD); held to five waves per SIMD (at most 102 VGPRs, a
-// few spilled bytes) the 13-parameter job's generations run ~15% faster, and eight waves per SIMD
-// spill too much.  32-byte rows hold twice the digits and spill hundreds of bytes per lane under
-// any such limit, so they are left to the compiler.
-template <int RW>
-constexpr int scan_waves_per_eu() { return RW >= 8 ? 1 : 5; }
-
 template <int M, int RW>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<RW>()))) void k_repair_scan(const RepairSet* __restrict__ sets, uint32_t n_sets,
+__global__ __launch_bounds__(kBlock) void k_repair_scan(const RepairSet* __restrict__ sets, uint32_t n_sets,
                                                         RepairPlan plan, uint32_t which, uint32_t tab_stride) {
     constexpr uint32_t cls = (uint32_t)M * 4u + (RW == 1 ? 0u : RW == 2 ? 1u : RW == 4 ? 2u : 3u);
     extern __shared__ uint64_t lds_tabs[];
@@ -591,7 +584,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(scan_wav
 // any of them, so the latency chains of the classes overlap instead of running one launch after
 // another.  Each item runs the same code as in its own class's kernel.
 template <int RW>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<RW>()))) void k_repair_scan_mix(const RepairSet* __restrict__ sets, uint32_t n_sets,
+__global__ __launch_bounds__(kBlock) void k_repair_scan_mix(const RepairSet* __restrict__ sets, uint32_t n_sets,
                                                             RepairPlan plan, uint32_t which, uint32_t tab_stride,
                                                             uint32_t mmask) {
     constexpr uint32_t rwi = RW == 1 ? 0u : RW == 2 ? 1u : RW == 4 ? 2u : 3u;
