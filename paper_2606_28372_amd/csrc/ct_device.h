@@ -47,6 +47,8 @@ struct DevSpace {
     const uint16_t* dir8;       // valid configurations from the group start to each 8-word block
     const uint8_t* boxes;       // per 64-row block of the valid list: min row, max row (2 * R bytes)
     uint64_t n_sub;             // number of 64-row blocks
+    const uint8_t* chunks;      // per 64 boxes (4096 rows): the same min / max rows over its boxes
+    uint64_t n_chunk;           // ceil(n_sub / 64)
 };
 
 // Validity of a linear index from the bitmask.

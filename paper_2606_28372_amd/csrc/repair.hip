@@ -80,8 +80,9 @@ struct Cand {
     uint32_t c[RW];
     uint32_t pv[RW], nx[RW];     // nearest present value index below / above each digit
     bool adj_is_sa;
-    // TIER_EUCLID: squared distance of the particle to each value centre, T[v * D + j] =
-    // (X_j - (v * 2^16 + 2^15))^2 in this wave's LDS slice, and the value index s_j whose centre
+    // TIER_EUCLID: squared distance of the particle to each value centre, T[v * 4RW + j] =
+    // (X_j - (v * 2^16 + 2^15))^2 (0 for the padding digits j >= D) in this wave's LDS slice, so
+    // every digit of a row is looked up unconditionally; and the value index s_j whose centre
     // is nearest to X_j (the squared distance is convex in v, so over a box's range [a, b] its
     // minimum is at clamp(s_j, a, b))
     const CT_LDS uint64_t* tab;
@@ -104,43 +105,54 @@ struct Cand {
             c[k] = uni(cr[k] & keep);
         }
         adj_is_sa = true;
+        // Per-digit tables are looked up by lane (lane j: parameter j), so all digits cost one
+        // round trip to memory instead of one dependent round trip each.
+        const uint32_t lane = wave_lane();
         if constexpr (M == CT_TIER_EUCLID || M == CT_TIER_RANDOM) {
+            uint32_t dj = 0;
 #pragma unroll
-            for (int k = 0; k < RW; ++k) { pv[k] = 0; nx[k] = 0; }
+            for (int k = 0; k < RW; ++k) dj = (lane >> 2) == (uint32_t)k ? (c[k] >> ((lane & 3u) * 8u)) & 0xFFu : dj;
+            // (previous, next) present value index of digit j, low byte first; 0 past the last parameter
+            const uint32_t pnj = lane < D ? (uint32_t)gptr(reinterpret_cast<const uint16_t*>(S.prevnext))[lane * 256u + dj] : 0u;
+            const uint32_t pj = pnj & 0xFFu, nj = pnj >> 8;
+            // the two rules agree on parameter j unless a present value lies below (above) d while
+            // d-1 (d+1) itself never occurs in a solution; "none" is 0xFF, which no digit equals
+            const bool ok = lane >= D || ((pj == dj - 1u || pj == 0xFFu) && (nj == dj + 1u || nj == 0xFFu));
+            adj_is_sa = __ballot(!ok) == 0ull;
 #pragma unroll
-            for (int j = 0; j < RW * 4; ++j) {
-                const uint32_t d = (c[j >> 2] >> ((j & 3) * 8)) & 0xFFu;
-                uint32_t p = d, n = d;
-                if ((uint32_t)j < S.D) {
-                    const CT_GLOBAL uint8_t* pn = gptr(S.prevnext);
-                    p = uni(pn[((uint32_t)j * 256u + d) * 2u + 0u]);
-                    n = uni(pn[((uint32_t)j * 256u + d) * 2u + 1u]);
-                    // the two rules agree on parameter j unless a present value lies below (above) d while
-                    // d-1 (d+1) itself never occurs in a solution; "none" is 0xFF, which no digit equals
-                    adj_is_sa &= (p == d - 1u || p == 0xFFu) && (n == d + 1u || n == 0xFFu);
+            for (int k = 0; k < RW; ++k) {
+                uint32_t pw = 0, nw = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)pnj, k * 4 + q);
+                    pw |= (v & 0xFFu) << (q * 8);
+                    nw |= (v >> 8) << (q * 8);
                 }
-                pv[j >> 2] |= p << ((j & 3) * 8);
-                nx[j >> 2] |= n << ((j & 3) * 8);
+                pv[k] = pw;
+                nx[k] = nw;
             }
         }
         if constexpr (M == CT_TIER_EUCLID) {
             const CT_GLOBAL int32_t* xp = gptr(J.pos_q16 + (uint64_t)ci * S.D);
-            const uint32_t n_tab = S.max_radix * S.D;
-            for (uint32_t e = wave_lane(); e < n_tab; e += 64) {
-                const uint32_t v = e / S.D, j = e - v * S.D;
-                const int64_t d = (int64_t)xp[j] - (int64_t)((v << 16) + 32768u);
-                lds_tab[e] = (uint64_t)(d * d);
+            const int32_t xj = lane < D ? xp[lane] : 0;
+            const int32_t hj = lane < D ? (int32_t)S.radix[lane] - 1 : 0;
+            constexpr uint32_t R4 = RW * 4;
+            const uint32_t n_tab = S.max_radix * R4;
+            // a uniform trip count keeps every lane active for the shuffle
+            for (uint32_t e0 = 0; e0 < n_tab; e0 += 64) {
+                const uint32_t e = e0 + lane;
+                const uint32_t v = e / R4, j = e % R4;
+                const int32_t x = __shfl(xj, (int)j, 64);
+                const int64_t d = (int64_t)x - (int64_t)((v << 16) + 32768u);
+                if (e < n_tab) lds_tab[e] = j < D ? (uint64_t)(d * d) : 0ull;
             }
+            const uint32_t sj = lane < D ? (uint32_t)min(max(xj >> 16, 0), hj) : 0u;
 #pragma unroll
-            for (int k = 0; k < RW; ++k) s[k] = 0;
+            for (int k = 0; k < RW; ++k) {
+                uint32_t w = 0;
 #pragma unroll
-            for (int j = 0; j < RW * 4; ++j) {
-                if ((uint32_t)j < S.D) {
-                    const int32_t x = (int32_t)uni((uint32_t)xp[j]);
-                    const int32_t hi = (int32_t)S.radix[j] - 1;
-                    const int32_t sj = min(max(x >> 16, 0), hi);
-                    s[j >> 2] |= (uint32_t)sj << ((j & 3) * 8);
-                }
+                for (int q = 0; q < 4; ++q) w |= (uint32_t)__builtin_amdgcn_readlane((int)sj, k * 4 + q) << (q * 8);
+                s[k] = w;
             }
             tab = lds_tab;
             __builtin_amdgcn_wave_barrier();
@@ -200,7 +212,7 @@ struct Cand {
                     uint64_t d2 = 0;
 #pragma unroll
                     for (int j = 0; j < RW * 4; ++j)
-                        if ((uint32_t)j < D) d2 += tab[((v[j >> 2] >> ((j & 3) * 8)) & 0xFFu) * D + (uint32_t)j];
+                        d2 += tab[((v[j >> 2] >> ((j & 3) * 8)) & 0xFFu) * (RW * 4) + (uint32_t)j];
                     return ((uint64_t)tier << 62) | d2;
                 } else {
                     const uint64_t L = lin[pos];
@@ -214,6 +226,18 @@ struct Cand {
 
     // lower bound of key() over every row inside the box [lo, hi]
     __device__ __forceinline__ uint64_t bound_box(const uint32_t* lo32, const uint32_t* hi32, uint32_t D) const {
+        if constexpr (M == CT_INDEX_L1) {
+            // per digit, the distance from c to [a, b] (a <= b) is (|c - a| + |c - b| - (b - a)) / 2,
+            // and v_sad_u8 sums absolute byte differences four digits at a time
+            uint32_t both = 0, span = 0;
+#pragma unroll
+            for (int k = 0; k < RW; ++k) {
+                both = __builtin_amdgcn_sad_u8(c[k], lo32[k], both);
+                both = __builtin_amdgcn_sad_u8(c[k], hi32[k], both);
+                span = __builtin_amdgcn_sad_u8(hi32[k], lo32[k], span);
+            }
+            return (both - span) >> 1;
+        }
         uint32_t miss = 0, sum = 0, far = 0;
         bool adj_ok = true;
         uint64_t e2 = 0;
@@ -231,18 +255,17 @@ struct Cand {
                 far += d > 1u;
                 if constexpr (M == CT_TIER_EUCLID || M == CT_TIER_RANDOM) {
                     if (!adj_is_sa && d != 0u) {
+                        // "none" is 0xFF, above every box bound (radices are at most 255)
                         const int32_t p = (int32_t)((pv[k] >> (q * 8)) & 0xFFu);
                         const int32_t n = (int32_t)((nx[k] >> (q * 8)) & 0xFFu);
-                        adj_ok &= (p != 0xFF && p >= a && p <= b) || (n != 0xFF && n >= a && n <= b);
+                        adj_ok &= (p >= a && p <= b) || (n >= a && n <= b);
                     }
                 }
                 if constexpr (M == CT_TIER_EUCLID) {
                     // squared distance from the particle to the nearest value centre inside [a, b]
                     const uint32_t j = (uint32_t)(k * 4 + q);
-                    if (j < D) {
-                        const int32_t sj = (int32_t)((s[k] >> (q * 8)) & 0xFFu);
-                        e2 += tab[(uint32_t)min(max(sj, a), b) * D + j];
-                    }
+                    const int32_t sj = (int32_t)((s[k] >> (q * 8)) & 0xFFu);
+                    e2 += tab[(uint32_t)min(max(sj, a), b) * (RW * 4) + j];
                 }
             }
         }
@@ -272,14 +295,24 @@ __device__ __forceinline__ void wave_lexmin(uint64_t& k, uint32_t& p) {
     p = uni(p);
 }
 
-// rank_dir on a descriptor typed as device memory
+// rank_dir on a descriptor typed as device memory, for a wave-uniform L: lanes 0-7 read the words
+// of L's 8-word block up to L's word at once, so the rank costs one round trip after the
+// directory instead of one per word.
 __device__ __forceinline__ uint64_t rank_g(const CT_GLOBAL DevSpace* S, uint64_t L) {
     if (L >= S->N) return S->n_valid;
     const uint64_t w = L >> 6;
-    const CT_GLOBAL uint64_t* words = gptr(S->words);
-    uint64_t r = gptr(S->grp_off)[w >> 6] + gptr(S->dir8)[w >> 3];
-    for (uint64_t q = w & ~7ull; q < w; ++q) r += __popcll(words[q]);
-    return r + __popcll(words[w] & ((1ull << (L & 63u)) - 1ull));
+    const uint32_t lane = wave_lane();
+    const uint64_t q = (w & ~7ull) + (lane & 7u);
+    uint32_t cnt = 0;
+    if (lane < 8 && q <= w) {
+        const uint64_t word = gptr(S->words)[q];
+        cnt = (uint32_t)__popcll(q < w ? word : word & ((1ull << (L & 63u)) - 1ull));
+    }
+    const uint64_t base = gptr(S->grp_off)[w >> 6] + gptr(S->dir8)[w >> 3];
+    cnt += __shfl_xor(cnt, 1, 64);
+    cnt += __shfl_xor(cnt, 2, 64);
+    cnt += __shfl_xor(cnt, 4, 64);
+    return base + uni(cnt);
 }
 
 // One (candidate, part) item: the lexicographic (key, position) minimum over the rows of the
@@ -300,6 +333,7 @@ __device__ __forceinline__ void scan_item(const RepairSet& J, const DevSpace& S,
     const uint32_t lane = wave_lane();
     const CT_GLOBAL DevSpace* Sg = gptr(&S);
     const uint32_t ci = uni(gld(list + li));
+    const uint64_t Lc = gld(list_L + li);
     Cand<M, RW> C;
     C.load(J, Sg, ci, lds_tab);
     const CT_GLOBAL uint32_t* rows32 = gptr(reinterpret_cast<const uint32_t*>(Sg->rows));
@@ -309,7 +343,6 @@ __device__ __forceinline__ void scan_item(const RepairSet& J, const DevSpace& S,
 
     constexpr bool tiered = (M == CT_TIER_EUCLID || M == CT_TIER_RANDOM);
     uint64_t bk = tiered ? kTier3 : kNoKey;
-    const uint64_t Lc = gld(list_L + li);
     const uint64_t L = ((uint64_t)uni((uint32_t)(Lc >> 32)) << 32) | uni((uint32_t)Lc);
     if (L != ~0ull) {
         const uint64_t ins = rank_g(Sg, L);
@@ -328,50 +361,71 @@ __device__ __forceinline__ void scan_item(const RepairSet& J, const DevSpace& S,
     uint64_t mk = bk;                               // this lane's best key (exclusive until a row is found)
     uint32_t mp = kNoPos;
     const uint64_t b0 = (uint64_t)part * n_sub / parts, b1 = (uint64_t)(part + 1) * n_sub / parts;
+    const CT_GLOBAL uint32_t* chunk32 = gptr(reinterpret_cast<const uint32_t*>(Sg->chunks));
+    const uint64_t k0 = b0 >> 6, k1 = (b1 + 63u) >> 6;     // chunks (64 aligned boxes) meeting [b0, b1)
     uint32_t nv[RW];
-    for (uint64_t cb = b0; cb < b1; cb += 64) {
-        // lanes over 64 boxes: which ones can hold a row below the bound?
-        const uint64_t b = cb + lane;
-        uint64_t lb = kNoKey;
-        if (b < b1) {
+    for (uint64_t ck = k0; ck < k1; ck += 64) {
+        // lanes over 64 chunks: which ones can hold a row below the bound?
+        const uint64_t kc = ck + lane;
+        uint64_t lc = kNoKey;
+        if (kc < k1) {
             uint32_t lo[RW], hi[RW];
 #pragma unroll
             for (int w = 0; w < RW; ++w) {
-                lo[w] = box32[b * 2u * RW + w];
-                hi[w] = box32[b * 2u * RW + RW + w];
+                lo[w] = chunk32[kc * 2u * RW + w];
+                hi[w] = chunk32[kc * 2u * RW + RW + w];
             }
-            lb = C.bound_box(lo, hi, D);
+            lc = C.bound_box(lo, hi, D);
         }
-        uint64_t m = __ballot(lb < bk);
-        int tn = m ? __ffsll((long long)m) - 1 : -1;
-        auto fetch = [&](int t) {
-            const uint64_t q = (cb + (uint32_t)t) * 64u + lane;
+        uint64_t mc = __ballot(lc < bk);
+        while (mc) {
+            const uint32_t tc = (uint32_t)(__ffsll((long long)mc) - 1);
+            mc &= ~(1ull << tc);
+            const uint64_t cb = (ck + tc) * 64u;            // the chunk's first box
+            // lanes over the chunk's boxes inside [b0, b1)
+            const uint64_t b = cb + lane;
+            uint64_t lb = kNoKey;
+            if (b >= b0 && b < b1) {
+                uint32_t lo[RW], hi[RW];
 #pragma unroll
-            for (int w = 0; w < RW; ++w) nv[w] = q < n_valid ? rows32[q * RW + w] : 0u;
-        };
-        if (tn >= 0) fetch(tn);
-        while (tn >= 0) {
-            const uint32_t t = (uint32_t)tn;
-            m &= ~(1ull << t);
-            uint32_t v[RW];
-#pragma unroll
-            for (int w = 0; w < RW; ++w) v[w] = nv[w];
-            tn = m ? __ffsll((long long)m) - 1 : -1;
-            if (tn >= 0) fetch(tn);
-            const uint64_t r = (cb + t) * 64u + lane;
-            if (r < n_valid) {
-                const uint64_t k = C.key(S, v, r, mk < bk ? mk : bk);
-                if (k < mk) { mk = k; mp = (uint32_t)r; }
+                for (int w = 0; w < RW; ++w) {
+                    lo[w] = box32[b * 2u * RW + w];
+                    hi[w] = box32[b * 2u * RW + RW + w];
+                }
+                lb = C.bound_box(lo, hi, D);
             }
-            const uint64_t wm = wave_min_u64(mk);
-            bk = wm < bk ? wm : bk;
-            if (m) {
-                m &= __ballot(lb < bk);             // drop boxes the tighter bound now rules out
-                if (tn >= 0 && !((m >> tn) & 1ull)) {
-                    tn = m ? __ffsll((long long)m) - 1 : -1;
-                    if (tn >= 0) fetch(tn);
+            uint64_t m = __ballot(lb < bk);
+            int tn = m ? __ffsll((long long)m) - 1 : -1;
+            auto fetch = [&](int t) {
+                const uint64_t q = (cb + (uint32_t)t) * 64u + lane;
+#pragma unroll
+                for (int w = 0; w < RW; ++w) nv[w] = q < n_valid ? rows32[q * RW + w] : 0u;
+            };
+            if (tn >= 0) fetch(tn);
+            while (tn >= 0) {
+                const uint32_t t = (uint32_t)tn;
+                m &= ~(1ull << t);
+                uint32_t v[RW];
+#pragma unroll
+                for (int w = 0; w < RW; ++w) v[w] = nv[w];
+                tn = m ? __ffsll((long long)m) - 1 : -1;
+                if (tn >= 0) fetch(tn);
+                const uint64_t r = (cb + t) * 64u + lane;
+                if (r < n_valid) {
+                    const uint64_t k = C.key(S, v, r, mk < bk ? mk : bk);
+                    if (k < mk) { mk = k; mp = (uint32_t)r; }
+                }
+                const uint64_t wm = wave_min_u64(mk);
+                bk = wm < bk ? wm : bk;
+                if (m) {
+                    m &= __ballot(lb < bk);             // drop boxes the tighter bound now rules out
+                    if (tn >= 0 && !((m >> tn) & 1ull)) {
+                        tn = m ? __ffsll((long long)m) - 1 : -1;
+                        if (tn >= 0) fetch(tn);
+                    }
                 }
             }
+            mc &= __ballot(lc < bk);                    // and chunks
         }
     }
     // lexicographic (key, position) minimum over the wave

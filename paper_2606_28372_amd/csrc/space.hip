@@ -294,6 +294,31 @@ __global__ __launch_bounds__(kBlock) void k_boxes(DevSpace S, uint8_t* __restric
     }
 }
 
+// Per 64 boxes (4096 rows), the smallest box minimum and the largest box maximum of every
+// parameter: the level above the boxes, so a scan can rule out 64 boxes with one bound.
+__global__ __launch_bounds__(kBlock) void k_chunks(DevSpace S, uint8_t* __restrict__ chunks) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t ck = (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (ck >= S.n_chunk) return;
+    const uint64_t b = ck * 64u + lane;
+    const uint64_t src = (b < S.n_sub ? b : ck * 64u) * 2u * S.R;
+    Row lo_r, hi_r;
+    row_load(lo_r, S.boxes + src, S.R);
+    row_load(hi_r, S.boxes + src + S.R, S.R);
+    for (uint32_t j = 0; j < S.R; ++j) {
+        uint32_t lo = j < S.D ? lo_r.digit(j) : 0u, hi = j < S.D ? hi_r.digit(j) : 0u;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, 64));
+            hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
+        }
+        if (lane == 0) {
+            chunks[ck * 2u * S.R + j] = (uint8_t)lo;
+            chunks[ck * 2u * S.R + S.R + j] = (uint8_t)hi;
+        }
+    }
+}
+
 // Which value indices of each parameter occur in some solution, then the
 // nearest present index below/above each index ("adjacent" neighbour rule).
 __global__ __launch_bounds__(kBlock) void k_presence(DevSpace S, uint32_t* __restrict__ present /*[D][8]*/) {
@@ -375,7 +400,7 @@ uint64_t space_resident_bytes(const ct_space* s, uint64_t n_valid) {
     b += nv * (8u + S.R);                                                  // linear indices + rows
     b += (uint64_t)S.D * 256u * 2u;                                        // prev/next present values
     b += n_groups * 8u + (n_words_alloc / 8u) * 2u;                        // rank directory
-    b += std::max<uint64_t>((n_valid + 63u) / 64u, 1) * 2u * S.R;          // 64-row bounding boxes
+    b += (std::max<uint64_t>((n_valid + 63u) / 64u, 1) + (n_valid + 4095u) / 4096u) * 2u * S.R;  // boxes + chunks
     b += s->values.size() * 8u + std::max<size_t>(s->code.size(), 1) * 4u + sizeof(DevSpace);
     return b;
 }
@@ -453,7 +478,9 @@ int space_build_device(ct_space* s, hipStream_t st) {
     CT_HIP(hipMalloc(&s->d_grp_off, n_groups * sizeof(uint64_t)));
     CT_HIP(hipMalloc(&s->d_dir8, (n_words_alloc / 8) * sizeof(uint16_t)));
     S.n_sub = (total + 63u) / 64u;
-    CT_HIP(hipMalloc(&s->d_boxes, std::max<uint64_t>(S.n_sub, 1) * 2u * S.R));
+    S.n_chunk = (S.n_sub + 63u) / 64u;
+    // boxes, then the chunk level in the same allocation
+    CT_HIP(hipMalloc(&s->d_boxes, (std::max<uint64_t>(S.n_sub, 1) + S.n_chunk) * 2u * S.R));
     if (total) {
         { ProfScope ps_("k_compact", st); hipLaunchKernelGGL(k_compact, dim3(grid_for(n_groups, kWavesPerBlock)), dim3(kBlock), 0, st, S, s->d_words,
                            s->n_words, d_counts, d_off, n_groups, s->d_lin, s->d_rows, s->d_grp_off, s->d_dir8); }
@@ -465,8 +492,10 @@ int space_build_device(ct_space* s, hipStream_t st) {
     S.grp_off = s->d_grp_off;
     S.dir8 = s->d_dir8;
     S.boxes = s->d_boxes;
+    S.chunks = s->d_boxes + std::max<uint64_t>(S.n_sub, 1) * 2u * S.R;
     if (total) {
         { ProfScope ps_("k_boxes", st); hipLaunchKernelGGL(k_boxes, dim3(grid_for(S.n_sub, kWavesPerBlock)), dim3(kBlock), 0, st, S, s->d_boxes); }
+        { ProfScope ps_("k_chunks", st); hipLaunchKernelGGL(k_chunks, dim3(grid_for(S.n_chunk, kWavesPerBlock)), dim3(kBlock), 0, st, S, s->d_boxes + std::max<uint64_t>(S.n_sub, 1) * 2u * S.R); }
     }
     if (total) {
         { ProfScope ps_("k_presence", st); hipLaunchKernelGGL(k_presence, dim3(grid_for(total, kBlock, 1024)), dim3(kBlock), 0, st, S, d_present); }
