@@ -47,6 +47,16 @@ __device__ __forceinline__ uint32_t ne_bytes(uint32_t x) {
     return ((((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u);
 }
 
+// 0x80 in every byte where x < y (unsigned bytes): z's high bit says whether the low seven bits
+// of x reach those of y (no borrow crosses a byte), the high bits of x and y decide the rest
+__device__ __forceinline__ uint32_t lt_bytes(uint32_t x, uint32_t y) {
+    const uint32_t z = (x | 0x80808080u) - (y & 0x7F7F7F7Fu);
+    return ((~x & y) | (~(x ^ y) & ~z)) & 0x80808080u;
+}
+
+// 0xFF in every byte whose high bit is set in m (m holds only 0x80 or 0x00 bytes)
+__device__ __forceinline__ uint32_t byte_mask(uint32_t m) { return m | (m - (m >> 7)); }
+
 __device__ __forceinline__ uint32_t wave_lane() { return threadIdx.x & 63u; }
 __device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
@@ -238,39 +248,41 @@ struct Cand {
             }
             return (both - span) >> 1;
         }
-        uint32_t miss = 0, sum = 0, far = 0;
+        // Four digits per 32-bit word (SWAR): per-byte comparisons give 0x80 in the bytes where
+        // they hold.  Padding digits are 0 in the candidate and in both box rows: they add nothing.
+        uint32_t miss = 0, far = 0;
         bool adj_ok = true;
         uint64_t e2 = 0;
 #pragma unroll
         for (int k = 0; k < RW; ++k) {
-            const uint32_t lw = lo32[k], hw = hi32[k];
+            const uint32_t a = lo32[k], b = hi32[k], ck = c[k];
+            const uint32_t out = lt_bytes(ck, a) | lt_bytes(b, ck);          // digit outside [a, b]
+            miss += __popc(out);
+            if constexpr (M == CT_TIER_EUCLID || M == CT_TIER_RANDOM) {
+                // more than one index away: c + 1 < a or b + 1 < c (digits are at most 254, so
+                // adding 1 to every byte never carries)
+                far += __popc(lt_bytes(ck + 0x01010101u, a) | lt_bytes(b + 0x01010101u, ck));
+                if (!adj_is_sa) {
+                    // an adjacent value inside the box for every digit outside it; "none" is 0xFF,
+                    // above every box bound (radices are at most 255)
+                    const uint32_t p_in = ~(lt_bytes(pv[k], a) | lt_bytes(b, pv[k]));
+                    const uint32_t n_in = ~(lt_bytes(nx[k], a) | lt_bytes(b, nx[k]));
+                    adj_ok &= (out & ~(p_in | n_in)) == 0u;
+                }
+            }
+            if constexpr (M == CT_TIER_EUCLID) {
+                // squared distance from the particle to the nearest value centre inside [a, b]:
+                // the table at clamp(s_j, a_j, b_j)
+                const uint32_t m_lo = byte_mask(lt_bytes(s[k], a));
+                const uint32_t t1 = (a & m_lo) | (s[k] & ~m_lo);
+                const uint32_t m_hi = byte_mask(lt_bytes(b, t1));
+                const uint32_t t = (b & m_hi) | (t1 & ~m_hi);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                // padding digits are 0 in the candidate and in both box rows, so they add nothing
-                const int32_t cj = (int32_t)((c[k] >> (q * 8)) & 0xFFu);
-                const int32_t a = (int32_t)((lw >> (q * 8)) & 0xFFu), b = (int32_t)((hw >> (q * 8)) & 0xFFu);
-                const uint32_t d = (uint32_t)max(max(a - cj, cj - b), 0);
-                miss += d != 0u;
-                sum += d;
-                far += d > 1u;
-                if constexpr (M == CT_TIER_EUCLID || M == CT_TIER_RANDOM) {
-                    if (!adj_is_sa && d != 0u) {
-                        // "none" is 0xFF, above every box bound (radices are at most 255)
-                        const int32_t p = (int32_t)((pv[k] >> (q * 8)) & 0xFFu);
-                        const int32_t n = (int32_t)((nx[k] >> (q * 8)) & 0xFFu);
-                        adj_ok &= (p >= a && p <= b) || (n >= a && n <= b);
-                    }
-                }
-                if constexpr (M == CT_TIER_EUCLID) {
-                    // squared distance from the particle to the nearest value centre inside [a, b]
-                    const uint32_t j = (uint32_t)(k * 4 + q);
-                    const int32_t sj = (int32_t)((s[k] >> (q * 8)) & 0xFFu);
-                    e2 += tab[(uint32_t)min(max(sj, a), b) * (RW * 4) + j];
-                }
+                for (int q = 0; q < 4; ++q)
+                    e2 += tab[((t >> (q * 8)) & 0xFFu) * (RW * 4) + (uint32_t)(k * 4 + q)];
             }
         }
         if constexpr (M == CT_HAMMING) return miss;
-        else if constexpr (M == CT_INDEX_L1) return sum;
         else if constexpr (M == CT_HAM1_RANDOM) return miss <= 1u ? 0ull : kNoKey;
         else {
             const uint64_t sub = M == CT_TIER_EUCLID ? e2 : 0ull;
