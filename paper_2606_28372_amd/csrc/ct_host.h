@@ -102,11 +102,13 @@ __host__ __device__ inline uint32_t repair_class(uint32_t metric, uint32_t R) {
     return metric * 4u + (R <= 4 ? 0u : R <= 8 ? 1u : R <= 16 ? 2u : 3u);
 }
 
-// Device-side plan of one scan pass over a set array (written by k_repair_plan).
+// Device-side plan of one scan pass over a set array (written by the last block of the kernel
+// before the scans: proposal, preparation or main finish).
 struct RepairPlan {
     uint32_t* cand_off;               // [n_sets + 1] prefix of candidate counts
     uint32_t* item_off;               // [kRepairClasses][n_sets + 1] prefix of (candidate, part) items per class
     uint32_t* parts;                  // [n_sets]
+    uint32_t* done;                   // blocks finished in the kernel that plans (0 between launches)
 };
 
 constexpr uint32_t kRepairTargetWaves = 8192;   // scan items per pass (also the per-set slot minimum)
@@ -151,9 +153,12 @@ struct RepairPasses {
     RepairPlan plan{};
 };
 int repair_plan_alloc(RepairPlan& p, uint32_t n_sets, std::vector<void*>& owned);
+struct PlanArgs;
+PlanArgs main_plan(const RepairPasses& rp);   // what plans the main scans of a pass
 // prep + scan + finish (+ Hamming fallback for tiered metrics); `zero_counts` clears the
 // sets' counters with a kernel first (the step sequence clears them in its selection kernel);
-// prep = false when the candidates were already listed (the step's propose kernel does it).
+// prep = false when the candidates were already listed and the main scans planned (the step's
+// propose kernel does both).
 int launch_repair_passes(const RepairPasses& rp, bool zero_counts, hipStream_t st, bool count_tally = true,
                          bool prep = true);
 

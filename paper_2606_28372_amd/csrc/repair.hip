@@ -32,6 +32,7 @@
 #include <algorithm>
 
 #include "ct_host.h"
+#include "repair_plan.h"
 
 namespace {
 
@@ -509,7 +510,7 @@ __global__ void k_repair_zero(const RepairSet* __restrict__ sets, uint32_t n_set
 
 // Validity from the bitmask, rank from the directory, list of the candidates that need a scan.
 __global__ __launch_bounds__(kBlock) void k_repair_prep(const RepairSet* __restrict__ sets, uint32_t n_sets,
-                                                        const uint32_t* __restrict__ prep_off) {
+                                                        const uint32_t* __restrict__ prep_off, PlanArgs pa) {
     const uint32_t total = prep_off[n_sets];
     for (uint32_t item = blockIdx.x * blockDim.x + threadIdx.x; item < total; item += gridDim.x * blockDim.x) {
         const uint32_t s = find_set(prep_off, n_sets, item);
@@ -530,92 +531,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_prep(const RepairSet* __restr
             J.list_L[k] = L;
         }
     }
-}
-
-__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t lane) {
-    uint32_t x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o, 64);
-        if (lane >= (uint32_t)o) x += y;
-    }
-    return x - v;
-}
-
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// One wave: per-set candidate counts -> parts and item offsets of one scan pass.  Lane l owns
-// a contiguous slice of the sets; offsets are the wave prefix of the lanes' totals plus the
-// running sum inside the slice.  which = 0: main lists with each set's metric; which = 1:
-// fallback lists, Hamming.  Each scan class is its own launch, so its candidates are split
-// into parts to give that launch about target_items items, each part min_sub boxes or more.
-__global__ __launch_bounds__(64) void k_repair_plan(const RepairSet* __restrict__ sets, uint32_t n_sets,
-                                                    uint32_t which, RepairPlan plan, uint32_t class_mask,
-                                                    uint32_t target_items, uint32_t min_sub) {
-    const uint32_t lane = threadIdx.x;
-    const uint32_t chunk = (n_sets + 63u) / 64u;
-    const uint32_t s0 = min(n_sets, lane * chunk), s1 = min(n_sets, s0 + chunk);
-    uint32_t acc[kNumClasses];
-#pragma unroll
-    for (uint32_t q = 0; q < kNumClasses; ++q) acc[q] = 0;
-    for (uint32_t s = s0; s < s1; ++s) {
-        const uint32_t cls = repair_class(which ? (uint32_t)CT_HAMMING : sets[s].metric, sets[s].S->R);
-        const uint32_t c = sets[s].count[which];
-#pragma unroll
-        for (uint32_t q = 0; q < kNumClasses; ++q) acc[q] += q == cls ? c : 0u;
-    }
-    uint32_t gpc[kNumClasses];
-#pragma unroll
-    for (uint32_t q = 0; q < kNumClasses; ++q) {
-        gpc[q] = 1u;
-        if (class_mask & (1u << q)) {
-            const uint32_t total = wave_sum_u32(acc[q]);
-            gpc[q] = total ? max(target_items / total, 1u) : 1u;
-        }
-    }
-    uint32_t tc = 0;
-#pragma unroll
-    for (uint32_t q = 0; q < kNumClasses; ++q) acc[q] = 0;
-    for (uint32_t s = s0; s < s1; ++s) {
-        const uint64_t pmax = sets[s].S->n_sub / min_sub;
-        const uint32_t cls = repair_class(which ? (uint32_t)CT_HAMMING : sets[s].metric, sets[s].S->R);
-        uint32_t gp = gpc[0];
-#pragma unroll
-        for (uint32_t q = 1; q < kNumClasses; ++q) gp = q == cls ? gpc[q] : gp;
-        uint64_t p = gp > pmax ? pmax : gp;
-        if (p < 1 || cls / 4u == (uint32_t)CT_HAM1_RANDOM) p = 1;   // enumerated, not scanned
-        plan.parts[s] = (uint32_t)p;
-        const uint32_t c = sets[s].count[which];
-        tc += c;
-#pragma unroll
-        for (uint32_t q = 0; q < kNumClasses; ++q) acc[q] += q == cls ? c * (uint32_t)p : 0u;
-    }
-    uint32_t oc = wave_excl_scan(tc, lane);
-#pragma unroll
-    for (uint32_t q = 0; q < kNumClasses; ++q)
-        if (class_mask & (1u << q)) acc[q] = wave_excl_scan(acc[q], lane);
-    for (uint32_t s = s0; s < s1; ++s) {
-        const uint32_t p = plan.parts[s];
-        const uint32_t c = sets[s].count[which];
-        const uint32_t cls = repair_class(which ? (uint32_t)CT_HAMMING : sets[s].metric, sets[s].S->R);
-        plan.cand_off[s] = oc;
-#pragma unroll
-        for (uint32_t q = 0; q < kNumClasses; ++q)
-            if (class_mask & (1u << q)) plan.item_off[q * (n_sets + 1) + s] = acc[q];
-        oc += c;
-#pragma unroll
-        for (uint32_t q = 0; q < kNumClasses; ++q) acc[q] += q == cls ? c * p : 0u;
-    }
-    if (lane == 63) {
-        plan.cand_off[n_sets] = oc;
-#pragma unroll
-        for (uint32_t q = 0; q < kNumClasses; ++q)
-            if (class_mask & (1u << q)) plan.item_off[q * (n_sets + 1) + n_sets] = acc[q];
-    }
+    plan_if_last(sets, n_sets, pa);
 }
 
 template <int M, int RW>
@@ -686,10 +602,18 @@ __global__ __launch_bounds__(kBlock) void k_repair_scan_mix(const RepairSet* __r
     }
 }
 
+// The plan as a launch of its own (one wave).
+__global__ __launch_bounds__(64) void k_repair_plan(const RepairSet* __restrict__ sets, uint32_t n_sets, uint32_t which,
+                                                    RepairPlan plan, uint32_t class_mask, uint32_t target_items,
+                                                    uint32_t min_sub) {
+    plan_wave(sets, n_sets, which, plan, class_mask, target_items, min_sub);
+}
+
 // Reduce the parts of every candidate (one wave per candidate) and write the result.  In the main
 // pass of a tiered set, candidates without a tier 0-2 neighbour go to the fallback list.
 __global__ __launch_bounds__(kBlock) void k_repair_finish(const RepairSet* __restrict__ sets, uint32_t n_sets,
-                                                          RepairPlan plan, uint32_t which, uint32_t count_tally) {
+                                                          RepairPlan plan, uint32_t which, uint32_t count_tally,
+                                                          PlanArgs pa) {
     const uint32_t total = plan.cand_off[n_sets];
     const uint32_t lane = wave_lane();
     const uint32_t waves = gridDim.x * (kBlock / 64);
@@ -727,6 +651,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_finish(const RepairSet* __res
             J.fb_L[k] = ~0ull;           // no seed: the fallback scans the whole list
         }
     }
+    plan_if_last(sets, n_sets, pa);
 }
 
 template <int M, int RW>
@@ -847,14 +772,20 @@ void fan_destroy(StreamFan* f) {
 int repair_plan_alloc(RepairPlan& p, uint32_t n_sets, std::vector<void*>& owned) {
     if (n_sets > kMaxSets) return ct_fail(CT_EINVAL, "repair: at most 4096 candidate sets per launch");
     void* a = nullptr;
-    const size_t words = (size_t)(n_sets + 1) * (1 + kNumClasses) + n_sets;
+    const size_t words = (size_t)(n_sets + 1) * (1 + kNumClasses) + n_sets + 1;
     CT_HIP(hipMalloc(&a, words * sizeof(uint32_t)));
     owned.push_back(a);
     uint32_t* w = static_cast<uint32_t*>(a);
     p.cand_off = w;
     p.item_off = w + (n_sets + 1);
     p.parts = w + (n_sets + 1) * (1 + kNumClasses);
+    p.done = p.parts + n_sets;
+    CT_HIP(hipMemset(p.done, 0, sizeof(uint32_t)));
     return CT_OK;
+}
+
+PlanArgs main_plan(const RepairPasses& rp) {
+    return PlanArgs{rp.plan, rp.class_mask, rp.tune.items, rp.tune.min_sub, 0u, 1u};
 }
 
 int launch_repair_passes(const RepairPasses& rp, bool zero_counts, hipStream_t st, bool count_tally, bool prep) {
@@ -864,23 +795,22 @@ int launch_repair_passes(const RepairPasses& rp, bool zero_counts, hipStream_t s
         hipLaunchKernelGGL(k_repair_zero, dim3((rp.n_sets + 255) / 256), dim3(256), 0, st, rp.d_sets, rp.n_sets);
     }
     if (prep) {
+        // the preparation's last block plans the main scans
         ProfScope ps_("k_repair_prep", st);
         const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>((rp.total_n + kBlock - 1) / kBlock, 4096));
-        hipLaunchKernelGGL(k_repair_prep, dim3(g), dim3(kBlock), 0, st, rp.d_sets, rp.n_sets, rp.d_prep_off);
-    }
-    {
-        ProfScope ps_("k_repair_plan", st);
-        hipLaunchKernelGGL(k_repair_plan, dim3(1), dim3(64), 0, st, rp.d_sets, rp.n_sets, 0u, rp.plan, rp.class_mask,
-                           rp.tune.items, rp.tune.min_sub);
+        hipLaunchKernelGGL(k_repair_prep, dim3(g), dim3(kBlock), 0, st, rp.d_sets, rp.n_sets, rp.d_prep_off,
+                           main_plan(rp));
     }
     if (int rc = launch_scans(rp, rp.class_mask, 0, st)) return rc;
     {
         ProfScope ps_("k_repair_finish", st);
         hipLaunchKernelGGL(k_repair_finish, dim3(finish_grid(rp.total_n)), dim3(kBlock), 0, st, rp.d_sets, rp.n_sets,
-                           rp.plan, 0u, count_tally ? 1u : 0u);
+                           rp.plan, 0u, count_tally ? 1u : 0u, PlanArgs{});
     }
     if (rp.fb_class_mask) {
         {
+            // a launch of its own: the finish runs hundreds of blocks, and counting them all
+            // costs more than a one-wave launch
             ProfScope ps_("k_repair_plan", st);
             hipLaunchKernelGGL(k_repair_plan, dim3(1), dim3(64), 0, st, rp.d_sets, rp.n_sets, 1u, rp.plan,
                                rp.fb_class_mask, rp.tune.items, rp.tune.min_sub);
@@ -889,7 +819,7 @@ int launch_repair_passes(const RepairPasses& rp, bool zero_counts, hipStream_t s
         {
             ProfScope ps_("k_repair_finish", st);
             hipLaunchKernelGGL(k_repair_finish, dim3(finish_grid(rp.total_n)), dim3(kBlock), 0, st, rp.d_sets,
-                               rp.n_sets, rp.plan, 1u, 0u);
+                               rp.n_sets, rp.plan, 1u, 0u, PlanArgs{});
         }
     }
     CT_HIP(hipGetLastError());

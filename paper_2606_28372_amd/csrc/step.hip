@@ -26,6 +26,7 @@
 #include <chrono>
 
 #include "ct_host.h"
+#include "repair_plan.h"
 
 namespace {
 
@@ -301,7 +302,7 @@ __device__ __forceinline__ void list_for_repair(const PopDev& p, const RepairSet
 // generation's selection (or at creation), never by a memset node inside a captured graph.
 __global__ __launch_bounds__(kBlock) void k_propose(const PopDev* __restrict__ pops, uint32_t n,
                                                     const uint32_t* __restrict__ ind_off,
-                                                    const RepairSet* __restrict__ sets) {
+                                                    const RepairSet* __restrict__ sets, PlanArgs pa) {
     const uint32_t total = ind_off[n];
     for (uint32_t item = blockIdx.x * blockDim.x + threadIdx.x; item < total; item += gridDim.x * blockDim.x) {
         const uint32_t r = find_run(ind_off, n, item);
@@ -311,6 +312,7 @@ __global__ __launch_bounds__(kBlock) void k_propose(const PopDev* __restrict__ p
         const Row u = p.algo == CT_DE ? de_propose(p, i, g) : p.algo == CT_PSO ? pso_propose(p, i, g) : ga_propose(p, i, g);
         list_for_repair(p, sets[r], i, u);
     }
+    plan_if_last(sets, n, pa);                          // the last block plans the main scans
 }
 
 // ---------------------------------------------------------------------------
@@ -493,7 +495,8 @@ int batch_generation(ct_batch* b, hipStream_t st) {
     {
         ProfScope ps_("k_propose", st);
         const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>((b->total_ind + kBlock - 1) / kBlock, 4096));
-        hipLaunchKernelGGL(k_propose, dim3(g), dim3(kBlock), 0, st, b->d_pops, b->n, b->d_ind_off, b->passA.d_sets);
+        hipLaunchKernelGGL(k_propose, dim3(g), dim3(kBlock), 0, st, b->d_pops, b->n, b->d_ind_off, b->passA.d_sets,
+                           main_plan(b->passA));
     }
     int rc = launch_repair_passes(b->passA, false, st, true, false);
     if (rc) return rc;
@@ -573,7 +576,9 @@ int autotune_generation(ct_batch* b, hipStream_t st) {
     if (b->n_ga) hipLaunchKernelGGL(k_ga_sort, dim3(b->n), dim3(kSelBlock), 0, st, b->d_pops, b->n);
     {
         const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>((b->total_ind + kBlock - 1) / kBlock, 4096));
-        hipLaunchKernelGGL(k_propose, dim3(g), dim3(kBlock), 0, st, b->d_pops, b->n, b->d_ind_off, b->passA.d_sets);
+        // the sweep lists and plans again for every candidate
+        hipLaunchKernelGGL(k_propose, dim3(g), dim3(kBlock), 0, st, b->d_pops, b->n, b->d_ind_off, b->passA.d_sets,
+                           PlanArgs{});
     }
     CT_HIP(hipGetLastError());
     int rc = autotune_sweep(b, st);
