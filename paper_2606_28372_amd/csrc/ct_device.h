@@ -68,14 +68,20 @@ __device__ __forceinline__ bool bit_valid(const DevSpace& S, uint64_t L) {
 }
 
 // Number of valid configurations with linear index below L (the rank of L when it is valid),
-// from the group offsets, the 8-word directory and at most 8 word popcounts.
+// from the group offsets, the 8-word directory and at most 8 word popcounts.  The word loads are
+// unrolled and predicated, so they are in flight together rather than one after another.
 __device__ __forceinline__ uint64_t rank_dir(const DevSpace& S, uint64_t L) {
     if (L >= S.N) return S.n_valid;
-    const uint64_t w = L >> 6;
+    const uint64_t w = L >> 6, q0 = w & ~7ull;
     const CT_GLOBAL uint64_t* words = gptr(S.words);
     uint64_t r = gld(S.grp_off + (w >> 6)) + gld(S.dir8 + (w >> 3));
-    for (uint64_t q = w & ~7ull; q < w; ++q) r += __popcll(words[q]);
-    return r + __popcll(words[w] & ((1ull << (L & 63u)) - 1ull));
+#pragma unroll
+    for (uint32_t t = 0; t < 8; ++t) {
+        const uint64_t q = q0 + t;
+        const uint64_t word = q <= w ? words[q] : 0ull;
+        r += __popcll(q < w ? word : word & ((1ull << (L & 63u)) - 1ull));
+    }
+    return r;
 }
 
 // ---------------------------------------------------------------------------

@@ -648,7 +648,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_finish(const RepairSet* __res
         } else if (which == 0 && tiered_metric(J.metric) && lane == 0) {
             const uint32_t k = atomicAdd(&J.count[1], 1u);
             J.fb_list[k] = ci;
-            J.fb_L[k] = ~0ull;           // no seed: the fallback scans the whole list
+            J.fb_L[k] = J.list_L[li];     // the fallback seeds its bound around the same place
         }
     }
     plan_if_last(sets, n_sets, pa);
