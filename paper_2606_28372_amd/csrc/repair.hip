@@ -522,9 +522,10 @@ __global__ __launch_bounds__(kBlock) void k_repair_prep(const RepairSet* __restr
         const bool dom = row_in_domain(S, c);
         const uint64_t L = dom ? row_encode(S, c) : ~0ull;
         const bool valid = dom && bit_valid(S, L);
-        row_store(c, J.out_rows + (uint64_t)i * S.R, S.R);
-        J.out_pos[i] = valid ? (uint32_t)rank_dir(S, L) : kNoPos;
+        const uint32_t pos = valid ? (uint32_t)rank_dir(S, L) : kNoPos;    // loads before any store
         const bool act = J.apply == nullptr || J.apply[i];
+        row_store(c, J.out_rows + (uint64_t)i * S.R, S.R);
+        J.out_pos[i] = pos;
         if (act && (J.metric == CT_HAM1_RANDOM || !valid)) {
             const uint32_t k = atomicAdd(&J.count[0], 1u);
             J.list[k] = i;

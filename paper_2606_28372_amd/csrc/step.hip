@@ -217,6 +217,10 @@ __device__ Row pso_propose(const PopDev& p, uint32_t i, uint32_t g) {
     Row c;
 #pragma unroll
     for (int q = 0; q < CT_DMAX / 4; ++q) c.w[q] = 0;
+    // every load first, every store after: a store before a load would make the load's wait
+    // (one in-order counter for both) wait for the store too, one round trip per parameter
+    int32_t x_new[CT_DMAX];
+    int64_t v_new[CT_DMAX];
 #pragma unroll
     for (uint32_t j = 0; j < CT_DMAX; ++j) {
         if (j >= p.D) break;
@@ -229,10 +233,17 @@ __device__ Row pso_propose(const PopDev& p, uint32_t i, uint32_t g) {
             ((((p.c2_q16 * r2) >> 16) * (gb - x)) >> 16);
         x += v;
         x = x < 0 ? 0 : (x > xmax ? xmax : x);
-        p.V[k] = v;
-        p.X[k] = (int32_t)x;
+        x_new[j] = (int32_t)x;
+        v_new[j] = v;
         const uint32_t d = (uint32_t)(x >> 16);
         c.set(j, d < p.S->radix[j] ? d : p.S->radix[j] - 1u);
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < CT_DMAX; ++j) {
+        if (j >= p.D) break;
+        const uint64_t k = (uint64_t)i * p.D + j;
+        p.V[k] = v_new[j];
+        p.X[k] = x_new[j];
     }
     row_store(c, p.trial + (uint64_t)i * p.R, p.R);
     return c;
@@ -288,8 +299,9 @@ __device__ __forceinline__ void list_for_repair(const PopDev& p, const RepairSet
     }
     if (!dom) L = ~0ull;
     const bool valid = dom && bit_valid(S, L);
+    const uint32_t pos = valid ? (uint32_t)rank_dir(S, L) : 0xFFFFFFFFu;   // loads before any store
     row_store(u, J.out_rows + (uint64_t)i * p.R, p.R);
-    J.out_pos[i] = valid ? (uint32_t)rank_dir(S, L) : 0xFFFFFFFFu;
+    J.out_pos[i] = pos;
     if (!valid) {
         const uint32_t k = atomicAdd(&J.count[0], 1u);
         J.list[k] = i;
