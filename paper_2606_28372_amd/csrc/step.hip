@@ -170,161 +170,192 @@ __device__ __forceinline__ void sort3(uint32_t* e, uint32_t n) {
         }
 }
 
-__device__ Row de_propose(const PopDev& p, uint32_t i, uint32_t g) {
-    U4 o = ct_philox(p.seed, i, g, (uint32_t)PUR_DE_PICK << 24, 0);
-    uint32_t ex[3] = {i, 0, 0};
-    const uint32_t r1 = pick_excl(o.x, p.P, ex, 1);
-    ex[1] = r1;
-    sort3(ex, 2);
-    const uint32_t r2 = pick_excl(o.y, p.P, ex, 2);
-    ex[2] = r2;
-    sort3(ex, 3);
-    const uint32_t r3 = pick_excl(o.z, p.P, ex, 3);
-    const uint32_t jr = ct_below(o.w, p.D);
-    Row base, x, a, b, u;
-    valid_row(p, p.de_best ? (uint32_t)(*p.best & 0xFFFFFFFFu) : p.pos[r1], base);
-    valid_row(p, p.pos[i], x);
-    valid_row(p, p.pos[r2], a);
-    valid_row(p, p.pos[r3], b);
-    u = x;
-    // words of 4 digits, one Philox block per word (draw t of block j/4 decides digit j); both
-    // loops unrolled so every digit index is a compile-time constant and the rows stay in registers
+// ---------------------------------------------------------------------------
+// One group of G lanes per individual (G = 4 or 16), lane s owning digits s, s + G, s + 2G, ...:
+// the digits of a proposal are independent given the individual's shared draws, so the per-digit
+// work (a Philox block per PSO dimension, the DE mixing, the GA crossover) runs side by side
+// instead of one digit after another in a single thread.  Words are assembled with quad
+// shuffles, the linear index and the rank with group reductions.  Small batches take G = 16
+// (latency: one digit or two per lane); large ones G = 4, since every lane of a group repeats
+// the individual's shared draws and the device is then busy with other individuals anyway.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kWideGroupMax = 16384;   // individuals up to which a group has 16 lanes
+
+template <uint32_t G>
+__device__ __forceinline__ uint32_t grp_or4(uint32_t v) {
+    v |= __shfl_xor(v, 1, G);
+    v |= __shfl_xor(v, 2, G);
+    return v;
+}
+template <uint32_t G>
+__device__ __forceinline__ uint64_t grp_sum64(uint64_t v) {
 #pragma unroll
-    for (uint32_t q = 0; q < CT_DMAX / 4; ++q) {
-        if (q * 4u >= p.D) break;
-        const U4 cr = ct_philox(p.seed, i, g, ((uint32_t)PUR_DE_CR << 24) | q, 0);
-#pragma unroll
-        for (uint32_t t = 0; t < 4; ++t) {
-            const uint32_t j = q * 4u + t;
-            if (j < p.D) {
-                const int64_t num = (int64_t)base.digit(j) * 65536 +
-                                    (int64_t)p.F_q16 * ((int64_t)a.digit(j) - (int64_t)b.digit(j)) + 32768;
-                int64_t m = num >> 16;            // floor
-                const int64_t hi = (int64_t)p.S->radix[j] - 1;
-                m = m < 0 ? 0 : (m > hi ? hi : m);
-                const uint32_t cu = t == 0 ? cr.x : t == 1 ? cr.y : t == 2 ? cr.z : cr.w;
-                if ((uint64_t)cu < p.CR_q32 || j == jr) u.set(j, (uint32_t)m);
-            }
-        }
+    for (int o = 1; o < (int)G; o <<= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)v, o, G), hi = __shfl_xor((uint32_t)(v >> 32), o, G);
+        v += ((uint64_t)hi << 32) | lo;
     }
-    row_store(u, p.trial + (uint64_t)i * p.R, p.R);
-    return u;
+    return v;
 }
 
-__device__ Row pso_propose(const PopDev& p, uint32_t i, uint32_t g) {
-    const uint32_t gi = p.state[2];
-    const int64_t xmax = (int64_t)p.M * 65536 - 1;
-    Row c;
-#pragma unroll
-    for (int q = 0; q < CT_DMAX / 4; ++q) c.w[q] = 0;
-    // every load first, every store after: a store before a load would make the load's wait
-    // (one in-order counter for both) wait for the store too, one round trip per parameter
-    int32_t x_new[CT_DMAX];
-    int64_t v_new[CT_DMAX];
-#pragma unroll
-    for (uint32_t j = 0; j < CT_DMAX; ++j) {
-        if (j >= p.D) break;
-        U4 o = ct_philox(p.seed, i, g, ((uint32_t)PUR_PSO_R << 24) | j, 0);
-        const int64_t r1 = o.x >> 16, r2 = o.y >> 16;
-        const uint64_t k = (uint64_t)i * p.D + j;
-        int64_t x = p.X[k], v = p.V[k];
-        const int64_t pb = p.PB[k], gb = p.PB[(uint64_t)gi * p.D + j];
-        v = ((p.w_q16 * v) >> 16) + ((((p.c1_q16 * r1) >> 16) * (pb - x)) >> 16) +
-            ((((p.c2_q16 * r2) >> 16) * (gb - x)) >> 16);
-        x += v;
-        x = x < 0 ? 0 : (x > xmax ? xmax : x);
-        x_new[j] = (int32_t)x;
-        v_new[j] = v;
-        const uint32_t d = (uint32_t)(x >> 16);
-        c.set(j, d < p.S->radix[j] ? d : p.S->radix[j] - 1u);
-    }
-#pragma unroll
-    for (uint32_t j = 0; j < CT_DMAX; ++j) {
-        if (j >= p.D) break;
-        const uint64_t k = (uint64_t)i * p.D + j;
-        p.V[k] = v_new[j];
-        p.X[k] = x_new[j];
-    }
-    row_store(c, p.trial + (uint64_t)i * p.R, p.R);
-    return c;
+__device__ __forceinline__ uint32_t row_digit(const DevSpace& S, uint32_t pos, uint32_t R, uint32_t j) {
+    return gld(S.rows + (uint64_t)pos * R + j);
 }
 
 __device__ __forceinline__ uint32_t beta_rank(const PopDev& p, uint32_t u) {
     uint32_t lo = 0, hi = p.P - 1;
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
-        if ((uint64_t)u < p.beta[mid]) hi = mid; else lo = mid + 1;
+        if ((uint64_t)u < gld(p.beta + mid)) hi = mid; else lo = mid + 1;
     }
     return lo;
 }
 
-// child i of pair i/2: A[:cut] + B[cut:] for even i, B[:cut] + A[cut:] for odd i
-__device__ Row ga_propose(const PopDev& p, uint32_t i, uint32_t g) {
+// The new digit j (< D) of individual i of run p in generation g.  Every lane of the group
+// computes the individual's shared draws itself (same counters, same values).
+__device__ __forceinline__ uint32_t propose_digit(const PopDev& p, const DevSpace& S, uint32_t i, uint32_t g,
+                                                  uint32_t j) {
+    const uint32_t radix = gld(&S.radix[j]);
+    if (p.algo == CT_DE) {
+        U4 o = ct_philox(p.seed, i, g, (uint32_t)PUR_DE_PICK << 24, 0);
+        uint32_t ex[3] = {i, 0, 0};
+        const uint32_t r1 = pick_excl(o.x, p.P, ex, 1);
+        ex[1] = r1;
+        sort3(ex, 2);
+        const uint32_t r2 = pick_excl(o.y, p.P, ex, 2);
+        ex[2] = r2;
+        sort3(ex, 3);
+        const uint32_t r3 = pick_excl(o.z, p.P, ex, 3);
+        const uint32_t jr = ct_below(o.w, p.D);
+        const uint32_t pb = p.de_best ? (uint32_t)(gld(p.best) & 0xFFFFFFFFu) : gld(p.pos + r1);
+        const uint32_t base = row_digit(S, pb, p.R, j), x = row_digit(S, gld(p.pos + i), p.R, j);
+        const uint32_t a = row_digit(S, gld(p.pos + r2), p.R, j), b = row_digit(S, gld(p.pos + r3), p.R, j);
+        // block j/4 of the crossover draws, draw j%4 of it
+        const U4 cr = ct_philox(p.seed, i, g, ((uint32_t)PUR_DE_CR << 24) | (j >> 2), 0);
+        const uint32_t t = j & 3u;
+        const uint32_t cu = t == 0 ? cr.x : t == 1 ? cr.y : t == 2 ? cr.z : cr.w;
+        const int64_t num = (int64_t)base * 65536 + (int64_t)p.F_q16 * ((int64_t)a - (int64_t)b) + 32768;
+        int64_t m = num >> 16;            // floor
+        const int64_t hi = (int64_t)radix - 1;
+        m = m < 0 ? 0 : (m > hi ? hi : m);
+        return ((uint64_t)cu < p.CR_q32 || j == jr) ? (uint32_t)m : x;
+    }
+    if (p.algo == CT_PSO) {
+        const uint32_t gi = gld(p.state + 2);
+        const int64_t xmax = (int64_t)p.M * 65536 - 1;
+        U4 o = ct_philox(p.seed, i, g, ((uint32_t)PUR_PSO_R << 24) | j, 0);
+        const int64_t r1 = o.x >> 16, r2 = o.y >> 16;
+        const uint64_t k = (uint64_t)i * p.D + j;
+        int64_t x = gld(p.X + k), v = gld(p.V + k);
+        const int64_t pb = gld(p.PB + k), gb = gld(p.PB + (uint64_t)gi * p.D + j);
+        v = ((p.w_q16 * v) >> 16) + ((((p.c1_q16 * r1) >> 16) * (pb - x)) >> 16) +
+            ((((p.c2_q16 * r2) >> 16) * (gb - x)) >> 16);
+        x += v;
+        x = x < 0 ? 0 : (x > xmax ? xmax : x);
+        p.V[k] = v;
+        p.X[k] = (int32_t)x;
+        const uint32_t d = (uint32_t)(x >> 16);
+        return d < radix ? d : radix - 1u;
+    }
+    // GA: child i of pair i/2 is A[:cut] + B[cut:] for even i, B[:cut] + A[cut:] for odd i
     const uint32_t k = i >> 1;
     U4 o = ct_philox(p.seed, k, g, (uint32_t)PUR_GA_SEL << 24, 0);
     const uint32_t a = beta_rank(p, o.x), b = beta_rank(p, o.y);
     const uint32_t cut = 1u + ct_below(o.z, p.D - 1u);
-    Row A, B;
-    valid_row(p, p.sorted[a], A);
-    valid_row(p, p.sorted[b], B);
-    // word-wise selects keep both rows in registers (a reference picked at run time would not)
     const bool odd = (i & 1u) != 0;
-    Row c, tail;
-#pragma unroll
-    for (int q = 0; q < CT_DMAX / 4; ++q) {
-        c.w[q] = odd ? B.w[q] : A.w[q];
-        tail.w[q] = odd ? A.w[q] : B.w[q];
-    }
-#pragma unroll
-    for (uint32_t j = 1; j < CT_DMAX; ++j)
-        if (j >= cut && j < p.D) c.set(j, tail.digit(j));
-    row_store(c, p.trial + (uint64_t)i * p.R, p.R);
-    U4 m = ct_philox(p.seed, i, g, (uint32_t)PUR_GA_MUT << 24, 0);
-    p.apply[i] = m.x < p.mut_thresh;
-    return c;
+    const bool from_a = (j < cut) != odd;
+    return row_digit(S, gld(p.sorted + (from_a ? a : b)), p.R, j);
 }
 
-// What the main repair pass's prep step computes for a proposal -- its validity from the
-// bitmask, its position (or insertion point) from the rank directory, and its entry in the
-// list of candidates to repair -- done here while the row is still in registers.
-__device__ __forceinline__ void list_for_repair(const PopDev& p, const RepairSet& J, uint32_t i, const Row& u) {
-    const DevSpace& S = *p.S;
-    uint64_t L = 0;
-    bool dom = true;
-#pragma unroll
-    for (uint32_t j = 0; j < CT_DMAX; ++j) {
-        if (j >= p.D) break;
-        dom &= u.digit(j) < S.radix[j];
-        L += (uint64_t)u.digit(j) * S.stride[j];
-    }
-    if (!dom) L = ~0ull;
-    const bool valid = dom && bit_valid(S, L);
-    const uint32_t pos = valid ? (uint32_t)rank_dir(S, L) : 0xFFFFFFFFu;   // loads before any store
-    row_store(u, J.out_rows + (uint64_t)i * p.R, p.R);
-    J.out_pos[i] = pos;
-    if (!valid) {
-        const uint32_t k = atomicAdd(&J.count[0], 1u);
-        J.list[k] = i;
-        J.list_L[k] = L;
-    }
-}
-
-// Proposals of every run, one thread per individual, each listed for the main repair pass
-// (`sets`, one per run in run order).  The repair counters were cleared by the previous
+// Proposals of every run, one group of G lanes per individual, each proposal listed for the main
+// repair pass (`sets`, one per run in run order) the way the pass's preparation would list it: its
+// validity from the bitmask, its position (or insertion point) from the rank directory, its entry
+// in the list of candidates to repair.  The repair counters were cleared by the previous
 // generation's selection (or at creation), never by a memset node inside a captured graph.
+template <uint32_t G>
 __global__ __launch_bounds__(kBlock) void k_propose(const PopDev* __restrict__ pops, uint32_t n,
                                                     const uint32_t* __restrict__ ind_off,
                                                     const RepairSet* __restrict__ sets, PlanArgs pa) {
+    constexpr uint32_t T = CT_DMAX / G;                 // digit slots per lane
     const uint32_t total = ind_off[n];
-    for (uint32_t item = blockIdx.x * blockDim.x + threadIdx.x; item < total; item += gridDim.x * blockDim.x) {
+    const uint32_t slot = threadIdx.x & (G - 1u);
+    const uint32_t groups = gridDim.x * (blockDim.x / G);
+    // every lane of a group takes the same individual, so a group is active or idle as a whole
+    for (uint32_t item = (blockIdx.x * blockDim.x + threadIdx.x) / G; item < total; item += groups) {
         const uint32_t r = find_run(ind_off, n, item);
         const PopDev& p = pops[r];
+        const DevSpace& S = *p.S;
+        const RepairSet& J = sets[r];
         const uint32_t i = item - ind_off[r];
-        const uint32_t g = p.state[0];
-        const Row u = p.algo == CT_DE ? de_propose(p, i, g) : p.algo == CT_PSO ? pso_propose(p, i, g) : ga_propose(p, i, g);
-        list_for_repair(p, sets[r], i, u);
+        const uint32_t g = gld(p.state);
+        uint32_t d[T];
+        bool ok = true;
+        uint64_t term = 0;                              // digits past D are 0 and add nothing
+#pragma unroll
+        for (uint32_t t = 0; t < T; ++t) {
+            const uint32_t j = slot + G * t;
+            d[t] = 0;
+            if (j < p.D) {
+                d[t] = propose_digit(p, S, i, g, j);
+                ok &= d[t] < gld(&S.radix[j]);
+                term += (uint64_t)d[t] * gld(&S.stride[j]);
+            }
+        }
+        const uint64_t L_in = grp_sum64<G>(term);
+        const bool dom = grp_sum64<G>(ok ? 0u : 1u) == 0u;
+        const uint64_t L = dom ? L_in : ~0ull;
+        // validity, then the rank from the words of L's 8-word block up to L's word
+        const bool valid = dom && bit_valid(S, L);
+        uint32_t cnt = 0;
+        uint64_t base = 0;
+        if (valid) {
+            const uint64_t w = L >> 6;
+            for (uint32_t u = slot; u < 8; u += G) {
+                const uint64_t q = (w & ~7ull) + u;
+                if (q <= w) {
+                    const uint64_t word = gld(S.words + q);
+                    cnt += (uint32_t)__popcll(q < w ? word : word & ((1ull << (L & 63u)) - 1ull));
+                }
+            }
+            base = gld(S.grp_off + (w >> 6)) + gld(S.dir8 + (w >> 3));
+        }
+        const uint64_t rank = base + grp_sum64<G>(cnt);
+        // word (slot / 4) + (G / 4) t holds digit slot + G t at byte slot % 4
+        const uint32_t nw = p.R / 4;
+        uint32_t* trial = reinterpret_cast<uint32_t*>(p.trial + (uint64_t)i * p.R);
+        uint32_t* out = reinterpret_cast<uint32_t*>(J.out_rows + (uint64_t)i * p.R);
+#pragma unroll
+        for (uint32_t t = 0; t < T; ++t) {
+            const uint32_t word = grp_or4<G>(d[t] << ((slot & 3u) * 8u));
+            const uint32_t wi = (slot >> 2) + (G / 4) * t;
+            if ((slot & 3u) == 0 && wi < nw) {
+                trial[wi] = word;
+                out[wi] = word;
+            }
+        }
+        if (slot == 0) {
+            if (p.algo == CT_GA) {
+                const U4 m = ct_philox(p.seed, i, g, (uint32_t)PUR_GA_MUT << 24, 0);
+                p.apply[i] = m.x < p.mut_thresh;
+            }
+            J.out_pos[i] = valid ? (uint32_t)rank : 0xFFFFFFFFu;
+            if (!valid) {
+                const uint32_t k = atomicAdd(&J.count[0], 1u);
+                J.list[k] = i;
+                J.list_L[k] = L;
+            }
+        }
     }
     plan_if_last(sets, n, pa);                          // the last block plans the main scans
+}
+
+void launch_propose(const ct_batch* b, const PlanArgs& pa, hipStream_t st) {
+    if (b->total_ind <= kWideGroupMax) {
+        const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>((b->total_ind * 16 + kBlock - 1) / kBlock, 4096));
+        hipLaunchKernelGGL(k_propose<16>, dim3(g), dim3(kBlock), 0, st, b->d_pops, b->n, b->d_ind_off, b->passA.d_sets, pa);
+    } else {
+        const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>((b->total_ind * 4 + kBlock - 1) / kBlock, 4096));
+        hipLaunchKernelGGL(k_propose<4>, dim3(g), dim3(kBlock), 0, st, b->d_pops, b->n, b->d_ind_off, b->passA.d_sets, pa);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -506,9 +537,7 @@ int batch_generation(ct_batch* b, hipStream_t st) {
     }
     {
         ProfScope ps_("k_propose", st);
-        const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>((b->total_ind + kBlock - 1) / kBlock, 4096));
-        hipLaunchKernelGGL(k_propose, dim3(g), dim3(kBlock), 0, st, b->d_pops, b->n, b->d_ind_off, b->passA.d_sets,
-                           main_plan(b->passA));
+        launch_propose(b, main_plan(b->passA), st);
     }
     int rc = launch_repair_passes(b->passA, false, st, true, false);
     if (rc) return rc;
@@ -587,10 +616,8 @@ RepairTune sweep_best(const ct_batch* b, int streams) {
 int autotune_generation(ct_batch* b, hipStream_t st) {
     if (b->n_ga) hipLaunchKernelGGL(k_ga_sort, dim3(b->n), dim3(kSelBlock), 0, st, b->d_pops, b->n);
     {
-        const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>((b->total_ind + kBlock - 1) / kBlock, 4096));
         // the sweep lists and plans again for every candidate
-        hipLaunchKernelGGL(k_propose, dim3(g), dim3(kBlock), 0, st, b->d_pops, b->n, b->d_ind_off, b->passA.d_sets,
-                           PlanArgs{});
+        launch_propose(b, PlanArgs{}, st);
     }
     CT_HIP(hipGetLastError());
     int rc = autotune_sweep(b, st);

@@ -194,3 +194,25 @@ def test_set_tuning_rejects_out_of_range(spaces):
             b.set_tuning(*bad)
     assert b.tuning() == before
     b.close()
+
+
+def test_large_batch_equals_plain(spaces):
+    """A batch of more than 16,384 individuals takes the narrow proposal groups (4 lanes per
+    individual); one run at a time takes the wide ones (16 lanes): both give the same state."""
+    from paper_2606_28372_amd import Batch, CT_STEP_BATCHED, Pop, step_many
+    t = torch()
+    sp, obj = spaces["gemm10"]
+    opts = [W.OptParams(a, 1024, 40 + k) for k, a in enumerate([W.ALGO_DE, W.ALGO_PSO, W.ALGO_GA] * 6)]
+    plain = [Pop.from_opt(sp, o, obj) for o in opts]
+    big = [Pop.from_opt(sp, o, obj) for o in opts]
+    assert sum(o.pop_size for o in opts) > 16384
+    b = Batch(big)
+    say("[gpu_batched] 18 runs x 1024 individuals")
+    b.step(3, CT_STEP_BATCHED)
+    step_many(plain, 3)
+    t.cuda.synchronize()
+    for k, (x, y) in enumerate(zip(plain, big)):
+        assert x.snapshot() == y.snapshot(), f"run {k} differs"
+    b.close()
+    for p in plain + big:
+        p.close()
