@@ -69,7 +69,7 @@ CONFIG_KEY = {"gemm": "gemm", "gemm10": "gemm10", "tiny": "tiny", "sparse16": "s
 def kernel_names():
     return ["k_table", "k_mask", "k_tile_sums", "k_scan_tiles", "k_compact", "k_boxes", "k_presence",
             "k_prevnext", "k_init", "k_init_finish", "k_ga_sort", "k_propose", "k_repair_zero", "k_repair_prep",
-            "k_repair_plan", "k_repair_scan", "k_repair_finish", "k_select"]
+            "k_repair_plan", "k_repair_scan", "k_repair_finish", "k_mutate", "k_select"]
 
 
 def measured_traffic(kernel, workload):

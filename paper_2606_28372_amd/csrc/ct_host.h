@@ -161,6 +161,8 @@ PlanArgs main_plan(const RepairPasses& rp);   // what plans the main scans of a 
 // propose kernel does both).
 int launch_repair_passes(const RepairPasses& rp, bool zero_counts, hipStream_t st, bool count_tally = true,
                          bool prep = true);
+// GA mutation of the flagged children of a HAM1_RANDOM set array, in place, one kernel
+int launch_mutation(const RepairPasses& rp, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Optimiser runs

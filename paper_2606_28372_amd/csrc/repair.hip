@@ -603,6 +603,66 @@ __global__ __launch_bounds__(kBlock) void k_repair_scan_mix(const RepairSet* __r
     }
 }
 
+// GA mutation of every flagged child in one kernel, one wave per child (the preparation, plan,
+// enumeration and finish of a repair pass would be four launches): the child's row (already valid
+// after the main pass) is encoded, its single-parameter changes are looked up in the validity
+// bitmask, the valid ones compete with their Philox key (ties: lowest linear index), and the
+// winner replaces the child.  A child without a valid single-parameter change keeps its row.
+__global__ __launch_bounds__(kBlock) void k_mutate(const RepairSet* __restrict__ sets, uint32_t n_sets,
+                                                   const uint32_t* __restrict__ off) {
+    const uint32_t total = off[n_sets];
+    const uint32_t lane = wave_lane();
+    const uint32_t waves = gridDim.x * (kBlock / 64);
+    for (uint32_t item = uni(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)); item < total; item += waves) {
+        const uint32_t s = uni(find_set(off, n_sets, item));
+        const RepairSet& J = sets[s];
+        const uint32_t ci = item - off[s];
+        if (!uni(J.apply[ci])) continue;
+        const DevSpace& S = *J.S;
+        const uint8_t* cr = J.rows + (uint64_t)ci * S.R;
+        // linear index over the in-domain digits, and the digits outside their domain
+        uint64_t Lp = 0;
+        uint32_t bad = 0, bad_j = 0;
+        for (uint32_t j = 0; j < S.D; ++j) {
+            const uint32_t d = cr[j];
+            if (d < S.radix[j]) Lp += (uint64_t)d * S.stride[j];
+            else { ++bad; bad_j = j; }
+        }
+        const uint32_t who = J.who ? J.who[ci] : ci;
+        const uint32_t gen = J.gen ? *J.gen : J.gen_value;
+        uint64_t bkey = kNoKey, bL = ~0ull;
+        const uint32_t n_pairs = S.val_off[S.D - 1] + S.radix[S.D - 1];
+        if (bad <= 1) {
+            for (uint32_t e = lane; e < n_pairs; e += 64) {
+                uint32_t j = 0;
+                while (j + 1 < S.D && S.val_off[j + 1] <= e) ++j;
+                const uint32_t v = e - S.val_off[j];
+                const uint32_t d = cr[j];
+                if (v == d || (bad == 1 && j != bad_j)) continue;
+                const uint64_t Lq = (d < S.radix[j] ? Lp - (uint64_t)d * S.stride[j] : Lp) + (uint64_t)v * S.stride[j];
+                if (!bit_valid(S, Lq)) continue;
+                const U4 o = ct_philox(J.seed, who, gen, (PUR_MUT_KEY << 24) | (uint32_t)((Lq >> 32) & 0xFFFFFFu), (uint32_t)Lq);
+                if (o.x < bkey || (o.x == bkey && Lq < bL)) { bkey = o.x; bL = Lq; }
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint32_t klo = __shfl_xor((uint32_t)bkey, o, 64), khi = __shfl_xor((uint32_t)(bkey >> 32), o, 64);
+            const uint32_t llo = __shfl_xor((uint32_t)bL, o, 64), lhi = __shfl_xor((uint32_t)(bL >> 32), o, 64);
+            const uint64_t kq = ((uint64_t)khi << 32) | klo, lq = ((uint64_t)lhi << 32) | llo;
+            if (kq < bkey || (kq == bkey && lq < bL)) { bkey = kq; bL = lq; }
+        }
+        if (bkey != kNoKey) {
+            const uint32_t pos = uni((uint32_t)rank_dir(S, bL));
+            const uint32_t* src = reinterpret_cast<const uint32_t*>(S.rows + (uint64_t)pos * S.R);
+            uint32_t* dst = reinterpret_cast<uint32_t*>(J.out_rows + (uint64_t)ci * S.R);
+            if (lane < S.R / 4) dst[lane] = src[lane];
+            if (lane == 0) J.out_pos[ci] = pos;
+        }
+        if (lane == 0 && J.tally) atomicAdd(J.tally, 1ull);
+    }
+}
+
 // The plan as a launch of its own (one wave).
 __global__ __launch_bounds__(64) void k_repair_plan(const RepairSet* __restrict__ sets, uint32_t n_sets, uint32_t which,
                                                     RepairPlan plan, uint32_t class_mask, uint32_t target_items,
@@ -782,6 +842,15 @@ int repair_plan_alloc(RepairPlan& p, uint32_t n_sets, std::vector<void*>& owned)
     p.parts = w + (n_sets + 1) * (1 + kNumClasses);
     p.done = p.parts + n_sets;
     CT_HIP(hipMemset(p.done, 0, sizeof(uint32_t)));
+    return CT_OK;
+}
+
+int launch_mutation(const RepairPasses& rp, hipStream_t st) {
+    if (rp.n_sets == 0 || rp.total_n == 0) return CT_OK;
+    ProfScope ps_("k_mutate", st);
+    const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>((rp.total_n + kBlock / 64 - 1) / (kBlock / 64), 2048));
+    hipLaunchKernelGGL(k_mutate, dim3(g), dim3(kBlock), 0, st, rp.d_sets, rp.n_sets, rp.d_prep_off);
+    CT_HIP(hipGetLastError());
     return CT_OK;
 }
 

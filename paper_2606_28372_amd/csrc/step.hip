@@ -542,7 +542,7 @@ int batch_generation(ct_batch* b, hipStream_t st) {
     int rc = launch_repair_passes(b->passA, false, st, true, false);
     if (rc) return rc;
     if (b->n_ga) {
-        rc = launch_repair_passes(b->passC, false, st);
+        rc = launch_mutation(b->passC, st);
         if (rc) return rc;
     }
     {
@@ -625,7 +625,7 @@ int autotune_generation(ct_batch* b, hipStream_t st) {
     b->passA.tune = sweep_best(b, -1);
     // the generation's own pass, counting its scans
     if ((rc = launch_repair_passes(b->passA, true, st, true))) return rc;
-    if (b->n_ga && (rc = launch_repair_passes(b->passC, false, st))) return rc;
+    if (b->n_ga && (rc = launch_mutation(b->passC, st))) return rc;
     hipLaunchKernelGGL(k_select, dim3(b->n), dim3(kSelBlock), 0, st, b->d_pops, b->n);
     CT_HIP(hipGetLastError());
     return CT_OK;
