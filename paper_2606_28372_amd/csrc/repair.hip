@@ -618,29 +618,44 @@ __global__ __launch_bounds__(kBlock) void k_mutate(const RepairSet* __restrict__
         const RepairSet& J = sets[s];
         const uint32_t ci = item - off[s];
         if (!uni(J.apply[ci])) continue;
-        const DevSpace& S = *J.S;
-        const uint8_t* cr = J.rows + (uint64_t)ci * S.R;
+        const CT_GLOBAL DevSpace& S = *gptr(J.S);
+        // lane j < D holds digit j of the child, its radix, stride and first pair index, so the
+        // per-pair lookups below are shuffles, not memory round trips
+        const uint32_t D = S.D;
+        const uint32_t dj = lane < D ? (uint32_t)gld(J.rows + (uint64_t)ci * S.R + lane) : 0u;
+        const uint32_t rj = lane < D ? S.radix[lane] : 1u;
+        const uint64_t sj = lane < D ? S.stride[lane] : 0ull;
+        const uint32_t oj = lane < D ? S.val_off[lane] : 0xFFFFFFFFu;
         // linear index over the in-domain digits, and the digits outside their domain
-        uint64_t Lp = 0;
-        uint32_t bad = 0, bad_j = 0;
-        for (uint32_t j = 0; j < S.D; ++j) {
-            const uint32_t d = cr[j];
-            if (d < S.radix[j]) Lp += (uint64_t)d * S.stride[j];
-            else { ++bad; bad_j = j; }
+        const bool in = lane >= D || dj < rj;
+        uint64_t Lp = in && lane < D ? (uint64_t)dj * sj : 0ull;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint32_t lo = __shfl_xor((uint32_t)Lp, o, 64), hi = __shfl_xor((uint32_t)(Lp >> 32), o, 64);
+            Lp += ((uint64_t)hi << 32) | lo;
         }
+        const uint64_t out_mask = __ballot(!in);
+        const uint32_t bad = (uint32_t)__popcll(out_mask);
+        const uint32_t bad_j = out_mask ? (uint32_t)(__ffsll((long long)out_mask) - 1) : 0u;
         const uint32_t who = J.who ? J.who[ci] : ci;
         const uint32_t gen = J.gen ? *J.gen : J.gen_value;
         uint64_t bkey = kNoKey, bL = ~0ull;
-        const uint32_t n_pairs = S.val_off[S.D - 1] + S.radix[S.D - 1];
+        const uint32_t n_pairs = S.val_off[D - 1] + S.radix[D - 1];
         if (bad <= 1) {
-            for (uint32_t e = lane; e < n_pairs; e += 64) {
+            for (uint32_t e0 = 0; e0 < n_pairs; e0 += 64) {     // uniform trip count: shuffles need every lane
+                const uint32_t e = e0 + lane;
+                // parameter of pair e: the last j with val_off[j] <= e
                 uint32_t j = 0;
-                while (j + 1 < S.D && S.val_off[j + 1] <= e) ++j;
-                const uint32_t v = e - S.val_off[j];
-                const uint32_t d = cr[j];
-                if (v == d || (bad == 1 && j != bad_j)) continue;
-                const uint64_t Lq = (d < S.radix[j] ? Lp - (uint64_t)d * S.stride[j] : Lp) + (uint64_t)v * S.stride[j];
-                if (!bit_valid(S, Lq)) continue;
+                for (uint32_t t = 1; t < D; ++t) j += (uint32_t)__builtin_amdgcn_readlane((int)oj, (int)t) <= e ? 1u : 0u;
+                const uint32_t d = (uint32_t)__shfl((int)dj, (int)j, 64);
+                const uint32_t r = (uint32_t)__shfl((int)rj, (int)j, 64);
+                const uint32_t off_j = (uint32_t)__shfl((int)oj, (int)j, 64);
+                const uint64_t st = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(sj >> 32), (int)j, 64) << 32) |
+                                    (uint32_t)__shfl((int)(uint32_t)sj, (int)j, 64);
+                const uint32_t v = e - off_j;
+                if (e >= n_pairs || v == d || (bad == 1 && j != bad_j)) continue;
+                const uint64_t Lq = (d < r ? Lp - (uint64_t)d * st : Lp) + (uint64_t)v * st;
+                if (!bit_valid(J.S[0], Lq)) continue;
                 const U4 o = ct_philox(J.seed, who, gen, (PUR_MUT_KEY << 24) | (uint32_t)((Lq >> 32) & 0xFFFFFFu), (uint32_t)Lq);
                 if (o.x < bkey || (o.x == bkey && Lq < bL)) { bkey = o.x; bL = Lq; }
             }
@@ -653,8 +668,8 @@ __global__ __launch_bounds__(kBlock) void k_mutate(const RepairSet* __restrict__
             if (kq < bkey || (kq == bkey && lq < bL)) { bkey = kq; bL = lq; }
         }
         if (bkey != kNoKey) {
-            const uint32_t pos = uni((uint32_t)rank_dir(S, bL));
-            const uint32_t* src = reinterpret_cast<const uint32_t*>(S.rows + (uint64_t)pos * S.R);
+            const uint32_t pos = uni((uint32_t)rank_g(gptr(J.S), bL));
+            const CT_GLOBAL uint32_t* src = gptr(reinterpret_cast<const uint32_t*>(S.rows + (uint64_t)pos * S.R));
             uint32_t* dst = reinterpret_cast<uint32_t*>(J.out_rows + (uint64_t)ci * S.R);
             if (lane < S.R / 4) dst[lane] = src[lane];
             if (lane == 0) J.out_pos[ci] = pos;
