@@ -373,15 +373,23 @@ __device__ __forceinline__ void scan_item(const RepairSet& J, const DevSpace& S,
 
     uint64_t mk = bk;                               // this lane's best key (exclusive until a row is found)
     uint32_t mp = kNoPos;
-    const uint64_t b0 = (uint64_t)part * n_sub / parts, b1 = (uint64_t)(part + 1) * n_sub / parts;
+    // A part owns every parts-th chunk (64 aligned boxes) when there are enough chunks, so each
+    // part holds some of the region around the candidate, where most of the work is; otherwise
+    // a contiguous range of boxes.  Either way a part visits its rows in position order.
+    const uint64_t n_chunk = Sg->n_chunk;
+    const bool strided = n_chunk >= parts;
+    const uint64_t b0 = strided ? 0 : (uint64_t)part * n_sub / parts;
+    const uint64_t b1 = strided ? n_sub : (uint64_t)(part + 1) * n_sub / parts;
+    const uint64_t k0 = strided ? part : b0 >> 6;
+    const uint64_t kstep = strided ? parts : 1;
+    const uint64_t n_mine = strided ? (n_chunk - part + parts - 1) / parts : ((b1 + 63u) >> 6) - k0;
     const CT_GLOBAL uint32_t* chunk32 = gptr(reinterpret_cast<const uint32_t*>(Sg->chunks));
-    const uint64_t k0 = b0 >> 6, k1 = (b1 + 63u) >> 6;     // chunks (64 aligned boxes) meeting [b0, b1)
     uint32_t nv[RW];
-    for (uint64_t ck = k0; ck < k1; ck += 64) {
-        // lanes over 64 chunks: which ones can hold a row below the bound?
-        const uint64_t kc = ck + lane;
+    for (uint64_t ck = 0; ck < n_mine; ck += 64) {
+        // lanes over 64 of the part's chunks: which ones can hold a row below the bound?
+        const uint64_t kc = k0 + (ck + lane) * kstep;
         uint64_t lc = kNoKey;
-        if (kc < k1) {
+        if (ck + lane < n_mine) {
             uint32_t lo[RW], hi[RW];
 #pragma unroll
             for (int w = 0; w < RW; ++w) {
@@ -394,7 +402,7 @@ __device__ __forceinline__ void scan_item(const RepairSet& J, const DevSpace& S,
         while (mc) {
             const uint32_t tc = (uint32_t)(__ffsll((long long)mc) - 1);
             mc &= ~(1ull << tc);
-            const uint64_t cb = (ck + tc) * 64u;            // the chunk's first box
+            const uint64_t cb = (k0 + (ck + tc) * kstep) * 64u;   // the chunk's first box
             // lanes over the chunk's boxes inside [b0, b1)
             const uint64_t b = cb + lane;
             uint64_t lb = kNoKey;
