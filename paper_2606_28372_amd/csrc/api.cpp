@@ -124,7 +124,7 @@ int batch_fill(ct_batch* b, const std::vector<ct_pop*>& pops) {
         setsA.push_back(r);
         maskA |= 1u << repair_class(r.metric, d.R);
         if (r.metric == CT_TIER_EUCLID || r.metric == CT_TIER_RANDOM) fbA |= 1u << repair_class(CT_HAMMING, d.R);
-        if (r.metric == CT_TIER_EUCLID) tabA = std::max(tabA, p->space->dev.max_radix * d.R);
+        if (r.metric == CT_TIER_EUCLID) tabA = std::max(tabA, p->space->dev.max_radix * (d.R < 32 ? d.R + 1 : d.R));
         if (d.algo == CT_GA) {
             RepairSet m = r;
             m.metric = CT_HAM1_RANDOM;
@@ -517,7 +517,7 @@ int ct_repair(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t met
         rp.total_n = (uint32_t)n;
         rp.class_mask = 1u << repair_class(metric, s->R);
         rp.fb_class_mask = (metric == CT_TIER_EUCLID || metric == CT_TIER_RANDOM) ? 1u << repair_class(CT_HAMMING, s->R) : 0u;
-        rp.euclid_tab = s->dev.max_radix * s->dev.R;
+        rp.euclid_tab = s->dev.max_radix * (s->dev.R < 32 ? s->dev.R + 1 : s->dev.R);
         rc = launch_repair_passes(rp, true, st);
     }
     (void)hipFreeAsync(buf, st);

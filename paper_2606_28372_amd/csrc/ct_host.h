@@ -149,7 +149,7 @@ struct RepairPasses {
     uint32_t total_n = 0;
     uint32_t class_mask = 0;                // scan classes of the main pass (bit per repair_class)
     uint32_t fb_class_mask = 0;             // Hamming classes of the fallback pass of tiered sets (0: none)
-    uint32_t euclid_tab = 0;                // largest max_radix * R over TIER_EUCLID sets (LDS table entries)
+    uint32_t euclid_tab = 0;                // largest max_radix * (R + 1) over TIER_EUCLID sets (LDS table entries)
     RepairPlan plan{};
 };
 int repair_plan_alloc(RepairPlan& p, uint32_t n_sets, std::vector<void*>& owned);

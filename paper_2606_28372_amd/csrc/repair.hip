@@ -88,12 +88,17 @@ __device__ __forceinline__ bool tiered_metric(uint32_t m) { return m == CT_TIER_
 // ---------------------------------------------------------------------------
 template <int M, int RW>
 struct Cand {
+    // (32-byte rows keep the even stride: 255 values x 33 entries would not fit in 64 KiB of LDS)
+    static constexpr uint32_t kTabStride = RW < 8 ? RW * 4 + 1 : RW * 4;
     uint32_t c[RW];
     uint32_t pv[RW], nx[RW];     // nearest present value index below / above each digit
     bool adj_is_sa;
-    // TIER_EUCLID: squared distance of the particle to each value centre, T[v * 4RW + j] =
+    // TIER_EUCLID: squared distance of the particle to each value centre, T[v * (4RW + 1) + j] =
     // (X_j - (v * 2^16 + 2^15))^2 (0 for the padding digits j >= D) in this wave's LDS slice, so
-    // every digit of a row is looked up unconditionally; and the value index s_j whose centre
+    // every digit of a row is looked up unconditionally.  The odd row stride (in 8-byte entries)
+    // puts the entries of one digit for different values in different LDS bank pairs: with a
+    // stride of 4RW = 16 entries (128 bytes) every lane reading digit j hit the same banks.  And
+    // the value index s_j whose centre
     // is nearest to X_j (the squared distance is convex in v, so over a box's range [a, b] its
     // minimum is at clamp(s_j, a, b))
     const CT_LDS uint64_t* tab;
@@ -147,12 +152,12 @@ struct Cand {
             const CT_GLOBAL int32_t* xp = gptr(J.pos_q16 + (uint64_t)ci * S.D);
             const int32_t xj = lane < D ? xp[lane] : 0;
             const int32_t hj = lane < D ? (int32_t)S.radix[lane] - 1 : 0;
-            constexpr uint32_t R4 = RW * 4;
-            const uint32_t n_tab = S.max_radix * R4;
+            constexpr uint32_t TS = kTabStride;
+            const uint32_t n_tab = S.max_radix * TS;
             // a uniform trip count keeps every lane active for the shuffle
             for (uint32_t e0 = 0; e0 < n_tab; e0 += 64) {
                 const uint32_t e = e0 + lane;
-                const uint32_t v = e / R4, j = e % R4;
+                const uint32_t v = e / TS, j = e % TS;
                 const int32_t x = __shfl(xj, (int)j, 64);
                 const int64_t d = (int64_t)x - (int64_t)((v << 16) + 32768u);
                 if (e < n_tab) lds_tab[e] = j < D ? (uint64_t)(d * d) : 0ull;
@@ -223,7 +228,7 @@ struct Cand {
                     uint64_t d2 = 0;
 #pragma unroll
                     for (int j = 0; j < RW * 4; ++j)
-                        d2 += tab[((v[j >> 2] >> ((j & 3) * 8)) & 0xFFu) * (RW * 4) + (uint32_t)j];
+                        d2 += tab[((v[j >> 2] >> ((j & 3) * 8)) & 0xFFu) * kTabStride + (uint32_t)j];
                     return ((uint64_t)tier << 62) | d2;
                 } else {
                     const uint64_t L = lin[pos];
@@ -280,7 +285,7 @@ struct Cand {
                 const uint32_t t = (b & m_hi) | (t1 & ~m_hi);
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    e2 += tab[((t >> (q * 8)) & 0xFFu) * (RW * 4) + (uint32_t)(k * 4 + q)];
+                    e2 += tab[((t >> (q * 8)) & 0xFFu) * kTabStride + (uint32_t)(k * 4 + q)];
             }
         }
         if constexpr (M == CT_HAMMING) return miss;
