@@ -11,7 +11,7 @@ import pytest
 
 import workloads as W
 from oracle import steps as ost
-from tests.gpu_common import gpu_space, oracle_space, say, torch
+from tests.gpu_common import gpu_space, oracle_space, say, torch  # noqa: F401
 from tests.test_gpu_steps import compare, oracle_init, oracle_step
 
 pytestmark = pytest.mark.gpu
@@ -216,3 +216,25 @@ def test_large_batch_equals_plain(spaces):
     b.close()
     for p in plain + big:
         p.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_wide_rows_batch_equals_plain(mode):
+    """DE, PSO and GA over a 20-parameter space (32-byte rows) in one batch: the fused launch runs
+    the index-distance, Alg. 2 and Alg. 3 scans of the widest rows in one kernel."""
+    from paper_2606_28372_amd import Batch, CT_STEP_BATCHED, Pop, step_many
+    t = torch()
+    sp = gpu_space(W.space("wide20"))
+    obj = t.tensor(W.objective(sp.n_valid, 13), device="cuda")
+    opts = [W.OptParams(a, 200, 50 + a) for a in (W.ALGO_DE, W.ALGO_PSO, W.ALGO_GA)]
+    plain = [Pop.from_opt(sp, o, obj) for o in opts]
+    grouped = [Pop.from_opt(sp, o, obj) for o in opts]
+    b = Batch(grouped)
+    b.set_tuning(2048, 8, 4096, mode)
+    say(f"[gpu_batched] wide20 mode {mode}")
+    b.step(3, CT_STEP_BATCHED)
+    step_many(plain, 3)
+    t.cuda.synchronize()
+    for k, (x, y) in enumerate(zip(plain, grouped)):
+        assert x.snapshot() == y.snapshot(), f"run {k} differs"
+    b.close()

@@ -63,6 +63,11 @@ def test_repair_gemm13():
     run_parity(W.gemm13(), oracle_space("gemm13"), 700, 3)
 
 
+def test_repair_wide20():
+    """20 parameters: 32-byte rows, the widest scan kernels."""
+    run_parity(W.space("wide20"), oracle_space("wide20"), 400, 5)
+
+
 def test_repair_sparse16_sample():
     osp = oracle_space("sparse16")
     run_parity(W.sparse16(), osp, 40, 4,

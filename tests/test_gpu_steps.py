@@ -99,6 +99,12 @@ def test_gemm13_steps(algo):
     run("gemm13", W.OptParams(algo, 1024, 1), 2, 1)
 
 
+@pytest.mark.parametrize("algo", [W.ALGO_DE, W.ALGO_PSO, W.ALGO_GA])
+def test_wide20_steps(algo):
+    """20 parameters: two digits per proposal lane, 32-byte rows in the scans and the mutation."""
+    run("wide20", W.OptParams(algo, 256, 12), 3, 2)
+
+
 def test_small_populations_and_odd_sizes():
     run("tiny", W.OptParams(W.ALGO_GA, 33, 5), 6, 0)
     run("tiny", W.OptParams(W.ALGO_PSO, 100, 6), 5, 0)             # P == |V|: one member per stratum

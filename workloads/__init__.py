@@ -144,7 +144,23 @@ def sparse16() -> SpaceSpec:
     )
 
 
-SPACES = {"tiny": tiny, "gemm10": gemm10, "gemm13": gemm13, "sparse16": sparse16}
+def wide20() -> SpaceSpec:
+    """20 parameters (rows of 32 bytes): 18 on/off switches and two 3-way choices; at most five
+    switches on, and the two choices tied to the first switch (2,359,296 configurations)."""
+    p = {f"s{k}": [0, 1] for k in range(18)}
+    p["u"] = [1, 2, 3]
+    p["v"] = [1, 2, 3]
+    return SpaceSpec(
+        "wide20",
+        p,
+        [
+            " + ".join(f"s{k}" for k in range(18)) + " <= 5",
+            "(u + v) % 2 == 0 or s0 == 1",
+        ],
+    )
+
+
+SPACES = {"tiny": tiny, "gemm10": gemm10, "gemm13": gemm13, "sparse16": sparse16, "wide20": wide20}
 
 
 def space(name: str) -> SpaceSpec:
