@@ -850,6 +850,11 @@ int ct_pop_restore(ct_pop* p, const void* h_buf, size_t len) {
     }
     CT_HIP(hipMemcpy(d.state, stt, 16, hipMemcpyHostToDevice));
     CT_HIP(hipMemcpy(d.best, &b, 8, hipMemcpyHostToDevice));
+    if (d.algo == CT_GA) {
+        // the rank order the next proposals read is derived from the population
+        if (int rc = pop_sort_device(p, nullptr)) return rc;
+        CT_HIP(hipDeviceSynchronize());
+    }
     return CT_OK;
 }
 

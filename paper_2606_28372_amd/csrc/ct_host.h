@@ -245,6 +245,8 @@ uint64_t pop_footprint_bytes(uint32_t algo, uint32_t P, uint32_t D, uint32_t R, 
 
 // step.hip
 int pop_init_device(ct_pop* p, hipStream_t st);
+// GA: the population's rank order (after creation or a restore; generations keep it current)
+int pop_sort_device(ct_pop* p, hipStream_t st);
 int batch_generation(ct_batch* b, hipStream_t st);
 // n_generations generations; every sample_every-th sweeps the main repair pass over the candidate
 // partitionings, those in between decide the side-stream setting; installs the choice

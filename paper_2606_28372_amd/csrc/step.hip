@@ -361,10 +361,8 @@ void launch_propose(const ct_batch* b, const PlanArgs& pa, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // GA: sort the population by (objective, position), one block per GA run
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kSelBlock) void k_ga_sort(const PopDev* __restrict__ pops, uint32_t n) {
+__device__ void ga_sort_block(const PopDev& p) {
     __shared__ uint64_t key[kGaMaxSort];
-    const PopDev& p = pops[blockIdx.x];
-    if (p.algo != CT_GA) return;
     uint32_t m = 1;
     while (m < p.P) m <<= 1;
     if (m <= blockDim.x) {
@@ -407,6 +405,10 @@ __global__ __launch_bounds__(kSelBlock) void k_ga_sort(const PopDev* __restrict_
     }
     for (uint32_t i = threadIdx.x; i < p.P; i += blockDim.x) p.sorted[i] = (uint32_t)key[i];
 }
+
+// The rank order of a GA run's population (read by the next generation's proposals): sorted at
+// creation, after a restore, and by the selection kernel at the end of every generation.
+__global__ __launch_bounds__(kSelBlock) void k_ga_sort_one(PopDev p) { ga_sort_block(p); }
 
 // ---------------------------------------------------------------------------
 // select: one block per run
@@ -515,7 +517,11 @@ __global__ __launch_bounds__(kSelBlock) void k_select(const PopDev* __restrict__
     const PopDev& p = pops[blockIdx.x];
     if (p.algo == CT_DE) de_select(p);
     else if (p.algo == CT_PSO) pso_select(p);
-    else ga_select(p);
+    else {
+        ga_select(p);
+        __syncthreads();
+        ga_sort_block(p);                                 // the next generation's rank order
+    }
     if (threadIdx.x < 4) p.rcount[threadIdx.x] = 0;      // repair counters of the next generation
 }
 
@@ -525,16 +531,20 @@ int pop_init_device(ct_pop* p, hipStream_t st) {
     const PopDev& d = p->dev;
     { ProfScope ps_("k_init", st); hipLaunchKernelGGL(k_init, dim3((d.P + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d); }
     { ProfScope ps_("k_init_finish", st); hipLaunchKernelGGL(k_init_finish, dim3(1), dim3(kSelBlock), 0, st, d); }
+    if (d.algo == CT_GA) return pop_sort_device(p, st);
+    CT_HIP(hipGetLastError());
+    return CT_OK;
+}
+
+int pop_sort_device(ct_pop* p, hipStream_t st) {
+    if (p->dev.algo != CT_GA) return CT_OK;
+    { ProfScope ps_("k_ga_sort", st); hipLaunchKernelGGL(k_ga_sort_one, dim3(1), dim3(kSelBlock), 0, st, p->dev); }
     CT_HIP(hipGetLastError());
     return CT_OK;
 }
 
 int batch_generation(ct_batch* b, hipStream_t st) {
     if (b->n == 0) return CT_OK;
-    if (b->n_ga) {
-        ProfScope ps_("k_ga_sort", st);
-        hipLaunchKernelGGL(k_ga_sort, dim3(b->n), dim3(kSelBlock), 0, st, b->d_pops, b->n);
-    }
     {
         ProfScope ps_("k_propose", st);
         launch_propose(b, main_plan(b->passA), st);
@@ -614,7 +624,6 @@ RepairTune sweep_best(const ct_batch* b, int streams) {
 
 // One generation whose main repair pass is first swept over every candidate partitioning.
 int autotune_generation(ct_batch* b, hipStream_t st) {
-    if (b->n_ga) hipLaunchKernelGGL(k_ga_sort, dim3(b->n), dim3(kSelBlock), 0, st, b->d_pops, b->n);
     {
         // the sweep lists and plans again for every candidate
         launch_propose(b, PlanArgs{}, st);
