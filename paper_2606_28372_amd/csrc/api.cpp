@@ -114,9 +114,9 @@ int batch_fill(ct_batch* b, const std::vector<ct_pop*>& pops) {
         r.out_pos = d.tpos;
         r.apply = nullptr;
         r.list = p->r_list;
-        r.list_L = p->r_list_L;
+        r.list_ins = p->r_list_ins;
         r.fb_list = p->r_fb;
-        r.fb_L = p->r_fb_L;
+        r.fb_ins = p->r_fb_ins;
         r.count = d.rcount;
         r.part_key = p->r_part_key;
         r.part_pos = p->r_part_pos;
@@ -495,9 +495,9 @@ int ct_repair(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t met
     h.out_pos = d_out_pos;
     h.apply = nullptr;
     h.list = (uint32_t*)take(n * 4);
-    h.list_L = (uint64_t*)take(n * 8);
+    h.list_ins = (uint64_t*)take(n * 8);
     h.fb_list = (uint32_t*)take(n * 4);
-    h.fb_L = (uint64_t*)take(n * 8);
+    h.fb_ins = (uint64_t*)take(n * 8);
     h.part_key = (uint64_t*)take(slots * 8);
     h.part_pos = (uint32_t*)take(slots * 4);
     h.count = (uint32_t*)take(2 * 4);
@@ -607,8 +607,8 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_ob
     }
     if (hipMemsetAsync(d.tally, 0, 2 * sizeof(unsigned long long), st) != hipSuccess)
         return fail(ct_fail(CT_EDEVICE, "ct_pop_create: memset failed"));
-    if ((rc = dalloc(p, &p->r_list, P)) || (rc = dalloc(p, &p->r_list_L, P)) || (rc = dalloc(p, &p->r_fb, P)) ||
-        (rc = dalloc(p, &p->r_fb_L, P)) || (rc = dalloc(p, &p->r_part_key, slots)) ||
+    if ((rc = dalloc(p, &p->r_list, P)) || (rc = dalloc(p, &p->r_list_ins, P)) || (rc = dalloc(p, &p->r_fb, P)) ||
+        (rc = dalloc(p, &p->r_fb_ins, P)) || (rc = dalloc(p, &p->r_part_key, slots)) ||
         (rc = dalloc(p, &p->r_part_pos, slots)))
         return fail(rc);
     if ((rc = pop_init_device(p, st))) return fail(rc);

@@ -87,9 +87,9 @@ struct RepairSet {
     uint32_t* out_pos;                // [n]
     const uint8_t* apply;             // nullable: per-candidate flag, 0 = leave alone
     uint32_t* list;                   // candidates that need a scan [n]
-    uint64_t* list_L;                 // their linear indices [n]
+    uint64_t* list_ins;               // their insertion positions in the valid list (~0: outside the domain) [n]
     uint32_t* fb_list;                // candidates without any tier 0-2 neighbour [n]
-    uint64_t* fb_L;
+    uint64_t* fb_ins;
     uint32_t* count;                  // [0] list length, [1] fallback length
     uint64_t* part_key;               // per (candidate, part) winners [slots]
     uint32_t* part_pos;
@@ -210,9 +210,9 @@ struct ct_pop {
     ct_batch* single = nullptr;       // batch of this run alone (plain stepping)
     // repair scratch of this run
     uint32_t* r_list = nullptr;
-    uint64_t* r_list_L = nullptr;
+    uint64_t* r_list_ins = nullptr;
     uint32_t* r_fb = nullptr;
-    uint64_t* r_fb_L = nullptr;
+    uint64_t* r_fb_ins = nullptr;
     uint64_t* r_part_key = nullptr;
     uint32_t* r_part_pos = nullptr;
 };

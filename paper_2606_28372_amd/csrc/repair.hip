@@ -346,12 +346,12 @@ __device__ __forceinline__ uint64_t rank_g(const CT_GLOBAL DevSpace* S, uint64_t
 // Always inlined: with two kernels calling it the compiler would otherwise emit a call, whose
 // register convention costs the tiered metrics twice the VGPRs plus stack spills.
 template <int M, int RW>
-__device__ __forceinline__ void scan_item(const RepairSet& J, const DevSpace& S, const uint32_t* list, const uint64_t* list_L,
+__device__ __forceinline__ void scan_item(const RepairSet& J, const DevSpace& S, const uint32_t* list, const uint64_t* list_ins,
                           uint32_t li, uint32_t part, uint32_t parts, CT_LDS uint64_t* lds_tab) {
     const uint32_t lane = wave_lane();
     const CT_GLOBAL DevSpace* Sg = gptr(&S);
     const uint32_t ci = uni(gld(list + li));
-    const uint64_t Lc = gld(list_L + li);
+    const uint64_t Lc = gld(list_ins + li);
     Cand<M, RW> C;
     C.load(J, Sg, ci, lds_tab);
     const CT_GLOBAL uint32_t* rows32 = gptr(reinterpret_cast<const uint32_t*>(Sg->rows));
@@ -361,9 +361,9 @@ __device__ __forceinline__ void scan_item(const RepairSet& J, const DevSpace& S,
 
     constexpr bool tiered = (M == CT_TIER_EUCLID || M == CT_TIER_RANDOM);
     uint64_t bk = tiered ? kTier3 : kNoKey;
-    const uint64_t L = ((uint64_t)uni((uint32_t)(Lc >> 32)) << 32) | uni((uint32_t)Lc);
-    if (L != ~0ull) {
-        const uint64_t ins = rank_g(Sg, L);
+    // the candidate's insertion position in the valid list, found when it was listed
+    const uint64_t ins = ((uint64_t)uni((uint32_t)(Lc >> 32)) << 32) | uni((uint32_t)Lc);
+    if (ins != ~0ull) {
         const int64_t q = (int64_t)ins - 32 + (int64_t)lane;
         uint64_t k = kNoKey;
         if (q >= 0 && (uint64_t)q < n_valid) {
@@ -535,14 +535,15 @@ __global__ __launch_bounds__(kBlock) void k_repair_prep(const RepairSet* __restr
         const bool dom = row_in_domain(S, c);
         const uint64_t L = dom ? row_encode(S, c) : ~0ull;
         const bool valid = dom && bit_valid(S, L);
-        const uint32_t pos = valid ? (uint32_t)rank_dir(S, L) : kNoPos;    // loads before any store
+        const uint64_t ins = dom ? rank_dir(S, L) : ~0ull;                 // loads before any store
+        const uint32_t pos = valid ? (uint32_t)ins : kNoPos;
         const bool act = J.apply == nullptr || J.apply[i];
         row_store(c, J.out_rows + (uint64_t)i * S.R, S.R);
         J.out_pos[i] = pos;
         if (act && (J.metric == CT_HAM1_RANDOM || !valid)) {
             const uint32_t k = atomicAdd(&J.count[0], 1u);
             J.list[k] = i;
-            J.list_L[k] = L;
+            J.list_ins[k] = ins;
         }
     }
     plan_if_last(sets, n_sets, pa);
@@ -569,8 +570,8 @@ __global__ __launch_bounds__(kBlock) void k_repair_scan(const RepairSet* __restr
             ham1_item(J, S, li);
         } else {
             const uint32_t* list = which ? J.fb_list : J.list;
-            const uint64_t* list_L = which ? J.fb_L : J.list_L;
-            scan_item<M, RW>(J, S, list, list_L, li, part, parts, lds_tab);
+            const uint64_t* list_ins = which ? J.fb_ins : J.list_ins;
+            scan_item<M, RW>(J, S, list, list_ins, li, part, parts, lds_tab);
         }
     }
 }
@@ -606,12 +607,12 @@ __global__ __launch_bounds__(kBlock) void k_repair_scan_mix(const RepairSet* __r
         const uint32_t local = local_item - off[s];
         const uint32_t li = local / parts, part = local % parts;
         const uint32_t* list = which ? J.fb_list : J.list;
-        const uint64_t* list_L = which ? J.fb_L : J.list_L;
+        const uint64_t* list_ins = which ? J.fb_ins : J.list_ins;
         switch (m) {
-        case CT_HAMMING: scan_item<CT_HAMMING, RW>(J, S, list, list_L, li, part, parts, lds_tab); break;
-        case CT_INDEX_L1: scan_item<CT_INDEX_L1, RW>(J, S, list, list_L, li, part, parts, lds_tab); break;
-        case CT_TIER_EUCLID: scan_item<CT_TIER_EUCLID, RW>(J, S, list, list_L, li, part, parts, lds_tab); break;
-        default: scan_item<CT_TIER_RANDOM, RW>(J, S, list, list_L, li, part, parts, lds_tab); break;
+        case CT_HAMMING: scan_item<CT_HAMMING, RW>(J, S, list, list_ins, li, part, parts, lds_tab); break;
+        case CT_INDEX_L1: scan_item<CT_INDEX_L1, RW>(J, S, list, list_ins, li, part, parts, lds_tab); break;
+        case CT_TIER_EUCLID: scan_item<CT_TIER_EUCLID, RW>(J, S, list, list_ins, li, part, parts, lds_tab); break;
+        default: scan_item<CT_TIER_RANDOM, RW>(J, S, list, list_ins, li, part, parts, lds_tab); break;
         }
     }
 }
@@ -737,7 +738,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_finish(const RepairSet* __res
         } else if (which == 0 && tiered_metric(J.metric) && lane == 0) {
             const uint32_t k = atomicAdd(&J.count[1], 1u);
             J.fb_list[k] = ci;
-            J.fb_L[k] = J.list_L[li];     // the fallback seeds its bound around the same place
+            J.fb_ins[k] = J.list_ins[li];     // the fallback seeds its bound around the same place
         }
     }
     plan_if_last(sets, n_sets, pa);

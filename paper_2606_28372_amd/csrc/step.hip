@@ -303,11 +303,12 @@ __global__ __launch_bounds__(kBlock) void k_propose(const PopDev* __restrict__ p
         const uint64_t L_in = grp_sum64<G>(term);
         const bool dom = grp_sum64<G>(ok ? 0u : 1u) == 0u;
         const uint64_t L = dom ? L_in : ~0ull;
-        // validity, then the rank from the words of L's 8-word block up to L's word
+        // validity, then the rank (the position if valid, else the insertion position the repair
+        // scan seeds its bound around) from the words of L's 8-word block up to L's word
         const bool valid = dom && bit_valid(S, L);
         uint32_t cnt = 0;
         uint64_t base = 0;
-        if (valid) {
+        if (dom) {
             const uint64_t w = L >> 6;
             for (uint32_t u = slot; u < 8; u += G) {
                 const uint64_t q = (w & ~7ull) + u;
@@ -341,7 +342,7 @@ __global__ __launch_bounds__(kBlock) void k_propose(const PopDev* __restrict__ p
             if (!valid) {
                 const uint32_t k = atomicAdd(&J.count[0], 1u);
                 J.list[k] = i;
-                J.list_L[k] = L;
+                J.list_ins[k] = dom ? rank : ~0ull;
             }
         }
     }
