@@ -103,6 +103,8 @@ int batch_fill(ct_batch* b, const std::vector<ct_pop*>& pops) {
         ind_off.push_back(ind_off.back() + d.P);
         RepairSet r{};
         r.S = d.S;
+        r.R = d.R;
+        r.n_sub = p->space->dev.n_sub;
         r.rows = d.trial;
         r.n = d.P;
         r.metric = d.algo == CT_DE ? CT_INDEX_L1 : d.algo == CT_PSO ? CT_TIER_EUCLID : CT_TIER_RANDOM;
@@ -483,6 +485,8 @@ int ct_repair(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t met
     size_t o = 0;
     auto take = [&](size_t sz) { void* q = buf + o; o += (sz + 7) & ~size_t(7); return q; };
     h.S = s->d_dev;
+    h.R = s->dev.R;
+    h.n_sub = s->dev.n_sub;
     h.rows = d_rows;
     h.n = (uint32_t)n;
     h.metric = metric;

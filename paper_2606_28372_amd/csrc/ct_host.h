@@ -94,6 +94,9 @@ struct RepairSet {
     uint64_t* part_key;               // per (candidate, part) winners [slots]
     uint32_t* part_pos;
     unsigned long long* tally;        // nullable: += candidates scanned
+    uint32_t R;                       // copies of the space's row bytes and 64-row box count, so the
+    uint32_t pad1;                    // plan reads one descriptor instead of following S
+    uint64_t n_sub;
 };
 
 // Scan kernels are specialised by (metric, row width): class = metric * 4 + log2(R / 4).

@@ -44,7 +44,7 @@ __device__ inline void plan_wave(const RepairSet* __restrict__ sets, uint32_t n_
 #pragma unroll
     for (uint32_t q = 0; q < kRepairClasses; ++q) acc[q] = 0;
     for (uint32_t s = s0; s < s1; ++s) {
-        const uint32_t cls = repair_class(which ? (uint32_t)CT_HAMMING : sets[s].metric, sets[s].S->R);
+        const uint32_t cls = repair_class(which ? (uint32_t)CT_HAMMING : sets[s].metric, sets[s].R);
         const uint32_t c = plan_count(sets, s, which);
 #pragma unroll
         for (uint32_t q = 0; q < kRepairClasses; ++q) acc[q] += q == cls ? c : 0u;
@@ -62,8 +62,8 @@ __device__ inline void plan_wave(const RepairSet* __restrict__ sets, uint32_t n_
 #pragma unroll
     for (uint32_t q = 0; q < kRepairClasses; ++q) acc[q] = 0;
     for (uint32_t s = s0; s < s1; ++s) {
-        const uint64_t pmax = sets[s].S->n_sub / min_sub;
-        const uint32_t cls = repair_class(which ? (uint32_t)CT_HAMMING : sets[s].metric, sets[s].S->R);
+        const uint64_t pmax = sets[s].n_sub / min_sub;
+        const uint32_t cls = repair_class(which ? (uint32_t)CT_HAMMING : sets[s].metric, sets[s].R);
         uint32_t gp = gpc[0];
 #pragma unroll
         for (uint32_t q = 1; q < kRepairClasses; ++q) gp = q == cls ? gpc[q] : gp;
@@ -82,7 +82,7 @@ __device__ inline void plan_wave(const RepairSet* __restrict__ sets, uint32_t n_
     for (uint32_t s = s0; s < s1; ++s) {
         const uint32_t p = plan.parts[s];
         const uint32_t c = plan_count(sets, s, which);
-        const uint32_t cls = repair_class(which ? (uint32_t)CT_HAMMING : sets[s].metric, sets[s].S->R);
+        const uint32_t cls = repair_class(which ? (uint32_t)CT_HAMMING : sets[s].metric, sets[s].R);
         plan.cand_off[s] = oc;
 #pragma unroll
         for (uint32_t q = 0; q < kRepairClasses; ++q)
