@@ -240,8 +240,10 @@ struct Cand {
         }
     }
 
-    // lower bound of key() over every row inside the box [lo, hi]
-    __device__ __forceinline__ uint64_t bound_box(const uint32_t* lo32, const uint32_t* hi32, uint32_t D) const {
+    // lower bound of key() over every row inside the box [lo, hi]; where it is at least `bound`
+    // (the box cannot win) any value at least `bound` may be returned
+    __device__ __forceinline__ uint64_t bound_box(const uint32_t* lo32, const uint32_t* hi32, uint32_t D,
+                                                  uint64_t bound) const {
         if constexpr (M == CT_INDEX_L1) {
             // per digit, the distance from c to [a, b] (a <= b) is (|c - a| + |c - b| - (b - a)) / 2,
             // and v_sad_u8 sums absolute byte differences four digits at a time
@@ -258,7 +260,6 @@ struct Cand {
         // they hold.  Padding digits are 0 in the candidate and in both box rows: they add nothing.
         uint32_t miss = 0, far = 0;
         bool adj_ok = true;
-        uint64_t e2 = 0;
 #pragma unroll
         for (int k = 0; k < RW; ++k) {
             const uint32_t a = lo32[k], b = hi32[k], ck = c[k];
@@ -276,26 +277,36 @@ struct Cand {
                     adj_ok &= (out & ~(p_in | n_in)) == 0u;
                 }
             }
-            if constexpr (M == CT_TIER_EUCLID) {
-                // squared distance from the particle to the nearest value centre inside [a, b]:
-                // the table at clamp(s_j, a_j, b_j)
-                const uint32_t m_lo = byte_mask(lt_bytes(s[k], a));
-                const uint32_t t1 = (a & m_lo) | (s[k] & ~m_lo);
-                const uint32_t m_hi = byte_mask(lt_bytes(b, t1));
-                const uint32_t t = (b & m_hi) | (t1 & ~m_hi);
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    e2 += tab[((t >> (q * 8)) & 0xFFu) * kTabStride + (uint32_t)(k * 4 + q)];
-            }
         }
         if constexpr (M == CT_HAMMING) return miss;
         else if constexpr (M == CT_HAM1_RANDOM) return miss <= 1u ? 0ull : kNoKey;
         else {
-            const uint64_t sub = M == CT_TIER_EUCLID ? e2 : 0ull;
-            if (far == 0u) return sub;                              // strictly adjacent rows possible
-            if (!adj_is_sa && adj_ok) return (1ull << 62) | sub;     // adjacent rows possible
-            if (miss <= 1u) return (2ull << 62) | sub;               // Hamming-1 rows possible
-            return kTier3;
+            const uint64_t tier = far == 0u ? 0ull                      // strictly adjacent rows possible
+                                : (!adj_is_sa && adj_ok) ? 1ull         // adjacent rows possible
+                                : miss <= 1u ? 2ull                     // Hamming-1 rows possible
+                                : 3ull;
+            if (tier == 3u) return kTier3;
+            if constexpr (M == CT_TIER_EUCLID) {
+                // the squared distance only matters for boxes whose tier can still win
+                if ((tier << 62) >= bound) return tier << 62;
+                // squared distance from the particle to the nearest value centre inside [a, b]:
+                // the table at clamp(s_j, a_j, b_j)
+                uint64_t e2 = 0;
+#pragma unroll
+                for (int k = 0; k < RW; ++k) {
+                    const uint32_t a = lo32[k], b = hi32[k];
+                    const uint32_t m_lo = byte_mask(lt_bytes(s[k], a));
+                    const uint32_t t1 = (a & m_lo) | (s[k] & ~m_lo);
+                    const uint32_t m_hi = byte_mask(lt_bytes(b, t1));
+                    const uint32_t t = (b & m_hi) | (t1 & ~m_hi);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        e2 += tab[((t >> (q * 8)) & 0xFFu) * kTabStride + (uint32_t)(k * 4 + q)];
+                }
+                return (tier << 62) | e2;
+            } else {
+                return tier << 62;
+            }
         }
     }
 };
@@ -401,7 +412,7 @@ __device__ __forceinline__ void scan_item(const RepairSet& J, const DevSpace& S,
                 lo[w] = chunk32[kc * 2u * RW + w];
                 hi[w] = chunk32[kc * 2u * RW + RW + w];
             }
-            lc = C.bound_box(lo, hi, D);
+            lc = C.bound_box(lo, hi, D, bk);
         }
         uint64_t mc = __ballot(lc < bk);
         while (mc) {
@@ -418,7 +429,7 @@ __device__ __forceinline__ void scan_item(const RepairSet& J, const DevSpace& S,
                     lo[w] = box32[b * 2u * RW + w];
                     hi[w] = box32[b * 2u * RW + RW + w];
                 }
-                lb = C.bound_box(lo, hi, D);
+                lb = C.bound_box(lo, hi, D, bk);
             }
             uint64_t m = __ballot(lb < bk);
             int tn = m ? __ffsll((long long)m) - 1 : -1;
