@@ -367,24 +367,43 @@ __device__ void ga_sort_block(const PopDev& p) {
     uint32_t m = 1;
     while (m < p.P) m <<= 1;
     if (m <= blockDim.x) {
-        // one key per thread: bitonic stages whose partner is in the same wave exchange through
-        // cross-lane shuffles; only partners 64 or more apart go through LDS and a barrier
+        // one key per thread.  Each wave sorts its 64 keys ascending with a bitonic network over
+        // cross-lane shuffles; then rounds of pairwise merges double the sorted runs: a key's
+        // place in the merged run is its place in its own run plus the number of keys of the
+        // other run that go before it (found by binary search in LDS; on equal keys the left
+        // run's go first), so each round is one binary search and one barrier, not a series of
+        // exchange stages.
         const uint32_t i = threadIdx.x;
         uint64_t v = i < p.P ? best_key(p.f[i], p.pos[i]) : ~0ull;
-        for (uint32_t k = 2; k <= m; k <<= 1) {
+        const uint32_t w = m < 64 ? m : 64;
+        for (uint32_t k = 2; k <= w; k <<= 1) {
             for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-                uint64_t o;
-                if (j >= 64) {
-                    key[i] = v;
-                    __syncthreads();
-                    o = key[i ^ j];
-                    __syncthreads();
-                } else {
-                    o = shfl_xor_u64(v, (int)j);
-                }
-                const bool keep_min = ((i & j) == 0) == ((i & k) == 0);
+                const uint64_t o = shfl_xor_u64(v, (int)j);
+                const bool up = k == w || (i & k) == 0;       // the last stage sorts every run upward
+                const bool keep_min = ((i & j) == 0) == up;
                 v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
             }
+        }
+        uint64_t* src = key;
+        uint64_t* dst = key + kSelBlock;
+        if (i < m) src[i] = v;
+        __syncthreads();
+        for (uint32_t L = w; L < m; L <<= 1) {
+            if (i < m) {
+                const uint32_t base = i & ~(2 * L - 1), r = i & (L - 1);
+                const bool left = (i & L) == 0;
+                const uint64_t* other = src + base + (left ? L : 0);
+                uint32_t lo = 0, hi = L;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    const uint64_t x = other[mid];
+                    if (left ? x < v : x <= v) lo = mid + 1; else hi = mid;
+                }
+                dst[base + r + lo] = v;
+            }
+            __syncthreads();
+            uint64_t* t = src; src = dst; dst = t;
+            if (i < m) v = src[i];
         }
         if (i < p.P) p.sorted[i] = (uint32_t)v;
         return;
