@@ -6,11 +6,13 @@
 //     argmin_{v in V} (k(c, v), L(v))
 // with a metric-specific key k.  The work is a branch-and-bound scan:
 //   - the valid list is cut into 64-row blocks, each with a per-parameter
-//     bounding box [min, max] of its value indices (built with the space);
+//     bounding box [min, max] of its value indices, and the boxes into chunks
+//     of 64 with a box over each chunk (both built with the space);
 //   - one wave owns one (candidate, part of the list) item and holds the
-//     candidate wave-uniform; its lanes first test 64 boxes at once against
-//     the candidate's current bound (a lower bound of the key over the box),
-//     then evaluate each surviving block with one row per lane;
+//     candidate wave-uniform; its lanes first test 64 chunk boxes at once
+//     against the candidate's current bound (a lower bound of the key over
+//     the box), then the 64 row boxes of each surviving chunk, then evaluate
+//     each surviving block with one row per lane;
 //   - the bound starts from the 64 valid rows around the candidate's place in
 //     linear-index order, so pruning is effective from the first block;
 //   - keys use byte-SIMD instructions (v_sad_u8 for index distance, a
@@ -25,8 +27,10 @@
 //
 // Every kernel walks an array of RepairSets (device memory), so one launch per
 // phase serves any number of candidate batches over any number of spaces; a
-// one-block plan kernel turns the per-set candidate counts into the item
-// space of each scan without a round trip to the host.
+// one-wave plan (run by the last block of the kernel that listed the
+// candidates, or as a launch of its own before the fallback) turns the per-set
+// candidate counts into the item space of each scan without a round trip to
+// the host.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
