@@ -564,6 +564,19 @@ __global__ __launch_bounds__(kBlock) void k_repair_prep(const RepairSet* __restr
     plan_if_last(sets, n_sets, pa);
 }
 
+// The first item of this wave.  Workgroups go to the 8 XCDs in turn (block b to XCD b mod 8), so
+// numbering the waves XCD by XCD makes item i, and every item after it in the grid-stride loop,
+// run on XCD i mod 8.  With a multiple of 8 parts per candidate (the plan rounds to one) and
+// multiples of 8 items before each candidate, item i is a part p of its candidate with
+// p mod 8 = i mod 8: every candidate's part p reads the same chunks of the list, so one XCD's L2
+// holds the eighth of the list its items read instead of each XCD fetching all of it.  Grids
+// that are not a multiple of 8 blocks keep the plain numbering.
+__device__ __forceinline__ uint32_t first_item(uint32_t wpb) {
+    const uint32_t b = blockIdx.x, w = threadIdx.x >> 6;
+    if (gridDim.x & 7u) return b * wpb + w;
+    return 8u * (wpb * (b >> 3) + w) + (b & 7u);
+}
+
 template <int M, int RW>
 __global__ __launch_bounds__(kBlock) void k_repair_scan(const RepairSet* __restrict__ sets, uint32_t n_sets,
                                                         RepairPlan plan, uint32_t which, uint32_t tab_stride) {
@@ -574,7 +587,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_scan(const RepairSet* __restr
     const uint32_t* off = plan.item_off + cls * (n_sets + 1);
     const uint32_t total = off[n_sets];
     const uint32_t waves = gridDim.x * wpb;
-    for (uint32_t item = uni(blockIdx.x * wpb + (threadIdx.x >> 6)); item < total; item += waves) {
+    for (uint32_t item = uni(first_item(wpb)); item < total; item += waves) {
         const uint32_t s = uni(find_set(off, n_sets, item));
         const RepairSet& J = sets[s];
         const DevSpace& S = *J.S;
@@ -594,7 +607,14 @@ __global__ __launch_bounds__(kBlock) void k_repair_scan(const RepairSet* __restr
 // All scanned metrics of one row width in a single launch: the item ranges of the classes in
 // `mmask` (bit m: metric m, Hamming to Alg. 3) are laid end to end and every wave takes items of
 // any of them, so the latency chains of the classes overlap instead of running one launch after
-// another.  Each item runs the same code as in its own class's kernel.
+// another.  Each item runs the same code as in its own class's kernel.  The ranges go in the
+// order their items tend to run longest (Alg. 2's distances, the index distance, Alg. 3's keys,
+// Hamming), so the longest start first, while the grid is still filling.
+__device__ __forceinline__ uint32_t mix_metric(uint32_t q) {
+    return q == 0 ? (uint32_t)CT_TIER_EUCLID : q == 1 ? (uint32_t)CT_INDEX_L1 : q == 2 ? (uint32_t)CT_TIER_RANDOM
+                                                                                      : (uint32_t)CT_HAMMING;
+}
+
 template <int RW>
 __global__ __launch_bounds__(kBlock) void k_repair_scan_mix(const RepairSet* __restrict__ sets, uint32_t n_sets,
                                                             RepairPlan plan, uint32_t which, uint32_t tab_stride,
@@ -606,15 +626,17 @@ __global__ __launch_bounds__(kBlock) void k_repair_scan_mix(const RepairSet* __r
     uint32_t end[4];
     uint32_t acc = 0;
 #pragma unroll
-    for (uint32_t m = 0; m < 4; ++m) {
+    for (uint32_t q = 0; q < 4; ++q) {
+        const uint32_t m = mix_metric(q);
         if (mmask & (1u << m)) acc += plan.item_off[(m * 4u + rwi) * (n_sets + 1) + n_sets];
-        end[m] = acc;
+        end[q] = acc;
     }
     const uint32_t waves = gridDim.x * wpb;
-    for (uint32_t item = uni(blockIdx.x * wpb + (threadIdx.x >> 6)); item < acc; item += waves) {
-        const uint32_t m = item < end[0] ? 0u : item < end[1] ? 1u : item < end[2] ? 2u : 3u;
+    for (uint32_t item = uni(first_item(wpb)); item < acc; item += waves) {
+        const uint32_t q = item < end[0] ? 0u : item < end[1] ? 1u : item < end[2] ? 2u : 3u;
+        const uint32_t m = mix_metric(q);
         const uint32_t* off = plan.item_off + (m * 4u + rwi) * (n_sets + 1);
-        const uint32_t local_item = item - (m ? end[m - 1] : 0u);
+        const uint32_t local_item = item - (q ? end[q - 1] : 0u);
         const uint32_t s = uni(find_set(off, n_sets, local_item));
         const RepairSet& J = sets[s];
         const DevSpace& S = *J.S;

@@ -33,7 +33,8 @@ __device__ __forceinline__ uint32_t plan_sum_u32(uint32_t v) {
 // a contiguous slice of the sets; offsets are the wave prefix of the lanes' totals plus the
 // running sum inside the slice.  which = 0: main lists with each set's metric; which = 1:
 // fallback lists, Hamming.  Each scan class is its own launch, so its candidates are split
-// into parts to give that launch about target_items items, each part min_sub boxes or more.
+// into parts to give that launch about target_items items, each part min_sub boxes or more, in a
+// multiple of 8 parts where there are 8 or more (the scans place part p on XCD p mod 8).
 __device__ inline void plan_wave(const RepairSet* __restrict__ sets, uint32_t n_sets, uint32_t which,
                                  const RepairPlan& plan, uint32_t class_mask, uint32_t target_items,
                                  uint32_t min_sub) {
@@ -68,6 +69,7 @@ __device__ inline void plan_wave(const RepairSet* __restrict__ sets, uint32_t n_
 #pragma unroll
         for (uint32_t q = 1; q < kRepairClasses; ++q) gp = q == cls ? gpc[q] : gp;
         uint64_t p = gp > pmax ? pmax : gp;
+        if (p >= 8) p &= ~7ull;          // whole eighths: part p of every candidate on XCD p mod 8
         if (p < 1 || cls / 4u == (uint32_t)CT_HAM1_RANDOM) p = 1;   // enumerated, not scanned
         plan.parts[s] = (uint32_t)p;
         const uint32_t c = plan_count(sets, s, which);
