@@ -596,7 +596,7 @@ int autotune_sweep(ct_batch* b, hipStream_t st) {
         for (uint32_t mode : modes)
             for (uint32_t it : {2048u, 4096u, 8192u})
                 for (uint32_t ms : {8u, 16u, 32u, 64u})
-                    for (uint32_t gw : {4096u, 8192u}) b->tune_cand.push_back(RepairTune{it, ms, gw, mode});
+                    for (uint32_t gw : {4096u, 8192u, 16384u}) b->tune_cand.push_back(RepairTune{it, ms, gw, mode});
         b->tune_ms.assign(b->tune_cand.size(), 0.0);
     }
     const std::vector<RepairTune>& cand = b->tune_cand;
