@@ -161,12 +161,13 @@ def test_autotuned_batch_equals_plain(spaces):
 
 
 @pytest.mark.parametrize("tune", [(64, 1, 64, 0), (2048, 8, 4096, 1), (8192, 64, 8192, 1), (8192, 1024, 512, 0),
-                                  (64, 1, 64, 2), (4096, 16, 8192, 2), (8192, 64, 512, 2)])
+                                  (64, 1, 64, 2), (4096, 16, 8192, 2), (8192, 64, 512, 2), (8192, 16, 16384, 2),
+                                  (2048, 8, 100, 2), (4096, 32, 1000, 0)])
 def test_set_tuning_equals_plain(spaces, tune):
     """Any installed scan partitioning (few or many items per launch, small or large boxes per
-    part, small or large grids; scan classes one after another, on side streams or fused per row
-    width) gives the plain results,
-    both launched directly and replayed from a graph."""
+    part, small or large grids, grids of a multiple of 8 blocks (waves numbered XCD by XCD) or not
+    (plain numbering); scan classes one after another, on side streams or fused per row width)
+    gives the plain results, both launched directly and replayed from a graph."""
     from paper_2606_28372_amd import Batch, CT_STEP_BATCHED, CT_STEP_GRAPH, step_many
     t = torch()
     plain, tuned = make_runs(t, spaces), make_runs(t, spaces)
