@@ -781,6 +781,13 @@ __global__ __launch_bounds__(kBlock) void k_repair_finish(const RepairSet* __res
     plan_if_last(sets, n_sets, pa);
 }
 
+// Waves of one scan launch.  The fallback pass (which = 1) has one class, planned for about
+// `items` items (more only when it has more candidates than that), so a grid beyond that would
+// only add blocks that find no item.
+uint32_t scan_waves(const RepairPasses& rp, uint32_t which) {
+    return which ? std::min(rp.tune.grid_waves, rp.tune.items) : rp.tune.grid_waves;
+}
+
 template <int M, int RW>
 void launch_scan_rw(const RepairPasses& rp, uint32_t which, hipStream_t st) {
     ProfScope ps_("k_repair_scan", st);
@@ -788,7 +795,7 @@ void launch_scan_rw(const RepairPasses& rp, uint32_t which, hipStream_t st) {
     const uint32_t stride = M == CT_TIER_EUCLID ? std::max<uint32_t>(rp.euclid_tab, 1) : 0;
     uint32_t wpb = kBlock / 64;
     while (wpb > 1 && (size_t)wpb * stride * 8 > 65536) wpb >>= 1;
-    hipLaunchKernelGGL((k_repair_scan<M, RW>), dim3(std::max<uint32_t>(rp.tune.grid_waves / wpb, 1)), dim3(wpb * 64),
+    hipLaunchKernelGGL((k_repair_scan<M, RW>), dim3(std::max<uint32_t>(scan_waves(rp, which) / wpb, 1)), dim3(wpb * 64),
                        (size_t)wpb * stride * 8, st,
                        rp.d_sets, rp.n_sets, rp.plan, which, stride);
 }
@@ -799,7 +806,7 @@ void launch_mix_rw(const RepairPasses& rp, uint32_t mmask, uint32_t which, hipSt
     const uint32_t stride = (mmask & (1u << CT_TIER_EUCLID)) ? std::max<uint32_t>(rp.euclid_tab, 1) : 0;
     uint32_t wpb = kBlock / 64;
     while (wpb > 1 && (size_t)wpb * stride * 8 > 65536) wpb >>= 1;
-    hipLaunchKernelGGL((k_repair_scan_mix<RW>), dim3(std::max<uint32_t>(rp.tune.grid_waves / wpb, 1)), dim3(wpb * 64),
+    hipLaunchKernelGGL((k_repair_scan_mix<RW>), dim3(std::max<uint32_t>(scan_waves(rp, which) / wpb, 1)), dim3(wpb * 64),
                        (size_t)wpb * stride * 8, st, rp.d_sets, rp.n_sets, rp.plan, which, stride, mmask);
 }
 
