@@ -276,7 +276,7 @@ void ct_batch_free(ct_batch* b);
 int ct_batch_autotune(ct_batch* b, uint32_t n_generations, uint32_t sample_every, uint32_t force, void* stream);
 /*
  * ct_batch_set_tuning -- install a scan partitioning for this batch (one saved
- * from ct_batch_tuning, say): items in [64, 8192], min_boxes in [1, 2^20],
+ * from ct_batch_tuning, say): items in [64, 32768], min_boxes in [1, 2^20],
  * grid_waves in [64, 2^20], mode one of CT_SCAN_*; CT_EINVAL otherwise.
  * Results do not depend on it.  The batch counts as tuned; the process-wide
  * cache is left alone.  CT_SCAN_STREAMS on a batch of one run launches serially.

@@ -239,7 +239,7 @@ int batch_build(const std::vector<ct_pop*>& pops, ct_batch** out, hipStream_t st
 
 uint64_t pop_footprint_bytes(uint32_t algo, uint32_t P, uint32_t D, uint32_t R, uint64_t n_valid) {
     const uint64_t p = P, pd = (uint64_t)P * D;
-    const uint64_t slots = std::max<uint64_t>(P, kRepairTargetWaves);
+    const uint64_t slots = std::max<uint64_t>(P, kRepairMaxItems);
     uint64_t b = 16 + 16 + 16 + 8 + 2 * p * R + 4 * p + p;      // state, tally, rcount, best, trial, out, tpos, apply
     if (algo == CT_PSO) b += pd * (4 + 8 + 4) + 8 * p;           // X, V, PB, f_pb, pb_pos
     else b += 8 * p;                                              // pos, f
@@ -575,7 +575,7 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_ob
         ct_pop_free(p);
         return code_;
     };
-    const uint64_t slots = std::max<uint64_t>(P, kRepairTargetWaves);
+    const uint64_t slots = std::max<uint64_t>(P, kRepairMaxItems);
     if ((rc = dalloc(p, &d.state, 4)) || (rc = dalloc(p, &d.tally, 2)) || (rc = dalloc(p, &d.rcount, 4)) || (rc = dalloc(p, &d.best, 1)) || (rc = dalloc(p, &d.trial, (size_t)P * d.R)) ||
         (rc = dalloc(p, &d.out, (size_t)P * d.R)) || (rc = dalloc(p, &d.tpos, P)) || (rc = dalloc(p, &d.apply, P)))
         return fail(rc);
@@ -719,10 +719,10 @@ int ct_batch_autotune(ct_batch* b, uint32_t n_generations, uint32_t sample_every
 
 int ct_batch_set_tuning(ct_batch* b, uint32_t items, uint32_t min_boxes, uint32_t grid_waves, uint32_t mode) {
     if (!b) return ct_fail(CT_EINVAL, "ct_batch_set_tuning: null batch");
-    // items <= kRepairTargetWaves keeps every set's (candidate, part) winners within its slots
-    if (items < 64 || items > kRepairTargetWaves || min_boxes < 1 || min_boxes > (1u << 20) || grid_waves < 64 ||
+    // items <= kRepairMaxItems keeps every set's (candidate, part) winners within its slots
+    if (items < 64 || items > kRepairMaxItems || min_boxes < 1 || min_boxes > (1u << 20) || grid_waves < 64 ||
         grid_waves > (1u << 20) || mode > CT_SCAN_FUSED)
-        return ct_fail(CT_EINVAL, "ct_batch_set_tuning: items in [64, 8192], min_boxes in [1, 2^20], "
+        return ct_fail(CT_EINVAL, "ct_batch_set_tuning: items in [64, 32768], min_boxes in [1, 2^20], "
                                   "grid_waves in [64, 2^20], mode CT_SCAN_SERIAL, _STREAMS or _FUSED");
     b->passA.tune = RepairTune{items, min_boxes, grid_waves, mode};
     b->tuned = true;

@@ -114,7 +114,11 @@ struct RepairPlan {
     uint32_t* done;                   // blocks finished in the kernel that plans (0 between launches)
 };
 
-constexpr uint32_t kRepairTargetWaves = 8192;   // scan items per pass (also the per-set slot minimum)
+constexpr uint32_t kRepairTargetWaves = 8192;   // scan items per class launch, untuned (ct_repair's slot minimum)
+// Largest item target a batch may be tuned to; every run holds max(P, kRepairMaxItems) slots for
+// per-(candidate, part) winners, so c candidates of a set split into p parts (c * p <= the target,
+// or p = 1) always fit.
+constexpr uint32_t kRepairMaxItems = 32768;
 
 // How the scan classes of one pass are launched: one after another, side by side on the fan's
 // streams, or the scanned metrics of one row width together in one launch.

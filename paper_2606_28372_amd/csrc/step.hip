@@ -593,10 +593,14 @@ int autotune_sweep(ct_batch* b, hipStream_t st) {
     if (b->tune_cand.empty()) {
         std::vector<uint32_t> modes = {kScanSerial, kScanFused};
         if (b->fan.fork) modes.push_back(kScanStreams);
+        // item targets up to the slots' limit (large batches split their long scans finely);
+        // grids from a quarter of the target to four times it (a fused launch holds the items
+        // of several classes)
         for (uint32_t mode : modes)
-            for (uint32_t it : {2048u, 4096u, 8192u})
+            for (uint32_t it : {2048u, 4096u, 8192u, 16384u, 32768u})
                 for (uint32_t ms : {8u, 16u, 32u, 64u})
-                    for (uint32_t gw : {4096u, 8192u, 16384u}) b->tune_cand.push_back(RepairTune{it, ms, gw, mode});
+                    for (uint32_t gw : {4096u, 8192u, 16384u, 32768u})
+                        if (gw <= 4 * it && 4 * gw >= it) b->tune_cand.push_back(RepairTune{it, ms, gw, mode});
         b->tune_ms.assign(b->tune_cand.size(), 0.0);
     }
     const std::vector<RepairTune>& cand = b->tune_cand;

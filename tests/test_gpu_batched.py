@@ -143,8 +143,8 @@ def test_autotuned_batch_equals_plain(spaces):
     b.autotune(11, sample_every=5, force=True)    # sweeps at 0, 5 and 10; a timed block of each stream setting between
     tn = b.tuning()
     say(f"[gpu_batched] tuning {tn}")
-    assert tn["tuned"] and tn["items"] in (2048, 4096, 8192) and tn["min_boxes"] in (8, 16, 32, 64)
-    assert tn["grid_waves"] in (4096, 8192, 16384) and tn["mode"] in (0, 1, 2)
+    assert tn["tuned"] and tn["items"] in (2048, 4096, 8192, 16384, 32768) and tn["min_boxes"] in (8, 16, 32, 64)
+    assert tn["grid_waves"] in (4096, 8192, 16384, 32768) and tn["mode"] in (0, 1, 2)
     step_many(plain, 11)
     t.cuda.synchronize()
     for x, y in zip(plain, tuned):
@@ -162,7 +162,7 @@ def test_autotuned_batch_equals_plain(spaces):
 
 @pytest.mark.parametrize("tune", [(64, 1, 64, 0), (2048, 8, 4096, 1), (8192, 64, 8192, 1), (8192, 1024, 512, 0),
                                   (64, 1, 64, 2), (4096, 16, 8192, 2), (8192, 64, 512, 2), (8192, 16, 16384, 2),
-                                  (2048, 8, 100, 2), (4096, 32, 1000, 0)])
+                                  (32768, 64, 32768, 2), (2048, 8, 100, 2), (4096, 32, 1000, 0)])
 def test_set_tuning_equals_plain(spaces, tune):
     """Any installed scan partitioning (few or many items per launch, small or large boxes per
     part, small or large grids, grids of a multiple of 8 blocks (waves numbered XCD by XCD) or not
@@ -190,7 +190,7 @@ def test_set_tuning_rejects_out_of_range(spaces):
     t = torch()
     b = Batch(make_runs(t, spaces))
     before = b.tuning()
-    for bad in [(63, 16, 4096, 0), (8193, 16, 4096, 0), (4096, 0, 4096, 0), (4096, 16, 32, 0), (4096, 16, 4096, 3)]:
+    for bad in [(63, 16, 4096, 0), (32769, 16, 4096, 0), (4096, 0, 4096, 0), (4096, 16, 32, 0), (4096, 16, 4096, 3)]:
         with pytest.raises(CtError):
             b.set_tuning(*bad)
     assert b.tuning() == before
