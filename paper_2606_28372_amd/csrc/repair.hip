@@ -45,6 +45,7 @@ constexpr uint64_t kNoKey = ~0ull;
 constexpr uint32_t kNoPos = 0xFFFFFFFFu;
 constexpr uint64_t kTier3 = 3ull << 62;
 constexpr uint32_t kMaxSets = 4096;
+constexpr uint32_t kFallbackMinSub = 16;   // least boxes per part of the fallback pass, at most
 constexpr uint32_t kNumClasses = kRepairClasses;
 
 __device__ __forceinline__ uint32_t ne_bytes(uint32_t x) {
@@ -953,10 +954,12 @@ int launch_repair_passes(const RepairPasses& rp, bool zero_counts, hipStream_t s
     if (rp.fb_class_mask) {
         {
             // a launch of its own: the finish runs hundreds of blocks, and counting them all
-            // costs more than a one-wave launch
+            // costs more than a one-wave launch.  The few fallback candidates sit far from valid
+            // rows, where parts of more than 16 boxes only lengthen the pass, whatever suits the
+            // main pass.
             ProfScope ps_("k_repair_plan", st);
             hipLaunchKernelGGL(k_repair_plan, dim3(1), dim3(64), 0, st, rp.d_sets, rp.n_sets, 1u, rp.plan,
-                               rp.fb_class_mask, rp.tune.items, rp.tune.min_sub);
+                               rp.fb_class_mask, rp.tune.items, std::min(rp.tune.min_sub, kFallbackMinSub));
         }
         if (int rc = launch_scans(rp, rp.fb_class_mask, 1, st)) return rc;
         {
