@@ -241,24 +241,26 @@ def test_wide_rows_batch_equals_plain(mode):
     b.close()
 
 
-def test_sparse16_group_level_partitions_agree():
-    """On the 4.66M-row space (1,137 chunks, 18 groups) one part per candidate walks the group
-    level; the default partitioning cuts candidates into many strided parts: same results."""
+def test_sparse16_partitions_agree():
+    """On the 4.66M-row space (1,137 chunks) one part per candidate walks every chunk; the other
+    partitionings cut candidates into many strided parts, or into whole eighths of up to 32,768
+    items on a 32,768-wave grid: same results."""
     from paper_2606_28372_amd import Batch, CT_STEP_BATCHED, Pop
     t = torch()
     sp = gpu_space(W.space("sparse16"))
     obj = t.tensor(W.objective(sp.n_valid, 14), device="cuda")
     opts = [W.OptParams(W.ALGO_GA, 256, 60), W.OptParams(W.ALGO_DE, 256, 61), W.OptParams(W.ALGO_PSO, 256, 62)]
-    one = [Pop.from_opt(sp, o, obj) for o in opts]
-    many = [Pop.from_opt(sp, o, obj) for o in opts]
-    b1, b2 = Batch(one), Batch(many)
-    b1.set_tuning(64, 1, 4096, 2)          # fewer items than candidates: one part each
-    b2.set_tuning(8192, 1, 8192, 0)        # many small parts
-    say("[gpu_batched] sparse16 group level")
-    b1.step(2, CT_STEP_BATCHED)
-    b2.step(2, CT_STEP_BATCHED)
+    runs = [[Pop.from_opt(sp, o, obj) for o in opts] for _ in range(3)]
+    batches = [Batch(r) for r in runs]
+    batches[0].set_tuning(64, 1, 4096, 2)          # fewer items than candidates: one part each
+    batches[1].set_tuning(8192, 1, 8192, 0)        # many small parts
+    batches[2].set_tuning(32768, 64, 32768, 2)     # the largest item target, parts in eighths
+    say("[gpu_batched] sparse16 partitions")
+    for b in batches:
+        b.step(2, CT_STEP_BATCHED)
     t.cuda.synchronize()
-    for k, (x, y) in enumerate(zip(one, many)):
-        assert x.snapshot() == y.snapshot(), f"run {k} differs"
-    b1.close()
-    b2.close()
+    for other in runs[1:]:
+        for k, (x, y) in enumerate(zip(runs[0], other)):
+            assert x.snapshot() == y.snapshot(), f"run {k} differs"
+    for b in batches:
+        b.close()
