@@ -408,6 +408,63 @@ __device__ void ga_sort_block(const PopDev& p) {
         if (i < p.P) p.sorted[i] = (uint32_t)v;
         return;
     }
+    constexpr uint32_t kMaxPerThread = kGaMaxSort / kSelBlock;
+    const uint32_t q = m / blockDim.x;                    // keys per thread
+    if ((blockDim.x & 63u) == 0 && q <= kMaxPerThread) {
+        // More keys than threads: wave w holds keys w*64q + 64r + lane (r < q) in registers, so
+        // every stage whose partners lie less than 64 apart pairs lanes of one wave in one
+        // register and runs on cross-lane shuffles; only the stages 64 or more apart go through
+        // LDS and a barrier (4,096 keys: 21 of 78 stages).  The compare-exchange network is the
+        // plain bitonic one, so the order is the same.
+        const uint32_t base = (threadIdx.x >> 6) * 64u * q + (threadIdx.x & 63u);
+        uint64_t v[kMaxPerThread];
+#pragma unroll
+        for (uint32_t r = 0; r < kMaxPerThread; ++r) {
+            const uint32_t i = base + 64u * r;
+            v[r] = r < q && i < p.P ? best_key(p.f[i], p.pos[i]) : ~0ull;
+        }
+        for (uint32_t k = 2; k <= m; k <<= 1) {
+            uint32_t j = k >> 1;
+            if (j >= 64) {
+#pragma unroll
+                for (uint32_t r = 0; r < kMaxPerThread; ++r)
+                    if (r < q) key[base + 64u * r] = v[r];
+                __syncthreads();
+                for (; j >= 64; j >>= 1) {
+                    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+                        const uint32_t l = i ^ j;
+                        if (l > i) {
+                            const bool up = (i & k) == 0;
+                            const uint64_t a = key[i], b = key[l];
+                            if ((a > b) == up) { key[i] = b; key[l] = a; }
+                        }
+                    }
+                    __syncthreads();
+                }
+#pragma unroll
+                for (uint32_t r = 0; r < kMaxPerThread; ++r)
+                    if (r < q) v[r] = key[base + 64u * r];
+            }
+            for (; j > 0; j >>= 1) {
+#pragma unroll
+                for (uint32_t r = 0; r < kMaxPerThread; ++r) {
+                    if (r < q) {
+                        const uint32_t i = base + 64u * r;
+                        const uint64_t o = shfl_xor_u64(v[r], (int)j);
+                        const bool up = (i & k) == 0;
+                        const bool keep_min = ((i & j) == 0) == up;
+                        v[r] = keep_min ? (o < v[r] ? o : v[r]) : (o > v[r] ? o : v[r]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < kMaxPerThread; ++r) {
+            const uint32_t i = base + 64u * r;
+            if (r < q && i < p.P) p.sorted[i] = (uint32_t)v[r];
+        }
+        return;
+    }
     for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) key[i] = i < p.P ? best_key(p.f[i], p.pos[i]) : ~0ull;
     __syncthreads();
     for (uint32_t k = 2; k <= m; k <<= 1) {

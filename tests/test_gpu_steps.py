@@ -112,6 +112,18 @@ def test_small_populations_and_odd_sizes():
     run("tiny", W.OptParams(W.ALGO_DE, 20, 8, F_q16=0, CR_q32=1 << 32), 3, 0)   # forced reinitialisation
 
 
+@pytest.mark.parametrize("P", [1500, 3000])
+def test_ga_populations_past_the_block_size(P):
+    """GA populations larger than the selection block (1,024 threads) rank-sort with several keys
+    per thread (2 and 4 here): generation by generation equal to the oracle."""
+    run("gemm10", W.OptParams(W.ALGO_GA, P, 9), 3, 1)
+
+
+def test_ga_largest_population():
+    """GA at its largest population (8,192: eight keys per thread in the rank sort)."""
+    run("gemm13", W.OptParams(W.ALGO_GA, 8192, 10), 2, 1)
+
+
 def test_rand1bin_and_other_coefficients():
     run("gemm10", W.OptParams(W.ALGO_DE, 64, 9, de_best=0, F_q16=65536, CR_q32=1 << 31), 4, 1)
     run("gemm10", W.OptParams(W.ALGO_PSO, 64, 10, w_q16=50000, c1_q16=70000, c2_q16=150000), 4, 1)
