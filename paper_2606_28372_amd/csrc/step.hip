@@ -362,7 +362,10 @@ void launch_propose(const ct_batch* b, const PlanArgs& pa, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // GA: sort the population by (objective, position), one block per GA run
 // ---------------------------------------------------------------------------
-__device__ void ga_sort_block(const PopDev& p) {
+// Returns, in thread 0 when the population fits the block, the smallest key (the rank-0
+// individual's); `own`, when given, is the calling thread's individual's key (individual
+// threadIdx.x), so it need not be read back from memory.
+__device__ uint64_t ga_sort_block(const PopDev& p, const uint64_t* own = nullptr) {
     __shared__ uint64_t key[kGaMaxSort];
     uint32_t m = 1;
     while (m < p.P) m <<= 1;
@@ -374,7 +377,7 @@ __device__ void ga_sort_block(const PopDev& p) {
         // run's go first), so each round is one binary search and one barrier, not a series of
         // exchange stages.
         const uint32_t i = threadIdx.x;
-        uint64_t v = i < p.P ? best_key(p.f[i], p.pos[i]) : ~0ull;
+        uint64_t v = i < p.P ? (own ? *own : best_key(p.f[i], p.pos[i])) : ~0ull;
         const uint32_t w = m < 64 ? m : 64;
         for (uint32_t k = 2; k <= w; k <<= 1) {
             for (uint32_t j = k >> 1; j > 0; j >>= 1) {
@@ -406,7 +409,7 @@ __device__ void ga_sort_block(const PopDev& p) {
             if (i < m) v = src[i];
         }
         if (i < p.P) p.sorted[i] = (uint32_t)v;
-        return;
+        return v;
     }
     constexpr uint32_t kMaxPerThread = kGaMaxSort / kSelBlock;
     const uint32_t q = m / blockDim.x;                    // keys per thread
@@ -463,7 +466,7 @@ __device__ void ga_sort_block(const PopDev& p) {
             const uint32_t i = base + 64u * r;
             if (r < q && i < p.P) p.sorted[i] = (uint32_t)v[r];
         }
-        return;
+        return ~0ull;
     }
     for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) key[i] = i < p.P ? best_key(p.f[i], p.pos[i]) : ~0ull;
     __syncthreads();
@@ -481,11 +484,12 @@ __device__ void ga_sort_block(const PopDev& p) {
         }
     }
     for (uint32_t i = threadIdx.x; i < p.P; i += blockDim.x) p.sorted[i] = (uint32_t)key[i];
+    return ~0ull;
 }
 
 // The rank order of a GA run's population (read by the next generation's proposals): sorted at
 // creation, after a restore, and by the selection kernel at the end of every generation.
-__global__ __launch_bounds__(kSelBlock) void k_ga_sort_one(PopDev p) { ga_sort_block(p); }
+__global__ __launch_bounds__(kSelBlock) void k_ga_sort_one(PopDev p) { (void)ga_sort_block(p); }
 
 // ---------------------------------------------------------------------------
 // select: one block per run
@@ -594,10 +598,30 @@ __global__ __launch_bounds__(kSelBlock) void k_select(const PopDev* __restrict__
     const PopDev& p = pops[blockIdx.x];
     if (p.algo == CT_DE) de_select(p);
     else if (p.algo == CT_PSO) pso_select(p);
-    else {
+    else if (p.P <= blockDim.x) {
+        // one child per thread: its key goes to the rank sort (the next generation's rank order)
+        // in a register, and the sorted order's first key is the generation's best
+        const uint32_t g = p.state[0];
+        uint64_t k = ~0ull;
+        const uint32_t i = threadIdx.x;
+        if (i < p.P) {
+            uint32_t t = p.tpos[i];
+            if (t >= p.n_valid) t = p.pos[i];            // unreachable: every repaired child is valid
+            const float fv = p.obj[t];
+            p.pos[i] = t;
+            p.f[i] = fv;
+            k = best_key(fv, t);
+        }
+        const uint64_t m = ga_sort_block(p, &k);
+        if (threadIdx.x == 0) {
+            const uint64_t b = *p.best;
+            *p.best = m < b ? m : b;
+            p.state[0] = g + 1;
+        }
+    } else {
         ga_select(p);
         __syncthreads();
-        ga_sort_block(p);                                 // the next generation's rank order
+        (void)ga_sort_block(p);                           // the next generation's rank order
     }
     if (threadIdx.x < 4) p.rcount[threadIdx.x] = 0;      // repair counters of the next generation
 }
