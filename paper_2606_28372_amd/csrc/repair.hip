@@ -782,9 +782,9 @@ __global__ __launch_bounds__(kBlock) void k_repair_finish(const RepairSet* __res
     plan_if_last(sets, n_sets, pa);
 }
 
-// Waves of one scan launch.  The fallback pass (which = 1) has one class, planned for about
-// `items` items (more only when it has more candidates than that), so a grid beyond that would
-// only add blocks that find no item.
+// Waves of one scan launch.  Each launch of the fallback pass (which = 1) scans one class
+// (Hamming at one row width), planned for about `items` items (more only when it has more
+// candidates than that), so a grid beyond that would only add blocks that find no item.
 uint32_t scan_waves(const RepairPasses& rp, uint32_t which) {
     return which ? std::min(rp.tune.grid_waves, rp.tune.items) : rp.tune.grid_waves;
 }
