@@ -117,8 +117,9 @@ def de_init(space, obj, P, seed) -> DEState:
     return DEState(pos, f, np.float32(b[0]), int(b[1]))
 
 
-def de_step(space: core.Space, obj: np.ndarray, st: DEState, seed: int, F_q16: int, CR_q32: int,
-            use_best: bool = True) -> DEState:
+def de_trials(space: core.Space, st: DEState, seed: int, F_q16: int, CR_q32: int,
+              use_best: bool = True) -> np.ndarray:
+    """Alg. 1's Mutate and Crossover for every member: the trial vectors before repair."""
     P, D, g = len(st.pos), space.D, st.gen
     if P < 4:
         raise ValueError("DE needs at least 4 members")
@@ -139,6 +140,13 @@ def de_step(space: core.Space, obj: np.ndarray, st: DEState, seed: int, F_q16: i
             m = min(max(num // 65536, 0), int(rad[j]) - 1)
             cr = draw(seed, i, g, P_DE_CR, j >> 2)[j & 3]
             trials[i, j] = m if (cr < CR_q32 or j == j_rand) else X[i, j]
+    return trials
+
+
+def de_step(space: core.Space, obj: np.ndarray, st: DEState, seed: int, F_q16: int, CR_q32: int,
+            use_best: bool = True) -> DEState:
+    P, g = len(st.pos), st.gen
+    trials = de_trials(space, st, seed, F_q16, CR_q32, use_best)
     # Repair: invalid trials move to the nearest valid configuration by index distance
     trials = space.repair(trials, core.INDEX_L1)
     upos = space.pos(space.encode(trials))
@@ -204,12 +212,13 @@ def pso_init(space, obj, P, seed) -> PSOState:
     return PSOState(X.copy(), np.zeros_like(X), X.copy(), f.copy(), pos.copy(), _gbest(f))
 
 
-def pso_step(space: core.Space, obj: np.ndarray, st: PSOState, seed: int, w_q16: int, c1_q16: int,
-             c2_q16: int) -> PSOState:
+def pso_move(space: core.Space, st: PSOState, seed: int, w_q16: int, c1_q16: int, c2_q16: int):
+    """Velocity and position update of every particle and the snapped configurations
+    (before Alg. 2's repair): returns (X, V, snapped)."""
     P, D, g = st.X.shape[0], space.D, st.gen
     M = int(space.radices.max())
     hi = M * 65536 - 1
-    X, V, PB = st.X.copy(), st.V.copy(), st.PB.copy()
+    X, V, PB = st.X.copy(), st.V.copy(), st.PB
     GB = st.PB[st.g_idx].copy()
     snapped = np.zeros((P, D), dtype=np.int32)
     for i in range(P):
@@ -223,6 +232,14 @@ def pso_step(space: core.Space, obj: np.ndarray, st: PSOState, seed: int, w_q16:
             x = min(max(x + v, 0), hi)
             V[i, j], X[i, j] = v, x
             snapped[i, j] = min(x >> 16, int(space.radices[j]) - 1)
+    return X, V, snapped
+
+
+def pso_step(space: core.Space, obj: np.ndarray, st: PSOState, seed: int, w_q16: int, c1_q16: int,
+             c2_q16: int) -> PSOState:
+    P, g = st.X.shape[0], st.gen
+    X, V, snapped = pso_move(space, st, seed, w_q16, c1_q16, c2_q16)
+    PB = st.PB.copy()
     # Evaluation goes through Alg. 2: invalid snapped points are replaced by the nearest
     # neighbour (Euclidean distance to the particle) of the first non-empty neighbour set.
     ev = space.repair(snapped, core.TIER_EUCLID, pos_q16=X)
@@ -255,8 +272,10 @@ def ga_init(space, obj, P, seed) -> GAState:
     return GAState(pos, f, np.float32(b[0]), int(b[1]))
 
 
-def ga_step(space: core.Space, obj: np.ndarray, st: GAState, seed: int, mutation_chance: int,
-            beta_b: int, table: Optional[List[int]] = None) -> GAState:
+def ga_crossover(space: core.Space, st: GAState, seed: int, beta_b: int,
+                 table: Optional[List[int]] = None) -> np.ndarray:
+    """Rank selection of two parents per pair and single-point crossover: every child before
+    Alg. 3's repair and the mutation (child 2k is A[:cut] + B[cut:], child 2k+1 is B[:cut] + A[cut:])."""
     P, D, g = len(st.pos), space.D, st.gen
     order = sorted(range(P), key=lambda i: (float(st.f[i]), int(st.pos[i])))
     table = table or beta_rank_table(P, beta_b)
@@ -270,6 +289,13 @@ def ga_step(space: core.Space, obj: np.ndarray, st: GAState, seed: int, mutation
         children[2 * k] = np.concatenate([A[:cut], B[cut:]])
         if 2 * k + 1 < P:
             children[2 * k + 1] = np.concatenate([B[:cut], A[cut:]])
+    return children
+
+
+def ga_step(space: core.Space, obj: np.ndarray, st: GAState, seed: int, mutation_chance: int,
+            beta_b: int, table: Optional[List[int]] = None) -> GAState:
+    P, g = len(st.pos), st.gen
+    children = ga_crossover(space, st, seed, beta_b, table)
     # Alg. 3: invalid children become a random member of the first non-empty neighbour set
     children = space.repair(children, core.TIER_RANDOM, key=seed, gen=g)
     # Mutation (after repair): with chance 1/mutation_chance, a random valid Hamming neighbour
@@ -290,20 +316,11 @@ def ga_children(space: core.Space, obj: np.ndarray, st: GAState, seed: int, muta
                 indices, table: Optional[List[int]] = None) -> np.ndarray:
     """Final rows of selected children of generation st.gen (same definition as ga_step).
 
-    Lets a test check a sample of a large population without computing all of it.
+    Lets a test check a sample of a large population without repairing all of it.
     """
-    P, D, g = len(st.pos), space.D, st.gen
+    g = st.gen
     idx = np.asarray(indices, dtype=np.int64)
-    order = sorted(range(P), key=lambda i: (float(st.f[i]), int(st.pos[i])))
-    table = table or beta_rank_table(P, beta_b)
-    rows = space.vrows[st.pos]
-    kids = np.zeros((len(idx), D), dtype=np.int32)
-    for n, i in enumerate(idx):
-        o = draw(seed, int(i) // 2, g, P_GA_SEL)
-        A = rows[order[rank_from_draw(table, o[0])]]
-        B = rows[order[rank_from_draw(table, o[1])]]
-        cut = 1 + uniform_below(o[2], D - 1)
-        kids[n] = np.concatenate([A[:cut], B[cut:]]) if i % 2 == 0 else np.concatenate([B[:cut], A[cut:]])
+    kids = ga_crossover(space, st, seed, beta_b, table)[idx]
     kids = space.repair(kids, core.TIER_RANDOM, who=idx, key=seed, gen=g)
     thresh = (1 << 32) // mutation_chance
     mut = [n for n, i in enumerate(idx) if draw(seed, int(i), g, P_GA_MUT)[0] < thresh]
