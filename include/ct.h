@@ -77,6 +77,9 @@ enum ct_step_flags {
 #define CT_MAX_RADIX 255
 #define CT_MAX_POP 65536
 #define CT_MAX_CARTESIAN_LOG2 46
+/* Valid-list positions are 32-bit (0xFFFFFFFF means "none"): ct_repair, ct_pop_create and the
+   server need n_valid <= CT_MAX_VALID; larger spaces still build, count, mask and rank. */
+#define CT_MAX_VALID 0xFFFFFFFEull
 
 /* Message for the last error on this thread (never NULL). */
 const char* ct_last_error(void);
@@ -182,7 +185,7 @@ int ct_rank(const ct_space* s, const uint8_t* d_rows, uint64_t n, int64_t* d_pos
  * Outputs: d_out_rows[n][row_bytes], d_out_pos[n] (position of the result in
  * the valid list, or 0xFFFFFFFF for an unchanged invalid HAM1_RANDOM row).
  * d_out_rows may equal d_rows.
- * Errors: CT_EEMPTY (no valid configuration), CT_EINVAL, CT_ENOMEM.
+ * Errors: CT_EEMPTY (no valid configuration), CT_EINVAL (also n_valid > CT_MAX_VALID), CT_ENOMEM.
  */
 int ct_repair(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t metric,
               uint64_t seed, uint32_t generation, const uint32_t* d_who, const int32_t* d_pos_q16,
@@ -215,7 +218,7 @@ typedef struct {
  * d_objective[n_valid] (float32, > 0, borrowed: must outlive the run) stands
  * for the measured runtime of each valid configuration, indexed by position
  * in the valid list; lower is better.
- * Errors: CT_EINVAL (parameters), CT_EEMPTY, CT_ENOMEM.
+ * Errors: CT_EINVAL (parameters, n_valid > CT_MAX_VALID), CT_EEMPTY, CT_ENOMEM.
  */
 int ct_pop_create(const ct_space* s, const ct_pop_params* p, const float* d_objective, void* stream,
                   ct_pop** out);
@@ -306,6 +309,11 @@ int ct_pop_counters(const ct_pop* p, uint64_t* repairs, uint64_t* mutations);
  * float f[P]; for PSO int32 X[P][D], int64 V[P][D], int32 PB[P][D],
  * float f_pb[P], uint32 pb_pos[P], uint32 gbest_index.  Call with
  * h_buf = NULL to get the size.  A restored run continues bit-identically.
+ * ct_pop_restore checks the whole snapshot on the host before it writes
+ * anything to the device: the run's shape (algorithm, pop_size, n_params),
+ * every position and best_pos below n_valid, DE positions distinct, PSO
+ * coordinates X and PB in [0, M * 2^16) (M the largest radix), |V| < 2^46 and
+ * gbest_index < pop_size; on CT_EINVAL the run is left as it was.
  */
 int ct_pop_snapshot(const ct_pop* p, void* h_buf, size_t* len);
 int ct_pop_restore(ct_pop* p, const void* h_buf, size_t len);

@@ -42,6 +42,22 @@ def _ptr(t) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr() if t is not None else 0)
 
 
+def _device_arg(t, name: str, dtypes, shape=None):
+    """Check a tensor handed to the library by pointer: device memory, dtype, dense layout, shape."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor on the GPU, got {type(t).__name__}")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{name} must have dtype {' or '.join(str(d) for d in dtypes)}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be in GPU memory")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
 def compile_constraints(names: Sequence[str], values: Sequence[Sequence[int]],
                         constraints: Sequence[str]) -> Tuple[np.ndarray, np.ndarray]:
     """ct_compile: constraint strings -> (bytecode words, program offsets)."""
@@ -119,14 +135,21 @@ class Space:
         out[:, : self.D] = d.to(device="cuda", dtype=torch.uint8)
         return out
 
+    def _rows_arg(self, rows, name="rows"):
+        torch = _torch()
+        n = rows.shape[0] if isinstance(rows, torch.Tensor) and rows.dim() == 2 else -1
+        return _device_arg(rows, name, (torch.uint8,), (n, self.row_bytes))
+
     def valid_mask(self, rows):
         torch = _torch()
+        self._rows_arg(rows)
         out = torch.empty(rows.shape[0], dtype=torch.uint8, device="cuda")
         _lib.check(_lib.load().ct_valid_mask(self._h, _ptr(rows), rows.shape[0], _ptr(out), _stream()))
         return out
 
     def rank(self, rows):
         torch = _torch()
+        self._rows_arg(rows)
         out = torch.empty(rows.shape[0], dtype=torch.int64, device="cuda")
         _lib.check(_lib.load().ct_rank(self._h, _ptr(rows), rows.shape[0], _ptr(out), _stream()))
         return out
@@ -135,11 +158,18 @@ class Space:
                out_rows=None, out_pos=None):
         """ct_repair: returns (rows uint8 [n, row_bytes], positions int32 [n] (0xFFFFFFFF = none))."""
         torch = _torch()
+        self._rows_arg(rows)
         n = rows.shape[0]
+        if who is not None:
+            _device_arg(who, "who", (torch.int32,), (n,))
+        if pos_q16 is not None:
+            _device_arg(pos_q16, "pos_q16", (torch.int32,), (n, self.D))
         if out_rows is None:
             out_rows = torch.empty_like(rows)
         if out_pos is None:
             out_pos = torch.empty(n, dtype=torch.int32, device="cuda")
+        self._rows_arg(out_rows, "out_rows")
+        _device_arg(out_pos, "out_pos", (torch.int32,), (n,))
         _lib.check(_lib.load().ct_repair(self._h, _ptr(rows), n, metric, seed, generation, _ptr(who),
                                          _ptr(pos_q16), _ptr(out_rows), _ptr(out_pos), _stream()))
         return out_rows, out_pos
@@ -169,6 +199,8 @@ class Pop:
     """One optimiser run (ct_pop) over a Space; the objective tensor must outlive it."""
 
     def __init__(self, space: Space, algo: int, pop_size: int, seed: int, objective, **kw):
+        torch = _torch()
+        _device_arg(objective, "objective", (torch.float32,), (space.n_valid,))
         self.space = space
         self.objective = objective
         self.algo, self.pop_size = algo, pop_size

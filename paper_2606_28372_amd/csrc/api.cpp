@@ -474,6 +474,8 @@ int ct_repair(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t met
         return ct_fail(CT_EINVAL, "ct_repair: TIER_EUCLID needs particle positions");
     if (n > 0x7FFFFFFFull) return ct_fail(CT_EINVAL, "ct_repair: at most 2^31-1 rows per call");
     if (s->n_valid == 0) return ct_fail(CT_EEMPTY, "ct_repair: the space has no valid configuration");
+    if (s->n_valid > CT_MAX_VALID)
+        return ct_fail(CT_EINVAL, "ct_repair: more valid configurations than 32-bit positions can name");
     if (n == 0) return CT_OK;
     hipStream_t st = as_stream(stream);
     // one candidate set: scratch lists, per-part winners, the set itself and its plan
@@ -537,6 +539,8 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_ob
     const ct_pop_params& q = *prm;
     if (q.algo > CT_GA) return ct_fail(CT_EINVAL, "ct_pop_create: unknown algorithm");
     if (s->n_valid == 0) return ct_fail(CT_EEMPTY, "ct_pop_create: the space has no valid configuration");
+    if (s->n_valid > CT_MAX_VALID)
+        return ct_fail(CT_EINVAL, "ct_pop_create: more valid configurations than 32-bit positions can name");
     if (q.pop_size < 1 || q.pop_size > CT_MAX_POP) return ct_fail(CT_EINVAL, "ct_pop_create: pop_size out of range");
     if (q.pop_size > s->n_valid)
         return ct_fail(CT_EINVAL, "ct_pop_create: pop_size exceeds the number of valid configurations");
@@ -566,8 +570,7 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_ob
     d.w_q16 = q.w_q16;
     d.c1_q16 = q.c1_q16;
     d.c2_q16 = q.c2_q16;
-    d.mut_thresh = q.algo == CT_GA ? (uint32_t)((1ull << 32) / q.mutation_chance) : 0;
-    if (q.algo == CT_GA && q.mutation_chance == 1) d.mut_thresh = 0xFFFFFFFFu;
+    d.mut_thresh = q.algo == CT_GA ? (1ull << 32) / q.mutation_chance : 0;   // chance 1: 2^32, every child
     d.M = s->dev.max_radix;
     d.obj = d_objective;
     const uint32_t P = d.P;
@@ -826,31 +829,62 @@ int ct_pop_restore(ct_pop* p, const void* h_buf, size_t len) {
     o += 32;
     if (h[0] != 0x43545031u || h[1] != d.algo || h[2] != d.P || h[3] != d.D)
         return ct_fail(CT_EINVAL, "ct_pop_restore: snapshot is for a different run shape");
+    // every field is checked before anything reaches the device, so a rejected snapshot leaves
+    // the run as it was
+    const uint64_t nv = p->space->n_valid;
+    const size_t P = d.P, PD = (size_t)d.P * d.D;
+    if (h[6] >= nv) return ct_fail(CT_EINVAL, "ct_pop_restore: best position out of range");
+    std::vector<uint32_t> words;
+    if (d.algo == CT_PSO) {
+        const int64_t xmax = (int64_t)d.M * 65536;
+        std::vector<int32_t> X(PD), PB(PD);
+        std::vector<int64_t> V(PD);
+        std::vector<uint32_t> pb_pos(P);
+        uint32_t gi;
+        memcpy(X.data(), o, PD * 4);
+        memcpy(V.data(), o + PD * 4, PD * 8);
+        memcpy(PB.data(), o + PD * 12, PD * 4);
+        memcpy(pb_pos.data(), o + PD * 16 + P * 4, P * 4);
+        memcpy(&gi, o + PD * 16 + P * 8, 4);
+        for (size_t k = 0; k < PD; ++k) {
+            if (X[k] < 0 || X[k] >= xmax || PB[k] < 0 || PB[k] >= xmax)
+                return ct_fail(CT_EINVAL, "ct_pop_restore: particle coordinate outside [0, M * 2^16)");
+            // the inertia product w * V (w < 2^16) must stay inside int64
+            if (V[k] <= -(1ll << 46) || V[k] >= (1ll << 46))
+                return ct_fail(CT_EINVAL, "ct_pop_restore: velocity magnitude not below 2^46");
+        }
+        for (uint32_t v : pb_pos)
+            if (v >= nv) return ct_fail(CT_EINVAL, "ct_pop_restore: personal-best position out of range");
+        if (gi >= d.P) return ct_fail(CT_EINVAL, "ct_pop_restore: global-best index out of range");
+    } else {
+        std::vector<uint32_t> pos(P);
+        memcpy(pos.data(), o, P * 4);
+        for (uint32_t v : pos)
+            if (v >= nv) return ct_fail(CT_EINVAL, "ct_pop_restore: position out of range");
+        if (d.algo == CT_DE) {
+            // the membership bitmap is derived from the positions, which must be distinct
+            words.assign((nv + 31) / 32, 0);
+            for (uint32_t v : pos) {
+                if (words[v >> 5] & (1u << (v & 31u)))
+                    return ct_fail(CT_EINVAL, "ct_pop_restore: DE population holds a configuration twice");
+                words[v >> 5] |= 1u << (v & 31u);
+            }
+        }
+    }
     CT_HIP(hipDeviceSynchronize());
     uint32_t stt[4] = {h[4], h[5], 0, 0};
     uint64_t b = ((uint64_t)h[7] << 32) | h[6];
     if (d.algo == CT_PSO) {
-        size_t PD = (size_t)d.P * d.D;
         CT_HIP(hipMemcpy(d.X, o, PD * 4, hipMemcpyHostToDevice)); o += PD * 4;
         CT_HIP(hipMemcpy(d.V, o, PD * 8, hipMemcpyHostToDevice)); o += PD * 8;
         CT_HIP(hipMemcpy(d.PB, o, PD * 4, hipMemcpyHostToDevice)); o += PD * 4;
-        CT_HIP(hipMemcpy(d.f_pb, o, d.P * 4, hipMemcpyHostToDevice)); o += d.P * 4;
-        CT_HIP(hipMemcpy(d.pb_pos, o, d.P * 4, hipMemcpyHostToDevice)); o += d.P * 4;
+        CT_HIP(hipMemcpy(d.f_pb, o, P * 4, hipMemcpyHostToDevice)); o += P * 4;
+        CT_HIP(hipMemcpy(d.pb_pos, o, P * 4, hipMemcpyHostToDevice)); o += P * 4;
         memcpy(&stt[2], o, 4);
     } else {
-        std::vector<uint32_t> pos(d.P);
-        memcpy(pos.data(), o, d.P * 4);
-        CT_HIP(hipMemcpy(d.pos, o, d.P * 4, hipMemcpyHostToDevice)); o += d.P * 4;
-        CT_HIP(hipMemcpy(d.f, o, d.P * 4, hipMemcpyHostToDevice));
-        if (d.algo == CT_DE) {
-            // membership bitmap is derived from the positions
-            std::vector<uint32_t> words((p->space->n_valid + 31) / 32, 0);
-            for (uint32_t v : pos) {
-                if (v >= p->space->n_valid) return ct_fail(CT_EINVAL, "ct_pop_restore: position out of range");
-                words[v >> 5] |= 1u << (v & 31u);
-            }
-            CT_HIP(hipMemcpy(d.member, words.data(), words.size() * 4, hipMemcpyHostToDevice));
-        }
+        CT_HIP(hipMemcpy(d.pos, o, P * 4, hipMemcpyHostToDevice)); o += P * 4;
+        CT_HIP(hipMemcpy(d.f, o, P * 4, hipMemcpyHostToDevice));
+        if (d.algo == CT_DE) CT_HIP(hipMemcpy(d.member, words.data(), words.size() * 4, hipMemcpyHostToDevice));
     }
     CT_HIP(hipMemcpy(d.state, stt, 16, hipMemcpyHostToDevice));
     CT_HIP(hipMemcpy(d.best, &b, 8, hipMemcpyHostToDevice));

@@ -181,7 +181,7 @@ struct PopDev {
     uint32_t F_q16, de_best;
     uint64_t CR_q32;
     int64_t w_q16, c1_q16, c2_q16;
-    uint32_t mut_thresh;              // floor(2^32 / mutation_chance)
+    uint64_t mut_thresh;              // floor(2^32 / mutation_chance): a child mutates when its draw is below
     uint32_t M;                       // largest radix (PSO domain [0, M) per dimension)
     uint64_t n_valid;
     const float* obj;                 // [n_valid]

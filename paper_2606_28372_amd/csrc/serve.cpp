@@ -146,7 +146,8 @@ struct ct_server {
             if (r->prm.pop_size > r->n_valid) r->prm.pop_size = (uint32_t)r->n_valid;
             r->footprint = run_bytes(r, r->n_valid);
             r->sized = true;
-            const bool unusable = r->n_valid == 0 || (r->prm.algo == CT_DE && r->prm.pop_size < 4);
+            const bool unusable = r->n_valid == 0 || r->n_valid > CT_MAX_VALID ||
+                                  (r->prm.algo == CT_DE && r->prm.pop_size < 4);
             if (unusable || r->footprint + scratch > cfg.hbm_budget) {
                 release_space_device(r->space);
                 queue.pop_front();

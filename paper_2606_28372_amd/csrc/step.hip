@@ -336,7 +336,7 @@ __global__ __launch_bounds__(kBlock) void k_propose(const PopDev* __restrict__ p
         if (slot == 0) {
             if (p.algo == CT_GA) {
                 const U4 m = ct_philox(p.seed, i, g, (uint32_t)PUR_GA_MUT << 24, 0);
-                p.apply[i] = m.x < p.mut_thresh;
+                p.apply[i] = (uint64_t)m.x < p.mut_thresh;
             }
             J.out_pos[i] = valid ? (uint32_t)rank : 0xFFFFFFFFu;
             if (!valid) {

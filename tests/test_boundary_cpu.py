@@ -92,3 +92,78 @@ def test_batch_tuning_null_handles():
     assert lib.ct_batch_set_tuning(None, 4096, 16, 8192, 0) == _lib.CT_EINVAL
     assert lib.ct_batch_tuning(None, None, None, None, None, None) == _lib.CT_EINVAL
     assert lib.ct_batch_autotune(None, 1, 1, 0, None) == _lib.CT_EINVAL
+
+
+# ---------------------------------------------------------------------------
+# ct_space_build rejects malformed constraint programs on the host, before it
+# touches a device (CT_EINVAL); a well-formed program then needs the device.
+# ---------------------------------------------------------------------------
+def _w(op, imm=0):
+    return ((imm & 0xFFFFFF) << 8) | op
+
+
+OP = bytecode.OPS
+
+
+def _build(progs, radices=(4, 3, 5), offsets=None):
+    lib = _lib.load()
+    values = np.ascontiguousarray([v for r in radices for v in range(1, r + 1)], dtype=np.int64)
+    rad = np.ascontiguousarray(radices, dtype=np.uint32)
+    flat, offs = [], [0]
+    for p in progs:
+        flat += p
+        offs.append(len(flat))
+    code = np.ascontiguousarray(flat or [0], dtype=np.uint32)
+    offs = np.ascontiguousarray(offs if offsets is None else offsets, dtype=np.uint32)
+    h = ctypes.c_void_p()
+    rc = lib.ct_space_build(values.ctypes.data, rad.ctypes.data, len(radices), code.ctypes.data, offs.ctypes.data,
+                            len(progs), None, ctypes.byref(h))
+    if rc == 0:
+        lib.ct_space_free(h)
+    return rc, lib.ct_last_error().decode()
+
+
+@pytest.mark.parametrize("name,prog,why", [
+    ("binary underflow", [_w(OP["CONST"], 1), _w(OP["ADD"])], "underflow"),
+    ("unary underflow", [_w(OP["NEG"])], "underflow"),
+    ("depth 17", [_w(OP["CONST"], 1)] * 17 + [_w(OP["ADD"])] * 16, "deeper than 16"),
+    ("opcode 0", [_w(OP["CONST"], 1), _w(OP["CONST"], 1), _w(0)], "unknown opcode"),
+    ("opcode 22", [_w(OP["CONST"], 1), _w(OP["CONST"], 1), _w(22)], "unknown opcode"),
+    ("opcode 255", [_w(OP["CONST"], 1), _w(255)], "unknown opcode"),
+    ("parameter id = n", [_w(OP["PARAM"], 3)], "parameter id"),
+    ("negative parameter id", [_w(OP["PARAM"], -1)], "parameter id"),
+    ("truncated CONST64", [_w(OP["CONST64"]), 7], "truncated"),
+    ("two values left", [_w(OP["CONST"], 1), _w(OP["CONST"], 2)], "exactly one value"),
+    ("empty program", [], "exactly one value"),
+])
+def test_space_build_rejects_malformed_bytecode(name, prog, why):
+    rc, msg = _build([[_w(OP["PARAM"], 0), _w(OP["CONST"], 2), _w(OP["GT"])], prog])
+    assert rc == _lib.CT_EINVAL, name
+    assert "program 1" in msg and why in msg, msg
+
+
+@pytest.mark.parametrize("radices,why", [
+    ((), "parameters"), (tuple([2] * 33), "parameters"), ((4, 0, 5), "radix"), ((4, 256, 5), "radix"),
+    ((255,) * 6 + (6,), "2^46"),
+])
+def test_space_build_rejects_bad_sizes(radices, why):
+    rc, msg = _build([], radices=radices)
+    assert rc == _lib.CT_EINVAL and why in msg, msg
+
+
+def test_space_build_rejects_descending_offsets():
+    good = [_w(OP["CONST"], 1)]
+    rc, msg = _build([good, good], offsets=[0, 1, 0])
+    assert rc == _lib.CT_EINVAL and "ascending" in msg, msg
+
+
+def test_space_build_accepts_depth_16_then_needs_a_device():
+    """Sixteen values on the stack is the documented limit: the program passes validation, so
+    without a GPU the build stops at the device check instead."""
+    import torch
+    prog = [_w(OP["CONST"], 1)] * 16 + [_w(OP["ADD"])] * 15
+    rc, msg = _build([prog, [_w(OP["PARAM"], 2), _w(OP["CONST64"]), 5, 0, _w(OP["LT"])]])
+    if torch.cuda.is_available():
+        assert rc == 0, msg
+    else:
+        assert rc == _lib.CT_EDEVICE, msg
