@@ -29,6 +29,16 @@ Where the paper is silent the readings are:
   GA  - rank selection from Beta(1, b) over normalised rank; cut point uniform
         in 1..D-1; two children per pair (the last one dropped for odd P);
         repair, then mutation with probability 1/mutation_chance.
+  Firefly (Section IV-C, last paragraph: a PSO variant with PSO's sampling and
+        Alg. 2 evaluation; Table IV: B0, gamma, alpha) - the standard firefly
+        move (Yang, 2008): firefly i moves towards every firefly j that was
+        brighter (lower objective) at the start of the generation, in
+        ascending j, by beta = B0 exp(-gamma r^2) of the way plus a random
+        step alpha (u - 1/2) per dimension; r is measured in PSO's [0,1]^N
+        coordinates; positions in PSO's index units, clamped like PSO's;
+        brightness is the objective of the Alg. 2 evaluation; the brightest
+        firefly does not move.  Fixed point: exp by binary decomposition of
+        the exponent (below).
 """
 from __future__ import annotations
 
@@ -40,6 +50,7 @@ import numpy as np
 from . import core
 
 P_INIT, P_DE_PICK, P_DE_CR, P_PSO_R, P_GA_SEL, P_GA_MUT = 1, 2, 3, 4, 5, 6
+P_FF_NOISE = 9
 
 
 def uniform_below(u: int, n: int) -> int:
@@ -56,8 +67,8 @@ def pick_excluding(u: int, n: int, excluded: List[int]) -> int:
     return k
 
 
-def draw(seed: int, c0: int, c1: int, purpose: int, sub: int = 0) -> List[int]:
-    return core.philox(seed, [c0 & 0xFFFFFFFF, c1 & 0xFFFFFFFF, (purpose << 24) | sub, 0])
+def draw(seed: int, c0: int, c1: int, purpose: int, sub: int = 0, extra: int = 0) -> List[int]:
+    return core.philox(seed, [c0 & 0xFFFFFFFF, c1 & 0xFFFFFFFF, (purpose << 24) | sub, extra & 0xFFFFFFFF])
 
 
 def init_positions(space: core.Space, P: int, seed: int, tag: int) -> np.ndarray:
@@ -327,3 +338,115 @@ def ga_children(space: core.Space, obj: np.ndarray, st: GAState, seed: int, muta
     if mut:
         kids[mut] = space.repair(kids[mut], core.HAM1_RANDOM, who=idx[mut], key=seed, gen=g)
     return kids
+
+
+# ---------------------------------------------------------------------------
+# Firefly Algorithm (Section IV-C, last paragraph; Table IV hyperparameters)
+# ---------------------------------------------------------------------------
+
+FF_EXP_BITS = 21            # exponents x (Q16.16) below 2^21, i.e. below 32; e^-32 < 2^-32 rounds to 0
+
+
+def ff_exp_table() -> List[int]:
+    """T[b] = e^(-2^(b-16)) in Q0.32, rounded half up, b = 0..20, from 60-digit decimal arithmetic."""
+    import decimal
+    ctx = decimal.Context(prec=60)
+    out = []
+    for b in range(FF_EXP_BITS):
+        v = ctx.exp(ctx.minus(decimal.Decimal(2) ** (b - 16))) * (decimal.Decimal(2) ** 32)
+        out.append(int((v + decimal.Decimal("0.5")).to_integral_value(rounding=decimal.ROUND_FLOOR)))
+    return out
+
+
+_FF_T = None
+
+
+def ff_exp_q32(x_q16: int) -> int:
+    """e^(-x) for x = x_q16 / 2^16 >= 0, in Q0.32 (2^32 is 1.0).
+
+    e^-(sum of the set bits of x) is the product of e^-(2^(b-16)) over the set
+    bits b; the product runs over ascending b, each step rounded half up to
+    Q0.32.  Every step adds at most half a unit, the table another half per
+    factor, so the result is within 21 units of 2^-32 of the exact value.
+    """
+    global _FF_T
+    if _FF_T is None:
+        _FF_T = ff_exp_table()
+    x = int(x_q16)
+    if x < 0:
+        raise ValueError("exponent must be non-negative")
+    if x >> FF_EXP_BITS:
+        return 0
+    a = 1 << 32
+    for b in range(FF_EXP_BITS):
+        if (x >> b) & 1:
+            a = (a * _FF_T[b] + (1 << 31)) >> 32
+    return a
+
+
+@dataclasses.dataclass
+class FFState:
+    X: np.ndarray              # P x D positions, Q16.16 index units (PSO's mapping)
+    f: np.ndarray              # brightness: objective of each firefly's last evaluation (lower = brighter)
+    pos: np.ndarray            # valid-list position that evaluation used
+    best_f: float
+    best_pos: int
+    gen: int = 0
+
+
+def ff_init(space, obj, P, seed) -> FFState:
+    pos = init_positions(space, P, seed, 0)
+    X = centre_q16(space.vrows[pos])
+    f = obj[pos].astype(np.float32)
+    b = min(zip(f.tolist(), pos.tolist()))
+    return FFState(X, f, pos.copy(), np.float32(b[0]), int(b[1]))
+
+
+def ff_move(space: core.Space, st: FFState, seed: int, B0_q16: int, gamma_q16: int, alpha_q16: int) -> np.ndarray:
+    """Every firefly's new position (before Alg. 2's evaluation).
+
+    For firefly i and each j (ascending) with f_j < f_i at the start of the
+    generation: r^2 = sum_d ((X_j,d - x_d) / (M 2^16))^2 in [0,1]^N units
+    (x is i's position so far), beta = B0 e^(-gamma r^2), and per dimension
+    x_d += beta (X_j,d - x_d) + alpha (u - 1/2) M, with u uniform in [0, 1)
+    (a Philox draw at (i, generation, FF_NOISE | d/4, j), word d%4, top 16
+    bits), then x_d is clamped to [0, M 2^16 - 1] as in PSO.  Fixed point:
+    r^2 in Q16.16 is floor(floor(S / 2^16) / M^2) with S the integer sum of
+    squares, gamma r^2 is floor(gamma_q16 r2_q16 / 2^16), beta_q16 is
+    B0_q16 e_q32 / 2^32 rounded half up, the attraction floor(beta_q16 dX / 2^16)
+    and the random step floor(alpha_q16 M (u_16 - 2^15) / 2^16).
+    """
+    P, D, g = st.X.shape[0], space.D, st.gen
+    M = int(space.radices.max())
+    hi, mm = M * 65536 - 1, M * M
+    Xn = st.X.copy()
+    for i in range(P):
+        x = [int(v) for v in st.X[i]]
+        for j in range(P):
+            if not (st.f[j] < st.f[i]):
+                continue
+            xj = [int(v) for v in st.X[j]]
+            S = sum((xj[d] - x[d]) ** 2 for d in range(D))
+            r2 = (S >> 16) // mm
+            beta = (B0_q16 * ff_exp_q32((gamma_q16 * r2) >> 16) + (1 << 31)) >> 32
+            for d in range(D):
+                u = draw(seed, i, g, P_FF_NOISE, d >> 2, j)[d & 3]
+                noise = (alpha_q16 * M * ((u >> 16) - 32768)) >> 16
+                x[d] = min(max(x[d] + ((beta * (xj[d] - x[d])) >> 16) + noise, 0), hi)
+        Xn[i] = x
+    return Xn
+
+
+def ff_step(space: core.Space, obj: np.ndarray, st: FFState, seed: int, B0_q16: int, gamma_q16: int,
+            alpha_q16: int) -> FFState:
+    P, g = st.X.shape[0], st.gen
+    Xn = ff_move(space, st, seed, B0_q16, gamma_q16, alpha_q16)
+    snapped = np.minimum(Xn >> 16, space.radices.astype(np.int64) - 1).astype(np.int32)
+    # evaluation through Alg. 2 (as PSO): the nearest member of the first non-empty neighbour set
+    ev = space.repair(snapped, core.TIER_EUCLID, pos_q16=Xn)
+    epos = space.pos(space.encode(ev))
+    f = obj[epos].astype(np.float32)
+    best = (float(st.best_f), st.best_pos)
+    for i in range(P):
+        best = _lexmin(best, (float(f[i]), int(epos[i])))
+    return FFState(Xn, f, epos.astype(np.int64), np.float32(best[0]), int(best[1]), g + 1)

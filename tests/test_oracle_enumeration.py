@@ -166,3 +166,22 @@ def test_sparse16_sampled_words_match_python():
             assert bool((word >> b) & 1) == expect
             checked_set += expect
     assert checked_set >= len(dense_words)
+
+
+def test_many_problem_counts_match_dynamic_programming():
+    """The oracle's enumeration of many-problem spaces equals an exact DP count that never enumerates
+    (linear bound by convolution of per-parameter sum distributions, the modulo pair by direct sum)."""
+    from tests.helpers import dpcount
+    done = 0
+    for pr in W.batched(64, seed=3):
+        if pr.spec.n_cartesian > 4_000_000:
+            continue
+        osp = core.Space.from_spec(pr.spec).enumerate()
+        assert osp.n_valid == dpcount.count(pr.spec), pr.spec.name
+        done += 1
+    assert done >= 5
+    # a hand-checkable case: p0, p1 in 1..3, p2 in 1..2, p0 + p1 + p2 <= 5, (p0*p1)%3 != 0
+    spec = W.SpaceSpec("hand", {"p0": [1, 2, 3], "p1": [1, 2, 3], "p2": [1, 2]},
+                       ["1*p0+1*p1+1*p2 <= 5", "(p0*p1)%3 != 0"])
+    # admissible (p0, p1): (1,1) (1,2) (2,1) (2,2); p2 choices with sum <= 5: 2, 2, 2, 1
+    assert dpcount.count(spec) == 7 == core.Space.from_spec(spec).enumerate().n_valid
