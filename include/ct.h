@@ -192,6 +192,26 @@ int ct_repair(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t met
               uint8_t* d_out_rows, uint32_t* d_out_pos, void* stream);
 
 /*
+ * ct_repair_noalloc -- ct_repair for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid the
+ * allocator).  Same arguments, kernels and results as ct_repair; it calls no
+ * device or host allocator.  Its scratch (candidate lists, per-part winners,
+ * the set descriptor and the scan plan) is one static device array of
+ * CT_NOALLOC_SCRATCH_BYTES per GPU, held from the first call on that GPU until
+ * the process ends, so n <= CT_NOALLOC_MAX_ROWS (else CT_EINVAL, nothing
+ * launched).  The call is stream-ordered and does not synchronise.  Every call
+ * on one GPU shares that array (each call clears what it needs first): calls
+ * that overlap on one GPU -- on different streams or threads without ordering
+ * between them -- race and give undefined results.  The space must live on
+ * the current device.
+ */
+#define CT_NOALLOC_MAX_ROWS 16384u
+#define CT_NOALLOC_SCRATCH_BYTES (640u * 1024u)
+int ct_repair_noalloc(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t metric,
+                      uint64_t seed, uint32_t generation, const uint32_t* d_who, const int32_t* d_pos_q16,
+                      uint8_t* d_out_rows, uint32_t* d_out_pos, void* stream);
+
+/*
  * Optimiser hyperparameters in integer form (Table IV defaults in brackets).
  *   DE:  F_q16 = round(F * 2^16) [45875], CR_q32 = round(CR * 2^32) [2576980378],
  *        de_best 1 = best1bin, 0 = rand1bin [1]; requires 4 <= pop_size.

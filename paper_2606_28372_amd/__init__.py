@@ -174,6 +174,23 @@ class Space:
                                          _ptr(pos_q16), _ptr(out_rows), _ptr(out_pos), _stream()))
         return out_rows, out_pos
 
+    def repair_noalloc(self, rows, metric: int, seed: int = 0, generation: int = 0, who=None, pos_q16=None,
+                       out_rows=None, out_pos=None):
+        """ct_repair_noalloc: ct_repair on the library's static scratch (at most CT_NOALLOC_MAX_ROWS rows);
+        out_rows / out_pos must be given (this call allocates nothing)."""
+        torch = _torch()
+        self._rows_arg(rows)
+        n = rows.shape[0]
+        if who is not None:
+            _device_arg(who, "who", (torch.int32,), (n,))
+        if pos_q16 is not None:
+            _device_arg(pos_q16, "pos_q16", (torch.int32,), (n, self.D))
+        self._rows_arg(out_rows, "out_rows")
+        _device_arg(out_pos, "out_pos", (torch.int32,), (n,))
+        _lib.check(_lib.load().ct_repair_noalloc(self._h, _ptr(rows), n, metric, seed, generation, _ptr(who),
+                                                 _ptr(pos_q16), _ptr(out_rows), _ptr(out_pos), _stream()))
+        return out_rows, out_pos
+
     def close(self):
         if self._h:
             _lib.load().ct_space_free(self._h)
