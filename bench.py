@@ -15,6 +15,15 @@ printed:
   repairs_per_s, mutation_scans_per_s,
   roofline   for the kernel that takes most of the step (HIP events around its
              launches on its stream, over the timed steps),
+  scan       the main-pass and fallback repair scans apart: launches, mean
+             launch time, candidates, the (candidate, valid row) pairs of the
+             argmin's definition and the rows the pruned scans actually
+             evaluated (device counters, untimed warmup step),
+  build      the space build against the HBM roofline (bitmask + valid list
+             bytes over the summed build kernel time), on the job's space and
+             on the 4.35G-configuration sparse space,
+  valid_mask ct_valid_mask on 2^26 rows of the sparse space (16-byte rows,
+             half of them valid): configurations checked/s and HBM fraction,
   batched    generations/s of 256 independent problems (uneven spaces,
              dimensions, populations and algorithms) stepped one run at a time
              (plain), with one launch per phase for all runs (batched), and by
@@ -66,10 +75,89 @@ WORKLOADS = {
 CONFIG_KEY = {"gemm": "gemm", "gemm10": "gemm10", "tiny": "tiny", "sparse16": "sparse16"}
 
 
+BUILD_KERNELS = ["k_table", "k_mask", "k_tile_sums", "k_scan_tiles", "k_compact", "k_boxes", "k_chunks",
+                 "k_presence", "k_prevnext"]
+
+
 def kernel_names():
-    return ["k_table", "k_mask", "k_tile_sums", "k_scan_tiles", "k_compact", "k_boxes", "k_presence",
-            "k_prevnext", "k_init", "k_init_finish", "k_ga_sort", "k_propose", "k_repair_zero", "k_repair_prep",
-            "k_repair_plan", "k_repair_scan", "k_repair_finish", "k_mutate", "k_select"]
+    return BUILD_KERNELS + ["k_init", "k_init_finish", "k_ga_sort", "k_ff_move", "k_propose", "k_repair_zero",
+                            "k_repair_prep", "k_repair_plan", "k_repair_scan", "k_repair_scan_fb", "k_repair_finish",
+                            "k_mutate", "k_select"]
+
+
+def host_cpu():
+    """Host CPU as the oracle baseline sees it: logical CPUs, model name and clock."""
+    model, mhz = None, []
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name") and model is None:
+                    model = ln.split(":", 1)[1].strip()
+                elif ln.startswith("cpu MHz"):
+                    mhz.append(float(ln.split(":", 1)[1]))
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model,
+            "mhz_mean": round(sum(mhz) / len(mhz), 1) if mhz else None}
+
+
+def build_leg(ct, spec, reps=5):
+    """Space builds timed kernel by kernel; algorithmic bytes = the bitmask (N/8) plus the valid
+    list (8-byte linear index + R-byte row per valid configuration)."""
+    import torch
+    ct.prof_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sp = ct.Space.from_spec(spec)
+        n_cart, n_valid, R = sp.n_cartesian, sp.n_valid, sp.row_bytes
+        sp.close()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    per = {k: ct.prof_read(k)[0] / reps for k in BUILD_KERNELS}
+    ct.prof_enable(False)
+    kern_ms = sum(per.values())
+    nbytes = n_cart / 8 + n_valid * (8 + R)
+    ach = nbytes / (kern_ms * 1e-3) / 1e9
+    return {"space": spec.name, "configurations": n_cart, "valid": n_valid, "row_bytes": R,
+            "algorithmic_bytes": nbytes, "kernel_ms": kern_ms, "wall_ms_per_build": wall * 1e3,
+            "kernels_ms": {k: v for k, v in per.items() if v}, "configs_per_s": n_cart / (kern_ms * 1e-3),
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS}}
+
+
+def valid_mask_leg(ct, n_rows=1 << 26, reps=5, seed=5):
+    """ct_valid_mask on n_rows rows of the sparse space: half drawn from its valid list, half
+    uniform over the Cartesian space; algorithmic bytes = R read + 1 written per row."""
+    import torch
+    sp = ct.Space.from_spec(W.sparse16())
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    rows = torch.zeros((n_rows, sp.row_bytes), dtype=torch.uint8, device="cuda")
+    for j, r in enumerate(W.sparse16().radices):
+        rows[:, j] = torch.randint(0, r, (n_rows,), generator=g, device="cuda", dtype=torch.int32).to(torch.uint8)
+    _, vrows = sp.valid_list()
+    half = n_rows // 2
+    rows[:half] = vrows[torch.randint(0, sp.n_valid, (half,), generator=g, device="cuda")]
+    del vrows
+    out = sp.valid_mask(rows)                       # untimed first launch
+    torch.cuda.synchronize()
+    ct.prof_enable(True)
+    for _ in range(reps):
+        out = sp.valid_mask(rows)
+    ms, n = ct.prof_read("k_valid_rows")
+    ct.prof_enable(False)
+    avg = ms / max(n, 1)
+    share = float(out.float().mean().item())
+    nbytes = n_rows * (sp.row_bytes + 1)
+    ach = nbytes / (avg * 1e-3) / 1e9
+    res = {"space": "sparse16", "rows": n_rows, "row_bytes": sp.row_bytes, "valid_share": share,
+           "avg_launch_ms": avg, "configs_checked_per_s": n_rows / (avg * 1e-3),
+           "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": ach / HBM_PEAK_GBS, "kernel": "k_valid_rows"}}
+    del rows, out
+    sp.close()
+    torch.cuda.empty_cache()
+    return res
 
 
 def measured_traffic(kernel, workload):
@@ -118,6 +206,24 @@ def run_job(ct, spec, runs, objective_t, gens, tuning=None):
 
 
 def cpu_baseline(spec, runs, obj, gens, budget_s=12.0):
+    """The oracle with all of its threads, then the space build with one thread (the C core's
+    OpenMP loops; the generation steps are single-threaded Python either way)."""
+    from oracle import core as ocore
+    allt = cpu_baseline_run(spec, runs, obj, gens, budget_s)
+    t0 = time.perf_counter()
+    ocore.set_num_threads(1)
+    try:
+        osp = ocore.Space.from_spec(spec).enumerate()
+        t1 = time.perf_counter() - t0
+    finally:
+        ocore.set_num_threads(allt["cores"])
+    allt["single_thread_build_configs_per_s"] = osp.n_cartesian / t1
+    allt["all_threads_build_configs_per_s"] = osp.n_cartesian / allt["build_s"]
+    allt["host"] = host_cpu()
+    return allt
+
+
+def cpu_baseline_run(spec, runs, obj, gens, budget_s):
     """The oracle on the host cores: the full space build, then generations of every run (all runs
     advance together) until about budget_s seconds of generation time or the job's count, and the
     mean generation time extrapolated to the job's generation count (same unit as value)."""
@@ -139,7 +245,7 @@ def cpu_baseline(spec, runs, obj, gens, budget_s=12.0):
         t1 = time.perf_counter()
         for k, opt in enumerate(runs):
             if opt.algo == W.ALGO_DE:
-                states[k] = ost.de_step(osp, obj, states[k], opt.seed, opt.F_q16, opt.CR_q32, bool(opt.de_best))
+                states[k] = ost.de_step(osp, obj, states[k], opt.seed, opt.F_q16, opt.CR_q32, bool(opt.de_method))
             elif opt.algo == W.ALGO_PSO:
                 states[k] = ost.pso_step(osp, obj, states[k], opt.seed, opt.w_q16, opt.c1_q16, opt.c2_q16)
             else:
@@ -149,6 +255,7 @@ def cpu_baseline(spec, runs, obj, gens, budget_s=12.0):
     checked = osp.n_cartesian + gens * sum(o.pop_size for o in runs)
     t_job = t_build + gens * t_gens / done
     return {"value": checked / t_job, "unit": "configs/s", "cores": ocore.num_threads(), "kind": "oracle",
+            "build_s": t_build, "generation_s": t_gens / done,
             "sample": (f"oracle: full space build ({osp.n_cartesian} configurations, {t_build:.2f} s) plus the "
                        f"first {done} generations of the {len(runs)} runs ({t_gens:.2f} s), mean generation "
                        f"time extrapolated to {gens} generations per run")}
@@ -278,6 +385,8 @@ def main():
     ap.add_argument("--serving-generations", type=int, default=200)
     ap.add_argument("--serving-interarrival-ms", type=float, default=5.0)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-build-legs", action="store_true")
+    ap.add_argument("--valid-mask-log2", type=int, default=26)
     ap.add_argument("--tuning", default=None,
                     help="items,min_boxes,grid_waves,mode: install this scan partitioning in the job instead of "
                          "autotuning it (profiling runs repeat the timed configuration this way)")
@@ -322,11 +431,17 @@ def main():
 
     # warmup: events around every kernel give the per-kernel breakdown and the dominant kernel
     per_kernel = {}
+    boxes = [0, 0, 0, 0]
+    warm_repairs = 0
     if args.warmup:
         ct.prof_enable(True)
+        ct.prof_count_boxes(True)
         for _ in range(args.warmup):
-            run_job(ct, spec, runs, obj_t, gens, tuning)
+            _, rc, _ = run_job(ct, spec, runs, obj_t, gens, tuning)
+            warm_repairs += sum(c["repairs"] for _, c in rc)
         per_kernel = {k: ct.prof_read(k) for k in kernel_names()}
+        boxes = ct.prof_boxes()
+        ct.prof_count_boxes(False)
         ct.prof_enable(False)
         per_kernel = {k: (v[0] / args.warmup, v[1] / args.warmup) for k, v in per_kernel.items() if v[1]}
     dom = max(per_kernel, key=lambda k: per_kernel[k][0]) if per_kernel else "k_repair_scan"
@@ -356,9 +471,10 @@ def main():
     avg_ms = dom_ms / max(dom_n, 1)
     D = len(spec.params)
     if dom == "k_repair_scan":
-        # each scanned (candidate, valid row) pair compares D digit pairs; the chip's densest
-        # byte instruction does 4 digit pairs per lane op
-        pairs = (repairs + mutations) * n_valid
+        # each (candidate, valid row) pair of the main pass's argmin compares D digit pairs; the
+        # chip's densest byte instruction does 4 digit pairs per lane op.  GA mutations are
+        # enumerated (k_mutate) and the fallback scans are "k_repair_scan_fb": neither counts here.
+        pairs = repairs * n_valid
         ops = pairs * D / max(dom_n / args.steps, 1)              # per launch
         achieved = ops / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": BYTE_PEAK_TOPS, "unit": "Tdigitop/s",
@@ -394,6 +510,26 @@ def main():
         "scan_tuning": results[-1][2],
         "roofline": roof,
     }
+    if per_kernel:
+        main_n = per_kernel.get("k_repair_scan", (0, 0))[1]
+        fb = per_kernel.get("k_repair_scan_fb", (0.0, 0))
+        wr = warm_repairs / args.warmup
+        line["scan"] = {
+            "main": {"launches_per_step": main_n, "avg_launch_ms": avg_ms if dom == "k_repair_scan" else None,
+                     "candidates_per_launch": wr / max(main_n, 1),
+                     "argmin_rows_per_launch": wr * n_valid / max(main_n, 1),
+                     "rows_evaluated_per_launch": boxes[0] * 64 / args.warmup / max(main_n, 1),
+                     "chunks_opened_per_launch": boxes[1] / args.warmup / max(main_n, 1)},
+            "fallback": {"launches_per_step": fb[1], "avg_launch_ms": fb[0] / max(fb[1], 1),
+                         "rows_evaluated_per_launch": boxes[2] * 64 / args.warmup / max(fb[1], 1),
+                         "chunks_opened_per_launch": boxes[3] / args.warmup / max(fb[1], 1)},
+            "note": "rows_evaluated counts the 64-row boxes whose bound did not rule them out (warmup step)"}
+    if not args.no_build_legs:
+        torch.cuda.empty_cache()
+        line["build"] = [build_leg(ct, spec)]
+        if space_name != "sparse16":
+            line["build"].append(build_leg(ct, W.sparse16()))
+        line["valid_mask"] = valid_mask_leg(ct, 1 << args.valid_mask_log2)
     if not args.no_batched:
         torch.cuda.empty_cache()
         bl = batched_leg(ct, args.batched_problems, args.batched_generations)

@@ -65,7 +65,7 @@ enum ct_metric {
     CT_HAM1_RANDOM = 4   /* uniformly random valid Hamming-1 neighbour (GA mutation, Section IV-D) */
 };
 
-enum ct_algo { CT_DE = 0, CT_PSO = 1, CT_GA = 2 };
+enum ct_algo { CT_DE = 0, CT_PSO = 1, CT_GA = 2, CT_FIREFLY = 3 };
 
 enum ct_step_flags {
     CT_STEP_PLAIN = 0,    /* each population advanced by its own launch sequence */
@@ -84,7 +84,7 @@ enum ct_step_flags {
 /* Message for the last error on this thread (never NULL). */
 const char* ct_last_error(void);
 
-/* Library ABI version (currently 1). */
+/* Library ABI version (currently 2: ct_pop_params carries the Firefly parameters). */
 int ct_version(void);
 
 /*
@@ -214,23 +214,28 @@ int ct_repair_noalloc(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint
 /*
  * Optimiser hyperparameters in integer form (Table IV defaults in brackets).
  *   DE:  F_q16 = round(F * 2^16) [45875], CR_q32 = round(CR * 2^32) [2576980378],
- *        de_best 1 = best1bin, 0 = rand1bin [1]; requires 4 <= pop_size.
+ *        de_method 1 = best1bin, 0 = rand1bin [1]; requires 4 <= pop_size.
  *   PSO: w_q16 < 65536, c1_q16, c2_q16 <= 2^20  [32768, 196608, 32768].
  *   GA:  mutation_chance X = "one in X" [5]; rank selection Beta(1, beta_b), 1 <= beta_b <= 5 [3].
+ *   Firefly (Section IV-C, last paragraph; Table IV): ff_B0_q16 = round(B0 * 2^16) [65536],
+ *        ff_gamma_q16 = round(gamma * 2^16) [65536], ff_alpha_q16 = round(alpha * 2^16) [13107],
+ *        each <= 2^20.  Positions use PSO's index-unit mapping and Alg. 2 evaluation.
  * Every algorithm requires pop_size <= n_valid (its initial sample is stratified
- * over the valid list, one stratum per member).
+ * over the valid list, one stratum per member).  Fields a run does not use are ignored;
+ * reserved words must be 0.
  */
 typedef struct {
     uint32_t algo;
     uint32_t pop_size;
     uint64_t seed;
     uint32_t F_q16;
-    uint32_t de_best;
+    uint32_t de_method;
     uint64_t CR_q32;
     uint32_t w_q16, c1_q16, c2_q16;
     uint32_t mutation_chance;
     uint32_t beta_b;
-    uint32_t reserved[3];
+    uint32_t ff_B0_q16, ff_gamma_q16, ff_alpha_q16;
+    uint32_t reserved[7];
 } ct_pop_params;
 
 /*
@@ -251,6 +256,14 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* p, const float* d_obje
  * snap, TIER_EUCLID evaluation (position unchanged), personal/global best.
  * GA (Section IV-D): sort, Beta rank selection, single-point crossover,
  * TIER_RANDOM repair, HAM1_RANDOM mutation with chance 1/mutation_chance.
+ * Firefly (Section IV-C, last paragraph): each firefly moves towards every
+ * firefly that was brighter (lower objective) at the start of the generation,
+ * in ascending index, by B0 exp(-gamma r^2) of the way (r in PSO's [0,1]^N
+ * coordinates; exp in Q0.32 as a product of rounded e^(-2^(b-16)) factors
+ * over the set bits b of gamma r^2 in Q16.16) plus alpha (u - 1/2) M per
+ * dimension (u from a Philox draw at (i, generation, 9<<24 | d/4, j)), is
+ * clamped to [0, M 2^16), then snapped and evaluated through TIER_EUCLID
+ * (position unchanged); brightness is the evaluated objective.
  * Results do not depend on `flags`.  Runs may belong to different spaces.
  */
 int ct_step(ct_pop* const* pops, uint32_t n_pops, uint32_t n_generations, uint32_t flags, void* stream);
@@ -312,7 +325,8 @@ int ct_batch_tuning(const ct_batch* b, uint32_t* items, uint32_t* min_boxes, uin
 /*
  * ct_pop_read -- copy a run's state to the host (synchronises its stream).
  * h_pos[pop_size]: population as valid-list positions (PSO: the personal-best
- * configurations); h_f[pop_size]: their objective values.  Any output may be
+ * configurations; Firefly: each firefly's last evaluated configuration);
+ * h_f[pop_size]: their objective values.  Any output may be
  * NULL.  *best_pos / *best_f: best configuration found so far.
  */
 int ct_pop_read(const ct_pop* p, uint32_t* h_pos, float* h_f, uint32_t* best_pos, float* best_f,
@@ -326,13 +340,14 @@ int ct_pop_counters(const ct_pop* p, uint64_t* repairs, uint64_t* mutations);
  * ct_pop_snapshot / ct_pop_restore -- full run state as bytes (synchronising).
  * Layout: uint32 header[8] = {magic 0x43545031, algo, pop_size, n_params,
  * generation, reinits, best_pos, best_f bits}, then for DE/GA uint32 pos[P],
- * float f[P]; for PSO int32 X[P][D], int64 V[P][D], int32 PB[P][D],
+ * float f[P]; for Firefly uint32 pos[P] (evaluated positions), float f[P]
+ * (brightness), int32 X[P][D]; for PSO int32 X[P][D], int64 V[P][D], int32 PB[P][D],
  * float f_pb[P], uint32 pb_pos[P], uint32 gbest_index.  Call with
  * h_buf = NULL to get the size.  A restored run continues bit-identically.
  * ct_pop_restore checks the whole snapshot on the host before it writes
  * anything to the device: the run's shape (algorithm, pop_size, n_params),
- * every position and best_pos below n_valid, DE positions distinct, PSO
- * coordinates X and PB in [0, M * 2^16) (M the largest radix), |V| < 2^46 and
+ * every position and best_pos below n_valid, DE positions distinct, PSO and
+ * Firefly coordinates X and PB in [0, M * 2^16) (M the largest radix), |V| < 2^46 and
  * gbest_index < pop_size; on CT_EINVAL the run is left as it was.
  */
 int ct_pop_snapshot(const ct_pop* p, void* h_buf, size_t* len);
@@ -441,6 +456,14 @@ int ct_prof_enable(int on);
 int ct_prof_read(const char* kernel, double* total_ms, uint64_t* launches);
 /* Record events only around launches of the named kernel (NULL: every kernel). */
 int ct_prof_select(const char* kernel);
+/* Repair scans of the main pass are "k_repair_scan", those of the Hamming fallback pass of
+   Alg. 2/3 candidates without a tier 0-2 neighbour "k_repair_scan_fb".
+   ct_prof_count_boxes(1) clears and starts device counters of the work the scans actually do:
+   while on, every scan item adds the 64-row boxes whose rows it evaluated and the 64-box chunks
+   it opened (outside graph capture and tuning sweeps); ct_prof_boxes (synchronising) returns
+   {main-pass boxes, main-pass chunks, fallback boxes, fallback chunks}. */
+int ct_prof_count_boxes(int on);
+int ct_prof_boxes(uint64_t* out4);
 
 #ifdef __cplusplus
 }

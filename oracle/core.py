@@ -68,6 +68,7 @@ def lib():
             L.or_argmin_many.argtypes = [vp, vp, i64, ctypes.c_int, vp, u32, u32, vp, u32, vp]
             L.or_overflow_flag.restype = ctypes.c_int
             L.or_num_threads.restype = ctypes.c_int
+            L.or_set_num_threads.argtypes = [ctypes.c_int]
             _lib = L
     return _lib
 
@@ -262,3 +263,8 @@ def words_to_lin(words: np.ndarray, w0: int, chunk: int = 1 << 20) -> np.ndarray
 
 def num_threads() -> int:
     return int(lib().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the C core's parallel loops (timing the single-threaded oracle)."""
+    lib().or_set_num_threads(int(n))

@@ -435,6 +435,15 @@ void or_argmin_many(const or_valid* V, const int32_t* cands, int64_t n, int metr
                            pos_q16 ? pos_q16 + i * V->n_params : NULL, k0, k1, who[i], gen);
 }
 
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n < 1 ? 1 : n);
+#else
+    (void)n;
+#endif
+}
+
 int or_num_threads(void) {
 #ifdef _OPENMP
     extern int omp_get_max_threads(void);

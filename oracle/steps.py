@@ -450,3 +450,22 @@ def ff_step(space: core.Space, obj: np.ndarray, st: FFState, seed: int, B0_q16: 
     for i in range(P):
         best = _lexmin(best, (float(f[i]), int(epos[i])))
     return FFState(Xn, f, epos.astype(np.int64), np.float32(best[0]), int(best[1]), g + 1)
+
+
+# ---------------------------------------------------------------------------
+# dispatch on an optimiser description (algo 0 DE, 1 PSO, 2 GA, 3 Firefly and its hyperparameters)
+# ---------------------------------------------------------------------------
+
+def init_run(space, obj, opt):
+    f = {0: de_init, 1: pso_init, 2: ga_init, 3: ff_init}[opt.algo]
+    return f(space, obj, opt.pop_size, opt.seed)
+
+
+def step_run(space, obj, st, opt):
+    if opt.algo == 0:
+        return de_step(space, obj, st, opt.seed, opt.F_q16, opt.CR_q32, bool(opt.de_method))
+    if opt.algo == 1:
+        return pso_step(space, obj, st, opt.seed, opt.w_q16, opt.c1_q16, opt.c2_q16)
+    if opt.algo == 2:
+        return ga_step(space, obj, st, opt.seed, opt.mutation_chance, opt.beta_b)
+    return ff_step(space, obj, st, opt.seed, opt.ff_B0_q16, opt.ff_gamma_q16, opt.ff_alpha_q16)

@@ -19,12 +19,12 @@ from typing import Dict, List, Optional, Sequence, Tuple
 import numpy as np
 
 from . import _lib
-from ._lib import (CT_DE, CT_GA, CT_HAM1_RANDOM, CT_HAMMING, CT_INDEX_L1, CT_PSO, CT_SCAN_FUSED,  # noqa: F401
+from ._lib import (CT_DE, CT_FIREFLY, CT_GA, CT_HAM1_RANDOM, CT_HAMMING, CT_INDEX_L1, CT_PSO, CT_SCAN_FUSED,  # noqa: F401
                    CT_SCAN_SERIAL, CT_SCAN_STREAMS, CT_STEP_BATCHED, CT_STEP_GRAPH, CT_STEP_PLAIN, CT_TIER_EUCLID,
                    CT_TIER_RANDOM, CtError, ct_pop_params)
 
 __all__ = ["Space", "Pop", "Batch", "Server", "compile_constraints", "step_many", "CtError", "CT_HAMMING", "CT_INDEX_L1",
-           "CT_TIER_EUCLID", "CT_TIER_RANDOM", "CT_HAM1_RANDOM", "CT_DE", "CT_PSO", "CT_GA",
+           "CT_TIER_EUCLID", "CT_TIER_RANDOM", "CT_HAM1_RANDOM", "CT_DE", "CT_PSO", "CT_GA", "CT_FIREFLY",
            "CT_STEP_PLAIN", "CT_STEP_BATCHED", "CT_STEP_GRAPH", "CT_SCAN_SERIAL", "CT_SCAN_STREAMS", "CT_SCAN_FUSED"]
 
 
@@ -127,6 +127,16 @@ class Space:
         _lib.check(_lib.load().ct_space_copy_bitmask(self._h, _ptr(w), _stream()))
         return w
 
+    def borrowed(self):
+        """ct_space_valid_list / ct_space_bitmask: the space's own device pointers (borrowed, valid until
+        close) as integers: (linear indices, digit rows, bitmask words, number of words)."""
+        lib = _lib.load()
+        lin, rows, words = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        nw = ctypes.c_uint64()
+        _lib.check(lib.ct_space_valid_list(self._h, ctypes.byref(lin), ctypes.byref(rows)))
+        _lib.check(lib.ct_space_bitmask(self._h, ctypes.byref(words), ctypes.byref(nw)))
+        return lin.value or 0, rows.value or 0, words.value or 0, nw.value
+
     def pack_rows(self, digits) -> "object":
         """Digit matrix [n, D] (any integer tensor/array) -> uint8 rows [n, row_bytes] on the GPU."""
         torch = _torch()
@@ -206,10 +216,19 @@ class Space:
 def make_params(algo: int, pop_size: int, seed: int, **kw) -> ct_pop_params:
     p = ct_pop_params()
     p.algo, p.pop_size, p.seed = algo, pop_size, seed
-    p.F_q16, p.CR_q32, p.de_best = kw.get("F_q16", 45875), kw.get("CR_q32", 2576980378), kw.get("de_best", 1)
+    p.F_q16, p.CR_q32, p.de_method = kw.get("F_q16", 45875), kw.get("CR_q32", 2576980378), kw.get("de_method", 1)
     p.w_q16, p.c1_q16, p.c2_q16 = kw.get("w_q16", 32768), kw.get("c1_q16", 196608), kw.get("c2_q16", 32768)
     p.mutation_chance, p.beta_b = kw.get("mutation_chance", 5), kw.get("beta_b", 3)
+    p.ff_B0_q16, p.ff_gamma_q16 = kw.get("ff_B0_q16", 65536), kw.get("ff_gamma_q16", 65536)
+    p.ff_alpha_q16 = kw.get("ff_alpha_q16", 13107)
     return p
+
+
+def opt_kwargs(opt) -> Dict[str, int]:
+    """The hyperparameters of a workloads.OptParams as make_params keywords."""
+    return dict(F_q16=opt.F_q16, CR_q32=opt.CR_q32, de_method=opt.de_method, w_q16=opt.w_q16, c1_q16=opt.c1_q16,
+                c2_q16=opt.c2_q16, mutation_chance=opt.mutation_chance, beta_b=opt.beta_b,
+                ff_B0_q16=opt.ff_B0_q16, ff_gamma_q16=opt.ff_gamma_q16, ff_alpha_q16=opt.ff_alpha_q16)
 
 
 class Pop:
@@ -229,9 +248,7 @@ class Pop:
     @classmethod
     def from_opt(cls, space: Space, opt, objective) -> "Pop":
         """From a workloads.OptParams."""
-        return cls(space, opt.algo, opt.pop_size, opt.seed, objective, F_q16=opt.F_q16, CR_q32=opt.CR_q32,
-                   de_best=opt.de_best, w_q16=opt.w_q16, c1_q16=opt.c1_q16, c2_q16=opt.c2_q16,
-                   mutation_chance=opt.mutation_chance, beta_b=opt.beta_b)
+        return cls(space, opt.algo, opt.pop_size, opt.seed, objective, **opt_kwargs(opt))
 
     @property
     def handle(self):
@@ -359,9 +376,7 @@ class Server:
         flat = np.ascontiguousarray([int(x) for v in values for x in v], dtype=np.int64)
         rad = np.ascontiguousarray([len(v) for v in values], dtype=np.uint32)
         code = code if len(code) else np.zeros(1, dtype=np.uint32)
-        prm = make_params(opt.algo, opt.pop_size, opt.seed, F_q16=opt.F_q16, CR_q32=opt.CR_q32,
-                          de_best=opt.de_best, w_q16=opt.w_q16, c1_q16=opt.c1_q16, c2_q16=opt.c2_q16,
-                          mutation_chance=opt.mutation_chance, beta_b=opt.beta_b)
+        prm = make_params(opt.algo, opt.pop_size, opt.seed, **opt_kwargs(opt))
         rid = ctypes.c_uint64()
         _lib.check(_lib.load().ct_server_submit(self._h, flat.ctypes.data, rad.ctypes.data, len(values),
                                                 code.ctypes.data, offs.ctypes.data, len(spec.constraints),
@@ -445,6 +460,18 @@ def prof_read(kernel: str):
     t, n = ctypes.c_double(), ctypes.c_uint64()
     _lib.check(_lib.load().ct_prof_read(kernel.encode(), ctypes.byref(t), ctypes.byref(n)))
     return float(t.value), int(n.value)
+
+
+def prof_count_boxes(on: bool = True):
+    """Count the boxes and chunks the repair scans open (measurement support; clears the counters)."""
+    _lib.check(_lib.load().ct_prof_count_boxes(1 if on else 0))
+
+
+def prof_boxes() -> List[int]:
+    """[main-pass boxes, main-pass chunks, fallback boxes, fallback chunks] since prof_count_boxes(True)."""
+    out = np.zeros(4, dtype=np.uint64)
+    _lib.check(_lib.load().ct_prof_boxes(out.ctypes.data))
+    return [int(x) for x in out]
 
 
 def step_many(pops: List[Pop], n_generations: int = 1, flags: int = CT_STEP_PLAIN):

@@ -16,7 +16,7 @@ CT_OK, CT_EINVAL, CT_ENOMEM, CT_EOVERFLOW, CT_EEMPTY, CT_EDEVICE, CT_ESYNTAX = 0
 STATUS = {CT_EINVAL: "CT_EINVAL", CT_ENOMEM: "CT_ENOMEM", CT_EOVERFLOW: "CT_EOVERFLOW", CT_EEMPTY: "CT_EEMPTY",
           CT_EDEVICE: "CT_EDEVICE", CT_ESYNTAX: "CT_ESYNTAX"}
 CT_HAMMING, CT_INDEX_L1, CT_TIER_EUCLID, CT_TIER_RANDOM, CT_HAM1_RANDOM = 0, 1, 2, 3, 4
-CT_DE, CT_PSO, CT_GA = 0, 1, 2
+CT_DE, CT_PSO, CT_GA, CT_FIREFLY = 0, 1, 2, 3
 CT_STEP_PLAIN, CT_STEP_BATCHED, CT_STEP_GRAPH = 0, 1, 2
 CT_SCAN_SERIAL, CT_SCAN_STREAMS, CT_SCAN_FUSED = 0, 1, 2
 
@@ -29,10 +29,11 @@ class CtError(RuntimeError):
 
 class ct_pop_params(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_uint32), ("pop_size", ctypes.c_uint32), ("seed", ctypes.c_uint64),
-                ("F_q16", ctypes.c_uint32), ("de_best", ctypes.c_uint32), ("CR_q32", ctypes.c_uint64),
+                ("F_q16", ctypes.c_uint32), ("de_method", ctypes.c_uint32), ("CR_q32", ctypes.c_uint64),
                 ("w_q16", ctypes.c_uint32), ("c1_q16", ctypes.c_uint32), ("c2_q16", ctypes.c_uint32),
                 ("mutation_chance", ctypes.c_uint32), ("beta_b", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 3)]
+                ("ff_B0_q16", ctypes.c_uint32), ("ff_gamma_q16", ctypes.c_uint32), ("ff_alpha_q16", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 7)]
 
 
 _vp, _u32, _u64, _i32, _sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_size_t
@@ -105,6 +106,8 @@ SIGNATURES = {
     "ct_prof_enable": (_i32, [_i32]),
     "ct_prof_read": (_i32, [ctypes.c_char_p, _P(ctypes.c_double), _P(_u64)]),
     "ct_prof_select": (_i32, [ctypes.c_char_p]),
+    "ct_prof_count_boxes": (_i32, [_i32]),
+    "ct_prof_boxes": (_i32, [_vp]),
 }
 
 _lock = threading.Lock()

@@ -94,24 +94,25 @@ int batch_fill(ct_batch* b, const std::vector<ct_pop*>& pops) {
     if (pops.size() > 4096) return ct_fail(CT_EINVAL, "batch: at most 4096 populations");
     const uint32_t n = (uint32_t)pops.size();
     std::vector<PopDev> pd;
-    std::vector<uint32_t> ind_off{0}, ga_off{0};
+    std::vector<uint32_t> ind_off{0}, ga_off{0}, ff_off{0};
     std::vector<RepairSet> setsA, setsC;
     uint32_t maskA = 0, fbA = 0, max_pop = 0, tabA = 0;
     for (ct_pop* p : pops) {
         const PopDev& d = p->dev;
         pd.push_back(d);
         ind_off.push_back(ind_off.back() + d.P);
+        ff_off.push_back(ff_off.back() + (d.algo == CT_FIREFLY ? d.P : 0u));
         RepairSet r{};
         r.S = d.S;
         r.R = d.R;
         r.n_sub = p->space->dev.n_sub;
         r.rows = d.trial;
         r.n = d.P;
-        r.metric = d.algo == CT_DE ? CT_INDEX_L1 : d.algo == CT_PSO ? CT_TIER_EUCLID : CT_TIER_RANDOM;
+        r.metric = d.algo == CT_DE ? CT_INDEX_L1 : d.algo == CT_GA ? CT_TIER_RANDOM : CT_TIER_EUCLID;
         r.seed = d.seed;
         r.gen = d.state;
         r.who = nullptr;
-        r.pos_q16 = d.algo == CT_PSO ? d.X : nullptr;
+        r.pos_q16 = d.algo == CT_PSO ? d.X : d.algo == CT_FIREFLY ? d.Xn : nullptr;
         r.out_rows = d.out;
         r.out_pos = d.tpos;
         r.apply = nullptr;
@@ -156,9 +157,10 @@ int batch_fill(ct_batch* b, const std::vector<ct_pop*>& pops) {
         b->d_pops = (PopDev*)own(cap * sizeof(PopDev));
         b->d_ind_off = (uint32_t*)own((cap + 1) * 4);
         b->d_ga_off = (uint32_t*)own((cap + 1) * 4);
+        b->d_ff_off = (uint32_t*)own((cap + 1) * 4);
         b->d_setsA = (RepairSet*)own(cap * sizeof(RepairSet));
         b->d_setsC = (RepairSet*)own(cap * sizeof(RepairSet));
-        if (!b->d_pops || !b->d_ind_off || !b->d_ga_off || !b->d_setsA || !b->d_setsC) {
+        if (!b->d_pops || !b->d_ind_off || !b->d_ga_off || !b->d_ff_off || !b->d_setsA || !b->d_setsC) {
             b->cap = 0;
             b->d_pops = nullptr;
             return ct_fail(CT_ENOMEM, "batch: hipMalloc failed");
@@ -182,12 +184,14 @@ int batch_fill(ct_batch* b, const std::vector<ct_pop*>& pops) {
         (rc = upload(b->d_ind_off, ind_off.data(), ind_off.size() * 4)) ||
         (rc = upload(b->d_setsA, setsA.data(), setsA.size() * sizeof(RepairSet))) ||
         (rc = upload(b->d_setsC, setsC.data(), setsC.size() * sizeof(RepairSet))) ||
-        (rc = upload(b->d_ga_off, ga_off.data(), ga_off.size() * 4)))
+        (rc = upload(b->d_ga_off, ga_off.data(), ga_off.size() * 4)) ||
+        (rc = upload(b->d_ff_off, ff_off.data(), ff_off.size() * 4)))
         return rc;
     b->pops = pops;
     b->n = n;
     b->total_ind = ind_off.back();
     b->n_ga = (uint32_t)setsC.size();
+    b->total_ff = ff_off.back();
     b->max_pop = max_pop;
     // main repair pass: every run (its prep items are its individuals)
     b->passA.fan = &b->fan;
@@ -243,6 +247,7 @@ uint64_t pop_footprint_bytes(uint32_t algo, uint32_t P, uint32_t D, uint32_t R, 
     uint64_t b = 16 + 16 + 16 + 8 + 2 * p * R + 4 * p + p;      // state, tally, rcount, best, trial, out, tpos, apply
     if (algo == CT_PSO) b += pd * (4 + 8 + 4) + 8 * p;           // X, V, PB, f_pb, pb_pos
     else b += 8 * p;                                              // pos, f
+    if (algo == CT_FIREFLY) b += pd * (4 + 4);                    // X, Xn
     if (algo == CT_DE) b += (n_valid + 31) / 32 * 4 + std::max<uint64_t>(n_valid, 1) * 4;   // member, claim
     if (algo == CT_GA) b += 8 * p + 4 * p;                        // beta table, sorted
     b += 4 * p + 8 * p + 4 * p + 8 * p + slots * (8 + 4);         // repair scratch
@@ -252,7 +257,7 @@ uint64_t pop_footprint_bytes(uint32_t algo, uint32_t P, uint32_t D, uint32_t R, 
 uint64_t batch_bytes(uint32_t cap) {
     const uint64_t c = std::max<uint32_t>(cap, 1);
     const uint64_t plan = ((c + 1) * 6 + c) * 4;
-    return c * sizeof(PopDev) + 2 * (c + 1) * 4 + 2 * c * sizeof(RepairSet) + 2 * plan;
+    return c * sizeof(PopDev) + 3 * (c + 1) * 4 + 2 * c * sizeof(RepairSet) + 2 * plan;
 }
 
 void batch_free(ct_batch* b) {
@@ -383,7 +388,7 @@ extern "C" {
 
 const char* ct_last_error(void) { return g_err.c_str(); }
 
-int ct_version(void) { return 1; }
+int ct_version(void) { return 2; }
 
 int ct_space_build(const int64_t* values, const uint32_t* radices, uint32_t n_params, const uint32_t* code,
                    const uint32_t* cons_offsets, uint32_t n_cons, void* stream, ct_space** out) {
@@ -537,7 +542,7 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_ob
     if (!s || !prm || !d_objective || !out) return ct_fail(CT_EINVAL, "ct_pop_create: null argument");
     *out = nullptr;
     const ct_pop_params& q = *prm;
-    if (q.algo > CT_GA) return ct_fail(CT_EINVAL, "ct_pop_create: unknown algorithm");
+    if (q.algo > CT_FIREFLY) return ct_fail(CT_EINVAL, "ct_pop_create: unknown algorithm");
     if (s->n_valid == 0) return ct_fail(CT_EEMPTY, "ct_pop_create: the space has no valid configuration");
     if (s->n_valid > CT_MAX_VALID)
         return ct_fail(CT_EINVAL, "ct_pop_create: more valid configurations than 32-bit positions can name");
@@ -550,6 +555,10 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_ob
         return ct_fail(CT_EINVAL, "ct_pop_create: PSO coefficients out of range");
     if (q.algo == CT_GA && (q.mutation_chance < 1 || q.beta_b < 1 || q.beta_b > 5 || q.pop_size > 8192))
         return ct_fail(CT_EINVAL, "ct_pop_create: GA needs mutation_chance >= 1, 1 <= beta_b <= 5, pop_size <= 8192");
+    if (q.algo == CT_FIREFLY && (q.ff_B0_q16 > (1u << 20) || q.ff_gamma_q16 > (1u << 20) || q.ff_alpha_q16 > (1u << 20)))
+        return ct_fail(CT_EINVAL, "ct_pop_create: Firefly B0, gamma and alpha must be at most 2^20 (16.0)");
+    for (uint32_t w : q.reserved)
+        if (w) return ct_fail(CT_EINVAL, "ct_pop_create: reserved parameter words must be 0");
     int rc = require_device();
     if (rc) return rc;
     hipStream_t st = as_stream(stream);
@@ -565,13 +574,16 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_ob
     d.R = s->R;
     d.seed = q.seed;
     d.F_q16 = q.F_q16;
-    d.de_best = q.de_best;
+    d.de_method = q.de_method;
     d.CR_q32 = q.CR_q32;
     d.w_q16 = q.w_q16;
     d.c1_q16 = q.c1_q16;
     d.c2_q16 = q.c2_q16;
     d.mut_thresh = q.algo == CT_GA ? (1ull << 32) / q.mutation_chance : 0;   // chance 1: 2^32, every child
     d.M = s->dev.max_radix;
+    d.ff_B0 = q.ff_B0_q16;
+    d.ff_gamma = q.ff_gamma_q16;
+    d.ff_alpha = q.ff_alpha_q16;
     d.obj = d_objective;
     const uint32_t P = d.P;
     auto fail = [&](int code_) {
@@ -588,6 +600,9 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_ob
             return fail(rc);
     } else {
         if ((rc = dalloc(p, &d.pos, P)) || (rc = dalloc(p, &d.f, P))) return fail(rc);
+    }
+    if (q.algo == CT_FIREFLY) {
+        if ((rc = dalloc(p, &d.X, (size_t)P * d.D)) || (rc = dalloc(p, &d.Xn, (size_t)P * d.D))) return fail(rc);
     }
     if (q.algo == CT_DE) {
         size_t words = (s->n_valid + 31) / 32;
@@ -785,6 +800,7 @@ static size_t snapshot_size(const PopDev& d) {
     size_t n = 32;
     if (d.algo == CT_PSO) n += (size_t)d.P * d.D * (4 + 8 + 4) + (size_t)d.P * 8 + 4;
     else n += (size_t)d.P * 8;
+    if (d.algo == CT_FIREFLY) n += (size_t)d.P * d.D * 4;
     return n;
 }
 
@@ -813,7 +829,8 @@ int ct_pop_snapshot(const ct_pop* p, void* h_buf, size_t* len) {
         memcpy(o, &stt[2], 4);
     } else {
         CT_HIP(hipMemcpy(o, d.pos, d.P * 4, hipMemcpyDeviceToHost)); o += d.P * 4;
-        CT_HIP(hipMemcpy(o, d.f, d.P * 4, hipMemcpyDeviceToHost));
+        CT_HIP(hipMemcpy(o, d.f, d.P * 4, hipMemcpyDeviceToHost)); o += d.P * 4;
+        if (d.algo == CT_FIREFLY) CT_HIP(hipMemcpy(o, d.X, (size_t)d.P * d.D * 4, hipMemcpyDeviceToHost));
     }
     *len = need;
     return CT_OK;
@@ -861,6 +878,13 @@ int ct_pop_restore(ct_pop* p, const void* h_buf, size_t len) {
         memcpy(pos.data(), o, P * 4);
         for (uint32_t v : pos)
             if (v >= nv) return ct_fail(CT_EINVAL, "ct_pop_restore: position out of range");
+        if (d.algo == CT_FIREFLY) {
+            const int64_t xmax = (int64_t)d.M * 65536;
+            std::vector<int32_t> X(PD);
+            memcpy(X.data(), o + P * 8, PD * 4);
+            for (int32_t x : X)
+                if (x < 0 || x >= xmax) return ct_fail(CT_EINVAL, "ct_pop_restore: firefly coordinate outside [0, M * 2^16)");
+        }
         if (d.algo == CT_DE) {
             // the membership bitmap is derived from the positions, which must be distinct
             words.assign((nv + 31) / 32, 0);
@@ -883,7 +907,8 @@ int ct_pop_restore(ct_pop* p, const void* h_buf, size_t len) {
         memcpy(&stt[2], o, 4);
     } else {
         CT_HIP(hipMemcpy(d.pos, o, P * 4, hipMemcpyHostToDevice)); o += P * 4;
-        CT_HIP(hipMemcpy(d.f, o, P * 4, hipMemcpyHostToDevice));
+        CT_HIP(hipMemcpy(d.f, o, P * 4, hipMemcpyHostToDevice)); o += P * 4;
+        if (d.algo == CT_FIREFLY) CT_HIP(hipMemcpy(d.X, o, PD * 4, hipMemcpyHostToDevice));
         if (d.algo == CT_DE) CT_HIP(hipMemcpy(d.member, words.data(), words.size() * 4, hipMemcpyHostToDevice));
     }
     CT_HIP(hipMemcpy(d.state, stt, 16, hipMemcpyHostToDevice));

@@ -12,6 +12,8 @@
 
 int ct_fail(int code, const std::string& msg);
 void prof_suspend(bool on);          // no event records (while a stream is being captured)
+// device counters of the boxes and chunks the repair scans open, or null when not counting
+unsigned long long* prof_box_counter();
 
 // Records HIP events around the enclosed launch when kernel timing is enabled.
 class ProfScope {
@@ -112,6 +114,8 @@ struct RepairPlan {
     uint32_t* item_off;               // [kRepairClasses][n_sets + 1] prefix of (candidate, part) items per class
     uint32_t* parts;                  // [n_sets]
     uint32_t* done;                   // blocks finished in the kernel that plans (0 between launches)
+    unsigned long long* opened;       // nullable (measurement): [which * 2] += 64-row boxes opened,
+                                      // [which * 2 + 1] += chunks opened, over the pass's scan items
 };
 
 constexpr uint32_t kRepairTargetWaves = 8192;   // scan items per class launch, untuned (ct_repair's slot minimum)
@@ -178,17 +182,18 @@ struct PopDev {
     const DevSpace* S;                // device view of the run's space
     uint32_t algo, P, D, R;
     uint64_t seed;
-    uint32_t F_q16, de_best;
+    uint32_t F_q16, de_method;
     uint64_t CR_q32;
     int64_t w_q16, c1_q16, c2_q16;
     uint64_t mut_thresh;              // floor(2^32 / mutation_chance): a child mutates when its draw is below
-    uint32_t M;                       // largest radix (PSO domain [0, M) per dimension)
+    uint32_t M;                       // largest radix (PSO/Firefly domain [0, M) per dimension)
+    int64_t ff_B0, ff_gamma, ff_alpha;  // Firefly B0, gamma, alpha in Q16.16
     uint64_t n_valid;
     const float* obj;                 // [n_valid]
     uint32_t* state;                  // [0] generation, [1] reinits, [2] gbest index, [3] accepted
     uint64_t* best;                   // packed (orderable float bits << 32) | position
-    uint32_t* pos;                    // [P] population (DE/GA) as valid-list positions
-    float* f;                         // [P]
+    uint32_t* pos;                    // [P] population (DE/GA) as valid-list positions; Firefly: evaluated position
+    float* f;                         // [P] objective (Firefly: brightness, lower is brighter)
     uint8_t* trial;                   // [P][R] proposals
     uint8_t* out;                     // [P][R] after repair (and mutation)
     uint32_t* tpos;                   // [P] positions of `out`
@@ -197,7 +202,8 @@ struct PopDev {
     uint32_t* claim;                  // DE: [n_valid] lowest accepted trial index per position
     uint32_t* sorted;                 // GA: positions by rank
     const uint64_t* beta;             // GA: cumulative selection thresholds [P]
-    int32_t* X;                       // PSO [P][D] Q16.16 positions
+    int32_t* X;                       // PSO / Firefly [P][D] Q16.16 positions
+    int32_t* Xn;                      // Firefly [P][D] positions after this generation's moves
     int64_t* V;                       // PSO [P][D] velocities
     int32_t* PB;                      // PSO [P][D] personal-best positions
     float* f_pb;                      // PSO [P]
@@ -232,10 +238,12 @@ struct ct_batch {
     PopDev* d_pops = nullptr;
     uint32_t* d_ind_off = nullptr;    // [n + 1] prefix of population sizes
     uint32_t* d_ga_off = nullptr;     // [n_ga + 1] prefix of GA population sizes
+    uint32_t* d_ff_off = nullptr;     // [n + 1] prefix of Firefly population sizes (0 for other runs)
     RepairSet* d_setsA = nullptr;
     RepairSet* d_setsC = nullptr;
     uint32_t total_ind = 0;
     uint32_t n_ga = 0, max_pop = 0;
+    uint32_t total_ff = 0;            // fireflies in the group
     RepairPasses passA, passC;        // main repair, GA mutation
     std::vector<void*> owned;
     hipGraph_t graph = nullptr;

@@ -20,6 +20,8 @@ bool g_suspend = false;
 std::string g_only;                 // empty: every kernel
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
+unsigned long long* g_boxes = nullptr;   // [4] main boxes, main chunks, fallback boxes, fallback chunks
+bool g_count_boxes = false;
 
 hipEvent_t take() {
     if (!g_pool.empty()) {
@@ -52,6 +54,30 @@ ProfScope::~ProfScope() {
 void prof_suspend(bool on) {
     std::lock_guard<std::mutex> g(g_mu);
     g_suspend = on;
+}
+
+unsigned long long* prof_box_counter() {
+    std::lock_guard<std::mutex> g(g_mu);
+    return g_count_boxes && !g_suspend ? g_boxes : nullptr;
+}
+
+extern "C" int ct_prof_count_boxes(int on) {
+    std::lock_guard<std::mutex> g(g_mu);
+    CT_HIP(hipDeviceSynchronize());
+    if (on && !g_boxes) CT_HIP(hipMalloc(&g_boxes, 4 * sizeof(unsigned long long)));
+    if (g_boxes) CT_HIP(hipMemset(g_boxes, 0, 4 * sizeof(unsigned long long)));
+    g_count_boxes = on != 0;
+    return CT_OK;
+}
+
+extern "C" int ct_prof_boxes(uint64_t* out4) {
+    if (!out4) return ct_fail(CT_EINVAL, "ct_prof_boxes: null argument");
+    std::lock_guard<std::mutex> g(g_mu);
+    CT_HIP(hipDeviceSynchronize());
+    unsigned long long h[4] = {0, 0, 0, 0};
+    if (g_boxes) CT_HIP(hipMemcpy(h, g_boxes, sizeof(h), hipMemcpyDeviceToHost));
+    for (int k = 0; k < 4; ++k) out4[k] = h[k];
+    return CT_OK;
 }
 
 extern "C" int ct_prof_enable(int on) {

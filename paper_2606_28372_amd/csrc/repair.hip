@@ -363,7 +363,8 @@ __device__ __forceinline__ uint64_t rank_g(const CT_GLOBAL DevSpace* S, uint64_t
 // register convention costs the tiered metrics twice the VGPRs plus stack spills.
 template <int M, int RW>
 __device__ __forceinline__ void scan_item(const RepairSet& J, const DevSpace& S, const uint32_t* list, const uint64_t* list_ins,
-                          uint32_t li, uint32_t part, uint32_t parts, CT_LDS uint64_t* lds_tab) {
+                          uint32_t li, uint32_t part, uint32_t parts, CT_LDS uint64_t* lds_tab,
+                          unsigned long long* opened) {
     const uint32_t lane = wave_lane();
     const CT_GLOBAL DevSpace* Sg = gptr(&S);
     const uint32_t ci = uni(gld(list + li));
@@ -406,6 +407,7 @@ __device__ __forceinline__ void scan_item(const RepairSet& J, const DevSpace& S,
     const uint64_t n_mine = strided ? (n_chunk - part + parts - 1) / parts : ((b1 + 63u) >> 6) - k0;
     const CT_GLOBAL uint32_t* chunk32 = gptr(reinterpret_cast<const uint32_t*>(Sg->chunks));
     uint32_t nv[RW];
+    uint32_t n_box = 0, n_chunk_open = 0;           // measurement only (when `opened` is given)
     for (uint64_t ck = 0; ck < n_mine; ck += 64) {
         // lanes over 64 of the part's chunks: which ones can hold a row below the bound?
         const uint64_t kc = k0 + (ck + lane) * kstep;
@@ -424,6 +426,7 @@ __device__ __forceinline__ void scan_item(const RepairSet& J, const DevSpace& S,
             const uint32_t tc = (uint32_t)(__ffsll((long long)mc) - 1);
             mc &= ~(1ull << tc);
             const uint64_t cb = (k0 + (ck + tc) * kstep) * 64u;   // the chunk's first box
+            ++n_chunk_open;
             // lanes over the chunk's boxes inside [b0, b1)
             const uint64_t b = cb + lane;
             uint64_t lb = kNoKey;
@@ -447,6 +450,7 @@ __device__ __forceinline__ void scan_item(const RepairSet& J, const DevSpace& S,
             while (tn >= 0) {
                 const uint32_t t = (uint32_t)tn;
                 m &= ~(1ull << t);
+                ++n_box;
                 uint32_t v[RW];
 #pragma unroll
                 for (int w = 0; w < RW; ++w) v[w] = nv[w];
@@ -477,6 +481,10 @@ __device__ __forceinline__ void scan_item(const RepairSet& J, const DevSpace& S,
     if (lane == 0) {
         J.part_key[(uint64_t)li * parts + part] = k2;
         J.part_pos[(uint64_t)li * parts + part] = p2;
+        if (opened) {
+            atomicAdd(opened, (unsigned long long)n_box);
+            atomicAdd(opened + 1, (unsigned long long)n_chunk_open);
+        }
     }
 }
 
@@ -587,6 +595,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_scan(const RepairSet* __restr
     CT_LDS uint64_t* lds_tab = (CT_LDS uint64_t*)lds_tabs + (threadIdx.x >> 6) * tab_stride;
     const uint32_t* off = plan.item_off + cls * (n_sets + 1);
     const uint32_t total = off[n_sets];
+    unsigned long long* opened = plan.opened ? plan.opened + 2 * which : nullptr;
     const uint32_t waves = gridDim.x * wpb;
     for (uint32_t item = uni(first_item(wpb)); item < total; item += waves) {
         const uint32_t s = uni(find_set(off, n_sets, item));
@@ -600,7 +609,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_scan(const RepairSet* __restr
         } else {
             const uint32_t* list = which ? J.fb_list : J.list;
             const uint64_t* list_ins = which ? J.fb_ins : J.list_ins;
-            scan_item<M, RW>(J, S, list, list_ins, li, part, parts, lds_tab);
+            scan_item<M, RW>(J, S, list, list_ins, li, part, parts, lds_tab, opened);
         }
     }
 }
@@ -633,6 +642,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_scan_mix(const RepairSet* __r
         end[q] = acc;
     }
     const uint32_t waves = gridDim.x * wpb;
+    unsigned long long* opened = plan.opened ? plan.opened + 2 * which : nullptr;
     for (uint32_t item = uni(first_item(wpb)); item < acc; item += waves) {
         const uint32_t q = item < end[0] ? 0u : item < end[1] ? 1u : item < end[2] ? 2u : 3u;
         const uint32_t m = mix_metric(q);
@@ -647,10 +657,10 @@ __global__ __launch_bounds__(kBlock) void k_repair_scan_mix(const RepairSet* __r
         const uint32_t* list = which ? J.fb_list : J.list;
         const uint64_t* list_ins = which ? J.fb_ins : J.list_ins;
         switch (m) {
-        case CT_HAMMING: scan_item<CT_HAMMING, RW>(J, S, list, list_ins, li, part, parts, lds_tab); break;
-        case CT_INDEX_L1: scan_item<CT_INDEX_L1, RW>(J, S, list, list_ins, li, part, parts, lds_tab); break;
-        case CT_TIER_EUCLID: scan_item<CT_TIER_EUCLID, RW>(J, S, list, list_ins, li, part, parts, lds_tab); break;
-        default: scan_item<CT_TIER_RANDOM, RW>(J, S, list, list_ins, li, part, parts, lds_tab); break;
+        case CT_HAMMING: scan_item<CT_HAMMING, RW>(J, S, list, list_ins, li, part, parts, lds_tab, opened); break;
+        case CT_INDEX_L1: scan_item<CT_INDEX_L1, RW>(J, S, list, list_ins, li, part, parts, lds_tab, opened); break;
+        case CT_TIER_EUCLID: scan_item<CT_TIER_EUCLID, RW>(J, S, list, list_ins, li, part, parts, lds_tab, opened); break;
+        default: scan_item<CT_TIER_RANDOM, RW>(J, S, list, list_ins, li, part, parts, lds_tab, opened); break;
         }
     }
 }
@@ -789,26 +799,33 @@ uint32_t scan_waves(const RepairPasses& rp, uint32_t which) {
     return which ? std::min(rp.tune.grid_waves, rp.tune.items) : rp.tune.grid_waves;
 }
 
+// the pass's plan, with the measurement counters when they are on
+RepairPlan scan_plan(const RepairPasses& rp) {
+    RepairPlan p = rp.plan;
+    p.opened = prof_box_counter();
+    return p;
+}
+
 template <int M, int RW>
 void launch_scan_rw(const RepairPasses& rp, uint32_t which, hipStream_t st) {
-    ProfScope ps_("k_repair_scan", st);
+    ProfScope ps_(which ? "k_repair_scan_fb" : "k_repair_scan", st);
     // TIER_EUCLID keeps one distance table per wave in LDS (at most 64 KiB per block)
     const uint32_t stride = M == CT_TIER_EUCLID ? std::max<uint32_t>(rp.euclid_tab, 1) : 0;
     uint32_t wpb = kBlock / 64;
     while (wpb > 1 && (size_t)wpb * stride * 8 > 65536) wpb >>= 1;
     hipLaunchKernelGGL((k_repair_scan<M, RW>), dim3(std::max<uint32_t>(scan_waves(rp, which) / wpb, 1)), dim3(wpb * 64),
                        (size_t)wpb * stride * 8, st,
-                       rp.d_sets, rp.n_sets, rp.plan, which, stride);
+                       rp.d_sets, rp.n_sets, scan_plan(rp), which, stride);
 }
 
 template <int RW>
 void launch_mix_rw(const RepairPasses& rp, uint32_t mmask, uint32_t which, hipStream_t st) {
-    ProfScope ps_("k_repair_scan", st);
+    ProfScope ps_(which ? "k_repair_scan_fb" : "k_repair_scan", st);
     const uint32_t stride = (mmask & (1u << CT_TIER_EUCLID)) ? std::max<uint32_t>(rp.euclid_tab, 1) : 0;
     uint32_t wpb = kBlock / 64;
     while (wpb > 1 && (size_t)wpb * stride * 8 > 65536) wpb >>= 1;
     hipLaunchKernelGGL((k_repair_scan_mix<RW>), dim3(std::max<uint32_t>(scan_waves(rp, which) / wpb, 1)), dim3(wpb * 64),
-                       (size_t)wpb * stride * 8, st, rp.d_sets, rp.n_sets, rp.plan, which, stride, mmask);
+                       (size_t)wpb * stride * 8, st, rp.d_sets, rp.n_sets, scan_plan(rp), which, stride, mmask);
 }
 
 void launch_mix(const RepairPasses& rp, uint32_t rwi, uint32_t mmask, uint32_t which, hipStream_t st) {
@@ -915,6 +932,7 @@ int repair_plan_alloc(RepairPlan& p, uint32_t n_sets, std::vector<void*>& owned)
     p.item_off = w + (n_sets + 1);
     p.parts = w + (n_sets + 1) * (1 + kNumClasses);
     p.done = p.parts + n_sets;
+    p.opened = nullptr;
     CT_HIP(hipMemset(p.done, 0, sizeof(uint32_t)));
     return CT_OK;
 }

@@ -294,7 +294,7 @@ int ct_server_submit(ct_server* s, const int64_t* values, const uint32_t* radice
                      uint32_t n_generations, double arrival_s, uint64_t* run_id) {
     if (!s || !prm || !run_id) return ct_fail(CT_EINVAL, "ct_server_submit: null argument");
     if (n_generations < 1) return ct_fail(CT_EINVAL, "ct_server_submit: n_generations must be >= 1");
-    if (prm->algo > CT_GA) return ct_fail(CT_EINVAL, "ct_server_submit: unknown algorithm");
+    if (prm->algo > CT_FIREFLY) return ct_fail(CT_EINVAL, "ct_server_submit: unknown algorithm");
     ct_space* sp = nullptr;
     int rc = space_prepare(values, radices, n_params, code, cons_offsets, n_cons, &sp);
     if (rc) return rc;

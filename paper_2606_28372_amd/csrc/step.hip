@@ -12,6 +12,11 @@
 //   GA  (Section IV-D): population sorted by objective, Beta(1, b) rank
 //       selection, single-point crossover, Alg. 3 repair, then mutation to a
 //       random valid Hamming neighbour with chance 1/mutation_chance.
+//   Firefly (Section IV-C, last paragraph; Table IV): PSO's sampling, mapping
+//       and Alg. 2 evaluation; each firefly moves towards every firefly that
+//       was brighter at the start of the generation (ascending index) by
+//       B0 exp(-gamma r^2) of the way plus a uniform step of width alpha per
+//       dimension, all in Q16.16 with a Q0.32 exponential.
 //
 // One generation of a batch of runs is: sort (GA runs, one block each) ->
 // propose (one thread per individual of every run) -> repair passes (shared
@@ -24,6 +29,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 
 #include "ct_host.h"
 #include "repair_plan.h"
@@ -125,6 +131,13 @@ __global__ __launch_bounds__(kBlock) void k_init(PopDev p) {
         }
         p.f_pb[i] = f;
         p.pb_pos[i] = pos;
+    } else if (p.algo == CT_FIREFLY) {
+        // PSO's mapping: the centre of each value of the valid sample
+        Row r;
+        valid_row(p, pos, r);
+        for (uint32_t j = 0; j < p.D; ++j) p.X[(uint64_t)i * p.D + j] = (int32_t)((2u * r.digit(j) + 1u) << 15);
+        p.pos[i] = pos;
+        p.f[i] = f;
     } else {
         p.pos[i] = pos;
         p.f[i] = f;
@@ -226,7 +239,7 @@ __device__ __forceinline__ uint32_t propose_digit(const PopDev& p, const DevSpac
         sort3(ex, 3);
         const uint32_t r3 = pick_excl(o.z, p.P, ex, 3);
         const uint32_t jr = ct_below(o.w, p.D);
-        const uint32_t pb = p.de_best ? (uint32_t)(gld(p.best) & 0xFFFFFFFFu) : gld(p.pos + r1);
+        const uint32_t pb = p.de_method ? (uint32_t)(gld(p.best) & 0xFFFFFFFFu) : gld(p.pos + r1);
         const uint32_t base = row_digit(S, pb, p.R, j), x = row_digit(S, gld(p.pos + i), p.R, j);
         const uint32_t a = row_digit(S, gld(p.pos + r2), p.R, j), b = row_digit(S, gld(p.pos + r3), p.R, j);
         // block j/4 of the crossover draws, draw j%4 of it
@@ -238,6 +251,11 @@ __device__ __forceinline__ uint32_t propose_digit(const PopDev& p, const DevSpac
         const int64_t hi = (int64_t)radix - 1;
         m = m < 0 ? 0 : (m > hi ? hi : m);
         return ((uint64_t)cu < p.CR_q32 || j == jr) ? (uint32_t)m : x;
+    }
+    if (p.algo == CT_FIREFLY) {
+        // the position after this generation's moves, snapped to the nearest value
+        const uint32_t d = (uint32_t)(gld(p.Xn + (uint64_t)i * p.D + j) >> 16);
+        return d < radix ? d : radix - 1u;
     }
     if (p.algo == CT_PSO) {
         const uint32_t gi = gld(p.state + 2);
@@ -357,6 +375,81 @@ void launch_propose(const ct_batch* b, const PlanArgs& pa, hipStream_t st) {
         const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>((b->total_ind * 4 + kBlock - 1) / kBlock, 4096));
         hipLaunchKernelGGL(k_propose<4>, dim3(g), dim3(kBlock), 0, st, b->d_pops, b->n, b->d_ind_off, b->passA.d_sets, pa);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Firefly moves: one wave per firefly, lane d holding coordinate d (D <= 32)
+// ---------------------------------------------------------------------------
+// e^(-x) for x in Q16.16, in Q0.32: the product of the factors e^(-2^(b-16)) over the set bits b of
+// x, ascending, each step rounded half up; x >= 32 gives 0 (e^-32 < 2^-32).
+struct FFExp {
+    uint64_t t[21];
+};
+
+FFExp ff_exp_factors() {
+    FFExp e;
+    for (int b = 0; b < 21; ++b) e.t[b] = (uint64_t)floorl(expl(-ldexpl(1.0L, b - 16)) * 4294967296.0L + 0.5L);
+    return e;
+}
+
+__device__ __forceinline__ uint64_t ff_exp(const FFExp& ex, uint64_t x) {
+    if (x >> 21) return 0;
+    uint64_t a = 1ull << 32;
+#pragma unroll
+    for (int b = 0; b < 21; ++b)
+        if ((x >> b) & 1u) a = (a * ex.t[b] + (1ull << 31)) >> 32;
+    return a;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += shfl_xor_u64(v, o);
+    return v;
+}
+
+// New positions Xn of every firefly of every Firefly run (ff_off: prefix of their population sizes,
+// zero for other runs).  Firefly i reads the positions and brightness at the start of the
+// generation (X, f) and keeps its own moving position in its lanes, so fireflies are independent.
+__global__ __launch_bounds__(kBlock) void k_ff_move(const PopDev* __restrict__ pops, uint32_t n,
+                                                    const uint32_t* __restrict__ ff_off, FFExp ex) {
+    const uint32_t total = ff_off[n];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t waves = gridDim.x * (kBlock / 64);
+    for (uint32_t item = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); item < total; item += waves) {
+        const uint32_t r = find_run(ff_off, n, item);
+        const PopDev& p = pops[r];
+        const uint32_t i = item - ff_off[r];
+        const uint32_t D = p.D, P = p.P, g = p.state[0];
+        const bool act = lane < D;
+        const int64_t M = p.M, xmax = M * 65536 - 1;
+        const uint64_t mm = (uint64_t)(M * M);
+        int64_t x = act ? p.X[(uint64_t)i * D + lane] : 0;
+        const float fi = p.f[i];
+        for (uint32_t j = 0; j < P; ++j) {
+            if (!(p.f[j] < fi)) continue;                 // only brighter fireflies attract
+            const int64_t dx = (act ? (int64_t)p.X[(uint64_t)j * D + lane] : 0) - x;
+            // r^2 in [0,1]^N units, Q16.16: the sum of squares over (M 2^16)^2
+            const uint64_t r2 = (wave_sum_u64((uint64_t)(dx * dx)) >> 16) / mm;
+            const uint64_t e = ff_exp(ex, ((uint64_t)p.ff_gamma * r2) >> 16);
+            const int64_t beta = (int64_t)(((uint64_t)p.ff_B0 * e + (1ull << 31)) >> 32);
+            const U4 o = ct_philox(p.seed, i, g, ((uint32_t)PUR_FF_NOISE << 24) | (lane >> 2), j);
+            const uint32_t t = lane & 3u;
+            const uint32_t u = t == 0 ? o.x : t == 1 ? o.y : t == 2 ? o.z : o.w;
+            const int64_t noise = (p.ff_alpha * M * ((int64_t)(u >> 16) - 32768)) >> 16;
+            const int64_t nx = x + ((beta * dx) >> 16) + noise;
+            // lanes past D stay at 0, so they add nothing to the next distance
+            x = !act ? 0 : nx < 0 ? 0 : (nx > xmax ? xmax : nx);
+        }
+        if (act) p.Xn[(uint64_t)i * D + lane] = (int32_t)x;
+    }
+}
+
+void launch_ff_move(const ct_batch* b, hipStream_t st) {
+    if (!b->total_ff) return;
+    static const FFExp ex = ff_exp_factors();
+    ProfScope ps_("k_ff_move", st);
+    const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>((b->total_ff + kBlock / 64 - 1) / (kBlock / 64), 4096));
+    hipLaunchKernelGGL(k_ff_move, dim3(g), dim3(kBlock), 0, st, b->d_pops, b->n, b->d_ff_off, ex);
 }
 
 // ---------------------------------------------------------------------------
@@ -576,6 +669,25 @@ __device__ void pso_select(const PopDev& p) {
     }
 }
 
+__device__ void ff_select(const PopDev& p) {
+    const uint32_t g = p.state[0];
+    uint64_t m = ~0ull;
+    for (uint32_t i = threadIdx.x; i < p.P; i += blockDim.x) {
+        uint32_t t = p.tpos[i];
+        if (t >= p.n_valid) t = p.pos[i];      // unreachable: every evaluation goes to a valid configuration
+        p.pos[i] = t;
+        p.f[i] = p.obj[t];
+        m = min(m, best_key(p.f[i], t));
+        for (uint32_t j = 0; j < p.D; ++j) p.X[(uint64_t)i * p.D + j] = p.Xn[(uint64_t)i * p.D + j];
+    }
+    m = block_min_u64(m);
+    if (threadIdx.x == 0) {
+        const uint64_t b = *p.best;
+        *p.best = m < b ? m : b;
+        p.state[0] = g + 1;
+    }
+}
+
 __device__ void ga_select(const PopDev& p) {
     const uint32_t g = p.state[0];
     uint64_t m = ~0ull;
@@ -598,6 +710,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select(const PopDev* __restrict__
     const PopDev& p = pops[blockIdx.x];
     if (p.algo == CT_DE) de_select(p);
     else if (p.algo == CT_PSO) pso_select(p);
+    else if (p.algo == CT_FIREFLY) ff_select(p);
     else if (p.P <= blockDim.x) {
         // one child per thread: its key goes to the rank sort (the next generation's rank order)
         // in a register, and the sorted order's first key is the generation's best
@@ -646,6 +759,7 @@ int pop_sort_device(ct_pop* p, hipStream_t st) {
 
 int batch_generation(ct_batch* b, hipStream_t st) {
     if (b->n == 0) return CT_OK;
+    launch_ff_move(b, st);
     {
         ProfScope ps_("k_propose", st);
         launch_propose(b, main_plan(b->passA), st);
@@ -729,6 +843,7 @@ RepairTune sweep_best(const ct_batch* b, int streams) {
 
 // One generation whose main repair pass is first swept over every candidate partitioning.
 int autotune_generation(ct_batch* b, hipStream_t st) {
+    launch_ff_move(b, st);
     {
         // the sweep lists and plans again for every candidate
         launch_propose(b, PlanArgs{}, st);

@@ -54,5 +54,7 @@ def parse_snapshot(blob, algo, P, D):
         out["g_idx"] = struct.unpack_from("<I", blob, o)[0]
     else:
         out["pos"] = np.frombuffer(blob, dtype=np.uint32, count=P, offset=o).astype(np.int64); o += P * 4
-        out["f"] = np.frombuffer(blob, dtype=np.float32, count=P, offset=o).copy()
+        out["f"] = np.frombuffer(blob, dtype=np.float32, count=P, offset=o).copy(); o += P * 4
+        if algo == 3:
+            out["X"] = np.frombuffer(blob, dtype=np.int32, count=P * D, offset=o).reshape(P, D).astype(np.int64)
     return out

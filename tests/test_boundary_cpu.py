@@ -31,7 +31,7 @@ def test_library_exports_every_declared_function():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(_lib.SIGNATURES), "binding and header disagree"
-    assert lib.ct_version() == 1
+    assert lib.ct_version() == 2
 
 
 def eval_compiled(code, offs, k, pv):

@@ -133,3 +133,48 @@ def test_valid_mask_empty_batch():
     sp = gpu_space(W.tiny())
     rows = sp.pack_rows(np.zeros((0, 3), dtype=np.int64))
     assert sp.valid_mask(rows).shape[0] == 0
+
+
+def _hip_runtime():
+    """The HIP runtime this process already loaded (torch's), for raw device-to-host copies."""
+    import ctypes
+    with open("/proc/self/maps") as f:
+        paths = sorted({ln.split()[-1] for ln in f if "libamdhip64.so" in ln})
+    assert paths, "no HIP runtime loaded"
+    return ctypes.CDLL(paths[0])
+
+
+def test_borrowed_list_and_bitmask_pointers():
+    """ct_space_valid_list and ct_space_bitmask hand out the space's own buffers: read through them
+    they hold the oracle's valid list, rows and bitmask."""
+    import ctypes
+    t = torch()
+    osp = oracle_space("gemm10")
+    sp = gpu_space(W.gemm10())
+    t.cuda.synchronize()
+    plin, prows, pw, nw = sp.borrowed()
+    assert plin and prows and pw and nw == (osp.n_cartesian + 63) // 64
+    hip = _hip_runtime()
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    lin = np.empty(osp.n_valid, dtype=np.uint64)
+    rows = np.empty((osp.n_valid, sp.row_bytes), dtype=np.uint8)
+    words = np.empty(nw, dtype=np.uint64)
+    for host, dev in ((lin, plin), (rows, prows), (words, pw)):
+        assert hip.hipMemcpy(host.ctypes.data, dev, host.nbytes, 2) == 0     # device to host
+    assert np.array_equal(lin, osp.vlin)
+    assert np.array_equal(rows[:, :osp.D].astype(np.int32), osp.vrows)
+    assert np.all(rows[:, osp.D:] == 0)
+    bits = np.zeros(nw * 64, dtype=bool)
+    bits[osp.vlin.astype(np.int64)] = True
+    assert np.array_equal(words, np.packbits(bits.reshape(-1, 64)[:, ::-1], axis=1).view(">u8").ravel().astype(np.uint64))
+
+
+def test_many_problem_counts_match_dynamic_programming():
+    """ct_space_count on the first 64 problems of the 256-problem batch (up to ~1e9 configurations
+    each) equals the exact DP count of their linear and modulo constraints."""
+    from tests.helpers import dpcount
+    for pr in W.batched(64, seed=3):
+        sp = gpu_space(pr.spec)
+        assert sp.n_valid == dpcount.count(pr.spec), pr.spec.name
+        assert sp.n_cartesian == pr.spec.n_cartesian
+        sp.close()

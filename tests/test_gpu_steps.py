@@ -31,19 +31,11 @@ def make_pop(sp, opt, obj_t):
 
 
 def oracle_init(osp, obj, opt):
-    if opt.algo == W.ALGO_DE:
-        return ost.de_init(osp, obj, opt.pop_size, opt.seed)
-    if opt.algo == W.ALGO_PSO:
-        return ost.pso_init(osp, obj, opt.pop_size, opt.seed)
-    return ost.ga_init(osp, obj, opt.pop_size, opt.seed)
+    return ost.init_run(osp, obj, opt)
 
 
 def oracle_step(osp, obj, st, opt):
-    if opt.algo == W.ALGO_DE:
-        return ost.de_step(osp, obj, st, opt.seed, opt.F_q16, opt.CR_q32, bool(opt.de_best))
-    if opt.algo == W.ALGO_PSO:
-        return ost.pso_step(osp, obj, st, opt.seed, opt.w_q16, opt.c1_q16, opt.c2_q16)
-    return ost.ga_step(osp, obj, st, opt.seed, opt.mutation_chance, opt.beta_b)
+    return ost.step_run(osp, obj, st, opt)
 
 
 def compare(pop, st, opt, D, where):
@@ -58,13 +50,19 @@ def compare(pop, st, opt, D, where):
         assert g["g_idx"] == st.g_idx, where
         assert g["best_pos"] == st.best_pos
     else:
+        if opt.algo == W.ALGO_FF:
+            bad = np.argwhere(g["X"] != st.X)
+            assert len(bad) == 0, (f"{where}: Firefly X differs at {bad[:3].tolist()}: GPU "
+                                   f"{g['X'][bad[0][0]].tolist()} oracle {st.X[bad[0][0]].tolist()}")
         bad = np.flatnonzero(g["pos"] != st.pos)
-        assert len(bad) == 0, f"{where}: population differs at {bad[:5].tolist()}"
+        assert len(bad) == 0, (f"{where}: population differs at {bad[:5].tolist()}: GPU {g['pos'][bad[:5]].tolist()} "
+                               f"oracle {st.pos[bad[:5]].tolist()}")
         assert np.array_equal(g["f"], st.f.astype(np.float32)), where
         assert g["best_pos"] == st.best_pos, where
         assert np.float32(ord_to_f32(g["best_ord"])) == np.float32(st.best_f), where
         if opt.algo == W.ALGO_DE:
             assert g["reinits"] == st.reinits, where
+
 
 
 def run(space_name, opt, gens, obj_seed):
@@ -125,7 +123,7 @@ def test_ga_largest_population():
 
 
 def test_rand1bin_and_other_coefficients():
-    run("gemm10", W.OptParams(W.ALGO_DE, 64, 9, de_best=0, F_q16=65536, CR_q32=1 << 31), 4, 1)
+    run("gemm10", W.OptParams(W.ALGO_DE, 64, 9, de_method=0, F_q16=65536, CR_q32=1 << 31), 4, 1)
     run("gemm10", W.OptParams(W.ALGO_PSO, 64, 10, w_q16=50000, c1_q16=70000, c2_q16=150000), 4, 1)
     run("gemm10", W.OptParams(W.ALGO_GA, 64, 11, mutation_chance=2, beta_b=1), 4, 1)
 

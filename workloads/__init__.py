@@ -184,8 +184,8 @@ def objective(n_valid: int, seed: int) -> np.ndarray:
 # PSO coefficients as Q16.16, GA mutation chance "one in X".
 # ---------------------------------------------------------------------------
 
-ALGO_DE, ALGO_PSO, ALGO_GA = 0, 1, 2
-ALGO_NAMES = {ALGO_DE: "DE", ALGO_PSO: "PSO", ALGO_GA: "GA"}
+ALGO_DE, ALGO_PSO, ALGO_GA, ALGO_FF = 0, 1, 2, 3
+ALGO_NAMES = {ALGO_DE: "DE", ALGO_PSO: "PSO", ALGO_GA: "GA", ALGO_FF: "Firefly"}
 
 
 @dataclasses.dataclass(frozen=True)
@@ -196,7 +196,7 @@ class OptParams:
     # DE (Table IV: F 0.7, CR 0.6, best1bin)
     F_q16: int = 45875                  # round(0.7 * 2**16)
     CR_q32: int = 2576980378            # round(0.6 * 2**32)
-    de_best: int = 1                    # 1 = best1bin, 0 = rand1bin
+    de_method: int = 1                    # 1 = best1bin, 0 = rand1bin
     # PSO (Table IV: w 0.5, c1 3.0, c2 0.5)
     w_q16: int = 32768
     c1_q16: int = 196608
@@ -204,6 +204,10 @@ class OptParams:
     # GA (Table IV: single_point, mutation chance 5); rank selection Beta(1, beta_b)
     mutation_chance: int = 5
     beta_b: int = 3
+    # Firefly (Table IV: B0 1.0, gamma 1.0, alpha 0.2)
+    ff_B0_q16: int = 65536
+    ff_gamma_q16: int = 65536
+    ff_alpha_q16: int = 13107           # round(0.2 * 2**16)
 
 
 def q16(x: float) -> int:
