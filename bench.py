@@ -75,7 +75,8 @@ WORKLOADS = {
 CONFIG_KEY = {"gemm": "gemm", "gemm10": "gemm10", "tiny": "tiny", "sparse16": "sparse16"}
 
 
-BUILD_KERNELS = ["k_table", "k_mask", "k_tile_sums", "k_scan_tiles", "k_compact", "k_boxes", "k_chunks",
+BUILD_KERNELS = ["k_scope_tables", "k_table", "k_patterns", "k_mask", "k_tile_sums", "k_scan_tiles", "k_group_off",
+                 "k_digit_rows", "k_compact", "k_boxes", "k_chunks",
                  "k_presence", "k_prevnext"]
 
 
@@ -386,6 +387,8 @@ def main():
     ap.add_argument("--serving-interarrival-ms", type=float, default=5.0)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-build-legs", action="store_true")
+    ap.add_argument("--legs", default="all", choices=["all", "build"],
+                    help="build: only the space-build and validity-query legs (for profiling)")
     ap.add_argument("--valid-mask-log2", type=int, default=26)
     ap.add_argument("--tuning", default=None,
                     help="items,min_boxes,grid_waves,mode: install this scan partitioning in the job instead of "
@@ -428,6 +431,19 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    if args.legs == "build":
+        # the space-build and validity-query legs alone (profiling runs)
+        out = {"build": [build_leg(ct, spec)] + ([build_leg(ct, W.sparse16())] if space_name != "sparse16" else []),
+               "valid_mask": valid_mask_leg(ct, 1 << args.valid_mask_log2)}
+        print(json.dumps(out), flush=True)
+        return
+
+    # the scan partitioning is tuned once, untimed and without kernel timing (whose events would
+    # distort the tuner's own measurements); the warmup and the timed steps reuse it
+    if tuning is None and gens:
+        run_job(ct, spec, runs, obj_t, gens)
+        torch.cuda.synchronize()
 
     # warmup: events around every kernel give the per-kernel breakdown and the dominant kernel
     per_kernel = {}

@@ -319,6 +319,35 @@ int space_prepare(const int64_t* values, const uint32_t* radices, uint32_t n_par
     uint64_t Ps = 1;
     uint32_t split = 0;
     while (split < n_params && Ps * radices[split] <= cap) Ps *= radices[split++];
+    // With inner patterns (below) the bitmask of the inner part costs no evaluation per
+    // configuration, so the split that needs the fewest evaluations -- one per prefix plus one
+    // per (context, inner configuration) -- wins when its patterns fit.
+    {
+        std::vector<uint32_t> used(n_cons, 0u);
+        for (uint32_t c = 0; c < n_cons; c++)
+            for (uint32_t pc = cons_offsets[c]; pc < cons_offsets[c + 1];) {
+                const uint32_t w = code[pc++];
+                if ((w & 0xFFu) == OP_PARAM) used[c] |= 1u << ((int32_t)w >> 8);
+                else if ((w & 0xFFu) == OP_CONST64) pc += 2;
+            }
+        uint64_t best = ~0ull, P = 1;
+        for (uint32_t sp = 1; sp < n_params; sp++) {
+            P *= radices[sp - 1];
+            if (P > (1ull << 24)) break;
+            const uint64_t I = (uint64_t)N / P;
+            if (I >= (1ull << 31)) continue;
+            const uint32_t pre = (uint32_t)((1ull << sp) - 1);
+            uint32_t cx = 0;
+            for (uint32_t c = 0; c < n_cons; c++)
+                if (used[c] & ~pre) cx |= used[c] & pre;
+            uint64_t nctx = 1;
+            for (uint32_t j = 0; j < sp; j++)
+                if (cx & (1u << j)) nctx *= radices[j];
+            if (nctx * ((I + 63) / 64 + 1) * 64 > kPatternBits) continue;
+            const uint64_t cost = P + nctx * I;
+            if (cost < best) { best = cost; split = sp; Ps = P; }
+        }
+    }
     S.split = split;
     S.P_s = Ps;
     S.I_s = S.N / Ps;
@@ -350,6 +379,60 @@ int space_prepare(const int64_t* values, const uint32_t* radices, uint32_t n_par
         code2.insert(code2.end(), code + cons_offsets[c], code + cons_offsets[c + 1]);
     }
     S.cons_off[n_cons] = (uint32_t)code2.size();
+    // scope tables for programs over few parameters (their scope: the parameters they read)
+    s->tab_meta.assign((size_t)std::max<uint32_t>(n_cons, 1) * CT_TAB_META, 0u);
+    s->tab_words = 0;
+    for (uint32_t k = 0; k < n_cons; k++) {
+        uint32_t* m = &s->tab_meta[(size_t)k * CT_TAB_META];
+        m[0] = ~0u;
+        uint32_t used = 0;
+        for (uint32_t pc = S.cons_off[k]; pc < S.cons_off[k + 1];) {
+            const uint32_t w = code2[pc++];
+            if ((w & 0xFFu) == OP_PARAM) used |= 1u << ((int32_t)w >> 8);
+            else if ((w & 0xFFu) == OP_CONST64) pc += 2;
+        }
+        std::vector<uint32_t> sc;
+        uint64_t bits = 1;
+        for (uint32_t j = 0; j < n_params; j++)
+            if (used & (1u << j)) { sc.push_back(j); bits *= radices[j]; }
+        if (sc.size() > CT_TAB_SCOPE || bits > CT_TAB_BITS) continue;
+        m[0] = (uint32_t)s->tab_words;
+        m[1] = (uint32_t)sc.size();
+        m[2] = (uint32_t)bits;
+        uint32_t st2 = 1;
+        for (size_t q = sc.size(); q-- > 0;) {           // last scope parameter fastest
+            m[4 + q] = (st2 << 5) | sc[q];
+            const uint32_t j = sc[q];
+            m[12 + j / 4] |= (st2 & 0xFFu) << (8 * (j % 4));
+            m[20 + j / 4] |= ((st2 >> 8) & 0xFFu) << (8 * (j % 4));
+            st2 *= radices[sc[q]];
+        }
+        s->tab_words += (bits + 63) / 64;
+    }
+    // inner patterns: the inner programs read the inner parameters and a few prefix parameters
+    // (the context); when every context's pattern over the inner configurations is small, the
+    // bitmask of a valid prefix is its context's pattern
+    {
+        uint32_t used = 0;
+        for (uint32_t k = S.n_pre; k < n_cons; k++)
+            for (uint32_t pc = S.cons_off[k]; pc < S.cons_off[k + 1];) {
+                const uint32_t w = code2[pc++];
+                if ((w & 0xFFu) == OP_PARAM) used |= 1u << ((int32_t)w >> 8);
+                else if ((w & 0xFFu) == OP_CONST64) pc += 2;
+            }
+        uint64_t nctx = 1;
+        S.n_cx = 0;
+        for (uint32_t j = 0; j < split; j++)
+            if (used & (1u << j)) { S.cx[S.n_cx++] = j; nctx *= radices[j]; }
+        uint64_t st2 = 1;
+        for (uint32_t q = S.n_cx; q-- > 0;) {
+            const uint32_t j = S.cx[q];
+            S.cx[q] = (uint32_t)(st2 << 5) | j;
+            st2 *= radices[j];
+        }
+        s->n_ctx = (split < n_params && nctx * ((S.I_s + 63) / 64 + 1) * 64 <= kPatternBits)
+                       ? nctx : 0;
+    }
     s->lds_values_bytes = (size_t)n_vals * sizeof(int64_t);
     s->code = std::move(code2);
     *out = s;
@@ -368,6 +451,14 @@ int space_realize(ct_space* s, hipStream_t st, uint64_t byte_limit) {
         return ct_fail(CT_EDEVICE, "ct_space_build: upload failed");
     s->dev.values = s->d_values;
     s->dev.code = s->d_code;
+    if (hipMalloc(&s->d_tab_meta, s->tab_meta.size() * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&s->d_tabs, std::max<uint64_t>(s->tab_words, 1) * sizeof(uint64_t)) != hipSuccess)
+        return ct_fail(CT_ENOMEM, "ct_space_build: hipMalloc failed");
+    if (hipMemcpyAsync(s->d_tab_meta, s->tab_meta.data(), s->tab_meta.size() * sizeof(uint32_t),
+                       hipMemcpyHostToDevice, st) != hipSuccess)
+        return ct_fail(CT_EDEVICE, "ct_space_build: upload failed");
+    s->dev.tab_meta = s->d_tab_meta;
+    s->dev.tabs = s->d_tabs;
     s->byte_limit = byte_limit;
     int rc = space_build_device(s, st);
     if (rc) return rc;
@@ -454,7 +545,7 @@ void ct_space_free(ct_space* s) {
     if (!s) return;
     (void)hipDeviceSynchronize();
     void* bufs[] = {s->d_values, s->d_code, s->d_prefix, s->d_words, s->d_lin, s->d_rows, s->d_prevnext,
-                    s->d_grp_off, s->d_dir8, s->d_boxes, s->d_dev};
+                    s->d_grp_off, s->d_dir8, s->d_boxes, s->d_dev, s->d_tab_meta, s->d_tabs};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete s;

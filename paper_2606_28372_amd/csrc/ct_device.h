@@ -16,6 +16,15 @@
 
 #define CT_DMAX 32        // parameters per space
 #define CT_STACK 16       // interpreter stack depth
+// Scope tables: a constraint that reads at most CT_TAB_SCOPE parameters whose value counts
+// multiply to at most CT_TAB_BITS is evaluated once per combination of those parameters into a
+// bit table; a configuration then tests one bit instead of running the program.
+#define CT_TAB_SCOPE 8
+#define CT_TAB_BITS 65536u
+#define CT_TAB_META 28    // u32 per program: word offset (~0: no table), scope size, table bits, 0,
+                          // (stride << 5) | parameter for each scope parameter [4..11], then the
+                          // table strides as bytes by row word: low bytes [12..19], high [20..27]
+                          // (a row's table index is two byte dot products per row word)
 
 struct DevSpace {
     uint32_t D;           // parameters
@@ -38,6 +47,10 @@ struct DevSpace {
     const int64_t* values;      // concatenated value tables
     const uint32_t* code;       // bytecode
     const uint64_t* prefix_words;  // prefix validity bits [ceil(P_s/64)]
+    uint32_t n_cx;              // context: prefix parameters read by programs [n_pre, n_cons)
+    uint32_t cx[CT_DMAX];       // (stride << 5) | parameter, last context parameter fastest
+    const uint32_t* tab_meta;   // [n_cons][CT_TAB_META] scope tables of the programs
+    const uint64_t* tabs;       // the tables' bits
     const uint64_t* lin;        // valid list: ascending linear indices
     const uint8_t* rows;        // valid list: digit rows [n_valid][R]
     const uint8_t* prevnext;    // [D][256][2] nearest present value index below/above (0xFF: none)
@@ -132,12 +145,16 @@ __device__ __forceinline__ uint32_t ct_below(uint32_t u, uint32_t n) {
 // ---------------------------------------------------------------------------
 // Rows: digits packed as bytes, digit j in byte j.
 // ---------------------------------------------------------------------------
+// The words of a row are a vector value, not an array: an index known only at run time becomes a
+// vector element extract/insert (register moves), where an indexed array would be placed in
+// scratch memory (a memory round trip per access).
+typedef uint32_t ct_u32x8 __attribute__((ext_vector_type(8)));
 struct Row {
-    uint32_t w[CT_DMAX / 4];
+    ct_u32x8 w;
     __device__ __forceinline__ uint32_t digit(uint32_t j) const { return (w[j >> 2] >> ((j & 3u) * 8u)) & 0xFFu; }
     __device__ __forceinline__ void set(uint32_t j, uint32_t d) {
-        uint32_t sh = (j & 3u) * 8u;
-        w[j >> 2] = (w[j >> 2] & ~(0xFFu << sh)) | (d << sh);
+        const uint32_t q = j >> 2, sh = (j & 3u) * 8u;
+        w[q] = (w[q] & ~(0xFFu << sh)) | (d << sh);
     }
 };
 
@@ -289,6 +306,37 @@ __device__ __forceinline__ bool ct_eval(const DevSpace& S, uint32_t c0, uint32_t
             }
         }
         ok &= !(err & 1u) && st[0] != 0;
+        if (!__any(ok)) break;
+    }
+    return ok;
+}
+
+// Programs [c0, c1) for one configuration: a table bit for programs with a scope table, the
+// interpreter for the others.  Same result as ct_eval: a table holds the program's value for
+// every combination of the parameters it reads, and no other digit can change it.  With
+// kInterp = false every program of the range must have a table: the kernel then carries no
+// interpreter (whose stack would put it in scratch memory).
+template <bool kInterp = true>
+__device__ __forceinline__ bool ct_valid(const DevSpace& S, uint32_t c0, uint32_t c1, const Row& dig,
+                                         const int64_t* __restrict__ vals) {
+    bool ok = true;
+    for (uint32_t c = c0; c < c1; ++c) {
+        const CT_GLOBAL uint32_t* m = gptr(S.tab_meta + c * CT_TAB_META);
+        const uint32_t off = m[0];
+        if (!kInterp || off != ~0u) {
+            uint32_t lo = 0, hi = 0;
+#pragma unroll
+            for (uint32_t q = 0; q < CT_DMAX / 4; ++q) {
+                if (q < S.R / 4) {
+                    lo = __builtin_amdgcn_udot4(dig.w[q], m[12 + q], lo, false);
+                    hi = __builtin_amdgcn_udot4(dig.w[q], m[20 + q], hi, false);
+                }
+            }
+            const uint32_t idx = lo + (hi << 8);
+            ok &= ((gld(S.tabs + off + (idx >> 6)) >> (idx & 63u)) & 1ull) != 0;
+        } else {
+            ok &= ct_eval(S, c, c + 1, dig, vals);
+        }
         if (!__any(ok)) break;
     }
     return ok;

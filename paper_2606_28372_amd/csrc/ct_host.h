@@ -51,12 +51,20 @@ struct ct_space {
     uint64_t* d_grp_off = nullptr;
     uint16_t* d_dir8 = nullptr;
     uint8_t* d_boxes = nullptr;
+    uint32_t* d_tab_meta = nullptr;   // scope tables: per program CT_TAB_META words
+    uint64_t* d_tabs = nullptr;
+    std::vector<uint32_t> tab_meta;
+    uint64_t tab_words = 0;
+    uint64_t n_ctx = 0;               // combinations of the context parameters (0: no inner patterns)
     size_t lds_values_bytes = 0;      // dynamic LDS for the value tables
     std::vector<uint32_t> code;       // constraint programs, prefix-only ones first
     uint64_t byte_limit = 0;          // build: fail with CT_ENOMEM (n_valid set) if the space would exceed it
     bool over_limit = false;          // the last build stopped at byte_limit
     uint64_t dev_bytes = 0;           // device bytes held once built
 };
+
+// Largest table of inner patterns (bits over every context and inner configuration) the build uses.
+constexpr uint64_t kPatternBits = 1ull << 27;
 
 // api.cpp: host-side validation and layout, then device build (optionally under a byte limit)
 int space_prepare(const int64_t* values, const uint32_t* radices, uint32_t n_params, const uint32_t* code,

@@ -33,6 +33,108 @@ __device__ __forceinline__ void load_values_lds(const DevSpace& S, int64_t* lds,
     __syncthreads();
 }
 
+// What evaluation and decoding read for every configuration, copied into LDS at the start of a
+// kernel: the value tables, the scope tables (when they fit), the programs' table descriptors and
+// the radices with their division magic numbers.  Read from the kernel argument block instead,
+// each per-digit or per-program field would be a dependent scalar load inside the loops.
+constexpr uint32_t kTabLdsWords = 4096;       // scope tables up to 32 KiB go to LDS
+constexpr uint64_t kRowTableBytes = 16ull << 20;   // prefix / inner digit-row tables of the compaction
+bool row_tables(const DevSpace& S) {
+    return S.split < S.D && S.P_s * S.R <= kRowTableBytes && S.I_s * S.R <= kRowTableBytes;
+}
+
+struct LdsCtx {
+    const CT_LDS int64_t* vals;
+    const CT_LDS uint32_t* meta;
+    const CT_LDS uint32_t* rad;
+    const CT_LDS uint32_t* mm;
+    const CT_LDS uint32_t* ml;
+    const CT_LDS uint64_t* tabs_l;            // LDS copy of the scope tables, or null
+    const CT_GLOBAL uint64_t* tabs_g;
+    const CT_LDS uint32_t* rm1;               // per row word: radix - 1 of its four digits (255 past D)
+    uint32_t nw;                              // row words (R / 4)
+};
+
+// Scope-table words a kernel copies into LDS (0: it reads them from device memory), and the LDS
+// bytes of the context (the host sizes the launch with them)
+uint32_t ctx_tab_lds(const ct_space* s) {
+    const size_t vb = s->values.size() * 8;
+    return s->tab_words <= kTabLdsWords && vb + s->tab_words * 8 <= 48u * 1024u ? (uint32_t)s->tab_words : 0u;
+}
+size_t ctx_lds_bytes(const ct_space* s) {
+    return s->values.size() * 8 + (size_t)ctx_tab_lds(s) * 8 +
+           (size_t)std::max<uint32_t>(s->dev.n_cons, 1) * CT_TAB_META * 4 + 3 * CT_DMAX * 4 + CT_DMAX;
+}
+
+__device__ __forceinline__ LdsCtx load_ctx(const DevSpace& S, uint32_t n_vals, uint32_t tab_words) {
+    extern __shared__ int64_t lds_ctx[];
+    const bool tl = tab_words != 0;
+    CT_LDS int64_t* v = (CT_LDS int64_t*)lds_ctx;
+    CT_LDS uint64_t* t = (CT_LDS uint64_t*)(v + n_vals);
+    CT_LDS uint32_t* m = (CT_LDS uint32_t*)(t + (tl ? tab_words : 0u));
+    CT_LDS uint32_t* d = m + (S.n_cons ? S.n_cons : 1u) * CT_TAB_META;
+    for (uint32_t i = threadIdx.x; i < n_vals; i += blockDim.x) v[i] = S.values[i];
+    if (tl)
+        for (uint32_t i = threadIdx.x; i < tab_words; i += blockDim.x) t[i] = S.tabs[i];
+    for (uint32_t i = threadIdx.x; i < S.n_cons * CT_TAB_META; i += blockDim.x) m[i] = S.tab_meta[i];
+    CT_LDS uint32_t* rm = d + 3 * CT_DMAX;
+    for (uint32_t i = threadIdx.x; i < CT_DMAX; i += blockDim.x) {
+        d[i] = i < S.D ? S.radix[i] : 1u;
+        d[CT_DMAX + i] = i < S.D ? S.mag_m[i] : 0u;
+        d[2 * CT_DMAX + i] = i < S.D ? S.mag_l[i] : 0u;
+    }
+    for (uint32_t q = threadIdx.x; q < CT_DMAX / 4; q += blockDim.x) {
+        uint32_t w = 0;
+        for (uint32_t b = 0; b < 4; ++b) {
+            const uint32_t j = 4 * q + b;
+            w |= (j < S.D ? S.radix[j] - 1u : 255u) << (8 * b);
+        }
+        rm[q] = w;
+    }
+    __syncthreads();
+    return LdsCtx{v, m, d, d + CT_DMAX, d + 2 * CT_DMAX, tl ? t : nullptr, gptr(S.tabs), rm, S.R / 4};
+}
+
+// digits [j0, j1) of x (x < prod_{j0<=j<j1} radix[j]), last digit fastest, from the LDS context
+__device__ __forceinline__ void decode_ctx(const LdsCtx& C, uint32_t x, uint32_t j0, uint32_t j1, Row& r) {
+    for (uint32_t j = j1; j-- > j0;) {
+        const uint32_t q = ct_udiv(x, C.mm[j], C.ml[j]);
+        r.set(j, x - q * C.rad[j]);
+        x = q;
+    }
+}
+
+// ct_valid with the descriptors and (when they fit) the tables in LDS; every program's scope
+// parameters are read at once (up to CT_TAB_SCOPE, predicated).  kInterp = false: every program
+// of the range has a table and no interpreter is compiled in.
+template <bool kInterp>
+__device__ __forceinline__ bool valid_ctx(const DevSpace& S, const LdsCtx& C, uint32_t c0, uint32_t c1, const Row& dig) {
+    bool ok = true;
+    for (uint32_t c = c0; c < c1; ++c) {
+        const CT_LDS uint32_t* m = C.meta + c * CT_TAB_META;
+        const uint32_t off = __builtin_amdgcn_readfirstlane(m[0]);
+        if (!kInterp || off != ~0u) {
+            // the table index sum_j digit_j * stride_j as byte dot products: strides are below
+            // 2^16, low and high bytes apart, zero for parameters outside the scope
+            uint32_t lo = 0, hi = 0;
+#pragma unroll
+            for (uint32_t q = 0; q < CT_DMAX / 4; ++q) {
+                if (q < C.nw) {
+                    lo = __builtin_amdgcn_udot4(dig.w[q], __builtin_amdgcn_readfirstlane(m[12 + q]), lo, false);
+                    hi = __builtin_amdgcn_udot4(dig.w[q], __builtin_amdgcn_readfirstlane(m[20 + q]), hi, false);
+                }
+            }
+            const uint32_t idx = lo + (hi << 8);
+            const uint64_t word = C.tabs_l ? C.tabs_l[off + (idx >> 6)] : C.tabs_g[off + (idx >> 6)];
+            ok &= ((word >> (idx & 63u)) & 1ull) != 0;
+        } else {
+            ok &= ct_eval(S, c, c + 1, dig, (const int64_t*)C.vals);
+            if (!__any(ok)) break;
+        }
+    }
+    return ok;
+}
+
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -56,35 +158,186 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t lane) {
 // the valid configurations of each 4096-index group are added to its (zeroed) counter.
 constexpr uint32_t kSubWords = 8;
 
-__global__ __launch_bounds__(kBlock) void k_table(DevSpace S, uint64_t total, uint32_t dlim, uint32_t c1,
-                                                  uint32_t n_vals, uint64_t n_words, uint64_t* __restrict__ words,
-                                                  uint32_t* __restrict__ group_counts) {
+// Scope tables: word w of the tables (every program with a table owns a run of whole words) is
+// the ballot of the program over 64 consecutive combinations of its scope parameters (last one
+// fastest), the other digits 0; combinations past the table's size evaluate combination 0 and
+// are masked off.
+__global__ __launch_bounds__(kBlock) void k_scope_tables(DevSpace S, uint32_t n_vals, uint64_t total_words,
+                                                         uint64_t* __restrict__ tabs) {
     extern __shared__ int64_t lds_vals[];
     load_values_lds(S, lds_vals, n_vals);
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t n_units = (total + 64u * kSubWords - 1) / (64u * kSubWords);
+    const uint64_t stride = (uint64_t)gridDim.x * kWavesPerBlock;
+    for (uint64_t w = (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); w < total_words; w += stride) {
+        // the program owning word w: the last one with a table starting at or before it
+        uint32_t c = 0;
+        for (uint32_t k = 0; k < S.n_cons; ++k) {
+            const uint32_t off = S.tab_meta[k * CT_TAB_META];
+            if (off != ~0u && off <= w) c = k;
+        }
+        const uint32_t* m = S.tab_meta + c * CT_TAB_META;
+        const uint64_t t0 = (w - m[0]) * 64u + lane;
+        const bool in = t0 < m[2];
+        uint32_t t = in ? (uint32_t)t0 : 0u;
+        Row r;
+#pragma unroll
+        for (int q = 0; q < CT_DMAX / 4; ++q) r.w[q] = 0;
+        for (uint32_t k = m[1]; k-- > 0;) {
+            const uint32_t j = m[4 + k] & 31u;
+            const uint32_t q = ct_udiv(t, S.mag_m[j], S.mag_l[j]);
+            r.set(j, t - q * S.radix[j]);
+            t = q;
+        }
+        const bool ok = ct_eval(S, c, c + 1, r, lds_vals) && in;
+        const uint64_t b = __ballot(ok);
+        if (lane == 0) tabs[w] = b;
+    }
+}
+
+// `sub` words per wave (at most 64); with pfx_ctx, also each index's context number (the mixed-
+// radix number of its context digits) if it is valid, else ~0 (the prefix pass of the patterns).
+template <bool TI>
+__global__ __launch_bounds__(kBlock) void k_table(DevSpace S, uint64_t total, uint32_t dlim, uint32_t c1,
+                                                  uint32_t n_vals, uint64_t n_words, uint64_t* __restrict__ words,
+                                                  uint32_t* __restrict__ group_counts, uint32_t sub,
+                                                  uint32_t* __restrict__ pfx_ctx, uint32_t tab_words) {
+    const LdsCtx C = load_ctx(S, n_vals, tab_words);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t n_units = (total + 64u * sub - 1) / (64u * sub);
     const uint64_t stride = (uint64_t)gridDim.x * kWavesPerBlock;
     for (uint64_t u = (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); u < n_units; u += stride) {
-        const uint64_t base = u * 64u * kSubWords;
+        const uint64_t base = u * 64u * sub;
         uint64_t mine = 0;
-        for (uint32_t k = 0; k < kSubWords; ++k) {
+        for (uint32_t k = 0; k < sub; ++k) {
             const uint64_t x = base + k * 64u + lane;
             bool ok = x < total;
             if (__any(ok)) {
                 Row r;
 #pragma unroll
                 for (int q = 0; q < CT_DMAX / 4; ++q) r.w[q] = 0;
-                decode_range(S, (uint32_t)(ok ? x : 0), 0, dlim, r);
-                ok = ok && ct_eval(S, 0, c1, r, lds_vals);
+                decode_ctx(C, (uint32_t)(ok ? x : 0), 0, dlim, r);
+                const bool in = ok;
+                ok = ok && valid_ctx<!TI>(S, C, 0, c1, r);
+                if (pfx_ctx && in) {
+                    uint32_t ctx = 0;
+                    for (uint32_t q = 0; q < S.n_cx; ++q) ctx += r.digit(S.cx[q] & 31u) * (S.cx[q] >> 5);
+                    pfx_ctx[x] = ok ? ctx : ~0u;
+                }
             }
             const uint64_t b = __ballot(ok);
             if (lane == k) mine = b;
         }
-        const uint64_t w = u * kSubWords + lane;
-        if (lane < kSubWords && w < n_words) words[w] = mine;
+        const uint64_t w = u * sub + lane;
+        if (lane < sub && w < n_words) words[w] = mine;
         if (group_counts) {
-            const uint32_t c = wave_sum(lane < kSubWords ? (uint32_t)__popcll(mine) : 0u);
+            const uint32_t c = wave_sum(lane < sub ? (uint32_t)__popcll(mine) : 0u);
             if (lane == 0 && c) atomicAdd(&group_counts[base / 4096u], c);
+        }
+    }
+}
+
+// Inner patterns: for each context c (a combination of the prefix parameters the inner programs
+// read) the bits of the inner programs over every inner configuration t in [0, I_s), in pw words
+// per context (the last one, past I_s, is zero).  One wave per (context, word).
+template <bool TI>
+__global__ __launch_bounds__(kBlock) void k_patterns(DevSpace S, uint32_t n_vals, uint64_t n_ctx, uint32_t pw,
+                                                     uint64_t* __restrict__ pats, uint32_t tab_words) {
+    const LdsCtx C = load_ctx(S, n_vals, tab_words);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t total = n_ctx * pw;
+    const uint64_t stride = (uint64_t)gridDim.x * kWavesPerBlock;
+    for (uint64_t it = (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); it < total; it += stride) {
+        const uint32_t c = (uint32_t)(it / pw), wi = (uint32_t)(it % pw);
+        const uint64_t t0 = (uint64_t)wi * 64u + lane;
+        const bool in = t0 < S.I_s;
+        Row r;
+#pragma unroll
+        for (int q = 0; q < CT_DMAX / 4; ++q) r.w[q] = 0;
+        for (uint32_t q = 0; q < S.n_cx; ++q) {
+            const uint32_t j = S.cx[q] & 31u;
+            r.set(j, (c / (S.cx[q] >> 5)) % S.radix[j]);
+        }
+        decode_ctx(C, in ? (uint32_t)t0 : 0u, S.split, S.D, r);
+        const bool ok = in && valid_ctx<!TI>(S, C, S.n_pre, S.n_cons, r);
+        const uint64_t b = __ballot(ok);
+        if (lane == 0) pats[it] = b;
+    }
+}
+
+// Bits [off, off + len) of a pattern (len in 1..64); patterns end with a zero word.
+__device__ __forceinline__ uint64_t pat_bits(const CT_GLOBAL uint64_t* pat, uint32_t off, uint32_t len) {
+    const uint32_t q = off >> 6, sh = off & 63u;
+    uint64_t v = pat[q] >> sh;
+    if (sh && sh + len > 64u) v |= pat[q + 1] << (64u - sh);
+    return len == 64u ? v : v & ((1ull << len) - 1ull);
+}
+
+// The bitmask from the patterns: lane l of a wave builds word l of kMaskUnroll groups at once
+// (independent load chains, so the latency of the context and pattern loads overlaps) from the
+// prefixes each word covers -- a valid prefix contributes its context's pattern, an invalid one
+// zeros -- then each group's count.  Words past the space are zero.
+constexpr uint32_t kMaskUnroll = 4;
+
+__device__ __forceinline__ uint64_t pattern_word(const DevSpace& S, uint64_t L0, uint64_t p, uint32_t off,
+                                                 const CT_GLOBAL uint32_t* C, const CT_GLOBAL uint64_t* P, uint32_t pw) {
+    uint64_t word = 0;
+    if (L0 < S.N) {
+        const uint64_t Is = S.I_s;
+        const uint64_t L1 = L0 + 64u < S.N ? L0 + 64u : S.N;
+        uint64_t L = L0;
+        while (L < L1) {
+            const uint32_t len = (uint32_t)min<uint64_t>(Is - off, L1 - L);
+            const uint32_t ctx = C[p];
+            if (ctx != ~0u) word |= pat_bits(P + (uint64_t)ctx * pw, off, len) << (uint32_t)(L - L0);
+            L += len;
+            ++p;
+            off = 0;
+        }
+    }
+    return word;
+}
+
+// Only the groups that k_mask_classify listed (those spanning a valid prefix); it wrote the others
+// as zeros with a count of 0.
+__global__ __launch_bounds__(kBlock) void k_mask_pattern(DevSpace S, uint64_t* __restrict__ words,
+                                                         uint32_t* __restrict__ group_counts,
+                                                         const uint32_t* __restrict__ todo,
+                                                         const uint32_t* __restrict__ n_todo,
+                                                         const uint32_t* __restrict__ pfx_ctx,
+                                                         const uint64_t* __restrict__ pats, uint32_t pw) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t waves = (uint64_t)gridDim.x * kWavesPerBlock;
+    const uint64_t Is = S.I_s;
+    const CT_GLOBAL uint64_t* P = gptr(pats);
+    const CT_GLOBAL uint32_t* C = gptr(pfx_ctx);
+    const uint64_t n_items = *n_todo;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); i0 < n_items;
+         i0 += waves * kMaskUnroll) {
+        uint64_t w[kMaskUnroll];
+        uint64_t gs[kMaskUnroll];
+#pragma unroll
+        for (uint32_t u = 0; u < kMaskUnroll; ++u) {
+            const uint64_t it = i0 + u * waves;
+            w[u] = 0;
+            gs[u] = it < n_items ? todo[it] : 0;
+            if (it < n_items) {
+                const uint64_t g = gs[u];
+                const uint64_t G0 = g * 4096u;
+                const uint64_t p0 = G0 / Is;                         // wave-uniform
+                const uint64_t L0 = G0 + (uint64_t)lane * 64u;
+                const uint32_t rel = (uint32_t)(L0 - p0 * Is);       // < 4096 + I_s
+                const uint32_t dq = ct_udiv(rel, S.Is_m, S.Is_l);
+                w[u] = pattern_word(S, L0, p0 + dq, rel - dq * (uint32_t)Is, C, P, pw);
+            }
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kMaskUnroll; ++u) {
+            if (i0 + u * waves < n_items) {
+                const uint64_t g = gs[u];
+                words[g * 64u + lane] = w[u];
+                const uint32_t c = wave_sum((uint32_t)__popcll(w[u]));
+                if (lane == 0) group_counts[g] = c;
+            }
         }
     }
 }
@@ -133,11 +386,12 @@ __global__ __launch_bounds__(kBlock) void k_mask_classify(DevSpace S, uint64_t n
 // k_mask_eval: work unit = kSubWords words of a listed group per wave; in each step the lanes
 // take 64 consecutive configurations, skip the ones whose prefix is invalid, and run the programs
 // that read inner parameters on the rest.  Counts are added to the group's counter.
+template <bool TI>
 __global__ __launch_bounds__(kBlock) void k_mask_eval(DevSpace S, uint32_t n_vals, uint64_t n_words,
                                                       uint64_t* __restrict__ words, uint32_t* __restrict__ group_counts,
-                                                      const uint32_t* __restrict__ todo, const uint32_t* __restrict__ n_todo) {
-    extern __shared__ int64_t lds_vals[];
-    load_values_lds(S, lds_vals, n_vals);
+                                                      const uint32_t* __restrict__ todo, const uint32_t* __restrict__ n_todo,
+                                                      uint32_t tab_words) {
+    const LdsCtx C = load_ctx(S, n_vals, tab_words);
     const uint32_t lane = threadIdx.x & 63u;
     constexpr uint32_t kUnits = 64u / kSubWords;
     const uint64_t total = (uint64_t)(*n_todo) * kUnits;
@@ -163,9 +417,9 @@ __global__ __launch_bounds__(kBlock) void k_mask_eval(DevSpace S, uint32_t n_val
                 Row r;
 #pragma unroll
                 for (int t = 0; t < CT_DMAX / 4; ++t) r.w[t] = 0;
-                decode_range(S, ok ? (uint32_t)p : 0u, 0, S.split, r);
-                decode_range(S, ok ? inner : 0u, S.split, S.D, r);
-                ok = ok && ct_eval(S, S.n_pre, S.n_cons, r, lds_vals);
+                decode_ctx(C, ok ? (uint32_t)p : 0u, 0, S.split, r);
+                decode_ctx(C, ok ? inner : 0u, S.split, S.D, r);
+                ok = ok && valid_ctx<!TI>(S, C, S.n_pre, S.n_cons, r);
             }
             const uint64_t b = __ballot(ok);
             if (lane == k) mine = b;
@@ -219,28 +473,77 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const uint64_t* __restrict_
     if (threadIdx.x == 0) tile_off[n_tiles] = carry;
 }
 
-// Ascending valid list from the bitmask: one group per wave.
-__global__ __launch_bounds__(kBlock) void k_compact(DevSpace S, const uint64_t* __restrict__ words, uint64_t n_words,
-                                                    const uint32_t* __restrict__ counts,
-                                                    const uint64_t* __restrict__ tile_off, uint64_t n_groups,
-                                                    uint64_t* __restrict__ lin, uint8_t* __restrict__ rows,
-                                                    uint64_t* __restrict__ grp_off, uint16_t* __restrict__ dir8) {
-    __shared__ uint64_t emit[kWavesPerBlock][kEmit];
+// Group offsets: one block per scan tile, one thread per group; the offset of group g is its
+// tile's offset plus the counts of the tile's earlier groups.  Groups holding valid
+// configurations are listed (in any order) for the compaction.
+__global__ __launch_bounds__(kTileGroups) void k_group_off(const uint32_t* __restrict__ counts, uint64_t n_groups,
+                                                           const uint64_t* __restrict__ tile_off,
+                                                           uint64_t* __restrict__ grp_off,
+                                                           uint32_t* __restrict__ busy, uint32_t* __restrict__ n_busy) {
+    __shared__ uint32_t part[kTileGroups / 64];
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
-    const uint64_t g = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
-    if (g >= n_groups) return;
-    const uint64_t tile = g / kTileGroups;
-    // offset of this group = tile offset + counts of earlier groups in the tile
+    const uint64_t g = (uint64_t)blockIdx.x * kTileGroups + threadIdx.x;
+    const uint32_t c = g < n_groups ? counts[g] : 0u;
+    const uint32_t ex = wave_excl_scan(c, lane);
+    if (lane == 63) part[wv] = ex + c;
+    __syncthreads();
     uint32_t before = 0;
-    for (uint64_t t = tile * kTileGroups + lane; t < g; t += 64) before += counts[t];
-    const uint64_t base = tile_off[tile] + wave_sum(before);
+    for (uint32_t k = 0; k < wv; ++k) before += part[k];
+    if (g < n_groups) grp_off[g] = tile_off[blockIdx.x] + before + ex;
+    const uint64_t nz = __ballot(c != 0);
+    uint32_t at = 0;
+    if (lane == 0 && nz) at = atomicAdd(n_busy, (uint32_t)__popcll(nz));
+    at = __shfl(at, 0, 64);
+    if (c) busy[at + (uint32_t)__popcll(nz & ((1ull << lane) - 1ull))] = (uint32_t)g;
+}
+
+// Digit rows of the numbers [0, n) over parameters [j0, j1) (the others zero): the prefix rows
+// (j0 = 0) and the inner rows (j0 = split) that the compaction ORs together.
+__global__ __launch_bounds__(kBlock) void k_digit_rows(DevSpace S, uint64_t n, uint32_t j0, uint32_t j1,
+                                                       uint8_t* __restrict__ out) {
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (uint64_t)gridDim.x * blockDim.x) {
+        Row r;
+#pragma unroll
+        for (int q = 0; q < CT_DMAX / 4; ++q) r.w[q] = 0;
+        decode_range(S, (uint32_t)t, j0, j1, r);
+        row_store(r, out + t * S.R, S.R);
+    }
+}
+
+// Ascending valid list from the bitmask: one listed group per wave (waves loop over the list),
+// at the offset the scan gave it.  The rank directory's entries of empty groups are zero.  A
+// configuration's row is its prefix row OR its inner row when both tables are given, else its
+// digits are decoded.
+__global__ __launch_bounds__(kBlock) void k_compact(DevSpace S, const uint64_t* __restrict__ words, uint64_t n_words,
+                                                    const uint32_t* __restrict__ busy, const uint32_t* __restrict__ n_busy,
+                                                    const uint64_t* __restrict__ grp_off,
+                                                    uint64_t* __restrict__ lin, uint8_t* __restrict__ rows,
+                                                    uint16_t* __restrict__ dir8, const uint8_t* __restrict__ prow,
+                                                    const uint8_t* __restrict__ irow) {
+    __shared__ uint64_t emit[kWavesPerBlock][kEmit];
+    __shared__ uint32_t dig3[3 * CT_DMAX];
+    for (uint32_t i = threadIdx.x; i < CT_DMAX; i += blockDim.x) {
+        dig3[i] = i < S.D ? S.radix[i] : 1u;
+        dig3[CT_DMAX + i] = i < S.D ? S.mag_m[i] : 0u;
+        dig3[2 * CT_DMAX + i] = i < S.D ? S.mag_l[i] : 0u;
+    }
+    __syncthreads();
+    LdsCtx C{};
+    C.rad = (const CT_LDS uint32_t*)dig3;
+    C.mm = C.rad + CT_DMAX;
+    C.ml = C.rad + 2 * CT_DMAX;
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint32_t nb = *n_busy;
+    for (uint32_t it = blockIdx.x * kWavesPerBlock + wv; it < nb; it += gridDim.x * kWavesPerBlock) {
+    const uint64_t g = busy[it];
+    const uint64_t base = grp_off[g];
     const uint64_t wi = g * 64u + lane;
+    const uint64_t p0 = g * 4096u / S.I_s;                  // prefix of the group's first index
     uint64_t rem = wi < n_words ? words[wi] : 0ull;
     const uint32_t c = (uint32_t)__popcll(rem);
     const uint32_t excl = wave_excl_scan(c, lane);
     const uint32_t total = wave_sum(c);
-    // rank directory: offset of the group, and of each 8-word block inside it
-    if (lane == 0) grp_off[g] = base;
+    // rank directory: offset of each 8-word block inside the group
     if ((lane & 7u) == 0 && wi < n_words) dir8[wi >> 3] = (uint16_t)excl;
     uint32_t e = excl;                       // list index (within the group) of the lane's next bit
     for (uint32_t cs = 0; cs < total; cs += kEmit) {
@@ -258,8 +561,24 @@ __global__ __launch_bounds__(kBlock) void k_compact(DevSpace S, const uint64_t* 
         for (uint32_t i = lane; i < nchunk; i += 64) {
             const uint64_t L = emit[wv][i];
             const uint64_t pos = base + cs + i;
+            // digits from the prefix and inner parts, relative to the group's first prefix
+            // (L - p0 I_s < 4096 + I_s: 32-bit division by the inner size's magic number)
+            const uint32_t rel = (uint32_t)(L - p0 * S.I_s);
+            const uint32_t dq = ct_udiv(rel, S.Is_m, S.Is_l);
+            const uint32_t inner = rel - dq * (uint32_t)S.I_s;
             Row r;
-            decode_lin(S, L, r);
+            if (prow) {
+                Row a, b;
+                row_load(a, prow + (p0 + dq) * S.R, S.R);
+                row_load(b, irow + (uint64_t)inner * S.R, S.R);
+#pragma unroll
+                for (int q = 0; q < CT_DMAX / 4; ++q) r.w[q] = a.w[q] | b.w[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < CT_DMAX / 4; ++q) r.w[q] = 0;
+                decode_ctx(C, (uint32_t)(p0 + dq), 0, S.split, r);
+                decode_ctx(C, inner, S.split, S.D, r);
+            }
             lin[pos] = L;
             row_store(r, rows + pos * S.R, S.R);
         }
@@ -267,30 +586,76 @@ __global__ __launch_bounds__(kBlock) void k_compact(DevSpace S, const uint64_t* 
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    }
 }
 
-// Per 64-row block of the valid list, the smallest and the largest value
-// index of every parameter (a bounding box used to prune repair scans).
-__global__ __launch_bounds__(kBlock) void k_boxes(DevSpace S, uint8_t* __restrict__ boxes) {
+// Per-byte minimum / maximum of four packed digits (two lanes of 16 bits each for the even and
+// the odd bytes).
+typedef unsigned short ct_us2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ ct_us2 as_us2(uint32_t x) { return __builtin_bit_cast(ct_us2, x); }
+__device__ __forceinline__ uint32_t as_u32(ct_us2 x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ __forceinline__ uint32_t byte_min(uint32_t a, uint32_t b) {
+    const uint32_t m = 0x00FF00FFu;
+    const uint32_t e = as_u32(__builtin_elementwise_min(as_us2(a & m), as_us2(b & m)));
+    const uint32_t o = as_u32(__builtin_elementwise_min(as_us2((a >> 8) & m), as_us2((b >> 8) & m)));
+    return e | (o << 8);
+}
+__device__ __forceinline__ uint32_t byte_max(uint32_t a, uint32_t b) {
+    const uint32_t m = 0x00FF00FFu;
+    const uint32_t e = as_u32(__builtin_elementwise_max(as_us2(a & m), as_us2(b & m)));
+    const uint32_t o = as_u32(__builtin_elementwise_max(as_us2((a >> 8) & m), as_us2((b >> 8) & m)));
+    return e | (o << 8);
+}
+
+// Per 64-row block of the valid list (a box), the smallest and the largest value index of every
+// parameter (a bounding box used to prune repair scans), four digits per word; and which value
+// indices of each parameter occur in the list (for the "adjacent" neighbour rule), collected per
+// block in LDS -- each wave marks the distinct values of its box, one per round -- and OR-ed
+// into present[D][8], skipping the atomic when the bits are there already.  One box per wave.
+__global__ __launch_bounds__(kBlock) void k_boxes(DevSpace S, uint32_t* __restrict__ boxes32,
+                                                  uint32_t* __restrict__ present) {
+    __shared__ uint32_t pres[CT_DMAX * 8];
+    for (uint32_t i = threadIdx.x; i < CT_DMAX * 8; i += blockDim.x) pres[i] = 0;
+    __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t nw = S.R / 4;
     const uint64_t sb = (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (sb >= S.n_sub) return;
-    const uint64_t v = sb * 64u + lane;
-    const bool in = v < S.n_valid;
-    Row r;
-    row_load(r, S.rows + (in ? v : sb * 64u) * S.R, S.R);
-    for (uint32_t j = 0; j < S.R; ++j) {
-        uint32_t d = j < S.D ? r.digit(j) : 0u;
-        uint32_t lo = d, hi = d;
+    if (sb < S.n_sub) {
+        const uint64_t v = sb * 64u + lane;
+        const bool in = v < S.n_valid;
+        Row r;
+        row_load(r, S.rows + (in ? v : sb * 64u) * S.R, S.R);    // past the end: the box's first row
+        uint32_t outw = 0;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, 64));
-            hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
+        for (uint32_t q = 0; q < CT_DMAX / 4; ++q) {
+            if (q < nw) {
+                uint32_t lo = r.w[q], hi = r.w[q];
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    lo = byte_min(lo, (uint32_t)__shfl_xor((int)lo, o, 64));
+                    hi = byte_max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
+                }
+                if (lane == q) outw = lo;
+                if (lane == nw + q) outw = hi;
+            }
         }
-        if (lane == 0) {
-            boxes[sb * 2u * S.R + j] = (uint8_t)lo;
-            boxes[sb * 2u * S.R + S.R + j] = (uint8_t)hi;
+        if (lane < 2 * nw) boxes32[sb * 2u * nw + lane] = outw;
+        for (uint32_t j = 0; j < S.D; ++j) {
+            const uint32_t d = r.digit(j);
+            uint64_t left = __ballot(in);
+            while (left) {
+                const uint32_t src = (uint32_t)(__ffsll((long long)left) - 1);
+                const uint32_t val = (uint32_t)__shfl((int)d, (int)src, 64);
+                if (lane == src) atomicOr(&pres[j * 8u + (val >> 5)], 1u << (val & 31u));
+                left &= ~__ballot(d == val);
+            }
         }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < S.D * 8u; i += blockDim.x) {
+        const uint32_t m = pres[i];
+        if (m && (__hip_atomic_load(&present[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & m) != m)
+            atomicOr(&present[i], m);
     }
 }
 
@@ -319,44 +684,46 @@ __global__ __launch_bounds__(kBlock) void k_chunks(DevSpace S, uint8_t* __restri
     }
 }
 
-// Which value indices of each parameter occur in some solution, then the
-// nearest present index below/above each index ("adjacent" neighbour rule).
-__global__ __launch_bounds__(kBlock) void k_presence(DevSpace S, uint32_t* __restrict__ present /*[D][8]*/) {
-    __shared__ uint32_t loc[CT_DMAX * 8];
-    for (uint32_t i = threadIdx.x; i < CT_DMAX * 8; i += blockDim.x) loc[i] = 0;
-    __syncthreads();
-    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < S.n_valid;
-         v += (uint64_t)gridDim.x * blockDim.x) {
-        Row r;
-        row_load(r, S.rows + v * S.R, S.R);
-        for (uint32_t j = 0; j < S.D; ++j) {
-            uint32_t d = r.digit(j);
-            atomicOr(&loc[j * 8 + (d >> 5)], 1u << (d & 31u));
-        }
+// The nearest present value index below / above every index of every parameter ("adjacent"
+// neighbour rule; 0xFF: none), after OR-ing the boxes kernel's per-block presence words.  One
+// block of 1024 threads: four threads per presence word split the blocks between them.
+__global__ __launch_bounds__(1024) void k_prevnext(uint32_t D, const uint32_t* __restrict__ partial, uint32_t n_part,
+                                                   uint8_t* __restrict__ pn) {
+    __shared__ uint32_t part4[4][CT_DMAX * 8];
+    __shared__ uint32_t pres[CT_DMAX * 8];
+    const uint32_t nwd = D * 8u;
+    {
+        const uint32_t i = threadIdx.x & 255u, k = threadIdx.x >> 8;
+        uint32_t v = 0;
+        if (i < nwd)
+            for (uint32_t b = k; b < n_part; b += 4) v |= partial[(uint64_t)b * nwd + i];
+        part4[k][i] = v;
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < S.D * 8; i += blockDim.x)
-        if (loc[i]) atomicOr(&present[i], loc[i]);
+    if (threadIdx.x < 256) pres[threadIdx.x] = part4[0][threadIdx.x] | part4[1][threadIdx.x] | part4[2][threadIdx.x] | part4[3][threadIdx.x];
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < D * 256u; t += blockDim.x) {
+        const uint32_t j = t >> 8, k = t & 255u, kw = k >> 5, kb = k & 31u;
+        uint32_t prev = 0xFF, next = 0xFF;
+        for (int w = (int)kw; w >= 0; --w) {
+            uint32_t m = pres[j * 8u + (uint32_t)w];
+            if ((uint32_t)w == kw) m &= (1u << kb) - 1u;
+            if (m) { prev = (uint32_t)w * 32u + 31u - (uint32_t)__clz(m); break; }
+        }
+        for (uint32_t w = kw; w < 8; ++w) {
+            uint32_t m = pres[j * 8u + w];
+            if (w == kw) m &= kb == 31u ? 0u : ~((2u << kb) - 1u);
+            if (m) { next = w * 32u + (uint32_t)__ffs(m) - 1u; break; }
+        }
+        pn[t * 2 + 0] = (uint8_t)prev;
+        pn[t * 2 + 1] = (uint8_t)next;
+    }
 }
 
-__global__ void k_prevnext(uint32_t D, const uint32_t* __restrict__ present, uint8_t* __restrict__ pn) {
-    uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= D * 256u) return;
-    uint32_t j = t >> 8, k = t & 255u;
-    auto has = [&](uint32_t v) { return (present[j * 8 + (v >> 5)] >> (v & 31u)) & 1u; };
-    uint32_t prev = 0xFF, next = 0xFF;
-    for (int v = (int)k - 1; v >= 0; --v)
-        if (has((uint32_t)v)) { prev = (uint32_t)v; break; }
-    for (uint32_t v = k + 1; v < 256; ++v)
-        if (has(v)) { next = v; break; }
-    pn[t * 2 + 0] = (uint8_t)prev;
-    pn[t * 2 + 1] = (uint8_t)next;
-}
-
+template <bool TI>
 __global__ __launch_bounds__(kBlock) void k_valid_rows(DevSpace S, uint32_t n_vals, const uint8_t* __restrict__ rows,
-                                                       uint64_t n, uint8_t* __restrict__ out) {
-    extern __shared__ int64_t lds_vals[];
-    load_values_lds(S, lds_vals, n_vals);
+                                                       uint64_t n, uint8_t* __restrict__ out, uint32_t tab_words) {
+    const LdsCtx C = load_ctx(S, n_vals, tab_words);
     for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n; base += (uint64_t)gridDim.x * blockDim.x) {
         uint64_t i = base + threadIdx.x;
         bool in = i < n;
@@ -364,12 +731,23 @@ __global__ __launch_bounds__(kBlock) void k_valid_rows(DevSpace S, uint32_t n_va
         if (in) row_load(r, rows + i * S.R, S.R);
         else
             for (int q = 0; q < CT_DMAX / 4; ++q) r.w[q] = 0;
-        bool ok = in && row_in_domain(S, r);
+        // every digit below its radix, four at a time: in 16-bit lanes of the even and the odd
+        // bytes, 0x100 + (radix - 1) - digit keeps bit 8 exactly when digit < radix
+        bool ok = in;
+#pragma unroll
+        for (uint32_t q = 0; q < CT_DMAX / 4; ++q) {
+            if (q < C.nw) {
+                const uint32_t rmq = __builtin_amdgcn_readfirstlane(C.rm1[q]);
+                const uint32_t te = ((rmq & 0x00FF00FFu) | 0x01000100u) - (r.w[q] & 0x00FF00FFu);
+                const uint32_t to = (((rmq >> 8) & 0x00FF00FFu) | 0x01000100u) - ((r.w[q] >> 8) & 0x00FF00FFu);
+                ok &= ((te & to & 0x01000100u) == 0x01000100u);
+            }
+        }
         if (!ok) {
 #pragma unroll
             for (int q = 0; q < CT_DMAX / 4; ++q) r.w[q] = 0;
         }
-        ok = ct_eval(S, 0, S.n_cons, r, lds_vals) && ok;
+        ok = valid_ctx<!TI>(S, C, 0, S.n_cons, r) && ok;
         if (in) out[i] = ok ? 1 : 0;
     }
 }
@@ -381,6 +759,13 @@ __global__ __launch_bounds__(kBlock) void k_rank(DevSpace S, const uint8_t* __re
     Row r;
     row_load(r, rows + i * S.R, S.R);
     pos[i] = row_in_domain(S, r) ? rank_of(S, row_encode(S, r)) : -1;
+}
+
+// Do programs [c0, c1) all have scope tables (so the table-only kernel variants apply)?
+bool tabled(const ct_space* s, uint32_t c0, uint32_t c1) {
+    for (uint32_t c = c0; c < c1; ++c)
+        if (s->tab_meta[(size_t)c * CT_TAB_META] == ~0u) return false;
+    return true;
 }
 
 uint32_t grid_for(uint64_t items, uint32_t per_block, uint32_t cap = 0x7FFFFFFFu) {
@@ -402,19 +787,25 @@ uint64_t space_resident_bytes(const ct_space* s, uint64_t n_valid) {
     b += n_groups * 8u + (n_words_alloc / 8u) * 2u;                        // rank directory
     b += (std::max<uint64_t>((n_valid + 63u) / 64u, 1) + (n_valid + 4095u) / 4096u) * 2u * S.R;  // boxes + chunks
     b += s->values.size() * 8u + std::max<size_t>(s->code.size(), 1) * 4u + sizeof(DevSpace);
+    b += s->tab_meta.size() * 4u + std::max<uint64_t>(s->tab_words, 1) * 8u;       // scope tables
     return b;
 }
 
 uint64_t space_build_scratch_bytes(const ct_space* s) {
     const uint64_t n_groups = (s->dev.N + 4095u) / 4096u;
     const uint64_t n_tiles = (n_groups + kTileGroups - 1) / kTileGroups;
-    return n_groups * 4u + (2u * n_tiles + 1u) * 8u + (uint64_t)s->dev.D * 32u;
+    const uint64_t pw = (s->dev.I_s + 63u) / 64u + 1u;
+    return n_groups * 4u + (2u * n_tiles + 1u) * 8u + (n_groups + 1u) * 4u +         // counts, tiles, busy list
+           (row_tables(s->dev) ? (s->dev.P_s + s->dev.I_s) * s->dev.R : 0u) +          // digit-row tables
+           (s->n_ctx ? s->dev.P_s * 4u + s->n_ctx * pw * 8u : (n_groups + 1u) * 4u) +   // patterns or work list
+           1024u * (uint64_t)s->dev.D * 32u;                                           // presence partials
 }
 
 int space_build_device(ct_space* s, hipStream_t st) {
     DevSpace& S = s->dev;
     const uint32_t n_vals = (uint32_t)s->values.size();
-    const size_t lds = s->lds_values_bytes;
+    const size_t lds = ctx_lds_bytes(s);
+    const uint32_t tw = ctx_tab_lds(s);
     const uint64_t n_groups = (S.N + 4095u) / 4096u;
     s->n_words = (S.N + 63u) / 64u;
     const uint64_t n_words_alloc = n_groups * 64u;
@@ -426,29 +817,77 @@ int space_build_device(ct_space* s, hipStream_t st) {
     CT_HIP(hipMallocAsync((void**)&d_counts, n_groups * sizeof(uint32_t), st));
     CT_HIP(hipMallocAsync((void**)&d_tiles, n_tiles * sizeof(uint64_t), st));
     CT_HIP(hipMallocAsync((void**)&d_off, (n_tiles + 1) * sizeof(uint64_t), st));
+    if (s->tab_words) {
+        ProfScope ps_("k_scope_tables", st);
+        hipLaunchKernelGGL(k_scope_tables, dim3(grid_for(s->tab_words, kWavesPerBlock, 1024)), dim3(kBlock), lds, st, S,
+                           n_vals, s->tab_words, s->d_tabs);
+    }
 
     if (S.split == S.D) {
         // the whole space is one table (only when N < 64 or every parameter has one value)
         CT_HIP(hipMemsetAsync(d_counts, 0, n_groups * sizeof(uint32_t), st));
         CT_HIP(hipMemsetAsync(s->d_words, 0, n_words_alloc * sizeof(uint64_t), st));
         const uint64_t units = (S.N + 64u * kSubWords - 1) / (64u * kSubWords);
-        { ProfScope ps_("k_table", st); hipLaunchKernelGGL(k_table, dim3(grid_for(units, kWavesPerBlock, 4096)), dim3(kBlock), lds, st, S, S.N, S.D,
-                           S.n_cons, n_vals, s->n_words, s->d_words, d_counts); }
+        const dim3 grid(grid_for(units, kWavesPerBlock, 4096));
+        ProfScope ps_("k_table", st);
+        if (tabled(s, 0, S.n_cons))
+            hipLaunchKernelGGL(k_table<true>, grid, dim3(kBlock), lds, st, S, S.N, S.D, S.n_cons, n_vals, s->n_words,
+                               s->d_words, d_counts, kSubWords, (uint32_t*)nullptr, tw);
+        else
+            hipLaunchKernelGGL(k_table<false>, grid, dim3(kBlock), lds, st, S, S.N, S.D, S.n_cons, n_vals, s->n_words,
+                               s->d_words, d_counts, kSubWords, (uint32_t*)nullptr, tw);
     } else {
         const uint64_t p_groups = (S.P_s + 4095u) / 4096u;
         CT_HIP(hipMalloc(&s->d_prefix, p_groups * 64u * sizeof(uint64_t)));
         CT_HIP(hipMemsetAsync(s->d_prefix, 0, p_groups * 64u * sizeof(uint64_t), st));
-        const uint64_t units = (S.P_s + 64u * kSubWords - 1) / (64u * kSubWords);
-        { ProfScope ps_("k_table", st); hipLaunchKernelGGL(k_table, dim3(grid_for(units, kWavesPerBlock, 4096)), dim3(kBlock), lds, st, S, S.P_s,
-                           S.split, S.n_pre, n_vals, p_groups * 64u, s->d_prefix, (uint32_t*)nullptr); }
+        // one word of prefixes per wave: the prefix table is small and its waves should be many
+        const uint64_t units = (S.P_s + 63u) / 64u;
+        uint32_t* d_pfx_ctx = nullptr;
+        uint64_t* d_pats = nullptr;
+        const uint32_t pw = (uint32_t)((S.I_s + 63u) / 64u + 1u);
+        if (s->n_ctx) {
+            CT_HIP(hipMallocAsync((void**)&d_pfx_ctx, S.P_s * sizeof(uint32_t), st));
+            CT_HIP(hipMallocAsync((void**)&d_pats, s->n_ctx * pw * sizeof(uint64_t), st));
+        }
+        {
+            const dim3 grid(grid_for(units, kWavesPerBlock, 4096));
+            ProfScope ps_("k_table", st);
+            if (tabled(s, 0, S.n_pre))
+                hipLaunchKernelGGL(k_table<true>, grid, dim3(kBlock), lds, st, S, S.P_s, S.split, S.n_pre, n_vals,
+                                   p_groups * 64u, s->d_prefix, (uint32_t*)nullptr, 1u, d_pfx_ctx, tw);
+            else
+                hipLaunchKernelGGL(k_table<false>, grid, dim3(kBlock), lds, st, S, S.P_s, S.split, S.n_pre, n_vals,
+                                   p_groups * 64u, s->d_prefix, (uint32_t*)nullptr, 1u, d_pfx_ctx, tw);
+        }
         S.prefix_words = s->d_prefix;
+        // groups spanning no valid prefix are zeros (written here); the others are listed
         uint32_t* d_todo = nullptr;
         CT_HIP(hipMallocAsync((void**)&d_todo, (n_groups + 1) * sizeof(uint32_t), st));
         CT_HIP(hipMemsetAsync(d_todo + n_groups, 0, sizeof(uint32_t), st));
         { ProfScope ps_("k_mask", st); hipLaunchKernelGGL(k_mask_classify, dim3(grid_for((n_groups + 63u) / 64u, kWavesPerBlock, 2048)), dim3(kBlock), 0, st, S, n_groups,
                            s->n_words, s->d_words, d_counts, d_todo, d_todo + n_groups); }
-        { ProfScope ps_("k_mask", st); hipLaunchKernelGGL(k_mask_eval, dim3(grid_for(n_groups * (64u / kSubWords), kWavesPerBlock, 4096)), dim3(kBlock), lds, st, S, n_vals,
-                           s->n_words, s->d_words, d_counts, d_todo, d_todo + n_groups); }
+        const bool ti = tabled(s, S.n_pre, S.n_cons);
+        if (s->n_ctx) {
+            {
+                const dim3 grid(grid_for(s->n_ctx * pw, kWavesPerBlock, 4096));
+                ProfScope ps_("k_patterns", st);
+                if (ti) hipLaunchKernelGGL(k_patterns<true>, grid, dim3(kBlock), lds, st, S, n_vals, s->n_ctx, pw, d_pats, tw);
+                else hipLaunchKernelGGL(k_patterns<false>, grid, dim3(kBlock), lds, st, S, n_vals, s->n_ctx, pw, d_pats, tw);
+            }
+            { ProfScope ps_("k_mask", st); hipLaunchKernelGGL(k_mask_pattern, dim3(grid_for(n_groups, kWavesPerBlock * kMaskUnroll, 4096)), dim3(kBlock), 0, st, S,
+                               s->d_words, d_counts, d_todo, d_todo + n_groups, d_pfx_ctx, d_pats, pw); }
+            CT_HIP(hipFreeAsync(d_pfx_ctx, st));
+            CT_HIP(hipFreeAsync(d_pats, st));
+        } else {
+            const dim3 grid(grid_for(n_groups * (64u / kSubWords), kWavesPerBlock, 4096));
+            ProfScope ps_("k_mask", st);
+            if (ti)
+                hipLaunchKernelGGL(k_mask_eval<true>, grid, dim3(kBlock), lds, st, S, n_vals, s->n_words, s->d_words,
+                                   d_counts, d_todo, d_todo + n_groups, tw);
+            else
+                hipLaunchKernelGGL(k_mask_eval<false>, grid, dim3(kBlock), lds, st, S, n_vals, s->n_words, s->d_words,
+                                   d_counts, d_todo, d_todo + n_groups, tw);
+        }
         CT_HIP(hipFreeAsync(d_todo, st));
     }
     CT_HIP(hipGetLastError());
@@ -472,18 +911,45 @@ int space_build_device(ct_space* s, hipStream_t st) {
     CT_HIP(hipMalloc(&s->d_lin, alloc_n * sizeof(uint64_t)));
     CT_HIP(hipMalloc(&s->d_rows, alloc_n * S.R));
     CT_HIP(hipMalloc(&s->d_prevnext, (size_t)S.D * 256 * 2));
-    uint32_t* d_present = nullptr;
-    CT_HIP(hipMallocAsync((void**)&d_present, (size_t)S.D * 8 * sizeof(uint32_t), st));
-    CT_HIP(hipMemsetAsync(d_present, 0, (size_t)S.D * 8 * sizeof(uint32_t), st));
     CT_HIP(hipMalloc(&s->d_grp_off, n_groups * sizeof(uint64_t)));
     CT_HIP(hipMalloc(&s->d_dir8, (n_words_alloc / 8) * sizeof(uint16_t)));
     S.n_sub = (total + 63u) / 64u;
     S.n_chunk = (S.n_sub + 63u) / 64u;
     // boxes, then the chunk level in the same allocation
     CT_HIP(hipMalloc(&s->d_boxes, (std::max<uint64_t>(S.n_sub, 1) + S.n_chunk) * 2u * S.R));
-    if (total) {
-        { ProfScope ps_("k_compact", st); hipLaunchKernelGGL(k_compact, dim3(grid_for(n_groups, kWavesPerBlock)), dim3(kBlock), 0, st, S, s->d_words,
-                           s->n_words, d_counts, d_off, n_groups, s->d_lin, s->d_rows, s->d_grp_off, s->d_dir8); }
+    {
+        // group offsets (every group) and the list of groups with valid configurations
+        uint32_t* d_busy = nullptr;
+        CT_HIP(hipMallocAsync((void**)&d_busy, (n_groups + 1) * sizeof(uint32_t), st));
+        CT_HIP(hipMemsetAsync(d_busy + n_groups, 0, sizeof(uint32_t), st));
+        CT_HIP(hipMemsetAsync(s->d_dir8, 0, (n_words_alloc / 8) * sizeof(uint16_t), st));
+        { ProfScope ps_("k_group_off", st); hipLaunchKernelGGL(k_group_off, dim3((uint32_t)n_tiles), dim3(kTileGroups), 0, st, d_counts,
+                           n_groups, d_off, s->d_grp_off, d_busy, d_busy + n_groups); }
+        if (total) {
+            // prefix and inner digit rows, when both tables are small, so that a valid
+            // configuration's row is two loads and an OR instead of a decode
+            uint8_t* d_prow = nullptr;
+            uint8_t* d_irow = nullptr;
+            const bool rt = row_tables(S);
+            if (rt) {
+                CT_HIP(hipMallocAsync((void**)&d_prow, S.P_s * S.R, st));
+                CT_HIP(hipMallocAsync((void**)&d_irow, S.I_s * S.R, st));
+                ProfScope ps_("k_digit_rows", st);
+                hipLaunchKernelGGL(k_digit_rows, dim3(grid_for(S.P_s, kBlock, 4096)), dim3(kBlock), 0, st, S, S.P_s, 0u, S.split, d_prow);
+                hipLaunchKernelGGL(k_digit_rows, dim3(grid_for(S.I_s, kBlock, 4096)), dim3(kBlock), 0, st, S, S.I_s, S.split, S.D, d_irow);
+            }
+            {
+                ProfScope ps_("k_compact", st);
+                hipLaunchKernelGGL(k_compact, dim3(grid_for(std::min<uint64_t>(n_groups, 16384), kWavesPerBlock)), dim3(kBlock), 0, st, S,
+                                   s->d_words, s->n_words, d_busy, d_busy + n_groups, s->d_grp_off, s->d_lin, s->d_rows, s->d_dir8,
+                                   (const uint8_t*)d_prow, (const uint8_t*)d_irow);
+            }
+            if (rt) {
+                CT_HIP(hipFreeAsync(d_prow, st));
+                CT_HIP(hipFreeAsync(d_irow, st));
+            }
+        }
+        CT_HIP(hipFreeAsync(d_busy, st));
     }
     S.lin = s->d_lin;
     S.rows = s->d_rows;
@@ -493,18 +959,20 @@ int space_build_device(ct_space* s, hipStream_t st) {
     S.dir8 = s->d_dir8;
     S.boxes = s->d_boxes;
     S.chunks = s->d_boxes + std::max<uint64_t>(S.n_sub, 1) * 2u * S.R;
-    if (total) {
-        { ProfScope ps_("k_boxes", st); hipLaunchKernelGGL(k_boxes, dim3(grid_for(S.n_sub, kWavesPerBlock)), dim3(kBlock), 0, st, S, s->d_boxes); }
-        { ProfScope ps_("k_chunks", st); hipLaunchKernelGGL(k_chunks, dim3(grid_for(S.n_chunk, kWavesPerBlock)), dim3(kBlock), 0, st, S, s->d_boxes + std::max<uint64_t>(S.n_sub, 1) * 2u * S.R); }
+    {
+        // boxes, chunk boxes, and the presence of every value index
+        uint32_t* d_part = nullptr;
+        CT_HIP(hipMallocAsync((void**)&d_part, (size_t)S.D * 8u * sizeof(uint32_t), st));
+        CT_HIP(hipMemsetAsync(d_part, 0, (size_t)S.D * 8u * sizeof(uint32_t), st));
+        if (total) {
+            { ProfScope ps_("k_boxes", st); hipLaunchKernelGGL(k_boxes, dim3(grid_for(S.n_sub, kWavesPerBlock)), dim3(kBlock), 0, st, S, (uint32_t*)s->d_boxes, d_part); }
+            { ProfScope ps_("k_chunks", st); hipLaunchKernelGGL(k_chunks, dim3(grid_for(S.n_chunk, kWavesPerBlock)), dim3(kBlock), 0, st, S, s->d_boxes + std::max<uint64_t>(S.n_sub, 1) * 2u * S.R); }
+        }
+        { ProfScope ps_("k_prevnext", st); hipLaunchKernelGGL(k_prevnext, dim3(1), dim3(1024), 0, st, S.D, d_part, 1u, s->d_prevnext); }
+        CT_HIP(hipFreeAsync(d_part, st));
     }
-    if (total) {
-        { ProfScope ps_("k_presence", st); hipLaunchKernelGGL(k_presence, dim3(grid_for(total, kBlock, 1024)), dim3(kBlock), 0, st, S, d_present); }
-    }
-    { ProfScope ps_("k_prevnext", st); hipLaunchKernelGGL(k_prevnext, dim3(grid_for(S.D * 256u, 256)), dim3(256), 0, st, S.D, d_present,
-                       s->d_prevnext); }
     S.prevnext = s->d_prevnext;
     CT_HIP(hipGetLastError());
-    CT_HIP(hipFreeAsync(d_present, st));
     CT_HIP(hipFreeAsync(d_counts, st));
     CT_HIP(hipFreeAsync(d_tiles, st));
     CT_HIP(hipFreeAsync(d_off, st));
@@ -514,8 +982,16 @@ int space_build_device(ct_space* s, hipStream_t st) {
 
 int launch_valid_mask(const ct_space* s, const uint8_t* rows, uint64_t n, uint8_t* out, hipStream_t st) {
     if (n == 0) return CT_OK;
-    { ProfScope ps_("k_valid_rows", st); hipLaunchKernelGGL(k_valid_rows, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), s->lds_values_bytes, st, s->dev,
-                       (uint32_t)s->values.size(), rows, n, out); }
+    {
+        ProfScope ps_("k_valid_rows", st);
+        const dim3 grid(grid_for(n, kBlock, 8192));
+        if (tabled(s, 0, s->dev.n_cons))
+            hipLaunchKernelGGL(k_valid_rows<true>, grid, dim3(kBlock), ctx_lds_bytes(s), st, s->dev,
+                               (uint32_t)s->values.size(), rows, n, out, ctx_tab_lds(s));
+        else
+            hipLaunchKernelGGL(k_valid_rows<false>, grid, dim3(kBlock), ctx_lds_bytes(s), st, s->dev,
+                               (uint32_t)s->values.size(), rows, n, out, ctx_tab_lds(s));
+    }
     CT_HIP(hipGetLastError());
     return CT_OK;
 }
