@@ -50,7 +50,12 @@ import numpy as np
 from . import core
 
 P_INIT, P_DE_PICK, P_DE_CR, P_PSO_R, P_GA_SEL, P_GA_MUT = 1, 2, 3, 4, 5, 6
-P_FF_NOISE = 9
+P_FF_NOISE, P_GA_XO = 9, 10
+
+# DE mutation operators (Section IV-B, last paragraph) and crossovers; GA crossovers (Section IV-D)
+DE_RAND1, DE_BEST1, DE_RAND2, DE_BEST2, DE_CURRENTTOBEST1, DE_RANDTOBEST1 = 0, 1, 2, 3, 4, 5
+DE_BIN, DE_EXP = 0, 1
+GA_SINGLE_POINT, GA_TWO_POINT, GA_UNIFORM, GA_DISRUPTIVE_UNIFORM = 0, 1, 2, 3
 
 
 def uniform_below(u: int, n: int) -> int:
@@ -128,36 +133,83 @@ def de_init(space, obj, P, seed) -> DEState:
     return DEState(pos, f, np.float32(b[0]), int(b[1]))
 
 
+def de_picks(seed: int, i: int, g: int, P: int, k: int) -> List[int]:
+    """k distinct members other than i: r1, r2, r3 from words 0-2 of the individual's first draw
+    block (word 3 is j_rand), r4, r5 from words 0-1 of its second block."""
+    o = draw(seed, i, g, P_DE_PICK)
+    words = [o[0], o[1], o[2]]
+    if k > 3:
+        o2 = draw(seed, i, g, P_DE_PICK, 1)
+        words += [o2[0], o2[1]]
+    picks: List[int] = []
+    for t in range(k):
+        picks.append(pick_excluding(words[t], P, [i] + picks))
+    return picks
+
+
+def de_mutant_terms(method: int, i: int, r: List[int], X: np.ndarray, best_row: np.ndarray, j: int):
+    """(base, scaled difference) of coordinate j: the mutant is base + F * difference (Alg. 1's
+    Mutate for best1/rand1; Section IV-B's other operators)."""
+    x = lambda k: int(X[k, j])  # noqa: E731
+    b = int(best_row[j])
+    if method == DE_RAND1:
+        return x(r[0]), x(r[1]) - x(r[2])
+    if method == DE_BEST1:
+        return b, x(r[1]) - x(r[2])
+    if method == DE_RAND2:
+        return x(r[0]), x(r[1]) - x(r[2]) + x(r[3]) - x(r[4])
+    if method == DE_BEST2:
+        return b, x(r[1]) - x(r[2]) + x(r[3]) - x(r[4])
+    if method == DE_CURRENTTOBEST1:
+        return x(i), b - x(i) + x(r[1]) - x(r[2])
+    if method == DE_RANDTOBEST1:
+        return x(r[0]), b - x(r[0]) + x(r[1]) - x(r[2])
+    raise ValueError("unknown DE method")
+
+
 def de_trials(space: core.Space, st: DEState, seed: int, F_q16: int, CR_q32: int,
-              use_best: bool = True) -> np.ndarray:
-    """Alg. 1's Mutate and Crossover for every member: the trial vectors before repair."""
+              use_best=True, crossover: int = DE_BIN) -> np.ndarray:
+    """Alg. 1's Mutate and Crossover for every member: the trial vectors before repair.
+
+    use_best: True / False for best1 / rand1 (Alg. 1), or one of the DE_* operators.  Binomial
+    crossover takes each coordinate from the mutant with probability CR, and coordinate j_rand
+    always; exponential crossover takes the circular run of coordinates starting at j_rand that
+    continues while successive draws stay below CR (at most D).
+    """
+    method = use_best if not isinstance(use_best, bool) else (DE_BEST1 if use_best else DE_RAND1)
     P, D, g = len(st.pos), space.D, st.gen
-    if P < 4:
-        raise ValueError("DE needs at least 4 members")
+    k = 5 if method in (DE_RAND2, DE_BEST2) else 3
+    if P < k + 1:
+        raise ValueError(f"DE operator {method} needs at least {k + 1} members")
     rad = space.radices
     X = space.vrows[st.pos]                              # value indices of the population
     best_row = space.vrows[st.best_pos]
     trials = np.zeros((P, D), dtype=np.int32)
     for i in range(P):
-        o = draw(seed, i, g, P_DE_PICK)
-        r1 = pick_excluding(o[0], P, [i])
-        r2 = pick_excluding(o[1], P, [i, r1])
-        r3 = pick_excluding(o[2], P, [i, r1, r2])
-        j_rand = uniform_below(o[3], D)
-        base = best_row if use_best else X[r1]
+        r = de_picks(seed, i, g, P, k)
+        j_rand = uniform_below(draw(seed, i, g, P_DE_PICK)[3], D)
+        if crossover == DE_EXP:
+            run = 1
+            while run < D and draw(seed, i, g, P_DE_CR, run >> 2)[run & 3] < CR_q32:
+                run += 1
         for j in range(D):
-            # m = i_r1 + F*(i_r2 - i_r3), rounded half up in Q16.16, clipped to the domain
-            num = int(base[j]) * 65536 + F_q16 * (int(X[r2, j]) - int(X[r3, j])) + 32768
+            base, diff = de_mutant_terms(method, i, r, X, best_row, j)
+            # m = base + F*diff, rounded half up in Q16.16, clipped to the domain
+            num = base * 65536 + F_q16 * diff + 32768
             m = min(max(num // 65536, 0), int(rad[j]) - 1)
-            cr = draw(seed, i, g, P_DE_CR, j >> 2)[j & 3]
-            trials[i, j] = m if (cr < CR_q32 or j == j_rand) else X[i, j]
+            if crossover == DE_EXP:
+                take = (j - j_rand) % D < run
+            else:
+                cr = draw(seed, i, g, P_DE_CR, j >> 2)[j & 3]
+                take = cr < CR_q32 or j == j_rand
+            trials[i, j] = m if take else X[i, j]
     return trials
 
 
 def de_step(space: core.Space, obj: np.ndarray, st: DEState, seed: int, F_q16: int, CR_q32: int,
-            use_best: bool = True) -> DEState:
+            use_best=True, crossover: int = DE_BIN) -> DEState:
     P, g = len(st.pos), st.gen
-    trials = de_trials(space, st, seed, F_q16, CR_q32, use_best)
+    trials = de_trials(space, st, seed, F_q16, CR_q32, use_best, crossover)
     # Repair: invalid trials move to the nearest valid configuration by index distance
     trials = space.repair(trials, core.INDEX_L1)
     upos = space.pos(space.encode(trials))
@@ -283,10 +335,43 @@ def ga_init(space, obj, P, seed) -> GAState:
     return GAState(pos, f, np.float32(b[0]), int(b[1]))
 
 
+def ga_cross_pair(A: np.ndarray, B: np.ndarray, seed: int, k: int, g: int, o: List[int], method: int):
+    """The two children of pair k from parents A, B (Section IV-D's crossovers).
+
+    single point: cut c in 1..D-1 (word 2), children A[:c]+B[c:] and B[:c]+A[c:];
+    two point: two distinct cuts (words 2 and 3, the second drawn from the other D-2 points),
+    children A[:c1]+B[c1:c2]+A[c2:] and its mirror (single point when D < 3);
+    uniform: gene j from B when the top bit of draw (k, g, GA_XO | j/4, 0) word j%4 is set,
+    the second child the complement;
+    disruptive uniform: of the genes where A and B differ, exactly half (rounded down) are
+    swapped -- the ones with the smallest keys (draw (k, g, GA_XO | j/4, 1) word j%4, ties by j).
+    """
+    D = len(A)
+    if method == GA_SINGLE_POINT or (method == GA_TWO_POINT and D < 3):
+        cut = 1 + uniform_below(o[2], D - 1)
+        return np.concatenate([A[:cut], B[cut:]]), np.concatenate([B[:cut], A[cut:]])
+    if method == GA_TWO_POINT:
+        a = 1 + uniform_below(o[2], D - 1)
+        b = 1 + pick_excluding(o[3], D - 1, [a - 1])
+        c1, c2 = min(a, b), max(a, b)
+        return (np.concatenate([A[:c1], B[c1:c2], A[c2:]]), np.concatenate([B[:c1], A[c1:c2], B[c2:]]))
+    if method == GA_UNIFORM:
+        fromB = np.array([draw(seed, k, g, P_GA_XO, j >> 2)[j & 3] >> 31 for j in range(D)], dtype=bool)
+        return np.where(fromB, B, A), np.where(fromB, A, B)
+    if method == GA_DISRUPTIVE_UNIFORM:
+        diff = [j for j in range(D) if A[j] != B[j]]
+        keys = sorted(diff, key=lambda j: (draw(seed, k, g, P_GA_XO, j >> 2, 1)[j & 3], j))
+        swap = set(keys[:len(diff) // 2])
+        c1 = np.array([B[j] if j in swap else A[j] for j in range(D)], dtype=A.dtype)
+        c2 = np.array([A[j] if j in swap else B[j] for j in range(D)], dtype=A.dtype)
+        return c1, c2
+    raise ValueError("unknown GA crossover")
+
+
 def ga_crossover(space: core.Space, st: GAState, seed: int, beta_b: int,
-                 table: Optional[List[int]] = None) -> np.ndarray:
-    """Rank selection of two parents per pair and single-point crossover: every child before
-    Alg. 3's repair and the mutation (child 2k is A[:cut] + B[cut:], child 2k+1 is B[:cut] + A[cut:])."""
+                 table: Optional[List[int]] = None, method: int = GA_SINGLE_POINT) -> np.ndarray:
+    """Rank selection of two parents per pair and crossover (Section IV-D): every child before
+    Alg. 3's repair and the mutation (children 2k and 2k+1 are pair k's)."""
     P, D, g = len(st.pos), space.D, st.gen
     order = sorted(range(P), key=lambda i: (float(st.f[i]), int(st.pos[i])))
     table = table or beta_rank_table(P, beta_b)
@@ -296,17 +381,17 @@ def ga_crossover(space: core.Space, st: GAState, seed: int, beta_b: int,
         o = draw(seed, k, g, P_GA_SEL)
         A = rows[order[rank_from_draw(table, o[0])]]
         B = rows[order[rank_from_draw(table, o[1])]]
-        cut = 1 + uniform_below(o[2], D - 1)
-        children[2 * k] = np.concatenate([A[:cut], B[cut:]])
+        c1, c2 = ga_cross_pair(A, B, seed, k, g, o, method)
+        children[2 * k] = c1
         if 2 * k + 1 < P:
-            children[2 * k + 1] = np.concatenate([B[:cut], A[cut:]])
+            children[2 * k + 1] = c2
     return children
 
 
 def ga_step(space: core.Space, obj: np.ndarray, st: GAState, seed: int, mutation_chance: int,
-            beta_b: int, table: Optional[List[int]] = None) -> GAState:
+            beta_b: int, table: Optional[List[int]] = None, method: int = GA_SINGLE_POINT) -> GAState:
     P, g = len(st.pos), st.gen
-    children = ga_crossover(space, st, seed, beta_b, table)
+    children = ga_crossover(space, st, seed, beta_b, table, method)
     # Alg. 3: invalid children become a random member of the first non-empty neighbour set
     children = space.repair(children, core.TIER_RANDOM, key=seed, gen=g)
     # Mutation (after repair): with chance 1/mutation_chance, a random valid Hamming neighbour
@@ -324,14 +409,14 @@ def ga_step(space: core.Space, obj: np.ndarray, st: GAState, seed: int, mutation
 
 
 def ga_children(space: core.Space, obj: np.ndarray, st: GAState, seed: int, mutation_chance: int, beta_b: int,
-                indices, table: Optional[List[int]] = None) -> np.ndarray:
+                indices, table: Optional[List[int]] = None, method: int = GA_SINGLE_POINT) -> np.ndarray:
     """Final rows of selected children of generation st.gen (same definition as ga_step).
 
     Lets a test check a sample of a large population without repairing all of it.
     """
     g = st.gen
     idx = np.asarray(indices, dtype=np.int64)
-    kids = ga_crossover(space, st, seed, beta_b, table)[idx]
+    kids = ga_crossover(space, st, seed, beta_b, table, method)[idx]
     kids = space.repair(kids, core.TIER_RANDOM, who=idx, key=seed, gen=g)
     thresh = (1 << 32) // mutation_chance
     mut = [n for n, i in enumerate(idx) if draw(seed, int(i), g, P_GA_MUT)[0] < thresh]
@@ -463,9 +548,11 @@ def init_run(space, obj, opt):
 
 def step_run(space, obj, st, opt):
     if opt.algo == 0:
-        return de_step(space, obj, st, opt.seed, opt.F_q16, opt.CR_q32, bool(opt.de_method))
+        return de_step(space, obj, st, opt.seed, opt.F_q16, opt.CR_q32, int(opt.de_method),
+                       int(getattr(opt, "de_crossover", DE_BIN)))
     if opt.algo == 1:
         return pso_step(space, obj, st, opt.seed, opt.w_q16, opt.c1_q16, opt.c2_q16)
     if opt.algo == 2:
-        return ga_step(space, obj, st, opt.seed, opt.mutation_chance, opt.beta_b)
+        return ga_step(space, obj, st, opt.seed, opt.mutation_chance, opt.beta_b,
+                       method=int(getattr(opt, "ga_crossover", GA_SINGLE_POINT)))
     return ff_step(space, obj, st, opt.seed, opt.ff_B0_q16, opt.ff_gamma_q16, opt.ff_alpha_q16)
