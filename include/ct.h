@@ -84,7 +84,8 @@ enum ct_step_flags {
 /* Message for the last error on this thread (never NULL). */
 const char* ct_last_error(void);
 
-/* Library ABI version (currently 2: ct_pop_params carries the Firefly parameters). */
+/* Library ABI version (currently 2: ct_pop_params carries the Firefly parameters and the
+   DE / GA operator choices). */
 int ct_version(void);
 
 /*
@@ -214,9 +215,13 @@ int ct_repair_noalloc(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint
 /*
  * Optimiser hyperparameters in integer form (Table IV defaults in brackets).
  *   DE:  F_q16 = round(F * 2^16) [45875], CR_q32 = round(CR * 2^32) [2576980378],
- *        de_method 1 = best1bin, 0 = rand1bin [1]; requires 4 <= pop_size.
+ *        de_method: mutation operator (Alg. 1 and Section IV-B, last paragraph) [CT_DE_BEST1],
+ *        de_crossover: CT_DE_BIN (binomial, Alg. 1) or CT_DE_EXP (exponential) [CT_DE_BIN];
+ *        requires pop_size >= 4 (>= 6 for the two-difference operators).
  *   PSO: w_q16 < 65536, c1_q16, c2_q16 <= 2^20  [32768, 196608, 32768].
- *   GA:  mutation_chance X = "one in X" [5]; rank selection Beta(1, beta_b), 1 <= beta_b <= 5 [3].
+ *   GA:  mutation_chance X = "one in X" [5]; rank selection Beta(1, beta_b), 1 <= beta_b <= 5 [3];
+ *        ga_crossover: CT_GA_SINGLE_POINT [default], CT_GA_TWO_POINT, CT_GA_UNIFORM,
+ *        CT_GA_DISRUPTIVE_UNIFORM (Section IV-D).
  *   Firefly (Section IV-C, last paragraph; Table IV): ff_B0_q16 = round(B0 * 2^16) [65536],
  *        ff_gamma_q16 = round(gamma * 2^16) [65536], ff_alpha_q16 = round(alpha * 2^16) [13107],
  *        each <= 2^20.  Positions use PSO's index-unit mapping and Alg. 2 evaluation.
@@ -235,8 +240,28 @@ typedef struct {
     uint32_t mutation_chance;
     uint32_t beta_b;
     uint32_t ff_B0_q16, ff_gamma_q16, ff_alpha_q16;
-    uint32_t reserved[7];
+    uint32_t de_crossover, ga_crossover;
+    uint32_t reserved[5];
 } ct_pop_params;
+
+/* DE mutation operators on value indices, with picks r1..r5 distinct members other than i
+   (Philox words 0-2 of draw (i, g, 2<<24, 0), words 0-1 of (i, g, 2<<24 | 1, 0)) and
+   m = clip(round_half_up(base + F * difference)):
+     RAND1: x_r1 + F (x_r2 - x_r3)             BEST1: best + F (x_r2 - x_r3)
+     RAND2: x_r1 + F (x_r2 - x_r3 + x_r4 - x_r5)   BEST2: best + F (x_r2 - x_r3 + x_r4 - x_r5)
+     CURRENTTOBEST1: x_i + F (best - x_i + x_r2 - x_r3)
+     RANDTOBEST1: x_r1 + F (best - x_r1 + x_r2 - x_r3)
+   Exponential crossover takes the mutant on the circular run of coordinates from j_rand that
+   continues while draw k (word k%4 of (i, g, 3<<24 | k/4, 0)), k = 1, 2, ..., is below CR.
+   GA crossovers of parents A, B (child 2k; child 2k+1 is the mirror): SINGLE_POINT A[:c]+B[c:];
+   TWO_POINT A[:c1]+B[c1:c2]+A[c2:] (cuts from words 2 and 3 of the selection draw, distinct);
+   UNIFORM gene j from B when the top bit of word j%4 of (k, g, 10<<24 | j/4, 0) is set;
+   DISRUPTIVE_UNIFORM: of the genes where A and B differ, the half (rounded down) with the
+   smallest keys (word j%4 of (k, g, 10<<24 | j/4, 1), ties by j) come from B. */
+enum { CT_DE_RAND1 = 0, CT_DE_BEST1 = 1, CT_DE_RAND2 = 2, CT_DE_BEST2 = 3, CT_DE_CURRENTTOBEST1 = 4,
+       CT_DE_RANDTOBEST1 = 5 };
+enum { CT_DE_BIN = 0, CT_DE_EXP = 1 };
+enum { CT_GA_SINGLE_POINT = 0, CT_GA_TWO_POINT = 1, CT_GA_UNIFORM = 2, CT_GA_DISRUPTIVE_UNIFORM = 3 };
 
 /*
  * ct_pop_create -- allocate a run and draw its initial population (generation 0).

@@ -641,6 +641,12 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_ob
     if (q.pop_size > s->n_valid)
         return ct_fail(CT_EINVAL, "ct_pop_create: pop_size exceeds the number of valid configurations");
     if (q.algo == CT_DE && q.pop_size < 4) return ct_fail(CT_EINVAL, "ct_pop_create: DE needs pop_size >= 4");
+    if (q.algo == CT_DE && (q.de_method > CT_DE_RANDTOBEST1 || q.de_crossover > CT_DE_EXP))
+        return ct_fail(CT_EINVAL, "ct_pop_create: unknown DE operator or crossover");
+    if (q.algo == CT_DE && (q.de_method == CT_DE_RAND2 || q.de_method == CT_DE_BEST2) && q.pop_size < 6)
+        return ct_fail(CT_EINVAL, "ct_pop_create: the two-difference DE operators need pop_size >= 6");
+    if (q.algo == CT_GA && q.ga_crossover > CT_GA_DISRUPTIVE_UNIFORM)
+        return ct_fail(CT_EINVAL, "ct_pop_create: unknown GA crossover");
     if (q.algo == CT_DE && q.CR_q32 > (1ull << 32)) return ct_fail(CT_EINVAL, "ct_pop_create: CR_q32 above 2^32");
     if (q.algo == CT_PSO && (q.w_q16 >= 65536 || q.c1_q16 > (1u << 20) || q.c2_q16 > (1u << 20)))
         return ct_fail(CT_EINVAL, "ct_pop_create: PSO coefficients out of range");
@@ -666,6 +672,8 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_ob
     d.seed = q.seed;
     d.F_q16 = q.F_q16;
     d.de_method = q.de_method;
+    d.de_cross = q.de_crossover;
+    d.ga_cross = q.ga_crossover;
     d.CR_q32 = q.CR_q32;
     d.w_q16 = q.w_q16;
     d.c1_q16 = q.c1_q16;

@@ -136,7 +136,7 @@ __device__ __forceinline__ U4 ct_philox(uint64_t seed, uint32_t c0, uint32_t c1,
 
 // draw purposes (counter word 2, bits 24..31)
 enum { PUR_INIT = 1, PUR_DE_PICK = 2, PUR_DE_CR = 3, PUR_PSO_R = 4, PUR_GA_SEL = 5, PUR_GA_MUT = 6,
-       PUR_REPAIR_KEY = 7, PUR_MUT_KEY = 8, PUR_FF_NOISE = 9 };
+       PUR_REPAIR_KEY = 7, PUR_MUT_KEY = 8, PUR_FF_NOISE = 9, PUR_GA_XO = 10 };
 
 __device__ __forceinline__ uint32_t ct_below(uint32_t u, uint32_t n) {
     return (uint32_t)(((uint64_t)u * n) >> 32);

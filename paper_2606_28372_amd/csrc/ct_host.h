@@ -191,6 +191,7 @@ struct PopDev {
     uint32_t algo, P, D, R;
     uint64_t seed;
     uint32_t F_q16, de_method;
+    uint32_t de_cross, ga_cross;      // DE: binomial / exponential; GA: crossover operator
     uint64_t CR_q32;
     int64_t w_q16, c1_q16, c2_q16;
     uint64_t mut_thresh;              // floor(2^32 / mutation_chance): a child mutates when its draw is below
@@ -262,6 +263,9 @@ struct ct_batch {
     std::vector<double> tune_ms;         // their pass times summed over the tuning generations
     StreamFan fan;
 };
+
+// Smallest DE population for a mutation operator (i and its distinct picks).
+inline uint32_t de_min_pop(uint32_t method) { return method == CT_DE_RAND2 || method == CT_DE_BEST2 ? 6u : 4u; }
 
 // Device bytes a run of this shape allocates (its buffers and its one-run batch).
 uint64_t pop_footprint_bytes(uint32_t algo, uint32_t P, uint32_t D, uint32_t R, uint64_t n_valid);

@@ -147,7 +147,7 @@ struct ct_server {
             r->footprint = run_bytes(r, r->n_valid);
             r->sized = true;
             const bool unusable = r->n_valid == 0 || r->n_valid > CT_MAX_VALID ||
-                                  (r->prm.algo == CT_DE && r->prm.pop_size < 4);
+                                  (r->prm.algo == CT_DE && r->prm.pop_size < de_min_pop(r->prm.de_method));
             if (unusable || r->footprint + scratch > cfg.hbm_budget) {
                 release_space_device(r->space);
                 queue.pop_front();
@@ -295,6 +295,9 @@ int ct_server_submit(ct_server* s, const int64_t* values, const uint32_t* radice
     if (!s || !prm || !run_id) return ct_fail(CT_EINVAL, "ct_server_submit: null argument");
     if (n_generations < 1) return ct_fail(CT_EINVAL, "ct_server_submit: n_generations must be >= 1");
     if (prm->algo > CT_FIREFLY) return ct_fail(CT_EINVAL, "ct_server_submit: unknown algorithm");
+    if ((prm->algo == CT_DE && (prm->de_method > CT_DE_RANDTOBEST1 || prm->de_crossover > CT_DE_EXP)) ||
+        (prm->algo == CT_GA && prm->ga_crossover > CT_GA_DISRUPTIVE_UNIFORM))
+        return ct_fail(CT_EINVAL, "ct_server_submit: unknown operator");
     ct_space* sp = nullptr;
     int rc = space_prepare(values, radices, n_params, code, cons_offsets, n_cons, &sp);
     if (rc) return rc;

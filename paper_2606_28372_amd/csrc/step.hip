@@ -229,28 +229,64 @@ __device__ __forceinline__ uint32_t propose_digit(const PopDev& p, const DevSpac
                                                   uint32_t j) {
     const uint32_t radix = gld(&S.radix[j]);
     if (p.algo == CT_DE) {
-        U4 o = ct_philox(p.seed, i, g, (uint32_t)PUR_DE_PICK << 24, 0);
-        uint32_t ex[3] = {i, 0, 0};
-        const uint32_t r1 = pick_excl(o.x, p.P, ex, 1);
-        ex[1] = r1;
-        sort3(ex, 2);
-        const uint32_t r2 = pick_excl(o.y, p.P, ex, 2);
-        ex[2] = r2;
-        sort3(ex, 3);
-        const uint32_t r3 = pick_excl(o.z, p.P, ex, 3);
+        // picks r1..r5: distinct members other than i (two-difference operators use five)
+        const uint32_t meth = p.de_method;
+        const uint32_t k = (meth == CT_DE_RAND2 || meth == CT_DE_BEST2) ? 5u : 3u;
+        const U4 o = ct_philox(p.seed, i, g, (uint32_t)PUR_DE_PICK << 24, 0);
+        uint32_t u[5] = {o.x, o.y, o.z, 0u, 0u};
+        if (k > 3) {
+            const U4 o2 = ct_philox(p.seed, i, g, ((uint32_t)PUR_DE_PICK << 24) | 1u, 0);
+            u[3] = o2.x;
+            u[4] = o2.y;
+        }
+        uint32_t ex[6] = {i, 0, 0, 0, 0, 0};
+        uint32_t r[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+        for (uint32_t t = 0; t < 5; ++t) {
+            if (t < k) {
+                r[t] = pick_excl(u[t], p.P, ex, t + 1);
+                ex[t + 1] = r[t];
+                sort3(ex, t + 2);
+            }
+        }
         const uint32_t jr = ct_below(o.w, p.D);
-        const uint32_t pb = p.de_method ? (uint32_t)(gld(p.best) & 0xFFFFFFFFu) : gld(p.pos + r1);
-        const uint32_t base = row_digit(S, pb, p.R, j), x = row_digit(S, gld(p.pos + i), p.R, j);
-        const uint32_t a = row_digit(S, gld(p.pos + r2), p.R, j), b = row_digit(S, gld(p.pos + r3), p.R, j);
-        // block j/4 of the crossover draws, draw j%4 of it
-        const U4 cr = ct_philox(p.seed, i, g, ((uint32_t)PUR_DE_CR << 24) | (j >> 2), 0);
-        const uint32_t t = j & 3u;
-        const uint32_t cu = t == 0 ? cr.x : t == 1 ? cr.y : t == 2 ? cr.z : cr.w;
-        const int64_t num = (int64_t)base * 65536 + (int64_t)p.F_q16 * ((int64_t)a - (int64_t)b) + 32768;
+        const int64_t best = row_digit(S, (uint32_t)(gld(p.best) & 0xFFFFFFFFu), p.R, j);
+        const int64_t x = row_digit(S, gld(p.pos + i), p.R, j);
+        const int64_t x1 = row_digit(S, gld(p.pos + r[0]), p.R, j);
+        const int64_t x2 = row_digit(S, gld(p.pos + r[1]), p.R, j), x3 = row_digit(S, gld(p.pos + r[2]), p.R, j);
+        int64_t base, diff = x2 - x3;
+        if (meth == CT_DE_RAND1) base = x1;
+        else if (meth == CT_DE_BEST1) base = best;
+        else if (meth == CT_DE_CURRENTTOBEST1) { base = x; diff += best - x; }
+        else if (meth == CT_DE_RANDTOBEST1) { base = x1; diff += best - x1; }
+        else {
+            base = meth == CT_DE_RAND2 ? x1 : best;
+            diff += (int64_t)row_digit(S, gld(p.pos + r[3]), p.R, j) - (int64_t)row_digit(S, gld(p.pos + r[4]), p.R, j);
+        }
+        const int64_t num = base * 65536 + (int64_t)p.F_q16 * diff + 32768;
         int64_t m = num >> 16;            // floor
         const int64_t hi = (int64_t)radix - 1;
         m = m < 0 ? 0 : (m > hi ? hi : m);
-        return ((uint64_t)cu < p.CR_q32 || j == jr) ? (uint32_t)m : x;
+        bool take;
+        if (p.de_cross == CT_DE_EXP) {
+            // the circular run from j_rand continues while successive draws stay below CR
+            uint32_t run = 1;
+            while (run < p.D) {
+                const U4 c = ct_philox(p.seed, i, g, ((uint32_t)PUR_DE_CR << 24) | (run >> 2), 0);
+                const uint32_t t = run & 3u;
+                const uint32_t cu = t == 0 ? c.x : t == 1 ? c.y : t == 2 ? c.z : c.w;
+                if ((uint64_t)cu >= p.CR_q32) break;
+                ++run;
+            }
+            take = (j + p.D - jr) % p.D < run;
+        } else {
+            // block j/4 of the crossover draws, draw j%4 of it
+            const U4 cr = ct_philox(p.seed, i, g, ((uint32_t)PUR_DE_CR << 24) | (j >> 2), 0);
+            const uint32_t t = j & 3u;
+            const uint32_t cu = t == 0 ? cr.x : t == 1 ? cr.y : t == 2 ? cr.z : cr.w;
+            take = (uint64_t)cu < p.CR_q32 || j == jr;
+        }
+        return take ? (uint32_t)m : (uint32_t)x;
     }
     if (p.algo == CT_FIREFLY) {
         // the position after this generation's moves, snapped to the nearest value
@@ -274,14 +310,48 @@ __device__ __forceinline__ uint32_t propose_digit(const PopDev& p, const DevSpac
         const uint32_t d = (uint32_t)(x >> 16);
         return d < radix ? d : radix - 1u;
     }
-    // GA: child i of pair i/2 is A[:cut] + B[cut:] for even i, B[:cut] + A[cut:] for odd i
+    // GA: child i of pair i/2 takes gene j from parent A where the even child does (the odd child
+    // is its mirror)
     const uint32_t k = i >> 1;
     U4 o = ct_philox(p.seed, k, g, (uint32_t)PUR_GA_SEL << 24, 0);
     const uint32_t a = beta_rank(p, o.x), b = beta_rank(p, o.y);
-    const uint32_t cut = 1u + ct_below(o.z, p.D - 1u);
-    const bool odd = (i & 1u) != 0;
-    const bool from_a = (j < cut) != odd;
-    return row_digit(S, gld(p.sorted + (from_a ? a : b)), p.R, j);
+    const uint32_t pa = gld(p.sorted + a), pb = gld(p.sorted + b);
+    bool even_a;
+    if (p.ga_cross == CT_GA_UNIFORM) {
+        const U4 x = ct_philox(p.seed, k, g, ((uint32_t)PUR_GA_XO << 24) | (j >> 2), 0);
+        const uint32_t t = j & 3u;
+        even_a = ((t == 0 ? x.x : t == 1 ? x.y : t == 2 ? x.z : x.w) >> 31) == 0u;
+    } else if (p.ga_cross == CT_GA_DISRUPTIVE_UNIFORM) {
+        // of the genes where the parents differ, the half with the smallest keys come from B
+        const uint32_t aj = row_digit(S, pa, p.R, j), bj = row_digit(S, pb, p.R, j);
+        even_a = true;
+        if (aj != bj) {
+            const U4 kj4 = ct_philox(p.seed, k, g, ((uint32_t)PUR_GA_XO << 24) | (j >> 2), 1);
+            const uint32_t t = j & 3u;
+            const uint32_t kj = t == 0 ? kj4.x : t == 1 ? kj4.y : t == 2 ? kj4.z : kj4.w;
+            uint32_t n_diff = 0, rank = 0;
+            for (uint32_t q = 0; q < p.D; ++q) {
+                if (row_digit(S, pa, p.R, q) == row_digit(S, pb, p.R, q)) continue;
+                ++n_diff;
+                const U4 kq4 = ct_philox(p.seed, k, g, ((uint32_t)PUR_GA_XO << 24) | (q >> 2), 1);
+                const uint32_t tq = q & 3u;
+                const uint32_t kq = tq == 0 ? kq4.x : tq == 1 ? kq4.y : tq == 2 ? kq4.z : kq4.w;
+                rank += (kq < kj || (kq == kj && q < j)) ? 1u : 0u;
+            }
+            even_a = rank >= n_diff / 2;
+        }
+    } else if (p.ga_cross == CT_GA_TWO_POINT && p.D >= 3) {
+        const uint32_t c1 = 1u + ct_below(o.z, p.D - 1u);
+        uint32_t c2 = ct_below(o.w, p.D - 2u);
+        if (c2 >= c1 - 1u) ++c2;                 // a distinct second cut
+        c2 += 1u;
+        const uint32_t lo = c1 < c2 ? c1 : c2, hi = c1 < c2 ? c2 : c1;
+        even_a = j < lo || j >= hi;
+    } else {
+        even_a = j < 1u + ct_below(o.z, p.D - 1u);
+    }
+    const bool from_a = even_a != ((i & 1u) != 0);
+    return row_digit(S, from_a ? pa : pb, p.R, j);
 }
 
 // Proposals of every run, one group of G lanes per individual, each proposal listed for the main

@@ -196,7 +196,8 @@ class OptParams:
     # DE (Table IV: F 0.7, CR 0.6, best1bin)
     F_q16: int = 45875                  # round(0.7 * 2**16)
     CR_q32: int = 2576980378            # round(0.6 * 2**32)
-    de_method: int = 1                    # 1 = best1bin, 0 = rand1bin
+    de_method: int = 1                  # 0 rand1, 1 best1, 2 rand2, 3 best2, 4 current-to-best1, 5 rand-to-best1
+    de_crossover: int = 0               # 0 binomial, 1 exponential
     # PSO (Table IV: w 0.5, c1 3.0, c2 0.5)
     w_q16: int = 32768
     c1_q16: int = 196608
@@ -204,6 +205,7 @@ class OptParams:
     # GA (Table IV: single_point, mutation chance 5); rank selection Beta(1, beta_b)
     mutation_chance: int = 5
     beta_b: int = 3
+    ga_crossover: int = 0               # 0 single point, 1 two point, 2 uniform, 3 disruptive uniform
     # Firefly (Table IV: B0 1.0, gamma 1.0, alpha 0.2)
     ff_B0_q16: int = 65536
     ff_gamma_q16: int = 65536
