@@ -542,11 +542,24 @@ def ff_step(space: core.Space, obj: np.ndarray, st: FFState, seed: int, B0_q16: 
 # ---------------------------------------------------------------------------
 
 def init_run(space, obj, opt):
-    f = {0: de_init, 1: pso_init, 2: ga_init, 3: ff_init}[opt.algo]
+    if getattr(opt, "unaware", 0):
+        f = {0: u_init, 1: upso_init, 2: u_init, 3: uff_init}[opt.algo]
+    else:
+        f = {0: de_init, 1: pso_init, 2: ga_init, 3: ff_init}[opt.algo]
     return f(space, obj, opt.pop_size, opt.seed)
 
 
 def step_run(space, obj, st, opt):
+    if getattr(opt, "unaware", 0):
+        if opt.algo == 0:
+            return ude_step(space, obj, st, opt.seed, opt.F_q16, opt.CR_q32, int(opt.de_method),
+                            int(getattr(opt, "de_crossover", DE_BIN)))
+        if opt.algo == 1:
+            return upso_step(space, obj, st, opt.seed, opt.w_q16, opt.c1_q16, opt.c2_q16)
+        if opt.algo == 2:
+            return uga_step(space, obj, st, opt.seed, opt.mutation_chance, opt.beta_b,
+                            int(getattr(opt, "ga_crossover", GA_SINGLE_POINT)))
+        return uff_step(space, obj, st, opt.seed, opt.ff_B0_q16, opt.ff_gamma_q16, opt.ff_alpha_q16)
     if opt.algo == 0:
         return de_step(space, obj, st, opt.seed, opt.F_q16, opt.CR_q32, int(opt.de_method),
                        int(getattr(opt, "de_crossover", DE_BIN)))
@@ -556,3 +569,199 @@ def step_run(space, obj, st, opt):
         return ga_step(space, obj, st, opt.seed, opt.mutation_chance, opt.beta_b,
                        method=int(getattr(opt, "ga_crossover", GA_SINGLE_POINT)))
     return ff_step(space, obj, st, opt.seed, opt.ff_B0_q16, opt.ff_gamma_q16, opt.ff_alpha_q16)
+
+
+# ---------------------------------------------------------------------------
+# Non-constraint-aware variants (Section IV-B, last sentence; Section IV-C, last sentence):
+# a random initial population over the whole Cartesian space (coordinates uniform in PSO's
+# [0,1]^N for PSO and Firefly), no repair, and one static penalty for invalid configurations
+# (+infinity: the objective is minimised).  DE/GA members are digit rows; a member's position
+# is its place in the valid list or NONE.
+# ---------------------------------------------------------------------------
+
+NONE = 0xFFFFFFFF
+
+
+def evaluate(space: core.Space, obj: np.ndarray, rows: np.ndarray):
+    """(positions, objective) of configurations: NONE and +inf for the invalid ones."""
+    rows = np.asarray(rows, dtype=np.int32).reshape(-1, space.D)
+    ok = space.valid_rows(rows) if len(rows) else np.zeros(0, dtype=bool)
+    pos = np.full(len(rows), NONE, dtype=np.int64)
+    f = np.full(len(rows), np.inf, dtype=np.float32)
+    if ok.any():
+        p = space.pos(space.encode(rows[ok]))
+        pos[ok] = p
+        f[ok] = obj[p]
+    return pos, f
+
+
+def random_rows(space: core.Space, P: int, seed: int, tag: int) -> np.ndarray:
+    """Member i, digit j: uniform in [0, r_j) from word j%4 of draw (i, tag, INIT | 1 + j/4)."""
+    rows = np.zeros((P, space.D), dtype=np.int32)
+    for i in range(P):
+        for j in range(space.D):
+            rows[i, j] = uniform_below(draw(seed, i, tag, P_INIT, 1 + (j >> 2))[j & 3], int(space.radices[j]))
+    return rows
+
+
+def random_coords(space: core.Space, P: int, seed: int) -> np.ndarray:
+    """Particle i, coordinate j: uniform in [0, M 2^16) (PSO's [0,1]^N in index units), same draws."""
+    M = int(space.radices.max())
+    X = np.zeros((P, space.D), dtype=np.int64)
+    for i in range(P):
+        for j in range(space.D):
+            X[i, j] = uniform_below(draw(seed, i, 0, P_INIT, 1 + (j >> 2))[j & 3], M * 65536)
+    return X
+
+
+def _best(best, f, pos):
+    for i in range(len(f)):
+        best = _lexmin(best, (float(f[i]), int(pos[i])))
+    return best
+
+
+@dataclasses.dataclass
+class UState:
+    rows: np.ndarray           # DE / GA members as digit rows
+    pos: np.ndarray            # valid-list positions (NONE for invalid members)
+    f: np.ndarray              # objective (+inf for invalid members)
+    best_f: float
+    best_pos: int
+    gen: int = 0
+    reinits: int = 0
+
+
+def u_init(space, obj, P, seed) -> UState:
+    rows = random_rows(space, P, seed, 0)
+    pos, f = evaluate(space, obj, rows)
+    b = _best((np.inf, NONE), f, pos)
+    return UState(rows, pos, f, np.float32(b[0]), int(b[1]))
+
+
+def _pop_best(f) -> int:
+    """The population's best member: lowest (objective, member index)."""
+    return int(min(range(len(f)), key=lambda i: (float(f[i]), i)))
+
+
+def ude_trials(space: core.Space, st: UState, seed: int, F_q16: int, CR_q32: int, method: int,
+               crossover: int = DE_BIN) -> np.ndarray:
+    """Non-aware DE trials: the operators of de_trials on the member rows, with "best" the
+    population's best member (lowest objective, then index)."""
+    P, D, g = len(st.pos), space.D, st.gen
+    k = 5 if method in (DE_RAND2, DE_BEST2) else 3
+    X = st.rows
+    best_row = X[_pop_best(st.f)]
+    trials = np.zeros((P, D), dtype=np.int32)
+    for i in range(P):
+        r = de_picks(seed, i, g, P, k)
+        j_rand = uniform_below(draw(seed, i, g, P_DE_PICK)[3], D)
+        if crossover == DE_EXP:
+            run = 1
+            while run < D and draw(seed, i, g, P_DE_CR, run >> 2)[run & 3] < CR_q32:
+                run += 1
+        for j in range(D):
+            base, diff = de_mutant_terms(method, i, r, X, best_row, j)
+            num = base * 65536 + F_q16 * diff + 32768
+            m = min(max(num // 65536, 0), int(space.radices[j]) - 1)
+            if crossover == DE_EXP:
+                take = (j - j_rand) % D < run
+            else:
+                take = draw(seed, i, g, P_DE_CR, j >> 2)[j & 3] < CR_q32 or j == j_rand
+            trials[i, j] = m if take else X[i, j]
+    return trials
+
+
+def ude_step(space: core.Space, obj: np.ndarray, st: UState, seed: int, F_q16: int, CR_q32: int,
+             method: int = DE_BEST1, crossover: int = DE_BIN) -> UState:
+    """Non-aware DE: the trials are evaluated as they are (no repair); u_i replaces x_i when
+    f(u_i) <= f(x_i) and u_i is not in X (by configuration), the lowest index winning equal
+    trials; a generation without replacement reinitialises randomly."""
+    P, g = len(st.pos), st.gen
+    trials = ude_trials(space, st, seed, F_q16, CR_q32, method, crossover)
+    upos, fu = evaluate(space, obj, trials)
+    uL = space.encode(trials)
+    members = set(space.encode(st.rows).tolist())
+    taken = set()
+    rows, pos, f = st.rows.copy(), st.pos.copy(), st.f.copy()
+    accepted = 0
+    for i in range(P):
+        if fu[i] <= st.f[i] and int(uL[i]) not in members and int(uL[i]) not in taken:
+            taken.add(int(uL[i]))
+            rows[i], pos[i], f[i] = trials[i], upos[i], fu[i]
+            accepted += 1
+    best = _best((float(st.best_f), st.best_pos), f, pos)
+    reinits = st.reinits
+    if accepted == 0:
+        rows = random_rows(space, P, seed, g + 1)
+        pos, f = evaluate(space, obj, rows)
+        best = _best(best, f, pos)
+        reinits += 1
+    return UState(rows, pos, f, np.float32(best[0]), int(best[1]), g + 1, reinits)
+
+
+def uga_step(space: core.Space, obj: np.ndarray, st: UState, seed: int, mutation_chance: int, beta_b: int,
+             method: int = GA_SINGLE_POINT) -> UState:
+    """Non-aware GA: rank selection over the members sorted by (objective, index), crossover,
+    no repair, and with chance 1/mutation_chance one parameter (word 1 of the mutation draw)
+    set to another of its values (word 2), valid or not."""
+    P, D, g = len(st.pos), space.D, st.gen
+    order = sorted(range(P), key=lambda i: (float(st.f[i]), i))
+    table = beta_rank_table(P, beta_b)
+    kids = np.zeros((P, D), dtype=np.int32)
+    for k in range((P + 1) // 2):
+        o = draw(seed, k, g, P_GA_SEL)
+        A = st.rows[order[rank_from_draw(table, o[0])]]
+        B = st.rows[order[rank_from_draw(table, o[1])]]
+        c1, c2 = ga_cross_pair(A, B, seed, k, g, o, method)
+        kids[2 * k] = c1
+        if 2 * k + 1 < P:
+            kids[2 * k + 1] = c2
+    thresh = (1 << 32) // mutation_chance
+    for i in range(P):
+        o = draw(seed, i, g, P_GA_MUT)
+        if o[0] < thresh:
+            j = uniform_below(o[1], D)
+            r = int(space.radices[j])
+            if r > 1:
+                v = uniform_below(o[2], r - 1)
+                kids[i, j] = v + 1 if v >= kids[i, j] else v
+    pos, f = evaluate(space, obj, kids)
+    best = _best((float(st.best_f), st.best_pos), f, pos)
+    return UState(kids, pos, f, np.float32(best[0]), int(best[1]), g + 1)
+
+
+def upso_init(space, obj, P, seed) -> PSOState:
+    X = random_coords(space, P, seed)
+    snapped = np.minimum(X >> 16, space.radices.astype(np.int64) - 1)
+    pos, f = evaluate(space, obj, snapped)
+    return PSOState(X.copy(), np.zeros_like(X), X.copy(), f.copy(), pos.copy(), _gbest(f))
+
+
+def upso_step(space: core.Space, obj: np.ndarray, st: PSOState, seed: int, w_q16: int, c1_q16: int,
+              c2_q16: int) -> PSOState:
+    """Non-aware PSO: the snapped position is evaluated as it is (static penalty if invalid)."""
+    X, V, snapped = pso_move(space, st, seed, w_q16, c1_q16, c2_q16)
+    epos, f = evaluate(space, obj, snapped)
+    PB, f_pb, pb_pos = st.PB.copy(), st.f_pb.copy(), st.pb_pos.copy()
+    for i in range(X.shape[0]):
+        if f[i] < f_pb[i]:
+            PB[i], f_pb[i], pb_pos[i] = X[i], f[i], epos[i]
+    return PSOState(X, V, PB, f_pb, pb_pos, _gbest(f_pb), st.gen + 1)
+
+
+def uff_init(space, obj, P, seed) -> FFState:
+    X = random_coords(space, P, seed)
+    snapped = np.minimum(X >> 16, space.radices.astype(np.int64) - 1)
+    pos, f = evaluate(space, obj, snapped)
+    b = _best((np.inf, NONE), f, pos)
+    return FFState(X, f, pos, np.float32(b[0]), int(b[1]))
+
+
+def uff_step(space: core.Space, obj: np.ndarray, st: FFState, seed: int, B0_q16: int, gamma_q16: int,
+             alpha_q16: int) -> FFState:
+    """Non-aware Firefly: moves as the aware one, the snapped position evaluated as it is."""
+    Xn = ff_move(space, st, seed, B0_q16, gamma_q16, alpha_q16)
+    snapped = np.minimum(Xn >> 16, space.radices.astype(np.int64) - 1)
+    pos, f = evaluate(space, obj, snapped)
+    best = _best((float(st.best_f), st.best_pos), f, pos)
+    return FFState(Xn, f, pos, np.float32(best[0]), int(best[1]), st.gen + 1)

@@ -206,6 +206,7 @@ class OptParams:
     mutation_chance: int = 5
     beta_b: int = 3
     ga_crossover: int = 0               # 0 single point, 1 two point, 2 uniform, 3 disruptive uniform
+    unaware: int = 0                    # 1: the non-constraint-aware variant (random init, no repair)
     # Firefly (Table IV: B0 1.0, gamma 1.0, alpha 0.2)
     ff_B0_q16: int = 65536
     ff_gamma_q16: int = 65536
