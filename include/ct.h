@@ -76,6 +76,7 @@ enum ct_step_flags {
 #define CT_MAX_PARAMS 32
 #define CT_MAX_RADIX 255
 #define CT_MAX_POP 65536
+#define CT_UNAWARE_DE_MAX_POP 8192   /* non-aware DE: its selection compares every pair of members */
 #define CT_MAX_CARTESIAN_LOG2 46
 /* Valid-list positions are 32-bit (0xFFFFFFFF means "none"): ct_repair, ct_pop_create and the
    server need n_valid <= CT_MAX_VALID; larger spaces still build, count, mask and rank. */
@@ -225,9 +226,17 @@ int ct_repair_noalloc(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint
  *   Firefly (Section IV-C, last paragraph; Table IV): ff_B0_q16 = round(B0 * 2^16) [65536],
  *        ff_gamma_q16 = round(gamma * 2^16) [65536], ff_alpha_q16 = round(alpha * 2^16) [13107],
  *        each <= 2^20.  Positions use PSO's index-unit mapping and Alg. 2 evaluation.
- * Every algorithm requires pop_size <= n_valid (its initial sample is stratified
- * over the valid list, one stratum per member).  Fields a run does not use are ignored;
- * reserved words must be 0.
+ * Every constraint-aware algorithm requires pop_size <= n_valid (its initial sample is
+ * stratified over the valid list, one stratum per member).  Fields a run does not use are
+ * ignored; reserved words must be 0.
+ *   unaware = 1 selects the non-constraint-aware variant (Sections IV-B and IV-C, last
+ * sentences): the initial population is drawn over the whole Cartesian space (digit j of
+ * member i: word j%4 of draw (i, 0, 1<<24 | 1 + j/4, 0), uniform over the parameter's values;
+ * PSO / Firefly coordinates uniform in [0, M 2^16) from the same words), nothing is repaired,
+ * and an invalid configuration evaluates to +infinity (its position is 0xFFFFFFFF).  DE's
+ * "best" is then the population's best member (lowest objective, then index); GA ranks by
+ * (objective, index) and mutates one parameter (word 1 of the mutation draw) to another of its
+ * values (word 2).  Non-aware DE takes pop_size <= CT_UNAWARE_DE_MAX_POP.
  */
 typedef struct {
     uint32_t algo;
@@ -241,7 +250,8 @@ typedef struct {
     uint32_t beta_b;
     uint32_t ff_B0_q16, ff_gamma_q16, ff_alpha_q16;
     uint32_t de_crossover, ga_crossover;
-    uint32_t reserved[5];
+    uint32_t unaware;       /* 1: the non-constraint-aware variant [0] */
+    uint32_t reserved[4];
 } ct_pop_params;
 
 /* DE mutation operators on value indices, with picks r1..r5 distinct members other than i
@@ -363,17 +373,18 @@ int ct_pop_counters(const ct_pop* p, uint64_t* repairs, uint64_t* mutations);
 
 /*
  * ct_pop_snapshot / ct_pop_restore -- full run state as bytes (synchronising).
- * Layout: uint32 header[8] = {magic 0x43545031, algo, pop_size, n_params,
- * generation, reinits, best_pos, best_f bits}, then for DE/GA uint32 pos[P],
- * float f[P]; for Firefly uint32 pos[P] (evaluated positions), float f[P]
- * (brightness), int32 X[P][D]; for PSO int32 X[P][D], int64 V[P][D], int32 PB[P][D],
- * float f_pb[P], uint32 pb_pos[P], uint32 gbest_index.  Call with
- * h_buf = NULL to get the size.  A restored run continues bit-identically.
- * ct_pop_restore checks the whole snapshot on the host before it writes
- * anything to the device: the run's shape (algorithm, pop_size, n_params),
- * every position and best_pos below n_valid, DE positions distinct, PSO and
- * Firefly coordinates X and PB in [0, M * 2^16) (M the largest radix), |V| < 2^46 and
- * gbest_index < pop_size; on CT_EINVAL the run is left as it was.
+ * Layout: uint32 header[8] = {magic 0x43545031 (non-aware runs: 0x43545531), algo,
+ * pop_size, n_params, generation, reinits, best_pos, best_f bits}, then for DE/GA uint32
+ * pos[P], float f[P] (non-aware: followed by uint8 rows[P][D], the members' digits); for
+ * Firefly uint32 pos[P] (evaluated positions), float f[P] (brightness), int32 X[P][D]; for
+ * PSO int32 X[P][D], int64 V[P][D], int32 PB[P][D], float f_pb[P], uint32 pb_pos[P],
+ * uint32 gbest_index.  Call with h_buf = NULL to get the size.  A restored run continues
+ * bit-identically.  ct_pop_restore checks the whole snapshot on the host before it writes
+ * anything to the device: the run's shape (algorithm, pop_size, n_params, aware or not),
+ * every position and best_pos below n_valid (non-aware runs: or 0xFFFFFFFF), aware DE
+ * positions distinct, non-aware digits inside their domains, PSO and Firefly coordinates X
+ * and PB in [0, M * 2^16) (M the largest radix), |V| < 2^46 and gbest_index < pop_size; on
+ * CT_EINVAL the run is left as it was.
  */
 int ct_pop_snapshot(const ct_pop* p, void* h_buf, size_t* len);
 int ct_pop_restore(ct_pop* p, const void* h_buf, size_t len);

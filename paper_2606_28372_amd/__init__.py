@@ -222,6 +222,7 @@ def make_params(algo: int, pop_size: int, seed: int, **kw) -> ct_pop_params:
     p.ff_B0_q16, p.ff_gamma_q16 = kw.get("ff_B0_q16", 65536), kw.get("ff_gamma_q16", 65536)
     p.ff_alpha_q16 = kw.get("ff_alpha_q16", 13107)
     p.de_crossover, p.ga_crossover = kw.get("de_crossover", 0), kw.get("ga_crossover", 0)
+    p.unaware = kw.get("unaware", 0)
     return p
 
 
@@ -230,7 +231,7 @@ def opt_kwargs(opt) -> Dict[str, int]:
     return dict(F_q16=opt.F_q16, CR_q32=opt.CR_q32, de_method=opt.de_method, w_q16=opt.w_q16, c1_q16=opt.c1_q16,
                 c2_q16=opt.c2_q16, mutation_chance=opt.mutation_chance, beta_b=opt.beta_b,
                 ff_B0_q16=opt.ff_B0_q16, ff_gamma_q16=opt.ff_gamma_q16, ff_alpha_q16=opt.ff_alpha_q16,
-                de_crossover=opt.de_crossover, ga_crossover=opt.ga_crossover)
+                de_crossover=opt.de_crossover, ga_crossover=opt.ga_crossover, unaware=opt.unaware)
 
 
 class Pop:

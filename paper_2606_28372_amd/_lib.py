@@ -34,7 +34,7 @@ class ct_pop_params(ctypes.Structure):
                 ("mutation_chance", ctypes.c_uint32), ("beta_b", ctypes.c_uint32),
                 ("ff_B0_q16", ctypes.c_uint32), ("ff_gamma_q16", ctypes.c_uint32), ("ff_alpha_q16", ctypes.c_uint32),
                 ("de_crossover", ctypes.c_uint32), ("ga_crossover", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 5)]
+                ("unaware", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 4)]
 
 
 _vp, _u32, _u64, _i32, _sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_size_t

@@ -63,14 +63,15 @@ int check_program(const uint32_t* code, uint32_t b, uint32_t e, uint32_t n_param
 std::mutex g_tune_mu;
 std::map<std::string, RepairTune> g_tune;
 
-// Shape of a group of runs: per run (algorithm, row bytes, parameters, log2 |V|, log2 P), sorted.
+// Shape of a group of runs: per run (algorithm, row bytes, parameters, log2 |V|, log2 P, aware or
+// not), sorted.
 std::string group_shape(const std::vector<ct_pop*>& pops) {
     std::vector<std::string> parts;
     auto lg = [](uint64_t x) { uint32_t k = 0; while (x >>= 1) ++k; return k; };
     for (const ct_pop* p : pops) {
         const PopDev& d = p->dev;
         parts.push_back(std::to_string(d.algo) + "," + std::to_string(d.R) + "," + std::to_string(d.D) + "," +
-                        std::to_string(lg(d.n_valid)) + "," + std::to_string(lg(d.P)));
+                        std::to_string(lg(d.n_valid)) + "," + std::to_string(lg(d.P)) + "," + std::to_string(d.unaware));
     }
     std::sort(parts.begin(), parts.end());
     std::string s;
@@ -241,14 +242,15 @@ int batch_build(const std::vector<ct_pop*>& pops, ct_batch** out, hipStream_t st
     return CT_OK;
 }
 
-uint64_t pop_footprint_bytes(uint32_t algo, uint32_t P, uint32_t D, uint32_t R, uint64_t n_valid) {
+uint64_t pop_footprint_bytes(uint32_t algo, uint32_t P, uint32_t D, uint32_t R, uint64_t n_valid, uint32_t unaware) {
     const uint64_t p = P, pd = (uint64_t)P * D;
     const uint64_t slots = std::max<uint64_t>(P, kRepairMaxItems);
     uint64_t b = 16 + 16 + 16 + 8 + 2 * p * R + 4 * p + p;      // state, tally, rcount, best, trial, out, tpos, apply
     if (algo == CT_PSO) b += pd * (4 + 8 + 4) + 8 * p;           // X, V, PB, f_pb, pb_pos
     else b += 8 * p;                                              // pos, f
     if (algo == CT_FIREFLY) b += pd * (4 + 4);                    // X, Xn
-    if (algo == CT_DE) b += (n_valid + 31) / 32 * 4 + std::max<uint64_t>(n_valid, 1) * 4;   // member, claim
+    if (unaware && (algo == CT_DE || algo == CT_GA)) b += p * R + 16 * p;                    // prow, pL, tL
+    else if (algo == CT_DE) b += (n_valid + 31) / 32 * 4 + std::max<uint64_t>(n_valid, 1) * 4;   // member, claim
     if (algo == CT_GA) b += 8 * p + 4 * p;                        // beta table, sorted
     b += 4 * p + 8 * p + 4 * p + 8 * p + slots * (8 + 4);         // repair scratch
     return b;
@@ -638,9 +640,12 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_ob
     if (s->n_valid > CT_MAX_VALID)
         return ct_fail(CT_EINVAL, "ct_pop_create: more valid configurations than 32-bit positions can name");
     if (q.pop_size < 1 || q.pop_size > CT_MAX_POP) return ct_fail(CT_EINVAL, "ct_pop_create: pop_size out of range");
-    if (q.pop_size > s->n_valid)
+    if (q.unaware > 1) return ct_fail(CT_EINVAL, "ct_pop_create: unaware is 0 or 1");
+    if (!q.unaware && q.pop_size > s->n_valid)
         return ct_fail(CT_EINVAL, "ct_pop_create: pop_size exceeds the number of valid configurations");
     if (q.algo == CT_DE && q.pop_size < 4) return ct_fail(CT_EINVAL, "ct_pop_create: DE needs pop_size >= 4");
+    if (q.unaware && q.algo == CT_DE && q.pop_size > CT_UNAWARE_DE_MAX_POP)
+        return ct_fail(CT_EINVAL, "ct_pop_create: the non-aware DE supports pop_size <= 8192");
     if (q.algo == CT_DE && (q.de_method > CT_DE_RANDTOBEST1 || q.de_crossover > CT_DE_EXP))
         return ct_fail(CT_EINVAL, "ct_pop_create: unknown DE operator or crossover");
     if (q.algo == CT_DE && (q.de_method == CT_DE_RAND2 || q.de_method == CT_DE_BEST2) && q.pop_size < 6)
@@ -674,6 +679,7 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_ob
     d.de_method = q.de_method;
     d.de_cross = q.de_crossover;
     d.ga_cross = q.ga_crossover;
+    d.unaware = q.unaware;
     d.CR_q32 = q.CR_q32;
     d.w_q16 = q.w_q16;
     d.c1_q16 = q.c1_q16;
@@ -703,7 +709,11 @@ int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_ob
     if (q.algo == CT_FIREFLY) {
         if ((rc = dalloc(p, &d.X, (size_t)P * d.D)) || (rc = dalloc(p, &d.Xn, (size_t)P * d.D))) return fail(rc);
     }
-    if (q.algo == CT_DE) {
+    if (q.unaware && (q.algo == CT_DE || q.algo == CT_GA)) {
+        if ((rc = dalloc(p, &d.prow, (size_t)P * d.R)) || (rc = dalloc(p, &d.pL, P)) || (rc = dalloc(p, &d.tL, P)))
+            return fail(rc);
+    }
+    if (q.algo == CT_DE && !q.unaware) {
         size_t words = (s->n_valid + 31) / 32;
         if ((rc = dalloc(p, &d.member, words)) || (rc = dalloc(p, &d.claim, s->n_valid))) return fail(rc);
         if (hipMemsetAsync(d.member, 0, words * 4, st) != hipSuccess ||
@@ -895,11 +905,15 @@ int ct_pop_counters(const ct_pop* p, uint64_t* repairs, uint64_t* mutations) {
     return CT_OK;
 }
 
+static bool has_rows(const PopDev& d) { return d.unaware && (d.algo == CT_DE || d.algo == CT_GA); }
+static uint32_t snapshot_magic(const PopDev& d) { return d.unaware ? 0x43545531u : 0x43545031u; }
+
 static size_t snapshot_size(const PopDev& d) {
     size_t n = 32;
     if (d.algo == CT_PSO) n += (size_t)d.P * d.D * (4 + 8 + 4) + (size_t)d.P * 8 + 4;
     else n += (size_t)d.P * 8;
     if (d.algo == CT_FIREFLY) n += (size_t)d.P * d.D * 4;
+    if (has_rows(d)) n += (size_t)d.P * d.D;
     return n;
 }
 
@@ -915,7 +929,7 @@ int ct_pop_snapshot(const ct_pop* p, void* h_buf, size_t* len) {
     uint64_t b;
     CT_HIP(hipMemcpy(stt, d.state, 16, hipMemcpyDeviceToHost));
     CT_HIP(hipMemcpy(&b, d.best, 8, hipMemcpyDeviceToHost));
-    uint32_t h[8] = {0x43545031u, d.algo, d.P, d.D, stt[0], stt[1], (uint32_t)b, (uint32_t)(b >> 32)};
+    uint32_t h[8] = {snapshot_magic(d), d.algo, d.P, d.D, stt[0], stt[1], (uint32_t)b, (uint32_t)(b >> 32)};
     memcpy(o, h, 32);
     o += 32;
     if (d.algo == CT_PSO) {
@@ -930,6 +944,12 @@ int ct_pop_snapshot(const ct_pop* p, void* h_buf, size_t* len) {
         CT_HIP(hipMemcpy(o, d.pos, d.P * 4, hipMemcpyDeviceToHost)); o += d.P * 4;
         CT_HIP(hipMemcpy(o, d.f, d.P * 4, hipMemcpyDeviceToHost)); o += d.P * 4;
         if (d.algo == CT_FIREFLY) CT_HIP(hipMemcpy(o, d.X, (size_t)d.P * d.D * 4, hipMemcpyDeviceToHost));
+        if (has_rows(d)) {
+            // member rows, D digits each (the device rows are padded to R bytes)
+            std::vector<uint8_t> rows((size_t)d.P * d.R);
+            CT_HIP(hipMemcpy(rows.data(), d.prow, rows.size(), hipMemcpyDeviceToHost));
+            for (uint32_t i = 0; i < d.P; ++i) memcpy(o + (size_t)i * d.D, rows.data() + (size_t)i * d.R, d.D);
+        }
     }
     *len = need;
     return CT_OK;
@@ -943,14 +963,19 @@ int ct_pop_restore(ct_pop* p, const void* h_buf, size_t len) {
     uint32_t h[8];
     memcpy(h, o, 32);
     o += 32;
-    if (h[0] != 0x43545031u || h[1] != d.algo || h[2] != d.P || h[3] != d.D)
+    if (h[0] != snapshot_magic(d) || h[1] != d.algo || h[2] != d.P || h[3] != d.D)
         return ct_fail(CT_EINVAL, "ct_pop_restore: snapshot is for a different run shape");
     // every field is checked before anything reaches the device, so a rejected snapshot leaves
     // the run as it was
     const uint64_t nv = p->space->n_valid;
     const size_t P = d.P, PD = (size_t)d.P * d.D;
-    if (h[6] >= nv) return ct_fail(CT_EINVAL, "ct_pop_restore: best position out of range");
+    // the non-aware variant's positions may name no configuration (an invalid one, +inf)
+    auto bad_pos = [&](uint32_t v) { return v >= nv && !(d.unaware && v == 0xFFFFFFFFu); };
+    if (bad_pos(h[6])) return ct_fail(CT_EINVAL, "ct_pop_restore: best position out of range");
     std::vector<uint32_t> words;
+    std::vector<uint8_t> rows;
+    std::vector<uint64_t> lin;
+    uint32_t pop_best = 0;
     if (d.algo == CT_PSO) {
         const int64_t xmax = (int64_t)d.M * 65536;
         std::vector<int32_t> X(PD), PB(PD);
@@ -970,13 +995,32 @@ int ct_pop_restore(ct_pop* p, const void* h_buf, size_t len) {
                 return ct_fail(CT_EINVAL, "ct_pop_restore: velocity magnitude not below 2^46");
         }
         for (uint32_t v : pb_pos)
-            if (v >= nv) return ct_fail(CT_EINVAL, "ct_pop_restore: personal-best position out of range");
+            if (bad_pos(v)) return ct_fail(CT_EINVAL, "ct_pop_restore: personal-best position out of range");
         if (gi >= d.P) return ct_fail(CT_EINVAL, "ct_pop_restore: global-best index out of range");
     } else {
         std::vector<uint32_t> pos(P);
+        std::vector<float> f(P);
         memcpy(pos.data(), o, P * 4);
+        memcpy(f.data(), o + P * 4, P * 4);
         for (uint32_t v : pos)
-            if (v >= nv) return ct_fail(CT_EINVAL, "ct_pop_restore: position out of range");
+            if (bad_pos(v)) return ct_fail(CT_EINVAL, "ct_pop_restore: position out of range");
+        if (has_rows(d)) {
+            // rows to the device layout (R bytes each) and their linear indices
+            const uint8_t* src = o + P * 8;
+            const DevSpace& S = p->space->dev;
+            rows.assign(P * d.R, 0);
+            lin.assign(P, 0);
+            for (size_t i = 0; i < P; ++i)
+                for (uint32_t j = 0; j < d.D; ++j) {
+                    const uint8_t v = src[i * d.D + j];
+                    if (v >= S.radix[j]) return ct_fail(CT_EINVAL, "ct_pop_restore: member digit outside its domain");
+                    rows[i * d.R + j] = v;
+                    lin[i] += (uint64_t)v * S.stride[j];
+                }
+            // DE's "best" member: lowest objective, then index
+            for (uint32_t i = 1; i < d.P; ++i)
+                if (f[i] < f[pop_best]) pop_best = i;
+        }
         if (d.algo == CT_FIREFLY) {
             const int64_t xmax = (int64_t)d.M * 65536;
             std::vector<int32_t> X(PD);
@@ -984,7 +1028,7 @@ int ct_pop_restore(ct_pop* p, const void* h_buf, size_t len) {
             for (int32_t x : X)
                 if (x < 0 || x >= xmax) return ct_fail(CT_EINVAL, "ct_pop_restore: firefly coordinate outside [0, M * 2^16)");
         }
-        if (d.algo == CT_DE) {
+        if (d.algo == CT_DE && !d.unaware) {
             // the membership bitmap is derived from the positions, which must be distinct
             words.assign((nv + 31) / 32, 0);
             for (uint32_t v : pos) {
@@ -995,7 +1039,7 @@ int ct_pop_restore(ct_pop* p, const void* h_buf, size_t len) {
         }
     }
     CT_HIP(hipDeviceSynchronize());
-    uint32_t stt[4] = {h[4], h[5], 0, 0};
+    uint32_t stt[4] = {h[4], h[5], d.unaware && d.algo == CT_DE ? pop_best : 0u, 0};
     uint64_t b = ((uint64_t)h[7] << 32) | h[6];
     if (d.algo == CT_PSO) {
         CT_HIP(hipMemcpy(d.X, o, PD * 4, hipMemcpyHostToDevice)); o += PD * 4;
@@ -1008,7 +1052,12 @@ int ct_pop_restore(ct_pop* p, const void* h_buf, size_t len) {
         CT_HIP(hipMemcpy(d.pos, o, P * 4, hipMemcpyHostToDevice)); o += P * 4;
         CT_HIP(hipMemcpy(d.f, o, P * 4, hipMemcpyHostToDevice)); o += P * 4;
         if (d.algo == CT_FIREFLY) CT_HIP(hipMemcpy(d.X, o, PD * 4, hipMemcpyHostToDevice));
-        if (d.algo == CT_DE) CT_HIP(hipMemcpy(d.member, words.data(), words.size() * 4, hipMemcpyHostToDevice));
+        if (has_rows(d)) {
+            CT_HIP(hipMemcpy(d.prow, rows.data(), rows.size(), hipMemcpyHostToDevice));
+            CT_HIP(hipMemcpy(d.pL, lin.data(), P * 8, hipMemcpyHostToDevice));
+        } else if (d.algo == CT_DE) {
+            CT_HIP(hipMemcpy(d.member, words.data(), words.size() * 4, hipMemcpyHostToDevice));
+        }
     }
     CT_HIP(hipMemcpy(d.state, stt, 16, hipMemcpyHostToDevice));
     CT_HIP(hipMemcpy(d.best, &b, 8, hipMemcpyHostToDevice));

@@ -192,6 +192,10 @@ struct PopDev {
     uint64_t seed;
     uint32_t F_q16, de_method;
     uint32_t de_cross, ga_cross;      // DE: binomial / exponential; GA: crossover operator
+    uint32_t unaware;                 // the non-constraint-aware variant
+    uint8_t* prow;                    // non-aware DE/GA: member rows [P][R] (members may be invalid)
+    uint64_t* pL;                     // non-aware DE/GA: member linear indices [P]
+    uint64_t* tL;                     // non-aware DE: trial linear indices [P] (selection scratch)
     uint64_t CR_q32;
     int64_t w_q16, c1_q16, c2_q16;
     uint64_t mut_thresh;              // floor(2^32 / mutation_chance): a child mutates when its draw is below
@@ -268,7 +272,7 @@ struct ct_batch {
 inline uint32_t de_min_pop(uint32_t method) { return method == CT_DE_RAND2 || method == CT_DE_BEST2 ? 6u : 4u; }
 
 // Device bytes a run of this shape allocates (its buffers and its one-run batch).
-uint64_t pop_footprint_bytes(uint32_t algo, uint32_t P, uint32_t D, uint32_t R, uint64_t n_valid);
+uint64_t pop_footprint_bytes(uint32_t algo, uint32_t P, uint32_t D, uint32_t R, uint64_t n_valid, uint32_t unaware);
 
 // step.hip
 int pop_init_device(ct_pop* p, hipStream_t st);

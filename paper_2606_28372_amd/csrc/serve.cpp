@@ -112,7 +112,7 @@ struct ct_server {
     uint64_t run_bytes(const Run* r, uint64_t n_valid) const {
         const ct_space* s = r->space;
         return space_resident_bytes(s, n_valid) +
-               pop_footprint_bytes(r->prm.algo, r->prm.pop_size, s->D, s->R, n_valid) +
+               pop_footprint_bytes(r->prm.algo, r->prm.pop_size, s->D, s->R, n_valid, r->prm.unaware) +
                std::max<uint64_t>(n_valid, 1) * sizeof(float);
     }
 
@@ -143,7 +143,8 @@ struct ct_server {
             }
             r->n_valid = r->space->n_valid;
             // a population larger than the valid set is cut to it (the initial sample is one member per stratum)
-            if (r->prm.pop_size > r->n_valid) r->prm.pop_size = (uint32_t)r->n_valid;
+            // an aware sample is stratified over the valid list: at most one member per configuration
+            if (!r->prm.unaware && r->prm.pop_size > r->n_valid) r->prm.pop_size = (uint32_t)r->n_valid;
             r->footprint = run_bytes(r, r->n_valid);
             r->sized = true;
             const bool unusable = r->n_valid == 0 || r->n_valid > CT_MAX_VALID ||
@@ -298,6 +299,8 @@ int ct_server_submit(ct_server* s, const int64_t* values, const uint32_t* radice
     if ((prm->algo == CT_DE && (prm->de_method > CT_DE_RANDTOBEST1 || prm->de_crossover > CT_DE_EXP)) ||
         (prm->algo == CT_GA && prm->ga_crossover > CT_GA_DISRUPTIVE_UNIFORM))
         return ct_fail(CT_EINVAL, "ct_server_submit: unknown operator");
+    if (prm->unaware > 1 || (prm->unaware && prm->algo == CT_DE && prm->pop_size > CT_UNAWARE_DE_MAX_POP))
+        return ct_fail(CT_EINVAL, "ct_server_submit: unaware is 0 or 1 (non-aware DE: pop_size <= 8192)");
     ct_space* sp = nullptr;
     int rc = space_prepare(values, radices, n_params, code, cons_offsets, n_cons, &sp);
     if (rc) return rc;

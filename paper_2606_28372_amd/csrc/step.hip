@@ -17,6 +17,12 @@
 //       was brighter at the start of the generation (ascending index) by
 //       B0 exp(-gamma r^2) of the way plus a uniform step of width alpha per
 //       dimension, all in Q16.16 with a Q0.32 exponential.
+//   Non-constraint-aware variants (Sections IV-B and IV-C, last sentences): a
+//       random initial sample over the whole Cartesian space, no repair, and
+//       +infinity as the objective of an invalid configuration.  DE and GA
+//       members are then digit rows (they may be invalid), DE's "best" is the
+//       population's best member, GA ranks by (objective, member index) and
+//       mutates one parameter to another of its values.
 //
 // One generation of a batch of runs is: sort (GA runs, one block each) ->
 // propose (one thread per individual of every run) -> repair passes (shared
@@ -94,6 +100,70 @@ __device__ uint32_t block_sum_u32(uint32_t v) {
     return r;
 }
 
+constexpr uint32_t kNone = 0xFFFFFFFFu;    // position of an invalid configuration
+
+__device__ __forceinline__ float f_inf() { return __int_as_float(0x7F800000); }
+
+// place of linear index L in the valid list, or kNone when L names an invalid configuration
+__device__ __forceinline__ uint32_t pos_of(const DevSpace& S, uint64_t L) {
+    return bit_valid(S, L) ? (uint32_t)rank_dir(S, L) : kNone;
+}
+
+__device__ __forceinline__ float objective_at(const PopDev& p, uint32_t pos) {
+    return pos < p.n_valid ? p.obj[pos] : f_inf();
+}
+
+// word j%4 of the draw behind coordinate j of a non-aware sample (tag 0: the initial one, g + 1:
+// DE's reinitialisation after generation g)
+__device__ __forceinline__ uint32_t sample_word(const PopDev& p, uint32_t i, uint32_t tag, uint32_t j) {
+    const U4 o = ct_philox(p.seed, i, tag, ((uint32_t)PUR_INIT << 24) | (1u + (j >> 2)), 0);
+    const uint32_t t = j & 3u;
+    return t == 0 ? o.x : t == 1 ? o.y : t == 2 ? o.z : o.w;
+}
+
+// Non-aware DE/GA member i drawn uniformly over the Cartesian space into its row; returns its
+// linear index.
+__device__ uint64_t sample_member(const PopDev& p, const DevSpace& S, uint32_t i, uint32_t tag) {
+    uint8_t* row = p.prow + (uint64_t)i * p.R;
+    uint64_t L = 0;
+    for (uint32_t j = 0; j < p.R; ++j) {
+        uint32_t d = 0;
+        if (j < p.D) {
+            d = ct_below(sample_word(p, i, tag, j), gld(&S.radix[j]));
+            L += (uint64_t)d * gld(&S.stride[j]);
+        }
+        row[j] = (uint8_t)d;
+    }
+    return L;
+}
+
+// Non-aware PSO / Firefly particle i: coordinates uniform in [0, M 2^16), written to X (and to
+// the personal best, with zero velocity, for PSO); returns the linear index of the snapped position.
+__device__ uint64_t sample_particle(const PopDev& p, const DevSpace& S, uint32_t i) {
+    uint64_t L = 0;
+    for (uint32_t j = 0; j < p.D; ++j) {
+        const uint32_t x = ct_below(sample_word(p, i, 0, j), p.M * 65536u);
+        const uint32_t r = gld(&S.radix[j]), d = x >> 16;
+        L += (uint64_t)(d < r ? d : r - 1u) * gld(&S.stride[j]);
+        const uint64_t k = (uint64_t)i * p.D + j;
+        p.X[k] = (int32_t)x;
+        if (p.algo == CT_PSO) {
+            p.PB[k] = (int32_t)x;
+            p.V[k] = 0;
+        }
+    }
+    return L;
+}
+
+// Non-aware DE/GA: copy the proposal row of individual i into its member row.
+__device__ __forceinline__ void adopt_row(const PopDev& p, uint32_t i) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(p.trial + (uint64_t)i * p.R);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(p.prow + (uint64_t)i * p.R);
+    for (uint32_t k = 0; k < p.R / 4; ++k) dst[k] = src[k];
+}
+
+__device__ __forceinline__ uint64_t index_key(float f, uint32_t i) { return ((uint64_t)ford(f) << 32) | i; }
+
 __device__ __forceinline__ void valid_row(const PopDev& p, uint32_t pos, Row& r) {
     row_load(r, p.S->rows + (uint64_t)pos * p.R, p.R);
 }
@@ -118,6 +188,22 @@ __device__ __forceinline__ uint32_t find_run(const uint32_t* off, uint32_t n, ui
 __global__ __launch_bounds__(kBlock) void k_init(PopDev p) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p.P) return;
+    if (p.unaware) {
+        const DevSpace& S = *p.S;
+        const bool particle = p.algo == CT_PSO || p.algo == CT_FIREFLY;
+        const uint64_t L = particle ? sample_particle(p, S, i) : sample_member(p, S, i, 0);
+        const uint32_t pos = pos_of(S, L);
+        const float f = objective_at(p, pos);
+        if (p.algo == CT_PSO) {
+            p.f_pb[i] = f;
+            p.pb_pos[i] = pos;
+        } else {
+            p.pos[i] = pos;
+            p.f[i] = f;
+            if (!particle) p.pL[i] = L;
+        }
+        return;
+    }
     uint32_t pos = init_pos(p, i, 0);
     float f = p.obj[pos];
     if (p.algo == CT_PSO) {
@@ -146,10 +232,13 @@ __global__ __launch_bounds__(kBlock) void k_init(PopDev p) {
 }
 
 __global__ __launch_bounds__(kSelBlock) void k_init_finish(PopDev p) {
-    uint64_t m = ~0ull;
-    for (uint32_t i = threadIdx.x; i < p.P; i += blockDim.x)
-        m = min(m, p.algo == CT_PSO ? (((uint64_t)ford(p.f_pb[i]) << 32) | i) : best_key(p.f[i], p.pos[i]));
+    uint64_t m = ~0ull, mi = ~0ull;
+    for (uint32_t i = threadIdx.x; i < p.P; i += blockDim.x) {
+        m = min(m, p.algo == CT_PSO ? index_key(p.f_pb[i], i) : best_key(p.f[i], p.pos[i]));
+        if (p.algo != CT_PSO) mi = min(mi, index_key(p.f[i], i));
+    }
     m = block_min_u64(m);
+    mi = block_min_u64(mi);
     if (threadIdx.x < 4) p.rcount[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
         p.state[0] = 0;
@@ -160,7 +249,7 @@ __global__ __launch_bounds__(kSelBlock) void k_init_finish(PopDev p) {
             p.state[2] = gi;
             *p.best = best_key(p.f_pb[gi], p.pb_pos[gi]);
         } else {
-            p.state[2] = 0;
+            p.state[2] = p.unaware && p.algo == CT_DE ? (uint32_t)mi : 0u;   // non-aware DE's best member
             *p.best = m;
         }
     }
@@ -214,6 +303,17 @@ __device__ __forceinline__ uint32_t row_digit(const DevSpace& S, uint32_t pos, u
     return gld(S.rows + (uint64_t)pos * R + j);
 }
 
+// digit j of member m: its row for the non-aware variant (members may be invalid), else its valid
+// configuration
+__device__ __forceinline__ uint32_t member_digit(const PopDev& p, const DevSpace& S, uint32_t m, uint32_t j) {
+    return p.unaware ? (uint32_t)gld(p.prow + (uint64_t)m * p.R + j) : row_digit(S, gld(p.pos + m), p.R, j);
+}
+
+// digit j of a GA rank-order entry: a member index (non-aware) or a valid-list position
+__device__ __forceinline__ uint32_t parent_digit(const PopDev& p, const DevSpace& S, uint32_t e, uint32_t j) {
+    return p.unaware ? (uint32_t)gld(p.prow + (uint64_t)e * p.R + j) : row_digit(S, e, p.R, j);
+}
+
 __device__ __forceinline__ uint32_t beta_rank(const PopDev& p, uint32_t u) {
     uint32_t lo = 0, hi = p.P - 1;
     while (lo < hi) {
@@ -250,10 +350,12 @@ __device__ __forceinline__ uint32_t propose_digit(const PopDev& p, const DevSpac
             }
         }
         const uint32_t jr = ct_below(o.w, p.D);
-        const int64_t best = row_digit(S, (uint32_t)(gld(p.best) & 0xFFFFFFFFu), p.R, j);
-        const int64_t x = row_digit(S, gld(p.pos + i), p.R, j);
-        const int64_t x1 = row_digit(S, gld(p.pos + r[0]), p.R, j);
-        const int64_t x2 = row_digit(S, gld(p.pos + r[1]), p.R, j), x3 = row_digit(S, gld(p.pos + r[2]), p.R, j);
+        // the best configuration so far (non-aware: the population's best member)
+        const int64_t best = p.unaware ? member_digit(p, S, gld(p.state + 2), j)
+                                       : row_digit(S, (uint32_t)(gld(p.best) & 0xFFFFFFFFu), p.R, j);
+        const int64_t x = member_digit(p, S, i, j);
+        const int64_t x1 = member_digit(p, S, r[0], j);
+        const int64_t x2 = member_digit(p, S, r[1], j), x3 = member_digit(p, S, r[2], j);
         int64_t base, diff = x2 - x3;
         if (meth == CT_DE_RAND1) base = x1;
         else if (meth == CT_DE_BEST1) base = best;
@@ -261,7 +363,7 @@ __device__ __forceinline__ uint32_t propose_digit(const PopDev& p, const DevSpac
         else if (meth == CT_DE_RANDTOBEST1) { base = x1; diff += best - x1; }
         else {
             base = meth == CT_DE_RAND2 ? x1 : best;
-            diff += (int64_t)row_digit(S, gld(p.pos + r[3]), p.R, j) - (int64_t)row_digit(S, gld(p.pos + r[4]), p.R, j);
+            diff += (int64_t)member_digit(p, S, r[3], j) - (int64_t)member_digit(p, S, r[4], j);
         }
         const int64_t num = base * 65536 + (int64_t)p.F_q16 * diff + 32768;
         int64_t m = num >> 16;            // floor
@@ -323,7 +425,7 @@ __device__ __forceinline__ uint32_t propose_digit(const PopDev& p, const DevSpac
         even_a = ((t == 0 ? x.x : t == 1 ? x.y : t == 2 ? x.z : x.w) >> 31) == 0u;
     } else if (p.ga_cross == CT_GA_DISRUPTIVE_UNIFORM) {
         // of the genes where the parents differ, the half with the smallest keys come from B
-        const uint32_t aj = row_digit(S, pa, p.R, j), bj = row_digit(S, pb, p.R, j);
+        const uint32_t aj = parent_digit(p, S, pa, j), bj = parent_digit(p, S, pb, j);
         even_a = true;
         if (aj != bj) {
             const U4 kj4 = ct_philox(p.seed, k, g, ((uint32_t)PUR_GA_XO << 24) | (j >> 2), 1);
@@ -331,7 +433,7 @@ __device__ __forceinline__ uint32_t propose_digit(const PopDev& p, const DevSpac
             const uint32_t kj = t == 0 ? kj4.x : t == 1 ? kj4.y : t == 2 ? kj4.z : kj4.w;
             uint32_t n_diff = 0, rank = 0;
             for (uint32_t q = 0; q < p.D; ++q) {
-                if (row_digit(S, pa, p.R, q) == row_digit(S, pb, p.R, q)) continue;
+                if (parent_digit(p, S, pa, q) == parent_digit(p, S, pb, q)) continue;
                 ++n_diff;
                 const U4 kq4 = ct_philox(p.seed, k, g, ((uint32_t)PUR_GA_XO << 24) | (q >> 2), 1);
                 const uint32_t tq = q & 3u;
@@ -351,7 +453,16 @@ __device__ __forceinline__ uint32_t propose_digit(const PopDev& p, const DevSpac
         even_a = j < 1u + ct_below(o.z, p.D - 1u);
     }
     const bool from_a = even_a != ((i & 1u) != 0);
-    return row_digit(S, from_a ? pa : pb, p.R, j);
+    uint32_t c = parent_digit(p, S, from_a ? pa : pb, j);
+    if (p.unaware) {
+        // with chance 1/mutation_chance one parameter (word 1) takes another of its values (word 2)
+        const U4 m = ct_philox(p.seed, i, g, (uint32_t)PUR_GA_MUT << 24, 0);
+        if ((uint64_t)m.x < p.mut_thresh && j == ct_below(m.y, p.D) && radix > 1) {
+            const uint32_t v = ct_below(m.z, radix - 1u);
+            c = v >= c ? v + 1u : v;
+        }
+    }
+    return c;
 }
 
 // Proposals of every run, one group of G lanes per individual, each proposal listed for the main
@@ -423,11 +534,13 @@ __global__ __launch_bounds__(kBlock) void k_propose(const PopDev* __restrict__ p
         }
         if (slot == 0) {
             if (p.algo == CT_GA) {
+                // the non-aware GA mutated in the proposal: the mutation pass skips its children
                 const U4 m = ct_philox(p.seed, i, g, (uint32_t)PUR_GA_MUT << 24, 0);
-                p.apply[i] = (uint64_t)m.x < p.mut_thresh;
+                p.apply[i] = !p.unaware && (uint64_t)m.x < p.mut_thresh;
             }
-            J.out_pos[i] = valid ? (uint32_t)rank : 0xFFFFFFFFu;
-            if (!valid) {
+            if (p.unaware && p.algo == CT_DE) p.tL[i] = L;
+            J.out_pos[i] = valid ? (uint32_t)rank : kNone;
+            if (!valid && !p.unaware) {
                 const uint32_t k = atomicAdd(&J.count[0], 1u);
                 J.list[k] = i;
                 J.list_ins[k] = dom ? rank : ~0ull;
@@ -528,6 +641,13 @@ void launch_ff_move(const ct_batch* b, hipStream_t st) {
 // Returns, in thread 0 when the population fits the block, the smallest key (the rank-0
 // individual's); `own`, when given, is the calling thread's individual's key (individual
 // threadIdx.x), so it need not be read back from memory.
+// GA rank-sort key of member i: (objective, position), or (objective, member index) for the
+// non-aware variant, whose members need not have a position; the low word is what the rank order
+// holds (a position, or a member index)
+__device__ __forceinline__ uint64_t ga_key(const PopDev& p, uint32_t i) {
+    return p.unaware ? index_key(p.f[i], i) : best_key(p.f[i], p.pos[i]);
+}
+
 __device__ uint64_t ga_sort_block(const PopDev& p, const uint64_t* own = nullptr) {
     __shared__ uint64_t key[kGaMaxSort];
     uint32_t m = 1;
@@ -540,7 +660,7 @@ __device__ uint64_t ga_sort_block(const PopDev& p, const uint64_t* own = nullptr
         // run's go first), so each round is one binary search and one barrier, not a series of
         // exchange stages.
         const uint32_t i = threadIdx.x;
-        uint64_t v = i < p.P ? (own ? *own : best_key(p.f[i], p.pos[i])) : ~0ull;
+        uint64_t v = i < p.P ? (own ? *own : ga_key(p, i)) : ~0ull;
         const uint32_t w = m < 64 ? m : 64;
         for (uint32_t k = 2; k <= w; k <<= 1) {
             for (uint32_t j = k >> 1; j > 0; j >>= 1) {
@@ -587,7 +707,7 @@ __device__ uint64_t ga_sort_block(const PopDev& p, const uint64_t* own = nullptr
 #pragma unroll
         for (uint32_t r = 0; r < kMaxPerThread; ++r) {
             const uint32_t i = base + 64u * r;
-            v[r] = r < q && i < p.P ? best_key(p.f[i], p.pos[i]) : ~0ull;
+            v[r] = r < q && i < p.P ? ga_key(p, i) : ~0ull;
         }
         for (uint32_t k = 2; k <= m; k <<= 1) {
             uint32_t j = k >> 1;
@@ -631,7 +751,7 @@ __device__ uint64_t ga_sort_block(const PopDev& p, const uint64_t* own = nullptr
         }
         return ~0ull;
     }
-    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) key[i] = i < p.P ? best_key(p.f[i], p.pos[i]) : ~0ull;
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) key[i] = i < p.P ? ga_key(p, i) : ~0ull;
     __syncthreads();
     for (uint32_t k = 2; k <= m; k <<= 1) {
         for (uint32_t j = k >> 1; j > 0; j >>= 1) {
@@ -717,6 +837,94 @@ __device__ void de_select(const PopDev& p) {
     }
 }
 
+// Non-aware DE selection (population <= 8,192: at most 8 members per thread, one bit each in
+// `pre` and `lost`).  Trial u_i replaces x_i when f(u_i) <= f(x_i) and no member has u_i's
+// configuration; of equal trials the lowest index wins.  Both tests compare linear indices,
+// member ones and trial ones, chunk by chunk through LDS (P^2 / 1,024 comparisons a thread).
+__device__ void de_select_unaware(const PopDev& p) {
+    __shared__ uint64_t chunk[kSelBlock];
+    const DevSpace& S = *p.S;
+    const uint32_t g = p.state[0];
+    const uint32_t per = (p.P + blockDim.x - 1) / blockDim.x;
+    uint32_t pre = 0, lost = 0;
+    for (uint32_t k = 0; k < per; ++k) {
+        const uint32_t i = threadIdx.x + k * blockDim.x;
+        if (i < p.P && objective_at(p, p.tpos[i]) <= p.f[i]) pre |= 1u << k;
+    }
+    for (uint32_t c0 = 0; c0 < p.P; c0 += blockDim.x) {
+        const uint32_t n = min(blockDim.x, p.P - c0);
+        __syncthreads();
+        if (threadIdx.x < n) chunk[threadIdx.x] = p.pL[c0 + threadIdx.x];
+        __syncthreads();
+        for (uint32_t k = 0; k < per; ++k) {
+            if (!((pre >> k) & 1u)) continue;
+            const uint64_t L = p.tL[threadIdx.x + k * blockDim.x];
+            bool hit = false;
+            for (uint32_t t = 0; t < n; ++t) hit |= chunk[t] == L;
+            if (hit) pre &= ~(1u << k);
+        }
+    }
+    for (uint32_t k = 0; k < per; ++k) {
+        const uint32_t i = threadIdx.x + k * blockDim.x;
+        if (i < p.P) p.apply[i] = (pre >> k) & 1u;
+    }
+    for (uint32_t c0 = 0; c0 < p.P; c0 += blockDim.x) {
+        const uint32_t n = min(blockDim.x, p.P - c0);
+        __syncthreads();
+        if (threadIdx.x < n) chunk[threadIdx.x] = p.apply[c0 + threadIdx.x] ? p.tL[c0 + threadIdx.x] : ~0ull;
+        __syncthreads();
+        for (uint32_t k = 0; k < per; ++k) {
+            const uint32_t i = threadIdx.x + k * blockDim.x;
+            if (!((pre >> k) & 1u) || c0 >= i) continue;
+            const uint64_t L = p.tL[i];
+            const uint32_t lim = min(n, i - c0);          // earlier individuals only
+            bool hit = false;
+            for (uint32_t t = 0; t < lim; ++t) hit |= chunk[t] == L;
+            if (hit) lost |= 1u << k;
+        }
+    }
+    const uint32_t acc_bits = pre & ~lost;
+    const uint32_t acc = block_sum_u32((uint32_t)__popc(acc_bits));
+    uint64_t m = ~0ull, mi = ~0ull;
+    for (uint32_t k = 0; k < per; ++k) {
+        const uint32_t i = threadIdx.x + k * blockDim.x;
+        if (i >= p.P) continue;
+        if ((acc_bits >> k) & 1u) {
+            adopt_row(p, i);
+            p.pL[i] = p.tL[i];
+            p.pos[i] = p.tpos[i];
+            p.f[i] = objective_at(p, p.tpos[i]);
+        }
+        m = min(m, best_key(p.f[i], p.pos[i]));
+        mi = min(mi, index_key(p.f[i], i));
+    }
+    m = block_min_u64(m);
+    mi = block_min_u64(mi);
+    if (acc == 0) {
+        // no member replaced: a new random population (tag g + 1)
+        uint64_t m2 = ~0ull, mi2 = ~0ull;
+        for (uint32_t i = threadIdx.x; i < p.P; i += blockDim.x) {
+            const uint64_t L = sample_member(p, S, i, g + 1);
+            const uint32_t t = pos_of(S, L);
+            p.pL[i] = L;
+            p.pos[i] = t;
+            p.f[i] = objective_at(p, t);
+            m2 = min(m2, best_key(p.f[i], t));
+            mi2 = min(mi2, index_key(p.f[i], i));
+        }
+        m = min(m, block_min_u64(m2));
+        mi = block_min_u64(mi2);
+    }
+    if (threadIdx.x == 0) {
+        const uint64_t b = *p.best;
+        *p.best = m < b ? m : b;
+        p.state[2] = (uint32_t)mi;
+        p.state[3] = acc;
+        if (acc == 0) p.state[1] += 1;
+        p.state[0] = g + 1;
+    }
+}
+
 __device__ void pso_select(const PopDev& p) {
     const uint32_t g = p.state[0];
     uint64_t m = ~0ull;
@@ -744,9 +952,10 @@ __device__ void ff_select(const PopDev& p) {
     uint64_t m = ~0ull;
     for (uint32_t i = threadIdx.x; i < p.P; i += blockDim.x) {
         uint32_t t = p.tpos[i];
-        if (t >= p.n_valid) t = p.pos[i];      // unreachable: every evaluation goes to a valid configuration
+        // aware: unreachable, every evaluation goes to a valid configuration; non-aware: +inf
+        if (t >= p.n_valid && !p.unaware) t = p.pos[i];
         p.pos[i] = t;
-        p.f[i] = p.obj[t];
+        p.f[i] = objective_at(p, t);
         m = min(m, best_key(p.f[i], t));
         for (uint32_t j = 0; j < p.D; ++j) p.X[(uint64_t)i * p.D + j] = p.Xn[(uint64_t)i * p.D + j];
     }
@@ -758,15 +967,23 @@ __device__ void ff_select(const PopDev& p) {
     }
 }
 
+// child i becomes member i: its position (non-aware: kNone if invalid, and its row) and objective
+__device__ __forceinline__ float ga_adopt(const PopDev& p, uint32_t i) {
+    uint32_t t = p.tpos[i];
+    if (p.unaware) adopt_row(p, i);
+    else if (t >= p.n_valid) t = p.pos[i];             // unreachable: every repaired child is valid
+    const float fv = objective_at(p, t);
+    p.pos[i] = t;
+    p.f[i] = fv;
+    return fv;
+}
+
 __device__ void ga_select(const PopDev& p) {
     const uint32_t g = p.state[0];
     uint64_t m = ~0ull;
     for (uint32_t i = threadIdx.x; i < p.P; i += blockDim.x) {
-        uint32_t t = p.tpos[i];
-        if (t >= p.n_valid) t = p.pos[i];      // unreachable: every repaired child is valid
-        p.pos[i] = t;
-        p.f[i] = p.obj[t];
-        m = min(m, best_key(p.f[i], t));
+        ga_adopt(p, i);
+        m = min(m, best_key(p.f[i], p.pos[i]));
     }
     m = block_min_u64(m);
     if (threadIdx.x == 0) {
@@ -778,24 +995,23 @@ __device__ void ga_select(const PopDev& p) {
 
 __global__ __launch_bounds__(kSelBlock) void k_select(const PopDev* __restrict__ pops, uint32_t n) {
     const PopDev& p = pops[blockIdx.x];
-    if (p.algo == CT_DE) de_select(p);
+    if (p.algo == CT_DE && p.unaware) de_select_unaware(p);
+    else if (p.algo == CT_DE) de_select(p);
     else if (p.algo == CT_PSO) pso_select(p);
     else if (p.algo == CT_FIREFLY) ff_select(p);
     else if (p.P <= blockDim.x) {
         // one child per thread: its key goes to the rank sort (the next generation's rank order)
         // in a register, and the sorted order's first key is the generation's best
         const uint32_t g = p.state[0];
-        uint64_t k = ~0ull;
+        uint64_t k = ~0ull, bk = ~0ull;
         const uint32_t i = threadIdx.x;
         if (i < p.P) {
-            uint32_t t = p.tpos[i];
-            if (t >= p.n_valid) t = p.pos[i];            // unreachable: every repaired child is valid
-            const float fv = p.obj[t];
-            p.pos[i] = t;
-            p.f[i] = fv;
-            k = best_key(fv, t);
+            const float fv = ga_adopt(p, i);
+            bk = best_key(fv, p.pos[i]);
+            k = p.unaware ? index_key(fv, i) : bk;
         }
-        const uint64_t m = ga_sort_block(p, &k);
+        uint64_t m = ga_sort_block(p, &k);
+        if (p.unaware) m = block_min_u64(bk);            // the sort keys hold member indices
         if (threadIdx.x == 0) {
             const uint64_t b = *p.best;
             *p.best = m < b ? m : b;

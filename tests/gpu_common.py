@@ -41,9 +41,10 @@ def digits_to_rows(sp_gpu, digits):
 
 def parse_snapshot(blob, algo, P, D):
     h = struct.unpack_from("<8I", blob, 0)
-    assert h[0] == 0x43545031 and h[1] == algo and h[2] == P and h[3] == D
+    assert h[0] in (0x43545031, 0x43545531) and h[1] == algo and h[2] == P and h[3] == D
+    unaware = h[0] == 0x43545531
     o = 32
-    out = {"gen": h[4], "reinits": h[5], "best_pos": h[6], "best_ord": h[7]}
+    out = {"gen": h[4], "reinits": h[5], "best_pos": h[6], "best_ord": h[7], "unaware": unaware}
     if algo == 1:
         PD = P * D
         out["X"] = np.frombuffer(blob, dtype=np.int32, count=PD, offset=o).reshape(P, D).astype(np.int64); o += PD * 4
@@ -57,4 +58,6 @@ def parse_snapshot(blob, algo, P, D):
         out["f"] = np.frombuffer(blob, dtype=np.float32, count=P, offset=o).copy(); o += P * 4
         if algo == 3:
             out["X"] = np.frombuffer(blob, dtype=np.int32, count=P * D, offset=o).reshape(P, D).astype(np.int64)
+        elif unaware:
+            out["rows"] = np.frombuffer(blob, dtype=np.uint8, count=P * D, offset=o).reshape(P, D).astype(np.int32)
     return out
