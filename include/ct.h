@@ -367,6 +367,17 @@ int ct_batch_tuning(const ct_batch* b, uint32_t* items, uint32_t* min_boxes, uin
 int ct_pop_read(const ct_pop* p, uint32_t* h_pos, float* h_f, uint32_t* best_pos, float* best_f,
                 uint32_t* generation, uint32_t* reinits);
 
+/*
+ * ct_pop_evaluated -- the configurations the last generation evaluated (after creation: the
+ * initial population), as valid-list positions, one per individual in individual order
+ * (h_pos[pop_size]): DE's trials after repair, PSO's and Firefly's evaluated (repaired) positions,
+ * GA's children after repair and mutation; 0xFFFFFFFF for an invalid configuration of a
+ * non-aware run.  A DE generation that reinitialised its population (the reinits counter of
+ * ct_pop_read went up) then evaluated the new members too: ct_pop_read's positions.
+ * Synchronises.  After ct_pop_restore the output is undefined until the next generation.
+ */
+int ct_pop_evaluated(const ct_pop* p, uint32_t* h_pos);
+
 /* Cumulative number of configurations the run has sent through a repair scan
    (invalid proposals) and through a mutation scan (GA).  Synchronises. */
 int ct_pop_counters(const ct_pop* p, uint64_t* repairs, uint64_t* mutations);

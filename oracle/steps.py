@@ -124,13 +124,14 @@ class DEState:
     best_pos: int
     gen: int = 0
     reinits: int = 0
+    evaluated: Optional[np.ndarray] = None   # positions the last step evaluated (trials after repair)
 
 
 def de_init(space, obj, P, seed) -> DEState:
     pos = init_positions(space, P, seed, 0)
     f = obj[pos].astype(np.float32)
     b = min(zip(f.tolist(), pos.tolist()))
-    return DEState(pos, f, np.float32(b[0]), int(b[1]))
+    return DEState(pos, f, np.float32(b[0]), int(b[1]), evaluated=pos.copy())
 
 
 def de_picks(seed: int, i: int, g: int, P: int, k: int) -> List[int]:
@@ -234,7 +235,7 @@ def de_step(space: core.Space, obj: np.ndarray, st: DEState, seed: int, F_q16: i
         for i in range(P):
             best = _lexmin(best, (float(new_f[i]), int(new_pos[i])))
         reinits += 1
-    return DEState(new_pos, new_f, np.float32(best[0]), int(best[1]), g + 1, reinits)
+    return DEState(new_pos, new_f, np.float32(best[0]), int(best[1]), g + 1, reinits, evaluated=upos.copy())
 
 
 # ---------------------------------------------------------------------------
@@ -250,6 +251,7 @@ class PSOState:
     pb_pos: np.ndarray         # valid-list position evaluated at the personal best
     g_idx: int                 # particle holding the global best
     gen: int = 0
+    evaluated: Optional[np.ndarray] = None   # positions the last step evaluated (after Alg. 2)
 
     @property
     def best_f(self):
@@ -272,7 +274,7 @@ def pso_init(space, obj, P, seed) -> PSOState:
     pos = init_positions(space, P, seed, 0)
     X = centre_q16(space.vrows[pos])
     f = obj[pos].astype(np.float32)
-    return PSOState(X.copy(), np.zeros_like(X), X.copy(), f.copy(), pos.copy(), _gbest(f))
+    return PSOState(X.copy(), np.zeros_like(X), X.copy(), f.copy(), pos.copy(), _gbest(f), evaluated=pos.copy())
 
 
 def pso_move(space: core.Space, st: PSOState, seed: int, w_q16: int, c1_q16: int, c2_q16: int):
@@ -312,7 +314,7 @@ def pso_step(space: core.Space, obj: np.ndarray, st: PSOState, seed: int, w_q16:
     for i in range(P):
         if f[i] < f_pb[i]:
             PB[i], f_pb[i], pb_pos[i] = X[i], f[i], epos[i]
-    return PSOState(X, V, PB, f_pb, pb_pos, _gbest(f_pb), g + 1)
+    return PSOState(X, V, PB, f_pb, pb_pos, _gbest(f_pb), g + 1, evaluated=epos.copy())
 
 
 # ---------------------------------------------------------------------------
@@ -326,13 +328,14 @@ class GAState:
     best_f: float
     best_pos: int
     gen: int = 0
+    evaluated: Optional[np.ndarray] = None   # positions the last step evaluated (the children)
 
 
 def ga_init(space, obj, P, seed) -> GAState:
     pos = init_positions(space, P, seed, 0)
     f = obj[pos].astype(np.float32)
     b = min(zip(f.tolist(), pos.tolist()))
-    return GAState(pos, f, np.float32(b[0]), int(b[1]))
+    return GAState(pos, f, np.float32(b[0]), int(b[1]), evaluated=pos.copy())
 
 
 def ga_cross_pair(A: np.ndarray, B: np.ndarray, seed: int, k: int, g: int, o: List[int], method: int):
@@ -405,7 +408,7 @@ def ga_step(space: core.Space, obj: np.ndarray, st: GAState, seed: int, mutation
     best = (float(st.best_f), st.best_pos)
     for i in range(P):
         best = _lexmin(best, (float(f[i]), int(pos[i])))
-    return GAState(pos, f, np.float32(best[0]), int(best[1]), g + 1)
+    return GAState(pos, f, np.float32(best[0]), int(best[1]), g + 1, evaluated=pos.copy())
 
 
 def ga_children(space: core.Space, obj: np.ndarray, st: GAState, seed: int, mutation_chance: int, beta_b: int,
@@ -477,6 +480,7 @@ class FFState:
     best_f: float
     best_pos: int
     gen: int = 0
+    evaluated: Optional[np.ndarray] = None   # positions the last step evaluated (= pos)
 
 
 def ff_init(space, obj, P, seed) -> FFState:
@@ -484,7 +488,7 @@ def ff_init(space, obj, P, seed) -> FFState:
     X = centre_q16(space.vrows[pos])
     f = obj[pos].astype(np.float32)
     b = min(zip(f.tolist(), pos.tolist()))
-    return FFState(X, f, pos.copy(), np.float32(b[0]), int(b[1]))
+    return FFState(X, f, pos.copy(), np.float32(b[0]), int(b[1]), evaluated=pos.copy())
 
 
 def ff_move(space: core.Space, st: FFState, seed: int, B0_q16: int, gamma_q16: int, alpha_q16: int) -> np.ndarray:
@@ -534,7 +538,8 @@ def ff_step(space: core.Space, obj: np.ndarray, st: FFState, seed: int, B0_q16: 
     best = (float(st.best_f), st.best_pos)
     for i in range(P):
         best = _lexmin(best, (float(f[i]), int(epos[i])))
-    return FFState(Xn, f, epos.astype(np.int64), np.float32(best[0]), int(best[1]), g + 1)
+    return FFState(Xn, f, epos.astype(np.int64), np.float32(best[0]), int(best[1]), g + 1,
+                   evaluated=epos.astype(np.int64))
 
 
 # ---------------------------------------------------------------------------
@@ -629,13 +634,14 @@ class UState:
     best_pos: int
     gen: int = 0
     reinits: int = 0
+    evaluated: Optional[np.ndarray] = None   # positions the last step evaluated (NONE if invalid)
 
 
 def u_init(space, obj, P, seed) -> UState:
     rows = random_rows(space, P, seed, 0)
     pos, f = evaluate(space, obj, rows)
     b = _best((np.inf, NONE), f, pos)
-    return UState(rows, pos, f, np.float32(b[0]), int(b[1]))
+    return UState(rows, pos, f, np.float32(b[0]), int(b[1]), evaluated=pos.copy())
 
 
 def _pop_best(f) -> int:
@@ -696,7 +702,7 @@ def ude_step(space: core.Space, obj: np.ndarray, st: UState, seed: int, F_q16: i
         pos, f = evaluate(space, obj, rows)
         best = _best(best, f, pos)
         reinits += 1
-    return UState(rows, pos, f, np.float32(best[0]), int(best[1]), g + 1, reinits)
+    return UState(rows, pos, f, np.float32(best[0]), int(best[1]), g + 1, reinits, evaluated=upos.copy())
 
 
 def uga_step(space: core.Space, obj: np.ndarray, st: UState, seed: int, mutation_chance: int, beta_b: int,
@@ -727,14 +733,14 @@ def uga_step(space: core.Space, obj: np.ndarray, st: UState, seed: int, mutation
                 kids[i, j] = v + 1 if v >= kids[i, j] else v
     pos, f = evaluate(space, obj, kids)
     best = _best((float(st.best_f), st.best_pos), f, pos)
-    return UState(kids, pos, f, np.float32(best[0]), int(best[1]), g + 1)
+    return UState(kids, pos, f, np.float32(best[0]), int(best[1]), g + 1, evaluated=pos.copy())
 
 
 def upso_init(space, obj, P, seed) -> PSOState:
     X = random_coords(space, P, seed)
     snapped = np.minimum(X >> 16, space.radices.astype(np.int64) - 1)
     pos, f = evaluate(space, obj, snapped)
-    return PSOState(X.copy(), np.zeros_like(X), X.copy(), f.copy(), pos.copy(), _gbest(f))
+    return PSOState(X.copy(), np.zeros_like(X), X.copy(), f.copy(), pos.copy(), _gbest(f), evaluated=pos.copy())
 
 
 def upso_step(space: core.Space, obj: np.ndarray, st: PSOState, seed: int, w_q16: int, c1_q16: int,
@@ -746,7 +752,7 @@ def upso_step(space: core.Space, obj: np.ndarray, st: PSOState, seed: int, w_q16
     for i in range(X.shape[0]):
         if f[i] < f_pb[i]:
             PB[i], f_pb[i], pb_pos[i] = X[i], f[i], epos[i]
-    return PSOState(X, V, PB, f_pb, pb_pos, _gbest(f_pb), st.gen + 1)
+    return PSOState(X, V, PB, f_pb, pb_pos, _gbest(f_pb), st.gen + 1, evaluated=epos.copy())
 
 
 def uff_init(space, obj, P, seed) -> FFState:
@@ -754,7 +760,7 @@ def uff_init(space, obj, P, seed) -> FFState:
     snapped = np.minimum(X >> 16, space.radices.astype(np.int64) - 1)
     pos, f = evaluate(space, obj, snapped)
     b = _best((np.inf, NONE), f, pos)
-    return FFState(X, f, pos, np.float32(b[0]), int(b[1]))
+    return FFState(X, f, pos, np.float32(b[0]), int(b[1]), evaluated=pos.copy())
 
 
 def uff_step(space: core.Space, obj: np.ndarray, st: FFState, seed: int, B0_q16: int, gamma_q16: int,
@@ -764,4 +770,4 @@ def uff_step(space: core.Space, obj: np.ndarray, st: FFState, seed: int, B0_q16:
     snapped = np.minimum(Xn >> 16, space.radices.astype(np.int64) - 1)
     pos, f = evaluate(space, obj, snapped)
     best = _best((float(st.best_f), st.best_pos), f, pos)
-    return FFState(Xn, f, pos, np.float32(best[0]), int(best[1]), st.gen + 1)
+    return FFState(Xn, f, pos, np.float32(best[0]), int(best[1]), st.gen + 1, evaluated=pos.copy())

@@ -269,6 +269,18 @@ class Pop:
         return {"pos": pos, "f": f, "best_pos": int(bp.value), "best_f": np.float32(bf.value),
                 "generation": int(g.value), "reinits": int(r.value)}
 
+    def evaluated(self) -> np.ndarray:
+        """Valid-list positions the last generation evaluated (0xFFFFFFFF: invalid, non-aware)."""
+        pos = np.zeros(self.pop_size, dtype=np.uint32)
+        _lib.check(_lib.load().ct_pop_evaluated(self._h, pos.ctypes.data))
+        return pos
+
+    def best(self):
+        """(position, objective) of the best configuration evaluated so far (synchronises)."""
+        bp, bf = ctypes.c_uint32(), ctypes.c_float()
+        _lib.check(_lib.load().ct_pop_read(self._h, None, None, ctypes.byref(bp), ctypes.byref(bf), None, None))
+        return int(bp.value), float(np.float32(bf.value))
+
     def counters(self) -> Dict[str, int]:
         r, m = ctypes.c_uint64(), ctypes.c_uint64()
         _lib.check(_lib.load().ct_pop_counters(self._h, ctypes.byref(r), ctypes.byref(m)))

@@ -82,6 +82,7 @@ SIGNATURES = {
     "ct_step": (_i32, [_P(_vp), _u32, _u32, _u32, _vp]),
     "ct_pop_read": (_i32, [_vp, _vp, _vp, _P(_u32), _P(ctypes.c_float), _P(_u32), _P(_u32)]),
     "ct_pop_counters": (_i32, [_vp, _P(_u64), _P(_u64)]),
+    "ct_pop_evaluated": (_i32, [_vp, _vp]),
     "ct_batch_create": (_i32, [_P(_vp), _u32, _P(_vp)]),
     "ct_batch_step": (_i32, [_vp, _u32, _u32, _vp]),
     "ct_batch_free": (None, [_vp]),

@@ -895,6 +895,13 @@ int ct_pop_read(const ct_pop* p, uint32_t* h_pos, float* h_f, uint32_t* best_pos
     return CT_OK;
 }
 
+int ct_pop_evaluated(const ct_pop* p, uint32_t* h_pos) {
+    if (!p || !h_pos) return ct_fail(CT_EINVAL, "ct_pop_evaluated: null argument");
+    CT_HIP(hipDeviceSynchronize());
+    CT_HIP(hipMemcpy(h_pos, p->dev.tpos, p->dev.P * 4, hipMemcpyDeviceToHost));
+    return CT_OK;
+}
+
 int ct_pop_counters(const ct_pop* p, uint64_t* repairs, uint64_t* mutations) {
     if (!p) return ct_fail(CT_EINVAL, "ct_pop_counters: null population");
     unsigned long long t[2];

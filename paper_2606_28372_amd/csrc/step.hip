@@ -194,6 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_init(PopDev p) {
         const uint64_t L = particle ? sample_particle(p, S, i) : sample_member(p, S, i, 0);
         const uint32_t pos = pos_of(S, L);
         const float f = objective_at(p, pos);
+        p.tpos[i] = pos;                                  // the configurations generation 0 evaluated
         if (p.algo == CT_PSO) {
             p.f_pb[i] = f;
             p.pb_pos[i] = pos;
@@ -206,6 +207,7 @@ __global__ __launch_bounds__(kBlock) void k_init(PopDev p) {
     }
     uint32_t pos = init_pos(p, i, 0);
     float f = p.obj[pos];
+    p.tpos[i] = pos;
     if (p.algo == CT_PSO) {
         Row r;
         valid_row(p, pos, r);

@@ -52,8 +52,9 @@ def check_space(spec, osp=None):
     return sp, osp
 
 
-@pytest.mark.parametrize("name", ["tiny", "gemm10", "gemm13"])
+@pytest.mark.parametrize("name", ["tiny", "gemm10", "gemm13"] + list(W.BAT_SPACES))
 def test_space_build_parity(name):
+    """The GEMM-like spaces and the four Table III stand-ins (hotspot: 22.2M configurations)."""
     check_space(W.space(name), oracle_space(name))
 
 

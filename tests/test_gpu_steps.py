@@ -41,6 +41,10 @@ def oracle_step(osp, obj, st, opt):
 def compare(pop, st, opt, D, where):
     g = parse_snapshot(pop.snapshot(), opt.algo, opt.pop_size, D)
     assert g["gen"] == st.gen, where
+    if getattr(st, "evaluated", None) is not None:
+        # the configurations the last step evaluated (ct_pop_evaluated)
+        bad = np.flatnonzero(pop.evaluated() != st.evaluated)
+        assert len(bad) == 0, f"{where}: evaluated positions differ at {bad[:5].tolist()}"
     if opt.algo == W.ALGO_PSO:
         for k in ("X", "V", "PB"):
             bad = np.argwhere(g[k] != getattr(st, k))

@@ -160,7 +160,123 @@ def wide20() -> SpaceSpec:
     )
 
 
-SPACES = {"tiny": tiny, "gemm10": gemm10, "gemm13": gemm13, "sparse16": sparse16, "wide20": wide20}
+# ---------------------------------------------------------------------------
+# Stand-ins for the four real-world spaces of Table III (dedispersion, 2D
+# convolution, hotspot, GEMM).  Their parameter lists and constraints are not
+# published; each stand-in keeps the table's number of parameters, values per
+# parameter (so the Cartesian size is exact), number of constraints and, with
+# constraint bounds chosen for it, a density close to the table's:
+#   dedispersion  22,272 configurations, 10,780 valid (48.40%; table 49.97%)
+#   convolution   10,240 configurations,  4,338 valid (42.36%; table 42.60%)
+#   hotspot   22,200,000 configurations, 344,576 valid (1.552%; table 1.576%)
+#   GEMM         663,552 configurations, 114,768 valid (17.30%; table 17.62%)
+# ---------------------------------------------------------------------------
+
+def bat_dedispersion() -> SpaceSpec:
+    """8 parameters (1 to 29 values), 3 constraints."""
+    return SpaceSpec(
+        "bat_dedispersion",
+        {
+            "block_size_x": [1, 2, 4, 8] + [16 * k for k in range(1, 26)],
+            "block_size_y": [4, 8, 16],
+            "tile_stride_x": [0, 1],
+            "tile_stride_y": [0, 1],
+            "tile_size_x": [1, 2, 3, 4],
+            "tile_size_y": [1, 2, 4, 8],
+            "loop_unroll_factor_channel": [0, 1, 2, 4],
+            "blocks_per_sm": [0],
+        },
+        [
+            "32 <= block_size_x*block_size_y <= 2048",
+            "tile_size_x > 1 or tile_stride_x == 0",
+            "tile_size_y > 1 or tile_stride_y == 0",
+        ],
+    )
+
+
+def bat_convolution() -> SpaceSpec:
+    """10 parameters (1 to 16 values), 4 constraints."""
+    return SpaceSpec(
+        "bat_convolution",
+        {
+            "block_size_x": [16 * k for k in range(1, 17)],
+            "block_size_y": list(range(1, 17)),
+            "tile_size_x": [1, 2, 3, 4, 8],
+            "tile_size_y": [1, 2],
+            "use_padding": [0, 1],
+            "read_only": [0, 1],
+            "filter_height": [15],
+            "filter_width": [15],
+            "image_height": [4096],
+            "image_width": [4096],
+        },
+        [
+            "block_size_x*block_size_y <= 1024",
+            "block_size_x*block_size_y >= 64",
+            "tile_size_x*tile_size_y <= 8",
+            "use_padding == 0 or (block_size_x*tile_size_x + filter_width - 1)"
+            "*(block_size_y*tile_size_y + filter_height - 1)*4 <= 36864",
+        ],
+    )
+
+
+def bat_hotspot() -> SpaceSpec:
+    """11 parameters (1 to 37 values), 5 constraints; the sparsest of the four."""
+    return SpaceSpec(
+        "bat_hotspot",
+        {
+            "block_size_x": [1, 2, 4, 8, 16] + [32 * k for k in range(1, 33)],
+            "block_size_y": list(range(1, 26)),
+            "tile_size_x": list(range(1, 26)),
+            "tile_size_y": [1, 2, 3, 4, 5],
+            "temporal_tiling_factor": [1, 2, 3, 4, 5, 6],
+            "loop_unroll_factor_t": [1, 2, 3, 4],
+            "blocks_per_sm": [0, 1, 2, 3],
+            "sh_power": [0, 1],
+            "max_tfactor": [10],
+            "grid_width": [4096],
+            "grid_height": [4096],
+        },
+        [
+            "32 <= block_size_x*block_size_y <= 1024",
+            "temporal_tiling_factor % loop_unroll_factor_t == 0",
+            "temporal_tiling_factor <= max_tfactor",
+            "(block_size_x*tile_size_x + 2*temporal_tiling_factor)*(block_size_y*tile_size_y + "
+            "2*temporal_tiling_factor)*(2 + sh_power)*4 <= 24576",
+            "blocks_per_sm == 0 or block_size_x*block_size_y*blocks_per_sm <= 2048",
+        ],
+    )
+
+
+def bat_gemm() -> SpaceSpec:
+    """17 parameters (1 to 4 values), 8 constraints."""
+    return SpaceSpec(
+        "bat_gemm",
+        {
+            "MWG": [16, 32, 64, 128], "NWG": [16, 32, 64, 128],
+            "MDIMC": [8, 16, 32, 64], "NDIMC": [8, 16, 32, 64],
+            "MDIMA": [8, 16, 32], "NDIMB": [8, 16, 32], "VWM": [1, 2, 4], "VWN": [1, 2, 4],
+            "KWG": [16, 32], "KWI": [2, 8], "STRM": [0, 1], "STRN": [0, 1], "SA": [0, 1],
+            "SB": [1], "KREG": [1], "GEMMK": [0], "PRECISION": [32],
+        },
+        [
+            "MWG % (MDIMC*VWM) == 0",
+            "NWG % (NDIMC*VWN) == 0",
+            "MWG % (MDIMA*VWM) == 0",
+            "NWG % (NDIMB*VWN) == 0",
+            "KWG % ((MDIMC*NDIMC)//MDIMA) == 0",
+            "KWG % KWI == 0",
+            "STRM == 0 or MWG >= 32",
+            "STRN == 0 or NWG >= 32",
+        ],
+    )
+
+
+BAT_SPACES = ("bat_dedispersion", "bat_convolution", "bat_hotspot", "bat_gemm")
+
+SPACES = {"tiny": tiny, "gemm10": gemm10, "gemm13": gemm13, "sparse16": sparse16, "wide20": wide20,
+          "bat_dedispersion": bat_dedispersion, "bat_convolution": bat_convolution,
+          "bat_hotspot": bat_hotspot, "bat_gemm": bat_gemm}
 
 
 def space(name: str) -> SpaceSpec:
@@ -176,6 +292,25 @@ def space(name: str) -> SpaceSpec:
 
 def objective(n_valid: int, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).lognormal(0.0, 0.5, int(n_valid)).astype(np.float32)
+
+
+def runtime_model(spec: SpaceSpec, rows: np.ndarray, seed: int) -> np.ndarray:
+    """Synthetic runtimes with the structure of a tuning landscape (for the score harness, where a
+    structureless table would leave nothing for an optimiser to find): the log-runtime of a
+    configuration is a sum of per-parameter bowls c_j (u_j - m_j)^2 over the normalised value
+    index u_j in [0, 1], D/2 pairwise terms b (u_j - u_k)^2 and log-normal noise (sigma 0.15) per
+    configuration.  rows: value indices [n, D] in valid-list order; returns float32 [n] > 0."""
+    rng = np.random.default_rng(seed)
+    D = len(spec.params)
+    r = np.array(spec.radices, dtype=np.float64)
+    u = np.asarray(rows, dtype=np.float64).reshape(-1, D) / np.maximum(r - 1.0, 1.0)
+    c, m = rng.uniform(0.2, 1.5, D), rng.uniform(0.0, 1.0, D)
+    logf = ((u - m) ** 2 * c).sum(axis=1)
+    for _ in range(D // 2):
+        j, k = rng.choice(D, 2, replace=False)
+        logf += rng.uniform(0.2, 1.0) * (u[:, j] - u[:, k]) ** 2
+    logf += rng.normal(0.0, 0.15, len(u))
+    return np.exp(logf).astype(np.float32)
 
 
 # ---------------------------------------------------------------------------
@@ -211,6 +346,18 @@ class OptParams:
     ff_B0_q16: int = 65536
     ff_gamma_q16: int = 65536
     ff_alpha_q16: int = 13107           # round(0.2 * 2**16)
+
+
+# Table IV's population sizes and iteration limits (DE's popsize is per parameter; DE has no
+# iteration limit in the table and runs to the time budget).
+TABLE_IV_POP = {ALGO_DE: 16, ALGO_PSO: 30, ALGO_FF: 20, ALGO_GA: 20}
+TABLE_IV_MAXITER = {ALGO_DE: None, ALGO_PSO: 100, ALGO_FF: 100, ALGO_GA: 150}
+
+
+def table_iv(algo: int, n_params: int, seed: int, unaware: int = 0) -> OptParams:
+    """Table IV's hyperparameters for a space of n_params parameters (the defaults of OptParams)."""
+    P = TABLE_IV_POP[algo] * (n_params if algo == ALGO_DE else 1)
+    return OptParams(algo, P, seed, unaware=unaware)
 
 
 def q16(x: float) -> int:
