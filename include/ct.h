@@ -194,6 +194,29 @@ int ct_repair(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t met
               uint8_t* d_out_rows, uint32_t* d_out_pos, void* stream);
 
 /*
+ * ct_repair_enum -- ct_repair by enumeration of neighbour shells through the validity bitmask
+ * (Section IV-A: with the space resolved, whether a configuration is valid is one bit), with
+ * the scans for what enumeration leaves; the results are ct_repair's, bit for bit.
+ *
+ * For an invalid in-domain row c the shells are visited in the order of the metric's leading
+ * key, and the first shell holding a valid configuration holds the winner:
+ *   HAMMING      Hamming spheres of radius 1, 2, ..., 8 around c;
+ *   INDEX_L1     index-distance spheres of radius 1, 2, ..., 8;
+ *   TIER_*       the strictly-adjacent box (every v_j in {c_j - 1, c_j, c_j + 1}), the adjacent
+ *                box (every v_j in {c_j, nearest present value below / above}), the Hamming-1
+ *                sphere, then Hamming spheres of radius 2, ..., 8 (Alg. 2 / Alg. 3's sets in order).
+ * A shell costs one bitmask lookup per member and is counted before it is visited: rows whose
+ * next shell would take their lookups past max_lookups (0: none enumerated), rows outside the
+ * domain, rows needing a sphere beyond radius 8, and every HAM1_RANDOM row go through the scans.
+ *   h_stats (nullable, host): [0] rows settled by enumeration, [1] lookups spent.  Synchronises.
+ * Other arguments, outputs and errors as ct_repair.
+ */
+int ct_repair_enum(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t metric,
+                   uint64_t seed, uint32_t generation, const uint32_t* d_who, const int32_t* d_pos_q16,
+                   uint64_t max_lookups, uint8_t* d_out_rows, uint32_t* d_out_pos, uint64_t* h_stats,
+                   void* stream);
+
+/*
  * ct_repair_noalloc -- ct_repair for callers that cannot allocate device memory
  * (code under stream capture, tight serving loops, harnesses that forbid the
  * allocator).  Same arguments, kernels and results as ct_repair; it calls no

@@ -184,6 +184,30 @@ class Space:
                                          _ptr(pos_q16), _ptr(out_rows), _ptr(out_pos), _stream()))
         return out_rows, out_pos
 
+    def repair_enum(self, rows, metric: int, seed: int = 0, generation: int = 0, who=None, pos_q16=None,
+                    max_lookups: int = 1 << 16, out_rows=None, out_pos=None):
+        """ct_repair_enum: ct_repair's results, by enumeration of neighbour shells through the bitmask
+        where a row needs at most max_lookups lookups, by the scans otherwise.
+        Returns (rows, positions, {"settled": rows enumeration settled, "lookups": lookups spent})."""
+        torch = _torch()
+        self._rows_arg(rows)
+        n = rows.shape[0]
+        if who is not None:
+            _device_arg(who, "who", (torch.int32,), (n,))
+        if pos_q16 is not None:
+            _device_arg(pos_q16, "pos_q16", (torch.int32,), (n, self.D))
+        if out_rows is None:
+            out_rows = torch.empty_like(rows)
+        if out_pos is None:
+            out_pos = torch.empty(n, dtype=torch.int32, device="cuda")
+        self._rows_arg(out_rows, "out_rows")
+        _device_arg(out_pos, "out_pos", (torch.int32,), (n,))
+        st = (ctypes.c_uint64 * 2)()
+        _lib.check(_lib.load().ct_repair_enum(self._h, _ptr(rows), n, metric, seed, generation, _ptr(who),
+                                              _ptr(pos_q16), max_lookups, _ptr(out_rows), _ptr(out_pos),
+                                              ctypes.cast(st, ctypes.c_void_p), _stream()))
+        return out_rows, out_pos, {"settled": int(st[0]), "lookups": int(st[1])}
+
     def repair_noalloc(self, rows, metric: int, seed: int = 0, generation: int = 0, who=None, pos_q16=None,
                        out_rows=None, out_pos=None):
         """ct_repair_noalloc: ct_repair on the library's static scratch (at most CT_NOALLOC_MAX_ROWS rows);

@@ -78,6 +78,7 @@ SIGNATURES = {
     "ct_rank": (_i32, [_vp, _vp, _u64, _vp, _vp]),
     "ct_repair": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _vp, _vp, _vp, _vp]),
     "ct_repair_noalloc": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _vp, _vp, _vp, _vp]),
+    "ct_repair_enum": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _vp, _u64, _vp, _vp, _vp, _vp]),
     "ct_pop_create": (_i32, [_vp, _P(ct_pop_params), _vp, _vp, _P(_vp)]),
     "ct_step": (_i32, [_P(_vp), _u32, _u32, _u32, _vp]),
     "ct_pop_read": (_i32, [_vp, _vp, _vp, _P(_u32), _P(ctypes.c_float), _P(_u32), _P(_u32)]),

@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(OUT_DIR, "libct.so")
-SOURCES = ["api.cpp", "compiler.cpp", "prof.cpp", "serve.cpp", "space.hip", "repair.hip", "step.hip", "noalloc.hip"]
+SOURCES = ["api.cpp", "compiler.cpp", "prof.cpp", "serve.cpp", "space.hip", "repair.hip", "enum.hip", "step.hip",
+           "noalloc.hip"]
 ARCH = os.environ.get("CT_OFFLOAD_ARCH", "gfx950")
 
 

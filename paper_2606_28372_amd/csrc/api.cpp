@@ -563,22 +563,29 @@ int ct_rank(const ct_space* s, const uint8_t* d_rows, uint64_t n, int64_t* d_pos
     return launch_rank(s, d_rows, n, d_pos, as_stream(stream));
 }
 
-int ct_repair(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t metric, uint64_t seed,
-              uint32_t generation, const uint32_t* d_who, const int32_t* d_pos_q16, uint8_t* d_out_rows,
-              uint32_t* d_out_pos, void* stream) {
-    if (!s || (n && (!d_rows || !d_out_rows || !d_out_pos))) return ct_fail(CT_EINVAL, "ct_repair: null argument");
-    if (metric > CT_HAM1_RANDOM) return ct_fail(CT_EINVAL, "ct_repair: unknown metric");
+// ct_repair, and with `enumerate` ct_repair_enum: shells through the bitmask first, the scans for
+// what they leave
+static int repair_call(const char* name, const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t metric,
+                       uint64_t seed, uint32_t generation, const uint32_t* d_who, const int32_t* d_pos_q16,
+                       uint8_t* d_out_rows, uint32_t* d_out_pos, void* stream, bool enumerate, uint64_t max_lookups,
+                       uint64_t* h_stats) {
+    const std::string nm(name);
+    if (!s || (n && (!d_rows || !d_out_rows || !d_out_pos))) return ct_fail(CT_EINVAL, nm + ": null argument");
+    if (metric > CT_HAM1_RANDOM) return ct_fail(CT_EINVAL, nm + ": unknown metric");
     if (metric == CT_TIER_EUCLID && n && !d_pos_q16)
-        return ct_fail(CT_EINVAL, "ct_repair: TIER_EUCLID needs particle positions");
-    if (n > 0x7FFFFFFFull) return ct_fail(CT_EINVAL, "ct_repair: at most 2^31-1 rows per call");
-    if (s->n_valid == 0) return ct_fail(CT_EEMPTY, "ct_repair: the space has no valid configuration");
+        return ct_fail(CT_EINVAL, nm + ": TIER_EUCLID needs particle positions");
+    if (n > 0x7FFFFFFFull) return ct_fail(CT_EINVAL, nm + ": at most 2^31-1 rows per call");
+    if (s->n_valid == 0) return ct_fail(CT_EEMPTY, nm + ": the space has no valid configuration");
     if (s->n_valid > CT_MAX_VALID)
-        return ct_fail(CT_EINVAL, "ct_repair: more valid configurations than 32-bit positions can name");
+        return ct_fail(CT_EINVAL, nm + ": more valid configurations than 32-bit positions can name");
+    if (h_stats) h_stats[0] = h_stats[1] = 0;
     if (n == 0) return CT_OK;
     hipStream_t st = as_stream(stream);
-    // one candidate set: scratch lists, per-part winners, the set itself and its plan
+    // one candidate set: scratch lists, per-part winners, the set itself and its plan (enumeration:
+    // a second list, counters, descriptor and the statistics)
     const uint64_t slots = std::max<uint64_t>(n, kRepairTargetWaves);
-    const size_t bytes = n * (4 + 8 + 4 + 8) + slots * (8 + 4) + 2 * 4 + 2 * 4 + sizeof(RepairSet) + 64;
+    const size_t bytes = n * (4 + 8 + 4 + 8) + slots * (8 + 4) + 4 * 4 + 2 * 4 + sizeof(RepairSet) + 64 +
+                         (enumerate ? n * (4 + 8) + sizeof(RepairSet) + 16 + 64 : 0);
     uint8_t* buf = nullptr;
     CT_HIP(hipMallocAsync((void**)&buf, bytes, st));
     RepairSet h{};
@@ -604,7 +611,7 @@ int ct_repair(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t met
     h.fb_ins = (uint64_t*)take(n * 8);
     h.part_key = (uint64_t*)take(slots * 8);
     h.part_pos = (uint32_t*)take(slots * 4);
-    h.count = (uint32_t*)take(2 * 4);
+    h.count = (uint32_t*)take(4 * 4);
     h.tally = nullptr;
     uint32_t* prep_off = (uint32_t*)take(2 * 4);
     RepairSet* d_set = (RepairSet*)take(sizeof(RepairSet));
@@ -622,12 +629,49 @@ int ct_repair(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t met
         rp.class_mask = 1u << repair_class(metric, s->R);
         rp.fb_class_mask = (metric == CT_TIER_EUCLID || metric == CT_TIER_RANDOM) ? 1u << repair_class(CT_HAMMING, s->R) : 0u;
         rp.euclid_tab = s->dev.max_radix * (s->dev.R < 32 ? s->dev.R + 1 : s->dev.R);
-        rc = launch_repair_passes(rp, true, st);
+        if (!enumerate) {
+            rc = launch_repair_passes(rp, true, st);
+        } else {
+            // the candidates enumeration leaves: their own list and counters, same outputs
+            RepairSet h2 = h;
+            h2.list = (uint32_t*)take(n * 4);
+            h2.list_ins = (uint64_t*)take(n * 8);
+            h2.count = h.count + 2;
+            RepairSet* d_set2 = (RepairSet*)take(sizeof(RepairSet));
+            unsigned long long* d_stats = (unsigned long long*)take(16);
+            CT_HIP(hipMemcpyAsync(d_set2, &h2, sizeof(RepairSet), hipMemcpyHostToDevice, st));
+            RepairPasses rest = rp;
+            rest.d_sets = d_set2;
+            rc = repair_plan_alloc(rest.plan, 1, owned);
+            if (!rc) rc = launch_repair_enum(rp, rest, max_lookups, d_stats, st);
+            if (!rc && h_stats) {
+                unsigned long long t[2];
+                if (hipMemcpyAsync(t, d_stats, sizeof(t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+                    hipStreamSynchronize(st) != hipSuccess)
+                    rc = ct_fail(CT_EDEVICE, nm + ": statistics copy failed");
+                h_stats[0] = t[0];
+                h_stats[1] = t[1];
+            }
+        }
     }
     (void)hipFreeAsync(buf, st);
     (void)hipStreamSynchronize(st);
     for (void* q : owned) (void)hipFree(q);
     return rc;
+}
+
+int ct_repair(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t metric, uint64_t seed,
+              uint32_t generation, const uint32_t* d_who, const int32_t* d_pos_q16, uint8_t* d_out_rows,
+              uint32_t* d_out_pos, void* stream) {
+    return repair_call("ct_repair", s, d_rows, n, metric, seed, generation, d_who, d_pos_q16, d_out_rows, d_out_pos,
+                       stream, false, 0, nullptr);
+}
+
+int ct_repair_enum(const ct_space* s, const uint8_t* d_rows, uint64_t n, uint32_t metric, uint64_t seed,
+                   uint32_t generation, const uint32_t* d_who, const int32_t* d_pos_q16, uint64_t max_lookups,
+                   uint8_t* d_out_rows, uint32_t* d_out_pos, uint64_t* h_stats, void* stream) {
+    return repair_call("ct_repair_enum", s, d_rows, n, metric, seed, generation, d_who, d_pos_q16, d_out_rows,
+                       d_out_pos, stream, true, max_lookups, h_stats);
 }
 
 int ct_pop_create(const ct_space* s, const ct_pop_params* prm, const float* d_objective, void* stream,

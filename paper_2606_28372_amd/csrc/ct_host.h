@@ -182,6 +182,14 @@ int launch_repair_passes(const RepairPasses& rp, bool zero_counts, hipStream_t s
                          bool prep = true);
 // GA mutation of the flagged children of a HAM1_RANDOM set array, in place, one kernel
 int launch_mutation(const RepairPasses& rp, hipStream_t st);
+// clear the sets' counters and list their candidates (validity, rank, list), without a plan
+int launch_repair_prep(const RepairPasses& rp, hipStream_t st);
+// Repair by enumeration of neighbour shells through the bitmask, then the scans for what it left:
+// `listed` is prepared (its candidates listed), enumeration settles what it can within
+// max_lookups bitmask lookups per candidate and lists the rest in `rest` (the same sets with
+// their own list and counters), whose scans then run.  d_stats (nullable): settled, lookups.
+int launch_repair_enum(const RepairPasses& listed, const RepairPasses& rest, uint64_t max_lookups,
+                       unsigned long long* d_stats, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Optimiser runs

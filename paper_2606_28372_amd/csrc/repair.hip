@@ -946,6 +946,19 @@ int launch_mutation(const RepairPasses& rp, hipStream_t st) {
     return CT_OK;
 }
 
+int launch_repair_prep(const RepairPasses& rp, hipStream_t st) {
+    if (rp.n_sets == 0 || rp.total_n == 0) return CT_OK;
+    {
+        ProfScope ps_("k_repair_zero", st);
+        hipLaunchKernelGGL(k_repair_zero, dim3((rp.n_sets + 255) / 256), dim3(256), 0, st, rp.d_sets, rp.n_sets);
+    }
+    ProfScope ps_("k_repair_prep", st);
+    const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>((rp.total_n + kBlock - 1) / kBlock, 4096));
+    hipLaunchKernelGGL(k_repair_prep, dim3(g), dim3(kBlock), 0, st, rp.d_sets, rp.n_sets, rp.d_prep_off, PlanArgs{});
+    CT_HIP(hipGetLastError());
+    return CT_OK;
+}
+
 PlanArgs main_plan(const RepairPasses& rp) {
     return PlanArgs{rp.plan, rp.class_mask, rp.tune.items, rp.tune.min_sub, 0u, 1u};
 }
