@@ -26,7 +26,6 @@ namespace {
 constexpr int kBlock = 256;            // 4 waves
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kTileGroups = 256;       // groups per scan tile
-constexpr int kEmit = 256;             // LDS entries per wave in the emission stage
 
 __device__ __forceinline__ void load_values_lds(const DevSpace& S, int64_t* lds, uint32_t n_vals) {
     for (uint32_t i = threadIdx.x; i < n_vals; i += blockDim.x) lds[i] = S.values[i];
@@ -481,19 +480,26 @@ __global__ __launch_bounds__(kTileGroups) void k_group_off(const uint32_t* __res
                                                            uint64_t* __restrict__ grp_off,
                                                            uint32_t* __restrict__ busy, uint32_t* __restrict__ n_busy) {
     __shared__ uint32_t part[kTileGroups / 64];
+    __shared__ uint32_t nzp[kTileGroups / 64 + 1];
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const uint64_t g = (uint64_t)blockIdx.x * kTileGroups + threadIdx.x;
     const uint32_t c = g < n_groups ? counts[g] : 0u;
     const uint32_t ex = wave_excl_scan(c, lane);
-    if (lane == 63) part[wv] = ex + c;
-    __syncthreads();
-    uint32_t before = 0;
-    for (uint32_t k = 0; k < wv; ++k) before += part[k];
-    if (g < n_groups) grp_off[g] = tile_off[blockIdx.x] + before + ex;
     const uint64_t nz = __ballot(c != 0);
-    uint32_t at = 0;
-    if (lane == 0 && nz) at = atomicAdd(n_busy, (uint32_t)__popcll(nz));
-    at = __shfl(at, 0, 64);
+    if (lane == 63) part[wv] = ex + c;
+    if (lane == 0) nzp[wv] = (uint32_t)__popcll(nz);
+    __syncthreads();
+    uint32_t before = 0, nz_before = 0, nz_all = 0;
+    for (uint32_t k = 0; k < kTileGroups / 64; ++k) {
+        before += k < wv ? part[k] : 0u;
+        nz_before += k < wv ? nzp[k] : 0u;
+        nz_all += nzp[k];
+    }
+    if (g < n_groups) grp_off[g] = tile_off[blockIdx.x] + before + ex;
+    // the block's non-empty groups go to the busy list with one atomic
+    if (threadIdx.x == 0) nzp[kTileGroups / 64] = nz_all ? atomicAdd(n_busy, nz_all) : 0u;
+    __syncthreads();
+    const uint32_t at = nzp[kTileGroups / 64] + nz_before;
     if (c) busy[at + (uint32_t)__popcll(nz & ((1ull << lane) - 1ull))] = (uint32_t)g;
 }
 
@@ -511,16 +517,54 @@ __global__ __launch_bounds__(kBlock) void k_digit_rows(DevSpace S, uint64_t n, u
 }
 
 // Ascending valid list from the bitmask: one listed group per wave (waves loop over the list),
-// at the offset the scan gave it.  The rank directory's entries of empty groups are zero.  A
-// configuration's row is its prefix row OR its inner row when both tables are given, else its
-// digits are decoded.
+// at the offset the group scan gave it.  The group's set bits go through LDS in chunks of kChunk
+// consecutive entries, which the lanes then write kEntryBatch at a time, the table loads of a
+// batch issued together (a lane's entries would otherwise each wait for the last).  The rank
+// directory's entries of empty groups are zero.  A configuration's row is its prefix row OR its
+// inner row when both tables are given, else its digits are decoded.
+constexpr uint32_t kChunk = 256;
+constexpr uint32_t kEntryBatch = kChunk / 64;
+
+// RW words of a row, loaded / stored as whole vectors (rows are RW * 4 bytes, RW * 4 aligned)
+typedef uint32_t ct_u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t ct_u32x2 __attribute__((ext_vector_type(2)));
+template <uint32_t RW>
+__device__ __forceinline__ void words_load(const uint8_t* p, uint32_t (&w)[RW]) {
+    if constexpr (RW == 1) {
+        w[0] = *(const CT_GLOBAL uint32_t*)p;
+    } else if constexpr (RW == 2) {
+        const ct_u32x2 v = *(const CT_GLOBAL ct_u32x2*)p;
+        w[0] = v.x; w[1] = v.y;
+    } else {
+#pragma unroll
+        for (uint32_t h = 0; h < RW / 4; ++h) {
+            const ct_u32x4 v = ((const CT_GLOBAL ct_u32x4*)p)[h];
+            w[4 * h] = v.x; w[4 * h + 1] = v.y; w[4 * h + 2] = v.z; w[4 * h + 3] = v.w;
+        }
+    }
+}
+template <uint32_t RW>
+__device__ __forceinline__ void words_store(uint8_t* p, const uint32_t (&w)[RW]) {
+    if constexpr (RW == 1) {
+        *(CT_GLOBAL uint32_t*)p = w[0];
+    } else if constexpr (RW == 2) {
+        *(CT_GLOBAL ct_u32x2*)p = ct_u32x2{w[0], w[1]};
+    } else {
+#pragma unroll
+        for (uint32_t h = 0; h < RW / 4; ++h)
+            ((CT_GLOBAL ct_u32x4*)p)[h] = ct_u32x4{w[4 * h], w[4 * h + 1], w[4 * h + 2], w[4 * h + 3]};
+    }
+}
+
+template <uint32_t RW, bool TABLES>
 __global__ __launch_bounds__(kBlock) void k_compact(DevSpace S, const uint64_t* __restrict__ words, uint64_t n_words,
                                                     const uint32_t* __restrict__ busy, const uint32_t* __restrict__ n_busy,
                                                     const uint64_t* __restrict__ grp_off,
                                                     uint64_t* __restrict__ lin, uint8_t* __restrict__ rows,
                                                     uint16_t* __restrict__ dir8, const uint8_t* __restrict__ prow,
                                                     const uint8_t* __restrict__ irow) {
-    __shared__ uint64_t emit[kWavesPerBlock][kEmit];
+    constexpr uint32_t R = RW * 4;
+    __shared__ uint64_t emit[kWavesPerBlock][kChunk];
     __shared__ uint32_t dig3[3 * CT_DMAX];
     for (uint32_t i = threadIdx.x; i < CT_DMAX; i += blockDim.x) {
         dig3[i] = i < S.D ? S.radix[i] : 1u;
@@ -535,127 +579,228 @@ __global__ __launch_bounds__(kBlock) void k_compact(DevSpace S, const uint64_t* 
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const uint32_t nb = *n_busy;
     for (uint32_t it = blockIdx.x * kWavesPerBlock + wv; it < nb; it += gridDim.x * kWavesPerBlock) {
-    const uint64_t g = busy[it];
-    const uint64_t base = grp_off[g];
-    const uint64_t wi = g * 64u + lane;
-    const uint64_t p0 = g * 4096u / S.I_s;                  // prefix of the group's first index
-    uint64_t rem = wi < n_words ? words[wi] : 0ull;
-    const uint32_t c = (uint32_t)__popcll(rem);
-    const uint32_t excl = wave_excl_scan(c, lane);
-    const uint32_t total = wave_sum(c);
-    // rank directory: offset of each 8-word block inside the group
-    if ((lane & 7u) == 0 && wi < n_words) dir8[wi >> 3] = (uint16_t)excl;
-    uint32_t e = excl;                       // list index (within the group) of the lane's next bit
-    for (uint32_t cs = 0; cs < total; cs += kEmit) {
-        const uint32_t ce = cs + kEmit;
-        while (rem && e < ce) {
-            uint32_t b = (uint32_t)__ffsll((long long)rem) - 1u;
-            rem &= rem - 1ull;
-            emit[wv][e - cs] = wi * 64u + b;
-            ++e;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const uint32_t nchunk = std::min<uint32_t>(kEmit, total - cs);
-        for (uint32_t i = lane; i < nchunk; i += 64) {
-            const uint64_t L = emit[wv][i];
-            const uint64_t pos = base + cs + i;
-            // digits from the prefix and inner parts, relative to the group's first prefix
-            // (L - p0 I_s < 4096 + I_s: 32-bit division by the inner size's magic number)
-            const uint32_t rel = (uint32_t)(L - p0 * S.I_s);
-            const uint32_t dq = ct_udiv(rel, S.Is_m, S.Is_l);
-            const uint32_t inner = rel - dq * (uint32_t)S.I_s;
-            Row r;
-            if (prow) {
-                Row a, b;
-                row_load(a, prow + (p0 + dq) * S.R, S.R);
-                row_load(b, irow + (uint64_t)inner * S.R, S.R);
-#pragma unroll
-                for (int q = 0; q < CT_DMAX / 4; ++q) r.w[q] = a.w[q] | b.w[q];
-            } else {
-#pragma unroll
-                for (int q = 0; q < CT_DMAX / 4; ++q) r.w[q] = 0;
-                decode_ctx(C, (uint32_t)(p0 + dq), 0, S.split, r);
-                decode_ctx(C, inner, S.split, S.D, r);
+        const uint64_t g = busy[it];
+        const uint64_t base = grp_off[g];
+        const uint64_t wi = g * 64u + lane;
+        const uint64_t p0 = g * 4096u / S.I_s;                  // prefix of the group's first index
+        uint64_t rem = wi < n_words ? words[wi] : 0ull;
+        const uint32_t c = (uint32_t)__popcll(rem);
+        const uint32_t excl = wave_excl_scan(c, lane);
+        const uint32_t total = wave_sum(c);
+        // rank directory: offset of each 8-word block inside the group
+        if ((lane & 7u) == 0 && wi < n_words) dir8[wi >> 3] = (uint16_t)excl;
+        uint32_t e = excl;                       // group-local index of the lane's next bit
+        for (uint32_t cs = 0; cs < total; cs += kChunk) {
+            const uint32_t ce = cs + kChunk;
+            while (rem && e < ce) {
+                const uint32_t b = (uint32_t)__ffsll((long long)rem) - 1u;
+                rem &= rem - 1ull;
+                emit[wv][e - cs] = wi * 64u + b;
+                ++e;
             }
-            lin[pos] = L;
-            row_store(r, rows + pos * S.R, S.R);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const uint32_t n = std::min<uint32_t>(kChunk, total - cs);
+            uint64_t L[kEntryBatch];
+            uint32_t r[kEntryBatch][RW];
+#pragma unroll
+            for (uint32_t k = 0; k < kEntryBatch; ++k) {
+                const uint32_t i = k * 64u + lane;
+                const bool act = i < n;
+                L[k] = act ? emit[wv][i] : 0ull;
+                // digits from the prefix and inner parts, relative to the group's first prefix
+                // (L - p0 I_s < 4096 + I_s: 32-bit division by the inner size's magic number)
+                const uint32_t rel = (uint32_t)(L[k] - p0 * S.I_s);
+                const uint32_t dq = act ? ct_udiv(rel, S.Is_m, S.Is_l) : 0u;
+                const uint32_t inner = act ? rel - dq * (uint32_t)S.I_s : 0u;
+                if constexpr (TABLES) {
+                    uint32_t a[RW], b[RW];
+                    words_load<RW>(prow + (p0 + dq) * R, a);
+                    words_load<RW>(irow + (uint64_t)inner * R, b);
+#pragma unroll
+                    for (uint32_t q = 0; q < RW; ++q) r[k][q] = a[q] | b[q];
+                } else {
+                    Row rr;
+#pragma unroll
+                    for (int q = 0; q < CT_DMAX / 4; ++q) rr.w[q] = 0;
+                    decode_ctx(C, (uint32_t)(p0 + dq), 0, S.split, rr);
+                    decode_ctx(C, inner, S.split, S.D, rr);
+#pragma unroll
+                    for (uint32_t q = 0; q < RW; ++q) r[k][q] = rr.w[q];
+                }
+            }
+#pragma unroll
+            for (uint32_t k = 0; k < kEntryBatch; ++k) {
+                const uint32_t i = k * 64u + lane;
+                if (i < n) {
+                    lin[base + cs + i] = L[k];
+                    words_store<RW>(rows + (base + cs + i) * R, r[k]);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
     }
 }
 
-// Per-byte minimum / maximum of four packed digits (two lanes of 16 bits each for the even and
-// the odd bytes).
+// Two 16-bit lanes of a word (the even and the odd bytes of four packed digits, spread out) for
+// packed minimum / maximum.
 typedef unsigned short ct_us2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ ct_us2 as_us2(uint32_t x) { return __builtin_bit_cast(ct_us2, x); }
 __device__ __forceinline__ uint32_t as_u32(ct_us2 x) { return __builtin_bit_cast(uint32_t, x); }
-__device__ __forceinline__ uint32_t byte_min(uint32_t a, uint32_t b) {
-    const uint32_t m = 0x00FF00FFu;
-    const uint32_t e = as_u32(__builtin_elementwise_min(as_us2(a & m), as_us2(b & m)));
-    const uint32_t o = as_u32(__builtin_elementwise_min(as_us2((a >> 8) & m), as_us2((b >> 8) & m)));
-    return e | (o << 8);
+
+// Lane permutations inside rows of 16 lanes (data-parallel primitives, no LDS round trip): swap
+// neighbours, swap pairs, mirror each half-row, mirror the row.  Min/max over these four steps
+// leaves every lane of a row with the row's extremum.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, 0xF, 0xF, false);
 }
-__device__ __forceinline__ uint32_t byte_max(uint32_t a, uint32_t b) {
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+// packed 16-bit minimum / maximum of a value over groups of `span` lanes (8, 16, 32 or 64; every
+// lane gets its group's result)
+template <bool MAX>
+__device__ __forceinline__ ct_us2 group_ext(ct_us2 v, uint32_t span) {
+    auto f = [](ct_us2 a, ct_us2 b) { return MAX ? __builtin_elementwise_max(a, b) : __builtin_elementwise_min(a, b); };
+    v = f(v, as_us2(dpp<kDppXor1>(as_u32(v))));
+    v = f(v, as_us2(dpp<kDppXor2>(as_u32(v))));
+    v = f(v, as_us2(dpp<kDppHalfMirror>(as_u32(v))));
+    if (span >= 16) v = f(v, as_us2(dpp<kDppMirror>(as_u32(v))));
+    if (span >= 32) v = f(v, as_us2((uint32_t)__shfl_xor((int)as_u32(v), 16, 64)));
+    if (span >= 64) v = f(v, as_us2((uint32_t)__shfl_xor((int)as_u32(v), 32, 64)));
+    return v;
+}
+
+// Per-byte minimum / maximum over the wave of four packed digits, on the even and the odd bytes
+// as two packed 16-bit pairs (one v_pk_min_u16 / v_pk_max_u16 per step instead of a byte
+// emulation).
+__device__ __forceinline__ void wave_byte_minmax(uint32_t w, uint32_t& lo, uint32_t& hi) {
     const uint32_t m = 0x00FF00FFu;
-    const uint32_t e = as_u32(__builtin_elementwise_max(as_us2(a & m), as_us2(b & m)));
-    const uint32_t o = as_u32(__builtin_elementwise_max(as_us2((a >> 8) & m), as_us2((b >> 8) & m)));
-    return e | (o << 8);
+    ct_us2 le = as_us2(w & m), lo2 = as_us2((w >> 8) & m), he = le, ho = lo2;
+    le = group_ext<false>(le, 64);
+    lo2 = group_ext<false>(lo2, 64);
+    he = group_ext<true>(he, 64);
+    ho = group_ext<true>(ho, 64);
+    lo = as_u32(le) | (as_u32(lo2) << 8);
+    hi = as_u32(he) | (as_u32(ho) << 8);
 }
 
 // Per 64-row block of the valid list (a box), the smallest and the largest value index of every
 // parameter (a bounding box used to prune repair scans), four digits per word; and which value
-// indices of each parameter occur in the list (for the "adjacent" neighbour rule), collected per
-// block in LDS -- each wave marks the distinct values of its box, one per round -- and OR-ed
-// into present[D][8], skipping the atomic when the bits are there already.  One box per wave.
+// indices of each parameter occur in the list (for the "adjacent" neighbour rule).  Persistent
+// waves take one box after another.  Presence of a parameter with at most 32 values is one bit
+// per value in a per-lane mask OR-ed over every row the lane sees, reduced once at the end; a
+// wider parameter's values are marked per box, one distinct value per round, in LDS.  The masks
+// are OR-ed into present[D][8], skipping the atomic when the bits are there already.
+template <uint32_t RW, uint32_t DB>
 __global__ __launch_bounds__(kBlock) void k_boxes(DevSpace S, uint32_t* __restrict__ boxes32,
                                                   uint32_t* __restrict__ present) {
+    constexpr uint32_t kSlices = 64u / RW;               // rows of a box reduced by one lane: RW
     __shared__ uint32_t pres[CT_DMAX * 8];
+    __shared__ uint32_t tiles[kWavesPerBlock][64 * RW];
     for (uint32_t i = threadIdx.x; i < CT_DMAX * 8; i += blockDim.x) pres[i] = 0;
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t nw = S.R / 4;
-    const uint64_t sb = (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (sb < S.n_sub) {
+    CT_LDS uint32_t* tile = (CT_LDS uint32_t*)tiles[threadIdx.x >> 6];
+    const CT_GLOBAL uint32_t* rows32 = gptr(reinterpret_cast<const uint32_t*>(S.rows));
+    const bool wide = S.max_radix > 32;
+    // parameters whose presence goes through the per-lane masks (at most 32 values; DB >= D)
+    uint32_t small = 0;
+    for (uint32_t j = 0; j < S.D; ++j) small |= S.radix[j] <= 32u ? 1u << j : 0u;
+    uint32_t m[DB];
+#pragma unroll
+    for (uint32_t j = 0; j < DB; ++j) m[j] = 0;
+    const uint64_t waves = (uint64_t)gridDim.x * kWavesPerBlock;
+    // the next box's rows load while the current box is reduced (past the end: the box's first row)
+    auto box_row = [&](uint64_t sb, uint32_t (&w)[RW]) {
         const uint64_t v = sb * 64u + lane;
-        const bool in = v < S.n_valid;
-        Row r;
-        row_load(r, S.rows + (in ? v : sb * 64u) * S.R, S.R);    // past the end: the box's first row
-        uint32_t outw = 0;
+        const CT_GLOBAL uint32_t* src = rows32 + (v < S.n_valid ? v : sb * 64u) * RW;
 #pragma unroll
-        for (uint32_t q = 0; q < CT_DMAX / 4; ++q) {
-            if (q < nw) {
-                uint32_t lo = r.w[q], hi = r.w[q];
+        for (uint32_t q = 0; q < RW; ++q) w[q] = src[q];
+    };
+    const uint32_t q = lane / kSlices, sl = lane % kSlices;
+    const uint32_t m8 = 0x00FF00FFu;
+    uint64_t sb = (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    uint32_t rn[RW];
+    if (sb < S.n_sub) box_row(sb, rn);
+    for (; sb < S.n_sub; sb += waves) {
+        const bool in = sb * 64u + lane < S.n_valid;
+        uint32_t r[RW];
 #pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    lo = byte_min(lo, (uint32_t)__shfl_xor((int)lo, o, 64));
-                    hi = byte_max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
+        for (uint32_t k = 0; k < RW; ++k) r[k] = rn[k];
+        if (sb + waves < S.n_sub) box_row(sb + waves, rn);
+        // The box's 64 rows go through LDS so that lane (q, s) -- word q, slice s of RW rows --
+        // reduces RW rows of one word on its own; the slices then combine within groups of
+        // 64 / RW lanes (row permutations, plus shuffles across rows when RW < 4).
+#pragma unroll
+        for (uint32_t k = 0; k < RW; ++k) tile[lane * RW + k] = r[k];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t w0 = tile[sl * RW * RW + q];
+        ct_us2 le = as_us2(w0 & m8), lo2 = as_us2((w0 >> 8) & m8), he = le, ho = lo2;
+#pragma unroll
+        for (uint32_t t = 1; t < RW; ++t) {
+            const uint32_t w = tile[(sl * RW + t) * RW + q];
+            const ct_us2 e = as_us2(w & m8), o = as_us2((w >> 8) & m8);
+            le = __builtin_elementwise_min(le, e);
+            lo2 = __builtin_elementwise_min(lo2, o);
+            he = __builtin_elementwise_max(he, e);
+            ho = __builtin_elementwise_max(ho, o);
+        }
+        le = group_ext<false>(le, kSlices);
+        lo2 = group_ext<false>(lo2, kSlices);
+        he = group_ext<true>(he, kSlices);
+        ho = group_ext<true>(ho, kSlices);
+        if (sl == 0) {
+            boxes32[sb * 2u * RW + q] = as_u32(le) | (as_u32(lo2) << 8);
+            boxes32[sb * 2u * RW + RW + q] = as_u32(he) | (as_u32(ho) << 8);
+        }
+        // presence of each value of the small parameters, one bit per value in the lane's masks
+#pragma unroll
+        for (uint32_t j = 0; j < DB; ++j)
+            if ((small >> j) & 1u) m[j] |= in ? 1u << ((r[j >> 2] >> ((j & 3u) * 8u)) & 0xFFu) : 0u;
+        if (wide) {
+            Row rr;
+#pragma unroll
+            for (uint32_t k = 0; k < CT_DMAX / 4; ++k) rr.w[k] = k < RW ? r[k] : 0u;
+            for (uint32_t j = 0; j < S.D; ++j) {
+                if (S.radix[j] <= 32u) continue;
+                const uint32_t d = rr.digit(j);
+                uint64_t left = __ballot(in);
+                while (left) {
+                    const uint32_t src = (uint32_t)(__ffsll((long long)left) - 1);
+                    const uint32_t val = (uint32_t)__shfl((int)d, (int)src, 64);
+                    if (lane == src) atomicOr(&pres[j * 8u + (val >> 5)], 1u << (val & 31u));
+                    left &= ~__ballot(d == val);
                 }
-                if (lane == q) outw = lo;
-                if (lane == nw + q) outw = hi;
             }
         }
-        if (lane < 2 * nw) boxes32[sb * 2u * nw + lane] = outw;
-        for (uint32_t j = 0; j < S.D; ++j) {
-            const uint32_t d = r.digit(j);
-            uint64_t left = __ballot(in);
-            while (left) {
-                const uint32_t src = (uint32_t)(__ffsll((long long)left) - 1);
-                const uint32_t val = (uint32_t)__shfl((int)d, (int)src, 64);
-                if (lane == src) atomicOr(&pres[j * 8u + (val >> 5)], 1u << (val & 31u));
-                left &= ~__ballot(d == val);
-            }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < DB; ++j) {
+        if ((small >> j) & 1u) {
+            uint32_t x = m[j];
+            x |= dpp<kDppXor1>(x);
+            x |= dpp<kDppXor2>(x);
+            x |= dpp<kDppHalfMirror>(x);
+            x |= dpp<kDppMirror>(x);
+            x |= (uint32_t)__shfl_xor((int)x, 16, 64);
+            x |= (uint32_t)__shfl_xor((int)x, 32, 64);
+            if (lane == 0 && x) atomicOr(&pres[j * 8u], x);
         }
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < S.D * 8u; i += blockDim.x) {
-        const uint32_t m = pres[i];
-        if (m && (__hip_atomic_load(&present[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & m) != m)
-            atomicOr(&present[i], m);
+        const uint32_t mk = pres[i];
+        if (mk && (__hip_atomic_load(&present[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & mk) != mk)
+            atomicOr(&present[i], mk);
     }
 }
 
@@ -670,18 +815,19 @@ __global__ __launch_bounds__(kBlock) void k_chunks(DevSpace S, uint8_t* __restri
     Row lo_r, hi_r;
     row_load(lo_r, S.boxes + src, S.R);
     row_load(hi_r, S.boxes + src + S.R, S.R);
-    for (uint32_t j = 0; j < S.R; ++j) {
-        uint32_t lo = j < S.D ? lo_r.digit(j) : 0u, hi = j < S.D ? hi_r.digit(j) : 0u;
+    const uint32_t nw = S.R / 4;
+    uint32_t outw = 0;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, 64));
-            hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
-        }
-        if (lane == 0) {
-            chunks[ck * 2u * S.R + j] = (uint8_t)lo;
-            chunks[ck * 2u * S.R + S.R + j] = (uint8_t)hi;
+    for (uint32_t q = 0; q < CT_DMAX / 4; ++q) {
+        if (q < nw) {
+            uint32_t lo, hi, lo2, hi2;
+            wave_byte_minmax(lo_r.w[q], lo, hi2);          // the minimum of the boxes' minima
+            wave_byte_minmax(hi_r.w[q], lo2, hi);          // the maximum of their maxima
+            if (lane == q) outw = lo;
+            if (lane == nw + q) outw = hi;
         }
     }
+    if (lane < 2 * nw) reinterpret_cast<uint32_t*>(chunks + ck * 2u * S.R)[lane] = outw;
 }
 
 // The nearest present value index below / above every index of every parameter ("adjacent"
@@ -772,6 +918,36 @@ uint32_t grid_for(uint64_t items, uint32_t per_block, uint32_t cap = 0x7FFFFFFFu
     uint64_t g = (items + per_block - 1) / per_block;
     if (g < 1) g = 1;
     return (uint32_t)std::min<uint64_t>(g, cap);
+}
+
+template <uint32_t RW>
+void launch_compact_rw(const DevSpace& S, bool tables, const uint64_t* words, uint64_t n_words, const uint32_t* busy,
+                       uint64_t n_groups, const uint64_t* grp_off, uint64_t* lin, uint8_t* rows, uint16_t* dir8,
+                       const uint8_t* prow, const uint8_t* irow, hipStream_t st) {
+    const dim3 grid(grid_for(std::min<uint64_t>(n_groups, 16384), kWavesPerBlock));
+    if (tables)
+        hipLaunchKernelGGL((k_compact<RW, true>), grid, dim3(kBlock), 0, st, S, words, n_words, busy, busy + n_groups,
+                           grp_off, lin, rows, dir8, prow, irow);
+    else
+        hipLaunchKernelGGL((k_compact<RW, false>), grid, dim3(kBlock), 0, st, S, words, n_words, busy, busy + n_groups,
+                           grp_off, lin, rows, dir8, prow, irow);
+}
+
+void launch_compact(const DevSpace& S, bool tables, const uint64_t* words, uint64_t n_words, const uint32_t* busy,
+                    uint64_t n_groups, const uint64_t* grp_off, uint64_t* lin, uint8_t* rows, uint16_t* dir8,
+                    const uint8_t* prow, const uint8_t* irow, hipStream_t st) {
+    if (S.R == 4) launch_compact_rw<1>(S, tables, words, n_words, busy, n_groups, grp_off, lin, rows, dir8, prow, irow, st);
+    else if (S.R == 8) launch_compact_rw<2>(S, tables, words, n_words, busy, n_groups, grp_off, lin, rows, dir8, prow, irow, st);
+    else if (S.R == 16) launch_compact_rw<4>(S, tables, words, n_words, busy, n_groups, grp_off, lin, rows, dir8, prow, irow, st);
+    else launch_compact_rw<8>(S, tables, words, n_words, busy, n_groups, grp_off, lin, rows, dir8, prow, irow, st);
+}
+
+template <uint32_t RW>
+void launch_boxes(const DevSpace& S, uint32_t* boxes, uint32_t* present, hipStream_t st) {
+    const dim3 grid(grid_for(S.n_sub, kWavesPerBlock, 2048));
+    if (S.D <= 8 && RW * 4 >= 8) hipLaunchKernelGGL((k_boxes<RW, 8>), grid, dim3(kBlock), 0, st, S, boxes, present);
+    else if (S.D <= 16 && RW * 4 >= 16) hipLaunchKernelGGL((k_boxes<RW, 16>), grid, dim3(kBlock), 0, st, S, boxes, present);
+    else hipLaunchKernelGGL((k_boxes<RW, RW * 4>), grid, dim3(kBlock), 0, st, S, boxes, present);
 }
 
 }  // namespace
@@ -940,9 +1116,8 @@ int space_build_device(ct_space* s, hipStream_t st) {
             }
             {
                 ProfScope ps_("k_compact", st);
-                hipLaunchKernelGGL(k_compact, dim3(grid_for(std::min<uint64_t>(n_groups, 16384), kWavesPerBlock)), dim3(kBlock), 0, st, S,
-                                   s->d_words, s->n_words, d_busy, d_busy + n_groups, s->d_grp_off, s->d_lin, s->d_rows, s->d_dir8,
-                                   (const uint8_t*)d_prow, (const uint8_t*)d_irow);
+                launch_compact(S, rt, s->d_words, s->n_words, d_busy, n_groups, s->d_grp_off, s->d_lin, s->d_rows,
+                               s->d_dir8, d_prow, d_irow, st);
             }
             if (rt) {
                 CT_HIP(hipFreeAsync(d_prow, st));
@@ -965,7 +1140,14 @@ int space_build_device(ct_space* s, hipStream_t st) {
         CT_HIP(hipMallocAsync((void**)&d_part, (size_t)S.D * 8u * sizeof(uint32_t), st));
         CT_HIP(hipMemsetAsync(d_part, 0, (size_t)S.D * 8u * sizeof(uint32_t), st));
         if (total) {
-            { ProfScope ps_("k_boxes", st); hipLaunchKernelGGL(k_boxes, dim3(grid_for(S.n_sub, kWavesPerBlock)), dim3(kBlock), 0, st, S, (uint32_t*)s->d_boxes, d_part); }
+            {
+                ProfScope ps_("k_boxes", st);
+                uint32_t* bx = (uint32_t*)s->d_boxes;
+                if (S.R == 4) launch_boxes<1>(S, bx, d_part, st);
+                else if (S.R == 8) launch_boxes<2>(S, bx, d_part, st);
+                else if (S.R == 16) launch_boxes<4>(S, bx, d_part, st);
+                else launch_boxes<8>(S, bx, d_part, st);
+            }
             { ProfScope ps_("k_chunks", st); hipLaunchKernelGGL(k_chunks, dim3(grid_for(S.n_chunk, kWavesPerBlock)), dim3(kBlock), 0, st, S, s->d_boxes + std::max<uint64_t>(S.n_sub, 1) * 2u * S.R); }
         }
         { ProfScope ps_("k_prevnext", st); hipLaunchKernelGGL(k_prevnext, dim3(1), dim3(1024), 0, st, S.D, d_part, 1u, s->d_prevnext); }
