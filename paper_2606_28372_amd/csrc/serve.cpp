@@ -142,7 +142,6 @@ struct ct_server {
                 continue;
             }
             r->n_valid = r->space->n_valid;
-            // a population larger than the valid set is cut to it (the initial sample is one member per stratum)
             // an aware sample is stratified over the valid list: at most one member per configuration
             if (!r->prm.unaware && r->prm.pop_size > r->n_valid) r->prm.pop_size = (uint32_t)r->n_valid;
             r->footprint = run_bytes(r, r->n_valid);

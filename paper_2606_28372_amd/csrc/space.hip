@@ -26,6 +26,7 @@ namespace {
 constexpr int kBlock = 256;            // 4 waves
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kTileGroups = 256;       // groups per scan tile
+constexpr uint32_t kChunk = 256;       // valid configurations per compaction work item
 
 __device__ __forceinline__ void load_values_lds(const DevSpace& S, int64_t* lds, uint32_t n_vals) {
     for (uint32_t i = threadIdx.x; i < n_vals; i += blockDim.x) lds[i] = S.values[i];
@@ -478,29 +479,33 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const uint64_t* __restrict_
 __global__ __launch_bounds__(kTileGroups) void k_group_off(const uint32_t* __restrict__ counts, uint64_t n_groups,
                                                            const uint64_t* __restrict__ tile_off,
                                                            uint64_t* __restrict__ grp_off,
-                                                           uint32_t* __restrict__ busy, uint32_t* __restrict__ n_busy) {
+                                                           uint64_t* __restrict__ items, uint32_t* __restrict__ n_items) {
     __shared__ uint32_t part[kTileGroups / 64];
-    __shared__ uint32_t nzp[kTileGroups / 64 + 1];
+    __shared__ uint32_t nip[kTileGroups / 64 + 1];
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const uint64_t g = (uint64_t)blockIdx.x * kTileGroups + threadIdx.x;
     const uint32_t c = g < n_groups ? counts[g] : 0u;
+    const uint32_t nch = (c + kChunk - 1u) / kChunk;       // the group's compaction work items
     const uint32_t ex = wave_excl_scan(c, lane);
-    const uint64_t nz = __ballot(c != 0);
-    if (lane == 63) part[wv] = ex + c;
-    if (lane == 0) nzp[wv] = (uint32_t)__popcll(nz);
+    const uint32_t iex = wave_excl_scan(nch, lane);
+    if (lane == 63) {
+        part[wv] = ex + c;
+        nip[wv] = iex + nch;
+    }
     __syncthreads();
-    uint32_t before = 0, nz_before = 0, nz_all = 0;
+    uint32_t before = 0, i_before = 0, i_all = 0;
     for (uint32_t k = 0; k < kTileGroups / 64; ++k) {
         before += k < wv ? part[k] : 0u;
-        nz_before += k < wv ? nzp[k] : 0u;
-        nz_all += nzp[k];
+        i_before += k < wv ? nip[k] : 0u;
+        i_all += nip[k];
     }
     if (g < n_groups) grp_off[g] = tile_off[blockIdx.x] + before + ex;
-    // the block's non-empty groups go to the busy list with one atomic
-    if (threadIdx.x == 0) nzp[kTileGroups / 64] = nz_all ? atomicAdd(n_busy, nz_all) : 0u;
+    // the block's work items (group << 5 | chunk) go to the list with one atomic
     __syncthreads();
-    const uint32_t at = nzp[kTileGroups / 64] + nz_before;
-    if (c) busy[at + (uint32_t)__popcll(nz & ((1ull << lane) - 1ull))] = (uint32_t)g;
+    if (threadIdx.x == 0) nip[kTileGroups / 64] = i_all ? atomicAdd(n_items, i_all) : 0u;
+    __syncthreads();
+    const uint32_t at = nip[kTileGroups / 64] + i_before + iex;
+    for (uint32_t k = 0; k < nch; ++k) items[at + k] = (g << 5) | k;
 }
 
 // Digit rows of the numbers [0, n) over parameters [j0, j1) (the others zero): the prefix rows
@@ -522,7 +527,6 @@ __global__ __launch_bounds__(kBlock) void k_digit_rows(DevSpace S, uint64_t n, u
 // batch issued together (a lane's entries would otherwise each wait for the last).  The rank
 // directory's entries of empty groups are zero.  A configuration's row is its prefix row OR its
 // inner row when both tables are given, else its digits are decoded.
-constexpr uint32_t kChunk = 256;
 constexpr uint32_t kEntryBatch = kChunk / 64;
 
 // RW words of a row, loaded / stored as whole vectors (rows are RW * 4 bytes, RW * 4 aligned)
@@ -558,7 +562,7 @@ __device__ __forceinline__ void words_store(uint8_t* p, const uint32_t (&w)[RW])
 
 template <uint32_t RW, bool TABLES>
 __global__ __launch_bounds__(kBlock) void k_compact(DevSpace S, const uint64_t* __restrict__ words, uint64_t n_words,
-                                                    const uint32_t* __restrict__ busy, const uint32_t* __restrict__ n_busy,
+                                                    const uint64_t* __restrict__ items, const uint32_t* __restrict__ n_items,
                                                     const uint64_t* __restrict__ grp_off,
                                                     uint64_t* __restrict__ lin, uint8_t* __restrict__ rows,
                                                     uint16_t* __restrict__ dir8, const uint8_t* __restrict__ prow,
@@ -577,9 +581,11 @@ __global__ __launch_bounds__(kBlock) void k_compact(DevSpace S, const uint64_t* 
     C.mm = C.rad + CT_DMAX;
     C.ml = C.rad + 2 * CT_DMAX;
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
-    const uint32_t nb = *n_busy;
-    for (uint32_t it = blockIdx.x * kWavesPerBlock + wv; it < nb; it += gridDim.x * kWavesPerBlock) {
-        const uint64_t g = busy[it];
+    const uint32_t ni = *n_items;
+    for (uint32_t it = blockIdx.x * kWavesPerBlock + wv; it < ni; it += gridDim.x * kWavesPerBlock) {
+        const uint64_t item = items[it];
+        const uint64_t g = item >> 5;
+        const uint32_t cs = (uint32_t)(item & 31u) * kChunk;   // the item's entries: [cs, cs + kChunk)
         const uint64_t base = grp_off[g];
         const uint64_t wi = g * 64u + lane;
         const uint64_t p0 = g * 4096u / S.I_s;                  // prefix of the group's first index
@@ -587,10 +593,14 @@ __global__ __launch_bounds__(kBlock) void k_compact(DevSpace S, const uint64_t* 
         const uint32_t c = (uint32_t)__popcll(rem);
         const uint32_t excl = wave_excl_scan(c, lane);
         const uint32_t total = wave_sum(c);
-        // rank directory: offset of each 8-word block inside the group
-        if ((lane & 7u) == 0 && wi < n_words) dir8[wi >> 3] = (uint16_t)excl;
+        // rank directory: offset of each 8-word block inside the group (the group's first item)
+        if (cs == 0 && (lane & 7u) == 0 && wi < n_words) dir8[wi >> 3] = (uint16_t)excl;
         uint32_t e = excl;                       // group-local index of the lane's next bit
-        for (uint32_t cs = 0; cs < total; cs += kChunk) {
+        while (rem && e < cs) {                  // the lane's bits before the item
+            rem &= rem - 1ull;
+            ++e;
+        }
+        {
             const uint32_t ce = cs + kChunk;
             while (rem && e < ce) {
                 const uint32_t b = (uint32_t)__ffsll((long long)rem) - 1u;
@@ -921,25 +931,25 @@ uint32_t grid_for(uint64_t items, uint32_t per_block, uint32_t cap = 0x7FFFFFFFu
 }
 
 template <uint32_t RW>
-void launch_compact_rw(const DevSpace& S, bool tables, const uint64_t* words, uint64_t n_words, const uint32_t* busy,
-                       uint64_t n_groups, const uint64_t* grp_off, uint64_t* lin, uint8_t* rows, uint16_t* dir8,
-                       const uint8_t* prow, const uint8_t* irow, hipStream_t st) {
-    const dim3 grid(grid_for(std::min<uint64_t>(n_groups, 16384), kWavesPerBlock));
+void launch_compact_rw(const DevSpace& S, bool tables, const uint64_t* words, uint64_t n_words, const uint64_t* items,
+                       const uint32_t* n_items, uint64_t max_items, const uint64_t* grp_off, uint64_t* lin,
+                       uint8_t* rows, uint16_t* dir8, const uint8_t* prow, const uint8_t* irow, hipStream_t st) {
+    const dim3 grid(grid_for(std::min<uint64_t>(max_items, 32768), kWavesPerBlock));
     if (tables)
-        hipLaunchKernelGGL((k_compact<RW, true>), grid, dim3(kBlock), 0, st, S, words, n_words, busy, busy + n_groups,
-                           grp_off, lin, rows, dir8, prow, irow);
+        hipLaunchKernelGGL((k_compact<RW, true>), grid, dim3(kBlock), 0, st, S, words, n_words, items, n_items, grp_off,
+                           lin, rows, dir8, prow, irow);
     else
-        hipLaunchKernelGGL((k_compact<RW, false>), grid, dim3(kBlock), 0, st, S, words, n_words, busy, busy + n_groups,
-                           grp_off, lin, rows, dir8, prow, irow);
+        hipLaunchKernelGGL((k_compact<RW, false>), grid, dim3(kBlock), 0, st, S, words, n_words, items, n_items, grp_off,
+                           lin, rows, dir8, prow, irow);
 }
 
-void launch_compact(const DevSpace& S, bool tables, const uint64_t* words, uint64_t n_words, const uint32_t* busy,
-                    uint64_t n_groups, const uint64_t* grp_off, uint64_t* lin, uint8_t* rows, uint16_t* dir8,
-                    const uint8_t* prow, const uint8_t* irow, hipStream_t st) {
-    if (S.R == 4) launch_compact_rw<1>(S, tables, words, n_words, busy, n_groups, grp_off, lin, rows, dir8, prow, irow, st);
-    else if (S.R == 8) launch_compact_rw<2>(S, tables, words, n_words, busy, n_groups, grp_off, lin, rows, dir8, prow, irow, st);
-    else if (S.R == 16) launch_compact_rw<4>(S, tables, words, n_words, busy, n_groups, grp_off, lin, rows, dir8, prow, irow, st);
-    else launch_compact_rw<8>(S, tables, words, n_words, busy, n_groups, grp_off, lin, rows, dir8, prow, irow, st);
+void launch_compact(const DevSpace& S, bool tables, const uint64_t* words, uint64_t n_words, const uint64_t* items,
+                    const uint32_t* n_items, uint64_t max_items, const uint64_t* grp_off, uint64_t* lin, uint8_t* rows,
+                    uint16_t* dir8, const uint8_t* prow, const uint8_t* irow, hipStream_t st) {
+    if (S.R == 4) launch_compact_rw<1>(S, tables, words, n_words, items, n_items, max_items, grp_off, lin, rows, dir8, prow, irow, st);
+    else if (S.R == 8) launch_compact_rw<2>(S, tables, words, n_words, items, n_items, max_items, grp_off, lin, rows, dir8, prow, irow, st);
+    else if (S.R == 16) launch_compact_rw<4>(S, tables, words, n_words, items, n_items, max_items, grp_off, lin, rows, dir8, prow, irow, st);
+    else launch_compact_rw<8>(S, tables, words, n_words, items, n_items, max_items, grp_off, lin, rows, dir8, prow, irow, st);
 }
 
 template <uint32_t RW>
@@ -971,7 +981,9 @@ uint64_t space_build_scratch_bytes(const ct_space* s) {
     const uint64_t n_groups = (s->dev.N + 4095u) / 4096u;
     const uint64_t n_tiles = (n_groups + kTileGroups - 1) / kTileGroups;
     const uint64_t pw = (s->dev.I_s + 63u) / 64u + 1u;
-    return n_groups * 4u + (2u * n_tiles + 1u) * 8u + (n_groups + 1u) * 4u +         // counts, tiles, busy list
+    // counts, tiles, compaction work items (one per non-empty group; the items past those, one per
+    // kChunk valid configurations, are charged with the list when the build checks its byte limit)
+    return n_groups * 4u + (2u * n_tiles + 1u) * 8u + (n_groups + 2u) * 8u +
            (row_tables(s->dev) ? (s->dev.P_s + s->dev.I_s) * s->dev.R : 0u) +          // digit-row tables
            (s->n_ctx ? s->dev.P_s * 4u + s->n_ctx * pw * 8u : (n_groups + 1u) * 4u) +   // patterns or work list
            1024u * (uint64_t)s->dev.D * 32u;                                           // presence partials
@@ -1075,7 +1087,7 @@ int space_build_device(ct_space* s, hipStream_t st) {
     CT_HIP(hipStreamSynchronize(st));
     s->n_valid = total;
     S.n_valid = total;
-    s->over_limit = s->byte_limit && space_resident_bytes(s, total) > s->byte_limit;
+    s->over_limit = s->byte_limit && space_resident_bytes(s, total) + total / kChunk * 8u > s->byte_limit;
     if (s->over_limit) {
         (void)hipFreeAsync(d_counts, st);
         (void)hipFreeAsync(d_tiles, st);
@@ -1095,12 +1107,15 @@ int space_build_device(ct_space* s, hipStream_t st) {
     CT_HIP(hipMalloc(&s->d_boxes, (std::max<uint64_t>(S.n_sub, 1) + S.n_chunk) * 2u * S.R));
     {
         // group offsets (every group) and the list of groups with valid configurations
-        uint32_t* d_busy = nullptr;
-        CT_HIP(hipMallocAsync((void**)&d_busy, (n_groups + 1) * sizeof(uint32_t), st));
-        CT_HIP(hipMemsetAsync(d_busy + n_groups, 0, sizeof(uint32_t), st));
+        // compaction work items: a non-empty group's runs of kChunk valid configurations
+        const uint64_t max_items = std::min<uint64_t>(n_groups, total) + total / kChunk + 1;
+        uint64_t* d_items = nullptr;
+        CT_HIP(hipMallocAsync((void**)&d_items, (max_items + 1) * sizeof(uint64_t), st));
+        uint32_t* d_nitems = reinterpret_cast<uint32_t*>(d_items + max_items);
+        CT_HIP(hipMemsetAsync(d_nitems, 0, sizeof(uint32_t), st));
         CT_HIP(hipMemsetAsync(s->d_dir8, 0, (n_words_alloc / 8) * sizeof(uint16_t), st));
         { ProfScope ps_("k_group_off", st); hipLaunchKernelGGL(k_group_off, dim3((uint32_t)n_tiles), dim3(kTileGroups), 0, st, d_counts,
-                           n_groups, d_off, s->d_grp_off, d_busy, d_busy + n_groups); }
+                           n_groups, d_off, s->d_grp_off, d_items, d_nitems); }
         if (total) {
             // prefix and inner digit rows, when both tables are small, so that a valid
             // configuration's row is two loads and an OR instead of a decode
@@ -1116,15 +1131,15 @@ int space_build_device(ct_space* s, hipStream_t st) {
             }
             {
                 ProfScope ps_("k_compact", st);
-                launch_compact(S, rt, s->d_words, s->n_words, d_busy, n_groups, s->d_grp_off, s->d_lin, s->d_rows,
-                               s->d_dir8, d_prow, d_irow, st);
+                launch_compact(S, rt, s->d_words, s->n_words, d_items, d_nitems, max_items, s->d_grp_off, s->d_lin,
+                               s->d_rows, s->d_dir8, d_prow, d_irow, st);
             }
             if (rt) {
                 CT_HIP(hipFreeAsync(d_prow, st));
                 CT_HIP(hipFreeAsync(d_irow, st));
             }
         }
-        CT_HIP(hipFreeAsync(d_busy, st));
+        CT_HIP(hipFreeAsync(d_items, st));
     }
     S.lin = s->d_lin;
     S.rows = s->d_rows;
