@@ -431,46 +431,98 @@ __global__ __launch_bounds__(kBlock) void k_mask_eval(DevSpace S, uint32_t n_val
     }
 }
 
-// Sum of each tile of kTileGroups group counts.
+// Sums of each tile of kTileGroups group counts: valid configurations and compaction work items.
 __global__ __launch_bounds__(kTileGroups) void k_tile_sums(const uint32_t* __restrict__ counts, uint64_t n_groups,
-                                                           uint64_t* __restrict__ tile_sums) {
-    __shared__ uint64_t part[kTileGroups / 64];
+                                                           uint64_t* __restrict__ tile_sums,
+                                                           uint64_t* __restrict__ tile_items) {
+    __shared__ uint32_t part[2][kTileGroups / 64];
     uint64_t g = (uint64_t)blockIdx.x * kTileGroups + threadIdx.x;
-    uint32_t v = g < n_groups ? counts[g] : 0u;
-    uint32_t s = wave_sum(v);
-    if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = s;
+    const uint32_t v = g < n_groups ? counts[g] : 0u;
+    const uint32_t s = wave_sum(v), it = wave_sum((v + kChunk - 1u) / kChunk);
+    if ((threadIdx.x & 63u) == 0) {
+        part[0][threadIdx.x >> 6] = s;
+        part[1][threadIdx.x >> 6] = it;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint64_t t = 0;
-        for (int i = 0; i < kTileGroups / 64; ++i) t += part[i];
+        uint64_t t = 0, ti = 0;
+        for (int i = 0; i < kTileGroups / 64; ++i) {
+            t += part[0][i];
+            ti += part[1][i];
+        }
         tile_sums[blockIdx.x] = t;
+        tile_items[blockIdx.x] = ti;
     }
 }
 
-// Exclusive scan of the tile sums by one block; total at tile_off[n_tiles].
-__global__ __launch_bounds__(1024) void k_scan_tiles(const uint64_t* __restrict__ tile_sums, uint64_t n_tiles,
-                                                     uint64_t* __restrict__ tile_off) {
-    __shared__ uint64_t buf[1024];
-    __shared__ uint64_t carry;
-    if (threadIdx.x == 0) carry = 0;
+__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t x, uint32_t lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t lo = __shfl_up((uint32_t)x, o, 64), hi = __shfl_up((uint32_t)(x >> 32), o, 64);
+        if (lane >= (uint32_t)o) x += ((uint64_t)hi << 32) | lo;
+    }
+    return x;
+}
+
+// Exclusive scans of the tile sums and the tile work items by one block: each thread takes a run
+// of kScanRun consecutive tiles (all loaded before any is added), the threads' run totals are
+// scanned inside the waves and then across the waves, and each thread writes its run's offsets;
+// rounds of 1,024 runs repeat while tiles remain.  Totals at [n_tiles].
+constexpr uint32_t kScanRun = 8;
+__global__ __launch_bounds__(1024) void k_scan_tiles(const uint64_t* __restrict__ tile_sums,
+                                                     const uint64_t* __restrict__ tile_items, uint64_t n_tiles,
+                                                     uint64_t* __restrict__ tile_off, uint64_t* __restrict__ item_off) {
+    __shared__ uint64_t wsum[2][16];
+    __shared__ uint64_t carry[2];
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    if (threadIdx.x == 0) carry[0] = carry[1] = 0;
     __syncthreads();
-    for (uint64_t b = 0; b < n_tiles; b += 1024) {
-        uint64_t i = b + threadIdx.x;
-        uint64_t v = i < n_tiles ? tile_sums[i] : 0;
-        buf[threadIdx.x] = v;
-        __syncthreads();
-        for (int o = 1; o < 1024; o <<= 1) {
-            uint64_t y = threadIdx.x >= (unsigned)o ? buf[threadIdx.x - o] : 0;
-            __syncthreads();
-            buf[threadIdx.x] += y;
-            __syncthreads();
+    for (uint64_t b = 0; b < n_tiles; b += 1024u * kScanRun) {
+        const uint64_t i0 = b + (uint64_t)threadIdx.x * kScanRun;
+        uint64_t v[kScanRun], u[kScanRun];
+#pragma unroll
+        for (uint32_t k = 0; k < kScanRun; ++k) {
+            v[k] = i0 + k < n_tiles ? tile_sums[i0 + k] : 0;
+            u[k] = i0 + k < n_tiles ? tile_items[i0 + k] : 0;
         }
-        if (i < n_tiles) tile_off[i] = carry + buf[threadIdx.x] - v;
+        uint64_t tv = 0, tu = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kScanRun; ++k) {
+            tv += v[k];
+            tu += u[k];
+        }
+        const uint64_t iv = wave_incl_scan64(tv, lane), iu = wave_incl_scan64(tu, lane);
+        if (lane == 63) {
+            wsum[0][wv] = iv;
+            wsum[1][wv] = iu;
+        }
         __syncthreads();
-        if (threadIdx.x == 1023) carry += buf[1023];
+        uint64_t pv = carry[0], pu = carry[1];
+        for (uint32_t k = 0; k < wv; ++k) {
+            pv += wsum[0][k];
+            pu += wsum[1][k];
+        }
+        uint64_t ov = pv + iv - tv, ou = pu + iu - tu;
+#pragma unroll
+        for (uint32_t k = 0; k < kScanRun; ++k) {
+            if (i0 + k < n_tiles) {
+                tile_off[i0 + k] = ov;
+                item_off[i0 + k] = ou;
+            }
+            ov += v[k];
+            ou += u[k];
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023) {
+            carry[0] = pv + iv;
+            carry[1] = pu + iu;
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) tile_off[n_tiles] = carry;
+    if (threadIdx.x == 0) {
+        tile_off[n_tiles] = carry[0];
+        item_off[n_tiles] = carry[1];
+    }
 }
 
 // Group offsets: one block per scan tile, one thread per group; the offset of group g is its
@@ -478,10 +530,11 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const uint64_t* __restrict_
 // configurations are listed (in any order) for the compaction.
 __global__ __launch_bounds__(kTileGroups) void k_group_off(const uint32_t* __restrict__ counts, uint64_t n_groups,
                                                            const uint64_t* __restrict__ tile_off,
+                                                           const uint64_t* __restrict__ item_off,
                                                            uint64_t* __restrict__ grp_off,
-                                                           uint64_t* __restrict__ items, uint32_t* __restrict__ n_items) {
+                                                           uint64_t* __restrict__ items) {
     __shared__ uint32_t part[kTileGroups / 64];
-    __shared__ uint32_t nip[kTileGroups / 64 + 1];
+    __shared__ uint32_t nip[kTileGroups / 64];
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const uint64_t g = (uint64_t)blockIdx.x * kTileGroups + threadIdx.x;
     const uint32_t c = g < n_groups ? counts[g] : 0u;
@@ -493,18 +546,14 @@ __global__ __launch_bounds__(kTileGroups) void k_group_off(const uint32_t* __res
         nip[wv] = iex + nch;
     }
     __syncthreads();
-    uint32_t before = 0, i_before = 0, i_all = 0;
-    for (uint32_t k = 0; k < kTileGroups / 64; ++k) {
-        before += k < wv ? part[k] : 0u;
-        i_before += k < wv ? nip[k] : 0u;
-        i_all += nip[k];
+    uint32_t before = 0, i_before = 0;
+    for (uint32_t k = 0; k < wv; ++k) {
+        before += part[k];
+        i_before += nip[k];
     }
     if (g < n_groups) grp_off[g] = tile_off[blockIdx.x] + before + ex;
-    // the block's work items (group << 5 | chunk) go to the list with one atomic
-    __syncthreads();
-    if (threadIdx.x == 0) nip[kTileGroups / 64] = i_all ? atomicAdd(n_items, i_all) : 0u;
-    __syncthreads();
-    const uint32_t at = nip[kTileGroups / 64] + i_before + iex;
+    // the group's work items (group << 5 | run of kChunk entries), at the tile's item offset
+    const uint64_t at = item_off[blockIdx.x] + i_before + iex;
     for (uint32_t k = 0; k < nch; ++k) items[at + k] = (g << 5) | k;
 }
 
@@ -562,7 +611,7 @@ __device__ __forceinline__ void words_store(uint8_t* p, const uint32_t (&w)[RW])
 
 template <uint32_t RW, bool TABLES>
 __global__ __launch_bounds__(kBlock) void k_compact(DevSpace S, const uint64_t* __restrict__ words, uint64_t n_words,
-                                                    const uint64_t* __restrict__ items, const uint32_t* __restrict__ n_items,
+                                                    const uint64_t* __restrict__ items, const uint64_t* __restrict__ n_items,
                                                     const uint64_t* __restrict__ grp_off,
                                                     uint64_t* __restrict__ lin, uint8_t* __restrict__ rows,
                                                     uint16_t* __restrict__ dir8, const uint8_t* __restrict__ prow,
@@ -581,8 +630,8 @@ __global__ __launch_bounds__(kBlock) void k_compact(DevSpace S, const uint64_t* 
     C.mm = C.rad + CT_DMAX;
     C.ml = C.rad + 2 * CT_DMAX;
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
-    const uint32_t ni = *n_items;
-    for (uint32_t it = blockIdx.x * kWavesPerBlock + wv; it < ni; it += gridDim.x * kWavesPerBlock) {
+    const uint64_t ni = *n_items;
+    for (uint64_t it = (uint64_t)blockIdx.x * kWavesPerBlock + wv; it < ni; it += (uint64_t)gridDim.x * kWavesPerBlock) {
         const uint64_t item = items[it];
         const uint64_t g = item >> 5;
         const uint32_t cs = (uint32_t)(item & 31u) * kChunk;   // the item's entries: [cs, cs + kChunk)
@@ -932,7 +981,7 @@ uint32_t grid_for(uint64_t items, uint32_t per_block, uint32_t cap = 0x7FFFFFFFu
 
 template <uint32_t RW>
 void launch_compact_rw(const DevSpace& S, bool tables, const uint64_t* words, uint64_t n_words, const uint64_t* items,
-                       const uint32_t* n_items, uint64_t max_items, const uint64_t* grp_off, uint64_t* lin,
+                       const uint64_t* n_items, uint64_t max_items, const uint64_t* grp_off, uint64_t* lin,
                        uint8_t* rows, uint16_t* dir8, const uint8_t* prow, const uint8_t* irow, hipStream_t st) {
     const dim3 grid(grid_for(std::min<uint64_t>(max_items, 32768), kWavesPerBlock));
     if (tables)
@@ -944,7 +993,7 @@ void launch_compact_rw(const DevSpace& S, bool tables, const uint64_t* words, ui
 }
 
 void launch_compact(const DevSpace& S, bool tables, const uint64_t* words, uint64_t n_words, const uint64_t* items,
-                    const uint32_t* n_items, uint64_t max_items, const uint64_t* grp_off, uint64_t* lin, uint8_t* rows,
+                    const uint64_t* n_items, uint64_t max_items, const uint64_t* grp_off, uint64_t* lin, uint8_t* rows,
                     uint16_t* dir8, const uint8_t* prow, const uint8_t* irow, hipStream_t st) {
     if (S.R == 4) launch_compact_rw<1>(S, tables, words, n_words, items, n_items, max_items, grp_off, lin, rows, dir8, prow, irow, st);
     else if (S.R == 8) launch_compact_rw<2>(S, tables, words, n_words, items, n_items, max_items, grp_off, lin, rows, dir8, prow, irow, st);
@@ -983,7 +1032,7 @@ uint64_t space_build_scratch_bytes(const ct_space* s) {
     const uint64_t pw = (s->dev.I_s + 63u) / 64u + 1u;
     // counts, tiles, compaction work items (one per non-empty group; the items past those, one per
     // kChunk valid configurations, are charged with the list when the build checks its byte limit)
-    return n_groups * 4u + (2u * n_tiles + 1u) * 8u + (n_groups + 2u) * 8u +
+    return n_groups * 4u + (4u * n_tiles + 2u) * 8u + (n_groups + 2u) * 8u +
            (row_tables(s->dev) ? (s->dev.P_s + s->dev.I_s) * s->dev.R : 0u) +          // digit-row tables
            (s->n_ctx ? s->dev.P_s * 4u + s->n_ctx * pw * 8u : (n_groups + 1u) * 4u) +   // patterns or work list
            1024u * (uint64_t)s->dev.D * 32u;                                           // presence partials
@@ -1003,8 +1052,10 @@ int space_build_device(ct_space* s, hipStream_t st) {
     const uint64_t n_tiles = (n_groups + kTileGroups - 1) / kTileGroups;
     CT_HIP(hipMalloc(&s->d_words, n_words_alloc * sizeof(uint64_t)));
     CT_HIP(hipMallocAsync((void**)&d_counts, n_groups * sizeof(uint32_t), st));
-    CT_HIP(hipMallocAsync((void**)&d_tiles, n_tiles * sizeof(uint64_t), st));
-    CT_HIP(hipMallocAsync((void**)&d_off, (n_tiles + 1) * sizeof(uint64_t), st));
+    // per tile: sums (valid configurations, then work items); exclusive offsets of both
+    CT_HIP(hipMallocAsync((void**)&d_tiles, 2 * n_tiles * sizeof(uint64_t), st));
+    CT_HIP(hipMallocAsync((void**)&d_off, 2 * (n_tiles + 1) * sizeof(uint64_t), st));
+    uint64_t* d_ioff = d_off + n_tiles + 1;
     if (s->tab_words) {
         ProfScope ps_("k_scope_tables", st);
         hipLaunchKernelGGL(k_scope_tables, dim3(grid_for(s->tab_words, kWavesPerBlock, 1024)), dim3(kBlock), lds, st, S,
@@ -1079,8 +1130,10 @@ int space_build_device(ct_space* s, hipStream_t st) {
         CT_HIP(hipFreeAsync(d_todo, st));
     }
     CT_HIP(hipGetLastError());
-    { ProfScope ps_("k_tile_sums", st); hipLaunchKernelGGL(k_tile_sums, dim3((uint32_t)n_tiles), dim3(kTileGroups), 0, st, d_counts, n_groups, d_tiles); }
-    { ProfScope ps_("k_scan_tiles", st); hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, d_tiles, n_tiles, d_off); }
+    { ProfScope ps_("k_tile_sums", st); hipLaunchKernelGGL(k_tile_sums, dim3((uint32_t)n_tiles), dim3(kTileGroups), 0, st, d_counts, n_groups, d_tiles,
+                                                       d_tiles + n_tiles); }
+    { ProfScope ps_("k_scan_tiles", st); hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, d_tiles, d_tiles + n_tiles, n_tiles,
+                                                        d_off, d_ioff); }
     CT_HIP(hipGetLastError());
     uint64_t total = 0;
     CT_HIP(hipMemcpyAsync(&total, d_off + n_tiles, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
@@ -1110,12 +1163,11 @@ int space_build_device(ct_space* s, hipStream_t st) {
         // compaction work items: a non-empty group's runs of kChunk valid configurations
         const uint64_t max_items = std::min<uint64_t>(n_groups, total) + total / kChunk + 1;
         uint64_t* d_items = nullptr;
-        CT_HIP(hipMallocAsync((void**)&d_items, (max_items + 1) * sizeof(uint64_t), st));
-        uint32_t* d_nitems = reinterpret_cast<uint32_t*>(d_items + max_items);
-        CT_HIP(hipMemsetAsync(d_nitems, 0, sizeof(uint32_t), st));
+        CT_HIP(hipMallocAsync((void**)&d_items, max_items * sizeof(uint64_t), st));
+        const uint64_t* d_nitems = d_ioff + n_tiles;          // the item total
         CT_HIP(hipMemsetAsync(s->d_dir8, 0, (n_words_alloc / 8) * sizeof(uint16_t), st));
         { ProfScope ps_("k_group_off", st); hipLaunchKernelGGL(k_group_off, dim3((uint32_t)n_tiles), dim3(kTileGroups), 0, st, d_counts,
-                           n_groups, d_off, s->d_grp_off, d_items, d_nitems); }
+                           n_groups, d_off, d_ioff, s->d_grp_off, d_items); }
         if (total) {
             // prefix and inner digit rows, when both tables are small, so that a valid
             // configuration's row is two loads and an OR instead of a decode
