@@ -75,7 +75,7 @@ WORKLOADS = {
 CONFIG_KEY = {"gemm": "gemm", "gemm10": "gemm10", "tiny": "tiny", "sparse16": "sparse16"}
 
 
-BUILD_KERNELS = ["k_scope_tables", "k_table", "k_patterns", "k_mask", "k_tile_sums", "k_scan_tiles", "k_group_off",
+BUILD_KERNELS = ["k_scope_tables", "k_merge_tables", "k_table", "k_patterns", "k_mask", "k_tile_sums", "k_scan_tiles", "k_group_off",
                  "k_digit_rows", "k_compact", "k_boxes", "k_chunks",
                  "k_presence", "k_prevnext"]
 

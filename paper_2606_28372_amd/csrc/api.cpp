@@ -381,23 +381,26 @@ int space_prepare(const int64_t* values, const uint32_t* radices, uint32_t n_par
         code2.insert(code2.end(), code + cons_offsets[c], code + cons_offsets[c + 1]);
     }
     S.cons_off[n_cons] = (uint32_t)code2.size();
-    // scope tables for programs over few parameters (their scope: the parameters they read)
-    s->tab_meta.assign((size_t)std::max<uint32_t>(n_cons, 1) * CT_TAB_META, 0u);
+    // Scope tables for programs over few parameters (their scope: the parameters they read).
+    // Programs of one class (prefix programs [0, n_pre), inner programs [n_pre, n_cons)) join a
+    // table of the same class when the union of the scopes stays within CT_TAB_SCOPE parameters
+    // and CT_TAB_BITS bits (the smallest such union); the table's first program holds it with
+    // the member set, the others are marked covered.  Every tabled program also has its own
+    // table (entries [n_cons, 2 n_cons) of the descriptors): those are evaluated first, the
+    // shared tables are then their ANDs by lookup.  Table words: own tables, then shared ones.
+    s->tab_meta.assign((size_t)std::max<uint32_t>(n_cons, 1) * 2 * CT_TAB_META, 0u);
     s->tab_words = 0;
-    for (uint32_t k = 0; k < n_cons; k++) {
-        uint32_t* m = &s->tab_meta[(size_t)k * CT_TAB_META];
-        m[0] = ~0u;
-        uint32_t used = 0;
-        for (uint32_t pc = S.cons_off[k]; pc < S.cons_off[k + 1];) {
-            const uint32_t w = code2[pc++];
-            if ((w & 0xFFu) == OP_PARAM) used |= 1u << ((int32_t)w >> 8);
-            else if ((w & 0xFFu) == OP_CONST64) pc += 2;
-        }
-        std::vector<uint32_t> sc;
-        uint64_t bits = 1;
+    auto scope_bits = [&](uint32_t sc) {
+        uint64_t b = 1;
         for (uint32_t j = 0; j < n_params; j++)
-            if (used & (1u << j)) { sc.push_back(j); bits *= radices[j]; }
-        if (sc.size() > CT_TAB_SCOPE || bits > CT_TAB_BITS) continue;
+            if (sc & (1u << j)) b *= radices[j];
+        return b;
+    };
+    auto fill_meta = [&](uint32_t* m, uint32_t scope, uint64_t members) {
+        std::vector<uint32_t> sc;
+        for (uint32_t j = 0; j < n_params; j++)
+            if (scope & (1u << j)) sc.push_back(j);
+        const uint64_t bits = scope_bits(scope);
         m[0] = (uint32_t)s->tab_words;
         m[1] = (uint32_t)sc.size();
         m[2] = (uint32_t)bits;
@@ -409,7 +412,52 @@ int space_prepare(const int64_t* values, const uint32_t* radices, uint32_t n_par
             m[20 + j / 4] |= ((st2 >> 8) & 0xFFu) << (8 * (j % 4));
             st2 *= radices[sc[q]];
         }
+        m[28] = (uint32_t)members;
+        m[29] = (uint32_t)(members >> 32);
         s->tab_words += (bits + 63) / 64;
+    };
+    struct TabGroup { uint32_t leader, scope; uint64_t members; };
+    std::vector<TabGroup> groups;
+    for (uint32_t k = 0; k < n_cons; k++) {
+        s->tab_meta[(size_t)k * CT_TAB_META] = ~0u;
+        s->tab_meta[(size_t)(n_cons + k) * CT_TAB_META] = ~0u;
+        uint32_t used = 0;
+        for (uint32_t pc = S.cons_off[k]; pc < S.cons_off[k + 1];) {
+            const uint32_t w = code2[pc++];
+            if ((w & 0xFFu) == OP_PARAM) used |= 1u << ((int32_t)w >> 8);
+            else if ((w & 0xFFu) == OP_CONST64) pc += 2;
+        }
+        if ((uint32_t)__builtin_popcount(used) > CT_TAB_SCOPE || scope_bits(used) > CT_TAB_BITS) continue;
+        fill_meta(&s->tab_meta[(size_t)(n_cons + k) * CT_TAB_META], used, 1ull << k);   // its own table
+        const bool pre = k < S.n_pre;
+        size_t pick = groups.size();
+        uint64_t pick_bits = ~0ull;
+        for (size_t g = 0; g < groups.size(); g++) {
+            if ((groups[g].leader < S.n_pre) != pre) continue;
+            const uint32_t u = groups[g].scope | used;
+            const uint64_t b = scope_bits(u);
+            if ((uint32_t)__builtin_popcount(u) <= CT_TAB_SCOPE && b <= CT_TAB_BITS && b < pick_bits) {
+                pick = g;
+                pick_bits = b;
+            }
+        }
+        if (pick == groups.size()) {
+            groups.push_back(TabGroup{k, used, 1ull << k});
+        } else {
+            groups[pick].scope |= used;
+            groups[pick].members |= 1ull << k;
+            s->tab_meta[(size_t)k * CT_TAB_META] = CT_TAB_COVERED;
+        }
+    }
+    s->own_words = s->tab_words;
+    for (const TabGroup& g : groups) {
+        uint32_t* m = &s->tab_meta[(size_t)g.leader * CT_TAB_META];
+        if (__builtin_popcountll(g.members) == 1) {      // alone: its own table
+            std::copy(&s->tab_meta[(size_t)(n_cons + g.leader) * CT_TAB_META],
+                      &s->tab_meta[(size_t)(n_cons + g.leader + 1) * CT_TAB_META], m);
+        } else {
+            fill_meta(m, g.scope, g.members);
+        }
     }
     // inner patterns: the inner programs read the inner parameters and a few prefix parameters
     // (the context); when every context's pattern over the inner configurations is small, the

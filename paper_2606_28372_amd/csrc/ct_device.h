@@ -16,15 +16,19 @@
 
 #define CT_DMAX 32        // parameters per space
 #define CT_STACK 16       // interpreter stack depth
-// Scope tables: a constraint that reads at most CT_TAB_SCOPE parameters whose value counts
-// multiply to at most CT_TAB_BITS is evaluated once per combination of those parameters into a
-// bit table; a configuration then tests one bit instead of running the program.
+// Scope tables: constraints that read at most CT_TAB_SCOPE parameters whose value counts
+// multiply to at most CT_TAB_BITS are evaluated once per combination of those parameters into a
+// bit table; a configuration then tests one bit instead of running the programs.  Programs of one
+// class (prefix / inner) share a table over the union of their scopes while it stays within both
+// limits: its bit is the AND of theirs.
 #define CT_TAB_SCOPE 8
 #define CT_TAB_BITS 65536u
-#define CT_TAB_META 28    // u32 per program: word offset (~0: no table), scope size, table bits, 0,
-                          // (stride << 5) | parameter for each scope parameter [4..11], then the
-                          // table strides as bytes by row word: low bytes [12..19], high [20..27]
-                          // (a row's table index is two byte dot products per row word)
+#define CT_TAB_META 30    // u32 per program: word offset (~0: no table; CT_TAB_COVERED: in another
+                          // program's table), scope size, table bits, 0, (stride << 5) | parameter
+                          // for each scope parameter [4..11], the table strides as bytes by row
+                          // word: low bytes [12..19], high [20..27] (a row's table index is two
+                          // byte dot products per row word), the programs in the table [28..29]
+#define CT_TAB_COVERED 0xFFFFFFFEu
 
 struct DevSpace {
     uint32_t D;           // parameters
@@ -323,6 +327,7 @@ __device__ __forceinline__ bool ct_valid(const DevSpace& S, uint32_t c0, uint32_
     for (uint32_t c = c0; c < c1; ++c) {
         const CT_GLOBAL uint32_t* m = gptr(S.tab_meta + c * CT_TAB_META);
         const uint32_t off = m[0];
+        if (off == CT_TAB_COVERED) continue;              // tested by another program's table
         if (!kInterp || off != ~0u) {
             uint32_t lo = 0, hi = 0;
 #pragma unroll

@@ -53,7 +53,8 @@ struct ct_space {
     uint8_t* d_boxes = nullptr;
     uint32_t* d_tab_meta = nullptr;   // scope tables: per program CT_TAB_META words
     uint64_t* d_tabs = nullptr;
-    std::vector<uint32_t> tab_meta;
+    std::vector<uint32_t> tab_meta;       // [2 n_cons][CT_TAB_META]: tables tested, own tables
+    uint64_t own_words = 0;               // table words of the programs' own tables (the shared ones follow)
     uint64_t tab_words = 0;
     uint64_t n_ctx = 0;               // combinations of the context parameters (0: no inner patterns)
     size_t lds_values_bytes = 0;      // dynamic LDS for the value tables

@@ -113,6 +113,7 @@ __device__ __forceinline__ bool valid_ctx(const DevSpace& S, const LdsCtx& C, ui
     for (uint32_t c = c0; c < c1; ++c) {
         const CT_LDS uint32_t* m = C.meta + c * CT_TAB_META;
         const uint32_t off = __builtin_amdgcn_readfirstlane(m[0]);
+        if (off == CT_TAB_COVERED) continue;              // tested by another program's table
         if (!kInterp || off != ~0u) {
             // the table index sum_j digit_j * stride_j as byte dot products: strides are below
             // 2^16, low and high bytes apart, zero for parameters outside the scope
@@ -158,22 +159,56 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t lane) {
 // the valid configurations of each 4096-index group are added to its (zeroed) counter.
 constexpr uint32_t kSubWords = 8;
 
-// Scope tables: word w of the tables (every program with a table owns a run of whole words) is
-// the ballot of the program over 64 consecutive combinations of its scope parameters (last one
-// fastest), the other digits 0; combinations past the table's size evaluate combination 0 and
-// are masked off.
+// A program's own scope table: word w of the own tables (every tabled program owns a run of
+// whole words, descriptors [n_cons, 2 n_cons)) is the ballot of the program over 64 consecutive
+// combinations of its scope parameters (last one fastest), the other digits 0; combinations past
+// the table's size evaluate combination 0 and are masked off.
 __global__ __launch_bounds__(kBlock) void k_scope_tables(DevSpace S, uint32_t n_vals, uint64_t total_words,
                                                          uint64_t* __restrict__ tabs) {
     extern __shared__ int64_t lds_vals[];
     load_values_lds(S, lds_vals, n_vals);
     const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t* own = S.tab_meta + (uint64_t)S.n_cons * CT_TAB_META;
     const uint64_t stride = (uint64_t)gridDim.x * kWavesPerBlock;
     for (uint64_t w = (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); w < total_words; w += stride) {
         // the program owning word w: the last one with a table starting at or before it
         uint32_t c = 0;
         for (uint32_t k = 0; k < S.n_cons; ++k) {
+            const uint32_t off = own[k * CT_TAB_META];
+            if (off < CT_TAB_COVERED && off <= w) c = k;
+        }
+        const uint32_t* m = own + c * CT_TAB_META;
+        const uint64_t t0 = (w - m[0]) * 64u + lane;
+        const bool in = t0 < m[2];
+        uint32_t t = in ? (uint32_t)t0 : 0u;
+        Row r;
+#pragma unroll
+        for (int q = 0; q < CT_DMAX / 4; ++q) r.w[q] = 0;
+        for (uint32_t k = m[1]; k-- > 0;) {
+            const uint32_t j = m[4 + k] & 31u;
+            const uint32_t q = ct_udiv(t, S.mag_m[j], S.mag_l[j]);
+            r.set(j, t - q * S.radix[j]);
+            t = q;
+        }
+        const bool ok = ct_eval(S, c, c + 1, r, lds_vals) && in;
+        const uint64_t b = __ballot(ok);
+        if (lane == 0) tabs[w] = b;
+    }
+}
+
+// Shared scope tables (words [w0, w1), after the own tables): bit t of a table is the AND of its
+// programs' own-table bits at combination t of the shared scope, each found with the program's
+// byte dot products.
+__global__ __launch_bounds__(kBlock) void k_merge_tables(DevSpace S, uint64_t w0, uint64_t w1,
+                                                         uint64_t* __restrict__ tabs) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t* own = S.tab_meta + (uint64_t)S.n_cons * CT_TAB_META;
+    const uint64_t stride = (uint64_t)gridDim.x * kWavesPerBlock;
+    for (uint64_t w = w0 + (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); w < w1; w += stride) {
+        uint32_t c = 0;
+        for (uint32_t k = 0; k < S.n_cons; ++k) {
             const uint32_t off = S.tab_meta[k * CT_TAB_META];
-            if (off != ~0u && off <= w) c = k;
+            if (off < CT_TAB_COVERED && off >= w0 && off <= w) c = k;
         }
         const uint32_t* m = S.tab_meta + c * CT_TAB_META;
         const uint64_t t0 = (w - m[0]) * 64u + lane;
@@ -188,7 +223,21 @@ __global__ __launch_bounds__(kBlock) void k_scope_tables(DevSpace S, uint32_t n_
             r.set(j, t - q * S.radix[j]);
             t = q;
         }
-        const bool ok = ct_eval(S, c, c + 1, r, lds_vals) && in;
+        bool ok = in;
+        const uint64_t members = (uint64_t)m[28] | ((uint64_t)m[29] << 32);
+        for (uint64_t mm = members; mm; mm &= mm - 1ull) {
+            const uint32_t* om = own + (uint32_t)__builtin_ctzll(mm) * CT_TAB_META;
+            uint32_t lo = 0, hi = 0;
+#pragma unroll
+            for (uint32_t q = 0; q < CT_DMAX / 4; ++q) {
+                if (q < S.R / 4) {
+                    lo = __builtin_amdgcn_udot4(r.w[q], om[12 + q], lo, false);
+                    hi = __builtin_amdgcn_udot4(r.w[q], om[20 + q], hi, false);
+                }
+            }
+            const uint32_t idx = lo + (hi << 8);
+            ok = ok && ((tabs[om[0] + (idx >> 6)] >> (idx & 63u)) & 1ull);
+        }
         const uint64_t b = __ballot(ok);
         if (lane == 0) tabs[w] = b;
     }
@@ -1056,10 +1105,15 @@ int space_build_device(ct_space* s, hipStream_t st) {
     CT_HIP(hipMallocAsync((void**)&d_tiles, 2 * n_tiles * sizeof(uint64_t), st));
     CT_HIP(hipMallocAsync((void**)&d_off, 2 * (n_tiles + 1) * sizeof(uint64_t), st));
     uint64_t* d_ioff = d_off + n_tiles + 1;
-    if (s->tab_words) {
+    if (s->own_words) {
         ProfScope ps_("k_scope_tables", st);
-        hipLaunchKernelGGL(k_scope_tables, dim3(grid_for(s->tab_words, kWavesPerBlock, 1024)), dim3(kBlock), lds, st, S,
-                           n_vals, s->tab_words, s->d_tabs);
+        hipLaunchKernelGGL(k_scope_tables, dim3(grid_for(s->own_words, kWavesPerBlock, 1024)), dim3(kBlock), lds, st, S,
+                           n_vals, s->own_words, s->d_tabs);
+    }
+    if (s->tab_words > s->own_words) {
+        ProfScope ps_("k_merge_tables", st);
+        hipLaunchKernelGGL(k_merge_tables, dim3(grid_for(s->tab_words - s->own_words, kWavesPerBlock, 1024)), dim3(kBlock), 0,
+                           st, S, s->own_words, s->tab_words, s->d_tabs);
     }
 
     if (S.split == S.D) {
