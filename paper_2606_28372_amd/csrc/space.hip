@@ -107,7 +107,7 @@ __device__ __forceinline__ void decode_ctx(const LdsCtx& C, uint32_t x, uint32_t
 // ct_valid with the descriptors and (when they fit) the tables in LDS; every program's scope
 // parameters are read at once (up to CT_TAB_SCOPE, predicated).  kInterp = false: every program
 // of the range has a table and no interpreter is compiled in.
-template <bool kInterp>
+template <bool kInterp, uint32_t RW = 0>       // RW: row words when known at compile time
 __device__ __forceinline__ bool valid_ctx(const DevSpace& S, const LdsCtx& C, uint32_t c0, uint32_t c1, const Row& dig) {
     bool ok = true;
     for (uint32_t c = c0; c < c1; ++c) {
@@ -119,8 +119,8 @@ __device__ __forceinline__ bool valid_ctx(const DevSpace& S, const LdsCtx& C, ui
             // 2^16, low and high bytes apart, zero for parameters outside the scope
             uint32_t lo = 0, hi = 0;
 #pragma unroll
-            for (uint32_t q = 0; q < CT_DMAX / 4; ++q) {
-                if (q < C.nw) {
+            for (uint32_t q = 0; q < (RW ? RW : CT_DMAX / 4); ++q) {
+                if (RW || q < C.nw) {
                     lo = __builtin_amdgcn_udot4(dig.w[q], __builtin_amdgcn_readfirstlane(m[12 + q]), lo, false);
                     hi = __builtin_amdgcn_udot4(dig.w[q], __builtin_amdgcn_readfirstlane(m[20 + q]), hi, false);
                 }
@@ -974,35 +974,48 @@ __global__ __launch_bounds__(1024) void k_prevnext(uint32_t D, const uint32_t* _
     }
 }
 
-template <bool TI>
+// Validity of caller rows: kRowsPerThread rows per thread and round (their loads in flight
+// together), persistent blocks (the evaluation context goes to LDS once per block).
+constexpr uint32_t kRowsPerThread = 4;
+template <bool TI, uint32_t RW>
 __global__ __launch_bounds__(kBlock) void k_valid_rows(DevSpace S, uint32_t n_vals, const uint8_t* __restrict__ rows,
                                                        uint64_t n, uint8_t* __restrict__ out, uint32_t tab_words) {
     const LdsCtx C = load_ctx(S, n_vals, tab_words);
-    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n; base += (uint64_t)gridDim.x * blockDim.x) {
-        uint64_t i = base + threadIdx.x;
-        bool in = i < n;
-        Row r;
-        if (in) row_load(r, rows + i * S.R, S.R);
-        else
-            for (int q = 0; q < CT_DMAX / 4; ++q) r.w[q] = 0;
-        // every digit below its radix, four at a time: in 16-bit lanes of the even and the odd
-        // bytes, 0x100 + (radix - 1) - digit keeps bit 8 exactly when digit < radix
-        bool ok = in;
+    uint32_t rmq[RW];
 #pragma unroll
-        for (uint32_t q = 0; q < CT_DMAX / 4; ++q) {
-            if (q < C.nw) {
-                const uint32_t rmq = __builtin_amdgcn_readfirstlane(C.rm1[q]);
-                const uint32_t te = ((rmq & 0x00FF00FFu) | 0x01000100u) - (r.w[q] & 0x00FF00FFu);
-                const uint32_t to = (((rmq >> 8) & 0x00FF00FFu) | 0x01000100u) - ((r.w[q] >> 8) & 0x00FF00FFu);
+    for (uint32_t q = 0; q < RW; ++q) rmq[q] = __builtin_amdgcn_readfirstlane(C.rm1[q]);
+    const uint64_t step = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += step * kRowsPerThread) {
+        Row r[kRowsPerThread];
+#pragma unroll
+        for (uint32_t u = 0; u < kRowsPerThread; ++u) {
+            const uint64_t i = i0 + u * step;
+            uint32_t w[RW];
+            if (i < n) words_load<RW>(rows + i * (RW * 4u), w);
+            else
+                for (uint32_t q = 0; q < RW; ++q) w[q] = 0;
+#pragma unroll
+            for (uint32_t q = 0; q < CT_DMAX / 4; ++q) r[u].w[q] = q < RW ? w[q] : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kRowsPerThread; ++u) {
+            const uint64_t i = i0 + u * step;
+            // every digit below its radix, four at a time: in 16-bit lanes of the even and the odd
+            // bytes, 0x100 + (radix - 1) - digit keeps bit 8 exactly when digit < radix
+            bool ok = i < n;
+#pragma unroll
+            for (uint32_t q = 0; q < RW; ++q) {
+                const uint32_t te = ((rmq[q] & 0x00FF00FFu) | 0x01000100u) - (r[u].w[q] & 0x00FF00FFu);
+                const uint32_t to = (((rmq[q] >> 8) & 0x00FF00FFu) | 0x01000100u) - ((r[u].w[q] >> 8) & 0x00FF00FFu);
                 ok &= ((te & to & 0x01000100u) == 0x01000100u);
             }
-        }
-        if (!ok) {
+            if (!ok) {
 #pragma unroll
-            for (int q = 0; q < CT_DMAX / 4; ++q) r.w[q] = 0;
+                for (int q = 0; q < CT_DMAX / 4; ++q) r[u].w[q] = 0;
+            }
+            ok = valid_ctx<!TI, RW>(S, C, 0, S.n_cons, r[u]) && ok;
+            if (i < n) out[i] = ok ? 1 : 0;
         }
-        ok = valid_ctx<!TI>(S, C, 0, S.n_cons, r) && ok;
-        if (in) out[i] = ok ? 1 : 0;
     }
 }
 
@@ -1283,17 +1296,26 @@ int space_build_device(ct_space* s, hipStream_t st) {
     return CT_OK;
 }
 
+template <uint32_t RW>
+void launch_valid_rows(const ct_space* s, bool tabled_all, const uint8_t* rows, uint64_t n, uint8_t* out, hipStream_t st) {
+    const dim3 grid(grid_for((n + kRowsPerThread - 1) / kRowsPerThread, kBlock, 2048));
+    if (tabled_all)
+        hipLaunchKernelGGL((k_valid_rows<true, RW>), grid, dim3(kBlock), ctx_lds_bytes(s), st, s->dev,
+                           (uint32_t)s->values.size(), rows, n, out, ctx_tab_lds(s));
+    else
+        hipLaunchKernelGGL((k_valid_rows<false, RW>), grid, dim3(kBlock), ctx_lds_bytes(s), st, s->dev,
+                           (uint32_t)s->values.size(), rows, n, out, ctx_tab_lds(s));
+}
+
 int launch_valid_mask(const ct_space* s, const uint8_t* rows, uint64_t n, uint8_t* out, hipStream_t st) {
     if (n == 0) return CT_OK;
     {
         ProfScope ps_("k_valid_rows", st);
-        const dim3 grid(grid_for(n, kBlock, 8192));
-        if (tabled(s, 0, s->dev.n_cons))
-            hipLaunchKernelGGL(k_valid_rows<true>, grid, dim3(kBlock), ctx_lds_bytes(s), st, s->dev,
-                               (uint32_t)s->values.size(), rows, n, out, ctx_tab_lds(s));
-        else
-            hipLaunchKernelGGL(k_valid_rows<false>, grid, dim3(kBlock), ctx_lds_bytes(s), st, s->dev,
-                               (uint32_t)s->values.size(), rows, n, out, ctx_tab_lds(s));
+        const bool ti = tabled(s, 0, s->dev.n_cons);
+        if (s->dev.R == 4) launch_valid_rows<1>(s, ti, rows, n, out, st);
+        else if (s->dev.R == 8) launch_valid_rows<2>(s, ti, rows, n, out, st);
+        else if (s->dev.R == 16) launch_valid_rows<4>(s, ti, rows, n, out, st);
+        else launch_valid_rows<8>(s, ti, rows, n, out, st);
     }
     CT_HIP(hipGetLastError());
     return CT_OK;
