@@ -136,6 +136,43 @@ __device__ __forceinline__ bool valid_ctx(const DevSpace& S, const LdsCtx& C, ui
     return ok;
 }
 
+// valid_ctx for U rows at once: each program's descriptor is read once for all of them.  Bit u of
+// `okm` says whether row u is still valid; returns the updated bits.
+template <bool kInterp, uint32_t RW, uint32_t U>
+__device__ __forceinline__ uint32_t valid_ctx_rows(const DevSpace& S, const LdsCtx& C, uint32_t c0, uint32_t c1,
+                                                   const Row (&dig)[U], uint32_t okm) {
+    for (uint32_t c = c0; c < c1; ++c) {
+        const CT_LDS uint32_t* m = C.meta + c * CT_TAB_META;
+        const uint32_t off = __builtin_amdgcn_readfirstlane(m[0]);
+        if (off == CT_TAB_COVERED) continue;              // tested by another program's table
+        if (!kInterp || off != ~0u) {
+            uint32_t slo[RW], shi[RW];
+#pragma unroll
+            for (uint32_t q = 0; q < RW; ++q) {
+                slo[q] = __builtin_amdgcn_readfirstlane(m[12 + q]);
+                shi[q] = __builtin_amdgcn_readfirstlane(m[20 + q]);
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                uint32_t lo = 0, hi = 0;
+#pragma unroll
+                for (uint32_t q = 0; q < RW; ++q) {
+                    lo = __builtin_amdgcn_udot4(dig[u].w[q], slo[q], lo, false);
+                    hi = __builtin_amdgcn_udot4(dig[u].w[q], shi[q], hi, false);
+                }
+                const uint32_t idx = lo + (hi << 8);
+                const uint64_t word = C.tabs_l ? C.tabs_l[off + (idx >> 6)] : C.tabs_g[off + (idx >> 6)];
+                if (!((word >> (idx & 63u)) & 1ull)) okm &= ~(1u << u);
+            }
+        } else {
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u)
+                if (!ct_eval(S, c, c + 1, dig[u], (const int64_t*)C.vals)) okm &= ~(1u << u);
+        }
+    }
+    return okm;
+}
+
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -997,12 +1034,12 @@ __global__ __launch_bounds__(kBlock) void k_valid_rows(DevSpace S, uint32_t n_va
 #pragma unroll
             for (uint32_t q = 0; q < CT_DMAX / 4; ++q) r[u].w[q] = q < RW ? w[q] : 0u;
         }
+        uint32_t okm = 0;
 #pragma unroll
         for (uint32_t u = 0; u < kRowsPerThread; ++u) {
-            const uint64_t i = i0 + u * step;
             // every digit below its radix, four at a time: in 16-bit lanes of the even and the odd
             // bytes, 0x100 + (radix - 1) - digit keeps bit 8 exactly when digit < radix
-            bool ok = i < n;
+            bool ok = i0 + u * step < n;
 #pragma unroll
             for (uint32_t q = 0; q < RW; ++q) {
                 const uint32_t te = ((rmq[q] & 0x00FF00FFu) | 0x01000100u) - (r[u].w[q] & 0x00FF00FFu);
@@ -1013,9 +1050,12 @@ __global__ __launch_bounds__(kBlock) void k_valid_rows(DevSpace S, uint32_t n_va
 #pragma unroll
                 for (int q = 0; q < CT_DMAX / 4; ++q) r[u].w[q] = 0;
             }
-            ok = valid_ctx<!TI, RW>(S, C, 0, S.n_cons, r[u]) && ok;
-            if (i < n) out[i] = ok ? 1 : 0;
+            okm |= ok ? 1u << u : 0u;
         }
+        okm = valid_ctx_rows<!TI, RW, kRowsPerThread>(S, C, 0, S.n_cons, r, okm);
+#pragma unroll
+        for (uint32_t u = 0; u < kRowsPerThread; ++u)
+            if (i0 + u * step < n) out[i0 + u * step] = (okm >> u) & 1u;
     }
 }
 

@@ -179,3 +179,30 @@ def test_many_problem_counts_match_dynamic_programming():
         assert sp.n_valid == dpcount.count(pr.spec), pr.spec.name
         assert sp.n_cartesian == pr.spec.n_cartesian
         sp.close()
+
+
+@pytest.mark.parametrize("name,log2n", [("gemm13", 22), ("sparse16", 23)])
+def test_valid_mask_at_scale_matches_the_bitmask(name, log2n):
+    """Millions of rows (every round of the persistent kernel, every row slot of a thread): half
+    valid, half uniform over the Cartesian space, against the bitmask (checked against the oracle
+    by the build tests) looked up with torch."""
+    t = torch()
+    spec = W.space(name)
+    sp = gpu_space(spec)
+    n = 1 << log2n
+    g = t.Generator(device="cuda")
+    g.manual_seed(7)
+    D = len(spec.params)
+    dig = t.stack([t.randint(0, r, (n,), generator=g, device="cuda") for r in spec.radices], 1)
+    _, vrows = sp.valid_list()
+    half = n // 2
+    dig[:half] = vrows[t.randint(0, sp.n_valid, (half,), generator=g, device="cuda")][:, :D].long()
+    say(f"[gpu_space] valid_mask {name} n=2^{log2n}")
+    got = sp.valid_mask(sp.pack_rows(dig)).bool()
+    strides = np.cumprod([1] + spec.radices[::-1][:-1])[::-1].copy()
+    L = (dig * t.tensor(strides, device="cuda", dtype=t.int64)).sum(1)
+    words = sp.bitmask().view(t.int64)
+    expect = ((words[L >> 6] >> (L & 63)) & 1).bool()
+    bad = t.nonzero(got != expect).flatten()
+    assert bad.numel() == 0, f"{bad.numel()} rows differ, first {bad[:5].tolist()}"
+    assert bool(expect[:half].all())
