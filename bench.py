@@ -262,8 +262,11 @@ def cpu_baseline_run(spec, runs, obj, gens, budget_s):
                        f"time extrapolated to {gens} generations per run")}
 
 
-def batched_leg(ct, n_problems, gens):
-    """Plain vs batched vs graph generations/s over the many-problem workload (same start state)."""
+def batched_leg(ct, n_problems, gens, split=1):
+    """Plain vs batched vs graph generations/s over the many-problem workload (same start state).
+    With split > 1 the problems also run as `split` batches (problem i in batch i mod split), each
+    replaying its own graph on its own stream, so the phases of different batches overlap: how much
+    that gains bounds what the grid-wide phase boundaries of one batch cost."""
     import torch
     probs = W.batched(n_problems)
     t0 = time.perf_counter()
@@ -308,6 +311,30 @@ def batched_leg(ct, n_problems, gens):
     same = ends["plain"] == ends["batched"] == ends["graph"]
     tuning = batch.tuning()
     batch.close()
+    split_out = None
+    if split > 1:
+        restore()
+        parts = [ct.Batch([pops[i] for i in range(b, n_problems, split)]) for b in range(split)]
+        for bt in parts:
+            bt.autotune(gens, max(1, gens // 2))
+        streams = [torch.cuda.Stream() for _ in parts]
+        restore()
+        for bt, s in zip(parts, streams):
+            with torch.cuda.stream(s):
+                bt.step(1, ct.CT_STEP_GRAPH)       # capture + first replay, untimed
+        torch.cuda.synchronize()
+        restore()
+        t1 = time.perf_counter()
+        for bt, s in zip(parts, streams):
+            with torch.cuda.stream(s):
+                bt.step(gens, ct.CT_STEP_GRAPH)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        split_out = {"batches": split, "generations_per_s": n_problems * gens / dt,
+                     "identical_end_state": [p.snapshot() for p in pops] == ends["graph"],
+                     "tunings": [bt.tuning() for bt in parts]}
+        for bt in parts:
+            bt.close()
     for p in pops:
         p.close()
     n_valid = [s.n_valid for s in spaces]
@@ -317,7 +344,8 @@ def batched_leg(ct, n_problems, gens):
             "speedup_graph_vs_plain": out["graph"] / out["plain"], "identical_end_state": same,
             "setup_s": t_setup, "valid_total": int(sum(n_valid)),
             "population_total": int(sum(W.fit_pop(pr.opt, n).pop_size for pr, n in zip(probs, n_valid))),
-            "algorithms": {W.ALGO_NAMES[a]: sum(1 for pr in probs if pr.opt.algo == a) for a in range(3)}}
+            "algorithms": {W.ALGO_NAMES[a]: sum(1 for pr in probs if pr.opt.algo == a) for a in range(3)},
+            **({"split": split_out} if split_out else {})}
 
 
 def serving_leg(ct, n_runs, gens, mean_interval_ms, reserve_gib=8.0):
@@ -387,8 +415,11 @@ def main():
     ap.add_argument("--serving-interarrival-ms", type=float, default=5.0)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-build-legs", action="store_true")
-    ap.add_argument("--legs", default="all", choices=["all", "build"],
-                    help="build: only the space-build and validity-query legs (for profiling)")
+    ap.add_argument("--legs", default="all", choices=["all", "build", "batched"],
+                    help="build: only the space-build and validity-query legs; batched: only the "
+                         "many-problem leg (for profiling)")
+    ap.add_argument("--batched-split", type=int, default=1,
+                    help="also run the many-problem leg as this many batches on as many streams")
     ap.add_argument("--valid-mask-log2", type=int, default=26)
     ap.add_argument("--tuning", default=None,
                     help="items,min_boxes,grid_waves,mode: install this scan partitioning in the job instead of "
@@ -437,6 +468,10 @@ def main():
         out = {"build": [build_leg(ct, spec)] + ([build_leg(ct, W.sparse16())] if space_name != "sparse16" else []),
                "valid_mask": valid_mask_leg(ct, 1 << args.valid_mask_log2)}
         print(json.dumps(out), flush=True)
+        return
+    if args.legs == "batched":
+        out = batched_leg(ct, args.batched_problems, args.batched_generations, args.batched_split)
+        print(json.dumps({"batched": out}), flush=True)
         return
 
     # the scan partitioning is tuned once, untimed and without kernel timing (whose events would
@@ -548,7 +583,7 @@ def main():
         line["valid_mask"] = valid_mask_leg(ct, 1 << args.valid_mask_log2)
     if not args.no_batched:
         torch.cuda.empty_cache()
-        bl = batched_leg(ct, args.batched_problems, args.batched_generations)
+        bl = batched_leg(ct, args.batched_problems, args.batched_generations, args.batched_split)
         line["generations_per_s_plain"] = bl["generations_per_s"]["plain"]
         line["generations_per_s_batched"] = bl["generations_per_s"]["graph"]
         line["batched"] = bl

@@ -9,10 +9,12 @@
 //     bounding box [min, max] of its value indices, and the boxes into chunks
 //     of 64 with a box over each chunk (both built with the space);
 //   - one wave owns one (candidate, part of the list) item and holds the
-//     candidate wave-uniform; its lanes first test 64 chunk boxes at once
-//     against the candidate's current bound (a lower bound of the key over
-//     the box), then the 64 row boxes of each surviving chunk, then evaluate
-//     each surviving block with one row per lane;
+//     candidate wave-uniform; its lanes first test 64 of the part's chunk
+//     boxes at once against the candidate's current bound (a lower bound of
+//     the key over the box), then the row boxes the part owns in up to 8
+//     surviving chunks, then evaluate each surviving block with one row per
+//     lane (the parts of a candidate share each chunk's boxes, so a dense
+//     region is split between them);
 //   - the bound starts from the 64 valid rows around the candidate's place in
 //     linear-index order, so pruning is effective from the first block;
 //   - keys use byte-SIMD instructions (v_sad_u8 for index distance, a
@@ -369,16 +371,29 @@ __device__ __forceinline__ void scan_item(const RepairSet& J, const DevSpace& S,
     const CT_GLOBAL DevSpace* Sg = gptr(&S);
     const uint32_t ci = uni(gld(list + li));
     const uint64_t Lc = gld(list_ins + li);
-    Cand<M, RW> C;
-    C.load(J, Sg, ci, lds_tab);
     const CT_GLOBAL uint32_t* rows32 = gptr(reinterpret_cast<const uint32_t*>(Sg->rows));
     const CT_GLOBAL uint32_t* box32 = gptr(reinterpret_cast<const uint32_t*>(Sg->boxes));
-    const uint64_t n_valid = Sg->n_valid, n_sub = Sg->n_sub;
+    const CT_GLOBAL uint32_t* chunk32 = gptr(reinterpret_cast<const uint32_t*>(Sg->chunks));
+    const uint64_t n_valid = Sg->n_valid, n_sub = Sg->n_sub, n_chunk = Sg->n_chunk;
     const uint32_t D = Sg->D;
+    // A part owns some boxes of some chunks (64 aligned boxes): with GB the largest power of two
+    // (at most 8) dividing `parts` and GC = parts / GB, part p = pc GB + pb owns box pb (mod GB) of
+    // every chunk pc (mod GC).  The dense region around a candidate, where most boxes survive the
+    // bound, is thus shared by all of its parts instead of falling to the one or two that own its
+    // chunks, and a part still visits its rows in position order.
+    const uint32_t gb = min(parts & (0u - parts), 8u);
+    const uint32_t gc = parts / gb;
+    const uint32_t pb = part % gb, pc = part / gb;
+    const uint32_t lpc = 64u / gb;                  // lanes per chunk when lanes hold box bounds
+    const uint64_t n_mine = pc < n_chunk ? (n_chunk - pc + gc - 1) / gc : 0;   // chunks pc, pc + GC, ...
+
+    Cand<M, RW> C;
+    C.load(J, Sg, ci, lds_tab);
 
     constexpr bool tiered = (M == CT_TIER_EUCLID || M == CT_TIER_RANDOM);
     uint64_t bk = tiered ? kTier3 : kNoKey;
-    // the candidate's insertion position in the valid list, found when it was listed
+    // the candidate's insertion position in the valid list, found when it was listed: the 64 valid
+    // rows around it seed the bound
     const uint64_t ins = ((uint64_t)uni((uint32_t)(Lc >> 32)) << 32) | uni((uint32_t)Lc);
     if (ins != ~0ull) {
         const int64_t q = (int64_t)ins - 32 + (int64_t)lane;
@@ -395,22 +410,10 @@ __device__ __forceinline__ void scan_item(const RepairSet& J, const DevSpace& S,
 
     uint64_t mk = bk;                               // this lane's best key (exclusive until a row is found)
     uint32_t mp = kNoPos;
-    // A part owns every parts-th chunk (64 aligned boxes) when there are enough chunks, so each
-    // part holds some of the region around the candidate, where most of the work is; otherwise
-    // a contiguous range of boxes.  Either way a part visits its rows in position order.
-    const uint64_t n_chunk = Sg->n_chunk;
-    const bool strided = n_chunk >= parts;
-    const uint64_t b0 = strided ? 0 : (uint64_t)part * n_sub / parts;
-    const uint64_t b1 = strided ? n_sub : (uint64_t)(part + 1) * n_sub / parts;
-    const uint64_t k0 = strided ? part : b0 >> 6;
-    const uint64_t kstep = strided ? parts : 1;
-    const uint64_t n_mine = strided ? (n_chunk - part + parts - 1) / parts : ((b1 + 63u) >> 6) - k0;
-    const CT_GLOBAL uint32_t* chunk32 = gptr(reinterpret_cast<const uint32_t*>(Sg->chunks));
-    uint32_t nv[RW];
     uint32_t n_box = 0, n_chunk_open = 0;           // measurement only (when `opened` is given)
     for (uint64_t ck = 0; ck < n_mine; ck += 64) {
         // lanes over 64 of the part's chunks: which ones can hold a row below the bound?
-        const uint64_t kc = k0 + (ck + lane) * kstep;
+        const uint64_t kc = pc + (ck + lane) * gc;
         uint64_t lc = kNoKey;
         if (ck + lane < n_mine) {
             uint32_t lo[RW], hi[RW];
@@ -423,32 +426,44 @@ __device__ __forceinline__ void scan_item(const RepairSet& J, const DevSpace& S,
         }
         uint64_t mc = __ballot(lc < bk);
         while (mc) {
-            const uint32_t tc = (uint32_t)(__ffsll((long long)mc) - 1);
-            mc &= ~(1ull << tc);
-            const uint64_t cb = (k0 + (ck + tc) * kstep) * 64u;   // the chunk's first box
-            ++n_chunk_open;
-            // lanes over the chunk's boxes inside [b0, b1)
-            const uint64_t b = cb + lane;
+            // up to GB surviving chunks at a time, lowest first: lane l holds the bound of box
+            // pb + GB (l mod 64/GB) of the (l div 64/GB)-th of them, so lanes are in position order
+            const uint32_t grp = lane / lpc;
+            const uint32_t rk = __builtin_amdgcn_mbcnt_hi((uint32_t)(mc >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mc, 0u));
+            const bool take = ((mc >> lane) & 1ull) && rk < gb;
+            const uint64_t taken = __ballot(take);
+            const uint32_t n_grp = (uint32_t)__popcll(taken);
+            mc &= ~taken;
+            // lane g < n_grp receives the g-th taken chunk (the others go to lane 63, outside every
+            // group that reads), and each lane reads its group's
+            const uint32_t tg = (uint32_t)__builtin_amdgcn_ds_permute((int)((take ? rk : 63u) * 4u), (int)lane);
+            const uint32_t my_t = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(grp * 4u), (int)tg);
+            n_chunk_open += n_grp;
+            const uint32_t bx = (uint32_t)(pc + (ck + my_t) * gc) * 64u + pb + gb * (lane % lpc);
             uint64_t lb = kNoKey;
-            if (b >= b0 && b < b1) {
+            if (grp < n_grp && bx < n_sub) {
                 uint32_t lo[RW], hi[RW];
 #pragma unroll
                 for (int w = 0; w < RW; ++w) {
-                    lo[w] = box32[b * 2u * RW + w];
-                    hi[w] = box32[b * 2u * RW + RW + w];
+                    lo[w] = box32[(uint64_t)bx * 2u * RW + w];
+                    hi[w] = box32[(uint64_t)bx * 2u * RW + RW + w];
                 }
                 lb = C.bound_box(lo, hi, D, bk);
             }
             uint64_t m = __ballot(lb < bk);
+            // box of lane t, and the rows of the next surviving box loading while the current
+            // one is evaluated
+            auto box_of = [&](int t) { return (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)bx, t); };
+            uint32_t nv[RW];
             int tn = m ? __ffsll((long long)m) - 1 : -1;
             auto fetch = [&](int t) {
-                const uint64_t q = (cb + (uint32_t)t) * 64u + lane;
+                const uint64_t q = box_of(t) * 64u + lane;
 #pragma unroll
                 for (int w = 0; w < RW; ++w) nv[w] = q < n_valid ? rows32[q * RW + w] : 0u;
             };
             if (tn >= 0) fetch(tn);
             while (tn >= 0) {
-                const uint32_t t = (uint32_t)tn;
+                const int t = tn;
                 m &= ~(1ull << t);
                 ++n_box;
                 uint32_t v[RW];
@@ -456,7 +471,7 @@ __device__ __forceinline__ void scan_item(const RepairSet& J, const DevSpace& S,
                 for (int w = 0; w < RW; ++w) v[w] = nv[w];
                 tn = m ? __ffsll((long long)m) - 1 : -1;
                 if (tn >= 0) fetch(tn);
-                const uint64_t r = (cb + t) * 64u + lane;
+                const uint64_t r = box_of(t) * 64u + lane;
                 if (r < n_valid) {
                     const uint64_t k = C.key(S, v, r, mk < bk ? mk : bk);
                     if (k < mk) { mk = k; mp = (uint32_t)r; }

@@ -63,7 +63,8 @@ __device__ inline void plan_wave(const RepairSet* __restrict__ sets, uint32_t n_
 #pragma unroll
     for (uint32_t q = 0; q < kRepairClasses; ++q) acc[q] = 0;
     for (uint32_t s = s0; s < s1; ++s) {
-        const uint64_t pmax = sets[s].n_sub / min_sub;
+        // parts own box pb (mod 8) of chunk pc (mod parts / 8): more than 8 per chunk would idle
+        const uint64_t pmax = min(sets[s].n_sub / min_sub, ((sets[s].n_sub + 63u) >> 6) * 8u);
         const uint32_t cls = repair_class(which ? (uint32_t)CT_HAMMING : sets[s].metric, sets[s].R);
         uint32_t gp = gpc[0];
 #pragma unroll
