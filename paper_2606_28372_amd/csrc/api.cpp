@@ -265,6 +265,12 @@ uint64_t batch_bytes(uint32_t cap) {
 void batch_free(ct_batch* b) {
     if (!b) return;
     (void)hipDeviceSynchronize();
+    for (ct_batch* l : b->lanes) batch_free(l);
+    for (hipStream_t q : b->lane_st)
+        if (q) (void)hipStreamDestroy(q);
+    for (hipEvent_t e : b->lane_done)
+        if (e) (void)hipEventDestroy(e);
+    if (b->lane_fork) (void)hipEventDestroy(b->lane_fork);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     for (void* q : b->owned) (void)hipFree(q);
@@ -876,13 +882,78 @@ int ct_batch_create(ct_pop* const* pops, uint32_t n_pops, ct_batch** out) {
     for (size_t a = 0; a < v.size(); a++)
         for (size_t b = a + 1; b < v.size(); b++)
             if (v[a] == v[b]) return ct_fail(CT_EINVAL, "ct_batch_create: a population appears twice");
-    return batch_build(v, out, nullptr);
+    if (v.size() < kLaneMinRuns) return batch_build(v, out, nullptr);
+    // lanes: sub-batches on streams of their own, forked from and joined back into the caller's
+    ct_batch* b = new ct_batch();
+    b->pops = v;
+    b->n = (uint32_t)v.size();
+    int rc = CT_OK;
+    // the fork and join events order work of one device: a device-scope release is enough
+    const unsigned ev_flags = hipEventDisableTiming | hipEventReleaseToDevice;
+    if (hipEventCreateWithFlags(&b->lane_fork, ev_flags) != hipSuccess) rc = ct_fail(CT_EDEVICE, "hipEventCreate failed");
+    // the lanes' streams first, one after the other: HIP spreads streams over the device's hardware
+    // queues in the order they are created, and two lanes sharing one queue would not overlap
+    for (uint32_t l = 0; l < kLanes && !rc; ++l) {
+        hipStream_t q = nullptr;
+        hipEvent_t e = nullptr;
+        if (hipStreamCreateWithFlags(&q, hipStreamNonBlocking) != hipSuccess) {
+            rc = ct_fail(CT_EDEVICE, "hipStreamCreate failed");
+            break;
+        }
+        b->lane_st.push_back(q);
+        if (hipEventCreateWithFlags(&e, ev_flags) != hipSuccess) {
+            rc = ct_fail(CT_EDEVICE, "hipEventCreate failed");
+            break;
+        }
+        b->lane_done.push_back(e);
+    }
+    for (uint32_t l = 0; l < kLanes && !rc; ++l) {
+        std::vector<ct_pop*> part;
+        for (size_t i = l; i < v.size(); i += kLanes) part.push_back(v[i]);
+        ct_batch* lb = nullptr;
+        rc = batch_build(part, &lb, nullptr);
+        if (!rc) b->lanes.push_back(lb);
+    }
+    if (rc) {
+        batch_free(b);
+        return rc;
+    }
+    b->shape = b->lanes[0]->shape;
+    *out = b;
+    return CT_OK;
 }
+
+namespace {
+
+int batch_step_one(ct_batch* b, uint32_t n_generations, uint32_t flags, hipStream_t st);
+
+// Every lane steps from the state `st` has reached, each on its own stream; `st` then waits for
+// all of them.
+int step_lanes(ct_batch* b, uint32_t n_generations, uint32_t flags, hipStream_t st) {
+    CT_HIP(hipEventRecord(b->lane_fork, st));
+    int rc = CT_OK;
+    for (size_t l = 0; l < b->lanes.size(); ++l) {
+        CT_HIP(hipStreamWaitEvent(b->lane_st[l], b->lane_fork, 0));
+        if (!rc) rc = batch_step_one(b->lanes[l], n_generations, flags, b->lane_st[l]);
+        CT_HIP(hipEventRecord(b->lane_done[l], b->lane_st[l]));
+        CT_HIP(hipStreamWaitEvent(st, b->lane_done[l], 0));
+    }
+    return rc;
+}
+
+}  // namespace
 
 int ct_batch_step(ct_batch* b, uint32_t n_generations, uint32_t flags, void* stream) {
     if (!b) return ct_fail(CT_EINVAL, "ct_batch_step: null batch");
     if (flags != CT_STEP_BATCHED && flags != CT_STEP_GRAPH) return ct_fail(CT_EINVAL, "ct_batch_step: flags");
     hipStream_t st = as_stream(stream);
+    if (!b->lanes.empty()) return step_lanes(b, n_generations, flags, st);
+    return batch_step_one(b, n_generations, flags, st);
+}
+
+namespace {
+
+int batch_step_one(ct_batch* b, uint32_t n_generations, uint32_t flags, hipStream_t st) {
     if (flags == CT_STEP_BATCHED) {
         for (uint32_t g = 0; g < n_generations; g++) {
             int rc = batch_generation(b, st);
@@ -913,9 +984,18 @@ int ct_batch_step(ct_batch* b, uint32_t n_generations, uint32_t flags, void* str
     return CT_OK;
 }
 
+}  // namespace
+
 int ct_batch_autotune(ct_batch* b, uint32_t n_generations, uint32_t sample_every, uint32_t force, void* stream) {
     if (!b) return ct_fail(CT_EINVAL, "ct_batch_autotune: null batch");
     hipStream_t st = as_stream(stream);
+    if (!b->lanes.empty()) {
+        // each lane tuned on its own, one after the other on the caller's stream
+        for (ct_batch* l : b->lanes)
+            if (int rc = ct_batch_autotune(l, n_generations, sample_every, force, stream)) return rc;
+        b->tuned = true;
+        return CT_OK;
+    }
     if (b->tuned && !force) {
         for (uint32_t g = 0; g < n_generations; g++) {
             int rc = batch_generation(b, st);
@@ -943,6 +1023,8 @@ int ct_batch_set_tuning(ct_batch* b, uint32_t items, uint32_t min_boxes, uint32_
         grid_waves > (1u << 20) || mode > CT_SCAN_FUSED)
         return ct_fail(CT_EINVAL, "ct_batch_set_tuning: items in [64, 32768], min_boxes in [1, 2^20], "
                                   "grid_waves in [64, 2^20], mode CT_SCAN_SERIAL, _STREAMS or _FUSED");
+    for (ct_batch* l : b->lanes)
+        if (int rc = ct_batch_set_tuning(l, items, min_boxes, grid_waves, mode)) return rc;
     b->passA.tune = RepairTune{items, min_boxes, grid_waves, mode};
     b->tuned = true;
     b->tune_cand.clear();
@@ -955,6 +1037,11 @@ int ct_batch_set_tuning(ct_batch* b, uint32_t items, uint32_t min_boxes, uint32_
 int ct_batch_tuning(const ct_batch* b, uint32_t* items, uint32_t* min_boxes, uint32_t* grid_waves,
                     uint32_t* mode, uint32_t* tuned) {
     if (!b) return ct_fail(CT_EINVAL, "ct_batch_tuning: null batch");
+    if (!b->lanes.empty()) {
+        const int rc = ct_batch_tuning(b->lanes[0], items, min_boxes, grid_waves, mode, nullptr);
+        if (tuned) *tuned = b->tuned ? 1u : 0u;
+        return rc;
+    }
     if (items) *items = b->passA.tune.items;
     if (min_boxes) *min_boxes = b->passA.tune.min_sub;
     if (grid_waves) *grid_waves = b->passA.tune.grid_waves;

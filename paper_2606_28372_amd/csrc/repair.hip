@@ -43,6 +43,10 @@
 namespace {
 
 constexpr int kBlock = 256;
+// Scan blocks are single waves: items differ in length, and a block's resources are only freed
+// when its last wave ends, so a wave that finishes early in a larger block would hold its slot
+// idle (one-wave blocks: the gemm13 job's scan 59.0 -> 56.9 us)
+constexpr uint32_t kScanWavesPerBlock = 1;
 constexpr uint64_t kNoKey = ~0ull;
 constexpr uint32_t kNoPos = 0xFFFFFFFFu;
 constexpr uint64_t kTier3 = 3ull << 62;
@@ -824,10 +828,9 @@ RepairPlan scan_plan(const RepairPasses& rp) {
 template <int M, int RW>
 void launch_scan_rw(const RepairPasses& rp, uint32_t which, hipStream_t st) {
     ProfScope ps_(which ? "k_repair_scan_fb" : "k_repair_scan", st);
-    // TIER_EUCLID keeps one distance table per wave in LDS (at most 64 KiB per block)
+    // TIER_EUCLID keeps one distance table per wave in LDS
     const uint32_t stride = M == CT_TIER_EUCLID ? std::max<uint32_t>(rp.euclid_tab, 1) : 0;
-    uint32_t wpb = kBlock / 64;
-    while (wpb > 1 && (size_t)wpb * stride * 8 > 65536) wpb >>= 1;
+    const uint32_t wpb = kScanWavesPerBlock;
     hipLaunchKernelGGL((k_repair_scan<M, RW>), dim3(std::max<uint32_t>(scan_waves(rp, which) / wpb, 1)), dim3(wpb * 64),
                        (size_t)wpb * stride * 8, st,
                        rp.d_sets, rp.n_sets, scan_plan(rp), which, stride);
@@ -837,8 +840,7 @@ template <int RW>
 void launch_mix_rw(const RepairPasses& rp, uint32_t mmask, uint32_t which, hipStream_t st) {
     ProfScope ps_(which ? "k_repair_scan_fb" : "k_repair_scan", st);
     const uint32_t stride = (mmask & (1u << CT_TIER_EUCLID)) ? std::max<uint32_t>(rp.euclid_tab, 1) : 0;
-    uint32_t wpb = kBlock / 64;
-    while (wpb > 1 && (size_t)wpb * stride * 8 > 65536) wpb >>= 1;
+    const uint32_t wpb = kScanWavesPerBlock;
     hipLaunchKernelGGL((k_repair_scan_mix<RW>), dim3(std::max<uint32_t>(scan_waves(rp, which) / wpb, 1)), dim3(wpb * 64),
                        (size_t)wpb * stride * 8, st, rp.d_sets, rp.n_sets, scan_plan(rp), which, stride, mmask);
 }

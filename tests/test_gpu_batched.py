@@ -264,3 +264,51 @@ def test_sparse16_partitions_agree():
             assert x.snapshot() == y.snapshot(), f"run {k} differs"
     for b in batches:
         b.close()
+
+
+def test_lanes_equal_plain():
+    """A group of 64 runs or more steps as two lanes, each on a stream of its own: direct and
+    graph-replayed generations (also from a side stream), autotuning and an installed tuning all
+    leave every run where plain stepping does."""
+    from paper_2606_28372_amd import Batch, CT_STEP_BATCHED, CT_STEP_GRAPH, Pop, step_many
+    t = torch()
+    probs = W.batched(72, seed=11)
+    spaces, objs, a, b = [], [], [], []
+    for pr in probs:
+        sp = gpu_space(pr.spec)
+        obj = t.tensor(W.objective(sp.n_valid, pr.obj_seed), device="cuda")
+        opt = W.fit_pop(pr.opt, sp.n_valid)
+        spaces.append(sp)
+        objs.append(obj)
+        a.append(Pop.from_opt(sp, opt, obj))
+        b.append(Pop.from_opt(sp, opt, obj))
+    bt = Batch(b)
+
+    def check(stage):
+        t.cuda.synchronize()
+        for k in range(len(probs)):
+            assert a[k].snapshot() == b[k].snapshot(), f"problem {k} differs after {stage}"
+
+    say("[gpu_batched] lanes: direct generations")
+    step_many(a, 2)
+    bt.step(2, CT_STEP_BATCHED)
+    check("direct generations")
+    say("[gpu_batched] lanes: graph replays from a side stream")
+    step_many(a, 3)
+    side = t.cuda.Stream()
+    side.wait_stream(t.cuda.current_stream())
+    with t.cuda.stream(side):
+        bt.step(3, CT_STEP_GRAPH)
+    side.synchronize()
+    check("graph replays")
+    say("[gpu_batched] lanes: autotune")
+    step_many(a, 2)
+    bt.autotune(2, 1, force=True)
+    check("autotuning")
+    assert bt.tuning()["tuned"]
+    bt.set_tuning(4096, 16, 8192, 2)
+    assert bt.tuning()["items"] == 4096 and bt.tuning()["grid_waves"] == 8192
+    step_many(a, 2)
+    bt.step(2, CT_STEP_GRAPH)
+    check("an installed tuning")
+    bt.close()
