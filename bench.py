@@ -27,8 +27,11 @@ printed:
   batched    generations/s of 256 independent problems (uneven spaces,
              dimensions, populations and algorithms) stepped one run at a time
              (plain), with one launch per phase for all runs (batched), and by
-             replaying a captured hipGraph of one generation (graph); all three
-             start from the same state and must end in the same state,
+             replaying a captured hipGraph of one generation (graph), the
+             batch in two lanes on streams of their own; and by graph replay
+             with all runs in one lane (graph_one_lane), whose phase
+             boundaries hold every run; all start from the same state and must
+             end in the same state,
   serving    Poisson arrivals of runs from the same many-problem distribution
              (200 runs/s, 200 generations each) through the serving loop:
              admission by device footprint into one continuously re-formed
@@ -262,11 +265,10 @@ def cpu_baseline_run(spec, runs, obj, gens, budget_s):
                        f"time extrapolated to {gens} generations per run")}
 
 
-def batched_leg(ct, n_problems, gens, split=1):
-    """Plain vs batched vs graph generations/s over the many-problem workload (same start state).
-    With split > 1 the problems also run as `split` batches (problem i in batch i mod split), each
-    replaying its own graph on its own stream, so the phases of different batches overlap: how much
-    that gains bounds what the grid-wide phase boundaries of one batch cost."""
+def batched_leg(ct, n_problems, gens):
+    """Plain vs batched vs graph generations/s over the many-problem workload (same start state);
+    the graph replay also with the runs in one lane (every phase a barrier for all of them), which
+    is what the default two lanes, each on a stream of its own, gain over."""
     import torch
     probs = W.batched(n_problems)
     t0 = time.perf_counter()
@@ -279,10 +281,6 @@ def batched_leg(ct, n_problems, gens, split=1):
         pops.append(ct.Pop.from_opt(sp, W.fit_pop(pr.opt, sp.n_valid), obj))
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
-    batch = ct.Batch(pops)
-    # the scan partitioning, before the clock starts: two sweeps, the stream setting timed between
-    batch.autotune(gens, max(1, gens // 2))
-    torch.cuda.synchronize()
     start = [p.snapshot() for p in pops]
 
     def restore():
@@ -292,60 +290,45 @@ def batched_leg(ct, n_problems, gens, split=1):
 
     out = {}
     ends = {}
-    for mode in ("plain", "batched", "graph"):
+    tunings = {}
+    for lanes in (None, 1):
         restore()
-        if mode == "graph":
-            batch.step(1, ct.CT_STEP_GRAPH)        # capture + first replay, untimed
+        batch = ct.Batch(pops, lanes=lanes)
+        # the scan partitioning, before the clock starts: two sweeps, the stream setting timed between
+        batch.autotune(gens, max(1, gens // 2))
+        torch.cuda.synchronize()
+        modes = ("plain", "batched", "graph") if lanes is None else ("graph_one_lane",)
+        for mode in modes:
             restore()
-        t1 = time.perf_counter()
-        if mode == "plain":
-            ct.step_many(pops, gens, ct.CT_STEP_PLAIN)
-        elif mode == "batched":
-            batch.step(gens, ct.CT_STEP_BATCHED)
-        else:
-            batch.step(gens, ct.CT_STEP_GRAPH)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t1
-        out[mode] = n_problems * gens / dt
-        ends[mode] = [p.snapshot() for p in pops]
-    same = ends["plain"] == ends["batched"] == ends["graph"]
-    tuning = batch.tuning()
-    batch.close()
-    split_out = None
-    if split > 1:
-        restore()
-        parts = [ct.Batch([pops[i] for i in range(b, n_problems, split)]) for b in range(split)]
-        for bt in parts:
-            bt.autotune(gens, max(1, gens // 2))
-        streams = [torch.cuda.Stream() for _ in parts]
-        restore()
-        for bt, s in zip(parts, streams):
-            with torch.cuda.stream(s):
-                bt.step(1, ct.CT_STEP_GRAPH)       # capture + first replay, untimed
-        torch.cuda.synchronize()
-        restore()
-        t1 = time.perf_counter()
-        for bt, s in zip(parts, streams):
-            with torch.cuda.stream(s):
-                bt.step(gens, ct.CT_STEP_GRAPH)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t1
-        split_out = {"batches": split, "generations_per_s": n_problems * gens / dt,
-                     "identical_end_state": [p.snapshot() for p in pops] == ends["graph"],
-                     "tunings": [bt.tuning() for bt in parts]}
-        for bt in parts:
-            bt.close()
+            if mode.startswith("graph"):
+                batch.step(1, ct.CT_STEP_GRAPH)        # capture + first replay, untimed
+                restore()
+            t1 = time.perf_counter()
+            if mode == "plain":
+                ct.step_many(pops, gens, ct.CT_STEP_PLAIN)
+            elif mode == "batched":
+                batch.step(gens, ct.CT_STEP_BATCHED)
+            else:
+                batch.step(gens, ct.CT_STEP_GRAPH)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            out[mode] = n_problems * gens / dt
+            ends[mode] = [p.snapshot() for p in pops]
+        tunings["default" if lanes is None else "one_lane"] = batch.tuning()
+        batch.close()
+    same = all(ends[m] == ends["plain"] for m in ends)
     for p in pops:
         p.close()
     n_valid = [s.n_valid for s in spaces]
     for s in spaces:
         s.close()
-    return {"problems": n_problems, "generations": gens, "generations_per_s": out, "tuning": tuning,
-            "speedup_graph_vs_plain": out["graph"] / out["plain"], "identical_end_state": same,
+    return {"problems": n_problems, "generations": gens, "generations_per_s": out, "tuning": tunings["default"],
+            "tuning_one_lane": tunings["one_lane"], "lanes": 2 if n_problems >= 64 else 1,
+            "speedup_graph_vs_plain": out["graph"] / out["plain"],
+            "speedup_lanes": out["graph"] / out["graph_one_lane"], "identical_end_state": same,
             "setup_s": t_setup, "valid_total": int(sum(n_valid)),
             "population_total": int(sum(W.fit_pop(pr.opt, n).pop_size for pr, n in zip(probs, n_valid))),
-            "algorithms": {W.ALGO_NAMES[a]: sum(1 for pr in probs if pr.opt.algo == a) for a in range(3)},
-            **({"split": split_out} if split_out else {})}
+            "algorithms": {W.ALGO_NAMES[a]: sum(1 for pr in probs if pr.opt.algo == a) for a in range(3)}}
 
 
 def serving_leg(ct, n_runs, gens, mean_interval_ms, reserve_gib=8.0):
@@ -408,7 +391,7 @@ def main():
     ap.add_argument("--generations", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-problems", type=int, default=256)
-    ap.add_argument("--batched-generations", type=int, default=20)
+    ap.add_argument("--batched-generations", type=int, default=40)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--serving-runs", type=int, default=2000)
     ap.add_argument("--serving-generations", type=int, default=200)
@@ -418,8 +401,6 @@ def main():
     ap.add_argument("--legs", default="all", choices=["all", "build", "batched"],
                     help="build: only the space-build and validity-query legs; batched: only the "
                          "many-problem leg (for profiling)")
-    ap.add_argument("--batched-split", type=int, default=1,
-                    help="also run the many-problem leg as this many batches on as many streams")
     ap.add_argument("--valid-mask-log2", type=int, default=26)
     ap.add_argument("--tuning", default=None,
                     help="items,min_boxes,grid_waves,mode: install this scan partitioning in the job instead of "
@@ -470,7 +451,7 @@ def main():
         print(json.dumps(out), flush=True)
         return
     if args.legs == "batched":
-        out = batched_leg(ct, args.batched_problems, args.batched_generations, args.batched_split)
+        out = batched_leg(ct, args.batched_problems, args.batched_generations)
         print(json.dumps({"batched": out}), flush=True)
         return
 
@@ -583,7 +564,7 @@ def main():
         line["valid_mask"] = valid_mask_leg(ct, 1 << args.valid_mask_log2)
     if not args.no_batched:
         torch.cuda.empty_cache()
-        bl = batched_leg(ct, args.batched_problems, args.batched_generations, args.batched_split)
+        bl = batched_leg(ct, args.batched_problems, args.batched_generations)
         line["generations_per_s_plain"] = bl["generations_per_s"]["plain"]
         line["generations_per_s_batched"] = bl["generations_per_s"]["graph"]
         line["batched"] = bl

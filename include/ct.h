@@ -335,16 +335,20 @@ int ct_step(ct_pop* const* pops, uint32_t n_pops, uint32_t n_generations, uint32
  * same kernels directly.  Results equal those of stepping each run alone.
  * The runs must outlive the batch; a run may be in several batches but only
  * one of them may be stepped at a time.  At most 4096 runs per batch.
- * A batch of 64 runs or more is stepped as two lanes: run i goes to lane
- * i mod 2, and each lane advances on a stream of its own (forked from
+ * A batch of 64 runs or more is stepped as two lanes (ct_batch_create_lanes
+ * chooses the number): run i goes to lane i mod lanes, and each lane
+ * advances on a stream of its own (forked from
  * `stream` at the call and joined back into it before the call's work on
  * `stream` completes), so that one lane's phases run while the other's wait at
  * a phase boundary.  ct_batch_autotune tunes the lanes one after the other,
- * ct_batch_set_tuning installs the partitioning in both, and ct_batch_tuning
+ * ct_batch_set_tuning installs the partitioning in all, and ct_batch_tuning
  * reports the first lane's.
  */
 typedef struct ct_batch ct_batch;
 int ct_batch_create(ct_pop* const* pops, uint32_t n_pops, ct_batch** out);
+/* The same with an explicit number of lanes (1: none; at most 8, and at most one per run).
+   CT_EINVAL for 0 or more than 8. */
+int ct_batch_create_lanes(ct_pop* const* pops, uint32_t n_pops, uint32_t n_lanes, ct_batch** out);
 int ct_batch_step(ct_batch* b, uint32_t n_generations, uint32_t flags, void* stream);
 void ct_batch_free(ct_batch* b);
 

@@ -344,11 +344,16 @@ class Batch:
     """A fixed group of runs advanced together (ct_batch): one launch per phase for all of them;
     with CT_STEP_GRAPH one generation is captured into a hipGraph once and replayed."""
 
-    def __init__(self, pops: List[Pop]):
+    def __init__(self, pops: List[Pop], lanes: Optional[int] = None):
+        """lanes: sub-batches stepped on streams of their own (None: the library's choice,
+        ct_batch_create; else ct_batch_create_lanes)."""
         self.pops = list(pops)
         arr = (ctypes.c_void_p * max(1, len(self.pops)))(*[p.handle for p in self.pops])
         self._h = ctypes.c_void_p()
-        _lib.check(_lib.load().ct_batch_create(arr, len(self.pops), ctypes.byref(self._h)))
+        if lanes is None:
+            _lib.check(_lib.load().ct_batch_create(arr, len(self.pops), ctypes.byref(self._h)))
+        else:
+            _lib.check(_lib.load().ct_batch_create_lanes(arr, len(self.pops), int(lanes), ctypes.byref(self._h)))
 
     def step(self, n_generations: int = 1, flags: int = CT_STEP_GRAPH):
         _lib.check(_lib.load().ct_batch_step(self._h, n_generations, flags, _stream()))

@@ -85,6 +85,7 @@ SIGNATURES = {
     "ct_pop_counters": (_i32, [_vp, _P(_u64), _P(_u64)]),
     "ct_pop_evaluated": (_i32, [_vp, _vp]),
     "ct_batch_create": (_i32, [_P(_vp), _u32, _P(_vp)]),
+    "ct_batch_create_lanes": (_i32, [_P(_vp), _u32, _u32, _P(_vp)]),
     "ct_batch_step": (_i32, [_vp, _u32, _u32, _vp]),
     "ct_batch_free": (None, [_vp]),
     "ct_batch_autotune": (_i32, [_vp, _u32, _u32, _u32, _vp]),

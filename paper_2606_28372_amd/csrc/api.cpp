@@ -874,7 +874,12 @@ int ct_step(ct_pop* const* pops, uint32_t n_pops, uint32_t n_generations, uint32
 }
 
 int ct_batch_create(ct_pop* const* pops, uint32_t n_pops, ct_batch** out) {
+    return ct_batch_create_lanes(pops, n_pops, n_pops >= kLaneMinRuns ? kLanes : 1u, out);
+}
+
+int ct_batch_create_lanes(ct_pop* const* pops, uint32_t n_pops, uint32_t n_lanes, ct_batch** out) {
     if (!out || (n_pops && !pops)) return ct_fail(CT_EINVAL, "ct_batch_create: null argument");
+    if (n_lanes < 1 || n_lanes > kMaxLanes) return ct_fail(CT_EINVAL, "ct_batch_create_lanes: lanes in [1, 8]");
     *out = nullptr;
     std::vector<ct_pop*> v(pops, pops + n_pops);
     for (ct_pop* p : v)
@@ -882,7 +887,8 @@ int ct_batch_create(ct_pop* const* pops, uint32_t n_pops, ct_batch** out) {
     for (size_t a = 0; a < v.size(); a++)
         for (size_t b = a + 1; b < v.size(); b++)
             if (v[a] == v[b]) return ct_fail(CT_EINVAL, "ct_batch_create: a population appears twice");
-    if (v.size() < kLaneMinRuns) return batch_build(v, out, nullptr);
+    n_lanes = std::min<uint32_t>(n_lanes, std::max<uint32_t>((uint32_t)v.size(), 1u));
+    if (n_lanes == 1) return batch_build(v, out, nullptr);
     // lanes: sub-batches on streams of their own, forked from and joined back into the caller's
     ct_batch* b = new ct_batch();
     b->pops = v;
@@ -893,7 +899,7 @@ int ct_batch_create(ct_pop* const* pops, uint32_t n_pops, ct_batch** out) {
     if (hipEventCreateWithFlags(&b->lane_fork, ev_flags) != hipSuccess) rc = ct_fail(CT_EDEVICE, "hipEventCreate failed");
     // the lanes' streams first, one after the other: HIP spreads streams over the device's hardware
     // queues in the order they are created, and two lanes sharing one queue would not overlap
-    for (uint32_t l = 0; l < kLanes && !rc; ++l) {
+    for (uint32_t l = 0; l < n_lanes && !rc; ++l) {
         hipStream_t q = nullptr;
         hipEvent_t e = nullptr;
         if (hipStreamCreateWithFlags(&q, hipStreamNonBlocking) != hipSuccess) {
@@ -907,9 +913,9 @@ int ct_batch_create(ct_pop* const* pops, uint32_t n_pops, ct_batch** out) {
         }
         b->lane_done.push_back(e);
     }
-    for (uint32_t l = 0; l < kLanes && !rc; ++l) {
+    for (uint32_t l = 0; l < n_lanes && !rc; ++l) {
         std::vector<ct_pop*> part;
-        for (size_t i = l; i < v.size(); i += kLanes) part.push_back(v[i]);
+        for (size_t i = l; i < v.size(); i += n_lanes) part.push_back(v[i]);
         ct_batch* lb = nullptr;
         rc = batch_build(part, &lb, nullptr);
         if (!rc) b->lanes.push_back(lb);

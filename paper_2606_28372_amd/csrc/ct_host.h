@@ -275,9 +275,10 @@ struct ct_batch {
     std::vector<RepairTune> tune_cand;   // autotuner: candidate partitionings
     std::vector<double> tune_ms;         // their pass times summed over the tuning generations
     StreamFan fan;
-    // Lanes: a group of at least kLaneMinRuns runs is split into kLanes sub-batches (run i in lane
-    // i mod kLanes), each stepped on a stream of its own, so that one lane's phases run while the
-    // other's wait at a phase boundary.  The group's own descriptor arrays are then left empty.
+    // Lanes: the runs split into sub-batches (run i in lane i mod lanes), each stepped on a stream
+    // of its own, so that one lane's phases run while another's wait at a phase boundary (by
+    // default kLanes of them for groups of kLaneMinRuns runs or more).  The group's own descriptor
+    // arrays are then left empty.
     std::vector<ct_batch*> lanes;
     std::vector<hipStream_t> lane_st;
     std::vector<hipEvent_t> lane_done;
@@ -286,6 +287,7 @@ struct ct_batch {
 
 constexpr uint32_t kLaneMinRuns = 64;
 constexpr uint32_t kLanes = 2;
+constexpr uint32_t kMaxLanes = 8;
 
 // Smallest DE population for a mutation operator (i and its distinct picks).
 inline uint32_t de_min_pop(uint32_t method) { return method == CT_DE_RAND2 || method == CT_DE_BEST2 ? 6u : 4u; }

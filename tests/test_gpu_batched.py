@@ -312,3 +312,22 @@ def test_lanes_equal_plain():
     bt.step(2, CT_STEP_GRAPH)
     check("an installed tuning")
     bt.close()
+
+
+def test_explicit_lanes_equal_plain(spaces):
+    """ct_batch_create_lanes: three lanes over a small mixed group step like plain stepping; zero
+    or more than eight lanes are refused."""
+    from paper_2606_28372_amd import Batch, CT_STEP_GRAPH, CtError, step_many
+    t = torch()
+    a, b = make_runs(t, spaces), make_runs(t, spaces)
+    bt = Batch(b, lanes=3)
+    for stage in range(2):
+        step_many(a, 2)
+        bt.step(2, CT_STEP_GRAPH)
+        t.cuda.synchronize()
+        for k in range(len(a)):
+            assert a[k].snapshot() == b[k].snapshot(), f"run {k} differs at stage {stage}"
+    bt.close()
+    for bad in (0, 9):
+        with pytest.raises(CtError):
+            Batch(b, lanes=bad)
