@@ -667,6 +667,25 @@ constexpr uint32_t kEntryBatch = kChunk / 64;
 // RW words of a row, loaded / stored as whole vectors (rows are RW * 4 bytes, RW * 4 aligned)
 typedef uint32_t ct_u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t ct_u32x2 __attribute__((ext_vector_type(2)));
+// The same as a streaming (nontemporal) load: the validity query reads each row once, and keeping
+// the rows out of the caches leaves them to the constraint tables every row looks up (2^26 rows of
+// 16 bytes: 300 -> 261 us)
+template <uint32_t RW>
+__device__ __forceinline__ void words_load_nt(const uint8_t* p, uint32_t (&w)[RW]) {
+    if constexpr (RW == 1) {
+        w[0] = __builtin_nontemporal_load((const CT_GLOBAL uint32_t*)p);
+    } else if constexpr (RW == 2) {
+        const ct_u32x2 v = __builtin_nontemporal_load((const CT_GLOBAL ct_u32x2*)p);
+        w[0] = v.x; w[1] = v.y;
+    } else {
+#pragma unroll
+        for (uint32_t h = 0; h < RW / 4; ++h) {
+            const ct_u32x4 v = __builtin_nontemporal_load((const CT_GLOBAL ct_u32x4*)p + h);
+            w[4 * h] = v.x; w[4 * h + 1] = v.y; w[4 * h + 2] = v.z; w[4 * h + 3] = v.w;
+        }
+    }
+}
+
 template <uint32_t RW>
 __device__ __forceinline__ void words_load(const uint8_t* p, uint32_t (&w)[RW]) {
     if constexpr (RW == 1) {
@@ -1028,7 +1047,7 @@ __global__ __launch_bounds__(kBlock) void k_valid_rows(DevSpace S, uint32_t n_va
         for (uint32_t u = 0; u < kRowsPerThread; ++u) {
             const uint64_t i = i0 + u * step;
             uint32_t w[RW];
-            if (i < n) words_load<RW>(rows + i * (RW * 4u), w);
+            if (i < n) words_load_nt<RW>(rows + i * (RW * 4u), w);
             else
                 for (uint32_t q = 0; q < RW; ++q) w[q] = 0;
 #pragma unroll
