@@ -7,13 +7,17 @@
 // ballot the results into one word, which stays in the register of lane k;
 // the 64 words leave with one coalesced 512-byte store.
 //
-// Constraint scopes are hoisted: programs that only read the first `split`
+// Constraint scopes are hoisted: a program over few parameters becomes a bit
+// table over its scope's value combinations (programs of one scope class
+// share the AND of their tables); programs that only read the first `split`
 // parameters are evaluated once per prefix (a bit table over prod_{j<split}
-// r_j prefixes), and a group whose prefixes are all invalid is written as
-// zeros without decoding anything.  The valid list is then compacted in
-// ascending order: per-group counts, a two-level exclusive scan, and a
-// per-wave emission stage that spreads the group's valid indices over the
-// wave's lanes through LDS before decoding their digit rows.
+// r_j prefixes), a group whose prefixes are all invalid is written as zeros
+// without decoding anything, and the inner programs become bit patterns per
+// context of prefix values.  The valid list is then compacted in ascending
+// order without atomics: per-group counts, tile sums and one scan of them,
+// group offsets, and work items of at most 256 valid configurations whose
+// rows are ORs of a prefix and an inner digit row; then the 64-row boxes and
+// chunk boxes the repair scans prune with.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
