@@ -340,17 +340,28 @@ struct Cand {
     }
 };
 
-// lexicographic (key, position) minimum over the wave; every lane gets the result
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ void dpp_lexmin_step(uint64_t& k, uint32_t& p) {
+    const uint32_t klo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)k, (int)(uint32_t)k, CTRL, ROWS, 0xF, false);
+    const uint32_t khi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(k >> 32), (int)(uint32_t)(k >> 32), CTRL,
+                                                              ROWS, 0xF, false);
+    const uint32_t pq = (uint32_t)__builtin_amdgcn_update_dpp((int)p, (int)p, CTRL, ROWS, 0xF, false);
+    const uint64_t kq = ((uint64_t)khi << 32) | klo;
+    if (kq < k || (kq == k && pq < p)) { k = kq; p = pq; }
+}
+
+// Lexicographic (key, position) minimum over the wave, every lane gets the result: the same steps
+// as wave_min_u64 on the pairs.  Every lane must be active.
 __device__ __forceinline__ void wave_lexmin(uint64_t& k, uint32_t& p) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const uint32_t klo = __shfl_xor((uint32_t)k, o, 64), khi = __shfl_xor((uint32_t)(k >> 32), o, 64);
-        const uint32_t pq = __shfl_xor(p, o, 64);
-        const uint64_t kq = ((uint64_t)khi << 32) | klo;
-        if (kq < k || (kq == k && pq < p)) { k = kq; p = pq; }
-    }
-    k = ((uint64_t)uni((uint32_t)(k >> 32)) << 32) | uni((uint32_t)k);
-    p = uni(p);
+    dpp_lexmin_step<0xB1>(k, p);
+    dpp_lexmin_step<0x4E>(k, p);
+    dpp_lexmin_step<0x141>(k, p);
+    dpp_lexmin_step<0x140>(k, p);
+    dpp_lexmin_step<0x142, 0xA>(k, p);
+    dpp_lexmin_step<0x143, 0xC>(k, p);
+    k = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(k >> 32), 63) << 32) |
+        (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)k, 63);
+    p = (uint32_t)__builtin_amdgcn_readlane((int)p, 63);
 }
 
 // rank_dir on a descriptor typed as device memory, for a wave-uniform L: lanes 0-7 read the words
@@ -807,13 +818,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_finish(const RepairSet* __res
             const uint32_t q = J.part_pos[(uint64_t)li * parts + p];
             if (q != kNoPos && (k < bk || (k == bk && q < bp))) { bk = k; bp = q; }
         }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const uint32_t klo = __shfl_xor((uint32_t)bk, o, 64), khi = __shfl_xor((uint32_t)(bk >> 32), o, 64);
-            const uint32_t q = __shfl_xor(bp, o, 64);
-            const uint64_t k = ((uint64_t)khi << 32) | klo;
-            if (k < bk || (k == bk && q < bp)) { bk = k; bp = q; }
-        }
+        wave_lexmin(bk, bp);
         const uint32_t ci = (which ? J.fb_list : J.list)[li];
         if (bp != kNoPos) {
             const uint32_t* src = reinterpret_cast<const uint32_t*>(S.rows + (uint64_t)bp * S.R);
