@@ -285,18 +285,32 @@ __device__ __forceinline__ void sort3(uint32_t* e, uint32_t n) {
 // ---------------------------------------------------------------------------
 constexpr uint32_t kWideGroupMax = 16384;   // individuals up to which a group has 16 lanes
 
+// Group reductions through DPP row permutations (no LDS round trip): the two quad swaps combine
+// the four lanes of a quad, then (16-lane groups) the half-row mirror pairs each quad with the
+// other quad of its half and the row mirror each half with the other half, so every step adds
+// disjoint sets of lanes.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+    return ((uint64_t)dpp_u32<CTRL>((uint32_t)(v >> 32)) << 32) | dpp_u32<CTRL>((uint32_t)v);
+}
 template <uint32_t G>
 __device__ __forceinline__ uint32_t grp_or4(uint32_t v) {
-    v |= __shfl_xor(v, 1, G);
-    v |= __shfl_xor(v, 2, G);
+    v |= dpp_u32<0xB1>(v);        // quad_perm [1, 0, 3, 2]
+    v |= dpp_u32<0x4E>(v);        // quad_perm [2, 3, 0, 1]
     return v;
 }
 template <uint32_t G>
 __device__ __forceinline__ uint64_t grp_sum64(uint64_t v) {
-#pragma unroll
-    for (int o = 1; o < (int)G; o <<= 1) {
-        const uint32_t lo = __shfl_xor((uint32_t)v, o, G), hi = __shfl_xor((uint32_t)(v >> 32), o, G);
-        v += ((uint64_t)hi << 32) | lo;
+    static_assert(G == 4 || G == 16, "groups of 4 or 16 lanes");
+    v += dpp_u64<0xB1>(v);
+    v += dpp_u64<0x4E>(v);
+    if constexpr (G == 16) {
+        v += dpp_u64<0x141>(v);   // row_half_mirror
+        v += dpp_u64<0x140>(v);   // row_mirror
     }
     return v;
 }
