@@ -537,6 +537,14 @@ int ct_prof_enable(int on);
 int ct_prof_read(const char* kernel, double* total_ms, uint64_t* launches);
 /* Record events only around launches of the named kernel (NULL: every kernel). */
 int ct_prof_select(const char* kernel);
+/* Record events only around every `every`-th launch of each kernel name (counted from the last
+   ct_prof_enable; every = 1, the default: all of them; 0 is CT_EINVAL).  Each recorded event
+   stalls the stream around its launch by a few microseconds, so sampling keeps the timed work
+   close to unmeasured work while the sampled launches still give the mean launch time. */
+int ct_prof_sample(uint32_t every);
+/* Launches of the named kernel since the last ct_prof_enable that passed the ct_prof_select
+   filter, recorded or not (with sampling, ct_prof_read counts only the recorded ones). */
+int ct_prof_seen(const char* kernel, uint64_t* launches);
 /* Repair scans of the main pass are "k_repair_scan", those of the Hamming fallback pass of
    Alg. 2/3 candidates without a tier 0-2 neighbour "k_repair_scan_fb".
    ct_prof_count_boxes(1) clears and starts device counters of the work the scans actually do:

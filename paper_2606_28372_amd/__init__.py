@@ -499,11 +499,23 @@ def prof_select(kernel: Optional[str]):
     _lib.check(_lib.load().ct_prof_select(kernel.encode() if kernel else None))
 
 
+def prof_sample(every: int = 1):
+    """Record events only around every `every`-th launch of each kernel (ct_prof_sample)."""
+    _lib.check(_lib.load().ct_prof_sample(int(every)))
+
+
 def prof_read(kernel: str):
     """(total milliseconds, launches) of a kernel's base name since prof_enable."""
     t, n = ctypes.c_double(), ctypes.c_uint64()
     _lib.check(_lib.load().ct_prof_read(kernel.encode(), ctypes.byref(t), ctypes.byref(n)))
     return float(t.value), int(n.value)
+
+
+def prof_seen(kernel: str) -> int:
+    """Launches of a kernel's base name since prof_enable, recorded or not (ct_prof_seen)."""
+    n = ctypes.c_uint64()
+    _lib.check(_lib.load().ct_prof_seen(kernel.encode(), ctypes.byref(n)))
+    return int(n.value)
 
 
 def prof_count_boxes(on: bool = True):

@@ -86,6 +86,8 @@ SIGNATURES = {
     "ct_pop_evaluated": (_i32, [_vp, _vp]),
     "ct_batch_create": (_i32, [_P(_vp), _u32, _P(_vp)]),
     "ct_batch_create_lanes": (_i32, [_P(_vp), _u32, _u32, _P(_vp)]),
+    "ct_prof_sample": (_i32, [_u32]),
+    "ct_prof_seen": (_i32, [ctypes.c_char_p, _P(_u64)]),
     "ct_batch_step": (_i32, [_vp, _u32, _u32, _vp]),
     "ct_batch_free": (None, [_vp]),
     "ct_batch_autotune": (_i32, [_vp, _u32, _u32, _u32, _vp]),

@@ -3,6 +3,7 @@
 // bound a step against their roofline).
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -18,6 +19,8 @@ std::mutex g_mu;
 bool g_on = false;
 bool g_suspend = false;
 std::string g_only;                 // empty: every kernel
+uint32_t g_every = 1;               // record around every g_every-th launch of a name
+std::map<std::string, uint64_t> g_seen;   // launches of each name since the last enable
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 unsigned long long* g_boxes = nullptr;   // [4] main boxes, main chunks, fallback boxes, fallback chunks
@@ -39,6 +42,7 @@ hipEvent_t take() {
 ProfScope::ProfScope(const char* name, hipStream_t st) : name_(name), st_(st), a_(nullptr) {
     std::lock_guard<std::mutex> g(g_mu);
     if (!g_on || g_suspend || (!g_only.empty() && g_only != name_)) return;
+    if (g_seen[name_]++ % g_every != 0) return;
     a_ = take();
     (void)hipEventRecord((hipEvent_t)a_, st_);
 }
@@ -88,7 +92,24 @@ extern "C" int ct_prof_enable(int on) {
         g_pool.push_back(r.b);
     }
     g_recs.clear();
+    g_seen.clear();
     g_on = on != 0;
+    return CT_OK;
+}
+
+extern "C" int ct_prof_seen(const char* kernel, uint64_t* launches) {
+    if (!kernel || !launches) return ct_fail(CT_EINVAL, "ct_prof_seen: null argument");
+    std::lock_guard<std::mutex> g(g_mu);
+    const auto it = g_seen.find(kernel);
+    *launches = it == g_seen.end() ? 0 : it->second;
+    return CT_OK;
+}
+
+extern "C" int ct_prof_sample(uint32_t every) {
+    if (every == 0) return ct_fail(CT_EINVAL, "ct_prof_sample: every must be at least 1");
+    std::lock_guard<std::mutex> g(g_mu);
+    g_every = every;
+    g_seen.clear();
     return CT_OK;
 }
 
