@@ -92,3 +92,11 @@ def test_repair_large_batch():
     """More candidates than the scan launches items for: one part per candidate."""
     run_parity(W.gemm10(), oracle_space("gemm10"), 20000, 5, metrics=[ocore.HAMMING, ocore.INDEX_L1,
                                                                           ocore.TIER_RANDOM, ocore.HAM1_RANDOM])
+
+
+@pytest.mark.parametrize("n", [1480, 2070, 3450])
+def test_repair_gemm13_part_counts(n):
+    """Candidate counts for which the plan gives each candidate 7, 5 or 3 parts of the list (about
+    8,192 items over ~0.79 n candidates to repair): the parts then share each chunk's boxes two or
+    one ways instead of eight, and the result must not change."""
+    run_parity(W.gemm13(), oracle_space("gemm13"), n, 6, metrics=[ocore.INDEX_L1, ocore.TIER_EUCLID])
