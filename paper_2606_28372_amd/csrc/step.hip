@@ -70,14 +70,54 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// minimum over the block (all threads get the result)
+// a lane's value from another lane of its row through a DPP permutation
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+    return ((uint64_t)dpp_u32<CTRL>((uint32_t)(v >> 32)) << 32) | dpp_u32<CTRL>((uint32_t)v);
+}
+
+// Wave reductions through DPP (every lane active): within each row of 16 lanes the two quad swaps
+// and the half-row and row mirrors combine disjoint sets of lanes, then row 1 takes row 0's partial
+// and row 3 row 2's (lane 15 broadcast to the next row), row 3 takes row 1's (lane 31 broadcast to
+// rows 2 and 3), and lane 63 holds the wave's result.  A shuffle through LDS would be one dependent
+// LDS round trip per step.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_rows_u32(uint32_t old, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWS, 0xF, false);
+}
+__device__ __forceinline__ uint64_t wave_min_dpp(uint64_t v) {
+    auto step = [](uint64_t x, uint64_t w) { return w < x ? w : x; };
+    v = step(v, dpp_u64<0xB1>(v));
+    v = step(v, dpp_u64<0x4E>(v));
+    v = step(v, dpp_u64<0x141>(v));
+    v = step(v, dpp_u64<0x140>(v));
+    // rows outside the broadcast's row mask keep their own value
+    v = step(v, ((uint64_t)dpp_rows_u32<0x142, 0xA>((uint32_t)(v >> 32), (uint32_t)(v >> 32)) << 32) |
+                    dpp_rows_u32<0x142, 0xA>((uint32_t)v, (uint32_t)v));
+    v = step(v, ((uint64_t)dpp_rows_u32<0x143, 0xC>((uint32_t)(v >> 32), (uint32_t)(v >> 32)) << 32) |
+                    dpp_rows_u32<0x143, 0xC>((uint32_t)v, (uint32_t)v));
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+}
+__device__ __forceinline__ uint32_t wave_sum_dpp(uint32_t v) {
+    v += dpp_u32<0xB1>(v);
+    v += dpp_u32<0x4E>(v);
+    v += dpp_u32<0x141>(v);
+    v += dpp_u32<0x140>(v);
+    // rows outside the broadcast's row mask add 0
+    v += dpp_rows_u32<0x142, 0xA>(0u, v);
+    v += dpp_rows_u32<0x143, 0xC>(0u, v);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// minimum over the block (all threads get the result; every thread of the block calls it)
 __device__ uint64_t block_min_u64(uint64_t v) {
     __shared__ uint64_t part[kSelBlock / 64];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        uint64_t w = shfl_xor_u64(v, o);
-        v = w < v ? w : v;
-    }
+    v = wave_min_dpp(v);
     __syncthreads();
     if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -89,8 +129,7 @@ __device__ uint64_t block_min_u64(uint64_t v) {
 
 __device__ uint32_t block_sum_u32(uint32_t v) {
     __shared__ uint32_t part[kSelBlock / 64];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    v = wave_sum_dpp(v);
     __syncthreads();
     if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -289,14 +328,6 @@ constexpr uint32_t kWideGroupMax = 16384;   // individuals up to which a group h
 // the four lanes of a quad, then (16-lane groups) the half-row mirror pairs each quad with the
 // other quad of its half and the row mirror each half with the other half, so every step adds
 // disjoint sets of lanes.
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
-}
-template <int CTRL>
-__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
-    return ((uint64_t)dpp_u32<CTRL>((uint32_t)(v >> 32)) << 32) | dpp_u32<CTRL>((uint32_t)v);
-}
 template <uint32_t G>
 __device__ __forceinline__ uint32_t grp_or4(uint32_t v) {
     v |= dpp_u32<0xB1>(v);        // quad_perm [1, 0, 3, 2]
