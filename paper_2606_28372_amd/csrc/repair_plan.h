@@ -13,93 +13,134 @@ __device__ __forceinline__ uint32_t plan_count(const RepairSet* __restrict__ set
     return __hip_atomic_load(&sets[s].count[which], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ uint32_t plan_excl_scan(uint32_t v, uint32_t lane) {
-    uint32_t x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o, 64);
-        if (lane >= (uint32_t)o) x += y;
-    }
-    return x - v;
-}
-
-__device__ __forceinline__ uint32_t plan_sum_u32(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// Inclusive prefix sum over the wave (every lane active) through DPP, with no LDS round trip: shifts
+// by 1, 2, 4 and 8 lanes inside each row of 16 (a lane shifted in from outside the row adds 0), then
+// rows 1 and 3 add the last lane of the row before them and rows 2 and 3 add lane 31.
+__device__ __forceinline__ uint32_t plan_incl_scan(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);   // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);   // row_bcast:31
     return v;
 }
 
-// One wave: per-set candidate counts -> parts and item offsets of one scan pass.  Lane l owns
-// a contiguous slice of the sets; offsets are the wave prefix of the lanes' totals plus the
-// running sum inside the slice.  which = 0: main lists with each set's metric; which = 1:
-// fallback lists, Hamming.  Each scan class is its own launch, so its candidates are split
-// into parts to give that launch about target_items items, each part min_sub boxes or more, in a
-// multiple of 8 parts where there are 8 or more (the scans place part p on XCD p mod 8).
+__device__ __forceinline__ uint32_t plan_sum_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)plan_incl_scan(v), 63);
+}
+
+__device__ __forceinline__ uint32_t plan_cls(const RepairSet* __restrict__ sets, uint32_t s, uint32_t which) {
+    return repair_class(which ? (uint32_t)CT_HAMMING : sets[s].metric, sets[s].R);
+}
+
+// Parts per candidate of one set: gp of its class, at most one per min_sub boxes and eight per
+// 64-box chunk (parts own box pb (mod 8) of chunk pc (mod parts / 8): more would idle), in whole
+// eighths where there are 8 or more (part p of every candidate on XCD p mod 8), one for the
+// enumerated classes.
+__device__ __forceinline__ uint32_t plan_parts(const RepairSet& J, uint32_t cls, uint32_t gp, uint32_t min_sub) {
+    const uint64_t pmax = min(J.n_sub / min_sub, ((J.n_sub + 63u) >> 6) * 8u);
+    uint64_t p = gp > pmax ? pmax : gp;
+    if (p >= 8) p &= ~7ull;
+    if (p < 1 || cls / 4u == (uint32_t)CT_HAM1_RANDOM) p = 1;   // enumerated, not scanned
+    return (uint32_t)p;
+}
+
+constexpr uint32_t kPlanCache = 4;   // sets per lane per round of the plan
+
+// One wave: per-set candidate counts -> parts and item offsets of one scan pass.  which = 0: main
+// lists with each set's metric; which = 1: fallback lists, Hamming.  Each scan class is its own
+// launch, so its candidates are split into parts to give that launch about target_items items,
+// each part min_sub boxes or more.  The sets go in rounds of 64 * per (per = min(kPlanCache,
+// ceil(n_sets / 64))), lane l owning sets l * per .. l * per + per - 1 of a round, whose class and
+// list length stay in registers; every offset is a wave prefix (in set order) plus what earlier
+// rounds carried.  Only the classes in class_mask are visited, one at a time, class q's running
+// figures held by lane q: a single wave issues this, so its instruction count is its duration.
 __device__ inline void plan_wave(const RepairSet* __restrict__ sets, uint32_t n_sets, uint32_t which,
                                  const RepairPlan& plan, uint32_t class_mask, uint32_t target_items,
                                  uint32_t min_sub) {
+    static_assert(kRepairClasses <= 64, "one lane per scan class");
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t chunk = (n_sets + 63u) / 64u;
-    const uint32_t s0 = min(n_sets, lane * chunk), s1 = min(n_sets, s0 + chunk);
-    uint32_t acc[kRepairClasses];
+    const uint32_t per = min(kPlanCache, (n_sets + 63u) / 64u);
+    const uint32_t round_sets = 64u * per;
+    const uint32_t rounds = (n_sets + round_sets - 1u) / round_sets;
+    uint32_t kc[kPlanCache], kn[kPlanCache];
+    auto load = [&](uint32_t r) {
 #pragma unroll
-    for (uint32_t q = 0; q < kRepairClasses; ++q) acc[q] = 0;
-    for (uint32_t s = s0; s < s1; ++s) {
-        const uint32_t cls = repair_class(which ? (uint32_t)CT_HAMMING : sets[s].metric, sets[s].R);
-        const uint32_t c = plan_count(sets, s, which);
+        for (uint32_t k = 0; k < kPlanCache; ++k) {
+            const uint32_t s = r * round_sets + lane * per + k;
+            kc[k] = kRepairClasses;                    // no class: adds to nothing
+            kn[k] = 0;
+            if (k < per && s < n_sets) {
+                kc[k] = plan_cls(sets, s, which);
+                kn[k] = plan_count(sets, s, which);
+            }
+        }
+    };
+    // candidates per class (class q's total in lane q) -> parts per candidate of each class
+    uint32_t tot = 0;
+    for (uint32_t r = 0; r < rounds; ++r) {
+        load(r);
+        for (uint32_t m = class_mask; m; m &= m - 1u) {
+            const uint32_t q = (uint32_t)__builtin_ctz(m);
+            uint32_t v = 0;
 #pragma unroll
-        for (uint32_t q = 0; q < kRepairClasses; ++q) acc[q] += q == cls ? c : 0u;
-    }
-    uint32_t gpc[kRepairClasses];
-#pragma unroll
-    for (uint32_t q = 0; q < kRepairClasses; ++q) {
-        gpc[q] = 1u;
-        if (class_mask & (1u << q)) {
-            const uint32_t total = plan_sum_u32(acc[q]);
-            gpc[q] = total ? max(target_items / total, 1u) : 1u;
+            for (uint32_t k = 0; k < kPlanCache; ++k) v += kc[k] == q ? kn[k] : 0u;
+            const uint32_t t = plan_sum_u32(v);
+            tot += lane == q ? t : 0u;
         }
     }
-    uint32_t tc = 0;
+    const uint32_t gpc = tot ? max(target_items / tot, 1u) : 1u;
+    uint32_t carry_c = 0;                              // candidates of earlier rounds
+    uint32_t carry = 0;                                // lane q: class q's items of earlier rounds
+    for (uint32_t r = 0; r < rounds; ++r) {
+        if (rounds > 1) load(r);
+        uint32_t kw[kPlanCache];
+        uint32_t c_lane = 0;
 #pragma unroll
-    for (uint32_t q = 0; q < kRepairClasses; ++q) acc[q] = 0;
-    for (uint32_t s = s0; s < s1; ++s) {
-        // parts own box pb (mod 8) of chunk pc (mod parts / 8): more than 8 per chunk would idle
-        const uint64_t pmax = min(sets[s].n_sub / min_sub, ((sets[s].n_sub + 63u) >> 6) * 8u);
-        const uint32_t cls = repair_class(which ? (uint32_t)CT_HAMMING : sets[s].metric, sets[s].R);
-        uint32_t gp = gpc[0];
+        for (uint32_t k = 0; k < kPlanCache; ++k) {
+            const uint32_t s = r * round_sets + lane * per + k;
+            // parts per candidate of the set's class, from its lane (every lane takes part)
+            const uint32_t gp = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(min(kc[k], 63u) * 4u), (int)gpc);
+            kw[k] = 0;
+            if (k < per && s < n_sets) {
+                const uint32_t p = plan_parts(sets[s], kc[k], gp, min_sub);
+                plan.parts[s] = p;
+                kw[k] = kn[k] * p;
+                c_lane += kn[k];
+            }
+        }
+        const uint32_t ic = plan_incl_scan(c_lane);
+        uint32_t oc = carry_c + ic - c_lane;
 #pragma unroll
-        for (uint32_t q = 1; q < kRepairClasses; ++q) gp = q == cls ? gpc[q] : gp;
-        uint64_t p = gp > pmax ? pmax : gp;
-        if (p >= 8) p &= ~7ull;          // whole eighths: part p of every candidate on XCD p mod 8
-        if (p < 1 || cls / 4u == (uint32_t)CT_HAM1_RANDOM) p = 1;   // enumerated, not scanned
-        plan.parts[s] = (uint32_t)p;
-        const uint32_t c = plan_count(sets, s, which);
-        tc += c;
+        for (uint32_t k = 0; k < kPlanCache; ++k) {
+            const uint32_t s = r * round_sets + lane * per + k;
+            if (k < per && s < n_sets) {
+                plan.cand_off[s] = oc;
+                oc += kn[k];
+            }
+        }
+        carry_c += (uint32_t)__builtin_amdgcn_readlane((int)ic, 63);
+        for (uint32_t m = class_mask; m; m &= m - 1u) {
+            const uint32_t q = (uint32_t)__builtin_ctz(m);
+            uint32_t v = 0;
 #pragma unroll
-        for (uint32_t q = 0; q < kRepairClasses; ++q) acc[q] += q == cls ? c * (uint32_t)p : 0u;
+            for (uint32_t k = 0; k < kPlanCache; ++k) v += kc[k] == q ? kw[k] : 0u;
+            const uint32_t iv = plan_incl_scan(v);
+            uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)carry, (int)q) + iv - v;
+#pragma unroll
+            for (uint32_t k = 0; k < kPlanCache; ++k) {
+                const uint32_t s = r * round_sets + lane * per + k;
+                if (k < per && s < n_sets) {
+                    plan.item_off[q * (n_sets + 1) + s] = o;
+                    o += kc[k] == q ? kw[k] : 0u;
+                }
+            }
+            carry += lane == q ? (uint32_t)__builtin_amdgcn_readlane((int)iv, 63) : 0u;
+        }
     }
-    uint32_t oc = plan_excl_scan(tc, lane);
-#pragma unroll
-    for (uint32_t q = 0; q < kRepairClasses; ++q)
-        if (class_mask & (1u << q)) acc[q] = plan_excl_scan(acc[q], lane);
-    for (uint32_t s = s0; s < s1; ++s) {
-        const uint32_t p = plan.parts[s];
-        const uint32_t c = plan_count(sets, s, which);
-        const uint32_t cls = repair_class(which ? (uint32_t)CT_HAMMING : sets[s].metric, sets[s].R);
-        plan.cand_off[s] = oc;
-#pragma unroll
-        for (uint32_t q = 0; q < kRepairClasses; ++q)
-            if (class_mask & (1u << q)) plan.item_off[q * (n_sets + 1) + s] = acc[q];
-        oc += c;
-#pragma unroll
-        for (uint32_t q = 0; q < kRepairClasses; ++q) acc[q] += q == cls ? c * p : 0u;
-    }
-    if (lane == 63) {
-        plan.cand_off[n_sets] = oc;
-#pragma unroll
-        for (uint32_t q = 0; q < kRepairClasses; ++q)
-            if (class_mask & (1u << q)) plan.item_off[q * (n_sets + 1) + n_sets] = acc[q];
-    }
+    if (lane == 0) plan.cand_off[n_sets] = carry_c;
+    if (lane < kRepairClasses && ((class_mask >> lane) & 1u)) plan.item_off[lane * (n_sets + 1) + n_sets] = carry;
 }
 
 

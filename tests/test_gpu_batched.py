@@ -331,3 +331,33 @@ def test_explicit_lanes_equal_plain(spaces):
     for bad in (0, 9):
         with pytest.raises(CtError):
             Batch(b, lanes=bad)
+
+
+def test_wide_batch_plans_in_rounds():
+    """300 runs in one lane: the wave that plans each repair pass takes the runs' sets 256 at a
+    time (four per lane), carrying candidate and item offsets from one round to the next; every
+    run still ends where plain stepping leaves it."""
+    import dataclasses
+    from paper_2606_28372_amd import Batch, CT_STEP_BATCHED, CT_STEP_GRAPH, Pop, step_many
+    t = torch()
+    probs = W.batched(6, seed=13, max_pop=48)
+    spaces, objs = [], []
+    for pr in probs:
+        sp = gpu_space(pr.spec)
+        spaces.append(sp)
+        objs.append(t.tensor(W.objective(sp.n_valid, pr.obj_seed), device="cuda"))
+    a, b = [], []
+    for j in range(300):
+        k = j % len(probs)
+        opt = dataclasses.replace(W.fit_pop(probs[k].opt, spaces[k].n_valid), seed=probs[k].opt.seed + 7919 * j)
+        a.append(Pop.from_opt(spaces[k], opt, objs[k]))
+        b.append(Pop.from_opt(spaces[k], opt, objs[k]))
+    bt = Batch(b, lanes=1)
+    say(f"[gpu_batched] wide batch: {len(b)} runs in one lane")
+    for stage, mode in enumerate((CT_STEP_BATCHED, CT_STEP_GRAPH)):
+        step_many(a, 3)
+        bt.step(3, mode)
+        t.cuda.synchronize()
+        for k in range(len(a)):
+            assert a[k].snapshot() == b[k].snapshot(), f"run {k} differs at stage {stage}"
+    bt.close()
