@@ -370,13 +370,23 @@ __device__ __forceinline__ uint32_t beta_rank(const PopDev& p, uint32_t u) {
     return lo;
 }
 
-// The new digit j (< D) of individual i of run p in generation g.  Every lane of the group
-// computes the individual's shared draws itself (same counters, same values).
-__device__ __forceinline__ uint32_t propose_digit(const PopDev& p, const DevSpace& S, uint32_t i, uint32_t g,
-                                                  uint32_t j) {
-    const uint32_t radix = gld(&S.radix[j]);
+// What the digits of individual i's proposal share (generation g), drawn once per lane before its
+// digits: DE's picks, j_rand, exponential crossover run and best configuration; GA's parents, cut
+// points and (non-aware) mutation draw; PSO's global best member.  Every lane of the group draws
+// the same (same counters, same values).
+struct PropCtx {
+    uint32_t r[5];        // DE: distinct members other than i
+    uint32_t jr;          // DE: j_rand
+    uint32_t run;         // DE exponential crossover: length of the circular run from j_rand
+    uint32_t best;        // DE: best member (non-aware) or best configuration's position; PSO: global best
+    uint32_t pa, pb;      // GA: the parents (rank-order entries)
+    uint32_t lo, hi;      // GA: genes [lo, hi) of the even child come from parent B (one or two cuts)
+    U4 mut;               // GA non-aware: the mutation draw
+};
+
+__device__ __forceinline__ PropCtx propose_ctx(const PopDev& p, uint32_t i, uint32_t g) {
+    PropCtx c{};
     if (p.algo == CT_DE) {
-        // picks r1..r5: distinct members other than i (two-difference operators use five)
         const uint32_t meth = p.de_method;
         const uint32_t k = (meth == CT_DE_RAND2 || meth == CT_DE_BEST2) ? 5u : 3u;
         const U4 o = ct_philox(p.seed, i, g, (uint32_t)PUR_DE_PICK << 24, 0);
@@ -387,22 +397,64 @@ __device__ __forceinline__ uint32_t propose_digit(const PopDev& p, const DevSpac
             u[4] = o2.y;
         }
         uint32_t ex[6] = {i, 0, 0, 0, 0, 0};
-        uint32_t r[5] = {0, 0, 0, 0, 0};
 #pragma unroll
         for (uint32_t t = 0; t < 5; ++t) {
             if (t < k) {
-                r[t] = pick_excl(u[t], p.P, ex, t + 1);
-                ex[t + 1] = r[t];
+                c.r[t] = pick_excl(u[t], p.P, ex, t + 1);
+                ex[t + 1] = c.r[t];
                 sort3(ex, t + 2);
             }
         }
-        const uint32_t jr = ct_below(o.w, p.D);
+        c.jr = ct_below(o.w, p.D);
+        c.best = p.unaware ? gld(p.state + 2) : (uint32_t)(gld(p.best) & 0xFFFFFFFFu);
+        if (p.de_cross == CT_DE_EXP) {
+            // the circular run from j_rand continues while successive draws stay below CR
+            uint32_t run = 1;
+            while (run < p.D) {
+                const U4 d = ct_philox(p.seed, i, g, ((uint32_t)PUR_DE_CR << 24) | (run >> 2), 0);
+                const uint32_t t = run & 3u;
+                const uint32_t cu = t == 0 ? d.x : t == 1 ? d.y : t == 2 ? d.z : d.w;
+                if ((uint64_t)cu >= p.CR_q32) break;
+                ++run;
+            }
+            c.run = run;
+        }
+    } else if (p.algo == CT_PSO) {
+        c.best = gld(p.state + 2);
+    } else if (p.algo == CT_GA) {
+        // child i of pair i/2: the pair's parents and cuts
+        const uint32_t k = i >> 1;
+        const U4 o = ct_philox(p.seed, k, g, (uint32_t)PUR_GA_SEL << 24, 0);
+        c.pa = gld(p.sorted + beta_rank(p, o.x));
+        c.pb = gld(p.sorted + beta_rank(p, o.y));
+        c.lo = 1u;
+        c.hi = p.D;
+        if (p.ga_cross == CT_GA_TWO_POINT && p.D >= 3) {
+            const uint32_t c1 = 1u + ct_below(o.z, p.D - 1u);
+            uint32_t c2 = ct_below(o.w, p.D - 2u);
+            if (c2 >= c1 - 1u) ++c2;                 // a distinct second cut
+            c2 += 1u;
+            c.lo = c1 < c2 ? c1 : c2;
+            c.hi = c1 < c2 ? c2 : c1;
+        } else if (p.ga_cross != CT_GA_UNIFORM && p.ga_cross != CT_GA_DISRUPTIVE_UNIFORM) {
+            c.lo = 1u + ct_below(o.z, p.D - 1u);     // single point: genes from the cut on
+        }
+        if (p.unaware) c.mut = ct_philox(p.seed, i, g, (uint32_t)PUR_GA_MUT << 24, 0);
+    }
+    return c;
+}
+
+// The new digit j (< D) of individual i of run p in generation g, given its shared draws c.
+__device__ __forceinline__ uint32_t propose_digit(const PopDev& p, const DevSpace& S, const PropCtx& c, uint32_t i,
+                                                  uint32_t g, uint32_t j) {
+    const uint32_t radix = gld(&S.radix[j]);
+    if (p.algo == CT_DE) {
+        const uint32_t meth = p.de_method;
         // the best configuration so far (non-aware: the population's best member)
-        const int64_t best = p.unaware ? member_digit(p, S, gld(p.state + 2), j)
-                                       : row_digit(S, (uint32_t)(gld(p.best) & 0xFFFFFFFFu), p.R, j);
+        const int64_t best = p.unaware ? member_digit(p, S, c.best, j) : row_digit(S, c.best, p.R, j);
         const int64_t x = member_digit(p, S, i, j);
-        const int64_t x1 = member_digit(p, S, r[0], j);
-        const int64_t x2 = member_digit(p, S, r[1], j), x3 = member_digit(p, S, r[2], j);
+        const int64_t x1 = member_digit(p, S, c.r[0], j);
+        const int64_t x2 = member_digit(p, S, c.r[1], j), x3 = member_digit(p, S, c.r[2], j);
         int64_t base, diff = x2 - x3;
         if (meth == CT_DE_RAND1) base = x1;
         else if (meth == CT_DE_BEST1) base = best;
@@ -410,7 +462,7 @@ __device__ __forceinline__ uint32_t propose_digit(const PopDev& p, const DevSpac
         else if (meth == CT_DE_RANDTOBEST1) { base = x1; diff += best - x1; }
         else {
             base = meth == CT_DE_RAND2 ? x1 : best;
-            diff += (int64_t)member_digit(p, S, r[3], j) - (int64_t)member_digit(p, S, r[4], j);
+            diff += (int64_t)member_digit(p, S, c.r[3], j) - (int64_t)member_digit(p, S, c.r[4], j);
         }
         const int64_t num = base * 65536 + (int64_t)p.F_q16 * diff + 32768;
         int64_t m = num >> 16;            // floor
@@ -418,22 +470,13 @@ __device__ __forceinline__ uint32_t propose_digit(const PopDev& p, const DevSpac
         m = m < 0 ? 0 : (m > hi ? hi : m);
         bool take;
         if (p.de_cross == CT_DE_EXP) {
-            // the circular run from j_rand continues while successive draws stay below CR
-            uint32_t run = 1;
-            while (run < p.D) {
-                const U4 c = ct_philox(p.seed, i, g, ((uint32_t)PUR_DE_CR << 24) | (run >> 2), 0);
-                const uint32_t t = run & 3u;
-                const uint32_t cu = t == 0 ? c.x : t == 1 ? c.y : t == 2 ? c.z : c.w;
-                if ((uint64_t)cu >= p.CR_q32) break;
-                ++run;
-            }
-            take = (j + p.D - jr) % p.D < run;
+            take = (j + p.D - c.jr) % p.D < c.run;
         } else {
             // block j/4 of the crossover draws, draw j%4 of it
             const U4 cr = ct_philox(p.seed, i, g, ((uint32_t)PUR_DE_CR << 24) | (j >> 2), 0);
             const uint32_t t = j & 3u;
             const uint32_t cu = t == 0 ? cr.x : t == 1 ? cr.y : t == 2 ? cr.z : cr.w;
-            take = (uint64_t)cu < p.CR_q32 || j == jr;
+            take = (uint64_t)cu < p.CR_q32 || j == c.jr;
         }
         return take ? (uint32_t)m : (uint32_t)x;
     }
@@ -443,13 +486,12 @@ __device__ __forceinline__ uint32_t propose_digit(const PopDev& p, const DevSpac
         return d < radix ? d : radix - 1u;
     }
     if (p.algo == CT_PSO) {
-        const uint32_t gi = gld(p.state + 2);
         const int64_t xmax = (int64_t)p.M * 65536 - 1;
         U4 o = ct_philox(p.seed, i, g, ((uint32_t)PUR_PSO_R << 24) | j, 0);
         const int64_t r1 = o.x >> 16, r2 = o.y >> 16;
         const uint64_t k = (uint64_t)i * p.D + j;
         int64_t x = gld(p.X + k), v = gld(p.V + k);
-        const int64_t pb = gld(p.PB + k), gb = gld(p.PB + (uint64_t)gi * p.D + j);
+        const int64_t pb = gld(p.PB + k), gb = gld(p.PB + (uint64_t)c.best * p.D + j);
         v = ((p.w_q16 * v) >> 16) + ((((p.c1_q16 * r1) >> 16) * (pb - x)) >> 16) +
             ((((p.c2_q16 * r2) >> 16) * (gb - x)) >> 16);
         x += v;
@@ -462,9 +504,6 @@ __device__ __forceinline__ uint32_t propose_digit(const PopDev& p, const DevSpac
     // GA: child i of pair i/2 takes gene j from parent A where the even child does (the odd child
     // is its mirror)
     const uint32_t k = i >> 1;
-    U4 o = ct_philox(p.seed, k, g, (uint32_t)PUR_GA_SEL << 24, 0);
-    const uint32_t a = beta_rank(p, o.x), b = beta_rank(p, o.y);
-    const uint32_t pa = gld(p.sorted + a), pb = gld(p.sorted + b);
     bool even_a;
     if (p.ga_cross == CT_GA_UNIFORM) {
         const U4 x = ct_philox(p.seed, k, g, ((uint32_t)PUR_GA_XO << 24) | (j >> 2), 0);
@@ -472,7 +511,7 @@ __device__ __forceinline__ uint32_t propose_digit(const PopDev& p, const DevSpac
         even_a = ((t == 0 ? x.x : t == 1 ? x.y : t == 2 ? x.z : x.w) >> 31) == 0u;
     } else if (p.ga_cross == CT_GA_DISRUPTIVE_UNIFORM) {
         // of the genes where the parents differ, the half with the smallest keys come from B
-        const uint32_t aj = parent_digit(p, S, pa, j), bj = parent_digit(p, S, pb, j);
+        const uint32_t aj = parent_digit(p, S, c.pa, j), bj = parent_digit(p, S, c.pb, j);
         even_a = true;
         if (aj != bj) {
             const U4 kj4 = ct_philox(p.seed, k, g, ((uint32_t)PUR_GA_XO << 24) | (j >> 2), 1);
@@ -480,7 +519,7 @@ __device__ __forceinline__ uint32_t propose_digit(const PopDev& p, const DevSpac
             const uint32_t kj = t == 0 ? kj4.x : t == 1 ? kj4.y : t == 2 ? kj4.z : kj4.w;
             uint32_t n_diff = 0, rank = 0;
             for (uint32_t q = 0; q < p.D; ++q) {
-                if (parent_digit(p, S, pa, q) == parent_digit(p, S, pb, q)) continue;
+                if (parent_digit(p, S, c.pa, q) == parent_digit(p, S, c.pb, q)) continue;
                 ++n_diff;
                 const U4 kq4 = ct_philox(p.seed, k, g, ((uint32_t)PUR_GA_XO << 24) | (q >> 2), 1);
                 const uint32_t tq = q & 3u;
@@ -489,27 +528,20 @@ __device__ __forceinline__ uint32_t propose_digit(const PopDev& p, const DevSpac
             }
             even_a = rank >= n_diff / 2;
         }
-    } else if (p.ga_cross == CT_GA_TWO_POINT && p.D >= 3) {
-        const uint32_t c1 = 1u + ct_below(o.z, p.D - 1u);
-        uint32_t c2 = ct_below(o.w, p.D - 2u);
-        if (c2 >= c1 - 1u) ++c2;                 // a distinct second cut
-        c2 += 1u;
-        const uint32_t lo = c1 < c2 ? c1 : c2, hi = c1 < c2 ? c2 : c1;
-        even_a = j < lo || j >= hi;
     } else {
-        even_a = j < 1u + ct_below(o.z, p.D - 1u);
+        even_a = j < c.lo || j >= c.hi;             // one cut: hi = D
     }
     const bool from_a = even_a != ((i & 1u) != 0);
-    uint32_t c = parent_digit(p, S, from_a ? pa : pb, j);
+    uint32_t d = parent_digit(p, S, from_a ? c.pa : c.pb, j);
     if (p.unaware) {
         // with chance 1/mutation_chance one parameter (word 1) takes another of its values (word 2)
-        const U4 m = ct_philox(p.seed, i, g, (uint32_t)PUR_GA_MUT << 24, 0);
+        const U4& m = c.mut;
         if ((uint64_t)m.x < p.mut_thresh && j == ct_below(m.y, p.D) && radix > 1) {
             const uint32_t v = ct_below(m.z, radix - 1u);
-            c = v >= c ? v + 1u : v;
+            d = v >= d ? v + 1u : v;
         }
     }
-    return c;
+    return d;
 }
 
 // Proposals of every run, one group of G lanes per individual, each proposal listed for the main
@@ -533,6 +565,7 @@ __global__ __launch_bounds__(kBlock) void k_propose(const PopDev* __restrict__ p
         const RepairSet& J = sets[r];
         const uint32_t i = item - ind_off[r];
         const uint32_t g = gld(p.state);
+        const PropCtx ctx = propose_ctx(p, i, g);
         uint32_t d[T];
         bool ok = true;
         uint64_t term = 0;                              // digits past D are 0 and add nothing
@@ -541,7 +574,7 @@ __global__ __launch_bounds__(kBlock) void k_propose(const PopDev* __restrict__ p
             const uint32_t j = slot + G * t;
             d[t] = 0;
             if (j < p.D) {
-                d[t] = propose_digit(p, S, i, g, j);
+                d[t] = propose_digit(p, S, ctx, i, g, j);
                 ok &= d[t] < gld(&S.radix[j]);
                 term += (uint64_t)d[t] * gld(&S.stride[j]);
             }
