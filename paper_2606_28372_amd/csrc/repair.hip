@@ -523,17 +523,22 @@ __device__ __forceinline__ void scan_item(const RepairSet& J, const DevSpace& S,
                 tn = m ? __ffsll((long long)m) - 1 : -1;
                 if (tn >= 0) fetch(tn);
                 const uint64_t r = box_of(t) * 64u + lane;
+                bool found = false;
                 if (r < n_valid) {
                     const uint64_t k = C.key(S, v, r, mk < bk ? mk : bk);
-                    if (k < mk) { mk = k; mp = (uint32_t)r; }
+                    if (k < mk) { mk = k; mp = (uint32_t)r; found = true; }
                 }
-                const uint64_t wm = wave_min_u64(mk);
-                bk = wm < bk ? wm : bk;
-                if (m) {
-                    m &= __ballot(lb < bk);             // drop boxes the tighter bound now rules out
-                    if (tn >= 0 && !((m >> tn) & 1ull)) {
-                        tn = m ? __ffsll((long long)m) - 1 : -1;
-                        if (tn >= 0) fetch(tn);
+                // the bound (the wave's least key) only moves when some lane found a smaller key
+                // in this box: otherwise the minimum and the pruning below would change nothing
+                if (__ballot(found)) {
+                    const uint64_t wm = wave_min_u64(mk);
+                    bk = wm < bk ? wm : bk;
+                    if (m) {
+                        m &= __ballot(lb < bk);         // drop boxes the tighter bound now rules out
+                        if (tn >= 0 && !((m >> tn) & 1ull)) {
+                            tn = m ? __ffsll((long long)m) - 1 : -1;
+                            if (tn >= 0) fetch(tn);
+                        }
                     }
                 }
             }
