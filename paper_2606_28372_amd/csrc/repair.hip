@@ -657,23 +657,67 @@ __device__ __forceinline__ uint32_t first_item(uint32_t wpb) {
     return 8u * (wpb * (b >> 3) + w) + (b & 7u);
 }
 
+// A scan launch that plans its own items (SelfPlan::on; at most kSelfPlanSets sets): every wave
+// derives the plan of its class with lane s holding set s, in registers, instead of reading the
+// offsets a one-wave plan launch wrote, and global wave 0 writes the candidate offsets and this
+// class's parts that the finish reads.  The same figures as plan_wave's, one launch fewer.
+struct SelfPlan {
+    uint32_t on, target_items, min_sub;
+};
+constexpr uint32_t kSelfPlanSets = 64;
+
 template <int M, int RW>
 __global__ __launch_bounds__(kBlock) void k_repair_scan(const RepairSet* __restrict__ sets, uint32_t n_sets,
-                                                        RepairPlan plan, uint32_t which, uint32_t tab_stride) {
+                                                        RepairPlan plan, uint32_t which, uint32_t tab_stride,
+                                                        SelfPlan sp) {
     constexpr uint32_t cls = (uint32_t)M * 4u + (RW == 1 ? 0u : RW == 2 ? 1u : RW == 4 ? 2u : 3u);
     extern __shared__ uint64_t lds_tabs[];
     const uint32_t wpb = blockDim.x / 64;
     CT_LDS uint64_t* lds_tab = (CT_LDS uint64_t*)lds_tabs + (threadIdx.x >> 6) * tab_stride;
     const uint32_t* off = plan.item_off + cls * (n_sets + 1);
-    const uint32_t total = off[n_sets];
+    uint32_t total, sp_p = 1, sp_iv = 0, sp_ex = 0;
+    if (sp.on) {
+        const uint32_t lane = wave_lane();
+        uint32_t cls_s = kRepairClasses, cc = 0;
+        if (lane < n_sets) {
+            cls_s = plan_cls(sets, lane, which);
+            cc = plan_count(sets, lane, which);
+        }
+        const uint32_t c = cls_s == cls ? cc : 0u;
+        const uint32_t tot = plan_sum_u32(c);
+        const uint32_t gp = tot ? max(sp.target_items / tot, 1u) : 1u;
+        if (lane < n_sets) sp_p = plan_parts(sets[lane], cls_s, gp, sp.min_sub);
+        const uint32_t w = c * sp_p;
+        sp_iv = plan_incl_scan(w);                  // lanes past the sets repeat the total
+        sp_ex = sp_iv - w;
+        total = (uint32_t)__builtin_amdgcn_readlane((int)sp_iv, 63);
+        if (first_item(wpb) == 0) {
+            const uint32_t ic = plan_incl_scan(cc);
+            if (lane < n_sets) {
+                plan.cand_off[lane] = ic - cc;
+                if (cls_s == cls) plan.parts[lane] = sp_p;
+            }
+            if (lane == 63) plan.cand_off[n_sets] = ic;
+        }
+    } else {
+        total = off[n_sets];
+    }
     unsigned long long* opened = plan.opened ? plan.opened + 2 * which : nullptr;
     const uint32_t waves = gridDim.x * wpb;
     for (uint32_t item = uni(first_item(wpb)); item < total; item += waves) {
-        const uint32_t s = uni(find_set_wave(off, n_sets, item));
+        uint32_t s, parts, local;
+        if (sp.on) {
+            // the first lane whose inclusive prefix passes the item holds its set
+            s = (uint32_t)(__ffsll((long long)__ballot(item < sp_iv)) - 1);
+            parts = (uint32_t)__builtin_amdgcn_readlane((int)sp_p, (int)s);
+            local = item - (uint32_t)__builtin_amdgcn_readlane((int)sp_ex, (int)s);
+        } else {
+            s = uni(find_set_wave(off, n_sets, item));
+            parts = uni(plan.parts[s]);
+            local = item - off[s];
+        }
         const RepairSet& J = sets[s];
         const DevSpace& S = *J.S;
-        const uint32_t parts = uni(plan.parts[s]);
-        const uint32_t local = item - off[s];
         const uint32_t li = local / parts, part = local % parts;
         if constexpr (M == CT_HAM1_RANDOM) {
             ham1_item(J, S, li);
@@ -871,15 +915,23 @@ RepairPlan scan_plan(const RepairPasses& rp) {
     return p;
 }
 
+// The fallback pass plans inside its scans when the sets fit one wave's lanes (its scans are
+// single-class launches: the fallback is Hamming only).  The few fallback candidates sit far
+// from valid rows, where parts of more than 16 boxes only lengthen the pass, whatever suits the
+// main pass.
+bool fb_self_planned(const RepairPasses& rp) { return rp.n_sets <= kSelfPlanSets; }
+uint32_t fb_min_sub(const RepairPasses& rp) { return std::min(rp.tune.min_sub, kFallbackMinSub); }
+
 template <int M, int RW>
 void launch_scan_rw(const RepairPasses& rp, uint32_t which, hipStream_t st) {
     ProfScope ps_(which ? "k_repair_scan_fb" : "k_repair_scan", st);
     // TIER_EUCLID keeps one distance table per wave in LDS
     const uint32_t stride = M == CT_TIER_EUCLID ? std::max<uint32_t>(rp.euclid_tab, 1) : 0;
     const uint32_t wpb = kScanWavesPerBlock;
+    const SelfPlan sp{which == 1 && fb_self_planned(rp) ? 1u : 0u, rp.tune.items, fb_min_sub(rp)};
     hipLaunchKernelGGL((k_repair_scan<M, RW>), dim3(std::max<uint32_t>(scan_waves(rp, which) / wpb, 1)), dim3(wpb * 64),
                        (size_t)wpb * stride * 8, st,
-                       rp.d_sets, rp.n_sets, scan_plan(rp), which, stride);
+                       rp.d_sets, rp.n_sets, scan_plan(rp), which, stride, sp);
 }
 
 template <int RW>
@@ -926,8 +978,12 @@ int launch_scans(const RepairPasses& rp, uint32_t mask, uint32_t which, hipStrea
             uint32_t mm = 0;
             for (uint32_t m = 0; m < (uint32_t)CT_HAM1_RANDOM; ++m)
                 if (mask & (1u << (m * 4u + rwi))) mm |= 1u << m;
-            if (__builtin_popcount(mm) > 1) launch_mix(rp, rwi, mm, which, st);
-            else if (mm) launch_class(rp, (uint32_t)__builtin_ctz(mm) * 4u + rwi, which, st);
+            if (which == 0 && __builtin_popcount(mm) > 1) {
+                launch_mix(rp, rwi, mm, which, st);
+            } else {
+                // (the fallback pass is Hamming only; its single-class launches may plan themselves)
+                for (uint32_t m2 = mm; m2; m2 &= m2 - 1u) launch_class(rp, (uint32_t)__builtin_ctz(m2) * 4u + rwi, which, st);
+            }
             if (mask & (1u << ((uint32_t)CT_HAM1_RANDOM * 4u + rwi)))
                 launch_class(rp, (uint32_t)CT_HAM1_RANDOM * 4u + rwi, which, st);
         }
@@ -1046,14 +1102,12 @@ int launch_repair_passes(const RepairPasses& rp, bool zero_counts, hipStream_t s
                            rp.plan, 0u, count_tally ? 1u : 0u, PlanArgs{});
     }
     if (rp.fb_class_mask) {
-        {
+        if (!fb_self_planned(rp)) {
             // a launch of its own: the finish runs hundreds of blocks, and counting them all
-            // costs more than a one-wave launch.  The few fallback candidates sit far from valid
-            // rows, where parts of more than 16 boxes only lengthen the pass, whatever suits the
-            // main pass.
+            // costs more than a one-wave launch
             ProfScope ps_("k_repair_plan", st);
             hipLaunchKernelGGL(k_repair_plan, dim3(1), dim3(64), 0, st, rp.d_sets, rp.n_sets, 1u, rp.plan,
-                               rp.fb_class_mask, rp.tune.items, std::min(rp.tune.min_sub, kFallbackMinSub));
+                               rp.fb_class_mask, rp.tune.items, fb_min_sub(rp));
         }
         if (int rc = launch_scans(rp, rp.fb_class_mask, 1, st)) return rc;
         {
