@@ -46,15 +46,15 @@ __device__ __forceinline__ uint32_t plan_parts(const RepairSet& J, uint32_t cls,
     return (uint32_t)p;
 }
 
-constexpr uint32_t kPlanCache = 4;   // sets per lane per round of the plan
+constexpr uint32_t kPlanCache = 4;   // sets per lane per slice of the plan
 
 // One wave: per-set candidate counts -> parts and item offsets of one scan pass.  which = 0: main
 // lists with each set's metric; which = 1: fallback lists, Hamming.  Each scan class is its own
 // launch, so its candidates are split into parts to give that launch about target_items items,
-// each part min_sub boxes or more.  The sets go in rounds of 64 * per (per = min(kPlanCache,
-// ceil(n_sets / 64))), lane l owning sets l * per .. l * per + per - 1 of a round, whose class and
+// each part min_sub boxes or more.  The sets go in slices of 64 * per (per = min(kPlanCache,
+// ceil(n_sets / 64))), lane l owning sets l * per .. l * per + per - 1 of a slice, whose class and
 // list length stay in registers; every offset is a wave prefix (in set order) plus what earlier
-// rounds carried.  Only the classes in class_mask are visited, one at a time, class q's running
+// slices carried.  Only the classes in class_mask are visited, one at a time, class q's running
 // figures held by lane q: a single wave issues this, so its instruction count is its duration.
 __device__ inline void plan_wave(const RepairSet* __restrict__ sets, uint32_t n_sets, uint32_t which,
                                  const RepairPlan& plan, uint32_t class_mask, uint32_t target_items,
@@ -62,13 +62,13 @@ __device__ inline void plan_wave(const RepairSet* __restrict__ sets, uint32_t n_
     static_assert(kRepairClasses <= 64, "one lane per scan class");
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t per = min(kPlanCache, (n_sets + 63u) / 64u);
-    const uint32_t round_sets = 64u * per;
-    const uint32_t rounds = (n_sets + round_sets - 1u) / round_sets;
+    const uint32_t slice_sets = 64u * per;
+    const uint32_t slices = (n_sets + slice_sets - 1u) / slice_sets;
     uint32_t kc[kPlanCache], kn[kPlanCache];
     auto load = [&](uint32_t r) {
 #pragma unroll
         for (uint32_t k = 0; k < kPlanCache; ++k) {
-            const uint32_t s = r * round_sets + lane * per + k;
+            const uint32_t s = r * slice_sets + lane * per + k;
             kc[k] = kRepairClasses;                    // no class: adds to nothing
             kn[k] = 0;
             if (k < per && s < n_sets) {
@@ -79,7 +79,7 @@ __device__ inline void plan_wave(const RepairSet* __restrict__ sets, uint32_t n_
     };
     // candidates per class (class q's total in lane q) -> parts per candidate of each class
     uint32_t tot = 0;
-    for (uint32_t r = 0; r < rounds; ++r) {
+    for (uint32_t r = 0; r < slices; ++r) {
         load(r);
         for (uint32_t m = class_mask; m; m &= m - 1u) {
             const uint32_t q = (uint32_t)__builtin_ctz(m);
@@ -91,15 +91,15 @@ __device__ inline void plan_wave(const RepairSet* __restrict__ sets, uint32_t n_
         }
     }
     const uint32_t gpc = tot ? max(target_items / tot, 1u) : 1u;
-    uint32_t carry_c = 0;                              // candidates of earlier rounds
-    uint32_t carry = 0;                                // lane q: class q's items of earlier rounds
-    for (uint32_t r = 0; r < rounds; ++r) {
-        if (rounds > 1) load(r);
+    uint32_t carry_c = 0;                              // candidates of earlier slices
+    uint32_t carry = 0;                                // lane q: class q's items of earlier slices
+    for (uint32_t r = 0; r < slices; ++r) {
+        if (slices > 1) load(r);
         uint32_t kw[kPlanCache];
         uint32_t c_lane = 0;
 #pragma unroll
         for (uint32_t k = 0; k < kPlanCache; ++k) {
-            const uint32_t s = r * round_sets + lane * per + k;
+            const uint32_t s = r * slice_sets + lane * per + k;
             // parts per candidate of the set's class, from its lane (every lane takes part)
             const uint32_t gp = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(min(kc[k], 63u) * 4u), (int)gpc);
             kw[k] = 0;
@@ -114,7 +114,7 @@ __device__ inline void plan_wave(const RepairSet* __restrict__ sets, uint32_t n_
         uint32_t oc = carry_c + ic - c_lane;
 #pragma unroll
         for (uint32_t k = 0; k < kPlanCache; ++k) {
-            const uint32_t s = r * round_sets + lane * per + k;
+            const uint32_t s = r * slice_sets + lane * per + k;
             if (k < per && s < n_sets) {
                 plan.cand_off[s] = oc;
                 oc += kn[k];
@@ -130,7 +130,7 @@ __device__ inline void plan_wave(const RepairSet* __restrict__ sets, uint32_t n_
             uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)carry, (int)q) + iv - v;
 #pragma unroll
             for (uint32_t k = 0; k < kPlanCache; ++k) {
-                const uint32_t s = r * round_sets + lane * per + k;
+                const uint32_t s = r * slice_sets + lane * per + k;
                 if (k < per && s < n_sets) {
                     plan.item_off[q * (n_sets + 1) + s] = o;
                     o += kc[k] == q ? kw[k] : 0u;

@@ -333,9 +333,9 @@ def test_explicit_lanes_equal_plain(spaces):
             Batch(b, lanes=bad)
 
 
-def test_wide_batch_plans_in_rounds():
+def test_wide_batch_plans_in_slices():
     """300 runs in one lane: the wave that plans each repair pass takes the runs' sets 256 at a
-    time (four per lane), carrying candidate and item offsets from one round to the next; every
+    time (four per lane), carrying candidate and item offsets from one slice to the next; every
     run still ends where plain stepping leaves it."""
     import dataclasses
     from paper_2606_28372_amd import Batch, CT_STEP_BATCHED, CT_STEP_GRAPH, Pop, step_many
